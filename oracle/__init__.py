@@ -1,0 +1,199 @@
+"""ctypes front end of the plain CPU oracle (``pdit_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg may use this package; the GPU library never
+does.  The oracle shares no code with the GPU path.
+
+``build()`` compiles the C file with gcc (plain -O2, no vector intrinsics,
+floating-point contraction off so float32 products round exactly as
+written).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pdit_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+PO_OK, PO_EINVAL, PO_EMISMATCH, PO_EBADPERM, PO_ENOMEM = 0, -1, -2, -3, -4
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so next to the source."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                        "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        L.po_energy.restype = C.c_int64
+        L.po_energy.argtypes = [C.c_int, i32p, i32p, i32p]
+        L.po_influence.restype = None
+        L.po_influence.argtypes = [C.c_int, i32p, i32p, i32p, i64p]
+        for fn in (L.po_delta_eq3, L.po_delta_eq4):
+            fn.restype = C.c_int64
+            fn.argtypes = [C.c_int, i32p, i32p, i32p, i64p, C.c_int, C.c_int]
+        L.po_delta_row.restype = C.c_int
+        L.po_delta_row.argtypes = [C.c_int, i32p, i32p, i32p, C.c_int, i64p]
+        L.po_philox4x32_10.restype = None
+        L.po_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.po_uniform24.restype = C.c_uint32
+        L.po_uniform24.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.po_gibbs_choice.restype = C.c_int
+        L.po_gibbs_choice.argtypes = [C.c_int, i64p, C.c_float, C.c_uint32, C.POINTER(C.c_int)]
+        L.po_sample_choices.restype = C.c_int
+        L.po_sample_choices.argtypes = [C.c_int, i64p, C.c_float, C.c_uint64, C.c_uint32,
+                                        C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, i64p]
+        L.po_run.restype = C.c_int
+        L.po_run.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_void_p, C.c_int32, i32p, f32p,
+                             C.c_int64, C.c_uint64, C.c_uint64, i64p, i64p, i32p, C.c_int, i64p,
+                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.po_brute_min.restype = C.c_int64
+        L.po_brute_min.argtypes = [C.c_int, i32p, i32p, C.c_int, i32p]
+        _lib = L
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def energy(D, F, p) -> int:
+    """Eq. 1."""
+    D, F, p = _i32(D), _i32(F), _i32(p)
+    return int(lib().po_energy(D.shape[0], D, F, p))
+
+
+def influence(D, F, p) -> np.ndarray:
+    """Eq. 2 as an [N, N] array indexed (location, facility)."""
+    D, F, p = _i32(D), _i32(F), _i32(p)
+    N = D.shape[0]
+    out = np.zeros((N, N), dtype=np.int64)
+    lib().po_influence(N, D, F, p, out)
+    return out
+
+
+def delta_eq3(D, F, p, I, i, j) -> int:
+    D, F, p = _i32(D), _i32(F), _i32(p)
+    return int(lib().po_delta_eq3(D.shape[0], D, F, p, np.ascontiguousarray(I, np.int64), i, j))
+
+
+def delta_eq4(D, F, p, I, i, j) -> int:
+    D, F, p = _i32(D), _i32(F), _i32(p)
+    return int(lib().po_delta_eq4(D.shape[0], D, F, p, np.ascontiguousarray(I, np.int64), i, j))
+
+
+def delta_row(D, F, p, r) -> np.ndarray:
+    D, F, p = _i32(D), _i32(F), _i32(p)
+    N = D.shape[0]
+    out = np.zeros(N, dtype=np.int64)
+    rc = lib().po_delta_row(N, D, F, p, int(r), out)
+    if rc != PO_OK:
+        raise ValueError(f"po_delta_row failed: {rc}")
+    return out
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().po_philox4x32_10(c, k, out)
+    return out
+
+
+def uniform24(seed, r, g, rep, inst) -> int:
+    return int(lib().po_uniform24(seed, r, g, rep, inst))
+
+
+def gibbs_choice(dE, beta, u24) -> tuple[int, bool]:
+    dE = np.ascontiguousarray(dE, dtype=np.int64)
+    tie = C.c_int(0)
+    k = lib().po_gibbs_choice(dE.shape[0], dE, np.float32(beta), int(u24), C.byref(tie))
+    if k < 0:
+        raise MemoryError
+    return int(k), bool(tie.value)
+
+
+def sample_choices(dE, beta, seed, r, g0, rep, inst, M) -> np.ndarray:
+    dE = np.ascontiguousarray(dE, dtype=np.int64)
+    counts = np.zeros(dE.shape[0], dtype=np.int64)
+    rc = lib().po_sample_choices(dE.shape[0], dE, np.float32(beta), seed, r, g0, rep, inst,
+                                 int(M), counts)
+    if rc != PO_OK:
+        raise RuntimeError(rc)
+    return counts
+
+
+@dataclass
+class RunResult:
+    perm: np.ndarray
+    E: np.ndarray
+    E_best: np.ndarray
+    perm_best: np.ndarray
+    counters: np.ndarray          # [R, 3]: updates, accepted, ties
+    ties: np.ndarray              # [n, 3]: (row, sweep, location)
+    choices: np.ndarray | None    # [R, T, N]
+    E_trace: np.ndarray | None    # [R, T]
+
+
+def run(D, F, perm, beta, seed, sweep_offset=0, rep_ids=None, inst_id=0, E_best=None,
+        perm_best=None, record_choices=False, record_trace=False, paranoid=False,
+        tie_cap=100_000) -> RunResult:
+    """Run len(beta) sweeps on every row of ``perm`` (a copy; the input is
+    left untouched).  Without ``E_best`` the best state starts from the
+    initial one."""
+    D, F = _i32(D), _i32(F)
+    N = D.shape[0]
+    p = np.array(perm, dtype=np.int32, copy=True).reshape(-1, N)
+    R = p.shape[0]
+    beta = np.ascontiguousarray(beta, dtype=np.float32)
+    T = beta.shape[0]
+    E = np.zeros(R, dtype=np.int64)
+    init_best = E_best is None
+    Eb = np.zeros(R, dtype=np.int64) if init_best else np.array(E_best, dtype=np.int64, copy=True)
+    pb = (np.zeros((R, N), dtype=np.int32) if init_best
+          else np.array(perm_best, dtype=np.int32, copy=True).reshape(R, N))
+    counters = np.zeros((R, 3), dtype=np.int64)
+    tie_log = np.zeros((tie_cap, 3), dtype=np.int32)
+    tie_n = np.zeros(1, dtype=np.int64)
+    choices = np.full((R, T, N), -1, dtype=np.int32) if record_choices else None
+    trace = np.zeros((R, T), dtype=np.int64) if record_trace else None
+    reps = None if rep_ids is None else np.ascontiguousarray(rep_ids, dtype=np.int32)
+    rc = lib().po_run(N, D, F, R, None if reps is None else reps.ctypes.data, int(inst_id), p,
+                      beta, T, int(seed), int(sweep_offset), E, Eb, pb, int(init_best),
+                      counters, tie_log.ctypes.data, tie_cap, tie_n.ctypes.data,
+                      None if choices is None else choices.ctypes.data,
+                      None if trace is None else trace.ctypes.data, int(paranoid))
+    if rc != PO_OK:
+        raise RuntimeError(f"oracle run failed with status {rc}")
+    return RunResult(p, E, Eb, pb, counters, tie_log[: int(tie_n[0])].copy(), choices, trace)
+
+
+def brute_min(D, F, first=-1) -> tuple[int, np.ndarray]:
+    """Exhaustive minimum of Eq. 1 over all permutations (with p[0] = first
+    when first >= 0)."""
+    D, F = _i32(D), _i32(F)
+    N = D.shape[0]
+    bp = np.zeros(N, dtype=np.int32)
+    e = int(lib().po_brute_min(N, D, F, int(first), bp))
+    return e, bp

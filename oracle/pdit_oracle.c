@@ -1,0 +1,388 @@
+/*
+ * pdit_oracle.c -- plain CPU reference for the p-dit probabilistic Ising
+ * machine on the quadratic assignment problem (Duffee, Burling-Smith et al.,
+ * "P-dit Probabilistic Ising Machine for Solving the Quadratic Assignment
+ * Problem").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * library itself never links, loads or calls it, and it shares no code,
+ * header, table or constant with the GPU sources.
+ *
+ * What it follows:
+ *   - Eq. 1 (Introduction): E(p) = sum_i sum_j D_ij F_{p(i) p(j)}.
+ *   - Eq. 2 (Results, "Implementation"): influence of the other p-dits on
+ *     location i towards facility a,
+ *       I_i^a = - sum_j ( D_ij F_{a,p(j)} + D_ji F_{p(j),a} ),
+ *     the sum running over every location j (reading of the garbled bounds).
+ *   - Eq. 3: energy change of swapping the facilities a = p(i), b = p(j),
+ *       dE = -[ I_i^b - I_i^a + I_j^a - I_j^b
+ *               - (D_ii + D_jj - D_ij - D_ji)(F_aa + F_bb - F_ab - F_ba) ].
+ *     Eq. 4 (the same without the bracketed correction) is kept only so a
+ *     test can show it differs from the true change by 4 D_ij F_ab on
+ *     symmetric zero-diagonal data.
+ *   - Eq. 5: the update of p-dit i picks candidate k among all N locations
+ *     (k = i meaning "stay") with probability exp(-beta dE_k) / sum.
+ *   - "every p-dit initiates an update once" per iteration: a sweep visits
+ *     locations 0..N-1 in ascending order; only swaps are proposed, so the
+ *     state stays a permutation.
+ *   - Methods, "CPU-PIM Algorithm": I is kept up to date incrementally after
+ *     each accepted swap rather than recomputed.
+ *
+ * Readings where the paper is silent (the random source and the sampling
+ * arithmetic are not specified):
+ *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
+ *     key = (lo32(seed), hi32(seed)), counter = (r, g, replica, instance)
+ *     for the update of location r in global sweep g; word 0 shifted right
+ *     by 8 gives a 24-bit uniform u24 (u = u24 / 2^24);
+ *   - sampling is taken in the GPU kernel's precision: with m = min_k dE_k,
+ *     x_k = fl32(beta * fl32(dE_k - m)), w_k = expf(-x_k), and the weight is
+ *     quantised to q_k = rint(w_k * 2^30) (an integer in [0, 2^30]); the CDF
+ *     C_k = q_0 + ... + q_k is exact in 64-bit integers, Z = C_{N-1}, and the
+ *     chosen candidate is the first k with C_k * 2^24 > u24 * Z;
+ *   - a "tie" is a draw whose threshold u24 * Z lies within Z * 2^4 (a
+ *     relative 2^-20, about 1e-6) of a CDF boundary that separates two
+ *     candidates of nonzero weight: a last-ulp difference in expf could move
+ *     such a draw to the neighbouring candidate, so ties are counted.
+ *
+ * Integer arithmetic is int64 throughout; the only floating point is the
+ * float32 sampling above.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PO_OK 0
+#define PO_EINVAL (-1)
+#define PO_EMISMATCH (-2)
+#define PO_EBADPERM (-3)
+#define PO_ENOMEM (-4)
+
+#define IDX(i, j) ((int64_t)(i) * N + (j))
+
+/* ------------------------------------------------------------------ */
+/* Eq. 1                                                               */
+/* ------------------------------------------------------------------ */
+int64_t po_energy(int N, const int32_t *D, const int32_t *F, const int32_t *p)
+{
+    int64_t E = 0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            E += (int64_t)D[IDX(i, j)] * (int64_t)F[IDX(p[i], p[j])];
+    return E;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. 2: I[i*N + a] = influence on location i towards facility a      */
+/* ------------------------------------------------------------------ */
+void po_influence(int N, const int32_t *D, const int32_t *F, const int32_t *p, int64_t *I)
+{
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < N; ++a) {
+            int64_t s = 0;
+            for (int j = 0; j < N; ++j)
+                s += (int64_t)D[IDX(i, j)] * F[IDX(a, p[j])] + (int64_t)D[IDX(j, i)] * F[IDX(p[j], a)];
+            I[IDX(i, a)] = -s;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. 3 (exact) and Eq. 4 (as printed)                                */
+/* ------------------------------------------------------------------ */
+int64_t po_delta_eq3(int N, const int32_t *D, const int32_t *F, const int32_t *p,
+                     const int64_t *I, int i, int j)
+{
+    const int a = p[i], b = p[j];
+    const int64_t dterm = (int64_t)D[IDX(i, i)] + D[IDX(j, j)] - D[IDX(i, j)] - D[IDX(j, i)];
+    const int64_t fterm = (int64_t)F[IDX(a, a)] + F[IDX(b, b)] - F[IDX(a, b)] - F[IDX(b, a)];
+    return -(I[IDX(i, b)] - I[IDX(i, a)] + I[IDX(j, a)] - I[IDX(j, b)] - dterm * fterm);
+}
+
+int64_t po_delta_eq4(int N, const int32_t *D, const int32_t *F, const int32_t *p,
+                     const int64_t *I, int i, int j)
+{
+    (void)D; (void)F;
+    const int a = p[i], b = p[j];
+    return -(I[IDX(i, b)] - I[IDX(i, a)] + I[IDX(j, a)] - I[IDX(j, b)]);
+}
+
+/* Energy changes of every candidate for the update of p-dit r (Eq. 3 with
+ * I computed afresh from Eq. 2). */
+int po_delta_row(int N, const int32_t *D, const int32_t *F, const int32_t *p, int r, int64_t *out)
+{
+    if (N < 1 || r < 0 || r >= N) return PO_EINVAL;
+    int64_t *I = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * N);
+    if (!I) return PO_ENOMEM;
+    po_influence(N, D, F, p, I);
+    for (int s = 0; s < N; ++s) out[s] = po_delta_eq3(N, D, F, p, I, r, s);
+    free(I);
+    return PO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 S-box, */
+/* the key bumped by the Weyl constants between rounds.                */
+/* ------------------------------------------------------------------ */
+void po_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t prod0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t prod1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        const uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        const uint32_t y0 = hi1 ^ x1 ^ k0;
+        const uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+uint32_t po_uniform24(uint64_t seed, uint32_t r, uint32_t g, uint32_t rep, uint32_t inst)
+{
+    const uint32_t ctr[4] = {r, g, rep, inst};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    po_philox4x32_10(ctr, key, out);
+    return out[0] >> 8;
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. 5: Gibbs choice among the N candidates                          */
+/* ------------------------------------------------------------------ */
+int po_gibbs_choice(int N, const int64_t *dE, float beta, uint32_t u24, int *tie)
+{
+    uint64_t *q = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
+    if (!q) return PO_ENOMEM;
+    int64_t m = dE[0];
+    for (int s = 1; s < N; ++s)
+        if (dE[s] < m) m = dE[s];
+    uint64_t Z = 0;
+    for (int s = 0; s < N; ++s) {
+        const float d = (float)(dE[s] - m);
+        const float x = beta * d;
+        const float w = expf(-x);
+        q[s] = (uint64_t)rintf(w * 1073741824.0f); /* 2^30 */
+        Z += q[s];
+    }
+    const uint64_t target = (uint64_t)u24 * Z; /* u24 * Z < 2^63 */
+    const uint64_t thr = target >> 24;         /* C*2^24 > target <=> C > thr */
+    uint64_t C = 0, Cprev = 0;
+    int sel = N - 1;
+    for (int s = 0; s < N; ++s) {
+        Cprev = C;
+        C += q[s];
+        if (C > thr) {
+            sel = s;
+            break;
+        }
+    }
+    if (tie) {
+        const uint64_t band = Z << 4;
+        const uint64_t lo_margin = target - (Cprev << 24);
+        const uint64_t hi_margin = (C << 24) - target;
+        *tie = (Cprev > 0 && lo_margin < band) || (C < Z && hi_margin <= band);
+    }
+    free(q);
+    return sel;
+}
+
+/* Draw M updates of p-dit r from the fixed energy-change row dE, with the
+ * counters (r, g0 + m, rep, inst) for m = 0..M-1; counts[k] += 1 for each
+ * draw of candidate k. */
+int po_sample_choices(int N, const int64_t *dE, float beta, uint64_t seed, uint32_t r,
+                      uint32_t g0, uint32_t rep, uint32_t inst, int64_t M, int64_t *counts)
+{
+    for (int64_t m = 0; m < M; ++m) {
+        const uint32_t u24 = po_uniform24(seed, r, g0 + (uint32_t)m, rep, inst);
+        const int k = po_gibbs_choice(N, dE, beta, u24, NULL);
+        if (k < 0) return k;
+        counts[k] += 1;
+    }
+    return PO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* The sweep engine                                                    */
+/* ------------------------------------------------------------------ */
+static int is_permutation(int N, const int32_t *p, unsigned char *seen)
+{
+    memset(seen, 0, (size_t)N);
+    for (int i = 0; i < N; ++i) {
+        if (p[i] < 0 || p[i] >= N || seen[p[i]]) return 0;
+        seen[p[i]] = 1;
+    }
+    return 1;
+}
+
+/*
+ * Run T sweeps on each of R replicas of one instance.
+ *
+ *   perm       [R*N] in/out, each row a permutation (facility at location i)
+ *   rep_ids    [R] replica index of each row inside its instance (Philox)
+ *   inst_id    instance index (Philox)
+ *   beta       [T] inverse temperature of each sweep
+ *   sweep_off  global index of the first sweep (Philox)
+ *   E          [R] out: energy of the final state
+ *   E_best     [R] in/out, perm_best [R*N] in/out: lowest energy seen and
+ *              the first state that reached it; when init_best != 0 they
+ *              start from the initial state
+ *   counters   [R*3] out: updates, accepted swaps, ties
+ *   tie_log    optional [cap*3]: (row, sweep, location) of each tie
+ *   choices    optional [R*T*N]: the chosen candidate of every update
+ *   E_trace    optional [R*T]: the energy after every sweep
+ *   paranoid   after every sweep, check I against Eq. 2 and E against Eq. 1
+ */
+int po_run(int N, const int32_t *D, const int32_t *F, int R, const int32_t *rep_ids,
+           int32_t inst_id, int32_t *perm, const float *beta, int64_t T, uint64_t seed,
+           uint64_t sweep_off, int64_t *E, int64_t *E_best, int32_t *perm_best, int init_best,
+           int64_t *counters, int32_t *tie_log, int64_t tie_cap, int64_t *tie_n,
+           int32_t *choices, int64_t *E_trace, int paranoid)
+{
+    if (N < 2 || R < 1 || T < 0 || !D || !F || !perm || !beta || !E || !E_best || !perm_best ||
+        !counters)
+        return PO_EINVAL;
+    int64_t *I = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * N);
+    int64_t *I2 = paranoid ? (int64_t *)malloc(sizeof(int64_t) * (size_t)N * N) : NULL;
+    int64_t *dE = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    unsigned char *seen = (unsigned char *)malloc((size_t)N);
+    int rc = PO_OK;
+    if (!I || !dE || !seen || (paranoid && !I2)) {
+        rc = PO_ENOMEM;
+        goto done;
+    }
+    if (tie_n) *tie_n = 0;
+
+    for (int row = 0; row < R; ++row) {
+        int32_t *p = perm + (int64_t)row * N;
+        int32_t *pb = perm_best + (int64_t)row * N;
+        const uint32_t rep = rep_ids ? (uint32_t)rep_ids[row] : (uint32_t)row;
+        if (!is_permutation(N, p, seen)) {
+            rc = PO_EBADPERM;
+            goto done;
+        }
+        po_influence(N, D, F, p, I);
+        int64_t e = po_energy(N, D, F, p);
+        if (init_best) {
+            E_best[row] = e;
+            memcpy(pb, p, sizeof(int32_t) * (size_t)N);
+        }
+        int64_t n_upd = 0, n_acc = 0, n_tie = 0;
+        for (int64_t t = 0; t < T; ++t) {
+            const uint32_t g = (uint32_t)(sweep_off + (uint64_t)t);
+            const float b = beta[t];
+            for (int r = 0; r < N; ++r) {
+                for (int s = 0; s < N; ++s) dE[s] = po_delta_eq3(N, D, F, p, I, r, s);
+                const uint32_t u24 = po_uniform24(seed, (uint32_t)r, g, rep, (uint32_t)inst_id);
+                int tie = 0;
+                const int k = po_gibbs_choice(N, dE, b, u24, &tie);
+                if (k < 0) {
+                    rc = k;
+                    goto done;
+                }
+                ++n_upd;
+                if (tie) {
+                    ++n_tie;
+                    if (tie_log && tie_n && *tie_n < tie_cap) {
+                        tie_log[3 * *tie_n + 0] = row;
+                        tie_log[3 * *tie_n + 1] = (int32_t)g;
+                        tie_log[3 * *tie_n + 2] = r;
+                        ++*tie_n;
+                    }
+                }
+                if (choices) choices[((int64_t)row * T + t) * N + r] = k;
+                if (k == r) continue;
+                /* accept: energy, then influence of the moved facilities */
+                ++n_acc;
+                e += dE[k];
+                const int a = p[r], bfac = p[k];
+                for (int i = 0; i < N; ++i) {
+                    const int64_t du = (int64_t)D[IDX(i, r)] - D[IDX(i, k)];
+                    const int64_t dv = (int64_t)D[IDX(r, i)] - D[IDX(k, i)];
+                    for (int c = 0; c < N; ++c) {
+                        const int64_t fu = (int64_t)F[IDX(c, bfac)] - F[IDX(c, a)];
+                        const int64_t fv = (int64_t)F[IDX(bfac, c)] - F[IDX(a, c)];
+                        I[IDX(i, c)] -= du * fu + dv * fv;
+                    }
+                }
+                p[r] = bfac;
+                p[k] = a;
+                if (e < E_best[row]) {
+                    E_best[row] = e;
+                    memcpy(pb, p, sizeof(int32_t) * (size_t)N);
+                }
+            }
+            if (E_trace) E_trace[(int64_t)row * T + t] = e;
+            if (paranoid) {
+                po_influence(N, D, F, p, I2);
+                if (memcmp(I, I2, sizeof(int64_t) * (size_t)N * N) != 0 ||
+                    e != po_energy(N, D, F, p)) {
+                    rc = PO_EMISMATCH;
+                    goto done;
+                }
+            }
+        }
+        E[row] = e;
+        counters[3 * row + 0] = n_upd;
+        counters[3 * row + 1] = n_acc;
+        counters[3 * row + 2] = n_tie;
+    }
+done:
+    free(I);
+    free(I2);
+    free(dE);
+    free(seen);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exhaustive minimum of Eq. 1 (small N): all permutations with p[0] =  */
+/* first (or all of them when first < 0), enumerated by Heap's method. */
+/* ------------------------------------------------------------------ */
+int64_t po_brute_min(int N, const int32_t *D, const int32_t *F, int first, int32_t *best_perm)
+{
+    int32_t p[32], rest[32], c[32];
+    if (N < 1 || N > 16) return INT64_MIN;
+    int off = 0, m = 0;
+    if (first >= 0) {
+        p[0] = first;
+        off = 1;
+        for (int v = 0; v < N; ++v)
+            if (v != first) rest[m++] = v;
+    } else {
+        for (int v = 0; v < N; ++v) rest[m++] = v;
+    }
+    for (int k = 0; k < m; ++k) {
+        p[off + k] = rest[k];
+        c[k] = 0;
+    }
+    int64_t best = po_energy(N, D, F, p);
+    if (best_perm) memcpy(best_perm, p, sizeof(int32_t) * (size_t)N);
+    int k = 1;
+    while (k < m) {
+        if (c[k] < k) {
+            const int j = (k % 2 == 0) ? 0 : c[k];
+            const int32_t tmp = p[off + j];
+            p[off + j] = p[off + k];
+            p[off + k] = tmp;
+            const int64_t e = po_energy(N, D, F, p);
+            if (e < best) {
+                best = e;
+                if (best_perm) memcpy(best_perm, p, sizeof(int32_t) * (size_t)N);
+            }
+            ++c[k];
+            k = 1;
+        } else {
+            c[k] = 0;
+            ++k;
+        }
+    }
+    return best;
+}
