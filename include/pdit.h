@@ -1,0 +1,230 @@
+/*
+ * pdit.h -- C ABI of the MI355X (gfx950) p-dit sweep library for the
+ * symmetric quadratic assignment problem.
+ *
+ * The method (Duffee, Burling-Smith et al., "P-dit Probabilistic Ising
+ * Machine for Solving the Quadratic Assignment Problem"):
+ *   - the objective is Eq. 1, E(p) = sum_i sum_j D_ij F_{p(i) p(j)}, for
+ *     symmetric integer D (distances between locations) and F (flows
+ *     between facilities); p(i) is the facility at location i;
+ *   - there is one p-dit per location; a sweep ("iteration", Results,
+ *     "Implementation") updates locations 0..N-1 in order;
+ *   - the update of location r considers swapping its facility with that of
+ *     every location s (s = r meaning "stay") and draws s with the Gibbs
+ *     probability of Eq. 5, exp(-beta dE_rs) / sum_k exp(-beta dE_rk), where
+ *     dE is the exact integer swap change of Eq. 3;
+ *   - dE is read from the influence matrix H = D F[p,p] (H_ik =
+ *     sum_j D_ij F_{p(j) p(k)}); for symmetric data the influence of Eq. 2
+ *     is I_i^{p(k)} = -2 H_ik, and after an accepted swap H is brought up to
+ *     date by an O(N^2) rank-1 update (Methods, "CPU-PIM Algorithm": the
+ *     influence is kept incrementally);
+ *   - replicas (the paper's duplicated replica sets, "GPU Implementations")
+ *     are independent chains and run in parallel.
+ *
+ * Random numbers: the update of location r in global sweep g of replica k
+ * of instance n uses word 0 of Philox4x32-10 (Salmon et al., SC'11) with
+ * key (lo32(seed), hi32(seed)) and counter (r, g, k, n); u24 = word0 >> 8.
+ * The draw takes the first candidate s with C_s * 2^24 > u24 * Z, where
+ * C_s is the running sum over s' <= s of q_s' = rint(expf(-fl32(beta *
+ * fl32(dE_s' - min dE))) * 2^30) and Z = C_{N-1}.  All integer work (H, dE,
+ * E) is exact; energies are reported as int64.
+ *
+ * Conventions for every entry point:
+ *   - every pointer argument named as "device" is device memory of the
+ *     context's GPU (for example a torch tensor's data_ptr()); the caller
+ *     owns it and must keep it alive until the context's stream has passed
+ *     the call;
+ *   - matrices are row-major, int32, N x N; permutations are int32 rows of
+ *     length N (entry i = facility at location i, 0-based);
+ *   - calls are ordered on the context's stream and may return before the
+ *     GPU has finished; pdit_sync() waits and reports deferred errors;
+ *   - a context is not thread-safe: use one per host thread;
+ *   - the return value is PDIT_OK (0) or a negative status; the library
+ *     never aborts or prints; pdit_last_error() gives a message.
+ */
+#ifndef PDIT_H
+#define PDIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PDIT_OK 0
+#define PDIT_EINVAL (-1)    /* null pointer, N < 2, N > PDIT_NMAX, R < 1, n_sweeps < 0, bad option */
+#define PDIT_ENOTSYM (-2)   /* D or F is not symmetric */
+#define PDIT_EBADPERM (-3)  /* a permutation row is not a permutation of 0..N-1 */
+#define PDIT_EOVERFLOW (-4) /* an exact integer bound does not fit the requested arithmetic */
+#define PDIT_ENOMEM (-5)    /* device allocation failed */
+#define PDIT_EDEVICE (-6)   /* HIP runtime error (text in pdit_last_error) */
+#define PDIT_EBETA (-7)     /* an inverse temperature is NaN, infinite or negative */
+#define PDIT_ESTATE (-8)    /* query before any run, or buffers of the wrong run */
+
+#define PDIT_NMAX 512       /* largest supported instance size */
+
+/* How H = D F[p,p] is recomputed at the start of a run (step "H recompute"). */
+#define PDIT_RECOMPUTE_AUTO 0   /* cheapest exact mode for the data */
+#define PDIT_RECOMPUTE_PLAIN 1  /* vector ALU, int64 accumulation */
+#define PDIT_RECOMPUTE_I8 2     /* int8 MFMA, int32 accumulation: needs |D|,|F| <= 127 */
+#define PDIT_RECOMPUTE_BF16 3   /* bf16 MFMA, fp32 accumulation: needs |D|,|F| <= 256 and |H| < 2^24 */
+#define PDIT_RECOMPUTE_SPLIT 4  /* int8 MFMA on 7-bit byte planes, int64 combine: needs |D|,|F| < 2^14 */
+
+/* Which sweep kernel runs. */
+#define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else plain */
+#define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
+#define PDIT_SWEEP_FAST 2   /* H in LDS, speculative row evaluation; N <= 64, int32 range */
+
+typedef struct pdit_ctx pdit_t;
+
+typedef struct {
+    int device;           /* HIP device ordinal */
+    void *stream;         /* hipStream_t to run on; NULL = the device's null stream */
+    int recompute;        /* PDIT_RECOMPUTE_* */
+    int sweep;            /* PDIT_SWEEP_* */
+    int replicas_per_block; /* fast kernel: replicas (waves) per workgroup, 0 = tuned default */
+    int seq_threshold;    /* fast kernel: accepted moves in a sweep above which the next sweep
+                             runs one update at a time; < 0 = tuned default */
+} pdit_opts;
+
+typedef struct {
+    int64_t updates;      /* p-dit updates done (stays included) */
+    int64_t accepted;     /* updates that swapped two facilities */
+    int64_t ties;         /* draws within 2^-20 of a boundary between two candidates */
+} pdit_counters_t;
+
+/* One instance of a batched run (pdit_run_sweeps_batch). */
+typedef struct {
+    int32_t N;            /* instance size, 2..PDIT_NMAX */
+    int32_t R;            /* replicas of this instance, >= 1 */
+    const int32_t *D;     /* device, N x N, symmetric */
+    const int32_t *F;     /* device, N x N, symmetric */
+    int32_t *perm;        /* device, R x N, in/out */
+    const float *beta;    /* device, n_sweeps values */
+} pdit_instance;
+
+/* Fills *opts with the defaults (device 0, null stream, AUTO modes). */
+void pdit_default_opts(pdit_opts *opts);
+
+/* Creates a context on opts->device (opts may be NULL for defaults).
+ * *out receives the context; on error *out is NULL. */
+int pdit_create(pdit_t **out, const pdit_opts *opts);
+
+/* Waits for the context's stream, frees everything it owns.  NULL is a no-op. */
+int pdit_destroy(pdit_t *ctx);
+
+/*
+ * Runs n_sweeps sweeps (Results, "Implementation": every p-dit initiates one
+ * update per iteration; Eq. 3 and Eq. 5) on R independent replicas of one
+ * instance.
+ *   N       instance size, 2..PDIT_NMAX
+ *   D, F    device int32 N x N, symmetric (PDIT_ENOTSYM otherwise)
+ *   R       replicas, >= 1
+ *   perm    device int32 R x N, in/out: initial permutations, replaced by the
+ *           final ones (PDIT_EBADPERM if a row is not a permutation)
+ *   beta    device float n_sweeps: inverse temperature of each sweep,
+ *           finite and >= 0 (PDIT_EBETA otherwise)
+ *   seed    Philox key
+ * Sweep t uses global sweep index g = offset + t, where offset is the
+ * context's sweep offset, which then advances by n_sweeps; so two calls of
+ * T1 and T2 sweeps give the same result as one call of T1 + T2.  H is
+ * recomputed exactly from perm at the start of every call.  The best state
+ * (pdit_best) carries over between calls with the same N and R and is reset
+ * otherwise.  Validation reads small summaries back to the host, so the call
+ * synchronises once before the sweeps are queued; the sweeps themselves run
+ * asynchronously.
+ */
+int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                    int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed);
+
+/*
+ * Runs n_sweeps sweeps on every replica of n_inst instances of uneven size in
+ * one persistent launch.  Instance n's replicas use Philox counter word 3 = n.
+ * Replica state is laid out instance after instance: R_total = sum R_n
+ * energies, and permutation rows of each instance's own length N_n.
+ * inst points to host memory (n_inst entries).
+ */
+int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst,
+                          int64_t n_sweeps, uint64_t seed);
+
+/* E_out: device int64 R_total; current energies (Eq. 1) of the last run's
+ * final permutations. */
+int pdit_energy(pdit_t *ctx, int64_t *E_out);
+
+/* E_best: device int64 R_total; perm_best: device int32, R_total rows of the
+ * instance's N (packed instance after instance).  The lowest energy seen
+ * since the best state was last reset, and the first permutation that
+ * reached it. */
+int pdit_best(pdit_t *ctx, int64_t *E_best, int32_t *perm_best);
+
+/* Host struct: totals over all replicas of the last run. */
+int pdit_counters(pdit_t *ctx, pdit_counters_t *out);
+
+/* Device int64 R_total x 3: per-replica (updates, accepted, ties) of the last run. */
+int pdit_replica_counters(pdit_t *ctx, int64_t *out);
+
+/* Sets / reads the global index of the next sweep (Philox counter word 1). */
+int pdit_set_sweep_offset(pdit_t *ctx, uint64_t offset);
+int pdit_get_sweep_offset(pdit_t *ctx, uint64_t *offset);
+
+/* Forgets the best state: the next run starts it from its initial state. */
+int pdit_reset(pdit_t *ctx);
+
+/* Waits for the context's stream; returns any deferred device-side error. */
+int pdit_sync(pdit_t *ctx);
+
+/* Message of the last error on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char *pdit_last_error(const pdit_t *ctx);
+
+/*
+ * Recording for tests and tracing; buffers apply to the next run only and
+ * are then cleared.  choices: device int32 R_total x n_sweeps x N, the drawn
+ * candidate of every update; E_trace: device int64 R_total x n_sweeps, the
+ * energy after every sweep.  Either may be NULL.  Single-instance runs only.
+ */
+int pdit_set_recording(pdit_t *ctx, int32_t *choices, int64_t *E_trace);
+
+/*
+ * Step "H recompute" on its own: H = D F[p,p] and E = trace(H) (= Eq. 1)
+ * for R permutations, in the given PDIT_RECOMPUTE_* mode (PDIT_EOVERFLOW if
+ * that mode is not exact for the data).
+ *   H_out  device int64 R x N x N (may be NULL), E_out device int64 R.
+ */
+int pdit_h_recompute(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                     const int32_t *perm, int mode, int64_t *H_out, int64_t *E_out);
+
+/*
+ * The energy changes the sweep kernels compute for the update of location r
+ * (Eq. 3 specialised to symmetric data), for each of R permutations:
+ *   delta_out  device int64 R x N; entry s is the change of swapping the
+ *              facilities at r and s (0 at s = r).
+ */
+int pdit_debug_delta(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                     const int32_t *perm, int32_t r, int64_t *delta_out);
+
+/*
+ * The sweep kernels' Gibbs choice on its own: for each of M rows of N energy
+ * changes (device int64 M x N) and device float beta[M], device uint32
+ * u24[M], writes the chosen candidate (device int32 M) and a tie flag
+ * (device int32 M, may be NULL).
+ */
+int pdit_debug_choice(pdit_t *ctx, int32_t N, int32_t M, const int64_t *delta, const float *beta,
+                      const uint32_t *u24, int32_t *choice, int32_t *tie);
+
+/* Device durations of the last run's steps, from HIP events recorded on the
+ * context's stream around them (waits for the events): recompute_ms covers
+ * the H recompute, sweep_ms the sweep kernel.  Either pointer may be NULL. */
+int pdit_last_timing(pdit_t *ctx, double *recompute_ms, double *sweep_ms);
+
+/* Philox4x32-10 word 0 >> 8 for M counters (device uint32 M x 4) under seed,
+ * written to device uint32 M. */
+int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t seed,
+                         uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDIT_H */

@@ -1,0 +1,480 @@
+// api.hip -- the C ABI (include/pdit.h): validation, exact-width and mode
+// selection, buffer management and kernel sequencing on the caller's stream.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "pdit_internal.h"
+
+using pdit::InstanceStats;
+
+namespace {
+
+int fail(pdit_t *ctx, int code, const char *msg) {
+    if (ctx) ctx->last_error = msg;
+    return code;
+}
+
+int fail_hip(pdit_t *ctx, hipError_t e, const char *where) {
+    if (ctx) {
+        ctx->last_error = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    (void)hipGetLastError();  // clear the sticky-free error state
+    return e == hipErrorOutOfMemory ? PDIT_ENOMEM : PDIT_EDEVICE;
+}
+
+#define PDIT_HIP(ctx, expr)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return fail_hip(ctx, e_, #expr); \
+    } while (0)
+
+int ensure(pdit_t *ctx, pdit::DeviceBuffer &b, size_t bytes) {
+    if (b.bytes >= bytes && b.ptr) return PDIT_OK;
+    if (b.ptr) {
+        PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        PDIT_HIP(ctx, hipFree(b.ptr));
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    PDIT_HIP(ctx, hipMalloc(&b.ptr, want));
+    b.bytes = want;
+    return PDIT_OK;
+}
+
+void free_state(pdit::ReplicaState &s) {
+    hipFree(s.E);
+    hipFree(s.E_best);
+    hipFree(s.perm_best);
+    hipFree(s.counters);
+    s.E = s.E_best = s.counters = nullptr;
+    s.perm_best = nullptr;
+    s.R_total = s.perm_total = 0;
+    s.n_inst = 0;
+    s.Ns.clear();
+    s.Rs.clear();
+    s.best_valid = false;
+}
+
+// (Re)shape the replica state for a run; returns PDIT_OK and sets *fresh when
+// the best state has to start from the initial one.
+int shape_state(pdit_t *ctx, const std::vector<int32_t> &Ns, const std::vector<int32_t> &Rs,
+                bool *fresh) {
+    pdit::ReplicaState &s = ctx->st;
+    const bool same = s.E && s.Ns == Ns && s.Rs == Rs;
+    if (!same) {
+        PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        free_state(s);
+        int64_t R_total = 0, perm_total = 0;
+        for (size_t k = 0; k < Ns.size(); ++k) {
+            R_total += Rs[k];
+            perm_total += (int64_t)Rs[k] * Ns[k];
+        }
+        PDIT_HIP(ctx, hipMalloc(&s.E, sizeof(int64_t) * R_total));
+        PDIT_HIP(ctx, hipMalloc(&s.E_best, sizeof(int64_t) * R_total));
+        PDIT_HIP(ctx, hipMalloc(&s.perm_best, sizeof(int32_t) * perm_total));
+        PDIT_HIP(ctx, hipMalloc(&s.counters, sizeof(int64_t) * 3 * R_total));
+        s.Ns = Ns;
+        s.Rs = Rs;
+        s.n_inst = (int)Ns.size();
+        s.R_total = R_total;
+        s.perm_total = perm_total;
+        s.best_valid = false;
+    }
+    *fresh = !s.best_valid;
+    return PDIT_OK;
+}
+
+// Reads the instance summary (one host synchronisation) and validates.
+int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
+                  const int32_t *perm, const float *beta, int64_t T, InstanceStats *st) {
+    int rc = ensure(ctx, ctx->scratch, sizeof(InstanceStats));
+    if (rc) return rc;
+    InstanceStats *dev = (InstanceStats *)ctx->scratch.ptr;
+    PDIT_HIP(ctx, pdit::launch_instance_stats(ctx->stream, N, D, F, R, perm, beta, T, dev));
+    PDIT_HIP(ctx, hipMemcpyAsync(ctx->stats_host, dev, sizeof(InstanceStats),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *st = *ctx->stats_host;
+    if (st->asym_d || st->asym_f) return fail(ctx, PDIT_ENOTSYM, "D or F is not symmetric");
+    if (st->bad_perm_rows)
+        return fail(ctx, PDIT_EBADPERM, "a row of perm is not a permutation of 0..N-1");
+    if (st->bad_beta) return fail(ctx, PDIT_EBETA, "an inverse temperature is NaN, infinite or negative");
+    // |H| <= bound, |dE| <= 8 bound + 16 max|D| max|F| must stay far inside int64
+    const __int128 b1 = (__int128)st->max_abs_d * st->max_colsum_f;
+    const __int128 b2 = (__int128)st->max_abs_f * st->max_rowsum_d;
+    const __int128 b = b1 < b2 ? b1 : b2;
+    if (b > ((__int128)1 << 58))
+        return fail(ctx, PDIT_EOVERFLOW, "the exact bound on H exceeds the int64 range of the sweeps");
+    return PDIT_OK;
+}
+
+bool recompute_exact(int mode, const InstanceStats &st, int64_t bound) {
+    const int32_t mx = std::max(st.max_abs_d, st.max_abs_f);
+    switch (mode) {
+        case PDIT_RECOMPUTE_PLAIN: return true;
+        case PDIT_RECOMPUTE_I8: return mx <= 127 && bound <= INT32_MAX;
+        case PDIT_RECOMPUTE_BF16: return mx <= 256 && bound < (1 << 24);
+        case PDIT_RECOMPUTE_SPLIT: return mx < (1 << 14);
+        default: return false;
+    }
+}
+
+int pick_recompute(pdit_t *ctx, const InstanceStats &st, int64_t bound, int requested, int *mode) {
+    if (requested == PDIT_RECOMPUTE_AUTO) {
+        for (int m : {PDIT_RECOMPUTE_I8, PDIT_RECOMPUTE_BF16, PDIT_RECOMPUTE_SPLIT, PDIT_RECOMPUTE_PLAIN})
+            if (recompute_exact(m, st, bound)) {
+                *mode = m;
+                return PDIT_OK;
+            }
+    }
+    if (requested < PDIT_RECOMPUTE_PLAIN || requested > PDIT_RECOMPUTE_SPLIT)
+        return fail(ctx, PDIT_EINVAL, "unknown recompute mode");
+    if (!recompute_exact(requested, st, bound))
+        return fail(ctx, PDIT_EOVERFLOW, "the requested recompute mode is not exact for this data");
+    *mode = requested;
+    return PDIT_OK;
+}
+
+hipError_t run_recompute(pdit_t *ctx, int mode, int N, const int32_t *D, const int32_t *F, int R,
+                         const int32_t *perm, void *H, bool h64, int64_t *E) {
+    if (mode == PDIT_RECOMPUTE_PLAIN)
+        return pdit::launch_h_recompute_plain(ctx->stream, N, D, F, R, perm, H, h64, E);
+    return pdit::launch_h_recompute_mfma(ctx->stream, mode, N, D, F, R, perm, H, h64, E);
+}
+
+}  // namespace
+
+extern "C" {
+
+void pdit_default_opts(pdit_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->stream = nullptr;
+    o->recompute = PDIT_RECOMPUTE_AUTO;
+    o->sweep = PDIT_SWEEP_AUTO;
+    o->replicas_per_block = 0;
+    o->seq_threshold = -1;
+}
+
+int pdit_create(pdit_t **out, const pdit_opts *opts) {
+    if (!out) return PDIT_EINVAL;
+    *out = nullptr;
+    pdit_t *ctx = new (std::nothrow) pdit_ctx();
+    if (!ctx) return PDIT_ENOMEM;
+    if (opts)
+        ctx->opts = *opts;
+    else
+        pdit_default_opts(&ctx->opts);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ctx->opts.device < 0 || ctx->opts.device >= ndev) {
+        (void)hipGetLastError();
+        delete ctx;
+        return PDIT_EDEVICE;
+    }
+    if (hipSetDevice(ctx->opts.device) != hipSuccess) {
+        delete ctx;
+        return PDIT_EDEVICE;
+    }
+    // NULL is the device's null stream, which is also torch's default stream
+    ctx->stream = (hipStream_t)ctx->opts.stream;
+    for (auto &e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            pdit_destroy(ctx);
+            return PDIT_EDEVICE;
+        }
+    }
+    if (hipHostMalloc((void **)&ctx->stats_host, sizeof(InstanceStats), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc((void **)&ctx->err_dev, sizeof(int32_t)) != hipSuccess) {
+        pdit_destroy(ctx);
+        return PDIT_ENOMEM;
+    }
+    *out = ctx;
+    return PDIT_OK;
+}
+
+int pdit_destroy(pdit_t *ctx) {
+    if (!ctx) return PDIT_OK;
+    hipSetDevice(ctx->opts.device);
+    hipStreamSynchronize(ctx->stream);
+    free_state(ctx->st);
+    hipFree(ctx->h_buf.ptr);
+    hipFree(ctx->scratch.ptr);
+    hipFree(ctx->err_dev);
+    for (auto &e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    if (ctx->stats_host) hipHostFree(ctx->stats_host);
+    delete ctx;
+    return PDIT_OK;
+}
+
+int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                    int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!D || !F || !perm || (!beta && n_sweeps > 0))
+        return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
+    if (R < 1) return fail(ctx, PDIT_EINVAL, "R must be >= 1");
+    if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+
+    InstanceStats st;
+    int rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st);
+    if (rc) return rc;
+    const int64_t bound = pdit::h_bound(st);
+    const bool h64 = bound > INT32_MAX;
+    const bool fast_ok = pdit::sweep_fast_supports(N) && !h64 &&
+                         2 * pdit::delta_bound(st) < (int64_t)INT32_MAX;
+    bool use_fast = false;
+    if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
+        if (!fast_ok)
+            return fail(ctx, PDIT_EOVERFLOW,
+                        "the fast sweep kernel needs N <= 64 and energy changes within int32");
+        use_fast = true;
+    } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
+        use_fast = fast_ok;
+    }
+    int mode = 0;
+    rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
+    if (rc) return rc;
+
+    rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
+    if (rc) return rc;
+    bool fresh = false;
+    rc = shape_state(ctx, {N}, {R}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
+    if (fresh) {
+        PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * R, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+        PDIT_HIP(ctx, hipMemcpyAsync(S.perm_best, perm, sizeof(int32_t) * (size_t)R * N,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    pdit::SweepArgs a{};
+    a.N = N;
+    a.R = R;
+    a.D = D;
+    a.F = F;
+    a.perm = perm;
+    a.H = ctx->h_buf.ptr;
+    a.E = S.E;
+    a.E_best = S.E_best;
+    a.perm_best = S.perm_best;
+    a.counters = S.counters;
+    a.beta = beta;
+    a.T = n_sweeps;
+    a.seed = seed;
+    a.sweep_offset = ctx->sweep_offset;
+    a.inst_id = 0;
+    a.choices = ctx->rec_choices;
+    a.E_trace = ctx->rec_trace;
+    a.replicas_per_block = ctx->opts.replicas_per_block;
+    a.seq_threshold = ctx->opts.seq_threshold;
+    a.zero_diag = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    if (n_sweeps > 0) {
+        if (use_fast)
+            PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, a));
+        else
+            PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
+    } else {
+        PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * R, ctx->stream));
+    }
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->timed = true;
+    ctx->rec_choices = nullptr;
+    ctx->rec_trace = nullptr;
+    ctx->sweep_offset += (uint64_t)n_sweeps;
+    ctx->last_updates = (int64_t)R * N * n_sweeps;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
+int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst,
+                          int64_t n_sweeps, uint64_t seed) {
+    (void)n_inst;
+    (void)inst;
+    (void)n_sweeps;
+    (void)seed;
+    return fail(ctx, PDIT_EINVAL, "batched runs are not available in this build");
+}
+
+int pdit_energy(pdit_t *ctx, int64_t *E_out) {
+    if (!ctx || !E_out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (!ctx->st.E || !ctx->st.best_valid) return fail(ctx, PDIT_ESTATE, "no run yet");
+    PDIT_HIP(ctx, hipMemcpyAsync(E_out, ctx->st.E, sizeof(int64_t) * ctx->st.R_total,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    return PDIT_OK;
+}
+
+int pdit_best(pdit_t *ctx, int64_t *E_best, int32_t *perm_best) {
+    if (!ctx || (!E_best && !perm_best)) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (!ctx->st.E || !ctx->st.best_valid) return fail(ctx, PDIT_ESTATE, "no run yet");
+    if (E_best)
+        PDIT_HIP(ctx, hipMemcpyAsync(E_best, ctx->st.E_best, sizeof(int64_t) * ctx->st.R_total,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+    if (perm_best)
+        PDIT_HIP(ctx, hipMemcpyAsync(perm_best, ctx->st.perm_best,
+                                     sizeof(int32_t) * ctx->st.perm_total,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+    return PDIT_OK;
+}
+
+int pdit_replica_counters(pdit_t *ctx, int64_t *out) {
+    if (!ctx || !out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (!ctx->st.counters || !ctx->st.best_valid) return fail(ctx, PDIT_ESTATE, "no run yet");
+    PDIT_HIP(ctx, hipMemcpyAsync(out, ctx->st.counters, sizeof(int64_t) * 3 * ctx->st.R_total,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    return PDIT_OK;
+}
+
+int pdit_counters(pdit_t *ctx, pdit_counters_t *out) {
+    if (!ctx || !out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (!ctx->st.counters || !ctx->st.best_valid) return fail(ctx, PDIT_ESTATE, "no run yet");
+    std::vector<int64_t> h(3 * ctx->st.R_total);
+    PDIT_HIP(ctx, hipMemcpyAsync(h.data(), ctx->st.counters, sizeof(int64_t) * h.size(),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    out->updates = out->accepted = out->ties = 0;
+    for (int64_t k = 0; k < ctx->st.R_total; ++k) {
+        out->updates += h[3 * k];
+        out->accepted += h[3 * k + 1];
+        out->ties += h[3 * k + 2];
+    }
+    return PDIT_OK;
+}
+
+int pdit_set_sweep_offset(pdit_t *ctx, uint64_t offset) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->sweep_offset = offset;
+    return PDIT_OK;
+}
+
+int pdit_get_sweep_offset(pdit_t *ctx, uint64_t *offset) {
+    if (!ctx || !offset) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    *offset = ctx->sweep_offset;
+    return PDIT_OK;
+}
+
+int pdit_reset(pdit_t *ctx) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->st.best_valid = false;
+    return PDIT_OK;
+}
+
+int pdit_sync(pdit_t *ctx) {
+    if (!ctx) return PDIT_EINVAL;
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PDIT_OK;
+}
+
+const char *pdit_last_error(const pdit_t *ctx) {
+    if (!ctx) return "null context";
+    return ctx->last_error.c_str();
+}
+
+int pdit_set_recording(pdit_t *ctx, int32_t *choices, int64_t *E_trace) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->rec_choices = choices;
+    ctx->rec_trace = E_trace;
+    return PDIT_OK;
+}
+
+int pdit_h_recompute(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                     const int32_t *perm, int mode, int64_t *H_out, int64_t *E_out) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!D || !F || !perm || !E_out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 2 || N > PDIT_NMAX || R < 1) return fail(ctx, PDIT_EINVAL, "bad N or R");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    InstanceStats st;
+    int rc = instance_prep(ctx, N, D, F, R, perm, nullptr, 0, &st);
+    if (rc) return rc;
+    const int64_t bound = pdit::h_bound(st);
+    const bool h64 = bound > INT32_MAX;
+    int m = 0;
+    rc = pick_recompute(ctx, st, bound, mode, &m);
+    if (rc) return rc;
+    rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
+    if (rc) return rc;
+    PDIT_HIP(ctx, run_recompute(ctx, m, N, D, F, R, perm, ctx->h_buf.ptr, h64, E_out));
+    if (H_out) {
+        const int64_t count = (int64_t)R * N * N;
+        if (h64)
+            PDIT_HIP(ctx, hipMemcpyAsync(H_out, ctx->h_buf.ptr, sizeof(int64_t) * count,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+        else
+            PDIT_HIP(ctx, pdit::launch_widen_h(ctx->stream, count, (const int32_t *)ctx->h_buf.ptr,
+                                               H_out));
+    }
+    return PDIT_OK;
+}
+
+int pdit_debug_delta(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                     const int32_t *perm, int32_t r, int64_t *delta_out) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!D || !F || !perm || !delta_out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 2 || N > PDIT_NMAX || R < 1 || r < 0 || r >= N)
+        return fail(ctx, PDIT_EINVAL, "bad N, R or r");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    InstanceStats st;
+    int rc = instance_prep(ctx, N, D, F, R, perm, nullptr, 0, &st);
+    if (rc) return rc;
+    rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * 8 + sizeof(int64_t) * R);
+    if (rc) return rc;
+    int64_t *H = (int64_t *)ctx->h_buf.ptr;
+    int64_t *E = H + (size_t)R * N * N;
+    PDIT_HIP(ctx, pdit::launch_h_recompute_plain(ctx->stream, N, D, F, R, perm, H, true, E));
+    PDIT_HIP(ctx, pdit::launch_debug_delta(ctx->stream, N, D, F, R, perm, H, r, delta_out));
+    return PDIT_OK;
+}
+
+int pdit_debug_choice(pdit_t *ctx, int32_t N, int32_t M, const int64_t *delta, const float *beta,
+                      const uint32_t *u24, int32_t *choice, int32_t *tie) {
+    if (!ctx) return PDIT_EINVAL;
+    if (!delta || !beta || !u24 || !choice) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 1 || N > PDIT_NMAX || M < 0) return fail(ctx, PDIT_EINVAL, "bad N or M");
+    if (M == 0) return PDIT_OK;
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    PDIT_HIP(ctx, pdit::launch_debug_choice(ctx->stream, N, M, delta, beta, u24, choice, tie));
+    return PDIT_OK;
+}
+
+int pdit_last_timing(pdit_t *ctx, double *recompute_ms, double *sweep_ms) {
+    if (!ctx) return PDIT_EINVAL;
+    if (!ctx->timed) return fail(ctx, PDIT_ESTATE, "no timed run yet");
+    PDIT_HIP(ctx, hipEventSynchronize(ctx->ev[2]));
+    float a = 0.f, b = 0.f;
+    PDIT_HIP(ctx, hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+    PDIT_HIP(ctx, hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+    if (recompute_ms) *recompute_ms = a;
+    if (sweep_ms) *sweep_ms = b;
+    return PDIT_OK;
+}
+
+int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t seed,
+                         uint32_t *out) {
+    if (!ctx) return PDIT_EINVAL;
+    if (!ctr || !out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (M < 0) return fail(ctx, PDIT_EINVAL, "bad M");
+    if (M == 0) return PDIT_OK;
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    PDIT_HIP(ctx, pdit::launch_debug_uniform24(ctx->stream, M, ctr, seed, out));
+    return PDIT_OK;
+}
+
+}  // extern "C"

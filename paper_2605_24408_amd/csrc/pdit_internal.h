@@ -1,0 +1,127 @@
+// pdit_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pdit.h"
+
+namespace pdit {
+
+// Per-instance data summary computed on the device (step "instance prep").
+struct InstanceStats {
+    int32_t max_abs_d;      // max |D_ij|
+    int32_t max_abs_f;      // max |F_ij|
+    int64_t max_rowsum_d;   // max_i sum_j |D_ij|
+    int64_t max_colsum_f;   // max_c sum_j |F_jc|
+    int32_t asym_d;         // number of (i, j) with D_ij != D_ji
+    int32_t asym_f;
+    int32_t bad_perm_rows;  // rows of perm that are not permutations
+    int32_t bad_beta;       // beta values that are NaN, infinite or negative
+};
+
+// Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=
+// min(max|D| * max col-sum |F|, max|F| * max row-sum |D|).
+inline int64_t h_bound(const InstanceStats &s) {
+    const int64_t b1 = (int64_t)s.max_abs_d * s.max_colsum_f;
+    const int64_t b2 = (int64_t)s.max_abs_f * s.max_rowsum_d;
+    return b1 < b2 ? b1 : b2;
+}
+
+// Bound on |dE| = |2 (H_rs + H_sr - H_rr - H_ss) + (D_rr + D_ss - 2 D_rs)
+// (F_aa + F_bb - 2 F_ab)|.
+inline int64_t delta_bound(const InstanceStats &s) {
+    return 8 * h_bound(s) + 16 * (int64_t)s.max_abs_d * s.max_abs_f;
+}
+
+// Per-replica state buffers owned by the context (device memory).
+struct ReplicaState {
+    int n_inst = 0;
+    std::vector<int32_t> Ns, Rs;      // shape signature of the last run
+    int64_t R_total = 0;
+    int64_t perm_total = 0;           // sum R_n * N_n
+    int64_t *E = nullptr;             // [R_total]
+    int64_t *E_best = nullptr;        // [R_total]
+    int32_t *perm_best = nullptr;     // [perm_total]
+    int64_t *counters = nullptr;      // [R_total * 3]
+    bool best_valid = false;
+};
+
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace pdit
+
+struct pdit_ctx {
+    pdit_opts opts;
+    hipStream_t stream = nullptr;
+    uint64_t sweep_offset = 0;
+    std::string last_error;
+    pdit::ReplicaState st;
+    pdit::DeviceBuffer h_buf;         // H of all replicas (int32 or int64)
+    pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
+    pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
+    int32_t *err_dev = nullptr;       // deferred device error word
+    int32_t *rec_choices = nullptr;   // recording buffers for the next run
+    int64_t *rec_trace = nullptr;
+    int64_t last_updates = 0;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // before recompute, before sweep, after sweep
+    bool timed = false;                               // events of the last run are recorded
+};
+
+namespace pdit {
+
+// ---- launchers (each returns a hipError_t) --------------------------------
+hipError_t launch_instance_stats(hipStream_t s, int N, const int32_t *D, const int32_t *F,
+                                 int R, const int32_t *perm, const float *beta, int64_t T,
+                                 InstanceStats *out_dev);
+
+hipError_t launch_h_recompute_plain(hipStream_t s, int N, const int32_t *D, const int32_t *F,
+                                    int R, const int32_t *perm, void *H, bool h64,
+                                    int64_t *E);
+hipError_t launch_h_recompute_mfma(hipStream_t s, int mode, int N, const int32_t *D,
+                                   const int32_t *F, int R, const int32_t *perm, void *H,
+                                   bool h64, int64_t *E);
+hipError_t launch_widen_h(hipStream_t s, int64_t count, const int32_t *src, int64_t *dst);
+
+struct SweepArgs {
+    int N;
+    int R;
+    const int32_t *D;
+    const int32_t *F;
+    int32_t *perm;           // [R][N] in/out
+    void *H;                 // [R][N][N] int32 or int64, initial H (overwritten by plain)
+    int64_t *E;              // [R] in: initial energies; out: final
+    int64_t *E_best;         // [R] in/out
+    int32_t *perm_best;      // [R][N] in/out
+    int64_t *counters;       // [R][3] out
+    const float *beta;       // [T]
+    int64_t T;
+    uint64_t seed;
+    uint64_t sweep_offset;
+    uint32_t inst_id;
+    int32_t *choices;        // optional [R][T][N]
+    int64_t *E_trace;        // optional [R][T]
+    int replicas_per_block;
+    int seq_threshold;
+    bool zero_diag;          // D and F have zero diagonals
+};
+
+hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
+hipError_t launch_sweep_fast(hipStream_t s, const SweepArgs &a);
+bool sweep_fast_supports(int N);
+
+hipError_t launch_debug_delta(hipStream_t s, int N, const int32_t *D, const int32_t *F, int R,
+                              const int32_t *perm, const int64_t *H, int r, int64_t *out);
+hipError_t launch_debug_choice(hipStream_t s, int N, int M, const int64_t *delta,
+                               const float *beta, const uint32_t *u24, int32_t *choice,
+                               int32_t *tie);
+hipError_t launch_debug_uniform24(hipStream_t s, int M, const uint32_t *ctr, uint64_t seed,
+                                  uint32_t *out);
+
+}  // namespace pdit

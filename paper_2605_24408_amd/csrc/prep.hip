@@ -1,0 +1,104 @@
+// prep.hip -- step "instance prep": data summary used to choose exact
+// integer widths and the recompute mode, plus validation of the inputs
+// (symmetry of D and F, permutation rows, inverse temperatures).
+#include "device_common.h"
+#include "pdit_internal.h"
+
+namespace pdit {
+namespace {
+
+__global__ void zero_stats_kernel(InstanceStats *s) {
+    if (threadIdx.x == 0) {
+        s->max_abs_d = 0;
+        s->max_abs_f = 0;
+        s->max_rowsum_d = 0;
+        s->max_colsum_f = 0;
+        s->asym_d = 0;
+        s->asym_f = 0;
+        s->bad_perm_rows = 0;
+        s->bad_beta = 0;
+    }
+}
+
+// One thread per row i (D row sums, D symmetry/max) and per column c (F).
+__global__ void matrix_stats_kernel(int N, const int32_t *__restrict__ D,
+                                    const int32_t *__restrict__ F, InstanceStats *s) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * N) return;
+    const bool isD = t < N;
+    const int i = isD ? t : t - N;
+    const int32_t *M = isD ? D : F;
+    int64_t sum = 0;
+    int32_t mx = 0, asym = 0;
+    for (int j = 0; j < N; ++j) {
+        // row i of D; column i of F (sum over the row index j)
+        const int32_t v = isD ? M[(int64_t)i * N + j] : M[(int64_t)j * N + i];
+        const int32_t a = v < 0 ? -v : v;
+        sum += a;
+        mx = max(mx, a);
+        if (j > i && M[(int64_t)i * N + j] != M[(int64_t)j * N + i]) ++asym;
+    }
+    if (isD) {
+        atomicMax(&s->max_abs_d, mx);
+        atomicMax((unsigned long long *)&s->max_rowsum_d, (unsigned long long)sum);
+        if (asym) atomicAdd(&s->asym_d, asym);
+    } else {
+        atomicMax(&s->max_abs_f, mx);
+        atomicMax((unsigned long long *)&s->max_colsum_f, (unsigned long long)sum);
+        if (asym) atomicAdd(&s->asym_f, asym);
+    }
+}
+
+// One block per permutation row (grid-stride): every value in [0, N) seen once.
+__global__ void perm_check_kernel(int N, int R, const int32_t *__restrict__ perm,
+                                  InstanceStats *s) {
+    __shared__ int32_t seen[PDIT_NMAX];
+    for (int row = blockIdx.x; row < R; row += gridDim.x) {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) seen[i] = 0;
+        __syncthreads();
+        int bad = 0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const int32_t v = perm[(int64_t)row * N + i];
+            if (v < 0 || v >= N)
+                bad = 1;
+            else
+                atomicAdd(&seen[v], 1);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += blockDim.x)
+            if (seen[i] != 1) bad = 1;
+        bad = __syncthreads_or(bad);
+        if (bad && threadIdx.x == 0) atomicAdd(&s->bad_perm_rows, 1);
+        __syncthreads();
+    }
+}
+
+__global__ void beta_check_kernel(int64_t T, const float *__restrict__ beta, InstanceStats *s) {
+    int bad = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const float b = beta[t];
+        if (!(b >= 0.0f) || !isfinite(b)) ++bad;
+    }
+    if (bad) atomicAdd(&s->bad_beta, bad);
+}
+
+}  // namespace
+
+hipError_t launch_instance_stats(hipStream_t st, int N, const int32_t *D, const int32_t *F,
+                                 int R, const int32_t *perm, const float *beta, int64_t T,
+                                 InstanceStats *out) {
+    zero_stats_kernel<<<1, 64, 0, st>>>(out);
+    matrix_stats_kernel<<<(2 * N + 255) / 256, 256, 0, st>>>(N, D, F, out);
+    if (perm && R > 0) {
+        const int grid = R < 2048 ? R : 2048;
+        perm_check_kernel<<<grid, 256, 0, st>>>(N, R, perm, out);
+    }
+    if (beta && T > 0) {
+        const int64_t blocks = (T + 255) / 256;
+        beta_check_kernel<<<(int)(blocks < 1024 ? blocks : 1024), 256, 0, st>>>(T, beta, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pdit

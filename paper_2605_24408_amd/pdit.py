@@ -1,0 +1,264 @@
+"""Python binding of the gfx950 p-dit library (``include/pdit.h``).
+
+Argument marshalling only: every step of the sweep runs in the library's HIP
+kernels.  Tensors are torch CUDA (ROCm) tensors on the context's device;
+PyTorch provides device memory and the stream, nothing else.  If the built
+library is missing, loading fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdit.so")
+
+PDIT_OK = 0
+STATUS = {0: "PDIT_OK", -1: "PDIT_EINVAL", -2: "PDIT_ENOTSYM", -3: "PDIT_EBADPERM",
+          -4: "PDIT_EOVERFLOW", -5: "PDIT_ENOMEM", -6: "PDIT_EDEVICE", -7: "PDIT_EBETA",
+          -8: "PDIT_ESTATE"}
+NMAX = 512
+
+RECOMPUTE = {"auto": 0, "plain": 1, "i8": 2, "bf16": 3, "split": 4}
+SWEEP = {"auto": 0, "plain": 1, "fast": 2}
+
+
+class PditError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class _Opts(C.Structure):
+    _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("recompute", C.c_int),
+                ("sweep", C.c_int), ("replicas_per_block", C.c_int), ("seq_threshold", C.c_int)]
+
+
+class _Counters(C.Structure):
+    _fields_ = [("updates", C.c_int64), ("accepted", C.c_int64), ("ties", C.c_int64)]
+
+
+class _Instance(C.Structure):
+    _fields_ = [("N", C.c_int32), ("R", C.c_int32), ("D", C.c_void_p), ("F", C.c_void_p),
+                ("perm", C.c_void_p), ("beta", C.c_void_p)]
+
+
+_lib = None
+
+EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps",
+           "pdit_run_sweeps_batch", "pdit_energy", "pdit_best", "pdit_counters",
+           "pdit_replica_counters", "pdit_set_sweep_offset", "pdit_get_sweep_offset",
+           "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
+           "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
+           "pdit_last_timing"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libpdit.so`` and declare its signatures.  Raises if it is not
+    built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2605_24408_amd.build` "
+                           "(the p-dit path has no CPU fallback)")
+    L = C.CDLL(path)
+    vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    L.pdit_default_opts.restype = None
+    L.pdit_default_opts.argtypes = [C.POINTER(_Opts)]
+    L.pdit_create.argtypes = [C.POINTER(vp), C.POINTER(_Opts)]
+    L.pdit_destroy.argtypes = [vp]
+    L.pdit_run_sweeps.argtypes = [vp, i32, vp, vp, i32, vp, vp, i64, u64]
+    L.pdit_run_sweeps_batch.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64]
+    L.pdit_energy.argtypes = [vp, vp]
+    L.pdit_best.argtypes = [vp, vp, vp]
+    L.pdit_counters.argtypes = [vp, C.POINTER(_Counters)]
+    L.pdit_replica_counters.argtypes = [vp, vp]
+    L.pdit_set_sweep_offset.argtypes = [vp, u64]
+    L.pdit_get_sweep_offset.argtypes = [vp, C.POINTER(u64)]
+    L.pdit_reset.argtypes = [vp]
+    L.pdit_sync.argtypes = [vp]
+    L.pdit_last_error.restype = C.c_char_p
+    L.pdit_last_error.argtypes = [vp]
+    L.pdit_set_recording.argtypes = [vp, vp, vp]
+    L.pdit_h_recompute.argtypes = [vp, i32, vp, vp, i32, vp, C.c_int, vp, vp]
+    L.pdit_debug_delta.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp]
+    L.pdit_debug_choice.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    L.pdit_debug_uniform24.argtypes = [vp, i32, vp, u64, vp]
+    L.pdit_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("pdit_default_opts", "pdit_last_error"):
+            f.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_dev(t: torch.Tensor, dtype, name: str, device: torch.device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must live on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Pdit:
+    """A library context (``pdit_create``) bound to one device and stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
+                 recompute: str = "auto", sweep: str = "auto", replicas_per_block: int = 0,
+                 seq_threshold: int = -1):
+        self._L = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        o = _Opts()
+        self._L.pdit_default_opts(C.byref(o))
+        o.device = device
+        o.stream = stream.cuda_stream
+        o.recompute = RECOMPUTE[recompute]
+        o.sweep = SWEEP[sweep]
+        o.replicas_per_block = replicas_per_block
+        o.seq_threshold = seq_threshold
+        h = C.c_void_p()
+        rc = self._L.pdit_create(C.byref(h), C.byref(o))
+        if rc != PDIT_OK:
+            raise PditError(rc, "pdit_create failed")
+        self._h = h
+        self._last = None   # (R_total, perm_total, N) of the last run
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pdit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _rc(self, rc: int):
+        if rc != PDIT_OK:
+            msg = self._L.pdit_last_error(self._h)
+            raise PditError(rc, msg.decode() if msg else "")
+
+    # -- runs -------------------------------------------------------------
+    def run_sweeps(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor,
+                   beta: torch.Tensor, seed: int) -> None:
+        """pdit_run_sweeps: len(beta) sweeps on every row of perm (in/out)."""
+        N = int(D.shape[0])
+        for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"),
+                          (perm, torch.int32, "perm"), (beta, torch.float32, "beta")):
+            _check_dev(t, dt, nm, self.device)
+        if tuple(D.shape) != (N, N) or tuple(F.shape) != (N, N):
+            raise ValueError("D and F must be N x N")
+        if perm.dim() != 2 or perm.shape[1] != N:
+            raise ValueError("perm must be R x N")
+        R = int(perm.shape[0])
+        self._rc(self._L.pdit_run_sweeps(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm),
+                                         _ptr(beta), int(beta.numel()), int(seed)))
+        self._last = (R, R * N, N)
+
+    def energy(self) -> torch.Tensor:
+        out = torch.empty(self._last[0], dtype=torch.int64, device=self.device)
+        self._rc(self._L.pdit_energy(self._h, _ptr(out)))
+        return out
+
+    def best(self) -> tuple[torch.Tensor, torch.Tensor]:
+        R, PT, N = self._last
+        E = torch.empty(R, dtype=torch.int64, device=self.device)
+        P = torch.empty(PT, dtype=torch.int32, device=self.device)
+        self._rc(self._L.pdit_best(self._h, _ptr(E), _ptr(P)))
+        return E, (P.view(R, N) if N else P)
+
+    def counters(self) -> dict:
+        c = _Counters()
+        self._rc(self._L.pdit_counters(self._h, C.byref(c)))
+        return {"updates": c.updates, "accepted": c.accepted, "ties": c.ties}
+
+    def replica_counters(self) -> torch.Tensor:
+        out = torch.empty((self._last[0], 3), dtype=torch.int64, device=self.device)
+        self._rc(self._L.pdit_replica_counters(self._h, _ptr(out)))
+        return out
+
+    def last_timing(self) -> tuple[float, float]:
+        """(recompute_ms, sweep_ms) of the last run, from HIP events on the
+        context's stream."""
+        a, b = C.c_double(), C.c_double()
+        self._rc(self._L.pdit_last_timing(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_sweep_offset(self, offset: int):
+        self._rc(self._L.pdit_set_sweep_offset(self._h, int(offset)))
+
+    def get_sweep_offset(self) -> int:
+        v = C.c_uint64()
+        self._rc(self._L.pdit_get_sweep_offset(self._h, C.byref(v)))
+        return int(v.value)
+
+    def reset(self):
+        self._rc(self._L.pdit_reset(self._h))
+
+    def sync(self):
+        self._rc(self._L.pdit_sync(self._h))
+
+    def set_recording(self, choices: torch.Tensor | None = None,
+                      E_trace: torch.Tensor | None = None):
+        self._rc(self._L.pdit_set_recording(self._h, _ptr(choices), _ptr(E_trace)))
+
+    # -- single steps -----------------------------------------------------
+    def h_recompute(self, D, F, perm, mode: str = "plain", with_H: bool = True):
+        N = int(D.shape[0])
+        R = int(perm.shape[0])
+        for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"), (perm, torch.int32, "perm")):
+            _check_dev(t, dt, nm, self.device)
+        H = torch.empty((R, N, N), dtype=torch.int64, device=self.device) if with_H else None
+        E = torch.empty(R, dtype=torch.int64, device=self.device)
+        self._rc(self._L.pdit_h_recompute(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm),
+                                          RECOMPUTE[mode], _ptr(H), _ptr(E)))
+        return H, E
+
+    def debug_delta(self, D, F, perm, r: int) -> torch.Tensor:
+        N = int(D.shape[0])
+        R = int(perm.shape[0])
+        out = torch.empty((R, N), dtype=torch.int64, device=self.device)
+        self._rc(self._L.pdit_debug_delta(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), int(r),
+                                          _ptr(out)))
+        return out
+
+    def debug_choice(self, delta: torch.Tensor, beta: torch.Tensor, u24: torch.Tensor):
+        M, N = int(delta.shape[0]), int(delta.shape[1])
+        _check_dev(delta, torch.int64, "delta", self.device)
+        _check_dev(beta, torch.float32, "beta", self.device)
+        _check_dev(u24, torch.int32, "u24", self.device)
+        choice = torch.full((M,), -1, dtype=torch.int32, device=self.device)
+        tie = torch.zeros(M, dtype=torch.int32, device=self.device)
+        self._rc(self._L.pdit_debug_choice(self._h, N, M, _ptr(delta), _ptr(beta), _ptr(u24),
+                                           _ptr(choice), _ptr(tie)))
+        return choice, tie
+
+    def debug_uniform24(self, ctr: torch.Tensor, seed: int) -> torch.Tensor:
+        _check_dev(ctr, torch.int32, "ctr", self.device)
+        M = int(ctr.shape[0])
+        out = torch.empty(M, dtype=torch.int32, device=self.device)
+        self._rc(self._L.pdit_debug_uniform24(self._h, M, _ptr(ctr), int(seed), _ptr(out)))
+        return out

@@ -1,0 +1,380 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle
+on the same seeded inputs.  Integer results (H, energy changes, energies,
+permutations, chosen candidates) must be bit-exact; a trajectory may leave
+the oracle's only after a draw the oracle counted as a tie."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_24408_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2605_24408_amd import pdit
+    return pdit
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def run_gpu(P, inst_D, inst_F, perms, beta, seed, sweep="auto", recompute="auto",
+            record=False, offset=0, seq_threshold=-1, ctx=None):
+    own = ctx is None
+    if own:
+        ctx = P.Pdit(sweep=sweep, recompute=recompute, seq_threshold=seq_threshold)
+    D, F = dev(inst_D, torch.int32), dev(inst_F, torch.int32)
+    perm = dev(perms, torch.int32)
+    b = dev(np.asarray(beta, np.float32), torch.float32)
+    R, N = perm.shape
+    T = b.numel()
+    ch = tr = None
+    if record:
+        ch = torch.full((R, T, N), -1, dtype=torch.int32, device=DEV)
+        tr = torch.zeros((R, T), dtype=torch.int64, device=DEV)
+        ctx.set_recording(ch, tr)
+    if offset:
+        ctx.set_sweep_offset(offset)
+    ctx.run_sweeps(D, F, perm, b, seed)
+    E = ctx.energy()
+    Eb, pb = ctx.best()
+    cnt = ctx.replica_counters()
+    torch.cuda.synchronize()
+    out = dict(perm=perm.cpu().numpy(), E=E.cpu().numpy(), E_best=Eb.cpu().numpy(),
+               perm_best=pb.cpu().numpy(), counters=cnt.cpu().numpy(),
+               choices=None if ch is None else ch.cpu().numpy(),
+               trace=None if tr is None else tr.cpu().numpy())
+    if own:
+        ctx.close()
+    return out
+
+
+def compare_runs(gpu, ref, allow_ties=True):
+    """Per-replica comparison; returns the rows that differ (each must carry an
+    oracle tie)."""
+    R = ref.perm.shape[0]
+    bad = []
+    for k in range(R):
+        same = (np.array_equal(gpu["perm"][k], ref.perm[k]) and gpu["E"][k] == ref.E[k]
+                and gpu["E_best"][k] == ref.E_best[k]
+                and np.array_equal(gpu["perm_best"][k], ref.perm_best[k])
+                and gpu["counters"][k][0] == ref.counters[k][0]
+                and gpu["counters"][k][1] == ref.counters[k][1])
+        if not same:
+            bad.append(k)
+    for k in bad:
+        assert allow_ties and ref.counters[k][2] > 0, (
+            f"replica {k} differs from the oracle without a counted tie: gpu E={gpu['E'][k]} "
+            f"oracle E={ref.E[k]}, accepted {gpu['counters'][k][1]} vs {ref.counters[k][1]}")
+    return bad
+
+
+# ---------------------------------------------------------------------------
+def test_philox_stream(P):
+    rng = np.random.default_rng(0)
+    M = 20000
+    ctr = rng.integers(0, 2**32, size=(M, 4), dtype=np.uint64).astype(np.uint32)
+    for seed in (0, 2, 0xDEADBEEFCAFEF00D):
+        with P.Pdit() as ctx:
+            got = ctx.debug_uniform24(dev(ctr.view(np.int32), torch.int32), seed).cpu().numpy()
+        want = np.array([oracle.uniform24(seed, *map(int, c)) for c in ctr[:2000]], dtype=np.int64)
+        assert np.array_equal(got[:2000].astype(np.int64) & 0xFFFFFF, want)
+        assert (got >= 0).all() and (got < 2**24).all()
+
+
+@pytest.mark.parametrize("N,R,lo,hi", [(12, 3, 0, 9), (64, 5, 0, 99), (100, 3, 0, 127),
+                                       (130, 2, 0, 99), (2, 4, 0, 5), (256, 2, 0, 141)])
+def test_h_recompute_all_modes(P, N, R, lo, hi):
+    rng = np.random.default_rng(N)
+    D, F = W.random_instance(rng, N, lo, hi)
+    perms = W.random_perms(rng, R, N)
+    Dd, Fd, pd = dev(D, torch.int32), dev(F, torch.int32), dev(perms, torch.int32)
+    Di, Fi = D.astype(np.int64), F.astype(np.int64)
+    want_H = np.stack([Di @ Fi[np.ix_(p, p)] for p in perms])
+    want_E = np.array([oracle.energy(D, F, p) for p in perms])
+    bound = int(np.abs(D).max()) * int(np.abs(F).sum(0).max())
+    with P.Pdit() as ctx:
+        for mode in ("plain", "i8", "bf16", "split"):
+            exact = {"plain": True, "i8": hi <= 127, "bf16": hi <= 256 and bound < 2**24,
+                     "split": True}[mode]
+            say(f"h_recompute N={N} R={R} mode={mode} exact={exact}")
+            if not exact:
+                with pytest.raises(P.PditError) as ei:
+                    ctx.h_recompute(Dd, Fd, pd, mode)
+                assert ei.value.status == "PDIT_EOVERFLOW"
+                continue
+            H, E = ctx.h_recompute(Dd, Fd, pd, mode)
+            torch.cuda.synchronize()
+            assert np.array_equal(H.cpu().numpy(), want_H), mode
+            assert np.array_equal(E.cpu().numpy(), want_E), mode
+
+
+def test_h_recompute_split_int64():
+    """Byte-plane split products for values up to 10^4 (H needs int64)."""
+    from paper_2605_24408_amd import pdit as P
+    rng = np.random.default_rng(5)
+    N, R = 96, 3
+    D = W.sym_uniform(rng, N, 0, 10_000, zero_frac=0.2)
+    F = W.sym_uniform(rng, N, 0, 10_000, zero_frac=0.2)
+    perms = W.random_perms(rng, R, N)
+    Di, Fi = D.astype(np.int64), F.astype(np.int64)
+    want_H = np.stack([Di @ Fi[np.ix_(p, p)] for p in perms])
+    assert np.abs(want_H).max() > 2**31
+    with P.Pdit() as ctx:
+        for mode in ("plain", "split"):
+            H, E = ctx.h_recompute(dev(D, torch.int32), dev(F, torch.int32),
+                                   dev(perms, torch.int32), mode)
+            torch.cuda.synchronize()
+            assert np.array_equal(H.cpu().numpy(), want_H)
+            assert np.array_equal(E.cpu().numpy(), np.trace(want_H, axis1=1, axis2=2))
+
+
+@pytest.mark.parametrize("N,diag", [(5, False), (12, True), (64, False), (77, True)])
+def test_delta_rows(P, N, diag):
+    rng = np.random.default_rng(N + 1)
+    D, F = W.random_instance(rng, N, -20, 99, zero_diag=not diag)
+    perms = W.random_perms(rng, 4, N)
+    with P.Pdit() as ctx:
+        for r in (0, N // 2, N - 1):
+            got = ctx.debug_delta(dev(D, torch.int32), dev(F, torch.int32),
+                                  dev(perms, torch.int32), r).cpu().numpy()
+            for k in range(4):
+                assert np.array_equal(got[k], oracle.delta_row(D, F, perms[k], r))
+
+
+@pytest.mark.parametrize("N", [2, 7, 64, 65, 200, 512])
+def test_gibbs_choice(P, N):
+    rng = np.random.default_rng(N)
+    M = 400
+    delta = rng.integers(-3000, 3000, size=(M, N)).astype(np.int64)
+    delta[: M // 4] //= 50
+    beta = np.exp(rng.uniform(np.log(1e-4), np.log(2.0), size=M)).astype(np.float32)
+    beta[:5] = 0.0
+    u24 = rng.integers(0, 2**24, size=M).astype(np.int32)
+    u24[5:10] = [0, 1, 2**24 - 1, 2**23, 15]
+    with P.Pdit() as ctx:
+        ch, tie = ctx.debug_choice(dev(delta, torch.int64), dev(beta, torch.float32),
+                                   dev(u24, torch.int32))
+    ch, tie = ch.cpu().numpy(), tie.cpu().numpy()
+    mism = 0
+    for m in range(M):
+        k, t = oracle.gibbs_choice(delta[m], float(beta[m]), int(u24[m]))
+        if ch[m] != k:
+            mism += 1
+            assert t, f"row {m}: gpu {ch[m]} oracle {k} without a tie"
+    assert mism <= 2
+
+
+@pytest.mark.parametrize("sweep", ["plain", "fast"])
+def test_n12_workload_full_trajectory(P, sweep):
+    """The N=12 grid workload, full schedule (1000 sweeps), 32 replicas, with
+    every chosen candidate recorded: identical to the oracle."""
+    inst = W.config_n12(R=32)
+    say(f"n12 full trajectory sweep={sweep}")
+    ref = oracle.run(inst.D, inst.F, inst.perms, inst.beta, W.PHILOX_SEED, record_choices=True,
+                     record_trace=True)
+    got = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, W.PHILOX_SEED, sweep=sweep,
+                  record=True)
+    bad = compare_runs(got, ref)
+    good = [k for k in range(32) if k not in bad]
+    assert len(good) >= 30
+    for k in good:
+        assert np.array_equal(got["choices"][k], ref.choices[k])
+        assert np.array_equal(got["trace"][k], ref.E_trace[k])
+    assert got["counters"][:, 1].sum() > 500
+
+
+@pytest.mark.parametrize("N,R,T,hot", [(2, 8, 50, True), (7, 16, 60, True), (33, 8, 40, True),
+                                       (64, 8, 30, False), (64, 8, 25, True), (16, 70, 20, True)])
+@pytest.mark.parametrize("sweep", ["plain", "fast"])
+def test_random_instances_trajectory(P, N, R, T, hot, sweep):
+    """Ragged sizes, several workgroups, hot and cold schedules, nonzero
+    diagonals: trajectories identical to the oracle."""
+    rng = np.random.default_rng(1000 + N * 7 + T)
+    D, F = W.random_instance(rng, N, 0, 60, zero_diag=(N % 2 == 0))
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric((0.05 if hot else 2.0) / s, 50.0 / s, T)
+    say(f"random trajectory N={N} R={R} T={T} hot={hot} sweep={sweep}")
+    ref = oracle.run(D, F, perms, beta, 7, record_choices=True)
+    got = run_gpu(P, D, F, perms, beta, 7, sweep=sweep, record=True)
+    bad = compare_runs(got, ref)
+    assert len(bad) <= 1
+    for k in range(R):
+        if k not in bad:
+            assert np.array_equal(got["choices"][k], ref.choices[k])
+
+
+def test_beta_zero_uniform_choices(P):
+    N, R, T = 24, 4, 6
+    rng = np.random.default_rng(3)
+    D, F = W.random_instance(rng, N, 0, 9)
+    perms = W.random_perms(rng, R, N)
+    got = run_gpu(P, D, F, perms, np.zeros(T, np.float32), 11, sweep="fast", record=True,
+                  offset=123)
+    for k in range(R):
+        for t in range(T):
+            for r in range(N):
+                u = oracle.uniform24(11, r, 123 + t, k, 0)
+                assert got["choices"][k, t, r] == (u * N) >> 24
+
+
+@pytest.mark.parametrize("sweep", ["plain", "fast"])
+def test_chunked_equals_single_call(P, sweep):
+    inst = W.config_n12(R=8, T=200)
+    whole = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, 2, sweep=sweep)
+    with P.Pdit(sweep=sweep) as ctx:
+        D, F = dev(inst.D, torch.int32), dev(inst.F, torch.int32)
+        perm = dev(inst.perms, torch.int32)
+        b = dev(inst.beta, torch.float32)
+        ctx.run_sweeps(D, F, perm, b[:70].contiguous(), 2)
+        ctx.run_sweeps(D, F, perm, b[70:].contiguous(), 2)
+        assert ctx.get_sweep_offset() == 200
+        Eb, pb = ctx.best()
+        E = ctx.energy()
+        torch.cuda.synchronize()
+        assert np.array_equal(perm.cpu().numpy(), whole["perm"])
+        assert np.array_equal(E.cpu().numpy(), whole["E"])
+        assert np.array_equal(Eb.cpu().numpy(), whole["E_best"])
+        assert np.array_equal(pb.cpu().numpy(), whole["perm_best"])
+
+
+def test_fast_equals_plain_n64_workload(P):
+    """The N=64 workload's instance and schedule shape, 128 replicas, 300
+    sweeps: fast and plain kernels agree bit for bit (they share the integer
+    weights, so not even ties can separate them)."""
+    inst = W.config_n64(R=128, T=300)
+    a = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, 2, sweep="plain", recompute="plain")
+    b = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, 2, sweep="fast", recompute="i8")
+    for key in ("perm", "E", "E_best", "perm_best", "counters"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("thr", [0, 1000])
+def test_fast_schedules_agree(P, thr):
+    """One-update-at-a-time (threshold 0) and speculative rows (threshold
+    1000) give identical results."""
+    inst = W.config_n12(R=16, T=300)
+    ref = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, 2, sweep="plain")
+    got = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, 2, sweep="fast", seq_threshold=thr)
+    for key in ("perm", "E", "E_best", "perm_best", "counters"):
+        assert np.array_equal(ref[key], got[key]), key
+
+
+def test_n64_workload_full_size_sampled(P):
+    """The N=64 workload at full size (1024 replicas, 10^4 sweeps) in the
+    benchmark's launch configuration; 4 sampled replicas rerun on the oracle."""
+    inst = W.config_n64()
+    say("n64 full size on the GPU")
+    got = run_gpu(P, inst.D, inst.F, inst.perms, inst.beta, W.PHILOX_SEED, sweep="fast",
+                  recompute="i8")
+    sample = [0, 341, 682, 1023]
+    say("n64 sampled oracle replicas")
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(4) as ex:
+        refs = list(ex.map(lambda k: oracle.run(inst.D, inst.F, inst.perms[k:k + 1], inst.beta,
+                                                W.PHILOX_SEED, rep_ids=[k]), sample))
+    for k, ref in zip(sample, refs):
+        same = (np.array_equal(got["perm"][k], ref.perm[0]) and got["E"][k] == ref.E[0]
+                and got["E_best"][k] == ref.E_best[0])
+        assert same or ref.counters[0][2] > 0, k
+    # properties at any size
+    for k in range(0, 1024, 97):
+        assert sorted(got["perm"][k]) == list(range(64))
+        assert got["E"][k] == oracle.energy(inst.D, inst.F, got["perm"][k])
+        assert got["E_best"][k] == oracle.energy(inst.D, inst.F, got["perm_best"][k])
+    assert (got["counters"][:, 0] == 64 * 10_000).all()
+
+
+# ---------------------------------------------------------------------------
+# error paths
+# ---------------------------------------------------------------------------
+def test_error_paths(P):
+    rng = np.random.default_rng(0)
+    N = 10
+    D, F = W.random_instance(rng, N, 0, 9)
+    perms = W.random_perms(rng, 2, N)
+    beta = np.full(3, 0.1, np.float32)
+    with P.Pdit() as ctx:
+        scratch = torch.zeros(4, dtype=torch.int64, device=DEV)
+        with pytest.raises(P.PditError) as e:
+            ctx._rc(ctx._L.pdit_energy(ctx._h, P._ptr(scratch)))
+        assert e.value.status == "PDIT_ESTATE"
+        Dd, Fd = dev(D, torch.int32), dev(F, torch.int32)
+        pd, bd = dev(perms, torch.int32), dev(beta, torch.float32)
+        Da = D.copy()
+        Da[1, 2] += 1
+        with pytest.raises(P.PditError) as e:
+            ctx.run_sweeps(dev(Da, torch.int32), Fd, pd, bd, 1)
+        assert e.value.status == "PDIT_ENOTSYM"
+        bp = perms.copy()
+        bp[1, 0] = bp[1, 1]
+        with pytest.raises(P.PditError) as e:
+            ctx.run_sweeps(Dd, Fd, dev(bp, torch.int32), bd, 1)
+        assert e.value.status == "PDIT_EBADPERM"
+        bp = perms.copy()
+        bp[0, 3] = N
+        with pytest.raises(P.PditError) as e:
+            ctx.run_sweeps(Dd, Fd, dev(bp, torch.int32), bd, 1)
+        assert e.value.status == "PDIT_EBADPERM"
+        for bad in (-1.0, float("nan"), float("inf")):
+            bb = beta.copy()
+            bb[1] = bad
+            with pytest.raises(P.PditError) as e:
+                ctx.run_sweeps(Dd, Fd, pd, dev(bb, torch.float32), 1)
+            assert e.value.status == "PDIT_EBETA"
+        with pytest.raises(P.PditError) as e:
+            ctx._rc(ctx._L.pdit_run_sweeps(ctx._h, 1, P._ptr(Dd), P._ptr(Fd), 2, P._ptr(pd),
+                                           P._ptr(bd), 3, 1))
+        assert e.value.status == "PDIT_EINVAL"
+        with pytest.raises(P.PditError) as e:
+            ctx._rc(ctx._L.pdit_run_sweeps(ctx._h, N, None, P._ptr(Fd), 2, P._ptr(pd),
+                                           P._ptr(bd), 3, 1))
+        assert e.value.status == "PDIT_EINVAL"
+        # inputs untouched by refused calls
+        assert np.array_equal(pd.cpu().numpy(), perms)
+    with P.Pdit(sweep="fast") as ctx:
+        D2, F2 = W.random_instance(rng, 80, 0, 9)
+        with pytest.raises(P.PditError) as e:
+            ctx.run_sweeps(dev(D2, torch.int32), dev(F2, torch.int32),
+                           dev(W.random_perms(rng, 1, 80), torch.int32), bd, 1)
+        assert e.value.status == "PDIT_EOVERFLOW"
+    with P.Pdit(recompute="i8") as ctx:
+        D3, F3 = W.random_instance(rng, 12, 0, 200)
+        with pytest.raises(P.PditError) as e:
+            ctx.run_sweeps(dev(D3, torch.int32), dev(F3, torch.int32),
+                           dev(W.random_perms(rng, 1, 12), torch.int32), bd, 1)
+        assert e.value.status == "PDIT_EOVERFLOW"
+
+
+def test_zero_sweeps_and_reset(P):
+    inst = W.config_n12(R=4, T=50)
+    with P.Pdit() as ctx:
+        D, F = dev(inst.D, torch.int32), dev(inst.F, torch.int32)
+        perm = dev(inst.perms, torch.int32)
+        ctx.run_sweeps(D, F, perm, torch.zeros(0, dtype=torch.float32, device=DEV), 2)
+        E = ctx.energy().cpu().numpy()
+        assert np.array_equal(perm.cpu().numpy(), inst.perms)
+        assert list(E) == [oracle.energy(inst.D, inst.F, p) for p in inst.perms]
+        ctx.run_sweeps(D, F, perm, dev(inst.beta, torch.float32), 2)
+        ctx.reset()
+        start = perm.cpu().numpy().copy()
+        ctx.run_sweeps(D, F, perm, dev(inst.beta[:5], torch.float32), 2)
+        Eb, pb = ctx.best()
+        torch.cuda.synchronize()
+        ref = oracle.run(inst.D, inst.F, start, inst.beta[:5], 2, sweep_offset=50)
+        assert np.array_equal(Eb.cpu().numpy(), ref.E_best)
+        assert np.array_equal(pb.cpu().numpy(), ref.perm_best)
