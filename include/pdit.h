@@ -74,7 +74,8 @@ extern "C" {
 /* Which sweep kernel runs. */
 #define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else plain */
 #define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
-#define PDIT_SWEEP_FAST 2   /* H in LDS, speculative row evaluation; N <= 64, int32 range */
+#define PDIT_SWEEP_FAST 2   /* H in LDS, speculative row evaluation; N <= 64, |dE| < 2^30,
+                               |D| <= 8191, |F| <= 32767 */
 
 typedef struct pdit_ctx pdit_t;
 

@@ -231,8 +231,11 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (rc) return rc;
     const int64_t bound = pdit::h_bound(st);
     const bool h64 = bound > INT32_MAX;
+    // the fast kernel keeps H and dE in int32 (|dE| < 2^30), D (scaled by 4)
+    // and F[p,p] in int16, and multiplies in 24 bits
     const bool fast_ok = pdit::sweep_fast_supports(N) && !h64 &&
-                         2 * pdit::delta_bound(st) < (int64_t)INT32_MAX;
+                         2 * pdit::delta_bound(st) < (int64_t)INT32_MAX &&
+                         st.max_abs_d <= 8191 && st.max_abs_f <= 32767;
     bool use_fast = false;
     if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
         if (!fast_ok)
@@ -282,7 +285,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     a.E_trace = ctx->rec_trace;
     a.replicas_per_block = ctx->opts.replicas_per_block;
     a.seq_threshold = ctx->opts.seq_threshold;
-    a.zero_diag = false;
+    a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
     if (n_sweeps > 0) {
         if (use_fast)

@@ -21,6 +21,8 @@ struct InstanceStats {
     int32_t asym_f;
     int32_t bad_perm_rows;  // rows of perm that are not permutations
     int32_t bad_beta;       // beta values that are NaN, infinite or negative
+    int32_t diag_nz_d;      // nonzero diagonal entries of D
+    int32_t diag_nz_f;      // nonzero diagonal entries of F
 };
 
 // Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=

@@ -17,6 +17,8 @@ __global__ void zero_stats_kernel(InstanceStats *s) {
         s->asym_f = 0;
         s->bad_perm_rows = 0;
         s->bad_beta = 0;
+        s->diag_nz_d = 0;
+        s->diag_nz_f = 0;
     }
 }
 
@@ -38,11 +40,14 @@ __global__ void matrix_stats_kernel(int N, const int32_t *__restrict__ D,
         mx = max(mx, a);
         if (j > i && M[(int64_t)i * N + j] != M[(int64_t)j * N + i]) ++asym;
     }
+    const bool diag_nz = M[(int64_t)i * N + i] != 0;
     if (isD) {
+        if (diag_nz) atomicAdd(&s->diag_nz_d, 1);
         atomicMax(&s->max_abs_d, mx);
         atomicMax((unsigned long long *)&s->max_rowsum_d, (unsigned long long)sum);
         if (asym) atomicAdd(&s->asym_d, asym);
     } else {
+        if (diag_nz) atomicAdd(&s->diag_nz_f, 1);
         atomicMax(&s->max_abs_f, mx);
         atomicMax((unsigned long long *)&s->max_colsum_f, (unsigned long long)sum);
         if (asym) atomicAdd(&s->asym_f, asym);
