@@ -26,7 +26,7 @@
  * key (lo32(seed), hi32(seed)) and counter (r, g, k, n); u24 = word0 >> 8.
  * The draw takes the first candidate s with C_s * 2^24 > u24 * Z, where
  * C_s is the running sum over s' <= s of q_s' = rint(expf(-fl32(beta *
- * fl32(dE_s' - min dE))) * 2^30) and Z = C_{N-1}.  All integer work (H, dE,
+ * fl32(dE_s' - min dE))) * 2^25) and Z = C_{N-1}.  All integer work (H, dE,
  * E) is exact; energies are reported as int64.
  *
  * Conventions for every entry point:

@@ -38,7 +38,7 @@
  *     by 8 gives a 24-bit uniform u24 (u = u24 / 2^24);
  *   - sampling is taken in the GPU kernel's precision: with m = min_k dE_k,
  *     x_k = fl32(beta * fl32(dE_k - m)), w_k = expf(-x_k), and the weight is
- *     quantised to q_k = rint(w_k * 2^30) (an integer in [0, 2^30]); the CDF
+ *     quantised to q_k = rint(w_k * 2^25) (an integer in [0, 2^25]); the CDF
  *     C_k = q_0 + ... + q_k is exact in 64-bit integers, Z = C_{N-1}, and the
  *     chosen candidate is the first k with C_k * 2^24 > u24 * Z;
  *   - a "tie" is a draw whose threshold u24 * Z lies within Z * 2^4 (a
@@ -169,10 +169,10 @@ int po_gibbs_choice(int N, const int64_t *dE, float beta, uint32_t u24, int *tie
         const float d = (float)(dE[s] - m);
         const float x = beta * d;
         const float w = expf(-x);
-        q[s] = (uint64_t)rintf(w * 1073741824.0f); /* 2^30 */
+        q[s] = (uint64_t)rintf(w * 33554432.0f); /* 2^25 */
         Z += q[s];
     }
-    const uint64_t target = (uint64_t)u24 * Z; /* u24 * Z < 2^63 */
+    const uint64_t target = (uint64_t)u24 * Z; /* u24 * Z < 2^24 * 2^34 */
     const uint64_t thr = target >> 24;         /* C*2^24 > target <=> C > thr */
     uint64_t C = 0, Cprev = 0;
     int sel = N - 1;

@@ -45,22 +45,26 @@ __device__ __forceinline__ uint32_t uniform24(uint64_t seed, uint32_t r, uint32_
 
 // ---------------------------------------------------------------------------
 // Gibbs weights.  The weight of a candidate whose energy change exceeds the
-// row minimum by d >= 0 is q = rint(expf(-fl32(beta * fl32(d))) * 2^30), an
-// integer in [0, 2^30]; sums of q are exact in 64 bits and the draw is the
-// first candidate whose running sum C satisfies C * 2^24 > u24 * Z.
+// row minimum by d >= 0 is q = rint(expf(-fl32(beta * fl32(d))) * 2^25), an
+// integer in [0, 2^25]; sums of q are exact (32 bits for up to 64 candidates,
+// 64 bits beyond) and the draw is the first candidate whose running sum C
+// satisfies C * 2^24 > u24 * Z.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kWeightOne = 1u << 25;  // weight of the row minimum
+
 __device__ __forceinline__ uint32_t gibbs_weight(float beta, float d) {
     const float x = __fmul_rn(beta, d);
     const float w = expf(-x);
-    return (uint32_t)rintf(w * 1073741824.0f);
+    return (uint32_t)rintf(w * 33554432.0f);
 }
 
 // Smallest integer distance above which every weight is provably 0:
-// fl32(beta * fl32(d)) >= 23 for all d >= the returned value (e^-23 * 2^30 <
-// 0.12 rounds to 0).  Returns INT32_MAX when no such integer is in range.
+// fl32(beta * fl32(d)) >= 19.5 for all d >= the returned value
+// (e^-19.5 * 2^25 < 0.12 rounds to 0).  Returns INT32_MAX when no such
+// integer is in range.
 __device__ __forceinline__ int32_t zero_weight_distance(float beta) {
     if (!(beta > 0.0f)) return INT32_MAX;
-    const float t = 23.0f / beta * 1.0001f + 2.0f;
+    const float t = 19.5f / beta * 1.0001f + 2.0f;
     if (!(t < 2.0e9f)) return INT32_MAX;
     return (int32_t)t;
 }
@@ -124,6 +128,19 @@ __device__ __forceinline__ uint64_t wave_scan_u64(uint64_t v) {
     const int row = lane_id() >> 4;
     const uint64_t add = row == 0 ? 0 : row == 1 ? r0 : row == 2 ? r0 + r1 : r0 + r1 + r2;
     return x + add;
+}
+
+// Inclusive prefix sum of a 32-bit value across the wave (lane order).
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t v) {
+    v += (uint32_t)dpp_row_shr<1>(0, (int32_t)v);
+    v += (uint32_t)dpp_row_shr<2>(0, (int32_t)v);
+    v += (uint32_t)dpp_row_shr<4>(0, (int32_t)v);
+    v += (uint32_t)dpp_row_shr<8>(0, (int32_t)v);
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int32_t)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int32_t)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int32_t)v, 47);
+    const int row = lane_id() >> 4;
+    return v + (row == 0 ? 0u : row == 1 ? r0 : row == 2 ? r0 + r1 : r0 + r1 + r2);
 }
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {

@@ -1,13 +1,13 @@
 // sweep_fast.hip -- the sweep kernel with H on chip.
 //
-// One workgroup owns one replica.  Its H = D F[p,p] (int32) and its permuted
-// flows Fp = F[p,p] (int16), with D (int16), live in LDS for the whole run;
-// N <= 64.  The method's order of updates (locations 0..N-1 per sweep, each a
-// Gibbs choice among N candidates; Results, "Implementation", Eq. 3 and
-// Eq. 5) is kept exactly.  The workgroup has NMAX/16 waves; wave w owns the 16
-// locations 16w..16w+15 and the lanes of a quad split the candidates of one
-// location four ways, so a replica keeps NMAX/16 waves busy and four
-// replicas of N = 64 share a CU with four waves per SIMD.
+// One workgroup owns one replica.  Its H = D F[p,p] (int32, stored doubled)
+// and its permuted flows Fp = F[p,p] (int16), with D (int16), live in LDS for
+// the whole run; N <= 64.  The method's order of updates (locations 0..N-1 per
+// sweep, each a Gibbs choice among N candidates; Results, "Implementation",
+// Eq. 3 and Eq. 5) is kept exactly.  The workgroup has NMAX/16 waves; wave w
+// owns the 16 locations 16w..16w+15 and the lanes of a quad split the
+// candidates of one location four ways, so a replica keeps NMAX/16 waves
+// busy and four replicas of N = 64 share a CU with four waves per SIMD.
 //
 // Two schedules give the same result:
 //
@@ -23,14 +23,15 @@
 //    reductions, computed redundantly by every wave of the replica.  Used for
 //    a sweep when the previous one accepted more than `seq_threshold` swaps.
 //
-// The Gibbs weights are exact integers (q = rint(w 2^30)) summed in 64 bits,
-// so both schedules, whatever their summation order, select the same
-// candidate.  A candidate whose distance d to the row minimum satisfies
-// d >= dthr has q = 0 and skips the exponential; d = 0 gives q = 2^30.
+// The Gibbs weights are exact integers (q = rint(w 2^25)); for N <= 64 their
+// sums fit 32 bits, so both schedules, whatever their summation order, select
+// the same candidate.  A candidate whose distance d to the row minimum
+// satisfies d >= dthr has q = 0 and skips the exponential; d = 0 gives 2^25.
 //
 // The energy change of swapping the facilities of locations l and s is
 //   dE = 2 (H_ls + H_sl - H_ll - H_ss) + (D_ll + D_ss - 2 D_ls)(Fp_ll + Fp_ss - 2 Fp_ls)
 // (Eq. 3 with I = -2H); with zero diagonals the last term is 4 D_ls Fp_ls.
+// Keeping 2H and 4D makes it two adds and a 24-bit multiply-add.
 #include "device_common.h"
 #include "pdit_internal.h"
 
@@ -38,7 +39,7 @@ namespace pdit {
 namespace {
 
 constexpr int32_t kBig = (1 << 30) - 1;  // excluded candidates (|dE| < 2^30 is guaranteed)
-constexpr uint32_t kOne = 1u << 30;      // weight of the row minimum
+constexpr uint32_t kOne = kWeightOne;    // weight of the row minimum
 
 // quad_perm DPP selectors (lane i of each quad reads lane sel[i])
 constexpr int kQuadXor1 = 0xB1;   // [1,0,3,2]
@@ -53,10 +54,8 @@ __device__ __forceinline__ int32_t quad(int32_t v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 template <int CTRL>
-__device__ __forceinline__ uint64_t quad64(uint64_t v) {
-    const uint32_t lo = (uint32_t)quad<CTRL>((int32_t)(uint32_t)v);
-    const uint32_t hi = (uint32_t)quad<CTRL>((int32_t)(uint32_t)(v >> 32));
-    return (uint64_t)hi << 32 | lo;
+__device__ __forceinline__ uint32_t quadu(uint32_t v) {
+    return (uint32_t)quad<CTRL>((int32_t)v);
 }
 
 // four replicas of N = 64 per CU need four waves per SIMD: at most 128 VGPRs
@@ -69,11 +68,11 @@ sweep_fast_kernel(SweepArgs a) {
     constexpr int PF = NMAX + 2;    // Fp row pitch (int16)
     constexpr int kDScale = ZD ? 4 : 1;  // Ds holds 4 D with zero diagonals
 
-    __shared__ int32_t Hs[NMAX * P];
+    __shared__ int32_t Hs[NMAX * P];  // 2 H
     __shared__ int16_t Ds[NMAX * NMAX];
     __shared__ int16_t Fp[NMAX * PF];
-    __shared__ int32_t hdv[NMAX];  // H[l][l]
-    __shared__ int32_t ddv[NMAX];  // D[l][l] (scaled like Ds)
+    __shared__ int32_t hdv[NMAX];  // 2 H[l][l]
+    __shared__ int32_t ddv[NMAX];  // D[l][l]
     __shared__ int32_t fdv[NMAX];  // Fp[l][l]
     __shared__ int32_t pv[NMAX];   // p(l)
     __shared__ int32_t sel_row[2][NMAX];
@@ -85,7 +84,7 @@ sweep_fast_kernel(SweepArgs a) {
     const int wv = tid >> 6;
     const int64_t rep = blockIdx.x;
 
-    // ---- stage D, p, H and F[p,p] (zero outside N) ----
+    // ---- stage D, p, 2H and F[p,p] (zero outside N) ----
     for (int e = tid; e < NMAX * NMAX; e += 64 * WPR) {
         const int i = e / NMAX, j = e % NMAX;
         Ds[e] = (int16_t)((i < N && j < N) ? kDScale * a.D[(int64_t)i * N + j] : 0);
@@ -95,7 +94,7 @@ sweep_fast_kernel(SweepArgs a) {
         const int32_t *Hg = (const int32_t *)a.H + rep * (int64_t)N * N;
         for (int e = tid; e < NMAX * P; e += 64 * WPR) {
             const int i = e / P, k = e % P;
-            Hs[e] = (i < N && k < N) ? Hg[(int64_t)i * N + k] : 0;
+            Hs[e] = (i < N && k < N) ? 2 * Hg[(int64_t)i * N + k] : 0;
         }
     }
     __syncthreads();
@@ -125,10 +124,10 @@ sweep_fast_kernel(SweepArgs a) {
 
     // energy change of the (uniform) pair r, s, from LDS
     auto pair_delta = [&](int r, int s) -> int32_t {
-        const int32_t h = Hs[r * P + s] + Hs[s * P + r] - hdv[r] - hdv[s];
+        const int32_t h2 = Hs[r * P + s] + Hs[s * P + r] - hdv[r] - hdv[s];
         const int32_t dv = Ds[s * NMAX + r], fv = Fp[s * PF + r];
-        if (ZD) return 2 * h + dv * fv;
-        return 2 * h + (ddv[r] + ddv[s] - 2 * dv) * (fdv[r] + fdv[s] - 2 * fv);
+        if (ZD) return h2 + dv * fv;
+        return h2 + (ddv[r] + ddv[s] - 2 * dv) * (fdv[r] + fdv[s] - 2 * fv);
     };
 
     // ---- apply an accepted swap of locations r and s; every wave calls it ----
@@ -140,13 +139,14 @@ sweep_fast_kernel(SweepArgs a) {
         const int src = ls == r ? s : ls == s ? r : ls;
         const int32_t v = (int32_t)Fp[r * PF + src] - (int32_t)Fp[s * PF + src];
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
-#pragma unroll
+#pragma unroll 4
         for (int ii = 0; ii < 16; ++ii) {
             const int i = 16 * wv + ii;
             if (EXACT || i < N) {
-                const int32_t ui = ((int32_t)Ds[s * NMAX + i] - (int32_t)Ds[r * NMAX + i]) / kDScale;
+                const int32_t du = (int32_t)Ds[s * NMAX + i] - (int32_t)Ds[r * NMAX + i];
+                const int32_t u2 = ZD ? du / 2 : 2 * du;  // 2 u_i
                 const int32_t x = Hs[i * P + src];
-                if (lane < N) Hs[i * P + lane] = x + ui * v;
+                if (lane < N) Hs[i * P + lane] = x + u2 * v;
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -201,44 +201,39 @@ sweep_fast_kernel(SweepArgs a) {
                 int sel = rr;
                 bool tie = false, swaps = false;
                 if (__ballot(rowv)) {
-                    const int32_t hdr = hdv[rr];
+                    const int32_t nhdr = -hdv[rr];
                     const int32_t ddr = ddv[rr], fdr = fdv[rr];
                     int32_t dl[K];
                     int32_t mn = kBig;
-                    int am = 0;
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         const int s = cq * K + j;
-                        const int32_t h = Hs[rr * P + s] + Hs[s * P + rr] - hdr - hdv[s];
+                        const int32_t x = Hs[rr * P + s] + Hs[s * P + rr] + nhdr - hdv[s];
                         const int32_t dv = Ds[s * NMAX + rr];
                         const int32_t fv = Fp[s * PF + rr];
                         int32_t v;
                         if (ZD) {
-                            v = 2 * h + __mul24(dv, fv);
+                            v = __mul24(dv, fv) + x;
                         } else {
-                            v = 2 * h + __mul24(ddr + ddv[s] - 2 * dv, fdr + fdv[s] - 2 * fv);
+                            v = x + __mul24(ddr + ddv[s] - 2 * dv, fdr + fdv[s] - 2 * fv);
                         }
                         if (!EXACT && s >= N) v = kBig;
                         dl[j] = v;
-                        am = v < mn ? s : am;
                         mn = min(mn, v);
                     }
-                    // row minimum and its first position across the quad
-#pragma unroll
-                    for (int step = 0; step < 2; ++step) {
-                        const int32_t om = step ? quad<kQuadXor2>(mn) : quad<kQuadXor1>(mn);
-                        const int32_t oa = step ? quad<kQuadXor2>(am) : quad<kQuadXor1>(am);
-                        am = (om < mn || (om == mn && oa < am)) ? oa : am;
-                        mn = min(mn, om);
-                    }
-                    // weights: d = 0 -> 2^30; 0 < d < dthr -> expf; d >= dthr -> 0
+                    mn = min(mn, quad<kQuadXor1>(mn));
+                    mn = min(mn, quad<kQuadXor2>(mn));
+                    // weights: d = 0 -> 2^25; 0 < d < dthr -> expf; d >= dthr -> 0
                     uint32_t ql[K];
-                    uint64_t Zc = 0;
+                    uint32_t Zc = 0;
+                    int am = -1;
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         const int32_t d = dl[j] - mn;
-                        uint32_t q = d == 0 ? kOne : 0u;
-                        const bool need = (uint32_t)(d - 1) < (uint32_t)(dthr - 1);
+                        const bool zero = d == 0;
+                        uint32_t q = zero ? kOne : 0u;
+                        am = zero ? cq * K + j : am;
+                        const bool need = d < dthr && !zero;
                         if (__ballot(need)) {
                             if (need) q = gibbs_weight(beta, (float)d);
                         }
@@ -247,40 +242,41 @@ sweep_fast_kernel(SweepArgs a) {
                         Zc += q;
                     }
                     // quarters before this one, and the row total
-                    const uint64_t p1 = quad64<kQuadPrev1>(Zc), p2 = quad64<kQuadPrev2>(Zc),
-                                   p3 = quad64<kQuadPrev3>(Zc);
-                    const uint64_t off = (cq >= 1 ? p1 : 0) + (cq >= 2 ? p2 : 0) + (cq >= 3 ? p3 : 0);
-                    const uint64_t Z = quad64<kQuadLast>(off + Zc);
+                    const uint32_t p1 = quadu<kQuadPrev1>(Zc), p2 = quadu<kQuadPrev2>(Zc),
+                                   p3 = quadu<kQuadPrev3>(Zc);
+                    const uint32_t off = (cq >= 1 ? p1 : 0u) + (cq >= 2 ? p2 : 0u) + (cq >= 3 ? p3 : 0u);
+                    const uint32_t Z = quadu<kQuadLast>(off + Zc);
+                    am = max(am, quad<kQuadXor1>(am));
+                    am = max(am, quad<kQuadXor2>(am));
                     sel = am;
-                    // a row whose only nonzero weight is its minimum (Z = 2^30)
+                    // a row whose only nonzero weight is its minimum (Z = 2^25)
                     // picks the minimum; otherwise locate the threshold by
                     // counting: the first s with C_s > thr is #{s : C_s <= thr},
-                    // and a boundary 0 < C_s < Z within the tie band of the
-                    // threshold shows up as #{C_s <= thr_hi} > #{C_s <= thr_lo}
+                    // and a tie is a boundary thr_lo < C_s <= thr_hi (the band
+                    // around the threshold, with 0 < C_s < Z)
                     if (__ballot(rowv && Z != kOne)) {
                         const uint64_t target = (uint64_t)u24 * Z;
-                        const uint64_t band = Z << 4;
-                        const uint64_t thr = target >> 24;
-                        const uint64_t thr_lo = target >= band ? (target - band) >> 24 : 0;
-                        const uint64_t thr_hi = min((target + band) >> 24, Z - 1);
-                        uint64_t C = off;
-                        int n_sel = 0, n_lo = 0, n_hi = 0;
+                        const uint64_t band = (uint64_t)Z << 4;
+                        const uint32_t thr = (uint32_t)(target >> 24);
+                        const uint32_t thr_lo = target >= band ? (uint32_t)((target - band) >> 24) : 0u;
+                        const uint32_t thr_hi = (uint32_t)min((target + band) >> 24, (uint64_t)(Z - 1));
+                        const uint32_t lo1 = thr_lo + 1;
+                        const uint32_t width = thr_hi >= lo1 ? thr_hi - thr_lo : 0u;
+                        uint32_t C = off;
+                        int n_sel = 0, n_band = 0;
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
                             C += ql[j];
                             n_sel += C <= thr;
-                            n_lo += C <= thr_lo;
-                            n_hi += C <= thr_hi;
+                            n_band += (C - lo1) < width;
                         }
                         n_sel += quad<kQuadXor1>(n_sel);
                         n_sel += quad<kQuadXor2>(n_sel);
-                        n_lo += quad<kQuadXor1>(n_lo);
-                        n_lo += quad<kQuadXor2>(n_lo);
-                        n_hi += quad<kQuadXor1>(n_hi);
-                        n_hi += quad<kQuadXor2>(n_hi);
+                        n_band += quad<kQuadXor1>(n_band);
+                        n_band += quad<kQuadXor2>(n_band);
                         if (Z != kOne) {
                             sel = n_sel;
-                            tie = n_hi > n_lo;
+                            tie = n_band > 0;
                         }
                     }
                     swaps = rowv && sel != rr;
@@ -313,29 +309,29 @@ sweep_fast_kernel(SweepArgs a) {
             for (int r = 0; r < N; ++r) {
                 int32_t v = kBig;
                 if (lv) {
-                    const int32_t h = Hs[r * P + ls] + Hs[ls * P + r] - hdv[r] - hdv[ls];
+                    const int32_t x = Hs[r * P + ls] + Hs[ls * P + r] - hdv[r] - hdv[ls];
                     const int32_t dv = Ds[r * NMAX + ls];
                     const int32_t fv = Fp[r * PF + ls];
                     if (ZD) {
-                        v = 2 * h + __mul24(dv, fv);
+                        v = __mul24(dv, fv) + x;
                     } else {
-                        v = 2 * h + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
+                        v = x + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
                     }
                 }
                 const int32_t mn = wave_min_i32(v);
                 const int32_t d = lv ? v - mn : 0;
                 uint32_t q = d == 0 ? kOne : 0u;
-                if ((uint32_t)(d - 1) < (uint32_t)(dthr - 1)) q = gibbs_weight(beta, (float)d);
+                if (d > 0 && d < dthr) q = gibbs_weight(beta, (float)d);
                 if (!lv) q = 0;
-                const uint64_t C = wave_scan_u64(q);
-                const uint64_t Z = readlane_u64(C, 63);
+                const uint32_t C = wave_scan_u32(q);
+                const uint32_t Z = (uint32_t)__builtin_amdgcn_readlane((int32_t)C, 63);
                 const uint32_t ur24 = (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l, r);
-                const uint64_t thr = ((uint64_t)ur24 * Z) >> 24;
+                const uint32_t thr = (uint32_t)(((uint64_t)ur24 * Z) >> 24);
                 const uint64_t hit = __ballot(C > thr);
                 int s = __ffsll((unsigned long long)hit) - 1;
                 if (s < 0 || s >= N) s = r;  // unreachable: lane N-1 holds C = Z > thr
-                const uint64_t csel = readlane_u64(C, s);
-                const uint64_t cprev = csel - (uint32_t)__builtin_amdgcn_readlane((int32_t)q, s);
+                const uint32_t csel = (uint32_t)__builtin_amdgcn_readlane((int32_t)C, s);
+                const uint32_t cprev = csel - (uint32_t)__builtin_amdgcn_readlane((int32_t)q, s);
                 if (wv == 0) n_tie += is_tie(cprev, csel, Z, ur24) ? 1 : 0;
                 if (ch && lane == 0) ch[r] = s;
                 if (s != r) apply_swap(r, s, (int64_t)__builtin_amdgcn_readlane(v, s));
