@@ -74,7 +74,7 @@ extern "C" {
 /* Which sweep kernel runs. */
 #define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else plain */
 #define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
-#define PDIT_SWEEP_FAST 2   /* H in LDS, speculative row evaluation; N <= 64, |dE| < 2^30,
+#define PDIT_SWEEP_FAST 2   /* H in LDS, speculative row evaluation; N <= 128, |dE| < 2^30,
                                |D| <= 8191, |F| <= 32767 */
 
 typedef struct pdit_ctx pdit_t;
@@ -84,9 +84,10 @@ typedef struct {
     void *stream;         /* hipStream_t to run on; NULL = the device's null stream */
     int recompute;        /* PDIT_RECOMPUTE_* */
     int sweep;            /* PDIT_SWEEP_* */
-    int replicas_per_block; /* fast kernel: replicas (waves) per workgroup, 0 = tuned default */
+    int blocks_per_cu;    /* batched runs: resident workgroups per CU of the persistent
+                             kernels (one replica each); 0 = as many as fit */
     int seq_threshold;    /* fast kernel: accepted moves in a sweep above which the next sweep
-                             runs one update at a time; < 0 = tuned default */
+                             runs one update at a time; < 0 = default (3) */
 } pdit_opts;
 
 typedef struct {
@@ -140,14 +141,40 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
                     int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed);
 
 /*
- * Runs n_sweeps sweeps on every replica of n_inst instances of uneven size in
- * one persistent launch.  Instance n's replicas use Philox counter word 3 = n.
+ * Runs n_sweeps sweeps on every replica of n_inst instances of uneven size
+ * (the paper's independent duplicated replica sets, Results "GPU
+ * Implementations" and Methods "GPU-PIM Algorithm": persistent kernels over
+ * duplicates x replicas).  Each instance is validated and given exact widths
+ * as in pdit_run_sweeps; the (instance, replica) work items are handed out
+ * largest N first by persistent kernels (the on-chip kernel for N <= 128
+ * when the data fit it, the plain kernel otherwise), whose launches are
+ * captured once in a HIP graph and replayed while the batch keeps the same
+ * shape and buffers.  Instance n's replicas use Philox counter word 3 = n.
  * Replica state is laid out instance after instance: R_total = sum R_n
  * energies, and permutation rows of each instance's own length N_n.
- * inst points to host memory (n_inst entries).
+ *   inst   host array of n_inst descriptors (device pointers inside)
+ * The sweep offset and best state behave as in pdit_run_sweeps.  Recording
+ * (pdit_set_recording) is not available for batched runs.
  */
 int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst,
                           int64_t n_sweeps, uint64_t seed);
+
+/* Result of pdit_autotune. */
+typedef struct {
+    int blocks_per_cu;    /* chosen resident workgroups per CU */
+    int seq_threshold;    /* chosen sequential-sweep threshold */
+    double best_ms;       /* trial time of the chosen setting */
+} pdit_tuning;
+
+/*
+ * Times short trial batches (n_trial_sweeps sweeps of the given instances,
+ * on private copies of their permutations, so nothing the caller owns
+ * changes) for every resident-workgroups-per-CU count and a few sequential
+ * thresholds, and stores the fastest setting in the context's options for
+ * later runs.  *out may be NULL.
+ */
+int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_t n_trial_sweeps,
+                  uint64_t seed, pdit_tuning *out);
 
 /* E_out: device int64 R_total; current energies (Eq. 1) of the last run's
  * final permutations. */

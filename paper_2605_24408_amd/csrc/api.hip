@@ -157,7 +157,7 @@ void pdit_default_opts(pdit_opts *o) {
     o->stream = nullptr;
     o->recompute = PDIT_RECOMPUTE_AUTO;
     o->sweep = PDIT_SWEEP_AUTO;
-    o->replicas_per_block = 0;
+    o->blocks_per_cu = 0;
     o->seq_threshold = -1;
 }
 
@@ -188,6 +188,12 @@ int pdit_create(pdit_t **out, const pdit_opts *opts) {
             return PDIT_EDEVICE;
         }
     }
+    if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount,
+                              ctx->opts.device) != hipSuccess) {
+        pdit_destroy(ctx);
+        return PDIT_EDEVICE;
+    }
     if (hipHostMalloc((void **)&ctx->stats_host, sizeof(InstanceStats), hipHostMallocDefault) !=
             hipSuccess ||
         hipMalloc((void **)&ctx->err_dev, sizeof(int32_t)) != hipSuccess) {
@@ -208,6 +214,9 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
         if (e) hipEventDestroy(e);
+    if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
+    hipFree(ctx->batch_buf.ptr);
+    if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
     if (ctx->stats_host) hipHostFree(ctx->stats_host);
     delete ctx;
     return PDIT_OK;
@@ -240,7 +249,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
         if (!fast_ok)
             return fail(ctx, PDIT_EOVERFLOW,
-                        "the fast sweep kernel needs N <= 64 and energy changes within int32");
+                        "the fast sweep kernel needs N <= 128, |dE| < 2^30, |D| <= 8191 and |F| <= 32767");
         use_fast = true;
     } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
         use_fast = fast_ok;
@@ -283,7 +292,6 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     a.inst_id = 0;
     a.choices = ctx->rec_choices;
     a.E_trace = ctx->rec_trace;
-    a.replicas_per_block = ctx->opts.replicas_per_block;
     a.seq_threshold = ctx->opts.seq_threshold;
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
@@ -307,11 +315,319 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
 
 int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst,
                           int64_t n_sweeps, uint64_t seed) {
-    (void)n_inst;
-    (void)inst;
-    (void)n_sweeps;
-    (void)seed;
-    return fail(ctx, PDIT_EINVAL, "batched runs are not available in this build");
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!inst || n_inst < 1) return fail(ctx, PDIT_EINVAL, "empty or null instance list");
+    if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
+    if (ctx->rec_choices || ctx->rec_trace)
+        return fail(ctx, PDIT_EINVAL, "recording is not available for batched runs");
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+    for (int k = 0; k < n_inst; ++k) {
+        const pdit_instance &in = inst[k];
+        if (in.N < 2 || in.N > PDIT_NMAX || in.R < 1)
+            return fail(ctx, PDIT_EINVAL, "an instance has N outside [2, PDIT_NMAX] or R < 1");
+        if (!in.D || !in.F || !in.perm || (!in.beta && n_sweeps > 0))
+            return fail(ctx, PDIT_EINVAL, "null pointer in an instance");
+    }
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+
+    // ---- instance prep for every instance, one host synchronisation ----
+    int rc = ensure(ctx, ctx->scratch, sizeof(InstanceStats) * (size_t)n_inst);
+    if (rc) return rc;
+    InstanceStats *dev_st = (InstanceStats *)ctx->scratch.ptr;
+    for (int k = 0; k < n_inst; ++k)
+        PDIT_HIP(ctx, pdit::launch_instance_stats(ctx->stream, inst[k].N, inst[k].D, inst[k].F,
+                                                  inst[k].R, inst[k].perm, inst[k].beta, n_sweeps,
+                                                  dev_st + k));
+    std::vector<InstanceStats> st(n_inst);
+    PDIT_HIP(ctx, hipMemcpyAsync(st.data(), dev_st, sizeof(InstanceStats) * n_inst,
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+
+    struct Plan {
+        int mode;
+        bool h64, fast, zd;
+        int64_t hoff;  // byte offset of replica 0's H
+    };
+    std::vector<Plan> plan(n_inst);
+    size_t hbytes = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const InstanceStats &q = st[k];
+        if (q.asym_d || q.asym_f) return fail(ctx, PDIT_ENOTSYM, "D or F of an instance is not symmetric");
+        if (q.bad_perm_rows)
+            return fail(ctx, PDIT_EBADPERM, "a row of an instance's perm is not a permutation");
+        if (q.bad_beta)
+            return fail(ctx, PDIT_EBETA, "an instance's inverse temperature is NaN, infinite or negative");
+        const __int128 b1 = (__int128)q.max_abs_d * q.max_colsum_f;
+        const __int128 b2 = (__int128)q.max_abs_f * q.max_rowsum_d;
+        if ((b1 < b2 ? b1 : b2) > ((__int128)1 << 58))
+            return fail(ctx, PDIT_EOVERFLOW, "an instance's exact bound on H exceeds the int64 range");
+        const int64_t bound = pdit::h_bound(q);
+        Plan &pl = plan[k];
+        pl.h64 = bound > INT32_MAX;
+        const bool fast_ok = pdit::sweep_fast_supports(inst[k].N) && !pl.h64 &&
+                             2 * pdit::delta_bound(q) < (int64_t)INT32_MAX && q.max_abs_d <= 8191 &&
+                             q.max_abs_f <= 32767;
+        if (ctx->opts.sweep == PDIT_SWEEP_FAST && !fast_ok)
+            return fail(ctx, PDIT_EOVERFLOW, "an instance does not fit the fast sweep kernel");
+        pl.fast = ctx->opts.sweep != PDIT_SWEEP_PLAIN && fast_ok;
+        pl.zd = q.diag_nz_d == 0 && q.diag_nz_f == 0;
+        rc = pick_recompute(ctx, q, bound, ctx->opts.recompute, &pl.mode);
+        if (rc) return rc;
+        const size_t elem = pl.h64 ? 8 : 4;
+        hbytes = (hbytes + 7) & ~(size_t)7;
+        pl.hoff = (int64_t)hbytes;
+        hbytes += (size_t)inst[k].R * inst[k].N * inst[k].N * elem;
+    }
+    rc = ensure(ctx, ctx->h_buf, hbytes);
+    if (rc) return rc;
+    std::vector<int32_t> Ns(n_inst), Rs(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        Ns[k] = inst[k].N;
+        Rs[k] = inst[k].R;
+    }
+    bool fresh = false;
+    rc = shape_state(ctx, Ns, Rs, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+
+    // ---- descriptors ----
+    std::vector<pdit::BatchInstance> desc(n_inst);
+    int64_t rep_base = 0, perm_off = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        pdit::BatchInstance &d = desc[k];
+        d.N = inst[k].N;
+        d.R = inst[k].R;
+        d.D = inst[k].D;
+        d.F = inst[k].F;
+        d.perm = inst[k].perm;
+        d.beta = inst[k].beta;
+        d.h_off = plan[k].hoff / (plan[k].h64 ? 8 : 4);
+        d.rep_base = rep_base;
+        d.perm_off = perm_off;
+        d.zero_diag = plan[k].zd ? 1 : 0;
+        d.inst_id = k;
+        rep_base += inst[k].R;
+        perm_off += (int64_t)inst[k].R * inst[k].N;
+    }
+
+    // ---- H recompute and fresh best state ----
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    for (int k = 0; k < n_inst; ++k)
+        PDIT_HIP(ctx, run_recompute(ctx, plan[k].mode, inst[k].N, inst[k].D, inst[k].F, inst[k].R,
+                                    inst[k].perm, (char *)ctx->h_buf.ptr + plan[k].hoff,
+                                    plan[k].h64, S.E + desc[k].rep_base));
+    if (fresh) {
+        PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * S.R_total,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+        for (int k = 0; k < n_inst; ++k)
+            PDIT_HIP(ctx, hipMemcpyAsync(S.perm_best + desc[k].perm_off, inst[k].perm,
+                                         sizeof(int32_t) * (size_t)inst[k].R * inst[k].N,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+
+    if (n_sweeps > 0) {
+        // ---- groups of work items: (kernel, size class, diagonal mode), largest N first ----
+        struct Group {
+            bool fast, zd, h64;
+            int nmax;
+            std::vector<int2> items;
+            int grid;
+        };
+        std::vector<Group> groups;
+        std::vector<int> order(n_inst);
+        for (int k = 0; k < n_inst; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return inst[x].N > inst[y].N; });
+        for (int k : order) {
+            const Plan &pl = plan[k];
+            const int nmax = pl.fast ? pdit::fast_class(inst[k].N) : 0;
+            Group *g = nullptr;
+            for (auto &gg : groups)
+                if (gg.fast == pl.fast && gg.nmax == nmax && (pl.fast ? gg.zd == pl.zd : gg.h64 == pl.h64))
+                    g = &gg;
+            if (!g) {
+                groups.push_back(Group{pl.fast, pl.fast && pl.zd, !pl.fast && pl.h64, nmax, {}, 0});
+                g = &groups.back();
+            }
+            for (int r = 0; r < inst[k].R; ++r) g->items.push_back(make_int2(k, r));
+        }
+        for (auto &g : groups) {
+            int bpc = g.fast ? pdit::fast_blocks_per_cu(g.nmax) : pdit::plain_blocks_per_cu(g.h64);
+            if (ctx->opts.blocks_per_cu > 0 && ctx->opts.blocks_per_cu < bpc) bpc = ctx->opts.blocks_per_cu;
+            const int64_t want = (int64_t)bpc * std::max(ctx->num_cus, 1);
+            g.grid = (int)std::min<int64_t>(want, (int64_t)g.items.size());
+        }
+
+        // ---- device blob: descriptors, items, queues, parameters ----
+        auto align = [](size_t x) { return (x + 15) & ~(size_t)15; };
+        const size_t off_desc = 0;
+        size_t off = align(sizeof(pdit::BatchInstance) * n_inst);
+        std::vector<size_t> off_items(groups.size());
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            off_items[gi] = off;
+            off = align(off + sizeof(int2) * groups[gi].items.size());
+        }
+        const size_t off_queue = off;
+        off = align(off + sizeof(int) * groups.size());
+        const size_t off_params = off;
+        const size_t blob_bytes = align(off + sizeof(pdit::BatchParams));
+        std::vector<char> blob(blob_bytes, 0);
+        memcpy(blob.data() + off_desc, desc.data(), sizeof(pdit::BatchInstance) * n_inst);
+        for (size_t gi = 0; gi < groups.size(); ++gi)
+            memcpy(blob.data() + off_items[gi], groups[gi].items.data(),
+                   sizeof(int2) * groups[gi].items.size());
+        pdit::BatchParams params{seed, ctx->sweep_offset};
+
+        // signature of the captured graph: the blob without the parameters,
+        // the launch shapes and every buffer address the kernels receive
+        const int seq_thr = ctx->opts.seq_threshold < 0 ? pdit::kDefaultSeqThreshold
+                                                        : ctx->opts.seq_threshold;
+        std::vector<char> sig(blob.begin(), blob.begin() + off_params);
+        auto push = [&](const void *p, size_t n) {
+            sig.insert(sig.end(), (const char *)p, (const char *)p + n);
+        };
+        rc = ensure(ctx, ctx->batch_buf, blob_bytes);
+        if (rc) return rc;
+        void *ptrs[7] = {ctx->batch_buf.ptr, ctx->h_buf.ptr, S.E, S.E_best, S.perm_best, S.counters,
+                         (void *)ctx->stream};
+        push(ptrs, sizeof(ptrs));
+        push(&n_sweeps, sizeof(n_sweeps));
+        push(&seq_thr, sizeof(seq_thr));
+        for (auto &g : groups) push(&g.grid, sizeof(g.grid));
+
+        char *dbuf = (char *)ctx->batch_buf.ptr;
+        if (sig != ctx->graph_sig || !ctx->graph_exec) {
+            // descriptors and items change only with the signature
+            PDIT_HIP(ctx, hipMemcpyAsync(dbuf, blob.data(), off_params, hipMemcpyHostToDevice,
+                                         ctx->stream));
+            PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->graph_exec) {
+                PDIT_HIP(ctx, hipGraphExecDestroy(ctx->graph_exec));
+                ctx->graph_exec = nullptr;
+            }
+            ctx->graph_sig.clear();
+            hipStream_t cs = ctx->capture_stream;
+            PDIT_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            hipError_t cap = pdit::launch_queue_reset(cs, (int *)(dbuf + off_queue), (int)groups.size());
+            for (size_t gi = 0; gi < groups.size() && cap == hipSuccess; ++gi) {
+                const auto &g = groups[gi];
+                pdit::BatchArgs b{};
+                b.inst = (const pdit::BatchInstance *)(dbuf + off_desc);
+                b.items = (const int2 *)(dbuf + off_items[gi]);
+                b.n_items = (int)g.items.size();
+                b.queue = (int *)(dbuf + off_queue) + gi;
+                b.params = (const pdit::BatchParams *)(dbuf + off_params);
+                b.H = ctx->h_buf.ptr;
+                b.E = S.E;
+                b.E_best = S.E_best;
+                b.perm_best = S.perm_best;
+                b.counters = S.counters;
+                b.T = n_sweeps;
+                b.seq_threshold = seq_thr;
+                cap = g.fast ? pdit::launch_sweep_fast_persistent(cs, g.nmax, g.zd, b, g.grid)
+                             : pdit::launch_sweep_plain_persistent(cs, g.h64, b, g.grid);
+            }
+            hipGraph_t graph = nullptr;
+            const hipError_t end = hipStreamEndCapture(cs, &graph);
+            if (cap != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                return fail_hip(ctx, cap, "persistent launch during capture");
+            }
+            PDIT_HIP(ctx, end);
+            const hipError_t inst_rc = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            PDIT_HIP(ctx, inst_rc);
+            ctx->graph_sig = sig;
+        }
+        PDIT_HIP(ctx, hipMemcpyAsync(dbuf + off_params, &params, sizeof(params),
+                                     hipMemcpyHostToDevice, ctx->stream));
+        PDIT_HIP(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    } else {
+        PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * S.R_total, ctx->stream));
+    }
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->timed = true;
+    ctx->sweep_offset += (uint64_t)n_sweeps;
+    ctx->last_updates = 0;
+    for (int k = 0; k < n_inst; ++k) ctx->last_updates += (int64_t)inst[k].R * inst[k].N * n_sweeps;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
+int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_t n_trial_sweeps,
+                  uint64_t seed, pdit_tuning *out) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!inst || n_inst < 1 || n_trial_sweeps < 1)
+        return fail(ctx, PDIT_EINVAL, "bad instance list or trial length");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    // private copies of the permutations: trials must not touch the caller's state
+    std::vector<pdit_instance> trial(inst, inst + n_inst);
+    std::vector<int32_t *> copies(n_inst, nullptr);
+    int rc = PDIT_OK;
+    pdit_t *tmp = nullptr;
+    for (int k = 0; k < n_inst && rc == PDIT_OK; ++k) {
+        if (!inst[k].perm || inst[k].N < 2 || inst[k].R < 1) rc = PDIT_EINVAL;
+        else if (hipMalloc(&copies[k], sizeof(int32_t) * (size_t)inst[k].R * inst[k].N) != hipSuccess)
+            rc = PDIT_ENOMEM;
+        trial[k].perm = copies[k];
+    }
+    pdit_opts o = ctx->opts;
+    if (rc == PDIT_OK) rc = pdit_create(&tmp, &o);
+    int max_bpc = 1;
+    for (int k = 0; k < n_inst; ++k)
+        max_bpc = std::max(max_bpc, pdit::sweep_fast_supports(inst[k].N)
+                                        ? pdit::fast_blocks_per_cu(pdit::fast_class(inst[k].N))
+                                        : pdit::plain_blocks_per_cu(false));
+    pdit_tuning best{0, 0, 1e300};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == PDIT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = PDIT_EDEVICE;
+    const int thresholds[3] = {1, 3, 8};
+    for (int bpc = 1; bpc <= max_bpc && rc == PDIT_OK; ++bpc) {
+        for (int ti = 0; ti < 3 && rc == PDIT_OK; ++ti) {
+            for (int k = 0; k < n_inst; ++k)
+                if (hipMemcpyAsync(copies[k], inst[k].perm, sizeof(int32_t) * (size_t)inst[k].R * inst[k].N,
+                                   hipMemcpyDeviceToDevice, tmp->stream) != hipSuccess)
+                    rc = PDIT_EDEVICE;
+            tmp->opts.blocks_per_cu = bpc;
+            tmp->opts.seq_threshold = thresholds[ti];
+            tmp->sweep_offset = ctx->sweep_offset;
+            pdit_reset(tmp);
+            // first run captures the graph for this setting; the timed run replays it
+            if (rc == PDIT_OK) rc = pdit_run_sweeps_batch(tmp, n_inst, trial.data(), n_trial_sweeps, seed);
+            for (int k = 0; k < n_inst && rc == PDIT_OK; ++k)
+                if (hipMemcpyAsync(copies[k], inst[k].perm, sizeof(int32_t) * (size_t)inst[k].R * inst[k].N,
+                                   hipMemcpyDeviceToDevice, tmp->stream) != hipSuccess)
+                    rc = PDIT_EDEVICE;
+            tmp->sweep_offset = ctx->sweep_offset;
+            if (rc == PDIT_OK && hipEventRecord(e0, tmp->stream) != hipSuccess) rc = PDIT_EDEVICE;
+            if (rc == PDIT_OK) rc = pdit_run_sweeps_batch(tmp, n_inst, trial.data(), n_trial_sweeps, seed);
+            if (rc == PDIT_OK && (hipEventRecord(e1, tmp->stream) != hipSuccess ||
+                                  hipEventSynchronize(e1) != hipSuccess))
+                rc = PDIT_EDEVICE;
+            float ms = 0.f;
+            if (rc == PDIT_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = PDIT_EDEVICE;
+            if (rc == PDIT_OK && ms < best.best_ms) best = pdit_tuning{bpc, thresholds[ti], (double)ms};
+        }
+    }
+    if (rc != PDIT_OK && tmp && !tmp->last_error.empty()) ctx->last_error = tmp->last_error;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    pdit_destroy(tmp);
+    for (auto *c : copies) hipFree(c);
+    if (rc != PDIT_OK) {
+        if (ctx->last_error.empty()) ctx->last_error = "autotune trial failed";
+        return rc;
+    }
+    ctx->opts.blocks_per_cu = best.blocks_per_cu;
+    ctx->opts.seq_threshold = best.seq_threshold;
+    if (out) *out = best;
+    return PDIT_OK;
 }
 
 int pdit_energy(pdit_t *ctx, int64_t *E_out) {

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/pdit.h"
+#include "sweep_common.h"
 
 namespace pdit {
 
@@ -74,6 +75,12 @@ struct pdit_ctx {
     int64_t last_updates = 0;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // before recompute, before sweep, after sweep
     bool timed = false;                               // events of the last run are recorded
+    // batched runs: descriptors, work items, queues and per-call parameters
+    pdit::DeviceBuffer batch_buf;
+    hipStream_t capture_stream = nullptr;             // graphs are captured here, launched on `stream`
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<char> graph_sig;                      // what the captured graph was built for
+    int num_cus = 0;
 };
 
 namespace pdit {
@@ -109,14 +116,23 @@ struct SweepArgs {
     uint32_t inst_id;
     int32_t *choices;        // optional [R][T][N]
     int64_t *E_trace;        // optional [R][T]
-    int replicas_per_block;
     int seq_threshold;
     bool zero_diag;          // D and F have zero diagonals
 };
 
+constexpr int kFastNMax = 128;            // largest N of the on-chip kernel
+constexpr int kDefaultSeqThreshold = 3;   // swaps per sweep above which the next sweep is sequential
+
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
 hipError_t launch_sweep_fast(hipStream_t s, const SweepArgs &a);
 bool sweep_fast_supports(int N);
+int fast_class(int N);                    // 16, 32, 64 or 128: the kernel size that runs N
+hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zero_diag, const BatchArgs &b,
+                                        int grid);
+int fast_blocks_per_cu(int nmax);
+hipError_t launch_sweep_plain_persistent(hipStream_t s, bool h64, const BatchArgs &b, int grid);
+hipError_t launch_queue_reset(hipStream_t s, int *queue, int n);
+int plain_blocks_per_cu(bool h64);
 
 hipError_t launch_debug_delta(hipStream_t s, int N, const int32_t *D, const int32_t *F, int R,
                               const int32_t *perm, const int64_t *H, int r, int64_t *out);

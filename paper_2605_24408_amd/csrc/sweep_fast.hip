@@ -2,12 +2,13 @@
 //
 // One workgroup owns one replica.  Its H = D F[p,p] (int32, stored doubled)
 // and its permuted flows Fp = F[p,p] (int16), with D (int16), live in LDS for
-// the whole run; N <= 64.  The method's order of updates (locations 0..N-1 per
-// sweep, each a Gibbs choice among N candidates; Results, "Implementation",
-// Eq. 3 and Eq. 5) is kept exactly.  The workgroup has NMAX/16 waves; wave w
-// owns the 16 locations 16w..16w+15 and the lanes of a quad split the
-// candidates of one location four ways, so a replica keeps NMAX/16 waves
-// busy and four replicas of N = 64 share a CU with four waves per SIMD.
+// the whole run; N <= 128.  The method's order of updates (locations 0..N-1
+// per sweep, each a Gibbs choice among N candidates; Results,
+// "Implementation", Eq. 3 and Eq. 5) is kept exactly.  The workgroup has
+// NMAX/16 waves; wave w owns the 16 locations 16w..16w+15 and the lanes of a
+// quad split the candidates of one location four ways, so a replica keeps
+// NMAX/16 waves busy; four replicas of N = 64 share a CU with four waves per
+// SIMD, one replica of N = 128 fills a CU's LDS with two waves per SIMD.
 //
 // Two schedules give the same result:
 //
@@ -34,6 +35,7 @@
 // Keeping 2H and 4D makes it two adds and a 24-bit multiply-add.
 #include "device_common.h"
 #include "pdit_internal.h"
+#include "sweep_common.h"
 
 namespace pdit {
 namespace {
@@ -58,40 +60,51 @@ __device__ __forceinline__ uint32_t quadu(uint32_t v) {
     return (uint32_t)quad<CTRL>((int32_t)v);
 }
 
-// four replicas of N = 64 per CU need four waves per SIMD: at most 128 VGPRs
-template <int NMAX, bool ZD, bool EXACT>
-__global__ void __launch_bounds__(64 * (NMAX / 16)) __attribute__((amdgpu_waves_per_eu(4)))
-sweep_fast_kernel(SweepArgs a) {
-    constexpr int WPR = NMAX / 16;  // waves per replica
-    constexpr int K = NMAX / 4;     // candidates per lane in a speculative pass
-    constexpr int P = NMAX + 1;     // H row pitch (int32): column reads are conflict-free
-    constexpr int PF = NMAX + 2;    // Fp row pitch (int16)
-    constexpr int kDScale = ZD ? 4 : 1;  // Ds holds 4 D with zero diagonals
+template <int NMAX>
+struct FastSmem {
+    static constexpr int P = NMAX + 1;   // H row pitch (int32): column reads are conflict-free
+    static constexpr int PF = NMAX + 2;  // Fp row pitch (int16)
+    int32_t Hs[NMAX * P];                // 2 H
+    int16_t Ds[NMAX * NMAX];             // D, times 4 with zero diagonals
+    int16_t Fp[NMAX * PF];               // F[p,p]
+    int32_t hdv[NMAX];                   // 2 H[l][l]
+    int32_t ddv[NMAX];                   // D[l][l]
+    int32_t fdv[NMAX];                   // Fp[l][l]
+    int32_t pv[NMAX];                    // p(l)
+    int32_t sel_row[2][NMAX];
+    int32_t flag_row[2][NMAX];           // bit 0: the row swaps, bit 1: tie
+};
 
-    __shared__ int32_t Hs[NMAX * P];  // 2 H
-    __shared__ int16_t Ds[NMAX * NMAX];
-    __shared__ int16_t Fp[NMAX * PF];
-    __shared__ int32_t hdv[NMAX];  // 2 H[l][l]
-    __shared__ int32_t ddv[NMAX];  // D[l][l]
-    __shared__ int32_t fdv[NMAX];  // Fp[l][l]
-    __shared__ int32_t pv[NMAX];   // p(l)
-    __shared__ int32_t sel_row[2][NMAX];
-    __shared__ int32_t flag_row[2][NMAX];  // bit 0: the row swaps, bit 1: tie
+// Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).
+template <int NMAX, bool ZD, bool EXACT>
+__device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX> &sm) {
+    constexpr int WPR = NMAX / 16;       // waves per replica
+    constexpr int K = NMAX / 4;          // candidates per lane in a speculative pass
+    constexpr int CPL = (NMAX + 63) / 64;  // locations per lane in row-vector work
+    constexpr int P = FastSmem<NMAX>::P;
+    constexpr int PF = FastSmem<NMAX>::PF;
+    constexpr int kDScale = ZD ? 4 : 1;
+    int32_t *Hs = sm.Hs;
+    int16_t *Ds = sm.Ds;
+    int16_t *Fp = sm.Fp;
+    int32_t *hdv = sm.hdv;
+    int32_t *ddv = sm.ddv;
+    int32_t *fdv = sm.fdv;
+    int32_t *pv = sm.pv;
 
     const int N = EXACT ? NMAX : a.N;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
-    const int64_t rep = blockIdx.x;
 
     // ---- stage D, p, 2H and F[p,p] (zero outside N) ----
     for (int e = tid; e < NMAX * NMAX; e += 64 * WPR) {
         const int i = e / NMAX, j = e % NMAX;
         Ds[e] = (int16_t)((i < N && j < N) ? kDScale * a.D[(int64_t)i * N + j] : 0);
     }
-    for (int e = tid; e < NMAX; e += 64 * WPR) pv[e] = e < N ? a.perm[rep * N + e] : 0;
+    for (int e = tid; e < NMAX; e += 64 * WPR) pv[e] = e < N ? a.perm[e] : 0;
     {
-        const int32_t *Hg = (const int32_t *)a.H + rep * (int64_t)N * N;
+        const int32_t *Hg = (const int32_t *)a.H;
         for (int e = tid; e < NMAX * P; e += 64 * WPR) {
             const int i = e / P, k = e % P;
             Hs[e] = (i < N && k < N) ? 2 * Hg[(int64_t)i * N + k] : 0;
@@ -110,8 +123,8 @@ sweep_fast_kernel(SweepArgs a) {
     }
     __syncthreads();
 
-    int64_t E = a.E[rep];
-    int64_t E_best = a.E_best[rep];
+    int64_t E = *a.E;
+    int64_t E_best = *a.E_best;
     int64_t n_acc = 0, n_tie = 0;
     int parity = 0;
     bool seq_mode = false;
@@ -119,8 +132,6 @@ sweep_fast_kernel(SweepArgs a) {
     // speculative layout: this lane's location and candidate quarter
     const int rl = lane >> 2, cq = lane & 3;
     const int rr = 16 * wv + rl;  // location of this lane's row
-    // candidate layout for one-update-at-a-time (lanes >= NMAX are idle)
-    const int ls = lane < NMAX ? lane : 0;
 
     // energy change of the (uniform) pair r, s, from LDS
     auto pair_delta = [&](int r, int s) -> int32_t {
@@ -136,8 +147,14 @@ sweep_fast_kernel(SweepArgs a) {
         ++n_acc;
         // column k of the new H is column src(k) of H + u v^T, with
         // u_i = D[i][s] - D[i][r] and v_src = Fp[r][src] - Fp[s][src]
-        const int src = ls == r ? s : ls == s ? r : ls;
-        const int32_t v = (int32_t)Fp[r * PF + src] - (int32_t)Fp[s * PF + src];
+        int src[CPL];
+        int32_t v[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int k = (lane + 64 * c) < NMAX ? lane + 64 * c : 0;
+            src[c] = k == r ? s : k == s ? r : k;
+            v[c] = (int32_t)Fp[r * PF + src[c]] - (int32_t)Fp[s * PF + src[c]];
+        }
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
 #pragma unroll 4
         for (int ii = 0; ii < 16; ++ii) {
@@ -145,8 +162,12 @@ sweep_fast_kernel(SweepArgs a) {
             if (EXACT || i < N) {
                 const int32_t du = (int32_t)Ds[s * NMAX + i] - (int32_t)Ds[r * NMAX + i];
                 const int32_t u2 = ZD ? du / 2 : 2 * du;  // 2 u_i
-                const int32_t x = Hs[i * P + src];
-                if (lane < N) Hs[i * P + lane] = x + u2 * v;
+                int32_t x[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) x[c] = Hs[i * P + src[c]];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if (lane + 64 * c < N) Hs[i * P + lane + 64 * c] = x[c] + u2 * v[c];
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -156,16 +177,24 @@ sweep_fast_kernel(SweepArgs a) {
         }
         if (wv == 0) {
             // Fp <- Fp with rows r, s and then columns r, s exchanged
-            if (lane < N) {
-                const int16_t fr = Fp[r * PF + lane], fs = Fp[s * PF + lane];
-                Fp[r * PF + lane] = fs;
-                Fp[s * PF + lane] = fr;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int k = lane + 64 * c;
+                if (k < N) {
+                    const int16_t fr = Fp[r * PF + k], fs = Fp[s * PF + k];
+                    Fp[r * PF + k] = fs;
+                    Fp[s * PF + k] = fr;
+                }
             }
             __builtin_amdgcn_wave_barrier();
-            if (lane < N) {
-                const int16_t cr = Fp[lane * PF + r], cs = Fp[lane * PF + s];
-                Fp[lane * PF + r] = cs;
-                Fp[lane * PF + s] = cr;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int k = lane + 64 * c;
+                if (k < N) {
+                    const int16_t cr = Fp[k * PF + r], cs = Fp[k * PF + s];
+                    Fp[k * PF + r] = cs;
+                    Fp[k * PF + s] = cr;
+                }
             }
             if (lane == 0) {
                 const int32_t fa = pv[r], fb = pv[s];
@@ -181,7 +210,11 @@ sweep_fast_kernel(SweepArgs a) {
         __syncthreads();
         if (E < E_best) {
             E_best = E;
-            if (wv == 0 && lane < N) a.perm_best[rep * N + lane] = pv[lane];
+            if (wv == 0) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if (lane + 64 * c < N) a.perm_best[lane + 64 * c] = pv[lane + 64 * c];
+            }
         }
     };
 
@@ -190,11 +223,11 @@ sweep_fast_kernel(SweepArgs a) {
         const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
         const int32_t dthr = zero_weight_distance(beta);
         const int64_t acc_before = n_acc;
-        int32_t *ch = (a.choices && wv == 0) ? a.choices + (rep * a.T + t) * N : nullptr;
+        int32_t *ch = (a.choices && wv == 0) ? a.choices + t * N : nullptr;
 
         if (!seq_mode) {
             // ============ speculative rows: 16 locations per wave, 4 lanes each ============
-            const uint32_t u24 = uniform24(a.seed, (uint32_t)rr, g, (uint32_t)rep, a.inst_id);
+            const uint32_t u24 = uniform24(a.seed, (uint32_t)rr, g, a.rep, a.inst);
             int pos = 0;
             while (pos < N) {
                 const bool rowv = rr < N && rr >= pos;
@@ -282,21 +315,35 @@ sweep_fast_kernel(SweepArgs a) {
                     swaps = rowv && sel != rr;
                 }
                 if (cq == 0) {
-                    sel_row[parity][rr] = sel;
-                    flag_row[parity][rr] = (swaps ? 1 : 0) | (rowv && tie ? 2 : 0);
+                    sm.sel_row[parity][rr] = sel;
+                    sm.flag_row[parity][rr] = (swaps ? 1 : 0) | (rowv && tie ? 2 : 0);
                 }
                 __syncthreads();
                 // every wave reads the same flags: first swapping row from pos
-                const int32_t fl = lane < NMAX ? flag_row[parity][lane] : 0;
-                const uint64_t acc_mask = __ballot(fl & 1);
-                const int last = acc_mask ? __ffsll((unsigned long long)acc_mask) - 1 : N - 1;
-                const bool committed = lane >= pos && lane <= last && lane < N;
-                if (wv == 0) {
-                    n_tie += __popcll(__ballot(committed && (fl & 2)));
-                    if (ch && committed) ch[lane] = sel_row[parity][lane];
+                int last = N - 1;
+                bool found = false;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int row = lane + 64 * c;
+                    const int32_t fl = row < NMAX ? sm.flag_row[parity][row] : 0;
+                    const uint64_t acc_mask = __ballot(fl & 1);
+                    if (!found && acc_mask) {
+                        last = 64 * c + __ffsll((unsigned long long)acc_mask) - 1;
+                        found = true;
+                    }
                 }
-                if (acc_mask) {
-                    const int s = sel_row[parity][last];
+                if (wv == 0) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const int row = lane + 64 * c;
+                        const int32_t fl = row < NMAX ? sm.flag_row[parity][row] : 0;
+                        const bool committed = row >= pos && row <= last && row < N;
+                        n_tie += __popcll(__ballot(committed && (fl & 2)));
+                        if (ch && committed) ch[row] = sm.sel_row[parity][row];
+                    }
+                }
+                if (found) {
+                    const int s = sm.sel_row[parity][last];
                     apply_swap(last, s, (int64_t)pair_delta(last, s));
                 }
                 parity ^= 1;
@@ -304,52 +351,133 @@ sweep_fast_kernel(SweepArgs a) {
             }
         } else {
             // ============ one update at a time: lane = candidate ============
-            const uint32_t u24l = uniform24(a.seed, (uint32_t)ls, g, (uint32_t)rep, a.inst_id);
-            const bool lv = lane < N;
+            uint32_t u24l[CPL];
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                u24l[c] = uniform24(a.seed, (uint32_t)(lane + 64 * c), g, a.rep, a.inst);
             for (int r = 0; r < N; ++r) {
-                int32_t v = kBig;
-                if (lv) {
-                    const int32_t x = Hs[r * P + ls] + Hs[ls * P + r] - hdv[r] - hdv[ls];
-                    const int32_t dv = Ds[r * NMAX + ls];
-                    const int32_t fv = Fp[r * PF + ls];
-                    if (ZD) {
-                        v = __mul24(dv, fv) + x;
-                    } else {
-                        v = x + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
+                int32_t v[CPL];
+                uint32_t q[CPL];
+                int32_t lmin = kBig;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int ls = lane + 64 * c;
+                    v[c] = kBig;
+                    if (ls < N) {
+                        const int32_t x = Hs[r * P + ls] + Hs[ls * P + r] - hdv[r] - hdv[ls];
+                        const int32_t dv = Ds[r * NMAX + ls];
+                        const int32_t fv = Fp[r * PF + ls];
+                        if (ZD) {
+                            v[c] = __mul24(dv, fv) + x;
+                        } else {
+                            v[c] = x + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
+                        }
                     }
+                    lmin = min(lmin, v[c]);
                 }
-                const int32_t mn = wave_min_i32(v);
-                const int32_t d = lv ? v - mn : 0;
-                uint32_t q = d == 0 ? kOne : 0u;
-                if (d > 0 && d < dthr) q = gibbs_weight(beta, (float)d);
-                if (!lv) q = 0;
-                const uint32_t C = wave_scan_u32(q);
-                const uint32_t Z = (uint32_t)__builtin_amdgcn_readlane((int32_t)C, 63);
-                const uint32_t ur24 = (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l, r);
+                const int32_t mn = wave_min_i32(lmin);
+                uint32_t C[CPL];
+                uint32_t base = 0;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const bool valid = lane + 64 * c < N;
+                    const int32_t d = valid ? v[c] - mn : 0;
+                    q[c] = d == 0 ? kOne : 0u;
+                    if (d > 0 && d < dthr) q[c] = gibbs_weight(beta, (float)d);
+                    if (!valid) q[c] = 0;
+                    C[c] = base + wave_scan_u32(q[c]);
+                    base = (uint32_t)__builtin_amdgcn_readlane((int32_t)C[c], 63);
+                }
+                const uint32_t Z = base;
+                const uint32_t ur24 =
+                    (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l[CPL > 1 ? (r >> 6) : 0], r & 63);
                 const uint32_t thr = (uint32_t)(((uint64_t)ur24 * Z) >> 24);
-                const uint64_t hit = __ballot(C > thr);
-                int s = __ffsll((unsigned long long)hit) - 1;
-                if (s < 0 || s >= N) s = r;  // unreachable: lane N-1 holds C = Z > thr
-                const uint32_t csel = (uint32_t)__builtin_amdgcn_readlane((int32_t)C, s);
-                const uint32_t cprev = csel - (uint32_t)__builtin_amdgcn_readlane((int32_t)q, s);
+                int s = -1;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const uint64_t hit = __ballot(C[c] > thr);
+                    if (s < 0 && hit) s = 64 * c + __ffsll((unsigned long long)hit) - 1;
+                }
+                if (s < 0 || s >= N) s = r;  // unreachable: location N-1 holds C = Z > thr
+                const int sc = CPL > 1 ? (s >> 6) : 0, sl = s & 63;
+                const uint32_t csel = (uint32_t)__builtin_amdgcn_readlane((int32_t)C[sc], sl);
+                const uint32_t cprev = csel - (uint32_t)__builtin_amdgcn_readlane((int32_t)q[sc], sl);
                 if (wv == 0) n_tie += is_tie(cprev, csel, Z, ur24) ? 1 : 0;
                 if (ch && lane == 0) ch[r] = s;
-                if (s != r) apply_swap(r, s, (int64_t)__builtin_amdgcn_readlane(v, s));
+                if (s != r) apply_swap(r, s, (int64_t)__builtin_amdgcn_readlane(v[sc], sl));
             }
         }
         seq_mode = (n_acc - acc_before) > a.seq_threshold;
-        if (a.E_trace && tid == 0) a.E_trace[rep * a.T + t] = E;
+        if (a.E_trace && tid == 0) a.E_trace[t] = E;
     }
 
     if (wv == 0) {
-        if (lane < N) a.perm[rep * N + lane] = pv[lane];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+            if (lane + 64 * c < N) a.perm[lane + 64 * c] = pv[lane + 64 * c];
         if (lane == 0) {
-            a.E[rep] = E;
-            a.E_best[rep] = E_best;
-            a.counters[rep * 3 + 0] = (int64_t)N * a.T;
-            a.counters[rep * 3 + 1] = n_acc;
-            a.counters[rep * 3 + 2] = n_tie;
+            *a.E = E;
+            *a.E_best = E_best;
+            a.counters[0] = (int64_t)N * a.T;
+            a.counters[1] = n_acc;
+            a.counters[2] = n_tie;
         }
+    }
+}
+
+// four replicas of N <= 64 per CU need four waves per SIMD (at most 128
+// VGPRs); N <= 128 runs one replica of eight waves per CU
+template <int NMAX>
+constexpr int fast_waves_per_eu() { return NMAX >= 128 ? 2 : 4; }
+
+// One replica per workgroup (single-instance runs).
+template <int NMAX, bool ZD, bool EXACT>
+__global__ void __launch_bounds__(64 * (NMAX / 16))
+__attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<NMAX>())))
+sweep_fast_kernel(SweepArgs a) {
+    __shared__ FastSmem<NMAX> sm;
+    const int64_t rep = blockIdx.x;
+    ReplicaJob j;
+    j.N = a.N;
+    j.D = a.D;
+    j.F = a.F;
+    j.perm = a.perm + rep * a.N;
+    j.H = (const int32_t *)a.H + rep * (int64_t)a.N * a.N;
+    j.E = a.E + rep;
+    j.E_best = a.E_best + rep;
+    j.perm_best = a.perm_best + rep * a.N;
+    j.counters = a.counters + 3 * rep;
+    j.beta = a.beta;
+    j.T = a.T;
+    j.seed = a.seed;
+    j.sweep_offset = a.sweep_offset;
+    j.rep = (uint32_t)rep;
+    j.inst = a.inst_id;
+    j.choices = a.choices ? a.choices + rep * a.T * a.N : nullptr;
+    j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
+    j.seq_threshold = a.seq_threshold;
+    j.zero_diag = ZD;
+    fast_replica<NMAX, ZD, EXACT>(j, sm);
+}
+
+// Persistent: each workgroup takes (instance, replica) items from a queue
+// until it is exhausted; items come largest N first.
+// Every workgroup reaches the exit: the queue only grows, so each one reads
+// an item index >= n_items after at most n_items increments.
+template <int NMAX, bool ZD>
+__global__ void __launch_bounds__(64 * (NMAX / 16))
+__attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<NMAX>())))
+sweep_fast_persistent(BatchArgs b) {
+    __shared__ FastSmem<NMAX> sm;
+    __shared__ int item_sh;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
+        __syncthreads();
+        const int item = item_sh;
+        __syncthreads();
+        if (item >= b.n_items) break;
+        fast_replica<NMAX, ZD, false>(batch_job(b, item, sizeof(int32_t)), sm);
+        __syncthreads();
     }
 }
 
@@ -369,14 +497,51 @@ hipError_t launch_nmax(hipStream_t s, const SweepArgs &a) {
 
 }  // namespace
 
-bool sweep_fast_supports(int N) { return N >= 2 && N <= 64; }
+bool sweep_fast_supports(int N) { return N >= 2 && N <= kFastNMax; }
+
+int fast_class(int N) { return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 128; }
 
 hipError_t launch_sweep_fast(hipStream_t s, const SweepArgs &a0) {
     SweepArgs a = a0;
-    if (a.seq_threshold < 0) a.seq_threshold = 3;
+    if (a.seq_threshold < 0) a.seq_threshold = kDefaultSeqThreshold;
     if (a.N <= 16) return launch_nmax<16>(s, a);
     if (a.N <= 32) return launch_nmax<32>(s, a);
-    return launch_nmax<64>(s, a);
+    if (a.N <= 64) return launch_nmax<64>(s, a);
+    return launch_nmax<128>(s, a);
+}
+
+template <int NMAX>
+hipError_t launch_persistent_nmax(hipStream_t s, bool zd, const BatchArgs &b, int grid) {
+    if (zd)
+        sweep_fast_persistent<NMAX, true><<<grid, 64 * (NMAX / 16), 0, s>>>(b);
+    else
+        sweep_fast_persistent<NMAX, false><<<grid, 64 * (NMAX / 16), 0, s>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zd, const BatchArgs &b,
+                                        int grid) {
+    switch (nmax) {
+        case 16: return launch_persistent_nmax<16>(s, zd, b, grid);
+        case 32: return launch_persistent_nmax<32>(s, zd, b, grid);
+        case 64: return launch_persistent_nmax<64>(s, zd, b, grid);
+        case 128: return launch_persistent_nmax<128>(s, zd, b, grid);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int fast_blocks_per_cu(int nmax) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (nmax) {
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<16, true>, 64, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<32, true>, 128, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<64, true>, 256, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<128, true>, 512, 0); break;
+        default: break;
+    }
+    (void)hipGetLastError();
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 }  // namespace pdit

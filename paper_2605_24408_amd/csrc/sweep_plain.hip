@@ -10,6 +10,7 @@
 //     H are exchanged, which gives D F[p',p'] for the new permutation p'.
 #include "device_common.h"
 #include "pdit_internal.h"
+#include "sweep_common.h"
 
 namespace pdit {
 namespace {
@@ -28,27 +29,34 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *red) {
     return m;
 }
 
-template <typename HT>
-__global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
-    __shared__ int32_t p[PDIT_NMAX];
-    __shared__ int64_t dE[PDIT_NMAX];
-    __shared__ uint64_t C[PDIT_NMAX];
-    __shared__ uint64_t Ctmp[PDIT_NMAX];
-    __shared__ int32_t uvec[PDIT_NMAX];
-    __shared__ int32_t vvec[PDIT_NMAX];
-    __shared__ int64_t red[kBlock];
-    __shared__ int32_t sel_sh, tie_sh;
+struct PlainSmem {
+    int32_t p[PDIT_NMAX];
+    int64_t dE[PDIT_NMAX];
+    uint64_t C[PDIT_NMAX];
+    uint64_t Ctmp[PDIT_NMAX];
+    int32_t uvec[PDIT_NMAX];
+    int32_t vvec[PDIT_NMAX];
+    int64_t red[kBlock];
+    int32_t sel_sh, tie_sh;
+};
 
+// Runs one replica's sweeps with the whole workgroup.  H (this replica's
+// N x N, int32 or int64) is updated in place in device memory.
+template <typename HT>
+__device__ void plain_replica(const ReplicaJob &a, PlainSmem &sm) {
+    int32_t *p = sm.p;
+    int64_t *dE = sm.dE;
+    uint64_t *C = sm.C;
+    uint64_t *Ctmp = sm.Ctmp;
     const int N = a.N;
-    const int64_t rep = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int32_t *__restrict__ D = a.D;
     const int32_t *__restrict__ F = a.F;
-    HT *__restrict__ H = (HT *)a.H + rep * (int64_t)N * N;
+    HT *__restrict__ H = (HT *)a.H;
 
-    for (int s = tid; s < N; s += nt) p[s] = a.perm[rep * N + s];
-    int64_t E = a.E[rep];
-    int64_t E_best = a.E_best[rep];
+    for (int s = tid; s < N; s += nt) p[s] = a.perm[s];
+    int64_t E = *a.E;
+    int64_t E_best = *a.E_best;
     int64_t n_acc = 0, n_tie = 0;
     __syncthreads();
 
@@ -73,10 +81,10 @@ __global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
                 dE[s] = v;
                 lmin = min(lmin, v);
             }
-            const int64_t m = block_min_i64(lmin, red);
+            const int64_t m = block_min_i64(lmin, sm.red);
             if (tid == 0) {
-                sel_sh = r;  // overwritten below: exactly one candidate holds the threshold
-                tie_sh = 0;
+                sm.sel_sh = r;  // overwritten below: exactly one candidate holds the threshold
+                sm.tie_sh = 0;
             }
             // ---- Gibbs weights and their running sum (Eq. 5) ----
             for (int s = tid; s < N; s += nt) {
@@ -91,33 +99,33 @@ __global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
                 __syncthreads();
             }
             const uint64_t Z = C[N - 1];
-            const uint32_t u24 = uniform24(a.seed, (uint32_t)r, g, (uint32_t)rep, a.inst_id);
+            const uint32_t u24 = uniform24(a.seed, (uint32_t)r, g, a.rep, a.inst);
             const uint64_t thr = ((uint64_t)u24 * Z) >> 24;
             for (int s = tid; s < N; s += nt) {
                 const uint64_t prev = s > 0 ? C[s - 1] : 0;
                 if (prev <= thr && C[s] > thr) {
-                    sel_sh = s;
-                    tie_sh = is_tie(prev, C[s], Z, u24) ? 1 : 0;
+                    sm.sel_sh = s;
+                    sm.tie_sh = is_tie(prev, C[s], Z, u24) ? 1 : 0;
                 }
             }
             __syncthreads();
-            const int ss = sel_sh;
-            n_tie += tie_sh;
-            if (a.choices && tid == 0) a.choices[(rep * a.T + t) * N + r] = ss;
+            const int ss = sm.sel_sh;
+            n_tie += sm.tie_sh;
+            if (a.choices && tid == 0) a.choices[t * N + r] = ss;
             if (ss != r) {
                 // ---- accepted swap: energy, rank-1 update of H, column exchange ----
                 ++n_acc;
                 E += dE[ss];
                 const int fb = p[ss];
                 for (int i = tid; i < N; i += nt) {
-                    uvec[i] = D[(int64_t)i * N + ss] - D[(int64_t)i * N + r];
+                    sm.uvec[i] = D[(int64_t)i * N + ss] - D[(int64_t)i * N + r];
                     const int c = p[i];
-                    vvec[i] = F[(int64_t)fa * N + c] - F[(int64_t)fb * N + c];
+                    sm.vvec[i] = F[(int64_t)fa * N + c] - F[(int64_t)fb * N + c];
                 }
                 __syncthreads();
                 for (int64_t e = tid; e < (int64_t)N * N; e += nt) {
                     const int i = (int)(e / N), k = (int)(e % N);
-                    H[e] += (HT)((int64_t)uvec[i] * vvec[k]);
+                    H[e] += (HT)((int64_t)sm.uvec[i] * sm.vvec[k]);
                 }
                 __syncthreads();
                 for (int i = tid; i < N; i += nt) {
@@ -132,21 +140,73 @@ __global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
                 __syncthreads();
                 if (E < E_best) {
                     E_best = E;
-                    for (int s = tid; s < N; s += nt) a.perm_best[rep * N + s] = p[s];
+                    for (int s = tid; s < N; s += nt) a.perm_best[s] = p[s];
                 }
             }
             __syncthreads();
         }
-        if (a.E_trace && tid == 0) a.E_trace[rep * a.T + t] = E;
+        if (a.E_trace && tid == 0) a.E_trace[t] = E;
     }
-    for (int s = tid; s < N; s += nt) a.perm[rep * N + s] = p[s];
+    for (int s = tid; s < N; s += nt) a.perm[s] = p[s];
     if (tid == 0) {
-        a.E[rep] = E;
-        a.E_best[rep] = E_best;
-        a.counters[rep * 3 + 0] = (int64_t)N * a.T;
-        a.counters[rep * 3 + 1] = n_acc;
-        a.counters[rep * 3 + 2] = n_tie;
+        *a.E = E;
+        *a.E_best = E_best;
+        a.counters[0] = (int64_t)N * a.T;
+        a.counters[1] = n_acc;
+        a.counters[2] = n_tie;
     }
+}
+
+template <typename HT>
+__global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
+    __shared__ PlainSmem sm;
+    const int64_t rep = blockIdx.x;
+    ReplicaJob j;
+    j.N = a.N;
+    j.D = a.D;
+    j.F = a.F;
+    j.perm = a.perm + rep * a.N;
+    j.H = (HT *)a.H + rep * (int64_t)a.N * a.N;
+    j.E = a.E + rep;
+    j.E_best = a.E_best + rep;
+    j.perm_best = a.perm_best + rep * a.N;
+    j.counters = a.counters + 3 * rep;
+    j.beta = a.beta;
+    j.T = a.T;
+    j.seed = a.seed;
+    j.sweep_offset = a.sweep_offset;
+    j.rep = (uint32_t)rep;
+    j.inst = a.inst_id;
+    j.choices = a.choices ? a.choices + rep * a.T * a.N : nullptr;
+    j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
+    j.seq_threshold = a.seq_threshold;
+    j.zero_diag = a.zero_diag;
+    plain_replica<HT>(j, sm);
+}
+
+// Persistent: each workgroup takes (instance, replica) items from a queue
+// until it is exhausted (every workgroup reaches the exit: the queue only
+// grows).
+template <typename HT>
+__global__ void __launch_bounds__(kBlock) sweep_plain_persistent(BatchArgs b) {
+    __shared__ PlainSmem sm;
+    __shared__ int item_sh;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
+        __syncthreads();
+        const int item = item_sh;
+        __syncthreads();
+        if (item >= b.n_items) break;
+        plain_replica<HT>(batch_job(b, item, sizeof(HT)), sm);
+        __syncthreads();
+    }
+}
+
+// Clears the work queues before a persistent launch (a kernel, not a memset,
+// so that the sequence can be captured in a graph).
+__global__ void queue_reset_kernel(int *queue, int n) {
+    const int i = threadIdx.x;
+    if (i < n) queue[i] = 0;
 }
 
 }  // namespace
@@ -157,6 +217,32 @@ hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64) {
         sweep_plain_kernel<int64_t><<<a.R, threads, 0, s>>>(a);
     else
         sweep_plain_kernel<int32_t><<<a.R, threads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace pdit
+
+namespace pdit {
+
+hipError_t launch_sweep_plain_persistent(hipStream_t s, bool h64, const BatchArgs &b, int grid) {
+    if (h64)
+        sweep_plain_persistent<int64_t><<<grid, kBlock, 0, s>>>(b);
+    else
+        sweep_plain_persistent<int32_t><<<grid, kBlock, 0, s>>>(b);
+    return hipGetLastError();
+}
+
+int plain_blocks_per_cu(bool h64) {
+    int n = 0;
+    const hipError_t e =
+        h64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_plain_persistent<int64_t>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_plain_persistent<int32_t>, kBlock, 0);
+    (void)hipGetLastError();
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_queue_reset(hipStream_t s, int *queue, int n) {
+    queue_reset_kernel<<<1, 64, 0, s>>>(queue, n);
     return hipGetLastError();
 }
 

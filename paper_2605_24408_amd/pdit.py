@@ -34,7 +34,11 @@ class PditError(RuntimeError):
 
 class _Opts(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("recompute", C.c_int),
-                ("sweep", C.c_int), ("replicas_per_block", C.c_int), ("seq_threshold", C.c_int)]
+                ("sweep", C.c_int), ("blocks_per_cu", C.c_int), ("seq_threshold", C.c_int)]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int), ("seq_threshold", C.c_int), ("best_ms", C.c_double)]
 
 
 class _Counters(C.Structure):
@@ -53,7 +57,7 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_replica_counters", "pdit_set_sweep_offset", "pdit_get_sweep_offset",
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
-           "pdit_last_timing"]
+           "pdit_last_timing", "pdit_autotune"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -89,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     L.pdit_debug_choice.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     L.pdit_debug_uniform24.argtypes = [vp, i32, vp, u64, vp]
     L.pdit_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.pdit_autotune.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64, C.POINTER(_Tuning)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("pdit_default_opts", "pdit_last_error"):
@@ -116,7 +121,7 @@ class Pdit:
     """A library context (``pdit_create``) bound to one device and stream."""
 
     def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
-                 recompute: str = "auto", sweep: str = "auto", replicas_per_block: int = 0,
+                 recompute: str = "auto", sweep: str = "auto", blocks_per_cu: int = 0,
                  seq_threshold: int = -1):
         self._L = load_library()
         self.device = torch.device("cuda", device)
@@ -129,7 +134,7 @@ class Pdit:
         o.stream = stream.cuda_stream
         o.recompute = RECOMPUTE[recompute]
         o.sweep = SWEEP[sweep]
-        o.replicas_per_block = replicas_per_block
+        o.blocks_per_cu = blocks_per_cu
         o.seq_threshold = seq_threshold
         h = C.c_void_p()
         rc = self._L.pdit_create(C.byref(h), C.byref(o))
@@ -177,6 +182,44 @@ class Pdit:
         self._rc(self._L.pdit_run_sweeps(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm),
                                          _ptr(beta), int(beta.numel()), int(seed)))
         self._last = (R, R * N, N)
+
+    def _instances(self, instances, n_sweeps: int | None):
+        """instances: sequence of (D, F, perm, beta) tensors; every beta has the
+        same length."""
+        arr = (_Instance * len(instances))()
+        T = None
+        for k, (D, F, perm, beta) in enumerate(instances):
+            for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"),
+                              (perm, torch.int32, "perm"), (beta, torch.float32, "beta")):
+                _check_dev(t, dt, nm, self.device)
+            N = int(D.shape[0])
+            if tuple(D.shape) != (N, N) or tuple(F.shape) != (N, N) or perm.dim() != 2 \
+                    or perm.shape[1] != N:
+                raise ValueError(f"instance {k}: D, F must be N x N and perm R x N")
+            if T is None:
+                T = int(beta.numel())
+            elif int(beta.numel()) != T:
+                raise ValueError("every instance needs a beta schedule of the same length")
+            arr[k] = _Instance(N, int(perm.shape[0]), D.data_ptr(), F.data_ptr(), perm.data_ptr(),
+                               beta.data_ptr())
+        return arr, (T if n_sweeps is None else n_sweeps)
+
+    def run_sweeps_batch(self, instances, seed: int) -> None:
+        """pdit_run_sweeps_batch over (D, F, perm, beta) tensors of uneven N."""
+        arr, T = self._instances(instances, None)
+        self._rc(self._L.pdit_run_sweeps_batch(self._h, len(instances), arr, int(T), int(seed)))
+        R = sum(int(x[2].shape[0]) for x in instances)
+        PT = sum(int(x[2].numel()) for x in instances)
+        self._last = (R, PT, 0)
+
+    def autotune(self, instances, n_trial_sweeps: int, seed: int) -> dict:
+        """pdit_autotune: picks blocks per CU and the sequential threshold."""
+        arr, _ = self._instances(instances, None)
+        t = _Tuning()
+        self._rc(self._L.pdit_autotune(self._h, len(instances), arr, int(n_trial_sweeps),
+                                       int(seed), C.byref(t)))
+        return {"blocks_per_cu": t.blocks_per_cu, "seq_threshold": t.seq_threshold,
+                "best_ms": t.best_ms}
 
     def energy(self) -> torch.Tensor:
         out = torch.empty(self._last[0], dtype=torch.int64, device=self.device)

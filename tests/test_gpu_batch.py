@@ -1,0 +1,193 @@
+"""GPU parity of batched runs (instances of uneven size in persistent,
+graph-captured launches): every (instance, replica) against the oracle with
+the instance's own Philox word, graph replays against resumed oracle runs,
+the autotuner, and the full-size uneven workload on sampled replicas."""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_24408_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def small_batch(T=30, R=3):
+    """Instances across every kernel class: N <= 16, 32, 64, 128 on chip,
+    N > 128 on the plain kernel; zero and nonzero diagonals."""
+    rng = np.random.default_rng(77)
+    out = []
+    for k, (N, zd) in enumerate([(12, True), (20, False), (40, True), (64, True), (70, False),
+                                 (100, True), (130, True), (9, True)]):
+        D, F = W.random_instance(rng, N, 0, 40, zero_diag=zd)
+        perms = W.random_perms(rng, R, N)
+        s = W.energy_scale(D, F)
+        beta = W.beta_geometric(0.2 / s, 50.0 / s, T)
+        out.append((D, F, perms, beta))
+    return out
+
+
+def to_dev(batch):
+    return [(dev(D, torch.int32), dev(F, torch.int32), dev(p, torch.int32), dev(b, torch.float32))
+            for D, F, p, b in batch]
+
+
+def oracle_batch(batch, seed, sweep_offset=0, prev=None):
+    refs = []
+    for k, (D, F, perms, beta) in enumerate(batch):
+        kw = {}
+        if prev is not None:
+            kw = dict(E_best=prev[k].E_best, perm_best=prev[k].perm_best)
+            perms = prev[k].perm
+        refs.append(oracle.run(D, F, perms, beta, seed, sweep_offset=sweep_offset,
+                               rep_ids=list(range(perms.shape[0])), inst_id=k, **kw))
+    return refs
+
+
+def gpu_state(ctx, dbatch):
+    E = ctx.energy().cpu().numpy()
+    Eb, pb = ctx.best()
+    Eb, pb = Eb.cpu().numpy(), pb.cpu().numpy()
+    cnt = ctx.replica_counters().cpu().numpy()
+    out, rb, po = [], 0, 0
+    for D, F, perm, beta in dbatch:
+        R, N = perm.shape
+        out.append(dict(perm=perm.cpu().numpy(), E=E[rb:rb + R], E_best=Eb[rb:rb + R],
+                        perm_best=pb[po:po + R * N].reshape(R, N), counters=cnt[rb:rb + R]))
+        rb += R
+        po += R * N
+    return out
+
+
+def check(got, refs):
+    n_diff = 0
+    for k, (g, r) in enumerate(zip(got, refs)):
+        for j in range(r.perm.shape[0]):
+            same = (np.array_equal(g["perm"][j], r.perm[j]) and g["E"][j] == r.E[j]
+                    and g["E_best"][j] == r.E_best[j]
+                    and np.array_equal(g["perm_best"][j], r.perm_best[j])
+                    and g["counters"][j][1] == r.counters[j][1])
+            if not same:
+                n_diff += 1
+                assert r.counters[j][2] > 0, f"instance {k} replica {j} differs without a tie"
+    return n_diff
+
+
+@pytest.mark.parametrize("sweep", ["auto", "plain"])
+def test_batch_matches_oracle(sweep):
+    from paper_2605_24408_amd import pdit as P
+    batch = small_batch()
+    say(f"batch vs oracle, sweep={sweep}")
+    refs = oracle_batch(batch, 5)
+    dbatch = to_dev(batch)
+    with P.Pdit(sweep=sweep) as ctx:
+        ctx.run_sweeps_batch(dbatch, 5)
+        torch.cuda.synchronize()
+        got = gpu_state(ctx, dbatch)
+    assert check(got, refs) <= 1
+    assert sum(int(r.counters[:, 1].sum()) for r in refs) > 100
+
+
+def test_batch_graph_replays_match_resumed_oracle():
+    """Three calls with the same shapes: the first captures the graph, the
+    next two replay it (seed and sweep offset come from device memory).  Host
+    work and synchronisations run between the replays; every call is checked
+    against the oracle resumed from the previous state."""
+    from paper_2605_24408_amd import pdit as P
+    batch = small_batch(T=12, R=2)
+    dbatch = to_dev(batch)
+    prev = None
+    with P.Pdit() as ctx:
+        for call in range(3):
+            say(f"graph call {call}")
+            ctx.run_sweeps_batch(dbatch, 9)
+            torch.cuda.synchronize()
+            got = gpu_state(ctx, dbatch)
+            refs = oracle_batch(batch, 9, sweep_offset=12 * call, prev=prev)
+            assert check(got, refs) == 0
+            prev = refs
+            _ = torch.randn(1000, device=DEV).sum().item()  # unrelated eager work
+        assert ctx.get_sweep_offset() == 36
+
+
+def test_batch_instance0_equals_single_run():
+    from paper_2605_24408_amd import pdit as P
+    batch = small_batch(T=20)
+    dbatch = to_dev(batch)
+    with P.Pdit() as ctx:
+        ctx.run_sweeps_batch(dbatch, 3)
+        torch.cuda.synchronize()
+        got = gpu_state(ctx, dbatch)[0]
+    D, F, perms, beta = batch[0]
+    with P.Pdit() as ctx:
+        perm = dev(perms, torch.int32)
+        ctx.run_sweeps(dev(D, torch.int32), dev(F, torch.int32), perm, dev(beta, torch.float32), 3)
+        E = ctx.energy().cpu().numpy()
+        torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy(), got["perm"])
+    assert np.array_equal(E, got["E"])
+
+
+def test_autotune_then_run():
+    from paper_2605_24408_amd import pdit as P
+    batch = small_batch(T=10, R=2)
+    dbatch = to_dev(batch)
+    before = [p.clone() for _, _, p, _ in dbatch]
+    with P.Pdit() as ctx:
+        t = ctx.autotune(dbatch, 10, 4)
+        assert t["blocks_per_cu"] >= 1 and t["seq_threshold"] >= 1 and t["best_ms"] > 0
+        for b, (_, _, p, _) in zip(before, dbatch):
+            assert torch.equal(b, p)  # the trials ran on private copies
+        ctx.run_sweeps_batch(dbatch, 4)
+        torch.cuda.synchronize()
+        got = gpu_state(ctx, dbatch)
+    assert check(got, oracle_batch(batch, 4)) == 0
+
+
+def test_uneven_workload_full_size_sampled():
+    """The uneven workload at full size (256 instances, N in [20, 150], 64
+    replicas each, 2000 sweeps) in one batched call; sampled replicas rerun on
+    the oracle, properties checked on many more."""
+    from paper_2605_24408_amd import pdit as P
+    insts = W.config_uneven()
+    dbatch = [(dev(i.D, torch.int32), dev(i.F, torch.int32), dev(i.perms, torch.int32),
+               dev(i.beta, torch.float32)) for i in insts]
+    say("uneven workload on the GPU")
+    with P.Pdit() as ctx:
+        ctx.run_sweeps_batch(dbatch, W.PHILOX_SEED)
+        torch.cuda.synchronize()
+        got = gpu_state(ctx, dbatch)
+    Ns = [i.N for i in insts]
+    sample = [int(np.argmax(Ns)), int(np.argmin(Ns)), 1, 2, 3]
+    say("uneven workload: sampled oracle replicas")
+
+    def ref(k):
+        i = insts[k]
+        return oracle.run(i.D, i.F, i.perms[5:6], i.beta, W.PHILOX_SEED, rep_ids=[5], inst_id=k)
+
+    with ThreadPoolExecutor(5) as ex:
+        refs = list(ex.map(ref, sample))
+    for k, r in zip(sample, refs):
+        same = (np.array_equal(got[k]["perm"][5], r.perm[0]) and got[k]["E"][5] == r.E[0]
+                and got[k]["E_best"][5] == r.E_best[0])
+        assert same or r.counters[0][2] > 0, (k, insts[k].N)
+    for k in range(0, 256, 17):
+        i = insts[k]
+        for j in (0, 63):
+            assert sorted(got[k]["perm"][j]) == list(range(i.N))
+            assert got[k]["E"][j] == oracle.energy(i.D, i.F, got[k]["perm"][j])
+            assert got[k]["E_best"][j] == oracle.energy(i.D, i.F, got[k]["perm_best"][j])
+            assert got[k]["counters"][j][0] == i.N * 2000

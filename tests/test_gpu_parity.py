@@ -198,7 +198,8 @@ def test_n12_workload_full_trajectory(P, sweep):
 
 
 @pytest.mark.parametrize("N,R,T,hot", [(2, 8, 50, True), (7, 16, 60, True), (33, 8, 40, True),
-                                       (64, 8, 30, False), (64, 8, 25, True), (16, 70, 20, True)])
+                                       (64, 8, 30, False), (64, 8, 25, True), (16, 70, 20, True),
+                                       (65, 4, 12, True), (100, 3, 10, False), (128, 3, 8, True)])
 @pytest.mark.parametrize("sweep", ["plain", "fast"])
 def test_random_instances_trajectory(P, N, R, T, hot, sweep):
     """Ragged sizes, several workgroups, hot and cold schedules, nonzero
@@ -347,10 +348,10 @@ def test_error_paths(P):
         # inputs untouched by refused calls
         assert np.array_equal(pd.cpu().numpy(), perms)
     with P.Pdit(sweep="fast") as ctx:
-        D2, F2 = W.random_instance(rng, 80, 0, 9)
+        D2, F2 = W.random_instance(rng, 130, 0, 9)
         with pytest.raises(P.PditError) as e:
             ctx.run_sweeps(dev(D2, torch.int32), dev(F2, torch.int32),
-                           dev(W.random_perms(rng, 1, 80), torch.int32), bd, 1)
+                           dev(W.random_perms(rng, 1, 130), torch.int32), bd, 1)
         assert e.value.status == "PDIT_EOVERFLOW"
     with P.Pdit(recompute="i8") as ctx:
         D3, F3 = W.random_instance(rng, 12, 0, 200)
