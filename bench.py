@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-replicas", type=int, default=32)
+    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512"],
+                    help="n64 is the benchmark configuration; the others report the same "
+                         "fast-vs-plain comparison for the other workload shapes")
+    ap.add_argument("--sweeps", type=int, default=0,
+                    help="run only the first SWEEPS sweeps of the schedule (0 = all)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates the "
                          "profiler's byte counters against a kernel of known traffic)")
@@ -58,6 +63,60 @@ def src_hash(path: str) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+def other_workload(args):
+    """Fast (auto) vs plain path on one of the other workload shapes; one
+    JSON line, not the benchmark figure."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit
+    from paper_2605_24408_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    if args.workload == "uneven":
+        insts = W.config_uneven()
+    else:
+        insts = [{"n12": W.config_n12, "n256": W.config_n256, "n512": W.config_n512}[args.workload]()]
+    if args.sweeps:
+        for i in insts:
+            i.beta = i.beta[: args.sweeps]
+    dbatch = [(torch.from_numpy(i.D).to(dev), torch.from_numpy(i.F).to(dev),
+               torch.from_numpy(i.perms).to(dev), torch.from_numpy(i.beta).to(dev)) for i in insts]
+    perms0 = [p.clone() for _, _, p, _ in dbatch]
+    updates = sum(i.R * i.N * i.T for i in insts)
+    out = {"workload": args.workload, "instances": len(insts),
+           "replicas": sum(i.R for i in insts), "sweeps": insts[0].T, "updates": updates}
+    results = {}
+    for path in ("fast", "plain"):
+        ctx = pdit.Pdit(sweep="auto" if path == "fast" else "plain",
+                        recompute="auto" if path == "fast" else "plain")
+        times = []
+        for rep in range(2 if path == "fast" else 1):
+            for (_, _, p, _), p0 in zip(dbatch, perms0):
+                p.copy_(p0)
+            ctx.set_sweep_offset(0)
+            ctx.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if len(dbatch) > 1:
+                ctx.run_sweeps_batch(dbatch, W.PHILOX_SEED)
+            else:
+                D, F, p, b = dbatch[0]
+                ctx.run_sweeps(D, F, p, b, W.PHILOX_SEED)
+            Eb, _ = ctx.best()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        cnt = ctx.counters()
+        results[path] = (min(times), Eb.cpu().numpy(), cnt)
+        out[path] = {"updates_per_s": updates / min(times), "seconds": min(times),
+                     "kernel_ms": ctx.last_timing()[1],
+                     "acceptance": cnt["accepted"] / max(cnt["updates"], 1), "ties": cnt["ties"]}
+        ctx.close()
+    out["speedup"] = results["plain"][0] / results["fast"][0]
+    out["identical_best"] = bool(np.array_equal(results["fast"][1], results["plain"][1]))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -65,6 +124,9 @@ def main():
               "workload are independent chains and the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload != "n64":
+        other_workload(args)
+        return
 
     import numpy as np
     import torch

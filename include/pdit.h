@@ -246,6 +246,12 @@ int pdit_debug_choice(pdit_t *ctx, int32_t N, int32_t M, const int64_t *delta, c
  * the H recompute, sweep_ms the sweep kernel.  Either pointer may be NULL. */
 int pdit_last_timing(pdit_t *ctx, double *recompute_ms, double *sweep_ms);
 
+/* What the last single-instance run used: *sweep is PDIT_SWEEP_PLAIN or
+ * PDIT_SWEEP_FAST, *size_class the on-chip kernel's size class (16, 32, 64,
+ * 128, 160 or 256; 0 for the plain kernel), *recompute the PDIT_RECOMPUTE_*
+ * mode of the H recompute.  Any pointer may be NULL. */
+int pdit_last_plan(pdit_t *ctx, int *sweep, int *size_class, int *recompute);
+
 /* Philox4x32-10 word 0 >> 8 for M counters (device uint32 M x 4) under seed,
  * written to device uint32 M. */
 int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t seed,

@@ -240,19 +240,17 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (rc) return rc;
     const int64_t bound = pdit::h_bound(st);
     const bool h64 = bound > INT32_MAX;
-    // the fast kernel keeps H and dE in int32 (|dE| < 2^30), D (scaled by 4)
-    // and F[p,p] in int16, and multiplies in 24 bits
-    const bool fast_ok = pdit::sweep_fast_supports(N) && !h64 &&
-                         2 * pdit::delta_bound(st) < (int64_t)INT32_MAX &&
-                         st.max_abs_d <= 8191 && st.max_abs_f <= 32767;
+    // the on-chip kernel's size class, 0 if the data do not fit its exact arithmetic
+    const int fclass = pdit::fast_class(N, st);
     bool use_fast = false;
     if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
-        if (!fast_ok)
+        if (!fclass)
             return fail(ctx, PDIT_EOVERFLOW,
-                        "the fast sweep kernel needs N <= 128, |dE| < 2^30, |D| <= 8191 and |F| <= 32767");
+                        "the fast sweep kernel needs N <= 256, |dE| < 2^30 and, by size, "
+                        "|D| <= 8191 and |F| <= 32767 (N <= 128) or |2H| <= 32767 (N > 160)");
         use_fast = true;
     } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
-        use_fast = fast_ok;
+        use_fast = fclass != 0;
     }
     int mode = 0;
     rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
@@ -297,7 +295,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
     if (n_sweeps > 0) {
         if (use_fast)
-            PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, a));
+            PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
         else
             PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
     } else {
@@ -309,6 +307,9 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->rec_trace = nullptr;
     ctx->sweep_offset += (uint64_t)n_sweeps;
     ctx->last_updates = (int64_t)R * N * n_sweeps;
+    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
+    ctx->last_class = use_fast ? fclass : 0;
+    ctx->last_mode = mode;
     S.best_valid = true;
     return PDIT_OK;
 }
@@ -347,6 +348,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
 
     struct Plan {
         int mode;
+        int fclass;
         bool h64, fast, zd;
         int64_t hoff;  // byte offset of replica 0's H
     };
@@ -366,12 +368,10 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         const int64_t bound = pdit::h_bound(q);
         Plan &pl = plan[k];
         pl.h64 = bound > INT32_MAX;
-        const bool fast_ok = pdit::sweep_fast_supports(inst[k].N) && !pl.h64 &&
-                             2 * pdit::delta_bound(q) < (int64_t)INT32_MAX && q.max_abs_d <= 8191 &&
-                             q.max_abs_f <= 32767;
-        if (ctx->opts.sweep == PDIT_SWEEP_FAST && !fast_ok)
+        pl.fclass = pdit::fast_class(inst[k].N, q);
+        if (ctx->opts.sweep == PDIT_SWEEP_FAST && !pl.fclass)
             return fail(ctx, PDIT_EOVERFLOW, "an instance does not fit the fast sweep kernel");
-        pl.fast = ctx->opts.sweep != PDIT_SWEEP_PLAIN && fast_ok;
+        pl.fast = ctx->opts.sweep != PDIT_SWEEP_PLAIN && pl.fclass != 0;
         pl.zd = q.diag_nz_d == 0 && q.diag_nz_f == 0;
         rc = pick_recompute(ctx, q, bound, ctx->opts.recompute, &pl.mode);
         if (rc) return rc;
@@ -444,7 +444,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                          [&](int x, int y) { return inst[x].N > inst[y].N; });
         for (int k : order) {
             const Plan &pl = plan[k];
-            const int nmax = pl.fast ? pdit::fast_class(inst[k].N) : 0;
+            const int nmax = pl.fast ? pl.fclass : 0;
             Group *g = nullptr;
             for (auto &gg : groups)
                 if (gg.fast == pl.fast && gg.nmax == nmax && (pl.fast ? gg.zd == pl.zd : gg.h64 == pl.h64))
@@ -578,11 +578,10 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
     }
     pdit_opts o = ctx->opts;
     if (rc == PDIT_OK) rc = pdit_create(&tmp, &o);
-    int max_bpc = 1;
-    for (int k = 0; k < n_inst; ++k)
-        max_bpc = std::max(max_bpc, pdit::sweep_fast_supports(inst[k].N)
-                                        ? pdit::fast_blocks_per_cu(pdit::fast_class(inst[k].N))
-                                        : pdit::plain_blocks_per_cu(false));
+    // resident workgroups per CU to try: up to the most any kernel of the batch allows
+    int max_bpc = pdit::plain_blocks_per_cu(false);
+    for (int nmax : {16, 32, 64, 128, 160, 256}) max_bpc = std::max(max_bpc, pdit::fast_blocks_per_cu(nmax));
+    max_bpc = std::min(max_bpc, 4);
     pdit_tuning best{0, 0, 1e300};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == PDIT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -782,6 +781,15 @@ int pdit_last_timing(pdit_t *ctx, double *recompute_ms, double *sweep_ms) {
     PDIT_HIP(ctx, hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
     if (recompute_ms) *recompute_ms = a;
     if (sweep_ms) *sweep_ms = b;
+    return PDIT_OK;
+}
+
+int pdit_last_plan(pdit_t *ctx, int *sweep, int *size_class, int *recompute) {
+    if (!ctx) return PDIT_EINVAL;
+    if (!ctx->last_sweep) return fail(ctx, PDIT_ESTATE, "no single-instance run yet");
+    if (sweep) *sweep = ctx->last_sweep;
+    if (size_class) *size_class = ctx->last_class;
+    if (recompute) *recompute = ctx->last_mode;
     return PDIT_OK;
 }
 

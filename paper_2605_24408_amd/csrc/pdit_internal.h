@@ -81,6 +81,7 @@ struct pdit_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<char> graph_sig;                      // what the captured graph was built for
     int num_cus = 0;
+    int last_sweep = 0, last_class = 0, last_mode = 0;  // plan of the last single-instance run
 };
 
 namespace pdit {
@@ -120,13 +121,14 @@ struct SweepArgs {
     bool zero_diag;          // D and F have zero diagonals
 };
 
-constexpr int kFastNMax = 128;            // largest N of the on-chip kernel
+constexpr int kFastNMax = 256;            // largest N of the on-chip kernel
 constexpr int kDefaultSeqThreshold = 3;   // swaps per sweep above which the next sweep is sequential
 
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
-hipError_t launch_sweep_fast(hipStream_t s, const SweepArgs &a);
-bool sweep_fast_supports(int N);
-int fast_class(int N);                    // 16, 32, 64 or 128: the kernel size that runs N
+// size class of the on-chip kernel that runs an instance (16, 32, 64, 128,
+// 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic
+int fast_class(int N, const InstanceStats &st);
+hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a);
 hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zero_diag, const BatchArgs &b,
                                         int grid);
 int fast_blocks_per_cu(int nmax);

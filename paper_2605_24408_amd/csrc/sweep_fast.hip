@@ -1,14 +1,19 @@
 // sweep_fast.hip -- the sweep kernel with H on chip.
 //
-// One workgroup owns one replica.  Its H = D F[p,p] (int32, stored doubled)
-// and its permuted flows Fp = F[p,p] (int16), with D (int16), live in LDS for
-// the whole run; N <= 128.  The method's order of updates (locations 0..N-1
+// One workgroup owns one replica and keeps its H = D F[p,p] (stored doubled)
+// in LDS for the whole run.  The method's order of updates (locations 0..N-1
 // per sweep, each a Gibbs choice among N candidates; Results,
 // "Implementation", Eq. 3 and Eq. 5) is kept exactly.  The workgroup has
 // NMAX/16 waves; wave w owns the 16 locations 16w..16w+15 and the lanes of a
-// quad split the candidates of one location four ways, so a replica keeps
-// NMAX/16 waves busy; four replicas of N = 64 share a CU with four waves per
-// SIMD, one replica of N = 128 fills a CU's LDS with two waves per SIMD.
+// quad split the candidates of one location four ways.
+//
+// Size classes:
+//   NMAX = 16, 32, 64, 128: 2H int32, D and the permuted flows Fp = F[p,p]
+//     (int16) in LDS too; four replicas of N = 64 share a CU with four waves
+//     per SIMD, one replica of N = 128 fills a CU's LDS;
+//   NMAX = 160 (2H int32) and 256 (2H int16, for instances whose exact bound
+//     allows it): only H and per-location arrays in LDS, D and F read from
+//     device memory (shared by all replicas, so they stay in L2).
 //
 // Two schedules give the same result:
 //
@@ -24,9 +29,9 @@
 //    reductions, computed redundantly by every wave of the replica.  Used for
 //    a sweep when the previous one accepted more than `seq_threshold` swaps.
 //
-// The Gibbs weights are exact integers (q = rint(w 2^25)); for N <= 64 their
-// sums fit 32 bits, so both schedules, whatever their summation order, select
-// the same candidate.  A candidate whose distance d to the row minimum
+// The Gibbs weights are exact integers (q = rint(w 2^25)) summed exactly (in
+// 32 bits for N <= 64, in 64 bits beyond), so both schedules, whatever their
+// summation order, select the same candidate.  A candidate whose distance d to the row minimum
 // satisfies d >= dthr has q = 0 and skips the exponential; d = 0 gives 2^25.
 //
 // The energy change of swapping the facilities of locations l and s is
@@ -36,6 +41,8 @@
 #include "device_common.h"
 #include "pdit_internal.h"
 #include "sweep_common.h"
+
+#include <type_traits>
 
 namespace pdit {
 namespace {
@@ -59,14 +66,21 @@ template <int CTRL>
 __device__ __forceinline__ uint32_t quadu(uint32_t v) {
     return (uint32_t)quad<CTRL>((int32_t)v);
 }
+template <int CTRL>
+__device__ __forceinline__ uint64_t quadu(uint64_t v) {
+    const uint32_t lo = quadu<CTRL>((uint32_t)v), hi = quadu<CTRL>((uint32_t)(v >> 32));
+    return (uint64_t)hi << 32 | lo;
+}
 
-template <int NMAX>
+
+template <int NMAX, bool LARGE, typename HT>
 struct FastSmem {
-    static constexpr int P = NMAX + 1;   // H row pitch (int32): column reads are conflict-free
+    // padded H rows: column reads are bank-conflict-free
+    static constexpr int P = sizeof(HT) == 4 ? NMAX + 1 : NMAX + 2;
     static constexpr int PF = NMAX + 2;  // Fp row pitch (int16)
-    int32_t Hs[NMAX * P];                // 2 H
-    int16_t Ds[NMAX * NMAX];             // D, times 4 with zero diagonals
-    int16_t Fp[NMAX * PF];               // F[p,p]
+    HT Hs[NMAX * P];                     // 2 H
+    int16_t Ds[LARGE ? 2 : NMAX * NMAX];  // D, times 4 with zero diagonals
+    int16_t Fp[LARGE ? 2 : NMAX * PF];    // F[p,p]
     int32_t hdv[NMAX];                   // 2 H[l][l]
     int32_t ddv[NMAX];                   // D[l][l]
     int32_t fdv[NMAX];                   // Fp[l][l]
@@ -76,15 +90,21 @@ struct FastSmem {
 };
 
 // Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).
-template <int NMAX, bool ZD, bool EXACT>
-__device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX> &sm) {
-    constexpr int WPR = NMAX / 16;       // waves per replica
-    constexpr int K = NMAX / 4;          // candidates per lane in a speculative pass
+template <int NMAX, bool ZD, bool EXACT, bool LARGE, typename HT>
+__device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX, LARGE, HT> &sm) {
+    constexpr int WPR = NMAX / 16;         // waves per replica
+    constexpr int K = NMAX / 4;            // candidates per lane in a speculative pass
     constexpr int CPL = (NMAX + 63) / 64;  // locations per lane in row-vector work
-    constexpr int P = FastSmem<NMAX>::P;
-    constexpr int PF = FastSmem<NMAX>::PF;
-    constexpr int kDScale = ZD ? 4 : 1;
-    int32_t *Hs = sm.Hs;
+    constexpr int P = FastSmem<NMAX, LARGE, HT>::P;
+    constexpr int PF = FastSmem<NMAX, LARGE, HT>::PF;
+    // LDS classes keep 4 D with zero diagonals; large classes read D as is and
+    // scale the product instead
+    constexpr int kDScale = (ZD && !LARGE) ? 4 : 1;
+    constexpr int kProdScale = (ZD && LARGE) ? 4 : 1;
+    // CDF type: a lane's partial sum of at most 64 weights of 2^25 fits 32
+    // bits; a row's total fits 32 bits only for N <= 64
+    using CT = typename std::conditional<(NMAX <= 64), uint32_t, uint64_t>::type;
+    HT *Hs = sm.Hs;
     int16_t *Ds = sm.Ds;
     int16_t *Fp = sm.Fp;
     int32_t *hdv = sm.hdv;
@@ -96,30 +116,48 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
+    const int32_t *__restrict__ Dg = a.D;
+    const int32_t *__restrict__ Fg = a.F;
 
-    // ---- stage D, p, 2H and F[p,p] (zero outside N) ----
-    for (int e = tid; e < NMAX * NMAX; e += 64 * WPR) {
-        const int i = e / NMAX, j = e % NMAX;
-        Ds[e] = (int16_t)((i < N && j < N) ? kDScale * a.D[(int64_t)i * N + j] : 0);
-    }
+    // D[i][j] and Fp[i][j] = F[p(i)][p(j)]; in the large classes from device
+    // memory with indices clamped into the N x N matrices (padding rows and
+    // candidates beyond N are computed and discarded)
+    auto d_at = [&](int i, int j) -> int32_t {
+        if (LARGE) return Dg[(int64_t)min(i, N - 1) * N + min(j, N - 1)];
+        return Ds[i * NMAX + j];
+    };
+    auto fp_at = [&](int i, int j) -> int32_t {
+        if (LARGE) return Fg[(int64_t)pv[i] * N + pv[j]];
+        return Fp[i * PF + j];
+    };
+
+    // ---- stage p, 2H (and D, F[p,p] in the LDS classes); zero outside N ----
     for (int e = tid; e < NMAX; e += 64 * WPR) pv[e] = e < N ? a.perm[e] : 0;
+    if (!LARGE) {
+        for (int e = tid; e < NMAX * NMAX; e += 64 * WPR) {
+            const int i = e / NMAX, j = e % NMAX;
+            Ds[e] = (int16_t)((i < N && j < N) ? kDScale * Dg[(int64_t)i * N + j] : 0);
+        }
+    }
     {
         const int32_t *Hg = (const int32_t *)a.H;
         for (int e = tid; e < NMAX * P; e += 64 * WPR) {
             const int i = e / P, k = e % P;
-            Hs[e] = (i < N && k < N) ? 2 * Hg[(int64_t)i * N + k] : 0;
+            Hs[e] = (HT)((i < N && k < N) ? 2 * Hg[(int64_t)i * N + k] : 0);
         }
     }
     __syncthreads();
-    for (int e = tid; e < NMAX * PF; e += 64 * WPR) {
-        const int i = e / PF, k = e % PF;
-        Fp[e] = (int16_t)((i < N && k < N) ? a.F[(int64_t)pv[i] * N + pv[k]] : 0);
+    if (!LARGE) {
+        for (int e = tid; e < NMAX * PF; e += 64 * WPR) {
+            const int i = e / PF, k = e % PF;
+            Fp[e] = (int16_t)((i < N && k < N) ? Fg[(int64_t)pv[i] * N + pv[k]] : 0);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int e = tid; e < NMAX; e += 64 * WPR) {
         hdv[e] = Hs[e * P + e];
-        ddv[e] = ZD ? 0 : Ds[e * NMAX + e];
-        fdv[e] = ZD ? 0 : Fp[e * PF + e];
+        ddv[e] = (ZD || e >= N) ? 0 : d_at(e, e);
+        fdv[e] = (ZD || e >= N) ? 0 : fp_at(e, e);
     }
     __syncthreads();
 
@@ -133,11 +171,11 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
     const int rl = lane >> 2, cq = lane & 3;
     const int rr = 16 * wv + rl;  // location of this lane's row
 
-    // energy change of the (uniform) pair r, s, from LDS
+    // energy change of the (uniform) pair r, s
     auto pair_delta = [&](int r, int s) -> int32_t {
-        const int32_t h2 = Hs[r * P + s] + Hs[s * P + r] - hdv[r] - hdv[s];
-        const int32_t dv = Ds[s * NMAX + r], fv = Fp[s * PF + r];
-        if (ZD) return h2 + dv * fv;
+        const int32_t h2 = (int32_t)Hs[r * P + s] + (int32_t)Hs[s * P + r] - hdv[r] - hdv[s];
+        const int32_t dv = d_at(s, r), fv = fp_at(s, r);
+        if (ZD) return h2 + kProdScale * dv * fv;
         return h2 + (ddv[r] + ddv[s] - 2 * dv) * (fdv[r] + fdv[s] - 2 * fv);
     };
 
@@ -153,21 +191,21 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
         for (int c = 0; c < CPL; ++c) {
             const int k = (lane + 64 * c) < NMAX ? lane + 64 * c : 0;
             src[c] = k == r ? s : k == s ? r : k;
-            v[c] = (int32_t)Fp[r * PF + src[c]] - (int32_t)Fp[s * PF + src[c]];
+            v[c] = fp_at(r, src[c]) - fp_at(s, src[c]);
         }
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
 #pragma unroll 4
         for (int ii = 0; ii < 16; ++ii) {
             const int i = 16 * wv + ii;
             if (EXACT || i < N) {
-                const int32_t du = (int32_t)Ds[s * NMAX + i] - (int32_t)Ds[r * NMAX + i];
-                const int32_t u2 = ZD ? du / 2 : 2 * du;  // 2 u_i
+                const int32_t du = d_at(s, i) - d_at(r, i);
+                const int32_t u2 = kDScale == 4 ? du / 2 : 2 * du;  // 2 u_i
                 int32_t x[CPL];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) x[c] = Hs[i * P + src[c]];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    if (lane + 64 * c < N) Hs[i * P + lane + 64 * c] = x[c] + u2 * v[c];
+                    if (lane + 64 * c < N) Hs[i * P + lane + 64 * c] = (HT)(x[c] + u2 * v[c]);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -176,24 +214,26 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
             hdv[i] = Hs[i * P + i];
         }
         if (wv == 0) {
-            // Fp <- Fp with rows r, s and then columns r, s exchanged
+            if (!LARGE) {
+                // Fp <- Fp with rows r, s and then columns r, s exchanged
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int k = lane + 64 * c;
-                if (k < N) {
-                    const int16_t fr = Fp[r * PF + k], fs = Fp[s * PF + k];
-                    Fp[r * PF + k] = fs;
-                    Fp[s * PF + k] = fr;
+                for (int c = 0; c < CPL; ++c) {
+                    const int k = lane + 64 * c;
+                    if (k < N) {
+                        const int16_t fr = Fp[r * PF + k], fs = Fp[s * PF + k];
+                        Fp[r * PF + k] = fs;
+                        Fp[s * PF + k] = fr;
+                    }
                 }
-            }
-            __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int k = lane + 64 * c;
-                if (k < N) {
-                    const int16_t cr = Fp[k * PF + r], cs = Fp[k * PF + s];
-                    Fp[k * PF + r] = cs;
-                    Fp[k * PF + s] = cr;
+                for (int c = 0; c < CPL; ++c) {
+                    const int k = lane + 64 * c;
+                    if (k < N) {
+                        const int16_t cr = Fp[k * PF + r], cs = Fp[k * PF + s];
+                        Fp[k * PF + r] = cs;
+                        Fp[k * PF + s] = cr;
+                    }
                 }
             }
             if (lane == 0) {
@@ -236,49 +276,70 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
                 if (__ballot(rowv)) {
                     const int32_t nhdr = -hdv[rr];
                     const int32_t ddr = ddv[rr], fdr = fdv[rr];
-                    int32_t dl[K];
-                    int32_t mn = kBig;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
+                    const int32_t prr = pv[rr];
+                    const int64_t rrc = min(rr, N - 1);
+                    // energy change of candidate cq*K + j of this lane's row
+                    auto cand = [&](int j) -> int32_t {
                         const int s = cq * K + j;
-                        const int32_t x = Hs[rr * P + s] + Hs[s * P + rr] + nhdr - hdv[s];
-                        const int32_t dv = Ds[s * NMAX + rr];
-                        const int32_t fv = Fp[s * PF + rr];
+                        const int32_t x = (int32_t)Hs[rr * P + s] + (int32_t)Hs[s * P + rr] + nhdr - hdv[s];
+                        int32_t dv, fv;
+                        if (LARGE) {
+                            dv = Dg[(int64_t)min(s, N - 1) * N + rrc];
+                            fv = Fg[(int64_t)pv[s] * N + prr];
+                        } else {
+                            dv = Ds[s * NMAX + rr];
+                            fv = Fp[s * PF + rr];
+                        }
                         int32_t v;
                         if (ZD) {
-                            v = __mul24(dv, fv) + x;
+                            v = kProdScale * __mul24(dv, fv) + x;
                         } else {
                             v = x + __mul24(ddr + ddv[s] - 2 * dv, fdr + fdv[s] - 2 * fv);
                         }
                         if (!EXACT && s >= N) v = kBig;
-                        dl[j] = v;
-                        mn = min(mn, v);
-                    }
-                    mn = min(mn, quad<kQuadXor1>(mn));
-                    mn = min(mn, quad<kQuadXor2>(mn));
-                    // weights: d = 0 -> 2^25; 0 < d < dthr -> expf; d >= dthr -> 0
-                    uint32_t ql[K];
-                    uint32_t Zc = 0;
-                    int am = -1;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const int32_t d = dl[j] - mn;
+                        return v;
+                    };
+                    // weight of a candidate at distance d from the row minimum:
+                    // d = 0 -> 2^25; 0 < d < dthr -> expf; d >= dthr -> 0
+                    auto weight = [&](int j, int32_t d) -> uint32_t {
                         const bool zero = d == 0;
                         uint32_t q = zero ? kOne : 0u;
-                        am = zero ? cq * K + j : am;
                         const bool need = d < dthr && !zero;
                         if (__ballot(need)) {
                             if (need) q = gibbs_weight(beta, (float)d);
                         }
                         if (!EXACT && cq * K + j >= N) q = 0;
-                        ql[j] = q;
+                        return q;
+                    };
+                    // the small classes keep the row in registers; the large
+                    // ones recompute it in each pass instead
+                    constexpr int KR = LARGE ? 1 : K;
+                    int32_t dl[KR];
+                    uint32_t ql[KR];
+                    int32_t mn = kBig;
+#pragma unroll(LARGE ? 4 : K)
+                    for (int j = 0; j < K; ++j) {
+                        const int32_t v = cand(j);
+                        if (!LARGE) dl[j % KR] = v;
+                        mn = min(mn, v);
+                    }
+                    mn = min(mn, quad<kQuadXor1>(mn));
+                    mn = min(mn, quad<kQuadXor2>(mn));
+                    uint32_t Zc = 0;
+                    int am = -1;
+#pragma unroll(LARGE ? 4 : K)
+                    for (int j = 0; j < K; ++j) {
+                        const int32_t d = (LARGE ? cand(j) : dl[j % KR]) - mn;
+                        const uint32_t q = weight(j, d);
+                        am = d == 0 ? cq * K + j : am;
+                        if (!LARGE) ql[j % KR] = q;
                         Zc += q;
                     }
                     // quarters before this one, and the row total
-                    const uint32_t p1 = quadu<kQuadPrev1>(Zc), p2 = quadu<kQuadPrev2>(Zc),
-                                   p3 = quadu<kQuadPrev3>(Zc);
-                    const uint32_t off = (cq >= 1 ? p1 : 0u) + (cq >= 2 ? p2 : 0u) + (cq >= 3 ? p3 : 0u);
-                    const uint32_t Z = quadu<kQuadLast>(off + Zc);
+                    const CT p1 = quadu<kQuadPrev1>(Zc), p2 = quadu<kQuadPrev2>(Zc),
+                             p3 = quadu<kQuadPrev3>(Zc);
+                    const CT off = (cq >= 1 ? p1 : 0) + (cq >= 2 ? p2 : 0) + (cq >= 3 ? p3 : 0);
+                    const CT Z = quadu<kQuadLast>((CT)(off + Zc));
                     am = max(am, quad<kQuadXor1>(am));
                     am = max(am, quad<kQuadXor2>(am));
                     sel = am;
@@ -290,16 +351,16 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
                     if (__ballot(rowv && Z != kOne)) {
                         const uint64_t target = (uint64_t)u24 * Z;
                         const uint64_t band = (uint64_t)Z << 4;
-                        const uint32_t thr = (uint32_t)(target >> 24);
-                        const uint32_t thr_lo = target >= band ? (uint32_t)((target - band) >> 24) : 0u;
-                        const uint32_t thr_hi = (uint32_t)min((target + band) >> 24, (uint64_t)(Z - 1));
-                        const uint32_t lo1 = thr_lo + 1;
-                        const uint32_t width = thr_hi >= lo1 ? thr_hi - thr_lo : 0u;
-                        uint32_t C = off;
+                        const CT thr = (CT)(target >> 24);
+                        const CT thr_lo = target >= band ? (CT)((target - band) >> 24) : 0;
+                        const CT thr_hi = (CT)min((target + band) >> 24, (uint64_t)(Z - 1));
+                        const CT lo1 = thr_lo + 1;
+                        const CT width = thr_hi >= lo1 ? thr_hi - thr_lo : 0;
+                        CT C = off;
                         int n_sel = 0, n_band = 0;
-#pragma unroll
+#pragma unroll(LARGE ? 4 : K)
                         for (int j = 0; j < K; ++j) {
-                            C += ql[j];
+                            C += LARGE ? weight(j, cand(j) - mn) : ql[j % KR];
                             n_sel += C <= thr;
                             n_band += (C - lo1) < width;
                         }
@@ -359,16 +420,23 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
                 int32_t v[CPL];
                 uint32_t q[CPL];
                 int32_t lmin = kBig;
+                const int32_t pr = pv[r];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const int ls = lane + 64 * c;
                     v[c] = kBig;
                     if (ls < N) {
-                        const int32_t x = Hs[r * P + ls] + Hs[ls * P + r] - hdv[r] - hdv[ls];
-                        const int32_t dv = Ds[r * NMAX + ls];
-                        const int32_t fv = Fp[r * PF + ls];
+                        const int32_t x = (int32_t)Hs[r * P + ls] + (int32_t)Hs[ls * P + r] - hdv[r] - hdv[ls];
+                        int32_t dv, fv;
+                        if (LARGE) {
+                            dv = Dg[(int64_t)r * N + ls];
+                            fv = Fg[(int64_t)pr * N + pv[ls]];
+                        } else {
+                            dv = Ds[r * NMAX + ls];
+                            fv = Fp[r * PF + ls];
+                        }
                         if (ZD) {
-                            v[c] = __mul24(dv, fv) + x;
+                            v[c] = kProdScale * __mul24(dv, fv) + x;
                         } else {
                             v[c] = x + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
                         }
@@ -376,8 +444,8 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
                     lmin = min(lmin, v[c]);
                 }
                 const int32_t mn = wave_min_i32(lmin);
-                uint32_t C[CPL];
-                uint32_t base = 0;
+                CT C[CPL];
+                CT base = 0;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const bool valid = lane + 64 * c < N;
@@ -385,13 +453,16 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
                     q[c] = d == 0 ? kOne : 0u;
                     if (d > 0 && d < dthr) q[c] = gibbs_weight(beta, (float)d);
                     if (!valid) q[c] = 0;
-                    C[c] = base + wave_scan_u32(q[c]);
-                    base = (uint32_t)__builtin_amdgcn_readlane((int32_t)C[c], 63);
+                    // one chunk of 64 weights sums to at most 2^31
+                    C[c] = base + (CT)wave_scan_u32(q[c]);
+                    base = (CT)readlane_u64((uint64_t)C[c], 63);
                 }
-                const uint32_t Z = base;
-                const uint32_t ur24 =
-                    (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l[CPL > 1 ? (r >> 6) : 0], r & 63);
-                const uint32_t thr = (uint32_t)(((uint64_t)ur24 * Z) >> 24);
+                const CT Z = base;
+                uint32_t ur24 = 0;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if ((r >> 6) == c) ur24 = (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l[c], r & 63);
+                const CT thr = (CT)(((uint64_t)ur24 * Z) >> 24);
                 int s = -1;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
@@ -399,12 +470,21 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
                     if (s < 0 && hit) s = 64 * c + __ffsll((unsigned long long)hit) - 1;
                 }
                 if (s < 0 || s >= N) s = r;  // unreachable: location N-1 holds C = Z > thr
-                const int sc = CPL > 1 ? (s >> 6) : 0, sl = s & 63;
-                const uint32_t csel = (uint32_t)__builtin_amdgcn_readlane((int32_t)C[sc], sl);
-                const uint32_t cprev = csel - (uint32_t)__builtin_amdgcn_readlane((int32_t)q[sc], sl);
-                if (wv == 0) n_tie += is_tie(cprev, csel, Z, ur24) ? 1 : 0;
+                const int sl = s & 63;
+                CT csel = 0;
+                uint32_t qsel = 0;
+                int32_t vsel = 0;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    if ((s >> 6) == c) {
+                        csel = (CT)readlane_u64((uint64_t)C[c], sl);
+                        qsel = (uint32_t)__builtin_amdgcn_readlane((int32_t)q[c], sl);
+                        vsel = __builtin_amdgcn_readlane(v[c], sl);
+                    }
+                }
+                if (wv == 0) n_tie += is_tie(csel - qsel, csel, Z, ur24) ? 1 : 0;
                 if (ch && lane == 0) ch[r] = s;
-                if (s != r) apply_swap(r, s, (int64_t)__builtin_amdgcn_readlane(v[sc], sl));
+                if (s != r) apply_swap(r, s, (int64_t)vsel);
             }
         }
         seq_mode = (n_acc - acc_before) > a.seq_threshold;
@@ -425,17 +505,25 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX>
     }
 }
 
-// four replicas of N <= 64 per CU need four waves per SIMD (at most 128
-// VGPRs); N <= 128 runs one replica of eight waves per CU
+// Waves per SIMD each class runs at (one replica's waves spread over the
+// CU's four SIMDs): four replicas of N <= 64 per CU, one replica otherwise.
 template <int NMAX>
-constexpr int fast_waves_per_eu() { return NMAX >= 128 ? 2 : 4; }
+constexpr int fast_waves_per_eu() {
+    return NMAX <= 64 ? 4 : NMAX == 128 ? 2 : NMAX == 160 ? 3 : 4;
+}
+
+// H element type of each class.
+template <int NMAX>
+using FastH = typename std::conditional<NMAX == 256, int16_t, int32_t>::type;
+template <int NMAX>
+constexpr bool fast_large() { return NMAX > 128; }
 
 // One replica per workgroup (single-instance runs).
 template <int NMAX, bool ZD, bool EXACT>
 __global__ void __launch_bounds__(64 * (NMAX / 16))
 __attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<NMAX>())))
 sweep_fast_kernel(SweepArgs a) {
-    __shared__ FastSmem<NMAX> sm;
+    __shared__ FastSmem<NMAX, fast_large<NMAX>(), FastH<NMAX>> sm;
     const int64_t rep = blockIdx.x;
     ReplicaJob j;
     j.N = a.N;
@@ -457,18 +545,18 @@ sweep_fast_kernel(SweepArgs a) {
     j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
     j.seq_threshold = a.seq_threshold;
     j.zero_diag = ZD;
-    fast_replica<NMAX, ZD, EXACT>(j, sm);
+    fast_replica<NMAX, ZD, EXACT, fast_large<NMAX>(), FastH<NMAX>>(j, sm);
 }
 
 // Persistent: each workgroup takes (instance, replica) items from a queue
-// until it is exhausted; items come largest N first.
-// Every workgroup reaches the exit: the queue only grows, so each one reads
-// an item index >= n_items after at most n_items increments.
+// until it is exhausted; items come largest N first.  Every workgroup
+// reaches the exit: the queue only grows, so each one reads an item index
+// >= n_items after at most n_items increments.
 template <int NMAX, bool ZD>
 __global__ void __launch_bounds__(64 * (NMAX / 16))
 __attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<NMAX>())))
 sweep_fast_persistent(BatchArgs b) {
-    __shared__ FastSmem<NMAX> sm;
+    __shared__ FastSmem<NMAX, fast_large<NMAX>(), FastH<NMAX>> sm;
     __shared__ int item_sh;
     for (;;) {
         if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
@@ -476,7 +564,8 @@ sweep_fast_persistent(BatchArgs b) {
         const int item = item_sh;
         __syncthreads();
         if (item >= b.n_items) break;
-        fast_replica<NMAX, ZD, false>(batch_job(b, item, sizeof(int32_t)), sm);
+        fast_replica<NMAX, ZD, false, fast_large<NMAX>(), FastH<NMAX>>(
+            batch_job(b, item, sizeof(int32_t)), sm);
         __syncthreads();
     }
 }
@@ -495,21 +584,6 @@ hipError_t launch_nmax(hipStream_t s, const SweepArgs &a) {
     return exact ? launch_fast<NMAX, false, true>(s, a) : launch_fast<NMAX, false, false>(s, a);
 }
 
-}  // namespace
-
-bool sweep_fast_supports(int N) { return N >= 2 && N <= kFastNMax; }
-
-int fast_class(int N) { return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 128; }
-
-hipError_t launch_sweep_fast(hipStream_t s, const SweepArgs &a0) {
-    SweepArgs a = a0;
-    if (a.seq_threshold < 0) a.seq_threshold = kDefaultSeqThreshold;
-    if (a.N <= 16) return launch_nmax<16>(s, a);
-    if (a.N <= 32) return launch_nmax<32>(s, a);
-    if (a.N <= 64) return launch_nmax<64>(s, a);
-    return launch_nmax<128>(s, a);
-}
-
 template <int NMAX>
 hipError_t launch_persistent_nmax(hipStream_t s, bool zd, const BatchArgs &b, int grid) {
     if (zd)
@@ -519,6 +593,47 @@ hipError_t launch_persistent_nmax(hipStream_t s, bool zd, const BatchArgs &b, in
     return hipGetLastError();
 }
 
+template <int NMAX>
+int persistent_blocks_per_cu() {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, sweep_fast_persistent<NMAX, true>, 64 * (NMAX / 16), 0);
+    (void)hipGetLastError();
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace
+
+int fast_class(int N, const InstanceStats &st) {
+    if (N < 2 || N > kFastNMax) return 0;
+    const int64_t bound = h_bound(st);
+    // H and dE in int32 with |dE| < 2^30, 24-bit products
+    if (bound > INT32_MAX || 2 * delta_bound(st) >= (int64_t)INT32_MAX) return 0;
+    if (st.max_abs_d >= (1 << 21) || st.max_abs_f >= (1 << 21)) return 0;
+    if (N <= 128) {
+        // D (times 4) and F[p,p] in int16
+        if (st.max_abs_d > 8191 || st.max_abs_f > 32767) return 0;
+        return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 128;
+    }
+    if (N <= 160) return 160;
+    // 2H in int16
+    return 2 * bound <= 32767 ? 256 : 0;
+}
+
+hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a0) {
+    SweepArgs a = a0;
+    if (a.seq_threshold < 0) a.seq_threshold = kDefaultSeqThreshold;
+    switch (nmax) {
+        case 16: return launch_nmax<16>(s, a);
+        case 32: return launch_nmax<32>(s, a);
+        case 64: return launch_nmax<64>(s, a);
+        case 128: return launch_nmax<128>(s, a);
+        case 160: return launch_nmax<160>(s, a);
+        case 256: return launch_nmax<256>(s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zd, const BatchArgs &b,
                                         int grid) {
     switch (nmax) {
@@ -526,22 +641,22 @@ hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zd, const 
         case 32: return launch_persistent_nmax<32>(s, zd, b, grid);
         case 64: return launch_persistent_nmax<64>(s, zd, b, grid);
         case 128: return launch_persistent_nmax<128>(s, zd, b, grid);
+        case 160: return launch_persistent_nmax<160>(s, zd, b, grid);
+        case 256: return launch_persistent_nmax<256>(s, zd, b, grid);
         default: return hipErrorInvalidValue;
     }
 }
 
 int fast_blocks_per_cu(int nmax) {
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
     switch (nmax) {
-        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<16, true>, 64, 0); break;
-        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<32, true>, 128, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<64, true>, 256, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fast_persistent<128, true>, 512, 0); break;
-        default: break;
+        case 16: return persistent_blocks_per_cu<16>();
+        case 32: return persistent_blocks_per_cu<32>();
+        case 64: return persistent_blocks_per_cu<64>();
+        case 128: return persistent_blocks_per_cu<128>();
+        case 160: return persistent_blocks_per_cu<160>();
+        case 256: return persistent_blocks_per_cu<256>();
+        default: return 1;
     }
-    (void)hipGetLastError();
-    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 }  // namespace pdit

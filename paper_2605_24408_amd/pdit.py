@@ -57,7 +57,7 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_replica_counters", "pdit_set_sweep_offset", "pdit_get_sweep_offset",
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
-           "pdit_last_timing", "pdit_autotune"]
+           "pdit_last_timing", "pdit_autotune", "pdit_last_plan"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
     L.pdit_debug_uniform24.argtypes = [vp, i32, vp, u64, vp]
     L.pdit_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.pdit_autotune.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64, C.POINTER(_Tuning)]
+    L.pdit_last_plan.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("pdit_default_opts", "pdit_last_error"):
@@ -249,6 +250,14 @@ class Pdit:
         a, b = C.c_double(), C.c_double()
         self._rc(self._L.pdit_last_timing(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def last_plan(self) -> dict:
+        """Kernel, on-chip size class and recompute mode of the last run."""
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._rc(self._L.pdit_last_plan(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        inv = {v: k for k, v in RECOMPUTE.items()}
+        return {"sweep": {1: "plain", 2: "fast"}[a.value], "size_class": b.value,
+                "recompute": inv[c.value]}
 
     def set_sweep_offset(self, offset: int):
         self._rc(self._L.pdit_set_sweep_offset(self._h, int(offset)))

@@ -219,8 +219,39 @@ def test_random_instances_trajectory(P, N, R, T, hot, sweep):
             assert np.array_equal(got["choices"][k], ref.choices[k])
 
 
-def test_beta_zero_uniform_choices(P):
-    N, R, T = 24, 4, 6
+@pytest.mark.parametrize("N,lo,hi,kind,cls", [
+    (150, 0, 60, "uniform", 160), (140, 0, 60, "diag", 160),
+    (200, 0, 9, "uniform", 256), (256, 0, 9, "uniform", 256), (256, 0, 0, "euclid", 256)])
+def test_large_size_classes(P, N, lo, hi, kind, cls):
+    """The large on-chip classes (H in LDS, D and F from device memory):
+    trajectories identical to the oracle, and the class that ran is the one
+    the data allow."""
+    rng = np.random.default_rng(N + hi)
+    if kind == "euclid":
+        D = W.euclid_points(rng, N)
+        F = W.sym_bernoulli_values(rng, N, 0.1, 1, 1)
+    else:
+        D, F = W.random_instance(rng, N, lo, hi, zero_diag=(kind != "diag"))
+    R, T = 3, 5
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric(0.5 / s, 200.0 / s, T)
+    ref = oracle.run(D, F, perms, beta, 13, record_choices=True)
+    with P.Pdit(sweep="fast") as ctx:
+        got = run_gpu(P, D, F, perms, beta, 13, record=True, ctx=ctx)
+        plan = ctx.last_plan()
+    assert plan["sweep"] == "fast" and plan["size_class"] == cls
+    bad = compare_runs(got, ref)
+    assert len(bad) == 0
+    for k in range(R):
+        assert np.array_equal(got["choices"][k], ref.choices[k])
+
+
+@pytest.mark.parametrize("N", [24, 64, 128, 256])
+def test_beta_zero_uniform_choices(P, N):
+    """beta = 0 gives every candidate weight 2^25: the largest CDF total
+    (N 2^25, beyond 32 bits for N >= 128)."""
+    R, T = 4, 6
     rng = np.random.default_rng(3)
     D, F = W.random_instance(rng, N, 0, 9)
     perms = W.random_perms(rng, R, N)
@@ -348,10 +379,16 @@ def test_error_paths(P):
         # inputs untouched by refused calls
         assert np.array_equal(pd.cpu().numpy(), perms)
     with P.Pdit(sweep="fast") as ctx:
-        D2, F2 = W.random_instance(rng, 130, 0, 9)
+        # N in (160, 256] keeps 2H in 16 bits: values up to 200 overflow it
+        D2, F2 = W.random_instance(rng, 200, 0, 200)
         with pytest.raises(P.PditError) as e:
             ctx.run_sweeps(dev(D2, torch.int32), dev(F2, torch.int32),
-                           dev(W.random_perms(rng, 1, 130), torch.int32), bd, 1)
+                           dev(W.random_perms(rng, 1, 200), torch.int32), bd, 1)
+        assert e.value.status == "PDIT_EOVERFLOW"
+        D2, F2 = W.random_instance(rng, 257, 0, 1)
+        with pytest.raises(P.PditError) as e:
+            ctx.run_sweeps(dev(D2, torch.int32), dev(F2, torch.int32),
+                           dev(W.random_perms(rng, 1, 257), torch.int32), bd, 1)
         assert e.value.status == "PDIT_EOVERFLOW"
     with P.Pdit(recompute="i8") as ctx:
         D3, F3 = W.random_instance(rng, 12, 0, 200)
