@@ -74,8 +74,10 @@ extern "C" {
 /* Which sweep kernel runs. */
 #define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else plain */
 #define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
-#define PDIT_SWEEP_FAST 2   /* H in LDS, speculative row evaluation; N <= 128, |dE| < 2^30,
-                               |D| <= 8191, |F| <= 32767 */
+#define PDIT_SWEEP_FAST 2   /* replica state on chip, speculative row evaluation; needs
+                               |dE| < 2^30 and N <= 256.  N <= 128: the table of swap energy
+                               changes in LDS, |D|, |F| <= 32767; N <= 160: 2H int32 in LDS;
+                               N <= 256: 2H int16 in LDS, |2H| <= 32767 */
 
 typedef struct pdit_ctx pdit_t;
 

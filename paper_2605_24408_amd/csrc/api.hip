@@ -247,7 +247,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
         if (!fclass)
             return fail(ctx, PDIT_EOVERFLOW,
                         "the fast sweep kernel needs N <= 256, |dE| < 2^30 and, by size, "
-                        "|D| <= 8191 and |F| <= 32767 (N <= 128) or |2H| <= 32767 (N > 160)");
+                        "|D|, |F| <= 32767 (N <= 128) or |2H| <= 32767 (N > 160)");
         use_fast = true;
     } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
         use_fast = fclass != 0;

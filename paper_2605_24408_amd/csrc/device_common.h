@@ -153,4 +153,29 @@ __device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane) {
     return (int64_t)readlane_u64((uint64_t)v, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Quad (4-lane) exchanges by DPP quad_perm: lane i of each quad reads lane
+// sel[i] of the same quad.
+// ---------------------------------------------------------------------------
+constexpr int kQuadXor1 = 0xB1;   // [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;   // [2,3,0,1]
+constexpr int kQuadPrev1 = 0x90;  // [0,0,1,2]
+constexpr int kQuadPrev2 = 0x40;  // [0,0,0,1]
+constexpr int kQuadPrev3 = 0x00;  // [0,0,0,0]
+constexpr int kQuadLast = 0xFF;   // [3,3,3,3]
+
+template <int CTRL>
+__device__ __forceinline__ int32_t quad(int32_t v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint32_t quadu(uint32_t v) {
+    return (uint32_t)quad<CTRL>((int32_t)v);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t quadu(uint64_t v) {
+    const uint32_t lo = quadu<CTRL>((uint32_t)v), hi = quadu<CTRL>((uint32_t)(v >> 32));
+    return (uint64_t)hi << 32 | lo;
+}
+
 }  // namespace pdit

@@ -132,6 +132,11 @@ hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a);
 hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zero_diag, const BatchArgs &b,
                                         int grid);
 int fast_blocks_per_cu(int nmax);
+// the N <= 128 classes (table of energy changes on chip), called by the above
+hipError_t launch_sweep_table(hipStream_t s, int nmax, const SweepArgs &a);
+hipError_t launch_sweep_table_persistent(hipStream_t s, int nmax, bool zero_diag, const BatchArgs &b,
+                                         int grid);
+int table_blocks_per_cu(int nmax);
 hipError_t launch_sweep_plain_persistent(hipStream_t s, bool h64, const BatchArgs &b, int grid);
 hipError_t launch_queue_reset(hipStream_t s, int *queue, int n);
 int plain_blocks_per_cu(bool h64);

@@ -50,29 +50,6 @@ namespace {
 constexpr int32_t kBig = (1 << 30) - 1;  // excluded candidates (|dE| < 2^30 is guaranteed)
 constexpr uint32_t kOne = kWeightOne;    // weight of the row minimum
 
-// quad_perm DPP selectors (lane i of each quad reads lane sel[i])
-constexpr int kQuadXor1 = 0xB1;   // [1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;   // [2,3,0,1]
-constexpr int kQuadPrev1 = 0x90;  // [0,0,1,2]
-constexpr int kQuadPrev2 = 0x40;  // [0,0,0,1]
-constexpr int kQuadPrev3 = 0x00;  // [0,0,0,0]
-constexpr int kQuadLast = 0xFF;   // [3,3,3,3]
-
-template <int CTRL>
-__device__ __forceinline__ int32_t quad(int32_t v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ uint32_t quadu(uint32_t v) {
-    return (uint32_t)quad<CTRL>((int32_t)v);
-}
-template <int CTRL>
-__device__ __forceinline__ uint64_t quadu(uint64_t v) {
-    const uint32_t lo = quadu<CTRL>((uint32_t)v), hi = quadu<CTRL>((uint32_t)(v >> 32));
-    return (uint64_t)hi << 32 | lo;
-}
-
-
 template <int NMAX, bool LARGE, typename HT>
 struct FastSmem {
     // padded H rows: column reads are bank-conflict-free
@@ -611,8 +588,8 @@ int fast_class(int N, const InstanceStats &st) {
     if (bound > INT32_MAX || 2 * delta_bound(st) >= (int64_t)INT32_MAX) return 0;
     if (st.max_abs_d >= (1 << 21) || st.max_abs_f >= (1 << 21)) return 0;
     if (N <= 128) {
-        // D (times 4) and F[p,p] in int16
-        if (st.max_abs_d > 8191 || st.max_abs_f > 32767) return 0;
+        // D and F[p,p] in int16
+        if (st.max_abs_d > 32767 || st.max_abs_f > 32767) return 0;
         return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 128;
     }
     if (N <= 160) return 160;
@@ -623,11 +600,8 @@ int fast_class(int N, const InstanceStats &st) {
 hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a0) {
     SweepArgs a = a0;
     if (a.seq_threshold < 0) a.seq_threshold = kDefaultSeqThreshold;
+    if (nmax <= 128) return launch_sweep_table(s, nmax, a);
     switch (nmax) {
-        case 16: return launch_nmax<16>(s, a);
-        case 32: return launch_nmax<32>(s, a);
-        case 64: return launch_nmax<64>(s, a);
-        case 128: return launch_nmax<128>(s, a);
         case 160: return launch_nmax<160>(s, a);
         case 256: return launch_nmax<256>(s, a);
         default: return hipErrorInvalidValue;
@@ -636,11 +610,8 @@ hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a0) {
 
 hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zd, const BatchArgs &b,
                                         int grid) {
+    if (nmax <= 128) return launch_sweep_table_persistent(s, nmax, zd, b, grid);
     switch (nmax) {
-        case 16: return launch_persistent_nmax<16>(s, zd, b, grid);
-        case 32: return launch_persistent_nmax<32>(s, zd, b, grid);
-        case 64: return launch_persistent_nmax<64>(s, zd, b, grid);
-        case 128: return launch_persistent_nmax<128>(s, zd, b, grid);
         case 160: return launch_persistent_nmax<160>(s, zd, b, grid);
         case 256: return launch_persistent_nmax<256>(s, zd, b, grid);
         default: return hipErrorInvalidValue;
@@ -648,11 +619,8 @@ hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zd, const 
 }
 
 int fast_blocks_per_cu(int nmax) {
+    if (nmax <= 128) return table_blocks_per_cu(nmax);
     switch (nmax) {
-        case 16: return persistent_blocks_per_cu<16>();
-        case 32: return persistent_blocks_per_cu<32>();
-        case 64: return persistent_blocks_per_cu<64>();
-        case 128: return persistent_blocks_per_cu<128>();
         case 160: return persistent_blocks_per_cu<160>();
         case 256: return persistent_blocks_per_cu<256>();
         default: return 1;
