@@ -60,11 +60,12 @@ __device__ __forceinline__ uint32_t gibbs_weight(float beta, float d) {
 
 // Smallest integer distance above which every weight is provably 0:
 // fl32(beta * fl32(d)) >= 19.5 for all d >= the returned value
-// (e^-19.5 * 2^25 < 0.12 rounds to 0).  Returns INT32_MAX when no such
-// integer is in range.
+// (e^-19.5 * 2^25 < 0.12 rounds to 0).  The hardware reciprocal (error
+// within 1 ulp) and the rounding of beta * d are covered by the 1e-4 margin
+// and the +2.  Returns INT32_MAX when no such integer is in range.
 __device__ __forceinline__ int32_t zero_weight_distance(float beta) {
     if (!(beta > 0.0f)) return INT32_MAX;
-    const float t = 19.5f / beta * 1.0001f + 2.0f;
+    const float t = (19.5f * 1.0001f) * __builtin_amdgcn_rcpf(beta) + 2.0f;
     if (!(t < 2.0e9f)) return INT32_MAX;
     return (int32_t)t;
 }

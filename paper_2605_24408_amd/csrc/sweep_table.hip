@@ -39,11 +39,12 @@
 // Weights are the integers q = rint(expf(-fl32(beta fl32(d))) 2^25) of the
 // distance d >= 0 to the row minimum, summed exactly (32 bits for N <= 64,
 // 64 bits beyond), so the schedules agree whatever their summation order.
-// A candidate with d >= dthr has q = 0.  A row whose minimum is the stay
-// (T = 0, and no other candidate at 0) and whose second smallest entry is
-// at distance >= dthr puts all its weight on the stay: its draw keeps the
-// facility whatever the uniform, so its weights, and its uniform (a pure
-// function of location and sweep), are not evaluated.
+// A candidate with d >= dthr has q = 0.  The stay's energy change is 0, so
+// the table's diagonal holds a sentinel (kBig) instead and the smallest
+// entry m of a row is its best move: m >= dthr puts all the row's weight on
+// the stay, whose draw then keeps the facility whatever the uniform; such a
+// row evaluates no weights, and no uniform (a pure function of location and
+// sweep).
 #include "device_common.h"
 #include "pdit_internal.h"
 #include "sweep_common.h"
@@ -68,7 +69,7 @@ template <int NMAX>
 struct TableSmem {
     static constexpr int PT = NMAX + 4;  // table row pitch (int32), rows 16-byte aligned
     static constexpr int PD = NMAX + 8;  // D and Fp row pitch (int16), rows 16-byte aligned
-    int32_t T[NMAX * PT];                // T[l][s], kBig outside N x N
+    int32_t T[NMAX * PT];                // T[l][s]; kBig on the diagonal and outside N x N
     int16_t Ds[NMAX * PD];               // D
     int16_t Fp[NMAX * PD];               // F[p,p]
     int32_t hd[NMAX];                    // H[x][x]
@@ -76,12 +77,14 @@ struct TableSmem {
     int32_t av[NMAX];                    // a_x of the exchange being applied
     int32_t cv2[NMAX];                   // 2 c_x
     int32_t hv[4][NMAX];                 // H'[r][x], H'[t][x], H'[x][r], H'[x][t]
-    int32_t sel_row[2][NMAX];
-    int32_t flag_row[2][NMAX];           // bit 0: the row swaps, bit 1: tie
+    // per wave and pass: 0, or 2^30 | first swapping row << 16 | its choice
+    __align__(16) int32_t summ[2][NMAX / 16 < 4 ? 4 : NMAX / 16];
+    int64_t tie_sum[NMAX / 16];
 };
 
-// Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).
-template <int NMAX, bool ZD, bool EXACT>
+// Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).  REC:
+// the job records choices and/or the energy trace.
+template <int NMAX, bool ZD, bool EXACT, bool REC>
 __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMAX> &sm) {
     constexpr int WPR = NMAX / 16;         // waves per replica
     constexpr int NT = 64 * WPR;           // threads: 4 NMAX
@@ -138,7 +141,7 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
     for (int e = tid; e < NMAX * PT; e += NT) {
         const int l = e / PT, s = e % PT;
         int32_t v = kBig;
-        if (l < N && s < N)
+        if (l < N && s < N && l != s)
             v = eq3(l, s, Hg[(int64_t)l * N + s], Hg[(int64_t)s * N + l], hd[l], hd[s]);
         T[e] = v;
     }
@@ -250,7 +253,8 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
             if (x < N) {
                 const int32_t hww = sm.hv[vr][w];
                 const int32_t hxx = x == r ? sm.hv[0][r] : x == t ? sm.hv[1][t] : hd[x];
-                const int32_t v = eq3(w, x, sm.hv[vr][x], sm.hv[vr + 2][x], hww, hxx);
+                const int32_t v =
+                    x == w ? kBig : eq3(w, x, sm.hv[vr][x], sm.hv[vr + 2][x], hww, hxx);
                 T[w * PT + x] = v;
                 T[x * PT + w] = v;
             }
@@ -269,12 +273,22 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         }
     };
 
+    // beta and the zero-weight distance of 64 sweeps at a time, lane i
+    // holding sweep t0 + i
+    float bcache = 0.0f;
+    int32_t dcache = 0;
     for (int64_t t = 0; t < a.T; ++t) {
-        const float beta = a.beta[t];
+        const int slot = (int)(t & 63);
+        if (slot == 0) {
+            const int64_t tt = t + lane < a.T ? t + lane : a.T - 1;
+            bcache = a.beta[tt];
+            dcache = zero_weight_distance(bcache);
+        }
+        const float beta = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bcache), slot));
+        const int32_t dthr = __builtin_amdgcn_readlane(dcache, slot);
         const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
-        const int32_t dthr = zero_weight_distance(beta);
         const int64_t acc_before = n_acc;
-        int32_t *ch = (a.choices && wv == 0) ? a.choices + t * N : nullptr;
+        int32_t *ch = (REC && a.choices) ? a.choices + t * N : nullptr;
 
         if (!seq_mode) {
             // ============ speculative rows: 16 locations per wave, 4 lanes each ============
@@ -296,37 +310,31 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                         dl[j + 2] = x.z;
                         dl[j + 3] = x.w;
                     }
-                    // smallest and second smallest entry of the row
-                    int32_t m1 = kBig, m2 = kBig;
+                    // best move of the row (the diagonal holds the sentinel)
+                    int32_t m = kBig;
 #pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        m2 = max(m1, min(dl[j], m2));
-                        m1 = min(m1, dl[j]);
-                    }
-                    {
-                        const int32_t o1 = quad<kQuadXor1>(m1), o2 = quad<kQuadXor1>(m2);
-                        m2 = min(max(m1, o1), min(m2, o2));
-                        m1 = min(m1, o1);
-                    }
-                    {
-                        const int32_t o1 = quad<kQuadXor2>(m1), o2 = quad<kQuadXor2>(m2);
-                        m2 = min(max(m1, o1), min(m2, o2));
-                        m1 = min(m1, o1);
-                    }
-                    const bool stays = m1 == 0 && m2 >= dthr;
+                    for (int j = 0; j < K; j += 2) m = min(m, min(dl[j], dl[j + 1]));
+                    m = min(m, quad<kQuadXor1>(m));
+                    m = min(m, quad<kQuadXor2>(m));
+                    const bool stays = m >= dthr;
                     if (__ballot(rowv && !stays)) {
                         if (!have_u) {
-                            u24 = uniform24(a.seed, (uint32_t)rr, g, a.rep, a.inst);
+                            // kept inside the branch: the uniform is only
+                            // evaluated by passes that draw
+                            uint32_t row = (uint32_t)rr;
+                            asm volatile("" : "+v"(row));
+                            u24 = uniform24(a.seed, row, g, a.rep, a.inst);
                             have_u = true;
                         }
-                        const int32_t mn = m1;
+                        const int js = rr - cq * K;  // this lane's slot of the stay, if any
+                        const int32_t mn = min(m, 0);
                         // weights: d = 0 -> 2^25; 0 < d < dthr -> expf; d >= dthr -> 0
                         uint32_t ql[K];
                         uint32_t Zc = 0;
                         int am = -1;
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
-                            const int32_t d = dl[j] - mn;
+                            const int32_t d = (j == js ? 0 : dl[j]) - mn;
                             const bool zero = d == 0;
                             uint32_t q = zero ? kOne : 0u;
                             am = zero ? cq * K + j : am;
@@ -379,38 +387,35 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                     }
                 }
                 const bool swaps = rowv && sel != rr;
-                if (cq == 0) {
-                    sm.sel_row[parity][rr] = sel;
-                    sm.flag_row[parity][rr] = (swaps ? 1 : 0) | (rowv && tie ? 2 : 0);
+                // this wave's first swapping row and its choice, one word per wave
+                const uint64_t swm = __ballot(swaps);
+                int32_t word = 0;
+                if (swm) {
+                    const int fl = __ffsll((unsigned long long)swm) - 1;  // lane 4 rl + cq
+                    const int32_t sv = __builtin_amdgcn_readlane(sel, fl);
+                    word = (int32_t)(0x40000000u | ((uint32_t)(16 * wv + (fl >> 2)) << 16) |
+                                     (uint32_t)sv);
                 }
+                if (lane == 0) sm.summ[parity][wv] = word;
                 __syncthreads();
-                // every wave reads the same flags: first swapping row from pos
-                int last = N - 1;
+                // the first swapping row of the pass, from the waves in order
+                int last = N - 1, s_last = 0;
                 bool found = false;
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int row = lane + 64 * c;
-                    const int32_t fl = row < NMAX ? sm.flag_row[parity][row] : 0;
-                    const uint64_t acc_mask = __ballot(fl & 1);
-                    if (!found && acc_mask) {
-                        last = 64 * c + __ffsll((unsigned long long)acc_mask) - 1;
+                for (int w = 0; w < WPR; ++w) {
+                    const int32_t x = __builtin_amdgcn_readfirstlane(sm.summ[parity][w]);
+                    if (!found && x != 0) {
                         found = true;
+                        last = (x >> 16) & 0x3fff;
+                        s_last = x & 0xffff;
                     }
                 }
-                if (wv == 0) {
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const int row = lane + 64 * c;
-                        const int32_t fl = row < NMAX ? sm.flag_row[parity][row] : 0;
-                        const bool committed = row >= pos && row <= last && row < N;
-                        n_tie += __popcll(__ballot(committed && (fl & 2)));
-                        if (ch && committed) ch[row] = sm.sel_row[parity][row];
-                    }
-                }
-                if (found) {
-                    const int s = sm.sel_row[parity][last];
-                    apply_swap(last, s, T[last * PT + s]);
-                }
+                // rows pos..last are committed: each wave counts (and
+                // records) its own
+                const bool committed = rowv && rr <= last;
+                n_tie += __popcll(__ballot(committed && tie && cq == 0));
+                if (REC && ch && committed && cq == 0) ch[rr] = sel;
+                if (found) apply_swap(last, s_last, T[last * PT + s_last]);
                 parity ^= 1;
                 pos = last + 1;
             }
@@ -427,7 +432,7 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const int ls = lane + 64 * c;
-                    v[c] = ls < N ? T[r * PT + ls] : kBig;
+                    v[c] = ls < N ? (ls == r ? 0 : T[r * PT + ls]) : kBig;
                     lmin = min(lmin, v[c]);
                 }
                 const int32_t mn = wave_min_i32(lmin);
@@ -470,15 +475,21 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                     }
                 }
                 if (wv == 0) n_tie += is_tie(csel - qsel, csel, Z, ur24) ? 1 : 0;
-                if (ch && lane == 0) ch[r] = s;
+                if (REC && ch && tid == 0) ch[r] = s;
                 if (s != r) apply_swap(r, s, vsel);
             }
         }
         seq_mode = (n_acc - acc_before) > a.seq_threshold;
-        if (a.E_trace && tid == 0) a.E_trace[t] = E;
+        if (REC && a.E_trace && tid == 0) a.E_trace[t] = E;
     }
 
+    if (lane == 0) sm.tie_sum[wv] = n_tie;
+    __syncthreads();
     if (wv == 0) {
+        if (lane == 0) {
+#pragma unroll
+            for (int w = 1; w < WPR; ++w) n_tie += sm.tie_sum[w];
+        }
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
             if (lane + 64 * c < N) a.perm[lane + 64 * c] = pv[lane + 64 * c];
@@ -500,7 +511,7 @@ constexpr int table_waves_per_eu() {
 }
 
 // One replica per workgroup (single-instance runs).
-template <int NMAX, bool ZD, bool EXACT>
+template <int NMAX, bool ZD, bool EXACT, bool REC>
 __global__ void __launch_bounds__(4 * NMAX)
 __attribute__((amdgpu_waves_per_eu(table_waves_per_eu<NMAX>())))
 sweep_table_kernel(SweepArgs a) {
@@ -526,7 +537,7 @@ sweep_table_kernel(SweepArgs a) {
     j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
     j.seq_threshold = a.seq_threshold;
     j.zero_diag = ZD;
-    table_replica<NMAX, ZD, EXACT>(j, sm);
+    table_replica<NMAX, ZD, EXACT, REC>(j, sm);
 }
 
 // Persistent: each workgroup takes (instance, replica) items from a queue
@@ -545,14 +556,17 @@ sweep_table_persistent(BatchArgs b) {
         const int item = item_sh;
         __syncthreads();
         if (item >= b.n_items) break;
-        table_replica<NMAX, ZD, false>(batch_job(b, item, sizeof(int32_t)), sm);
+        table_replica<NMAX, ZD, false, false>(batch_job(b, item, sizeof(int32_t)), sm);
         __syncthreads();
     }
 }
 
 template <int NMAX, bool ZD, bool EXACT>
 hipError_t launch_one(hipStream_t s, const SweepArgs &a) {
-    sweep_table_kernel<NMAX, ZD, EXACT><<<a.R, 4 * NMAX, 0, s>>>(a);
+    if (a.choices || a.E_trace)
+        sweep_table_kernel<NMAX, ZD, EXACT, true><<<a.R, 4 * NMAX, 0, s>>>(a);
+    else
+        sweep_table_kernel<NMAX, ZD, EXACT, false><<<a.R, 4 * NMAX, 0, s>>>(a);
     return hipGetLastError();
 }
 
