@@ -75,7 +75,7 @@ extern "C" {
 #define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else plain */
 #define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
 #define PDIT_SWEEP_FAST 2   /* replica state on chip, speculative row evaluation; needs
-                               |dE| < 2^30 and N <= 256.  N <= 128: the table of swap energy
+                               |dE| < 2^30 - 1 and N <= 256.  N <= 128: the table of swap energy
                                changes in LDS, |D|, |F| <= 32767; N <= 160: 2H int32 in LDS;
                                N <= 256: 2H int16 in LDS, |2H| <= 32767 */
 

@@ -22,14 +22,14 @@ __device__ __forceinline__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint3
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
-        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
-        const uint32_t n0 = hiB ^ c1 ^ k0;
-        const uint32_t n2 = hiA ^ c3 ^ k1;
+        // one 32 x 32 -> 64-bit product per word (v_mad_u64_u32)
+        const uint64_t pA = (uint64_t)kMulA * c0, pB = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pB >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pA >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = loB;
+        c1 = (uint32_t)pB;
         c2 = n2;
-        c3 = loA;
+        c3 = (uint32_t)pA;
         k0 += kWeylA;
         k1 += kWeylB;
     }

@@ -584,8 +584,9 @@ int persistent_blocks_per_cu() {
 int fast_class(int N, const InstanceStats &st) {
     if (N < 2 || N > kFastNMax) return 0;
     const int64_t bound = h_bound(st);
-    // H and dE in int32 with |dE| < 2^30, 24-bit products
-    if (bound > INT32_MAX || 2 * delta_bound(st) >= (int64_t)INT32_MAX) return 0;
+    // H and dE in int32 with |dE| < 2^30 - 1 (below the excluded-candidate
+    // sentinel), 24-bit products
+    if (bound > INT32_MAX || delta_bound(st) >= (int64_t)(1 << 30) - 1) return 0;
     if (st.max_abs_d >= (1 << 21) || st.max_abs_f >= (1 << 21)) return 0;
     if (N <= 128) {
         // D and F[p,p] in int16

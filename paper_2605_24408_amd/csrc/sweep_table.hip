@@ -77,6 +77,8 @@ struct TableSmem {
     int32_t av[NMAX];                    // a_x of the exchange being applied
     int32_t cv2[NMAX];                   // 2 c_x
     int32_t hv[4][NMAX];                 // H'[r][x], H'[t][x], H'[x][r], H'[x][t]
+    int32_t fnew[2][NMAX];               // rows r and t of Fp'
+    int32_t fdn[NMAX];                   // diag Fp' (nonzero diagonals only)
     // per wave and pass: 0, or 2^30 | first swapping row << 16 | its choice
     __align__(16) int32_t summ[2][NMAX / 16 < 4 ? 4 : NMAX / 16];
     int64_t tie_sum[NMAX / 16];
@@ -158,21 +160,63 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
     const int rr = 16 * wv + rl;
 
     // ---- apply the exchange of locations r and t; every thread calls it ----
+    // Phase A reads only the state before the exchange (D, Fp, diag H) and
+    // fills a, 2c, the four H' vectors, diag H' and the new rows r, t of Fp';
+    // phase B rewrites the table, then Fp and p.  With pi the exchange of r
+    // and t and Fp' = Fp[pi, pi]:
+    //   H'[w][x] = dot(D[w], Fp[pi x]) + (D[w][t] - D[w][r])(Fp[pi x][r] - Fp[pi x][t])
+    //   H'[x][w] = dot(D[x], Fp[pi w]) + (D[x][t] - D[x][r])(Fp[pi w][r] - Fp[pi w][t])
     auto apply_swap = [&](int r, int t, int32_t dE) {
         E += dE;
         ++n_acc;
-        // (1) a and 2c from the flows before the exchange.  Nothing writes D
-        // or Fp before barrier (2), and av / cv2 were last read before the
-        // previous exchange's barrier (3).
-        for (int x = tid; x < NMAX; x += NT) {
-            const bool in = x < N;
-            av[x] = in ? (int32_t)Ds[x * PD + r] - (int32_t)Ds[x * PD + t] : 0;
-            cv2[x] = in ? 2 * ((int32_t)Fp[x * PD + t] - (int32_t)Fp[x * PD + r]) : 0;
+        {
+            const int vec = tid / NMAX, x = tid % NMAX;  // one (vector, x) per thread
+            if (x < N) {
+                const int px = x == r ? t : x == t ? r : x;
+                const int urow = vec == 0 ? r : vec == 1 ? t : x;
+                const int frow = vec < 2 ? px : vec == 2 ? t : r;
+                const int16_t *pu = Ds + urow * PD;
+                const int16_t *pf = Fp + frow * PD;
+                int32_t acc = 0;
+#pragma unroll
+                for (int k = 0; k < NMAX; k += 8) {
+                    const uint4 xu = *reinterpret_cast<const uint4 *>(pu + k);
+                    const uint4 xf = *reinterpret_cast<const uint4 *>(pf + k);
+                    acc = dot2(xu.x, xf.x, acc);
+                    acc = dot2(xu.y, xf.y, acc);
+                    acc = dot2(xu.z, xf.z, acc);
+                    acc = dot2(xu.w, xf.w, acc);
+                }
+                const int32_t du = (int32_t)pu[t] - (int32_t)pu[r];
+                const int32_t df = (int32_t)pf[r] - (int32_t)pf[t];
+                const int32_t h = (int32_t)((uint32_t)acc + (uint32_t)du * (uint32_t)df);
+                sm.hv[vec][x] = h;
+                if (vec == 0) {
+                    const int32_t ax = (int32_t)Ds[x * PD + r] - (int32_t)Ds[x * PD + t];
+                    const int32_t cx = (int32_t)Fp[x * PD + t] - (int32_t)Fp[x * PD + r];
+                    av[x] = ax;
+                    cv2[x] = 2 * cx;
+                    sm.fnew[0][x] = Fp[t * PD + px];
+                    if (x == r)
+                        hd[x] = h;
+                    else if (x != t)
+                        hd[x] = (int32_t)((uint32_t)hd[x] + (uint32_t)ax * (uint32_t)cx);
+                } else if (vec == 1) {
+                    sm.fnew[1][x] = Fp[r * PD + px];
+                    if (x == t) hd[x] = h;
+                } else if (vec == 2 && !ZD) {
+                    sm.fdn[x] = Fp[px * PD + px];
+                }
+            } else if (vec == 0) {
+                av[x] = 0;
+                cv2[x] = 0;
+            }
         }
         __syncthreads();  // also: every read of the table for this update is done
-        // (2) every table entry off rows/columns r, t (those are rewritten in
-        // (4)); wave 0 exchanges rows and columns r, t of Fp and p(r), p(t)
-        if (rr < N) {
+        // Phase B.  Entries off rows/columns r, t: T += (a_s - a_l)(2c_l - 2c_s).
+        // Columns r and t from Eq. 3, written with their transposes (rows r and
+        // t) by the owner of row l; T[r][t] = T[t][r] = -dE (the way back).
+        if (rr < N && rr != r && rr != t) {
             const int32_t al = av[rr], cl2 = cv2[rr];
             int32_t *row = T + rr * PT + cq * K;
 #pragma unroll
@@ -191,76 +235,44 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                 x.w = (EXACT || s0 + 3 < N) ? n3 : x.w;
                 *reinterpret_cast<int4 *>(row + j) = x;
             }
-        }
-        if (wv == 0) {
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int k = lane + 64 * c;
-                if (k < N) {
-                    const int16_t fr = Fp[r * PD + k], ft = Fp[t * PD + k];
-                    Fp[r * PD + k] = ft;
-                    Fp[t * PD + k] = fr;
+            for (int wi = 0; wi < 2; ++wi) {
+                const int w = wi == 0 ? r : t;
+                if (w >= cq * K && w < cq * K + K) {
+                    const int l = rr;
+                    const uint32_t h = 2u * ((uint32_t)sm.hv[2 + wi][l] + (uint32_t)sm.hv[wi][l] -
+                                             (uint32_t)hd[l] - (uint32_t)hd[w]);
+                    const int32_t dlw = Ds[l * PD + w], flw = sm.fnew[wi][l];
+                    uint32_t corr;
+                    if (ZD) {
+                        corr = 4u * (uint32_t)(dlw * flw);
+                    } else {
+                        const int32_t dd = (int32_t)Ds[l * PD + l] + (int32_t)Ds[w * PD + w] - 2 * dlw;
+                        const int32_t ff = sm.fdn[l] + sm.fdn[w] - 2 * flw;
+                        corr = (uint32_t)dd * (uint32_t)ff;
+                    }
+                    const int32_t v = (int32_t)(h + corr);
+                    T[l * PT + w] = v;
+                    T[w * PT + l] = v;
                 }
             }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int k = lane + 64 * c;
-                if (k < N) {
-                    const int16_t cr = Fp[k * PD + r], ct = Fp[k * PD + t];
-                    Fp[k * PD + r] = ct;
-                    Fp[k * PD + t] = cr;
-                }
-            }
-            if (lane == 0) {
-                const int32_t fa = pv[r], fb = pv[t];
-                pv[r] = fb;
-                pv[t] = fa;
-            }
         }
-        __syncthreads();
-        // (3) the four H' vectors, one (vector, x) per thread, and diag(H')
-        // off r, t
-        {
-            const int vec = tid / NMAX, x = tid % NMAX;
-            if (x < N) {
-                const int16_t *pl = (vec < 2 ? Fp : Ds) + x * PD;
-                const int16_t *pu = vec == 0 ? Ds + r * PD
-                                  : vec == 1 ? Ds + t * PD
-                                  : vec == 2 ? Fp + r * PD
-                                             : Fp + t * PD;
-                int32_t acc = 0;
-#pragma unroll
-                for (int k = 0; k < NMAX; k += 8) {
-                    const uint4 xl = *reinterpret_cast<const uint4 *>(pl + k);
-                    const uint4 xu = *reinterpret_cast<const uint4 *>(pu + k);
-                    acc = dot2(xl.x, xu.x, acc);
-                    acc = dot2(xl.y, xu.y, acc);
-                    acc = dot2(xl.z, xu.z, acc);
-                    acc = dot2(xl.w, xu.w, acc);
-                }
-                sm.hv[vec][x] = acc;
-            }
-            if (tid < N && tid != r && tid != t)
-                hd[tid] = (int32_t)((uint32_t)hd[tid] + (uint32_t)av[tid] * (uint32_t)(cv2[tid] >> 1));
+        if (tid == 0) {
+            T[r * PT + t] = -dE;
+            T[t * PT + r] = -dE;
         }
-        __syncthreads();
-        // (4) rows and columns r and t from Eq. 3
-        if (tid < 2 * NMAX) {
-            const int vr = tid < NMAX ? 0 : 1;
-            const int w = vr == 0 ? r : t;
-            const int x = tid % NMAX;
-            if (x < N) {
-                const int32_t hww = sm.hv[vr][w];
-                const int32_t hxx = x == r ? sm.hv[0][r] : x == t ? sm.hv[1][t] : hd[x];
-                const int32_t v =
-                    x == w ? kBig : eq3(w, x, sm.hv[vr][x], sm.hv[vr + 2][x], hww, hxx);
-                T[w * PT + x] = v;
-                T[x * PT + w] = v;
-            }
-        } else if (tid == 2 * NMAX) {
-            hd[r] = sm.hv[0][r];
-            hd[t] = sm.hv[1][t];
+        // Fp' rows and columns r, t from the buffer; p(r) <-> p(t)
+        for (int x = tid; x < N; x += NT) {
+            const int16_t fr = (int16_t)sm.fnew[0][x], ft = (int16_t)sm.fnew[1][x];
+            Fp[r * PD + x] = fr;
+            Fp[x * PD + r] = fr;
+            Fp[t * PD + x] = ft;
+            Fp[x * PD + t] = ft;
+        }
+        if (tid == 0) {
+            const int32_t fa = pv[r], fb = pv[t];
+            pv[r] = fb;
+            pv[t] = fa;
         }
         __syncthreads();
         if (E < E_best) {
@@ -328,38 +340,48 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                         }
                         const int js = rr - cq * K;  // this lane's slot of the stay, if any
                         const int32_t mn = min(m, 0);
-                        // weights: d = 0 -> 2^25; 0 < d < dthr -> expf; d >= dthr -> 0
-                        uint32_t ql[K];
-                        uint32_t Zc = 0;
-                        int am = -1;
+                        // candidates whose weight may be nonzero: d = v - mn < dthr,
+                        // i.e. v < lim (the sentinel never qualifies); the stay
+                        // (v = 0) by its own test
+                        const int32_t lim = (int32_t)min((int64_t)mn + (int64_t)dthr, (int64_t)kBig);
+                        uint32_t near = 0;
 #pragma unroll
-                        for (int j = 0; j < K; ++j) {
-                            const int32_t d = (j == js ? 0 : dl[j]) - mn;
-                            const bool zero = d == 0;
-                            uint32_t q = zero ? kOne : 0u;
-                            am = zero ? cq * K + j : am;
-                            const bool need = d < dthr && !zero;
+                        for (int j = 0; j < K; ++j) near |= (dl[j] < lim ? 1u : 0u) << j;
+                        if (js >= 0 && js < K && 0 < lim) near |= 1u << js;
+                        // sparse draw: up to S such candidates per lane, in order
+                        constexpr int S = 4;
+                        uint32_t qs[S];
+                        int jx[S];
+                        uint32_t rest = near;
+                        uint32_t Zc = 0;
+#pragma unroll
+                        for (int it = 0; it < S; ++it) {
+                            qs[it] = 0;
+                            jx[it] = -1;
+                            if (!__ballot(rest != 0)) continue;
+                            const bool has = rest != 0;
+                            const int j = has ? (int)__builtin_ctz(rest) : 0;
+                            rest &= rest - 1;
+                            const int32_t v = j == js ? 0 : T[rr * PT + cq * K + j];
+                            const int32_t d = v - mn;
+                            uint32_t q = (has && d == 0) ? kOne : 0u;
+                            const bool need = has && d != 0;
                             if (__ballot(need)) {
                                 if (need) q = gibbs_weight(beta, (float)d);
                             }
-                            if (!EXACT && cq * K + j >= N) q = 0;
-                            ql[j] = q;
+                            qs[it] = q;
+                            jx[it] = has ? cq * K + j : -1;
                             Zc += q;
                         }
-                        // quarters before this one, and the row total
-                        const CT p1 = quadu<kQuadPrev1>(Zc), p2 = quadu<kQuadPrev2>(Zc),
-                                 p3 = quadu<kQuadPrev3>(Zc);
-                        const CT off = (cq >= 1 ? p1 : 0) + (cq >= 2 ? p2 : 0) + (cq >= 3 ? p3 : 0);
-                        const CT Z = quadu<kQuadLast>((CT)(off + Zc));
-                        am = max(am, quad<kQuadXor1>(am));
-                        am = max(am, quad<kQuadXor2>(am));
-                        sel = am;
-                        // a row whose only nonzero weight is its minimum (Z = 2^25)
-                        // picks the minimum; otherwise locate the threshold by
-                        // counting: the first s with C_s > thr is #{s : C_s <= thr},
-                        // and a tie is a boundary thr_lo < C_s <= thr_hi (the band
-                        // around the threshold, with 0 < C_s < Z)
-                        if (__ballot(rowv && Z != kOne)) {
+                        if (!__ballot(rest != 0)) {
+                            // quarters before this one, the row total, and the
+                            // candidate where the running sum crosses the
+                            // threshold; a tie is a sum thr_lo < C <= thr_hi (the
+                            // band around it, with 0 < C < Z)
+                            const CT p1 = quadu<kQuadPrev1>(Zc), p2 = quadu<kQuadPrev2>(Zc),
+                                     p3 = quadu<kQuadPrev3>(Zc);
+                            const CT off = (cq >= 1 ? p1 : 0) + (cq >= 2 ? p2 : 0) + (cq >= 3 ? p3 : 0);
+                            const CT Z = quadu<kQuadLast>((CT)(off + Zc));
                             const uint64_t target = (uint64_t)u24 * Z;
                             const uint64_t band = (uint64_t)Z << 4;
                             const CT thr = (CT)(target >> 24);
@@ -368,20 +390,78 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                             const CT lo1 = thr_lo + 1;
                             const CT width = thr_hi >= lo1 ? thr_hi - thr_lo : 0;
                             CT C = off;
-                            int n_sel = 0, n_band = 0;
+                            int selx = 0x7fffffff, n_band = 0;
 #pragma unroll
-                            for (int j = 0; j < K; ++j) {
-                                C += ql[j];
-                                n_sel += C <= thr;
-                                n_band += (C - lo1) < width;
+                            for (int it = 0; it < S; ++it) {
+                                const CT Cp = C;
+                                C += qs[it];
+                                if (jx[it] >= 0 && Cp <= thr && C > thr) selx = jx[it];
+                                n_band += (jx[it] >= 0 && (C - lo1) < width) ? 1 : 0;
                             }
-                            n_sel += quad<kQuadXor1>(n_sel);
-                            n_sel += quad<kQuadXor2>(n_sel);
+                            selx = min(selx, quad<kQuadXor1>(selx));
+                            selx = min(selx, quad<kQuadXor2>(selx));
                             n_band += quad<kQuadXor1>(n_band);
                             n_band += quad<kQuadXor2>(n_band);
-                            if (Z != kOne) {
-                                sel = n_sel;
-                                tie = n_band > 0;
+                            sel = selx;
+                            tie = n_band > 0;
+                        } else {
+                            // more than S such candidates in some lane: every
+                            // candidate's weight, d = 0 -> 2^25; 0 < d < dthr ->
+                            // expf; d >= dthr -> 0
+                            uint32_t ql[K];
+                            uint32_t Zc = 0;
+                            int am = -1;
+#pragma unroll
+                            for (int j = 0; j < K; ++j) {
+                                const int32_t d = (j == js ? 0 : dl[j]) - mn;
+                                const bool zero = d == 0;
+                                uint32_t q = zero ? kOne : 0u;
+                                am = zero ? cq * K + j : am;
+                                const bool need = d < dthr && !zero;
+                                if (__ballot(need)) {
+                                    if (need) q = gibbs_weight(beta, (float)d);
+                                }
+                                if (!EXACT && cq * K + j >= N) q = 0;
+                                ql[j] = q;
+                                Zc += q;
+                            }
+                            // quarters before this one, and the row total
+                            const CT p1 = quadu<kQuadPrev1>(Zc), p2 = quadu<kQuadPrev2>(Zc),
+                                     p3 = quadu<kQuadPrev3>(Zc);
+                            const CT off = (cq >= 1 ? p1 : 0) + (cq >= 2 ? p2 : 0) + (cq >= 3 ? p3 : 0);
+                            const CT Z = quadu<kQuadLast>((CT)(off + Zc));
+                            am = max(am, quad<kQuadXor1>(am));
+                            am = max(am, quad<kQuadXor2>(am));
+                            sel = am;
+                            // a row whose only nonzero weight is its minimum (Z = 2^25)
+                            // picks the minimum; otherwise locate the threshold by
+                            // counting: the first s with C_s > thr is #{s : C_s <= thr},
+                            // and a tie is a boundary thr_lo < C_s <= thr_hi (the band
+                            // around the threshold, with 0 < C_s < Z)
+                            if (__ballot(rowv && Z != kOne)) {
+                                const uint64_t target = (uint64_t)u24 * Z;
+                                const uint64_t band = (uint64_t)Z << 4;
+                                const CT thr = (CT)(target >> 24);
+                                const CT thr_lo = target >= band ? (CT)((target - band) >> 24) : 0;
+                                const CT thr_hi = (CT)min((target + band) >> 24, (uint64_t)(Z - 1));
+                                const CT lo1 = thr_lo + 1;
+                                const CT width = thr_hi >= lo1 ? thr_hi - thr_lo : 0;
+                                CT C = off;
+                                int n_sel = 0, n_band = 0;
+#pragma unroll
+                                for (int j = 0; j < K; ++j) {
+                                    C += ql[j];
+                                    n_sel += C <= thr;
+                                    n_band += (C - lo1) < width;
+                                }
+                                n_sel += quad<kQuadXor1>(n_sel);
+                                n_sel += quad<kQuadXor2>(n_sel);
+                                n_band += quad<kQuadXor1>(n_band);
+                                n_band += quad<kQuadXor2>(n_band);
+                                if (Z != kOne) {
+                                    sel = n_sel;
+                                    tie = n_band > 0;
+                                }
                             }
                         }
                     }
