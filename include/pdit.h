@@ -89,7 +89,8 @@ typedef struct {
     int blocks_per_cu;    /* batched runs: resident workgroups per CU of the persistent
                              kernels (one replica each); 0 = as many as fit */
     int seq_threshold;    /* fast kernel: accepted moves in a sweep above which the next sweep
-                             runs one update at a time; < 0 = default (3) */
+                             runs one update at a time; < 0 = default: max(4, N/4) for
+                             N <= 128, 3 above */
 } pdit_opts;
 
 typedef struct {

@@ -484,8 +484,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
 
         // signature of the captured graph: the blob without the parameters,
         // the launch shapes and every buffer address the kernels receive
-        const int seq_thr = ctx->opts.seq_threshold < 0 ? pdit::kDefaultSeqThreshold
-                                                        : ctx->opts.seq_threshold;
+        const int seq_thr = ctx->opts.seq_threshold;  // < 0: each kernel's default
         std::vector<char> sig(blob.begin(), blob.begin() + off_params);
         auto push = [&](const void *p, size_t n) {
             sig.insert(sig.end(), (const char *)p, (const char *)p + n);
@@ -527,7 +526,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                 b.perm_best = S.perm_best;
                 b.counters = S.counters;
                 b.T = n_sweeps;
-                b.seq_threshold = seq_thr;
+                b.seq_threshold = seq_thr >= 0 ? seq_thr : pdit::default_seq_threshold(g.nmax, g.nmax);
                 cap = g.fast ? pdit::launch_sweep_fast_persistent(cs, g.nmax, g.zd, b, g.grid)
                              : pdit::launch_sweep_plain_persistent(cs, g.h64, b, g.grid);
             }
@@ -586,7 +585,7 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == PDIT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = PDIT_EDEVICE;
-    const int thresholds[3] = {1, 3, 8};
+    const int thresholds[3] = {3, 12, 40};
     for (int bpc = 1; bpc <= max_bpc && rc == PDIT_OK; ++bpc) {
         for (int ti = 0; ti < 3 && rc == PDIT_OK; ++ti) {
             for (int k = 0; k < n_inst; ++k)

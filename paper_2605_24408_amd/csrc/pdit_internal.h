@@ -122,7 +122,14 @@ struct SweepArgs {
 };
 
 constexpr int kFastNMax = 256;            // largest N of the on-chip kernel
-constexpr int kDefaultSeqThreshold = 3;   // swaps per sweep above which the next sweep is sequential
+// Accepted moves in a sweep above which the fast kernels run the next sweep
+// one update at a time.  On the table classes (N <= 128) a speculative pass
+// plus an accepted move costs about a tenth of a sequential sweep, so the
+// switch pays only for hot sweeps; the large classes switch early.
+inline int default_seq_threshold(int nmax, int N) {
+    if (nmax <= 128) return N / 4 > 4 ? N / 4 : 4;
+    return 3;
+}
 
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
 // size class of the on-chip kernel that runs an instance (16, 32, 64, 128,

@@ -600,7 +600,7 @@ int fast_class(int N, const InstanceStats &st) {
 
 hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a0) {
     SweepArgs a = a0;
-    if (a.seq_threshold < 0) a.seq_threshold = kDefaultSeqThreshold;
+    if (a.seq_threshold < 0) a.seq_threshold = default_seq_threshold(nmax, a.N);
     if (nmax <= 128) return launch_sweep_table(s, nmax, a);
     switch (nmax) {
         case 160: return launch_nmax<160>(s, a);

@@ -247,6 +247,51 @@ def test_large_size_classes(P, N, lo, hi, kind, cls):
         assert np.array_equal(got["choices"][k], ref.choices[k])
 
 
+@pytest.mark.parametrize("N,zd", [(40, True), (64, True), (64, False), (100, True)])
+def test_plateau_moves(P, N, zd):
+    """Two facilities with identical flows: exchanging them never changes the
+    energy, so cold replicas keep drawing between two zero-distance
+    candidates and accepting (the slowest replicas of an anneal).  Choices,
+    energies and states stay identical to the oracle's."""
+    rng = np.random.default_rng(N + (0 if zd else 1))
+    D, F = W.random_instance(rng, N, 0, 30, zero_diag=zd)
+    F[1, :] = F[0, :]
+    F[:, 1] = F[:, 0]
+    F[1, 1] = F[0, 0]
+    F[0, 1] = F[1, 0] = 7 if zd else F[0, 0]
+    assert (F == F.T).all()
+    R, T = 6, 120
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric(5.0 / s, 500.0 / s, T)
+    ref = oracle.run(D, F, perms, beta, 21, record_choices=True)
+    got = run_gpu(P, D, F, perms, beta, 21, sweep="fast", record=True)
+    assert ref.counters[:, 1].sum() > R * T // 8  # the plateau keeps accepting
+    assert len(compare_runs(got, ref)) == 0
+    for k in range(R):
+        assert np.array_equal(got["choices"][k], ref.choices[k])
+
+
+@pytest.mark.parametrize("N,scale", [(64, 2.0), (64, 20.0), (128, 5.0), (50, 10.0)])
+def test_constant_beta_many_candidates(P, N, scale):
+    """Constant beta at which rows have many candidates within the
+    zero-weight distance of their minimum (the weight pass's dense form) or a
+    few (its sparse form), schedules mixed by the accept threshold."""
+    rng = np.random.default_rng(N * 7 + int(scale))
+    D, F = W.random_instance(rng, N, 0, 40)
+    R, T = 6, 40
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = np.full(T, scale / s, np.float32)
+    ref = oracle.run(D, F, perms, beta, 5, record_choices=True)
+    for thr in (-1, 2, 1000):
+        got = run_gpu(P, D, F, perms, beta, 5, sweep="fast", record=True, seq_threshold=thr)
+        assert len(compare_runs(got, ref)) == 0
+        for k in range(R):
+            if ref.counters[k][2] == 0:
+                assert np.array_equal(got["choices"][k], ref.choices[k])
+
+
 @pytest.mark.parametrize("N", [24, 64, 128, 256])
 def test_beta_zero_uniform_choices(P, N):
     """beta = 0 gives every candidate weight 2^25: the largest CDF total
