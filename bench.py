@@ -32,12 +32,17 @@ METRIC = "p-dit updates/s + time-to-target gap; batched+int8 MFMA vs plain, 1 GP
 # int32 vector lane-ops per second of one MI355X: 256 CUs x 4 SIMD x 16 lanes
 # x 2.4 GHz (non-packed 32-bit integer VALU rate)
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
-# integer/float operations the method needs per candidate of an update: the
-# energy change (Eq. 3 in H form: 3 adds, shift, 2 x (add, add, shift),
-# multiply, add = 10), the minimum (1) and the weight sum (1)
-OPS_PER_CANDIDATE = 12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_fast_n64_counters.json")
-FAST_SRC = os.path.join(ROOT, "paper_2605_24408_amd", "csrc", "sweep_fast.hip")
+# integer operations of the table kernel's algorithm: an update reads and
+# compares its N candidates' energy changes (1 op each); an accepted move
+# updates the N x N table (2 subtractions and a multiply-add per entry), forms
+# the four H' vectors (4 N dot products of length N, 2 ops per term) and
+# rebuilds rows r and t (2 N entries, about 10 ops each)
+def ops_per_update(N: int, alpha: float) -> float:
+    return N + alpha * (11 * N * N + 20 * N)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_table_n64_counters.json")
+FAST_SRC = os.path.join(ROOT, "paper_2605_24408_amd", "csrc", "sweep_table.hip")
 
 
 def parse():
@@ -182,7 +187,7 @@ def main():
 
     # ---------------- roofline of the sweep kernel ----------------
     sweep_avg_ms = float(np.mean(sweep_ms))
-    ops_per_launch = (OPS_PER_CANDIDATE * N + 2 * alpha * N * N) * upd_per_step
+    ops_per_launch = ops_per_update(N, alpha) * upd_per_step
     achieved = ops_per_launch / (sweep_avg_ms * 1e-3)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -191,9 +196,10 @@ def main():
             traffic = rec.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved / ALU_PEAK_OPS, "traffic": traffic,
-                "kernel": "sweep_fast", "kernel_ms": sweep_avg_ms,
+                "kernel": "sweep_table_kernel<64, true, true, false>", "kernel_ms": sweep_avg_ms,
                 "recompute_ms": float(np.mean(rec_ms)),
-                "ops_per_update": OPS_PER_CANDIDATE * N + 2 * alpha * N * N}
+                "ops_per_update": ops_per_update(N, alpha),
+                "lds_bytes_per_update": 4 * N}
 
     # ---------------- plain path, target energy, time to target ----------------
     plain_rec = None
@@ -271,7 +277,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": "qap_n64_uniform99", "N": N, "replicas": R, "sweeps": T,
                       "beta": "geometric 0.001->1.0", "recompute": "int8 mfma",
-                      "sweep_kernel": "fast (H in LDS, speculative rows)",
+                      "sweep_kernel": "fast (table of swap energy changes in LDS, "
+                                      "speculative rows)",
                       "parallelism": "replicas"},
            "acceptance": alpha, "ties": cnt["ties"], "roofline": roofline,
            "plain": plain_rec, "time_to_target": ttt, "cpu_baseline": cpu}

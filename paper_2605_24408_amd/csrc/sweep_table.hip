@@ -285,6 +285,8 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         }
     };
 
+    uint32_t u4 = 0, u4_g = 0;  // cached uniforms (wave-uniform validity)
+    bool u4_valid = false;
     // beta and the zero-weight distance of 64 sweeps at a time, lane i
     // holding sweep t0 + i
     float bcache = 0.0f;
@@ -331,11 +333,21 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                     const bool stays = m >= dthr;
                     if (__ballot(rowv && !stays)) {
                         if (!have_u) {
-                            // kept inside the branch: the uniform is only
-                            // evaluated by passes that draw
-                            uint32_t row = (uint32_t)rr;
-                            asm volatile("" : "+v"(row));
-                            u24 = uniform24(a.seed, row, g, a.rep, a.inst);
+                            // the uniforms of four sweeps at a time: lane cq of
+                            // a quad holds sweep u4_g + cq of its row (kept
+                            // inside the branch: only passes that draw need them)
+                            if (!u4_valid || g - u4_g >= 4u) {
+                                uint32_t row = (uint32_t)rr;
+                                asm volatile("" : "+v"(row));
+                                u4 = uniform24(a.seed, row, g + (uint32_t)cq, a.rep, a.inst);
+                                u4_g = g;
+                                u4_valid = true;
+                            }
+                            const uint32_t k = g - u4_g;
+                            u24 = k == 0   ? quadu<0x00>(u4)
+                                  : k == 1 ? quadu<0x55>(u4)
+                                  : k == 2 ? quadu<0xAA>(u4)
+                                           : quadu<0xFF>(u4);
                             have_u = true;
                         }
                         const int js = rr - cq * K;  // this lane's slot of the stay, if any
