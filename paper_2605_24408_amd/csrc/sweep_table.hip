@@ -170,42 +170,50 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         E += dE;
         ++n_acc;
         {
+            // phase A: every LDS read first, then the arithmetic
             const int vec = tid / NMAX, x = tid % NMAX;  // one (vector, x) per thread
-            if (x < N) {
-                const int px = x == r ? t : x == t ? r : x;
-                const int urow = vec == 0 ? r : vec == 1 ? t : x;
-                const int frow = vec < 2 ? px : vec == 2 ? t : r;
-                const int16_t *pu = Ds + urow * PD;
-                const int16_t *pf = Fp + frow * PD;
-                int32_t acc = 0;
+            const int px = x == r ? t : x == t ? r : x;
+            const int urow = vec == 0 ? r : vec == 1 ? t : x;
+            const int frow = vec < 2 ? px : vec == 2 ? t : r;
+            const int16_t *pu = Ds + urow * PD;
+            const int16_t *pf = Fp + frow * PD;
+            uint4 xu[NMAX / 8], xf[NMAX / 8];
 #pragma unroll
-                for (int k = 0; k < NMAX; k += 8) {
-                    const uint4 xu = *reinterpret_cast<const uint4 *>(pu + k);
-                    const uint4 xf = *reinterpret_cast<const uint4 *>(pf + k);
-                    acc = dot2(xu.x, xf.x, acc);
-                    acc = dot2(xu.y, xf.y, acc);
-                    acc = dot2(xu.z, xf.z, acc);
-                    acc = dot2(xu.w, xf.w, acc);
-                }
-                const int32_t du = (int32_t)pu[t] - (int32_t)pu[r];
-                const int32_t df = (int32_t)pf[r] - (int32_t)pf[t];
-                const int32_t h = (int32_t)((uint32_t)acc + (uint32_t)du * (uint32_t)df);
+            for (int k = 0; k < NMAX / 8; ++k) {
+                xu[k] = *reinterpret_cast<const uint4 *>(pu + 8 * k);
+                xf[k] = *reinterpret_cast<const uint4 *>(pf + 8 * k);
+            }
+            const int32_t du = (int32_t)pu[t] - (int32_t)pu[r];
+            const int32_t df = (int32_t)pf[r] - (int32_t)pf[t];
+            const int32_t ax = (int32_t)Ds[x * PD + r] - (int32_t)Ds[x * PD + t];
+            const int32_t cx = (int32_t)Fp[x * PD + t] - (int32_t)Fp[x * PD + r];
+            const int32_t fsrc = Fp[(vec == 0 ? t : r) * PD + px];  // Fp'[r][x] or Fp'[t][x]
+            const int32_t fdg = ZD ? 0 : Fp[px * PD + px];        // Fp'[x][x]
+            const int32_t hdx = hd[x];
+            int32_t acc = 0;
+#pragma unroll
+            for (int k = 0; k < NMAX / 8; ++k) {
+                acc = dot2(xu[k].x, xf[k].x, acc);
+                acc = dot2(xu[k].y, xf[k].y, acc);
+                acc = dot2(xu[k].z, xf[k].z, acc);
+                acc = dot2(xu[k].w, xf[k].w, acc);
+            }
+            const int32_t h = (int32_t)((uint32_t)acc + (uint32_t)du * (uint32_t)df);
+            if (x < N) {
                 sm.hv[vec][x] = h;
                 if (vec == 0) {
-                    const int32_t ax = (int32_t)Ds[x * PD + r] - (int32_t)Ds[x * PD + t];
-                    const int32_t cx = (int32_t)Fp[x * PD + t] - (int32_t)Fp[x * PD + r];
                     av[x] = ax;
                     cv2[x] = 2 * cx;
-                    sm.fnew[0][x] = Fp[t * PD + px];
+                    sm.fnew[0][x] = fsrc;
                     if (x == r)
                         hd[x] = h;
                     else if (x != t)
-                        hd[x] = (int32_t)((uint32_t)hd[x] + (uint32_t)ax * (uint32_t)cx);
+                        hd[x] = (int32_t)((uint32_t)hdx + (uint32_t)ax * (uint32_t)cx);
                 } else if (vec == 1) {
-                    sm.fnew[1][x] = Fp[r * PD + px];
+                    sm.fnew[1][x] = fsrc;
                     if (x == t) hd[x] = h;
                 } else if (vec == 2 && !ZD) {
-                    sm.fdn[x] = Fp[px * PD + px];
+                    sm.fdn[x] = fdg;
                 }
             } else if (vec == 0) {
                 av[x] = 0;
@@ -217,14 +225,36 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         // Columns r and t from Eq. 3, written with their transposes (rows r and
         // t) by the owner of row l; T[r][t] = T[t][r] = -dE (the way back).
         if (rr < N && rr != r && rr != t) {
-            const int32_t al = av[rr], cl2 = cv2[rr];
-            int32_t *row = T + rr * PT + cq * K;
+            const int l = rr;
+            int32_t *row = T + l * PT + cq * K;
+            int4 xs[K / 4], as4[K / 4], cs4[K / 4];
 #pragma unroll
-            for (int j = 0; j < K; j += 4) {
-                int4 x = *reinterpret_cast<int4 *>(row + j);
-                const int4 as = *reinterpret_cast<const int4 *>(av + cq * K + j);
-                const int4 cs = *reinterpret_cast<const int4 *>(cv2 + cq * K + j);
-                const int s0 = cq * K + j;
+            for (int j = 0; j < K / 4; ++j) {
+                xs[j] = *reinterpret_cast<const int4 *>(row + 4 * j);
+                as4[j] = *reinterpret_cast<const int4 *>(av + cq * K + 4 * j);
+                cs4[j] = *reinterpret_cast<const int4 *>(cv2 + cq * K + 4 * j);
+            }
+            const int32_t al = av[l], cl2 = cv2[l];
+            // inputs of Eq. 3 for the entries (l, r) and (l, t)
+            const int32_t sr = (int32_t)((uint32_t)sm.hv[2][l] + (uint32_t)sm.hv[0][l]);
+            const int32_t st = (int32_t)((uint32_t)sm.hv[3][l] + (uint32_t)sm.hv[1][l]);
+            const int32_t hdl = hd[l], hdr = hd[r], hdt = hd[t];
+            const int32_t dlr = Ds[l * PD + r], dlt = Ds[l * PD + t];
+            const int32_t flr = sm.fnew[0][l], flt = sm.fnew[1][l];
+            int32_t dll = 0, drr = 0, dtt = 0, fll = 0, frr = 0, ftt = 0;
+            if (!ZD) {
+                dll = Ds[l * PD + l];
+                drr = Ds[r * PD + r];
+                dtt = Ds[t * PD + t];
+                fll = sm.fdn[l];
+                frr = sm.fdn[r];
+                ftt = sm.fdn[t];
+            }
+#pragma unroll
+            for (int j = 0; j < K / 4; ++j) {
+                int4 x = xs[j];
+                const int4 as = as4[j], cs = cs4[j];
+                const int s0 = cq * K + 4 * j;
                 const int32_t n0 = __mul24(as.x - al, cl2 - cs.x) + x.x;
                 const int32_t n1 = __mul24(as.y - al, cl2 - cs.y) + x.y;
                 const int32_t n2 = __mul24(as.z - al, cl2 - cs.z) + x.z;
@@ -233,22 +263,21 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
                 x.y = (EXACT || s0 + 1 < N) ? n1 : x.y;
                 x.z = (EXACT || s0 + 2 < N) ? n2 : x.z;
                 x.w = (EXACT || s0 + 3 < N) ? n3 : x.w;
-                *reinterpret_cast<int4 *>(row + j) = x;
+                *reinterpret_cast<int4 *>(row + 4 * j) = x;
             }
 #pragma unroll
             for (int wi = 0; wi < 2; ++wi) {
                 const int w = wi == 0 ? r : t;
                 if (w >= cq * K && w < cq * K + K) {
-                    const int l = rr;
-                    const uint32_t h = 2u * ((uint32_t)sm.hv[2 + wi][l] + (uint32_t)sm.hv[wi][l] -
-                                             (uint32_t)hd[l] - (uint32_t)hd[w]);
-                    const int32_t dlw = Ds[l * PD + w], flw = sm.fnew[wi][l];
+                    const uint32_t h = 2u * ((uint32_t)(wi == 0 ? sr : st) - (uint32_t)hdl -
+                                             (uint32_t)(wi == 0 ? hdr : hdt));
+                    const int32_t dlw = wi == 0 ? dlr : dlt, flw = wi == 0 ? flr : flt;
                     uint32_t corr;
                     if (ZD) {
                         corr = 4u * (uint32_t)(dlw * flw);
                     } else {
-                        const int32_t dd = (int32_t)Ds[l * PD + l] + (int32_t)Ds[w * PD + w] - 2 * dlw;
-                        const int32_t ff = sm.fdn[l] + sm.fdn[w] - 2 * flw;
+                        const int32_t dd = dll + (wi == 0 ? drr : dtt) - 2 * dlw;
+                        const int32_t ff = fll + (wi == 0 ? frr : ftt) - 2 * flw;
                         corr = (uint32_t)dd * (uint32_t)ff;
                     }
                     const int32_t v = (int32_t)(h + corr);
