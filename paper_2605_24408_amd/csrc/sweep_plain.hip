@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) sweep_plain_persistent(BatchArgs b) {
     for (;;) {
         if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
         __syncthreads();
-        const int item = item_sh;
+        const int item = __builtin_amdgcn_readfirstlane(item_sh);  // wave-uniform
         __syncthreads();
         if (item >= b.n_items) break;
         plain_replica<HT>(batch_job(b, item, sizeof(HT)), sm);

@@ -674,7 +674,7 @@ sweep_table_persistent(BatchArgs b) {
     for (;;) {
         if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
         __syncthreads();
-        const int item = item_sh;
+        const int item = __builtin_amdgcn_readfirstlane(item_sh);  // wave-uniform
         __syncthreads();
         if (item >= b.n_items) break;
         table_replica<NMAX, ZD, false, false>(batch_job(b, item, sizeof(int32_t)), sm);
