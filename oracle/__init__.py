@@ -70,6 +70,12 @@ def lib():
                              C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.po_brute_min.restype = C.c_int64
         L.po_brute_min.argtypes = [C.c_int, i32p, i32p, C.c_int, i32p]
+        L.po_pt_exchange.restype = C.c_int
+        L.po_pt_exchange.argtypes = [C.c_int, i64p, i32p, i32p, C.c_int32]
+        L.po_run_pt.restype = C.c_int
+        L.po_run_pt.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_int, i32p, f32p, i32p, i32p,
+                                C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
+                                C.c_int32, i64p, i64p, i32p, C.c_int, i64p]
         _lib = L
     return _lib
 
@@ -187,6 +193,57 @@ def run(D, F, perm, beta, seed, sweep_offset=0, rep_ids=None, inst_id=0, E_best=
     if rc != PO_OK:
         raise RuntimeError(f"oracle run failed with status {rc}")
     return RunResult(p, E, Eb, pb, counters, tie_log[: int(tie_n[0])].copy(), choices, trace)
+
+
+def pt_exchange(E, slot_of, since_top, timeout):
+    """One parallel-tempering exchange pass over a set (Methods, "CPU-PIM
+    Algorithm"); returns (slot_of, since_top, highest slot changed)."""
+    E = np.ascontiguousarray(E, dtype=np.int64)
+    sl = np.array(slot_of, dtype=np.int32, copy=True)
+    st = np.array([since_top], dtype=np.int32)
+    x = lib().po_pt_exchange(E.shape[0], E, sl, st, int(timeout))
+    if x < 0:
+        raise RuntimeError(f"oracle exchange failed with status {x}")
+    return sl, int(st[0]), bool(x)
+
+
+@dataclass
+class PTResult:
+    perm: np.ndarray
+    E: np.ndarray
+    E_best: np.ndarray
+    perm_best: np.ndarray
+    counters: np.ndarray          # [R, 3] totals
+    slot: np.ndarray              # [R] slot of each replica in its set
+    since_top: np.ndarray         # [R / L]
+
+
+def run_pt(D, F, perm, ladder, n_periods, period_sweeps, timeout, seed, sweep_offset=0,
+           slot=None, since_top=None, E_best=None, perm_best=None, inst_id=0) -> PTResult:
+    """Parallel tempering: sets of L = len(ladder) replicas (rows of perm in
+    order), n_periods periods of period_sweeps sweeps at each replica's slot
+    temperature, each followed by an exchange pass."""
+    D, F = _i32(D), _i32(F)
+    N = D.shape[0]
+    p = np.array(perm, dtype=np.int32, copy=True).reshape(-1, N)
+    R = p.shape[0]
+    ladder = np.ascontiguousarray(ladder, dtype=np.float32)
+    L = ladder.shape[0]
+    sl = (np.tile(np.arange(L, dtype=np.int32), R // L) if slot is None
+          else np.array(slot, dtype=np.int32, copy=True))
+    st = np.zeros(R // L, dtype=np.int32) if since_top is None else np.array(since_top, dtype=np.int32, copy=True)
+    E = np.zeros(R, dtype=np.int64)
+    init_best = E_best is None
+    Eb = np.zeros(R, dtype=np.int64) if init_best else np.array(E_best, dtype=np.int64, copy=True)
+    pb = (np.zeros((R, N), dtype=np.int32) if init_best
+          else np.array(perm_best, dtype=np.int32, copy=True).reshape(R, N))
+    counters = np.zeros((R, 3), dtype=np.int64)
+    rc = lib().po_run_pt(N, D, F, R, L, p, ladder, sl, st, int(n_periods), int(period_sweeps),
+                         int(timeout), int(seed), int(sweep_offset), int(inst_id), E, Eb, pb,
+                         int(init_best), counters)
+    if rc != PO_OK:
+        raise RuntimeError(f"oracle parallel tempering failed with status {rc}")
+    return PTResult(p, E, Eb, pb, counters, sl, st)
 
 
 def brute_min(D, F, first=-1) -> tuple[int, np.ndarray]:

@@ -343,6 +343,106 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
+/* Parallel tempering (Results, "Implementation"; Methods, "CPU-PIM      */
+/* Algorithm").  A set holds L replicas at L inverse temperatures, slot */
+/* 0 the lowest.  After every period of sweeps the slots are visited    */
+/* from the lowest beta up: when the replica in slot i+1 has an energy  */
+/* greater than or equal to the one in slot i, the two configurations   */
+/* change places, so a low-energy configuration can travel to the       */
+/* highest beta in one pass.  If the highest slot has not changed hands */
+/* for `timeout` passes, it changes places with the lowest slot.        */
+/* Configurations changing places is represented by the two replicas    */
+/* exchanging slots; each replica keeps its own random stream.          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One exchange pass over a set.  E[k]: energy of replica k of the set;
+ * slot_of[k] in/out: its slot; since_top in/out: passes since the highest
+ * slot last changed hands (timeout <= 0: never forced).  Returns 1 when the
+ * highest slot changed hands.
+ */
+int po_pt_exchange(int L, const int64_t *E, int32_t *slot_of, int32_t *since_top, int32_t timeout)
+{
+    if (L < 1 || L > 4096 || !E || !slot_of || !since_top) return PO_EINVAL;
+    int32_t who[4096];
+    for (int i = 0; i < L; ++i) who[i] = -1;
+    for (int k = 0; k < L; ++k) {
+        if (slot_of[k] < 0 || slot_of[k] >= L || who[slot_of[k]] >= 0) return PO_EINVAL;
+        who[slot_of[k]] = k;
+    }
+    int top = 0;
+    for (int i = 0; i + 1 < L; ++i) {
+        const int32_t lo = who[i], hi = who[i + 1];
+        if (E[hi] >= E[lo]) {
+            who[i] = hi;
+            who[i + 1] = lo;
+            if (i + 1 == L - 1) top = 1;
+        }
+    }
+    if (top) {
+        *since_top = 0;
+    } else if (timeout > 0 && ++*since_top >= timeout) {
+        const int32_t w = who[L - 1];
+        who[L - 1] = who[0];
+        who[0] = w;
+        *since_top = 0;
+        top = L > 1;
+    }
+    for (int i = 0; i < L; ++i) slot_of[who[i]] = i;
+    return top;
+}
+
+/*
+ * n_periods periods of `period_sweeps` sweeps, each followed by an exchange
+ * pass in every set; replica k (set k / L) runs its sweeps at
+ * ladder[slot_of[k]].  The arguments are those of po_run, plus:
+ *   L          replicas per set (R a multiple of L)
+ *   ladder     [L] inverse temperatures of the slots, lowest first
+ *   slot_of    [R] in/out: slot of each replica within its set
+ *   since_top  [R/L] in/out: exchange passes since the set's highest slot
+ *              last changed hands
+ *   counters   [R*3] out: totals over all periods
+ */
+int po_run_pt(int N, const int32_t *D, const int32_t *F, int R, int L, int32_t *perm,
+              const float *ladder, int32_t *slot_of, int32_t *since_top, int64_t n_periods,
+              int64_t period_sweeps, int32_t timeout, uint64_t seed, uint64_t sweep_off,
+              int32_t inst_id, int64_t *E, int64_t *E_best, int32_t *perm_best, int init_best,
+              int64_t *counters)
+{
+    if (N < 2 || R < 1 || L < 1 || R % L || n_periods < 0 || period_sweeps < 0 || !ladder ||
+        !slot_of || !since_top || !E || !E_best || !perm_best || !counters)
+        return PO_EINVAL;
+    float *b = (float *)malloc(sizeof(float) * (size_t)(period_sweeps > 0 ? period_sweeps : 1));
+    if (!b) return PO_ENOMEM;
+    int rc = PO_OK;
+    memset(counters, 0, sizeof(int64_t) * 3 * (size_t)R);
+    for (int64_t per = 0; per < n_periods && rc == PO_OK; ++per) {
+        for (int k = 0; k < R && rc == PO_OK; ++k) {
+            const int32_t sl = slot_of[k];
+            if (sl < 0 || sl >= L) {
+                rc = PO_EINVAL;
+                break;
+            }
+            for (int64_t t = 0; t < period_sweeps; ++t) b[t] = ladder[sl];
+            int64_t cnt[3];
+            const int32_t rep = k;
+            rc = po_run(N, D, F, 1, &rep, inst_id, perm + (int64_t)k * N, b, period_sweeps, seed,
+                        sweep_off + (uint64_t)(per * period_sweeps), E + k, E_best + k,
+                        perm_best + (int64_t)k * N, init_best && per == 0, cnt, NULL, 0, NULL,
+                        NULL, NULL, 0);
+            for (int c = 0; c < 3; ++c) counters[3 * k + c] += cnt[c];
+        }
+        for (int s = 0; s < R / L && rc == PO_OK; ++s) {
+            const int x = po_pt_exchange(L, E + (int64_t)s * L, slot_of + (int64_t)s * L,
+                                         since_top + s, timeout);
+            if (x < 0) rc = x;
+        }
+    }
+    free(b);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Exhaustive minimum of Eq. 1 (small N): all permutations with p[0] =  */
 /* first (or all of them when first < 0), enumerated by Heap's method. */
 /* ------------------------------------------------------------------ */
