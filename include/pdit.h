@@ -162,6 +162,39 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
 int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst,
                           int64_t n_sweeps, uint64_t seed);
 
+/* Parallel tempering (pdit_run_pt). */
+#define PDIT_PT_MAXL 64     /* largest number of replicas per set */
+typedef struct {
+    int32_t L;              /* replicas per set, 1..PDIT_PT_MAXL: rows k L .. k L + L - 1 of
+                               perm form set k */
+    const float *beta;      /* device float L: inverse temperature of each rung, ascending
+                               (rung 0 is the hottest), finite and >= 0 */
+    int32_t *slot;          /* device int32 R, in/out: rung of each replica in its set; each
+                               set's values a permutation of 0..L-1 (PDIT_EINVAL otherwise) */
+    int32_t *since_top;     /* device int32 R / L, in/out: exchange passes since the set's top
+                               rung last changed hands (start at 0) */
+    int64_t period_sweeps;  /* sweeps between exchange passes (4 in the paper) */
+    int32_t timeout;        /* passes without the top rung changing hands after which it trades
+                               with the bottom rung (100 in the paper); <= 0: never */
+} pdit_pt;
+
+/*
+ * Parallel tempering (Results, "Implementation"; Methods, "CPU-PIM
+ * Algorithm"): n_periods periods, each of period_sweeps sweeps on every
+ * replica at beta[slot[k]], followed by one exchange pass per set.  The pass
+ * visits the rungs from the lowest beta up; when the replica on rung i+1 has
+ * an energy greater than or equal to the replica on rung i, their
+ * configurations change rungs (slot values are exchanged; states and random
+ * streams stay with the replicas).  When the top rung has not changed hands
+ * for `timeout` passes it trades with the bottom rung.  Replica k draws from
+ * its own Philox stream (counter word 2 = k); sweep offset, best state and
+ * counters (totals of the call) behave as in pdit_run_sweeps, with
+ * n_periods x period_sweeps sweeps.  Each replica's on-chip state carries
+ * from one period to the next.  Recording is not available.
+ */
+int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                int32_t *perm, const pdit_pt *pt, int64_t n_periods, uint64_t seed);
+
 /* Result of pdit_autotune. */
 typedef struct {
     int blocks_per_cu;    /* chosen resident workgroups per CU */

@@ -90,11 +90,15 @@ int shape_state(pdit_t *ctx, const std::vector<int32_t> &Ns, const std::vector<i
 
 // Reads the instance summary (one host synchronisation) and validates.
 int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
-                  const int32_t *perm, const float *beta, int64_t T, InstanceStats *st) {
+                  const int32_t *perm, const float *beta, int64_t T, InstanceStats *st,
+                  const pdit_pt *pt = nullptr) {
     int rc = ensure(ctx, ctx->scratch, sizeof(InstanceStats));
     if (rc) return rc;
     InstanceStats *dev = (InstanceStats *)ctx->scratch.ptr;
     PDIT_HIP(ctx, pdit::launch_instance_stats(ctx->stream, N, D, F, R, perm, beta, T, dev));
+    if (pt)
+        PDIT_HIP(ctx, pdit::launch_pt_check(ctx->stream, R / pt->L, pt->L, pt->slot,
+                                            pt->since_top, dev));
     PDIT_HIP(ctx, hipMemcpyAsync(ctx->stats_host, dev, sizeof(InstanceStats),
                                  hipMemcpyDeviceToHost, ctx->stream));
     PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -103,6 +107,10 @@ int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
     if (st->bad_perm_rows)
         return fail(ctx, PDIT_EBADPERM, "a row of perm is not a permutation of 0..N-1");
     if (st->bad_beta) return fail(ctx, PDIT_EBETA, "an inverse temperature is NaN, infinite or negative");
+    if (st->bad_slots)
+        return fail(ctx, PDIT_EINVAL,
+                    "the slots of a parallel-tempering set are not a permutation of 0..L-1, or its "
+                    "pass counter is negative");
     // |H| <= bound, |dE| <= 8 bound + 16 max|D| max|F| must stay far inside int64
     const __int128 b1 = (__int128)st->max_abs_d * st->max_colsum_f;
     const __int128 b2 = (__int128)st->max_abs_f * st->max_rowsum_d;
@@ -210,6 +218,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipStreamSynchronize(ctx->stream);
     free_state(ctx->st);
     hipFree(ctx->h_buf.ptr);
+    hipFree(ctx->tstate.ptr);
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
@@ -307,6 +316,109 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->rec_trace = nullptr;
     ctx->sweep_offset += (uint64_t)n_sweeps;
     ctx->last_updates = (int64_t)R * N * n_sweeps;
+    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
+    ctx->last_class = use_fast ? fclass : 0;
+    ctx->last_mode = mode;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
+int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                int32_t *perm, const pdit_pt *pt, int64_t n_periods, uint64_t seed) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!D || !F || !perm || !pt || !pt->beta || !pt->slot || !pt->since_top)
+        return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
+    if (pt->L < 1 || pt->L > PDIT_PT_MAXL)
+        return fail(ctx, PDIT_EINVAL, "L must be in [1, PDIT_PT_MAXL]");
+    if (R < 1 || R % pt->L) return fail(ctx, PDIT_EINVAL, "R must be a positive multiple of L");
+    if (n_periods < 0 || pt->period_sweeps < 0)
+        return fail(ctx, PDIT_EINVAL, "n_periods and period_sweeps must be >= 0");
+    if (ctx->rec_choices || ctx->rec_trace)
+        return fail(ctx, PDIT_EINVAL, "recording is not available for parallel tempering");
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+
+    InstanceStats st;
+    int rc = instance_prep(ctx, N, D, F, R, perm, pt->beta, pt->L, &st, pt);
+    if (rc) return rc;
+    const int64_t bound = pdit::h_bound(st);
+    const bool h64 = bound > INT32_MAX;
+    const int fclass = pdit::fast_class(N, st);
+    bool use_fast = false;
+    if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
+        if (!fclass)
+            return fail(ctx, PDIT_EOVERFLOW, "the data do not fit the fast sweep kernel");
+        use_fast = true;
+    } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
+        use_fast = fclass != 0;
+    }
+    const bool table = use_fast && fclass <= 128;
+    int mode = 0;
+    rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
+    if (rc) return rc;
+    rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
+    if (rc) return rc;
+    if (table) {
+        rc = ensure(ctx, ctx->tstate, sizeof(int32_t) * (size_t)R * pdit::table_state_words(fclass));
+        if (rc) return rc;
+    }
+    bool fresh = false;
+    rc = shape_state(ctx, {N}, {R}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
+    if (fresh) {
+        PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * R, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+        PDIT_HIP(ctx, hipMemcpyAsync(S.perm_best, perm, sizeof(int32_t) * (size_t)R * N,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    pdit::SweepArgs a{};
+    a.N = N;
+    a.R = R;
+    a.D = D;
+    a.F = F;
+    a.perm = perm;
+    a.H = ctx->h_buf.ptr;
+    a.E = S.E;
+    a.E_best = S.E_best;
+    a.perm_best = S.perm_best;
+    a.counters = S.counters;
+    a.beta = pt->beta;
+    a.slot = pt->slot;
+    a.T = pt->period_sweeps;
+    a.seed = seed;
+    a.inst_id = 0;
+    a.seq_threshold = ctx->opts.seq_threshold;
+    a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
+    a.tstate = table ? (int32_t *)ctx->tstate.ptr : nullptr;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    if (pt->period_sweeps == 0 || n_periods == 0)
+        PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * R, ctx->stream));
+    // each period: the sweeps of every replica at its rung's beta (resuming
+    // from the state the previous period saved), then one exchange pass per set
+    for (int64_t per = 0; per < n_periods; ++per) {
+        if (pt->period_sweeps > 0) {
+            a.sweep_offset = ctx->sweep_offset + (uint64_t)(per * pt->period_sweeps);
+            a.flags = pdit::kSaveState | (per > 0 ? pdit::kLoadState | pdit::kAccumCounters : 0u);
+            if (use_fast)
+                PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
+            else
+                PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
+        }
+        PDIT_HIP(ctx, pdit::launch_pt_exchange(ctx->stream, R / pt->L, pt->L, S.E, pt->slot,
+                                               pt->since_top, pt->timeout));
+    }
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->timed = true;
+    ctx->sweep_offset += (uint64_t)(n_periods * pt->period_sweeps);
+    ctx->last_updates = (int64_t)R * N * n_periods * pt->period_sweeps;
     ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;

@@ -24,6 +24,8 @@ struct InstanceStats {
     int32_t bad_beta;       // beta values that are NaN, infinite or negative
     int32_t diag_nz_d;      // nonzero diagonal entries of D
     int32_t diag_nz_f;      // nonzero diagonal entries of F
+    int32_t bad_slots;      // parallel tempering: sets whose slots are not a permutation of
+                            // 0..L-1, or whose pass counter is negative
 };
 
 // Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=
@@ -67,6 +69,7 @@ struct pdit_ctx {
     std::string last_error;
     pdit::ReplicaState st;
     pdit::DeviceBuffer h_buf;         // H of all replicas (int32 or int64)
+    pdit::DeviceBuffer tstate;        // table-kernel states between parallel-tempering periods
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
     pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
     int32_t *err_dev = nullptr;       // deferred device error word
@@ -87,6 +90,13 @@ struct pdit_ctx {
 namespace pdit {
 
 // ---- launchers (each returns a hipError_t) --------------------------------
+// Parallel tempering: slot validation (into out->bad_slots) and the exchange
+// pass of every set after a period.
+constexpr int kPtMaxL = 64;
+hipError_t launch_pt_check(hipStream_t s, int n_sets, int L, const int32_t *slot,
+                           const int32_t *since_top, InstanceStats *out);
+hipError_t launch_pt_exchange(hipStream_t s, int n_sets, int L, const int64_t *E, int32_t *slot,
+                              int32_t *since_top, int32_t timeout);
 hipError_t launch_instance_stats(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                                  int R, const int32_t *perm, const float *beta, int64_t T,
                                  InstanceStats *out_dev);
@@ -119,7 +129,20 @@ struct SweepArgs {
     int64_t *E_trace;        // optional [R][T]
     int seq_threshold;
     bool zero_diag;          // D and F have zero diagonals
+    // parallel tempering: replica k runs every sweep of the launch at
+    // beta[slot[k]] (null: the schedule beta[t])
+    const int32_t *slot;
+    int32_t *tstate;         // table kernel: [R][table_state_words(N)] replica state between launches
+    uint32_t flags;          // kLoadState | kSaveState | kAccumCounters
 };
+
+// Launch flags of the sweep kernels (parallel-tempering periods).
+constexpr uint32_t kLoadState = 1;      // resume from the saved state (table kernel: tstate)
+constexpr uint32_t kSaveState = 2;      // save the state at the end (table: tstate; H kernels: H)
+constexpr uint32_t kAccumCounters = 4;  // add to the counters instead of overwriting them
+// int32 words of one replica's saved table state: the table (NMAX x (NMAX+4))
+// and diag H (NMAX) of its size class
+__host__ __device__ inline int64_t table_state_words(int nmax) { return (int64_t)nmax * (nmax + 4) + nmax; }
 
 constexpr int kFastNMax = 256;            // largest N of the on-chip kernel
 // Accepted moves in a sweep above which the fast kernels run the next sweep

@@ -19,6 +19,7 @@ __global__ void zero_stats_kernel(InstanceStats *s) {
         s->bad_beta = 0;
         s->diag_nz_d = 0;
         s->diag_nz_f = 0;
+        s->bad_slots = 0;
     }
 }
 
@@ -88,7 +89,32 @@ __global__ void beta_check_kernel(int64_t T, const float *__restrict__ beta, Ins
     if (bad) atomicAdd(&s->bad_beta, bad);
 }
 
+// One thread per parallel-tempering set: its L slots are distinct values in
+// [0, L) and its pass counter is not negative.
+__global__ void pt_check_kernel(int n_sets, int L, const int32_t *__restrict__ slot,
+                                const int32_t *__restrict__ since_top, InstanceStats *s) {
+    const int set = blockIdx.x * blockDim.x + threadIdx.x;
+    if (set >= n_sets) return;
+    uint64_t seen = 0;
+    bool bad = since_top[set] < 0;
+    for (int k = 0; k < L; ++k) {
+        const int32_t v = slot[(int64_t)set * L + k];
+        if (v < 0 || v >= L || ((seen >> v) & 1))
+            bad = true;
+        else
+            seen |= 1ull << v;
+    }
+    if (bad) atomicAdd(&s->bad_slots, 1);
+}
+
 }  // namespace
+
+hipError_t launch_pt_check(hipStream_t st, int n_sets, int L, const int32_t *slot,
+                           const int32_t *since_top, InstanceStats *out) {
+    if (L < 1 || L > kPtMaxL) return hipErrorInvalidValue;
+    pt_check_kernel<<<(n_sets + 255) / 256, 256, 0, st>>>(n_sets, L, slot, since_top, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_instance_stats(hipStream_t st, int N, const int32_t *D, const int32_t *F,
                                  int R, const int32_t *perm, const float *beta, int64_t T,

@@ -20,7 +20,8 @@ struct ReplicaJob {
     int64_t *E_best;         // in/out
     int32_t *perm_best;      // [N] in/out
     int64_t *counters;       // [3] out: updates, accepted, ties
-    const float *beta;       // [T]
+    const float *beta;       // beta of sweep t is beta[t * beta_stride]
+    int64_t beta_stride;     // 1: a schedule; 0: one beta for every sweep
     int64_t T;
     uint64_t seed;
     uint64_t sweep_offset;
@@ -30,7 +31,17 @@ struct ReplicaJob {
     int64_t *E_trace;        // [T] or null
     int seq_threshold;
     bool zero_diag;
+    int32_t *tstate;         // table kernel: this replica's saved state, or null
+    uint32_t flags;          // kLoadState | kSaveState | kAccumCounters
 };
+
+// Beta of the replica's sweeps: beta[slot[rep]] for every sweep when a slot
+// array is given, else the schedule.
+__device__ __forceinline__ void job_beta(ReplicaJob &j, const float *beta, const int32_t *slot,
+                                         int64_t rep) {
+    j.beta = slot ? beta + slot[rep] : beta;
+    j.beta_stride = slot ? 0 : 1;
+}
 
 // One instance of a batched run (device memory).
 struct BatchInstance {
@@ -84,6 +95,7 @@ __device__ __forceinline__ ReplicaJob batch_job(const BatchArgs &b, int item, si
     j.perm_best = b.perm_best + in.perm_off + r * in.N;
     j.counters = b.counters + 3 * (in.rep_base + r);
     j.beta = in.beta;
+    j.beta_stride = 1;
     j.T = b.T;
     j.seed = b.params->seed;
     j.sweep_offset = b.params->sweep_offset;
@@ -93,6 +105,8 @@ __device__ __forceinline__ ReplicaJob batch_job(const BatchArgs &b, int item, si
     j.E_trace = nullptr;
     j.seq_threshold = b.seq_threshold;
     j.zero_diag = in.zero_diag != 0;
+    j.tstate = nullptr;
+    j.flags = 0;
     return j;
 }
 

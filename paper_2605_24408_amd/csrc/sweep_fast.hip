@@ -236,7 +236,7 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
     };
 
     for (int64_t t = 0; t < a.T; ++t) {
-        const float beta = a.beta[t];
+        const float beta = a.beta[t * a.beta_stride];
         const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
         const int32_t dthr = zero_weight_distance(beta);
         const int64_t acc_before = n_acc;
@@ -468,6 +468,15 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         if (a.E_trace && tid == 0) a.E_trace[t] = E;
     }
 
+    if (a.flags & kSaveState) {
+        // H of the final state back to device memory (the next launch resumes from it)
+        __syncthreads();
+        int32_t *Hout = (int32_t *)const_cast<void *>(a.H);
+        for (int e = tid; e < N * N; e += 64 * WPR) {
+            const int i = e / N, k = e % N;
+            Hout[e] = (int32_t)Hs[i * P + k] / 2;
+        }
+    }
     if (wv == 0) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
@@ -475,9 +484,10 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         if (lane == 0) {
             *a.E = E;
             *a.E_best = E_best;
-            a.counters[0] = (int64_t)N * a.T;
-            a.counters[1] = n_acc;
-            a.counters[2] = n_tie;
+            const bool acc = (a.flags & kAccumCounters) != 0;
+            a.counters[0] = (acc ? a.counters[0] : 0) + (int64_t)N * a.T;
+            a.counters[1] = (acc ? a.counters[1] : 0) + n_acc;
+            a.counters[2] = (acc ? a.counters[2] : 0) + n_tie;
         }
     }
 }
@@ -512,7 +522,7 @@ sweep_fast_kernel(SweepArgs a) {
     j.E_best = a.E_best + rep;
     j.perm_best = a.perm_best + rep * a.N;
     j.counters = a.counters + 3 * rep;
-    j.beta = a.beta;
+    job_beta(j, a.beta, a.slot, rep);
     j.T = a.T;
     j.seed = a.seed;
     j.sweep_offset = a.sweep_offset;
@@ -522,6 +532,8 @@ sweep_fast_kernel(SweepArgs a) {
     j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
     j.seq_threshold = a.seq_threshold;
     j.zero_diag = ZD;
+    j.tstate = nullptr;
+    j.flags = a.flags;
     fast_replica<NMAX, ZD, EXACT, fast_large<NMAX>(), FastH<NMAX>>(j, sm);
 }
 

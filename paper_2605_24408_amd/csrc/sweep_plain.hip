@@ -61,7 +61,7 @@ __device__ void plain_replica(const ReplicaJob &a, PlainSmem &sm) {
     __syncthreads();
 
     for (int64_t t = 0; t < a.T; ++t) {
-        const float beta = a.beta[t];
+        const float beta = a.beta[t * a.beta_stride];
         const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
         const int32_t dthr = zero_weight_distance(beta);
         for (int r = 0; r < N; ++r) {
@@ -151,9 +151,10 @@ __device__ void plain_replica(const ReplicaJob &a, PlainSmem &sm) {
     if (tid == 0) {
         *a.E = E;
         *a.E_best = E_best;
-        a.counters[0] = (int64_t)N * a.T;
-        a.counters[1] = n_acc;
-        a.counters[2] = n_tie;
+        const bool acc = (a.flags & kAccumCounters) != 0;
+        a.counters[0] = (acc ? a.counters[0] : 0) + (int64_t)N * a.T;
+        a.counters[1] = (acc ? a.counters[1] : 0) + n_acc;
+        a.counters[2] = (acc ? a.counters[2] : 0) + n_tie;
     }
 }
 
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
     j.E_best = a.E_best + rep;
     j.perm_best = a.perm_best + rep * a.N;
     j.counters = a.counters + 3 * rep;
-    j.beta = a.beta;
+    job_beta(j, a.beta, a.slot, rep);
     j.T = a.T;
     j.seed = a.seed;
     j.sweep_offset = a.sweep_offset;
@@ -181,6 +182,8 @@ __global__ void __launch_bounds__(kBlock) sweep_plain_kernel(SweepArgs a) {
     j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
     j.seq_threshold = a.seq_threshold;
     j.zero_diag = a.zero_diag;
+    j.tstate = nullptr;
+    j.flags = a.flags;
     plain_replica<HT>(j, sm);
 }
 

@@ -132,22 +132,33 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         const int i = e / PD, k = e % PD;
         Ds[e] = (int16_t)((i < N && k < N) ? a.D[(int64_t)i * N + k] : 0);
     }
+    // a resumed replica (parallel-tempering periods) reloads its table and
+    // diag H; otherwise both come from the recomputed H
+    const bool resume = (a.flags & kLoadState) && a.tstate;
     const int32_t *Hg = (const int32_t *)a.H;
-    for (int e = tid; e < NMAX; e += NT) hd[e] = e < N ? Hg[(int64_t)e * N + e] : 0;
+    if (resume) {
+        for (int e = tid; e < NMAX * PT / 4; e += NT)
+            reinterpret_cast<int4 *>(T)[e] = reinterpret_cast<const int4 *>(a.tstate)[e];
+        for (int e = tid; e < NMAX; e += NT) hd[e] = a.tstate[NMAX * PT + e];
+    } else {
+        for (int e = tid; e < NMAX; e += NT) hd[e] = e < N ? Hg[(int64_t)e * N + e] : 0;
+    }
     __syncthreads();
     for (int e = tid; e < NMAX * PD; e += NT) {
         const int i = e / PD, k = e % PD;
         Fp[e] = (int16_t)((i < N && k < N) ? a.F[(int64_t)pv[i] * N + pv[k]] : 0);
     }
     __syncthreads();
-    for (int e = tid; e < NMAX * PT; e += NT) {
-        const int l = e / PT, s = e % PT;
-        int32_t v = kBig;
-        if (l < N && s < N && l != s)
-            v = eq3(l, s, Hg[(int64_t)l * N + s], Hg[(int64_t)s * N + l], hd[l], hd[s]);
-        T[e] = v;
+    if (!resume) {
+        for (int e = tid; e < NMAX * PT; e += NT) {
+            const int l = e / PT, s = e % PT;
+            int32_t v = kBig;
+            if (l < N && s < N && l != s)
+                v = eq3(l, s, Hg[(int64_t)l * N + s], Hg[(int64_t)s * N + l], hd[l], hd[s]);
+            T[e] = v;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     int64_t E = *a.E;
     int64_t E_best = *a.E_best;
@@ -324,7 +335,7 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         const int slot = (int)(t & 63);
         if (slot == 0) {
             const int64_t tt = t + lane < a.T ? t + lane : a.T - 1;
-            bcache = a.beta[tt];
+            bcache = a.beta[tt * a.beta_stride];
             dcache = zero_weight_distance(bcache);
         }
         const float beta = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bcache), slot));
@@ -606,6 +617,11 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
 
     if (lane == 0) sm.tie_sum[wv] = n_tie;
     __syncthreads();
+    if ((a.flags & kSaveState) && a.tstate) {
+        for (int e = tid; e < NMAX * PT / 4; e += NT)
+            reinterpret_cast<int4 *>(a.tstate)[e] = reinterpret_cast<const int4 *>(T)[e];
+        for (int e = tid; e < NMAX; e += NT) a.tstate[NMAX * PT + e] = hd[e];
+    }
     if (wv == 0) {
         if (lane == 0) {
 #pragma unroll
@@ -617,9 +633,10 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         if (lane == 0) {
             *a.E = E;
             *a.E_best = E_best;
-            a.counters[0] = (int64_t)N * a.T;
-            a.counters[1] = n_acc;
-            a.counters[2] = n_tie;
+            const bool acc = (a.flags & kAccumCounters) != 0;
+            a.counters[0] = (acc ? a.counters[0] : 0) + (int64_t)N * a.T;
+            a.counters[1] = (acc ? a.counters[1] : 0) + n_acc;
+            a.counters[2] = (acc ? a.counters[2] : 0) + n_tie;
         }
     }
 }
@@ -648,7 +665,7 @@ sweep_table_kernel(SweepArgs a) {
     j.E_best = a.E_best + rep;
     j.perm_best = a.perm_best + rep * a.N;
     j.counters = a.counters + 3 * rep;
-    j.beta = a.beta;
+    job_beta(j, a.beta, a.slot, rep);
     j.T = a.T;
     j.seed = a.seed;
     j.sweep_offset = a.sweep_offset;
@@ -658,6 +675,8 @@ sweep_table_kernel(SweepArgs a) {
     j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
     j.seq_threshold = a.seq_threshold;
     j.zero_diag = ZD;
+    j.tstate = a.tstate ? a.tstate + rep * table_state_words(NMAX) : nullptr;
+    j.flags = a.flags;
     table_replica<NMAX, ZD, EXACT, REC>(j, sm);
 }
 

@@ -50,6 +50,11 @@ class _Instance(C.Structure):
                 ("perm", C.c_void_p), ("beta", C.c_void_p)]
 
 
+class _PT(C.Structure):
+    _fields_ = [("L", C.c_int32), ("beta", C.c_void_p), ("slot", C.c_void_p),
+                ("since_top", C.c_void_p), ("period_sweeps", C.c_int64), ("timeout", C.c_int32)]
+
+
 _lib = None
 
 EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps",
@@ -57,7 +62,7 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_replica_counters", "pdit_set_sweep_offset", "pdit_get_sweep_offset",
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
-           "pdit_last_timing", "pdit_autotune", "pdit_last_plan"]
+           "pdit_last_timing", "pdit_autotune", "pdit_last_plan", "pdit_run_pt"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -77,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     L.pdit_destroy.argtypes = [vp]
     L.pdit_run_sweeps.argtypes = [vp, i32, vp, vp, i32, vp, vp, i64, u64]
     L.pdit_run_sweeps_batch.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64]
+    L.pdit_run_pt.argtypes = [vp, i32, vp, vp, i32, vp, C.POINTER(_PT), i64, u64]
     L.pdit_energy.argtypes = [vp, vp]
     L.pdit_best.argtypes = [vp, vp, vp]
     L.pdit_counters.argtypes = [vp, C.POINTER(_Counters)]
@@ -204,6 +210,23 @@ class Pdit:
             arr[k] = _Instance(N, int(perm.shape[0]), D.data_ptr(), F.data_ptr(), perm.data_ptr(),
                                beta.data_ptr())
         return arr, (T if n_sweeps is None else n_sweeps)
+
+    def run_pt(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor, beta: torch.Tensor,
+               slot: torch.Tensor, since_top: torch.Tensor, n_periods: int, period_sweeps: int,
+               timeout: int, seed: int) -> None:
+        """pdit_run_pt: parallel tempering over sets of L = len(beta) rows of
+        perm (slot, since_top and perm in/out)."""
+        N = int(D.shape[0])
+        for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"), (perm, torch.int32, "perm"),
+                          (beta, torch.float32, "beta"), (slot, torch.int32, "slot"),
+                          (since_top, torch.int32, "since_top")):
+            _check_dev(t, dt, nm, self.device)
+        R = int(perm.shape[0])
+        pt = _PT(int(beta.shape[0]), _ptr(beta), _ptr(slot), _ptr(since_top), int(period_sweeps),
+                 int(timeout))
+        self._rc(self._L.pdit_run_pt(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), C.byref(pt),
+                                     int(n_periods), int(seed)))
+        self._last = (R, R * N, N)
 
     def run_sweeps_batch(self, instances, seed: int) -> None:
         """pdit_run_sweeps_batch over (D, F, perm, beta) tensors of uneven N."""

@@ -1,0 +1,138 @@
+"""Parallel tempering on the GPU (pdit_run_pt) against the oracle's
+run_pt: every sweep kernel, resume across calls, forced top-bottom trades,
+exchange-only periods and the error paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_24408_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def gpu_pt(ctx, D, F, perms, ladder, periods, per_sweeps, timeout, seed, slot=None, since=None):
+    L = len(ladder)
+    R = perms.shape[0]
+    p = dev(perms, torch.int32)
+    sl = dev(np.tile(np.arange(L), R // L) if slot is None else slot, torch.int32)
+    st = dev(np.zeros(R // L) if since is None else since, torch.int32)
+    ctx.run_pt(dev(D, torch.int32), dev(F, torch.int32), p, dev(ladder, torch.float32), sl, st,
+               periods, per_sweeps, timeout, seed)
+    E_best, perm_best = ctx.best()
+    return {"perm": p.cpu().numpy(), "E": ctx.energy().cpu().numpy(),
+            "E_best": E_best.cpu().numpy(), "perm_best": perm_best.cpu().numpy(),
+            "counters": ctx.replica_counters().cpu().numpy(), "slot": sl.cpu().numpy(),
+            "since_top": st.cpu().numpy()}
+
+
+def compare(got, ref, L):
+    """Set by set: every replica and the set's ladder state equal the
+    oracle's, unless the oracle counted a tie in that set (a tie can swap a
+    choice, and the exchange then carries the difference to the whole set).
+    Returns the sets that differ."""
+    R = ref.perm.shape[0]
+    differ = []
+    for g in range(R // L):
+        rows = range(g * L, (g + 1) * L)
+        same = all(np.array_equal(got["perm"][k], ref.perm[k]) and got["E"][k] == ref.E[k]
+                   and got["E_best"][k] == ref.E_best[k]
+                   and np.array_equal(got["perm_best"][k], ref.perm_best[k])
+                   and np.array_equal(got["counters"][k][:2], ref.counters[k][:2]) for k in rows)
+        same = same and np.array_equal(got["slot"][g * L:(g + 1) * L], ref.slot[g * L:(g + 1) * L])
+        same = same and got["since_top"][g] == ref.since_top[g]
+        if not same:
+            assert ref.counters[g * L:(g + 1) * L, 2].sum() > 0, (
+                f"set {g} differs from the oracle without a counted tie: "
+                f"slots {got['slot'][g * L:(g + 1) * L]} vs {ref.slot[g * L:(g + 1) * L]}")
+            differ.append(g)
+    return differ
+
+
+@pytest.mark.parametrize("N,L,sets,sweep,kind", [
+    (12, 4, 3, "fast", "grid"), (16, 4, 2, "fast", "uniform"), (40, 5, 2, "fast", "uniform"),
+    (128, 4, 1, "fast", "uniform"), (64, 10, 2, "fast", "uniform"),
+    (64, 6, 2, "fast", "diag"), (140, 4, 2, "fast", "uniform"), (33, 5, 2, "plain", "uniform")])
+def test_pt_matches_oracle(N, L, sets, sweep, kind):
+    from paper_2605_24408_amd import pdit as P
+    say(f"pt N={N} L={L} sets={sets} sweep={sweep} kind={kind}")
+    rng = np.random.default_rng(N * 3 + L)
+    if kind == "grid":
+        inst = W.config_n12(R=L * sets, T=1)
+        D, F = inst.D, inst.F
+    else:
+        D, F = W.random_instance(rng, N, 0, 40, zero_diag=(kind != "diag"))
+    perms = W.random_perms(rng, L * sets, N)
+    s = W.energy_scale(D, F)
+    ladder = W.beta_geometric(0.5 / s, 60.0 / s, L)
+    periods, per, timeout = 12, 4, 3
+    ref = oracle.run_pt(D, F, perms, ladder, periods, per, timeout, 17)
+    with P.Pdit(sweep=sweep) as ctx:
+        got = gpu_pt(ctx, D, F, perms, ladder, periods, per, timeout, 17)
+        plan = ctx.last_plan()
+    assert plan["sweep"] == sweep
+    differ = compare(got, ref, L)
+    assert sets == 1 or len(differ) < sets
+    assert ref.counters[:, 1].sum() > 0
+
+
+def test_pt_resume_equals_single_call():
+    from paper_2605_24408_amd import pdit as P
+    rng = np.random.default_rng(5)
+    N, L = 48, 6
+    D, F = W.random_instance(rng, N, 0, 30)
+    perms = W.random_perms(rng, 2 * L, N)
+    s = W.energy_scale(D, F)
+    ladder = W.beta_geometric(1.0 / s, 40.0 / s, L)
+    with P.Pdit() as ctx:
+        one = gpu_pt(ctx, D, F, perms, ladder, 10, 4, 2, 3)
+    with P.Pdit() as ctx:
+        a = gpu_pt(ctx, D, F, perms, ladder, 6, 4, 2, 3)
+        b = gpu_pt(ctx, D, F, a["perm"], ladder, 4, 4, 2, 3, slot=a["slot"], since=a["since_top"])
+    for f in ("perm", "E", "E_best", "perm_best", "slot", "since_top"):
+        assert np.array_equal(one[f], b[f]), f
+
+
+def test_pt_exchange_only_periods():
+    """period_sweeps = 0: the passes act on the recomputed energies alone."""
+    from paper_2605_24408_amd import pdit as P
+    rng = np.random.default_rng(9)
+    N, L = 20, 8
+    D, F = W.random_instance(rng, N, 0, 9)
+    perms = W.random_perms(rng, 3 * L, N)
+    ladder = np.linspace(0.1, 0.8, L).astype(np.float32)
+    ref = oracle.run_pt(D, F, perms, ladder, 7, 0, 2, 1)
+    with P.Pdit() as ctx:
+        got = gpu_pt(ctx, D, F, perms, ladder, 7, 0, 2, 1)
+    assert np.array_equal(got["slot"], ref.slot) and np.array_equal(got["since_top"], ref.since_top)
+    assert np.array_equal(got["perm"], perms)
+
+
+def test_pt_error_paths():
+    from paper_2605_24408_amd import pdit as P
+    rng = np.random.default_rng(2)
+    N, L = 16, 4
+    D, F = W.random_instance(rng, N, 0, 9)
+    perms = W.random_perms(rng, 2 * L, N)
+    ladder = np.linspace(0.1, 1.0, L).astype(np.float32)
+    with P.Pdit() as ctx:
+        for slot, why in ((np.array([0, 1, 2, 2, 0, 1, 2, 3]), "repeated rung"),
+                          (np.array([0, 1, 2, 4, 0, 1, 2, 3]), "rung out of range")):
+            with pytest.raises(P.PditError) as e:
+                gpu_pt(ctx, D, F, perms, ladder, 1, 1, 5, 1, slot=slot)
+            assert e.value.status == "PDIT_EINVAL", why
+        with pytest.raises(P.PditError) as e:
+            gpu_pt(ctx, D, F, perms[:7], ladder, 1, 1, 5, 1, slot=np.arange(7) % L)
+        assert e.value.status == "PDIT_EINVAL"
+        with pytest.raises(P.PditError) as e:
+            gpu_pt(ctx, D, F, perms, np.array([0.1, -1.0, 0.2, 0.3], np.float32), 1, 1, 5, 1)
+        assert e.value.status == "PDIT_EBETA"
