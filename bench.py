@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-replicas", type=int, default=32)
-    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512"],
+    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512", "pt"],
                     help="n64 is the benchmark configuration; the others report the same "
                          "fast-vs-plain comparison for the other workload shapes")
     ap.add_argument("--sweeps", type=int, default=0,
@@ -122,6 +122,114 @@ def other_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def pt_workload(args):
+    """Parallel tempering against annealing on the N=64 instance: 102 ladders
+    of 10 rungs (1020 replicas), 4-sweep periods, a 100-period timeout, the
+    same total sweeps as the annealing schedule. One JSON line with the
+    update rates, the best energies and the time each method needs to reach
+    the other's final best; not the benchmark figure."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit
+    from paper_2605_24408_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    L, sets, period, timeout = 10, 102, 4, 100
+    R = L * sets
+    inst = W.config_n64(R=R)
+    T = args.sweeps or inst.T
+    N = inst.N
+    n_periods = T // period
+    chunks = 10
+    D = torch.from_numpy(inst.D).to(dev)
+    F = torch.from_numpy(inst.F).to(dev)
+    perm0 = torch.from_numpy(inst.perms).to(dev)
+    beta = torch.from_numpy(inst.beta[:T].copy()).to(dev)
+    ladder = torch.from_numpy(W.beta_geometric(1e-3, 1.0, L)).to(dev)
+    seed = W.PHILOX_SEED
+    perm = perm0.clone()
+    slot = torch.empty(R, dtype=torch.int32, device=dev)
+    since = torch.empty(sets, dtype=torch.int32, device=dev)
+
+    def run_pt(ctx, record, schedule="fused"):
+        perm.copy_(perm0)
+        slot.copy_(torch.arange(L, dtype=torch.int32, device=dev).repeat(sets))
+        since.zero_()
+        ctx.set_sweep_offset(0)
+        ctx.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        curve = []
+        per_chunk = (n_periods + chunks - 1) // chunks if record else n_periods
+        done = 0
+        while done < n_periods:
+            k = min(per_chunk, n_periods - done)
+            ctx.run_pt(D, F, perm, ladder, slot, since, k, period, timeout, seed, schedule)
+            done += k
+            if record:
+                e, _ = ctx.best()
+                v = int(e.min())  # synchronises before the clock is read
+                curve.append((done * period, time.perf_counter() - t0, v))
+        e, _ = ctx.best()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e.cpu().numpy(), curve
+
+    def run_anneal(ctx, record):
+        perm.copy_(perm0)
+        ctx.set_sweep_offset(0)
+        ctx.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        curve = []
+        step = (T + chunks - 1) // chunks if record else T
+        done = 0
+        while done < T:
+            k = min(step, T - done)
+            ctx.run_sweeps(D, F, perm, beta[done:done + k].contiguous(), seed)
+            done += k
+            if record:
+                e, _ = ctx.best()
+                v = int(e.min())
+                curve.append((done, time.perf_counter() - t0, v))
+        e, _ = ctx.best()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e.cpu().numpy(), curve
+
+    out = {"workload": "qap_n64_uniform99_parallel_tempering", "N": N, "replicas": R,
+           "ladders": sets, "rungs": L, "ladder": "geometric 0.001->1.0",
+           "period_sweeps": period, "timeout_periods": timeout, "sweeps": T}
+    ctx = pdit.Pdit(sweep="fast", recompute="i8")
+    run_pt(ctx, False)
+    t_pt, eb_pt, _ = run_pt(ctx, False)
+    _, _, c_pt = run_pt(ctx, True)
+    cnt = ctx.counters()
+    run_pt(ctx, False, "periodic")
+    t_per, eb_per, _ = run_pt(ctx, False, "periodic")
+    run_anneal(ctx, False)
+    t_an, eb_an, _ = run_anneal(ctx, False)
+    _, _, c_an = run_anneal(ctx, True)
+    ctx.close()
+    upd = R * N * n_periods * period
+
+    def reach(curve, target):
+        hit = [c for c in curve if c[2] <= target]
+        return None if not hit else {"sweeps": hit[0][0], "seconds": hit[0][1]}
+
+    ladder_best = eb_pt.reshape(sets, L).min(axis=1)
+    out["pt"] = {"updates_per_s": upd / t_pt, "seconds": t_pt, "best": int(eb_pt.min()),
+                 "mean_ladder_best": float(ladder_best.mean()),
+                 "acceptance": cnt["accepted"] / max(cnt["updates"], 1),
+                 "curve": c_pt, "reaches_anneal_best": reach(c_pt, int(eb_an.min())),
+                 "schedule": "fused (one cooperative launch, sets meet on the device)",
+                 "periodic_schedule": {"updates_per_s": upd / t_per, "seconds": t_per,
+                                       "identical_best": bool(np.array_equal(eb_per, eb_pt))}}
+    out["anneal"] = {"updates_per_s": R * N * T / t_an, "seconds": t_an, "best": int(eb_an.min()),
+                     "mean_best": float(eb_an.mean()),
+                     "curve": c_an, "reaches_pt_best": reach(c_an, int(eb_pt.min()))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,6 +237,9 @@ def main():
               "workload are independent chains and the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "pt":
+        pt_workload(args)
+        return
     if args.workload != "n64":
         other_workload(args)
         return

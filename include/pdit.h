@@ -176,7 +176,24 @@ typedef struct {
     int64_t period_sweeps;  /* sweeps between exchange passes (4 in the paper) */
     int32_t timeout;        /* passes without the top rung changing hands after which it trades
                                with the bottom rung (100 in the paper); <= 0: never */
+    int32_t schedule;       /* PDIT_PT_AUTO, PDIT_PT_PERIODIC or PDIT_PT_FUSED (below) */
 } pdit_pt;
+
+/* How pdit_run_pt launches its work; every schedule gives the same results.
+ *   PERIODIC  one sweep launch per period (each replica's state saved and
+ *             reloaded between them) and one exchange launch per period.
+ *   FUSED     N <= 128 and data that fit the fast kernel (PDIT_SWEEP_FAST):
+ *             every period in one cooperative launch per group of whole sets
+ *             that are resident at once; the members of a set meet on the
+ *             device after each period and run the pass themselves.  A
+ *             meeting that does not complete within max(20 s, 1000 times the
+ *             waiting member's period) ends the call with PDIT_EDEVICE (the
+ *             outputs are then undefined); with resident members it cannot
+ *             happen.  Ends with a host synchronisation.
+ *   AUTO      FUSED where it applies, else PERIODIC. */
+#define PDIT_PT_AUTO 0
+#define PDIT_PT_PERIODIC 1
+#define PDIT_PT_FUSED 2
 
 /*
  * Parallel tempering (Results, "Implementation"; Methods, "CPU-PIM

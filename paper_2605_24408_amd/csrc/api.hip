@@ -198,13 +198,18 @@ int pdit_create(pdit_t **out, const pdit_opts *opts) {
     }
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess ||
         hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount,
+                              ctx->opts.device) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->coop, hipDeviceAttributeCooperativeLaunch, ctx->opts.device) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&ctx->wall_clock_khz, hipDeviceAttributeWallClockRate,
                               ctx->opts.device) != hipSuccess) {
         pdit_destroy(ctx);
         return PDIT_EDEVICE;
     }
     if (hipHostMalloc((void **)&ctx->stats_host, sizeof(InstanceStats), hipHostMallocDefault) !=
             hipSuccess ||
-        hipMalloc((void **)&ctx->err_dev, sizeof(int32_t)) != hipSuccess) {
+        hipMalloc((void **)&ctx->err_dev, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->flag_host, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         pdit_destroy(ctx);
         return PDIT_ENOMEM;
     }
@@ -219,6 +224,7 @@ int pdit_destroy(pdit_t *ctx) {
     free_state(ctx->st);
     hipFree(ctx->h_buf.ptr);
     hipFree(ctx->tstate.ptr);
+    hipFree(ctx->pt_buf.ptr);
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
@@ -227,6 +233,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->batch_buf.ptr);
     if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
     if (ctx->stats_host) hipHostFree(ctx->stats_host);
+    if (ctx->flag_host) hipHostFree(ctx->flag_host);
     delete ctx;
     return PDIT_OK;
 }
@@ -335,6 +342,8 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     if (R < 1 || R % pt->L) return fail(ctx, PDIT_EINVAL, "R must be a positive multiple of L");
     if (n_periods < 0 || pt->period_sweeps < 0)
         return fail(ctx, PDIT_EINVAL, "n_periods and period_sweeps must be >= 0");
+    if (pt->schedule < PDIT_PT_AUTO || pt->schedule > PDIT_PT_FUSED)
+        return fail(ctx, PDIT_EINVAL, "unknown parallel-tempering schedule");
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for parallel tempering");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
@@ -356,12 +365,24 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
         use_fast = fclass != 0;
     }
     const bool table = use_fast && fclass <= 128;
+    // fused: the table kernel, cooperative launches, energies inside the
+    // published word (|E| <= N max|H| < 2^35; the table classes imply it)
+    const bool can_fuse = table && ctx->coop && ctx->wall_clock_khz > 0 &&
+                          (int64_t)N * bound < ((int64_t)1 << (pdit::kPtEBits - 1));
+    if (pt->schedule == PDIT_PT_FUSED && !can_fuse)
+        return fail(ctx, PDIT_EINVAL,
+                    "the fused schedule needs N <= 128, data that fit the fast kernel and a "
+                    "device with cooperative launches");
+    const bool fused = can_fuse && pt->schedule != PDIT_PT_PERIODIC && n_periods > 0;
     int mode = 0;
     rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
     if (rc) return rc;
     rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
     if (rc) return rc;
-    if (table) {
+    if (fused) {
+        rc = ensure(ctx, ctx->pt_buf, sizeof(uint64_t) * 2 * (size_t)R + sizeof(int32_t));
+        if (rc) return rc;
+    } else if (table) {
         rc = ensure(ctx, ctx->tstate, sizeof(int32_t) * (size_t)R * pdit::table_state_words(fclass));
         if (rc) return rc;
     }
@@ -399,11 +420,36 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     a.tstate = table ? (int32_t *)ctx->tstate.ptr : nullptr;
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
-    if (pt->period_sweeps == 0 || n_periods == 0)
+    if (!fused && (pt->period_sweeps == 0 || n_periods == 0))
         PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * R, ctx->stream));
+    if (fused) {
+        // every period in one launch per group of resident sets
+        uint64_t *Epub = (uint64_t *)ctx->pt_buf.ptr;
+        int32_t *err = (int32_t *)(Epub + 2 * (size_t)R);
+        PDIT_HIP(ctx, hipMemsetAsync(Epub, 0, sizeof(uint64_t) * 2 * (size_t)R + sizeof(int32_t),
+                                     ctx->stream));
+        pdit::PtFusedArgs p{};
+        p.L = pt->L;
+        p.ladder = pt->beta;
+        p.slot = pt->slot;
+        p.since_top = pt->since_top;
+        p.n_periods = n_periods;
+        p.period_sweeps = pt->period_sweeps;
+        p.timeout = pt->timeout;
+        p.Epub = Epub;
+        p.err = err;
+        p.R = R;
+        p.min_wait = (uint64_t)ctx->wall_clock_khz * 1000u * 20u;
+        a.sweep_offset = ctx->sweep_offset;
+        a.flags = 0;
+        a.tstate = nullptr;
+        PDIT_HIP(ctx, pdit::launch_sweep_table_pt(ctx->stream, fclass, a, p, ctx->num_cus));
+        PDIT_HIP(ctx, hipMemcpyAsync(ctx->flag_host, err, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     ctx->stream));
+    }
     // each period: the sweeps of every replica at its rung's beta (resuming
     // from the state the previous period saved), then one exchange pass per set
-    for (int64_t per = 0; per < n_periods; ++per) {
+    for (int64_t per = 0; per < n_periods && !fused; ++per) {
         if (pt->period_sweeps > 0) {
             a.sweep_offset = ctx->sweep_offset + (uint64_t)(per * pt->period_sweeps);
             a.flags = pdit::kSaveState | (per > 0 ? pdit::kLoadState | pdit::kAccumCounters : 0u);
@@ -417,6 +463,13 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     }
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
     ctx->timed = true;
+    if (fused) {
+        PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (*ctx->flag_host)
+            return fail(ctx, PDIT_EDEVICE,
+                        "a parallel-tempering set did not meet within the wait bound (members "
+                        "not resident together); the outputs are undefined");
+    }
     ctx->sweep_offset += (uint64_t)(n_periods * pt->period_sweeps);
     ctx->last_updates = (int64_t)R * N * n_periods * pt->period_sweeps;
     ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;

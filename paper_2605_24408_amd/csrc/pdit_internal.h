@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/pdit.h"
+#include "pt_common.h"
 #include "sweep_common.h"
 
 namespace pdit {
@@ -70,9 +71,13 @@ struct pdit_ctx {
     pdit::ReplicaState st;
     pdit::DeviceBuffer h_buf;         // H of all replicas (int32 or int64)
     pdit::DeviceBuffer tstate;        // table-kernel states between parallel-tempering periods
+    pdit::DeviceBuffer pt_buf;        // fused parallel tempering: published energies, arrivals
+    int coop = 0;                     // the device supports cooperative launches
+    int wall_clock_khz = 0;
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
     pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
     int32_t *err_dev = nullptr;       // deferred device error word
+    int32_t *flag_host = nullptr;     // pinned: fused parallel tempering's wait flag
     int32_t *rec_choices = nullptr;   // recording buffers for the next run
     int64_t *rec_trace = nullptr;
     int64_t last_updates = 0;
@@ -92,7 +97,6 @@ namespace pdit {
 // ---- launchers (each returns a hipError_t) --------------------------------
 // Parallel tempering: slot validation (into out->bad_slots) and the exchange
 // pass of every set after a period.
-constexpr int kPtMaxL = 64;
 hipError_t launch_pt_check(hipStream_t s, int n_sets, int L, const int32_t *slot,
                            const int32_t *since_top, InstanceStats *out);
 hipError_t launch_pt_exchange(hipStream_t s, int n_sets, int L, const int64_t *E, int32_t *slot,
@@ -167,6 +171,10 @@ hipError_t launch_sweep_table(hipStream_t s, int nmax, const SweepArgs &a);
 hipError_t launch_sweep_table_persistent(hipStream_t s, int nmax, bool zero_diag, const BatchArgs &b,
                                          int grid);
 int table_blocks_per_cu(int nmax);
+// fused parallel tempering on the table classes: cooperative launches of as
+// many whole sets as are resident at once
+hipError_t launch_sweep_table_pt(hipStream_t s, int nmax, const SweepArgs &a, const PtFusedArgs &p,
+                                 int num_cus);
 hipError_t launch_sweep_plain_persistent(hipStream_t s, bool h64, const BatchArgs &b, int grid);
 hipError_t launch_queue_reset(hipStream_t s, int *queue, int n);
 int plain_blocks_per_cu(bool h64);

@@ -1,54 +1,34 @@
-// pt.hip -- parallel tempering: the exchange pass between sweep periods
-// (Results, "Implementation"; Methods, "CPU-PIM Algorithm").
-//
-// A set holds L replicas (rows set*L .. set*L+L-1 of the batch) on an
-// ascending ladder of inverse temperatures; slot[k] is the rung replica k
-// sits on.  After each period of sweeps the rungs are visited from the
-// lowest beta up: when the replica on rung i+1 has an energy greater than or
-// equal to the one on rung i, the two configurations change rungs, so a
-// low-energy configuration can climb the whole ladder in one pass.  If the
-// top rung has not changed hands for `timeout` passes it trades with the
-// bottom rung.  Replicas keep their states and random streams; only the
-// rung assignment moves.
+// pt.hip -- parallel tempering: the stand-alone exchange pass between sweep
+// periods, for the kernels that run one period per launch (the pass itself
+// is in pt_common.h).
 #include "pdit_internal.h"
 
 namespace pdit {
 namespace {
 
-// One thread per set (L <= kPtMaxL; the slots were validated as a
-// permutation of 0..L-1 and the kernel keeps them one).
-__global__ void pt_exchange_kernel(int n_sets, int L, const int64_t *__restrict__ E,
-                                   int32_t *__restrict__ slot, int32_t *__restrict__ since_top,
-                                   int32_t timeout) {
-    const int set = blockIdx.x * blockDim.x + threadIdx.x;
-    if (set >= n_sets) return;
+// One wave per set (L <= kPtMaxL; the slots were validated as a permutation
+// of 0..L-1 and the pass keeps them one): lanes load the set's slots and
+// energies together, lane 0 runs the pass on LDS, lanes write the new slots.
+__global__ void __launch_bounds__(64)
+pt_exchange_kernel(int n_sets, int L, const int64_t *__restrict__ E, int32_t *__restrict__ slot,
+                   int32_t *__restrict__ since_top, int32_t timeout) {
+    __shared__ int64_t Es[kPtMaxL];
+    __shared__ int32_t who[kPtMaxL];
+    const int set = blockIdx.x;
+    const int k = threadIdx.x;
     const int64_t base = (int64_t)set * L;
-    int32_t who[kPtMaxL];  // replica (within the set) on each rung
-    for (int i = 0; i < L; ++i) who[i] = i;
-    for (int k = 0; k < L; ++k) {
-        const int32_t v = slot[base + k];
-        if (v >= 0 && v < L) who[v] = k;
+    if (k < L) {
+        Es[k] = E[base + k];
+        who[slot[base + k]] = k;
     }
-    bool top = false;
-    for (int i = 0; i + 1 < L; ++i) {
-        const int32_t lo = who[i], hi = who[i + 1];
-        if (E[base + hi] >= E[base + lo]) {
-            who[i] = hi;
-            who[i + 1] = lo;
-            if (i + 1 == L - 1) top = true;
-        }
+    __syncthreads();
+    if (k == 0) {
+        int32_t c = since_top[set];
+        pt_pass(L, Es, who, c, timeout);
+        since_top[set] = c;
     }
-    int32_t c = since_top[set];
-    if (top) {
-        c = 0;
-    } else if (timeout > 0 && ++c >= timeout) {
-        const int32_t w = who[L - 1];
-        who[L - 1] = who[0];
-        who[0] = w;
-        c = 0;
-    }
-    since_top[set] = c;
-    for (int i = 0; i < L; ++i) slot[base + who[i]] = i;
+    __syncthreads();
+    if (k < L) slot[base + who[k]] = k;
 }
 
 }  // namespace
@@ -56,7 +36,8 @@ __global__ void pt_exchange_kernel(int n_sets, int L, const int64_t *__restrict_
 hipError_t launch_pt_exchange(hipStream_t s, int n_sets, int L, const int64_t *E, int32_t *slot,
                               int32_t *since_top, int32_t timeout) {
     if (L < 1 || L > kPtMaxL) return hipErrorInvalidValue;
-    pt_exchange_kernel<<<(n_sets + 63) / 64, 64, 0, s>>>(n_sets, L, E, slot, since_top, timeout);
+    if (n_sets < 1) return hipSuccess;
+    pt_exchange_kernel<<<n_sets, 64, 0, s>>>(n_sets, L, E, slot, since_top, timeout);
     return hipGetLastError();
 }
 

@@ -84,10 +84,27 @@ struct TableSmem {
     int64_t tie_sum[NMAX / 16];
 };
 
+// Per-workgroup state of fused parallel tempering: the set's energies and
+// rung assignment (identical in every member), this replica's rung.
+struct PtSmem {
+    int64_t E[kPtMaxL];      // energy of each member at the end of the period
+    int32_t who[kPtMaxL];    // member on each rung
+    int32_t rung;            // this replica's rung
+    int32_t since;           // passes since the top rung changed hands
+    int32_t abort;           // a wait exceeded its bound
+    uint64_t tper;           // wall clock at the start of the period
+};
+
 // Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).  REC:
-// the job records choices and/or the energy trace.
-template <int NMAX, bool ZD, bool EXACT, bool REC>
-__device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMAX> &sm) {
+// the job records choices and/or the energy trace.  PTF: fused parallel
+// tempering -- pf->n_periods periods of pf->period_sweeps sweeps at the
+// beta of the replica's rung, each followed by a meeting of the set's
+// members and the exchange pass (replica `rep` is member rep % L of set
+// rep / L).
+template <int NMAX, bool ZD, bool EXACT, bool REC, bool PTF = false>
+__device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMAX> &sm,
+                                              const PtFusedArgs *pf = nullptr,
+                                              PtSmem *ps = nullptr, int64_t rep = 0) {
     constexpr int WPR = NMAX / 16;         // waves per replica
     constexpr int NT = 64 * WPR;           // threads: 4 NMAX
     constexpr int K = NMAX / 4;            // candidates per lane in a speculative pass
@@ -127,6 +144,19 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
     };
 
     // ---- stage p, D, F[p,p], diag(H) and the table (zero / kBig outside N) ----
+    if (PTF) {
+        // the set's rung assignment and pass counter, read before this
+        // replica's first arrival (no member writes them before the last)
+        const int L = pf->L;
+        const int64_t set = rep / L;
+        if (tid < L) ps->who[pf->slot[set * L + tid]] = tid;
+        if (tid == 0) {
+            ps->since = pf->since_top[set];
+            ps->rung = pf->slot[rep];
+            ps->abort = 0;
+            ps->tper = wall_clock64();
+        }
+    }
     for (int e = tid; e < NMAX; e += NT) pv[e] = e < N ? a.perm[e] : 0;
     for (int e = tid; e < NMAX * PD; e += NT) {
         const int i = e / PD, k = e % PD;
@@ -331,16 +361,26 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
     // holding sweep t0 + i
     float bcache = 0.0f;
     int32_t dcache = 0;
-    for (int64_t t = 0; t < a.T; ++t) {
+    const int64_t n_per = PTF ? pf->n_periods : 1;
+    const int64_t T_per = PTF ? pf->period_sweeps : a.T;
+    const float *bsrc = a.beta;
+    int64_t bstride = a.beta_stride;
+    uint64_t t_done = 0;  // sweeps of the earlier periods
+    for (int64_t per = 0; per < n_per; ++per, t_done += (uint64_t)T_per) {
+    if (PTF) {
+        bsrc = pf->ladder + __builtin_amdgcn_readfirstlane(ps->rung);
+        bstride = 0;
+    }
+    for (int64_t t = 0; t < T_per; ++t) {
         const int slot = (int)(t & 63);
         if (slot == 0) {
-            const int64_t tt = t + lane < a.T ? t + lane : a.T - 1;
-            bcache = a.beta[tt * a.beta_stride];
+            const int64_t tt = t + lane < T_per ? t + lane : T_per - 1;
+            bcache = bsrc[tt * bstride];
             dcache = zero_weight_distance(bcache);
         }
         const float beta = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bcache), slot));
         const int32_t dthr = __builtin_amdgcn_readlane(dcache, slot);
-        const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
+        const uint32_t g = (uint32_t)(a.sweep_offset + t_done + (uint64_t)t);
         const int64_t acc_before = n_acc;
         int32_t *ch = (REC && a.choices) ? a.choices + t * N : nullptr;
 
@@ -614,6 +654,67 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         seq_mode = (n_acc - acc_before) > a.seq_threshold;
         if (REC && a.E_trace && tid == 0) a.E_trace[t] = E;
     }
+    if (PTF) {
+        // ---- meet the set's other members, then the exchange pass ----
+        // Each member publishes one 64-bit word, the period number (28
+        // bits) over its energy (36 bits, two's complement; the table
+        // classes bound |E| below 2^35), with a device-scope store, and
+        // reads its set's words until every tag is this period's.  One
+        // atomic word carries both the value and its validity, so no
+        // cache-wide release or acquire is needed.  Words alternate between
+        // two buffers by period parity: a member can be at most one period
+        // ahead of the slowest reader of its set.
+        const int L = pf->L;
+        const int64_t set = rep / L;
+        const int32_t m = (int32_t)(rep - set * L);
+        uint64_t *pub = pf->Epub + (per & 1) * pf->R;
+        if (wv == 0) {
+            const uint64_t tag = (uint64_t)(per + 1) & kPtTagMask;
+            const uint64_t mine = (tag << kPtEBits) | ((uint64_t)E & kPtEMask);
+            if (lane == 0) __hip_atomic_store(pub + rep, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // every wait ends: the members are resident together and each
+            // publishes after its own sweeps; the bound (1000 times this
+            // member's period, at least pf->min_wait ticks) only guards
+            // against a launch that broke that premise, and once one member
+            // gave up every other waiter stops at its next poll
+            const uint64_t w0 = wall_clock64();
+            const uint64_t own = w0 - ps->tper;
+            const uint64_t bound = own * 1000 > pf->min_wait ? own * 1000 : pf->min_wait;
+            uint64_t w = mine;
+            bool ready = lane >= L || lane == m;
+            int32_t ab = 0;
+            for (;;) {
+                if (!ready) {
+                    w = __hip_atomic_load(pub + set * L + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ready = (w >> kPtEBits) == tag;
+                }
+                if (__ballot(!ready) == 0) break;
+                __builtin_amdgcn_s_sleep(2);
+                const int32_t e = __hip_atomic_load(pf->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (__builtin_amdgcn_readfirstlane(e) != 0 || wall_clock64() - w0 > bound) {
+                    ab = 1;
+                    break;
+                }
+            }
+            if (lane < L) ps->E[lane] = (int64_t)(w << (64 - kPtEBits)) >> (64 - kPtEBits);
+            if (lane == 0) {
+                if (ab) __hip_atomic_store(pf->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ps->abort = ab;
+            }
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(ps->abort)) break;
+        if (tid == 0) {
+            int32_t c = ps->since;
+            pt_pass(L, ps->E, ps->who, c, pf->timeout);
+            ps->since = c;
+            for (int i = 0; i < L; ++i)
+                if (ps->who[i] == m) ps->rung = i;
+            ps->tper = wall_clock64();
+        }
+        __syncthreads();
+    }
+    }
 
     if (lane == 0) sm.tie_sum[wv] = n_tie;
     __syncthreads();
@@ -631,6 +732,10 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         for (int c = 0; c < CPL; ++c)
             if (lane + 64 * c < N) a.perm[lane + 64 * c] = pv[lane + 64 * c];
         if (lane == 0) {
+            if (PTF) {
+                pf->slot[rep] = ps->rung;
+                if (rep % pf->L == 0) pf->since_top[rep / pf->L] = ps->since;
+            }
             *a.E = E;
             *a.E_best = E_best;
             const bool acc = (a.flags & kAccumCounters) != 0;
@@ -648,13 +753,9 @@ constexpr int table_waves_per_eu() {
     return NMAX <= 64 ? 4 : 2;
 }
 
-// One replica per workgroup (single-instance runs).
-template <int NMAX, bool ZD, bool EXACT, bool REC>
-__global__ void __launch_bounds__(4 * NMAX)
-__attribute__((amdgpu_waves_per_eu(table_waves_per_eu<NMAX>())))
-sweep_table_kernel(SweepArgs a) {
-    __shared__ __align__(16) TableSmem<NMAX> sm;
-    const int64_t rep = blockIdx.x;
+// Replica rep's job in a single-instance launch.
+template <int NMAX, bool ZD>
+__device__ __forceinline__ ReplicaJob table_job(const SweepArgs &a, int64_t rep) {
     ReplicaJob j;
     j.N = a.N;
     j.D = a.D;
@@ -677,7 +778,34 @@ sweep_table_kernel(SweepArgs a) {
     j.zero_diag = ZD;
     j.tstate = a.tstate ? a.tstate + rep * table_state_words(NMAX) : nullptr;
     j.flags = a.flags;
-    table_replica<NMAX, ZD, EXACT, REC>(j, sm);
+    return j;
+}
+
+// One replica per workgroup (single-instance runs).
+template <int NMAX, bool ZD, bool EXACT, bool REC>
+__global__ void __launch_bounds__(4 * NMAX)
+__attribute__((amdgpu_waves_per_eu(table_waves_per_eu<NMAX>())))
+sweep_table_kernel(SweepArgs a) {
+    __shared__ __align__(16) TableSmem<NMAX> sm;
+    table_replica<NMAX, ZD, EXACT, REC>(table_job<NMAX, ZD>(a, blockIdx.x), sm);
+}
+
+// Fused parallel tempering: replicas rep0 .. rep0 + gridDim.x - 1 (whole
+// sets), every period in one cooperative launch.
+template <int NMAX, bool ZD, bool EXACT>
+__global__ void __launch_bounds__(4 * NMAX)
+__attribute__((amdgpu_waves_per_eu(table_waves_per_eu<NMAX>())))
+sweep_table_pt(SweepArgs a, PtFusedArgs p, int64_t rep0) {
+    __shared__ __align__(16) TableSmem<NMAX> sm;
+    __shared__ PtSmem ps;
+    const int64_t rep = rep0 + blockIdx.x;
+    ReplicaJob j = table_job<NMAX, ZD>(a, rep);
+    j.beta = p.ladder;
+    j.beta_stride = 0;
+    j.T = p.n_periods * p.period_sweeps;
+    j.tstate = nullptr;
+    j.flags = 0;
+    table_replica<NMAX, ZD, EXACT, false, true>(j, sm, &p, &ps, rep);
 }
 
 // Persistent: each workgroup takes (instance, replica) items from a queue
@@ -727,6 +855,40 @@ hipError_t launch_persistent_nmax(hipStream_t s, bool zd, const BatchArgs &b, in
     return hipGetLastError();
 }
 
+// Cooperative launches of whole sets, as many per launch as fit the device
+// at once (the members of a set must all be resident to meet).
+template <int NMAX, bool ZD, bool EXACT>
+hipError_t launch_pt_one(hipStream_t s, const SweepArgs &a, const PtFusedArgs &p, int num_cus) {
+    const void *kern = reinterpret_cast<const void *>(&sweep_table_pt<NMAX, ZD, EXACT>);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_table_pt<NMAX, ZD, EXACT>,
+                                                                4 * NMAX, 0);
+    if (e != hipSuccess) return e;
+    const int64_t sets_per_launch = (int64_t)per_cu * num_cus / p.L;
+    if (sets_per_launch < 1) return hipErrorCooperativeLaunchTooLarge;
+    const int64_t n_sets = a.R / p.L;
+    for (int64_t s0 = 0; s0 < n_sets; s0 += sets_per_launch) {
+        const int64_t ns = n_sets - s0 < sets_per_launch ? n_sets - s0 : sets_per_launch;
+        SweepArgs aa = a;
+        PtFusedArgs pp = p;
+        int64_t rep0 = s0 * p.L;
+        void *args[] = {&aa, &pp, &rep0};
+        e = hipLaunchCooperativeKernel(kern, dim3((unsigned)(ns * p.L)), dim3(4 * NMAX), args, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int NMAX>
+hipError_t launch_pt_nmax(hipStream_t s, const SweepArgs &a, const PtFusedArgs &p, int num_cus) {
+    const bool exact = a.N == NMAX;
+    if (a.zero_diag)
+        return exact ? launch_pt_one<NMAX, true, true>(s, a, p, num_cus)
+                     : launch_pt_one<NMAX, true, false>(s, a, p, num_cus);
+    return exact ? launch_pt_one<NMAX, false, true>(s, a, p, num_cus)
+                 : launch_pt_one<NMAX, false, false>(s, a, p, num_cus);
+}
+
 template <int NMAX>
 int persistent_blocks_per_cu() {
     int n = 0;
@@ -755,6 +917,20 @@ hipError_t launch_sweep_table_persistent(hipStream_t s, int nmax, bool zd, const
         case 32: return launch_persistent_nmax<32>(s, zd, b, grid);
         case 64: return launch_persistent_nmax<64>(s, zd, b, grid);
         case 128: return launch_persistent_nmax<128>(s, zd, b, grid);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_table_pt(hipStream_t s, int nmax, const SweepArgs &args, const PtFusedArgs &p,
+                                 int num_cus) {
+    if (p.L < 1 || p.L > kPtMaxL || args.R % p.L) return hipErrorInvalidValue;
+    SweepArgs a = args;
+    if (a.seq_threshold < 0) a.seq_threshold = default_seq_threshold(nmax, a.N);
+    switch (nmax) {
+        case 16: return launch_pt_nmax<16>(s, a, p, num_cus);
+        case 32: return launch_pt_nmax<32>(s, a, p, num_cus);
+        case 64: return launch_pt_nmax<64>(s, a, p, num_cus);
+        case 128: return launch_pt_nmax<128>(s, a, p, num_cus);
         default: return hipErrorInvalidValue;
     }
 }

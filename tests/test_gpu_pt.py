@@ -20,14 +20,15 @@ def dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-def gpu_pt(ctx, D, F, perms, ladder, periods, per_sweeps, timeout, seed, slot=None, since=None):
+def gpu_pt(ctx, D, F, perms, ladder, periods, per_sweeps, timeout, seed, slot=None, since=None,
+           schedule="auto"):
     L = len(ladder)
     R = perms.shape[0]
     p = dev(perms, torch.int32)
     sl = dev(np.tile(np.arange(L), R // L) if slot is None else slot, torch.int32)
     st = dev(np.zeros(R // L) if since is None else since, torch.int32)
     ctx.run_pt(dev(D, torch.int32), dev(F, torch.int32), p, dev(ladder, torch.float32), sl, st,
-               periods, per_sweeps, timeout, seed)
+               periods, per_sweeps, timeout, seed, schedule)
     E_best, perm_best = ctx.best()
     return {"perm": p.cpu().numpy(), "E": ctx.energy().cpu().numpy(),
             "E_best": E_best.cpu().numpy(), "perm_best": perm_best.cpu().numpy(),
@@ -58,13 +59,18 @@ def compare(got, ref, L):
     return differ
 
 
-@pytest.mark.parametrize("N,L,sets,sweep,kind", [
-    (12, 4, 3, "fast", "grid"), (16, 4, 2, "fast", "uniform"), (40, 5, 2, "fast", "uniform"),
-    (128, 4, 1, "fast", "uniform"), (64, 10, 2, "fast", "uniform"),
-    (64, 6, 2, "fast", "diag"), (140, 4, 2, "fast", "uniform"), (33, 5, 2, "plain", "uniform")])
-def test_pt_matches_oracle(N, L, sets, sweep, kind):
+TABLE_CASES = [(12, 4, 3, "fast", "grid"), (16, 4, 2, "fast", "uniform"),
+               (40, 5, 2, "fast", "uniform"), (128, 4, 1, "fast", "uniform"),
+               (64, 10, 2, "fast", "uniform"), (64, 6, 2, "fast", "diag"), (100, 3, 2, "fast", "diag")]
+
+
+@pytest.mark.parametrize("N,L,sets,sweep,kind,schedule",
+                         [c + (s,) for c in TABLE_CASES for s in ("periodic", "fused")]
+                         + [(140, 4, 2, "fast", "uniform", "auto"),
+                            (33, 5, 2, "plain", "uniform", "auto")])
+def test_pt_matches_oracle(N, L, sets, sweep, kind, schedule):
     from paper_2605_24408_amd import pdit as P
-    say(f"pt N={N} L={L} sets={sets} sweep={sweep} kind={kind}")
+    say(f"pt N={N} L={L} sets={sets} sweep={sweep} kind={kind} schedule={schedule}")
     rng = np.random.default_rng(N * 3 + L)
     if kind == "grid":
         inst = W.config_n12(R=L * sets, T=1)
@@ -77,7 +83,7 @@ def test_pt_matches_oracle(N, L, sets, sweep, kind):
     periods, per, timeout = 12, 4, 3
     ref = oracle.run_pt(D, F, perms, ladder, periods, per, timeout, 17)
     with P.Pdit(sweep=sweep) as ctx:
-        got = gpu_pt(ctx, D, F, perms, ladder, periods, per, timeout, 17)
+        got = gpu_pt(ctx, D, F, perms, ladder, periods, per, timeout, 17, schedule=schedule)
         plan = ctx.last_plan()
     assert plan["sweep"] == sweep
     differ = compare(got, ref, L)
@@ -85,7 +91,8 @@ def test_pt_matches_oracle(N, L, sets, sweep, kind):
     assert ref.counters[:, 1].sum() > 0
 
 
-def test_pt_resume_equals_single_call():
+@pytest.mark.parametrize("schedule", ["periodic", "fused"])
+def test_pt_resume_equals_single_call(schedule):
     from paper_2605_24408_amd import pdit as P
     rng = np.random.default_rng(5)
     N, L = 48, 6
@@ -94,12 +101,39 @@ def test_pt_resume_equals_single_call():
     s = W.energy_scale(D, F)
     ladder = W.beta_geometric(1.0 / s, 40.0 / s, L)
     with P.Pdit() as ctx:
-        one = gpu_pt(ctx, D, F, perms, ladder, 10, 4, 2, 3)
+        one = gpu_pt(ctx, D, F, perms, ladder, 10, 4, 2, 3, schedule=schedule)
     with P.Pdit() as ctx:
-        a = gpu_pt(ctx, D, F, perms, ladder, 6, 4, 2, 3)
-        b = gpu_pt(ctx, D, F, a["perm"], ladder, 4, 4, 2, 3, slot=a["slot"], since=a["since_top"])
+        a = gpu_pt(ctx, D, F, perms, ladder, 6, 4, 2, 3, schedule=schedule)
+        b = gpu_pt(ctx, D, F, a["perm"], ladder, 4, 4, 2, 3, slot=a["slot"], since=a["since_top"],
+                   schedule=schedule)
     for f in ("perm", "E", "E_best", "perm_best", "slot", "since_top"):
         assert np.array_equal(one[f], b[f]), f
+
+
+@pytest.mark.parametrize("N,L,sets,periods,per_sweeps,timeout", [
+    (64, 10, 102, 40, 4, 5), (128, 4, 70, 6, 3, 2), (20, 64, 40, 30, 2, 7), (32, 1, 300, 5, 3, 2)])
+def test_pt_fused_equals_periodic(N, L, sets, periods, per_sweeps, timeout):
+    """Full-size ladders: the fused launch (whole sets per cooperative
+    launch; 280 replicas of N = 128 need two launches) against one launch per
+    period, every output equal."""
+    from paper_2605_24408_amd import pdit as P
+    say(f"pt fused vs periodic N={N} L={L} sets={sets}")
+    rng = np.random.default_rng(N + L)
+    D, F = W.random_instance(rng, N, 0, 99)
+    perms = W.random_perms(rng, L * sets, N)
+    s = W.energy_scale(D, F)
+    ladder = W.beta_geometric(0.3 / s, 30.0 / s, L)
+    with P.Pdit() as ctx:
+        a = gpu_pt(ctx, D, F, perms, ladder, periods, per_sweeps, timeout, 11, schedule="periodic")
+        ca = ctx.counters()
+    with P.Pdit() as ctx:
+        b = gpu_pt(ctx, D, F, perms, ladder, periods, per_sweeps, timeout, 11, schedule="fused")
+        cb = ctx.counters()
+    for f in ("perm", "E", "E_best", "perm_best", "counters", "slot", "since_top"):
+        assert np.array_equal(a[f], b[f]), f
+    assert ca == cb and ca["accepted"] > 0
+    for g in range(sets):
+        assert sorted(b["slot"][g * L:(g + 1) * L]) == list(range(L))
 
 
 def test_pt_exchange_only_periods():
@@ -136,3 +170,14 @@ def test_pt_error_paths():
         with pytest.raises(P.PditError) as e:
             gpu_pt(ctx, D, F, perms, np.array([0.1, -1.0, 0.2, 0.3], np.float32), 1, 1, 5, 1)
         assert e.value.status == "PDIT_EBETA"
+    # the fused schedule needs the table kernel
+    with P.Pdit(sweep="plain") as ctx:
+        with pytest.raises(P.PditError) as e:
+            gpu_pt(ctx, D, F, perms, ladder, 1, 1, 5, 1, schedule="fused")
+        assert e.value.status == "PDIT_EINVAL"
+    rng = np.random.default_rng(3)
+    D2, F2 = W.random_instance(rng, 140, 0, 9)
+    with P.Pdit() as ctx:
+        with pytest.raises(P.PditError) as e:
+            gpu_pt(ctx, D2, F2, W.random_perms(rng, 4, 140), ladder, 1, 1, 5, 1, schedule="fused")
+        assert e.value.status == "PDIT_EINVAL"
