@@ -76,6 +76,12 @@ def lib():
         L.po_run_pt.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_int, i32p, f32p, i32p, i32p,
                                 C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
                                 C.c_int32, i64p, i64p, i32p, C.c_int, i64p]
+        L.po_beta_rule.restype = C.c_int
+        L.po_beta_rule.argtypes = [C.c_int, i64p, f32p, C.c_int, f32p, i32p]
+        L.po_beta_select.restype = C.c_int
+        L.po_beta_select.argtypes = [C.c_int, i32p, i32p, C.c_int, i32p, f32p, C.c_int, C.c_int64,
+                                     C.c_uint64, C.c_int32, C.c_int, i64p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
         _lib = L
     return _lib
 
@@ -244,6 +250,51 @@ def run_pt(D, F, perm, ladder, n_periods, period_sweeps, timeout, seed, sweep_of
     if rc != PO_OK:
         raise RuntimeError(f"oracle parallel tempering failed with status {rc}")
     return PTResult(p, E, Eb, pb, counters, sl, st)
+
+
+def beta_rule(E_sum, grid, L):
+    """The range rule of the beta selection (Results, "Implementation";
+    Methods, "CPU-PIM Algorithm") on summed trial energies: returns
+    (lo, hi, ladder)."""
+    E_sum = np.ascontiguousarray(E_sum, dtype=np.int64)
+    grid = np.ascontiguousarray(grid, dtype=np.float32)
+    ladder = np.zeros(int(L), dtype=np.float32)
+    lo_hi = np.zeros(2, dtype=np.int32)
+    rc = lib().po_beta_rule(E_sum.shape[0], E_sum, grid, int(L), ladder, lo_hi)
+    if rc != PO_OK:
+        raise RuntimeError(f"oracle beta rule failed with status {rc}")
+    return int(lo_hi[0]), int(lo_hi[1]), ladder
+
+
+@dataclass
+class BetaSelection:
+    E_sum: np.ndarray      # [G] summed ending energies of the trials
+    E_trial: np.ndarray    # [G, R] every trial replica's ending energy
+    lo: int
+    hi: int
+    ladder: np.ndarray     # [L]
+
+
+def beta_select(D, F, perm, grid, trial_sweeps, seed, L, inst_id=0) -> BetaSelection:
+    """Beta-range selection: fixed-beta trials of trial_sweeps sweeps from
+    the rows of perm at every grid value, then the range rule and a
+    geometric ladder of L rungs."""
+    D, F = _i32(D), _i32(F)
+    N = D.shape[0]
+    p = np.ascontiguousarray(perm, dtype=np.int32).reshape(-1, N)
+    R = p.shape[0]
+    grid = np.ascontiguousarray(grid, dtype=np.float32)
+    G = grid.shape[0]
+    E_sum = np.zeros(G, dtype=np.int64)
+    E_trial = np.zeros((G, R), dtype=np.int64)
+    ladder = np.zeros(int(L), dtype=np.float32)
+    lo_hi = np.zeros(2, dtype=np.int32)
+    rc = lib().po_beta_select(N, D, F, R, p, grid, G, int(trial_sweeps), int(seed), int(inst_id),
+                              int(L), E_sum, ladder.ctypes.data, lo_hi.ctypes.data,
+                              E_trial.ctypes.data)
+    if rc != PO_OK:
+        raise RuntimeError(f"oracle beta selection failed with status {rc}")
+    return BetaSelection(E_sum, E_trial, int(lo_hi[0]), int(lo_hi[1]), ladder)
 
 
 def brute_min(D, F, first=-1) -> tuple[int, np.ndarray]:

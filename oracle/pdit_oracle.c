@@ -443,6 +443,104 @@ int po_run_pt(int N, const int32_t *D, const int32_t *F, int R, int L, int32_t *
 }
 
 /* ------------------------------------------------------------------ */
+/* beta-range selection (Results, "Implementation"; Methods, "CPU-PIM   */
+/* Algorithm"): short fixed-beta trials on a grid, then the range rule. */
+/* ------------------------------------------------------------------ */
+/*
+ * The rule, on the summed ending energies of the trials (E_sum[g] = sum of
+ * the R trial replicas' energies at grid[g], the mean times R, so exact):
+ * with Smax and Smin the largest and smallest sums, the low end lo is the
+ * first g (lowest beta first) whose sum has come down from Smax by at least
+ * 40% of Smax - Smin, i.e. 5 E_sum[g] <= 3 Smax + 2 Smin; the high end is
+ * two grid steps past the first g holding Smin, at most G - 1.  The ladder
+ * of L >= 2 rungs is geometric between grid[lo] and grid[hi]:
+ * ladder[i] = fl32(grid[lo] * exp(log(grid[hi] / grid[lo]) * i / (L - 1)))
+ * in double, with both ends exactly the grid values.  lo_hi[0] = lo,
+ * lo_hi[1] = hi.  Sums must stay below 2^59 in magnitude.
+ */
+int po_beta_rule(int G, const int64_t *E_sum, const float *grid, int L, float *ladder,
+                 int32_t *lo_hi)
+{
+    if (G < 1 || L < 2 || !E_sum || !grid || !ladder || !lo_hi) return PO_EINVAL;
+    const int64_t lim = (int64_t)1 << 59;
+    int64_t smax = E_sum[0], smin = E_sum[0];
+    int gmin = 0;
+    for (int g = 0; g < G; ++g) {
+        if (E_sum[g] >= lim || E_sum[g] <= -lim) return PO_EINVAL;
+        if (E_sum[g] > smax) smax = E_sum[g];
+        if (E_sum[g] < smin) {
+            smin = E_sum[g];
+            gmin = g;
+        }
+    }
+    int lo = -1;
+    for (int g = 0; g < G && lo < 0; ++g)
+        if (5 * E_sum[g] <= 3 * smax + 2 * smin) lo = g;
+    int hi = gmin + 2 < G ? gmin + 2 : G - 1;
+    lo_hi[0] = lo;
+    lo_hi[1] = hi;
+    const double b0 = grid[lo], b1 = grid[hi];
+    for (int i = 0; i < L; ++i)
+        ladder[i] = (float)(b0 * exp(log(b1 / b0) * (double)i / (double)(L - 1)));
+    ladder[0] = grid[lo];
+    ladder[L - 1] = grid[hi];
+    return PO_OK;
+}
+
+/*
+ * The trials: for each beta of the grid (finite, > 0, strictly ascending),
+ * R replicas start from the given permutations and run trial_sweeps sweeps
+ * at that fixed beta with no exchanges; trial replica k of grid point g
+ * draws with Philox replica id g R + k, instance inst_id, from sweep 0.
+ * E_trial (optional, [G*R]) receives every ending energy; then the rule.
+ */
+int po_beta_select(int N, const int32_t *D, const int32_t *F, int R, const int32_t *perm,
+                   const float *grid, int G, int64_t trial_sweeps, uint64_t seed, int32_t inst_id,
+                   int L, int64_t *E_sum, float *ladder, int32_t *lo_hi, int64_t *E_trial)
+{
+    if (N < 2 || R < 1 || G < 1 || trial_sweeps < 0 || !D || !F || !perm || !grid || !E_sum)
+        return PO_EINVAL;
+    for (int g = 0; g < G; ++g)
+        if (!(grid[g] > 0.0f) || !isfinite(grid[g]) || (g > 0 && !(grid[g] > grid[g - 1])))
+            return PO_EINVAL;
+    int32_t *p = (int32_t *)malloc(sizeof(int32_t) * (size_t)N * R);
+    int32_t *pb = (int32_t *)malloc(sizeof(int32_t) * (size_t)N * R);
+    int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)R);
+    int64_t *E = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int64_t *Eb = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * 3 * (size_t)R);
+    float *b = (float *)malloc(sizeof(float) * (size_t)(trial_sweeps > 0 ? trial_sweeps : 1));
+    int rc = PO_OK;
+    if (!p || !pb || !ids || !E || !Eb || !cnt || !b) {
+        rc = PO_ENOMEM;
+        goto done;
+    }
+    for (int g = 0; g < G && rc == PO_OK; ++g) {
+        memcpy(p, perm, sizeof(int32_t) * (size_t)N * R);
+        for (int k = 0; k < R; ++k) ids[k] = g * R + k;
+        for (int64_t t = 0; t < trial_sweeps; ++t) b[t] = grid[g];
+        rc = po_run(N, D, F, R, ids, inst_id, p, b, trial_sweeps, seed, 0, E, Eb, pb, 1, cnt, NULL,
+                    0, NULL, NULL, NULL, 0);
+        int64_t sum = 0;
+        for (int k = 0; k < R; ++k) {
+            sum += E[k];
+            if (E_trial) E_trial[(int64_t)g * R + k] = E[k];
+        }
+        E_sum[g] = sum;
+    }
+    if (rc == PO_OK && ladder && lo_hi) rc = po_beta_rule(G, E_sum, grid, L, ladder, lo_hi);
+done:
+    free(p);
+    free(pb);
+    free(ids);
+    free(E);
+    free(Eb);
+    free(cnt);
+    free(b);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Exhaustive minimum of Eq. 1 (small N): all permutations with p[0] =  */
 /* first (or all of them when first < 0), enumerated by Heap's method. */
 /* ------------------------------------------------------------------ */
