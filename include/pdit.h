@@ -212,6 +212,38 @@ typedef struct {
 int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                 int32_t *perm, const pdit_pt *pt, int64_t n_periods, uint64_t seed);
 
+/*
+ * Beta-range selection (Results, "Implementation"; Methods, "CPU-PIM
+ * Algorithm"): short trials at fixed beta, without exchanges, on an
+ * ascending grid; the averaged ending energies fall with beta and turn up
+ * again where the replicas freeze.  For every grid value g, R trial
+ * replicas start from the rows of perm (unchanged by the call) and run
+ * trial_sweeps sweeps (400 in the paper) at beta grid[g]; trial replica k of
+ * grid value g draws as replica g R + k of a run from sweep 0 (the
+ * context's sweep offset is neither used nor advanced).  Then, with Smax and
+ * Smin the largest and smallest sums of ending energies:
+ *   range[0] = lo, the first g whose sum has come down from Smax by at least
+ *              40% of Smax - Smin (5 E_sum[g] <= 3 Smax + 2 Smin);
+ *   range[1] = hi, two grid values past the first g holding Smin (at most
+ *              G - 1);
+ *   ladder[i] = grid[lo] (grid[hi] / grid[lo])^(i / (L - 1)), evaluated in
+ *              double and rounded to float, ladder[0] = grid[lo] and
+ *              ladder[L - 1] = grid[hi] exactly: a parallel-tempering ladder
+ *              (pdit_pt.beta) of L rungs.
+ *   perm     device int32 R x N, the trials' starting permutations
+ *   grid     device float G, finite, > 0, strictly ascending (PDIT_EBETA)
+ *   E_sum    device int64 G, out: summed ending energies (exact; the mean
+ *            times R)
+ *   ladder   device float L (L >= 2), out;   range: device int32 2, out
+ * R * N * (bound on |H|) must stay below 2^59 (PDIT_EOVERFLOW).  The
+ * context's replica state becomes that of the G * R trial replicas
+ * (pdit_energy, pdit_best, pdit_replica_counters report them).  Recording is
+ * not available.
+ */
+int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                     const int32_t *perm, const float *grid, int32_t G, int64_t trial_sweeps,
+                     uint64_t seed, int32_t L, int64_t *E_sum, float *ladder, int32_t *range);
+
 /* Result of pdit_autotune. */
 typedef struct {
     int blocks_per_cu;    /* chosen resident workgroups per CU */

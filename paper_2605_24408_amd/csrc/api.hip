@@ -91,7 +91,7 @@ int shape_state(pdit_t *ctx, const std::vector<int32_t> &Ns, const std::vector<i
 // Reads the instance summary (one host synchronisation) and validates.
 int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
                   const int32_t *perm, const float *beta, int64_t T, InstanceStats *st,
-                  const pdit_pt *pt = nullptr) {
+                  const pdit_pt *pt = nullptr, bool beta_is_grid = false) {
     int rc = ensure(ctx, ctx->scratch, sizeof(InstanceStats));
     if (rc) return rc;
     InstanceStats *dev = (InstanceStats *)ctx->scratch.ptr;
@@ -99,6 +99,7 @@ int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
     if (pt)
         PDIT_HIP(ctx, pdit::launch_pt_check(ctx->stream, R / pt->L, pt->L, pt->slot,
                                             pt->since_top, dev));
+    if (beta_is_grid) PDIT_HIP(ctx, pdit::launch_grid_check(ctx->stream, (int)T, beta, dev));
     PDIT_HIP(ctx, hipMemcpyAsync(ctx->stats_host, dev, sizeof(InstanceStats),
                                  hipMemcpyDeviceToHost, ctx->stream));
     PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -107,6 +108,8 @@ int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
     if (st->bad_perm_rows)
         return fail(ctx, PDIT_EBADPERM, "a row of perm is not a permutation of 0..N-1");
     if (st->bad_beta) return fail(ctx, PDIT_EBETA, "an inverse temperature is NaN, infinite or negative");
+    if (st->bad_grid)
+        return fail(ctx, PDIT_EBETA, "the beta grid must be > 0 and strictly ascending");
     if (st->bad_slots)
         return fail(ctx, PDIT_EINVAL,
                     "the slots of a parallel-tempering set are not a permutation of 0..L-1, or its "
@@ -225,6 +228,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->h_buf.ptr);
     hipFree(ctx->tstate.ptr);
     hipFree(ctx->pt_buf.ptr);
+    hipFree(ctx->trial_buf.ptr);
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
@@ -472,6 +476,104 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     }
     ctx->sweep_offset += (uint64_t)(n_periods * pt->period_sweeps);
     ctx->last_updates = (int64_t)R * N * n_periods * pt->period_sweeps;
+    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
+    ctx->last_class = use_fast ? fclass : 0;
+    ctx->last_mode = mode;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
+int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                     const int32_t *perm, const float *grid, int32_t G, int64_t trial_sweeps,
+                     uint64_t seed, int32_t L, int64_t *E_sum, float *ladder, int32_t *range) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!D || !F || !perm || !grid || !E_sum || !ladder || !range)
+        return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
+    if (R < 1 || G < 1 || (int64_t)R * G > INT32_MAX)
+        return fail(ctx, PDIT_EINVAL, "R and G must be >= 1 with R * G < 2^31");
+    if (L < 2) return fail(ctx, PDIT_EINVAL, "the ladder needs L >= 2 rungs");
+    if (trial_sweeps < 0) return fail(ctx, PDIT_EINVAL, "trial_sweeps must be >= 0");
+    if (ctx->rec_choices || ctx->rec_trace)
+        return fail(ctx, PDIT_EINVAL, "recording is not available for beta selection");
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+
+    InstanceStats st;
+    int rc = instance_prep(ctx, N, D, F, R, perm, grid, G, &st, nullptr, true);
+    if (rc) return rc;
+    const int64_t bound = pdit::h_bound(st);
+    // |E| <= N bound; the rule adds up to 5 sums of R energies exactly in int64
+    if ((__int128)R * N * bound >= ((__int128)1 << 59))
+        return fail(ctx, PDIT_EOVERFLOW, "R * N * (bound on |H|) must stay below 2^59");
+    const bool h64 = bound > INT32_MAX;
+    const int fclass = pdit::fast_class(N, st);
+    bool use_fast = false;
+    if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
+        if (!fclass) return fail(ctx, PDIT_EOVERFLOW, "the data do not fit the fast sweep kernel");
+        use_fast = true;
+    } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
+        use_fast = fclass != 0;
+    }
+    int mode = 0;
+    rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
+    if (rc) return rc;
+    const int RT = R * G;  // trial replicas: row g R + k is replica k at grid[g]
+    rc = ensure(ctx, ctx->h_buf, (size_t)RT * N * N * (h64 ? 8 : 4));
+    if (rc) return rc;
+    rc = ensure(ctx, ctx->trial_buf, sizeof(int32_t) * (size_t)RT * (N + 1));
+    if (rc) return rc;
+    int32_t *tperm = (int32_t *)ctx->trial_buf.ptr;
+    int32_t *tslot = tperm + (size_t)RT * N;
+    ctx->st.best_valid = false;  // the trials start their own best states
+    bool fresh = false;
+    rc = shape_state(ctx, {N}, {RT}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, pdit::launch_trial_setup(ctx->stream, N, R, G, perm, tperm, tslot));
+    PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, RT, tperm, ctx->h_buf.ptr, h64, S.E));
+    PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * RT, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+    PDIT_HIP(ctx, hipMemcpyAsync(S.perm_best, tperm, sizeof(int32_t) * (size_t)RT * N,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    pdit::SweepArgs a{};
+    a.N = N;
+    a.R = RT;
+    a.D = D;
+    a.F = F;
+    a.perm = tperm;
+    a.H = ctx->h_buf.ptr;
+    a.E = S.E;
+    a.E_best = S.E_best;
+    a.perm_best = S.perm_best;
+    a.counters = S.counters;
+    a.beta = grid;
+    a.slot = tslot;
+    a.T = trial_sweeps;
+    a.seed = seed;
+    a.sweep_offset = 0;  // every trial starts at sweep 0
+    a.inst_id = 0;
+    a.seq_threshold = ctx->opts.seq_threshold;
+    a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    if (trial_sweeps > 0) {
+        if (use_fast)
+            PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
+        else
+            PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
+    } else {
+        PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * RT, ctx->stream));
+    }
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, pdit::launch_group_sums(ctx->stream, R, G, S.E, E_sum));
+    PDIT_HIP(ctx, pdit::launch_beta_rule(ctx->stream, G, E_sum, grid, L, ladder, range));
+    ctx->timed = true;
+    ctx->last_updates = (int64_t)RT * N * trial_sweeps;
     ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;

@@ -27,6 +27,7 @@ struct InstanceStats {
     int32_t diag_nz_f;      // nonzero diagonal entries of F
     int32_t bad_slots;      // parallel tempering: sets whose slots are not a permutation of
                             // 0..L-1, or whose pass counter is negative
+    int32_t bad_grid;       // beta selection: grid values <= 0 or not above the previous one
 };
 
 // Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=
@@ -71,7 +72,8 @@ struct pdit_ctx {
     pdit::ReplicaState st;
     pdit::DeviceBuffer h_buf;         // H of all replicas (int32 or int64)
     pdit::DeviceBuffer tstate;        // table-kernel states between parallel-tempering periods
-    pdit::DeviceBuffer pt_buf;        // fused parallel tempering: published energies, arrivals
+    pdit::DeviceBuffer pt_buf;        // fused parallel tempering: published energy words
+    pdit::DeviceBuffer trial_buf;     // beta selection: trial permutations and their slots
     int coop = 0;                     // the device supports cooperative launches
     int wall_clock_khz = 0;
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
@@ -101,6 +103,14 @@ hipError_t launch_pt_check(hipStream_t s, int n_sets, int L, const int32_t *slot
                            const int32_t *since_top, InstanceStats *out);
 hipError_t launch_pt_exchange(hipStream_t s, int n_sets, int L, const int64_t *E, int32_t *slot,
                               int32_t *since_top, int32_t timeout);
+hipError_t launch_grid_check(hipStream_t s, int G, const float *grid, InstanceStats *out);
+// beta-range selection: trial replicas (perm rows repeated per grid value,
+// slot = grid index), summed ending energies per grid value, the range rule
+hipError_t launch_trial_setup(hipStream_t s, int N, int R, int G, const int32_t *perm,
+                              int32_t *trial_perm, int32_t *slot);
+hipError_t launch_group_sums(hipStream_t s, int R, int G, const int64_t *E, int64_t *E_sum);
+hipError_t launch_beta_rule(hipStream_t s, int G, const int64_t *E_sum, const float *grid, int L,
+                            float *ladder, int32_t *range);
 hipError_t launch_instance_stats(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                                  int R, const int32_t *perm, const float *beta, int64_t T,
                                  InstanceStats *out_dev);

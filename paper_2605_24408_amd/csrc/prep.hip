@@ -20,6 +20,7 @@ __global__ void zero_stats_kernel(InstanceStats *s) {
         s->diag_nz_d = 0;
         s->diag_nz_f = 0;
         s->bad_slots = 0;
+        s->bad_grid = 0;
     }
 }
 
@@ -89,6 +90,14 @@ __global__ void beta_check_kernel(int64_t T, const float *__restrict__ beta, Ins
     if (bad) atomicAdd(&s->bad_beta, bad);
 }
 
+// A beta grid for trials: every value > 0 and above the one before it.
+__global__ void grid_check_kernel(int G, const float *__restrict__ grid, InstanceStats *s) {
+    int bad = 0;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
+        if (!(grid[g] > 0.0f) || (g > 0 && !(grid[g] > grid[g - 1]))) ++bad;
+    if (bad) atomicAdd(&s->bad_grid, bad);
+}
+
 // One thread per parallel-tempering set: its L slots are distinct values in
 // [0, L) and its pass counter is not negative.
 __global__ void pt_check_kernel(int n_sets, int L, const int32_t *__restrict__ slot,
@@ -113,6 +122,11 @@ hipError_t launch_pt_check(hipStream_t st, int n_sets, int L, const int32_t *slo
                            const int32_t *since_top, InstanceStats *out) {
     if (L < 1 || L > kPtMaxL) return hipErrorInvalidValue;
     pt_check_kernel<<<(n_sets + 255) / 256, 256, 0, st>>>(n_sets, L, slot, since_top, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_check(hipStream_t st, int G, const float *grid, InstanceStats *out) {
+    grid_check_kernel<<<(G + 255) / 256 < 64 ? (G + 255) / 256 : 64, 256, 0, st>>>(G, grid, out);
     return hipGetLastError();
 }
 

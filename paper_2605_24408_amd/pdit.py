@@ -64,7 +64,8 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_replica_counters", "pdit_set_sweep_offset", "pdit_get_sweep_offset",
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
-           "pdit_last_timing", "pdit_autotune", "pdit_last_plan", "pdit_run_pt"]
+           "pdit_last_timing", "pdit_autotune", "pdit_last_plan", "pdit_run_pt",
+           "pdit_beta_select"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.pdit_run_sweeps.argtypes = [vp, i32, vp, vp, i32, vp, vp, i64, u64]
     L.pdit_run_sweeps_batch.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64]
     L.pdit_run_pt.argtypes = [vp, i32, vp, vp, i32, vp, C.POINTER(_PT), i64, u64]
+    L.pdit_beta_select.argtypes = [vp, i32, vp, vp, i32, vp, vp, i32, i64, u64, i32, vp, vp, vp]
     L.pdit_energy.argtypes = [vp, vp]
     L.pdit_best.argtypes = [vp, vp, vp]
     L.pdit_counters.argtypes = [vp, C.POINTER(_Counters)]
@@ -230,6 +232,25 @@ class Pdit:
         self._rc(self._L.pdit_run_pt(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), C.byref(pt),
                                      int(n_periods), int(seed)))
         self._last = (R, R * N, N)
+
+    def beta_select(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor,
+                    grid: torch.Tensor, trial_sweeps: int, seed: int, L: int):
+        """pdit_beta_select: fixed-beta trials on the grid from the rows of
+        perm (unchanged); returns (E_sum [G] int64, ladder [L] float32,
+        range [2] int32 = (lo, hi))."""
+        N = int(D.shape[0])
+        for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"), (perm, torch.int32, "perm"),
+                          (grid, torch.float32, "grid")):
+            _check_dev(t, dt, nm, self.device)
+        R, G = int(perm.shape[0]), int(grid.numel())
+        E_sum = torch.empty(G, dtype=torch.int64, device=self.device)
+        ladder = torch.empty(max(int(L), 1), dtype=torch.float32, device=self.device)
+        rng = torch.empty(2, dtype=torch.int32, device=self.device)
+        self._rc(self._L.pdit_beta_select(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), _ptr(grid),
+                                          G, int(trial_sweeps), int(seed), int(L), _ptr(E_sum),
+                                          _ptr(ladder), _ptr(rng)))
+        self._last = (R * G, R * G * N, N)
+        return E_sum, ladder, rng
 
     def run_sweeps_batch(self, instances, seed: int) -> None:
         """pdit_run_sweeps_batch over (D, F, perm, beta) tensors of uneven N."""
