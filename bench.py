@@ -123,11 +123,14 @@ def other_workload(args):
 
 
 def pt_workload(args):
-    """Parallel tempering against annealing on the N=64 instance: 102 ladders
-    of 10 rungs (1020 replicas), 4-sweep periods, a 100-period timeout, the
-    same total sweeps as the annealing schedule. One JSON line with the
-    update rates, the best energies and the time each method needs to reach
-    the other's final best; not the benchmark figure."""
+    """Parallel tempering against annealing on the N=64 instance, with the
+    ladder from the beta-range selection: 32 grid values from 0.01/s to
+    100/s (s: the RMS swap change of the instance), 64 trial replicas x 400
+    sweeps, 10 rungs.  Then 102 ladders (1020 replicas), 4-sweep periods, a
+    100-period timeout and 10^4 sweeps, against annealing of the same
+    replicas over the benchmark schedule (0.001 -> 1.0) and over the selected
+    range.  One JSON line with update rates, best energies and the time each
+    run needs to reach the others' final best; not the benchmark figure."""
     import numpy as np
     import torch
 
@@ -145,14 +148,30 @@ def pt_workload(args):
     D = torch.from_numpy(inst.D).to(dev)
     F = torch.from_numpy(inst.F).to(dev)
     perm0 = torch.from_numpy(inst.perms).to(dev)
-    beta = torch.from_numpy(inst.beta[:T].copy()).to(dev)
-    ladder = torch.from_numpy(W.beta_geometric(1e-3, 1.0, L)).to(dev)
     seed = W.PHILOX_SEED
     perm = perm0.clone()
     slot = torch.empty(R, dtype=torch.int32, device=dev)
     since = torch.empty(sets, dtype=torch.int32, device=dev)
+    ctx = pdit.Pdit(sweep="fast", recompute="i8")
 
-    def run_pt(ctx, record, schedule="fused"):
+    # ---- beta-range selection ----
+    s = W.energy_scale(inst.D, inst.F)
+    grid = torch.from_numpy(np.geomspace(0.01 / s, 100.0 / s, 32).astype(np.float32)).to(dev)
+    trial_R, trial_sweeps = 64, 400
+    ctx.beta_select(D, F, perm0[:trial_R].contiguous(), grid, trial_sweeps, seed, L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E_sum, ladder, rng = ctx.beta_select(D, F, perm0[:trial_R].contiguous(), grid, trial_sweeps,
+                                         seed, L)
+    lo, hi = (int(x) for x in rng.cpu().numpy())
+    t_sel = time.perf_counter() - t0
+    sel = {"grid": f"geometric 0.01/s -> 100/s, 32 values, s = {s:.1f}", "trial_replicas": trial_R,
+           "trial_sweeps": trial_sweeps, "seconds": t_sel, "lo": lo, "hi": hi,
+           "beta_lo": float(grid[lo]), "beta_hi": float(grid[hi]),
+           "mean_ending_energy": (E_sum.cpu().numpy() / trial_R).tolist(),
+           "ladder": ladder.cpu().numpy().tolist()}
+
+    def run_pt(record, schedule="fused"):
         perm.copy_(perm0)
         slot.copy_(torch.arange(L, dtype=torch.int32, device=dev).repeat(sets))
         since.zero_()
@@ -175,7 +194,7 @@ def pt_workload(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, e.cpu().numpy(), curve
 
-    def run_anneal(ctx, record):
+    def run_anneal(beta, record):
         perm.copy_(perm0)
         ctx.set_sweep_offset(0)
         ctx.reset()
@@ -196,19 +215,22 @@ def pt_workload(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, e.cpu().numpy(), curve
 
-    out = {"workload": "qap_n64_uniform99_parallel_tempering", "N": N, "replicas": R,
-           "ladders": sets, "rungs": L, "ladder": "geometric 0.001->1.0",
-           "period_sweeps": period, "timeout_periods": timeout, "sweeps": T}
-    ctx = pdit.Pdit(sweep="fast", recompute="i8")
-    run_pt(ctx, False)
-    t_pt, eb_pt, _ = run_pt(ctx, False)
-    _, _, c_pt = run_pt(ctx, True)
+    run_pt(False)
+    t_pt, eb_pt, _ = run_pt(False)
+    _, _, c_pt = run_pt(True)
     cnt = ctx.counters()
-    run_pt(ctx, False, "periodic")
-    t_per, eb_per, _ = run_pt(ctx, False, "periodic")
-    run_anneal(ctx, False)
-    t_an, eb_an, _ = run_anneal(ctx, False)
-    _, _, c_an = run_anneal(ctx, True)
+    run_pt(False, "periodic")
+    t_per, eb_per, _ = run_pt(False, "periodic")
+    schedules = {"benchmark schedule 0.001 -> 1.0":
+                 torch.from_numpy(inst.beta[:T].copy()).to(dev),
+                 "selected range": torch.from_numpy(
+                     W.beta_geometric(float(grid[lo]), float(grid[hi]), T)).to(dev)}
+    anneal = {}
+    for name, beta in schedules.items():
+        run_anneal(beta, False)
+        t_an, eb_an, _ = run_anneal(beta, False)
+        _, _, c_an = run_anneal(beta, True)
+        anneal[name] = (t_an, eb_an, c_an)
     ctx.close()
     upd = R * N * n_periods * period
 
@@ -217,16 +239,20 @@ def pt_workload(args):
         return None if not hit else {"sweeps": hit[0][0], "seconds": hit[0][1]}
 
     ladder_best = eb_pt.reshape(sets, L).min(axis=1)
+    out = {"workload": "qap_n64_uniform99_parallel_tempering", "N": N, "replicas": R,
+           "ladders": sets, "rungs": L, "period_sweeps": period, "timeout_periods": timeout,
+           "sweeps": T, "beta_selection": sel}
     out["pt"] = {"updates_per_s": upd / t_pt, "seconds": t_pt, "best": int(eb_pt.min()),
                  "mean_ladder_best": float(ladder_best.mean()),
-                 "acceptance": cnt["accepted"] / max(cnt["updates"], 1),
-                 "curve": c_pt, "reaches_anneal_best": reach(c_pt, int(eb_an.min())),
+                 "acceptance": cnt["accepted"] / max(cnt["updates"], 1), "curve": c_pt,
                  "schedule": "fused (one cooperative launch, sets meet on the device)",
                  "periodic_schedule": {"updates_per_s": upd / t_per, "seconds": t_per,
                                        "identical_best": bool(np.array_equal(eb_per, eb_pt))}}
-    out["anneal"] = {"updates_per_s": R * N * T / t_an, "seconds": t_an, "best": int(eb_an.min()),
-                     "mean_best": float(eb_an.mean()),
-                     "curve": c_an, "reaches_pt_best": reach(c_an, int(eb_pt.min()))}
+    for name, (t_an, eb_an, c_an) in anneal.items():
+        out["pt"]["reaches_best_of_anneal_" + name] = reach(c_pt, int(eb_an.min()))
+        out["anneal " + name] = {"updates_per_s": R * N * T / t_an, "seconds": t_an,
+                                 "best": int(eb_an.min()), "mean_best": float(eb_an.mean()),
+                                 "curve": c_an, "reaches_pt_best": reach(c_an, int(eb_pt.min()))}
     print(json.dumps(out), flush=True)
 
 
