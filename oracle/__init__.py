@@ -76,6 +76,13 @@ def lib():
         L.po_run_pt.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_int, i32p, f32p, i32p, i32p,
                                 C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
                                 C.c_int32, i64p, i64p, i32p, C.c_int, i64p]
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.po_cupim_resolve.restype = C.c_int
+        L.po_cupim_resolve.argtypes = [C.c_int, i32p, i64p, u8p]
+        L.po_run_cupim.restype = C.c_int
+        L.po_run_cupim.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_void_p, C.c_int32, i32p, f32p,
+                                   C.c_int64, C.c_uint64, C.c_uint64, i64p, i64p, i32p, C.c_int,
+                                   i64p, C.c_void_p, C.c_void_p]
         L.po_beta_rule.restype = C.c_int
         L.po_beta_rule.argtypes = [C.c_int, i64p, f32p, C.c_int, f32p, i32p]
         L.po_beta_select.restype = C.c_int
@@ -250,6 +257,58 @@ def run_pt(D, F, perm, ladder, n_periods, period_sweeps, timeout, seed, sweep_of
     if rc != PO_OK:
         raise RuntimeError(f"oracle parallel tempering failed with status {rc}")
     return PTResult(p, E, Eb, pb, counters, sl, st)
+
+
+def cupim_resolve(sel, dE):
+    """GPU-CUPIM conflict resolution (Methods, "GPU-CUPIM Algorithm"):
+    returns the boolean winner mask of the proposals r -> sel[r]."""
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    dE = np.ascontiguousarray(dE, dtype=np.int64)
+    win = np.zeros(sel.shape[0], dtype=np.uint8)
+    n = lib().po_cupim_resolve(sel.shape[0], sel, dE, win)
+    if n < 0:
+        raise RuntimeError(f"oracle resolution failed with status {n}")
+    return win.astype(bool)
+
+
+@dataclass
+class CupimResult:
+    perm: np.ndarray
+    E: np.ndarray
+    E_best: np.ndarray
+    perm_best: np.ndarray
+    counters: np.ndarray          # [R, 3]: updates, accepted (winning exchanges), ties
+    choices: np.ndarray | None    # [R, T, N] every draw
+    won: np.ndarray | None        # [R, T, N] winner masks
+
+
+def run_cupim(D, F, perm, beta, seed, sweep_offset=0, rep_ids=None, inst_id=0, E_best=None,
+              perm_best=None, record=False) -> CupimResult:
+    """GPU-CUPIM iterations (Results, "GPU Implementations"; Methods,
+    "GPU-CUPIM Algorithm") on every row of perm; `choices` holds the draws
+    and `trace` the winner masks when record is set."""
+    D, F = _i32(D), _i32(F)
+    N = D.shape[0]
+    p = np.array(perm, dtype=np.int32, copy=True).reshape(-1, N)
+    R = p.shape[0]
+    beta = np.ascontiguousarray(beta, dtype=np.float32)
+    T = beta.shape[0]
+    ids = None if rep_ids is None else np.ascontiguousarray(rep_ids, dtype=np.int32)
+    E = np.zeros(R, dtype=np.int64)
+    init_best = E_best is None
+    Eb = np.zeros(R, dtype=np.int64) if init_best else np.array(E_best, dtype=np.int64, copy=True)
+    pb = (np.zeros((R, N), dtype=np.int32) if init_best
+          else np.array(perm_best, dtype=np.int32, copy=True).reshape(R, N))
+    counters = np.zeros((R, 3), dtype=np.int64)
+    choices = np.full((R, T, N), -1, dtype=np.int32) if record else None
+    won = np.zeros((R, T, N), dtype=np.uint8) if record else None
+    rc = lib().po_run_cupim(N, D, F, R, None if ids is None else ids.ctypes.data, int(inst_id), p,
+                            beta, T, int(seed), int(sweep_offset), E, Eb, pb, int(init_best),
+                            counters, None if choices is None else choices.ctypes.data,
+                            None if won is None else won.ctypes.data)
+    if rc != PO_OK:
+        raise RuntimeError(f"oracle CUPIM run failed with status {rc}")
+    return CupimResult(p, E, Eb, pb, counters, choices, None if won is None else won.astype(bool))
 
 
 def beta_rule(E_sum, grid, L):

@@ -443,6 +443,135 @@ int po_run_pt(int N, const int32_t *D, const int32_t *F, int R, int L, int32_t *
 }
 
 /* ------------------------------------------------------------------ */
+/* GPU-CUPIM (Results, "GPU Implementations"; Methods, "GPU-CUPIM      */
+/* Algorithm"): every p-dit of an iteration draws from a snapshot of   */
+/* the energy changes taken at the iteration's start; overlapping      */
+/* proposals are resolved, and the winners are applied together.      */
+/* ------------------------------------------------------------------ */
+/*
+ * Conflict resolution.  Location r proposes exchanging its facility with
+ * location sel[r] (sel[r] == r: no proposal) at snapshot energy change
+ * dE[r].  A proposal's key is (dE[r], r), smaller first: the larger energy
+ * decrease wins, a tie goes to the lower proposing index.  A proposal wins
+ * when no other proposal touching either of its two locations has a
+ * smaller key; losers do not move.  Winners are pairwise disjoint.
+ * win[r] = 1 for a winning proposal, else 0; returns the number of winners.
+ */
+int po_cupim_resolve(int N, const int32_t *sel, const int64_t *dE, unsigned char *win)
+{
+    if (N < 1 || !sel || !dE || !win) return PO_EINVAL;
+    int n = 0;
+    for (int r = 0; r < N; ++r) {
+        win[r] = 0;
+        const int s = sel[r];
+        if (s < 0 || s >= N) return PO_EINVAL;
+        if (s == r) continue;
+        int ok = 1;
+        for (int q = 0; q < N && ok; ++q) {
+            const int u = sel[q];
+            if (q == r || u == q) continue;
+            if (q != r && q != s && u != r && u != s) continue; /* shares no location */
+            if (dE[q] < dE[r] || (dE[q] == dE[r] && q < r)) ok = 0;
+        }
+        if (ok) {
+            win[r] = 1;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/*
+ * T iterations of the concurrent update.  Per iteration g (global sweep
+ * sweep_off + t) and replica: the snapshot row of every location r (Eq. 3 on
+ * the iteration's starting permutation), the Gibbs choice of each row (Eq. 5,
+ * uniform from the Philox counter (r, g, replica, instance) as in po_run),
+ * the resolution above, every winning exchange applied, then I and E
+ * recomputed from Eq. 2 and Eq. 1.  The best state is checked once per
+ * iteration (strict improvement).  counters: updates (N per iteration),
+ * accepted (winning exchanges), ties (draws within the tie band).  choices
+ * (optional, [R][T][N]): every draw; won (optional, [R][T][N]): the winners.
+ */
+int po_run_cupim(int N, const int32_t *D, const int32_t *F, int R, const int32_t *rep_ids,
+                 int32_t inst_id, int32_t *perm, const float *beta, int64_t T, uint64_t seed,
+                 uint64_t sweep_off, int64_t *E, int64_t *E_best, int32_t *perm_best,
+                 int init_best, int64_t *counters, int32_t *choices, unsigned char *won)
+{
+    if (N < 2 || R < 1 || T < 0 || !D || !F || !perm || !beta || !E || !E_best || !perm_best ||
+        !counters)
+        return PO_EINVAL;
+    int64_t *I = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * N);
+    int64_t *row = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    int64_t *dsel = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    int32_t *sel = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    unsigned char *win = (unsigned char *)malloc((size_t)N);
+    unsigned char *seen = (unsigned char *)malloc((size_t)N);
+    int rc = PO_OK;
+    if (!I || !row || !dsel || !sel || !win || !seen) {
+        rc = PO_ENOMEM;
+        goto done;
+    }
+    for (int k = 0; k < R; ++k) {
+        int32_t *p = perm + (int64_t)k * N;
+        int32_t *pb = perm_best + (int64_t)k * N;
+        const uint32_t rep = rep_ids ? (uint32_t)rep_ids[k] : (uint32_t)k;
+        if (!is_permutation(N, p, seen)) {
+            rc = PO_EBADPERM;
+            goto done;
+        }
+        int64_t e = po_energy(N, D, F, p);
+        if (init_best) {
+            E_best[k] = e;
+            memcpy(pb, p, sizeof(int32_t) * (size_t)N);
+        }
+        int64_t n_acc = 0, n_tie = 0;
+        for (int64_t t = 0; t < T; ++t) {
+            const uint32_t g = (uint32_t)(sweep_off + (uint64_t)t);
+            po_influence(N, D, F, p, I); /* the snapshot */
+            for (int r = 0; r < N; ++r) {
+                for (int s = 0; s < N; ++s) row[s] = po_delta_eq3(N, D, F, p, I, r, s);
+                const uint32_t u24 = po_uniform24(seed, (uint32_t)r, g, rep, (uint32_t)inst_id);
+                int tie = 0;
+                const int c = po_gibbs_choice(N, row, beta[t], u24, &tie);
+                if (c < 0) {
+                    rc = c;
+                    goto done;
+                }
+                n_tie += tie;
+                sel[r] = c;
+                dsel[r] = row[c];
+                if (choices) choices[((int64_t)k * T + t) * N + r] = c;
+            }
+            n_acc += po_cupim_resolve(N, sel, dsel, win);
+            for (int r = 0; r < N; ++r) {
+                if (won) won[((int64_t)k * T + t) * N + r] = win[r];
+                if (!win[r]) continue;
+                const int32_t a = p[r];
+                p[r] = p[sel[r]];
+                p[sel[r]] = a;
+            }
+            e = po_energy(N, D, F, p);
+            if (e < E_best[k]) {
+                E_best[k] = e;
+                memcpy(pb, p, sizeof(int32_t) * (size_t)N);
+            }
+        }
+        E[k] = e;
+        counters[3 * k + 0] = (int64_t)N * T;
+        counters[3 * k + 1] = n_acc;
+        counters[3 * k + 2] = n_tie;
+    }
+done:
+    free(I);
+    free(row);
+    free(dsel);
+    free(sel);
+    free(win);
+    free(seen);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* beta-range selection (Results, "Implementation"; Methods, "CPU-PIM   */
 /* Algorithm"): short fixed-beta trials on a grid, then the range rule. */
 /* ------------------------------------------------------------------ */
