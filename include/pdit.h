@@ -213,6 +213,26 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
                 int32_t *perm, const pdit_pt *pt, int64_t n_periods, uint64_t seed);
 
 /*
+ * GPU-CUPIM, concurrent updates (Results, "GPU Implementations"; Methods,
+ * "GPU-CUPIM Algorithm"): a different dynamics from pdit_run_sweeps.  In
+ * each iteration every location draws (Eq. 5, the same weights and Philox
+ * stream as a sweep) from a snapshot of the swap energy changes (Eq. 3)
+ * taken at the iteration's start.  Location r proposes exchanging its
+ * facility with its draw s != r; the proposal's key is (snapshot dE, r),
+ * smaller first -- the larger energy decrease wins, a tie goes to the lower
+ * proposing index -- and a proposal is applied when it holds the smallest
+ * key at both of its locations (one round; losers stay).  All applied
+ * exchanges are disjoint and happen together; then the snapshot is
+ * refreshed.  Arguments, sweep offset, best state (checked once per
+ * iteration) and outputs as in pdit_run_sweeps; counters: updates = N per
+ * iteration, accepted = applied exchanges, ties = draws within the tie
+ * band.  Needs N <= 128 and |D|, |F| <= 127 (PDIT_EOVERFLOW otherwise: the
+ * refresh runs on int8 MFMA).  Recording is not available.
+ */
+int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                   int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed);
+
+/*
  * Beta-range selection (Results, "Implementation"; Methods, "CPU-PIM
  * Algorithm"): short trials at fixed beta, without exchanges, on an
  * ascending grid; the averaged ending energies fall with beta and turn up

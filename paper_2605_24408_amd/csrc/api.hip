@@ -483,6 +483,61 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     return PDIT_OK;
 }
 
+int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                   int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!D || !F || !perm || (!beta && n_sweeps > 0))
+        return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
+    if (R < 1) return fail(ctx, PDIT_EINVAL, "R must be >= 1");
+    if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
+    if (ctx->rec_choices || ctx->rec_trace)
+        return fail(ctx, PDIT_EINVAL, "recording is not available for concurrent updates");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    InstanceStats st;
+    int rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st);
+    if (rc) return rc;
+    const int cls = pdit::cupim_class(N, st);
+    if (!cls)
+        return fail(ctx, PDIT_EOVERFLOW,
+                    "concurrent updates need N <= 128 and |D|, |F| <= 127 (int8 MFMA refresh)");
+    bool fresh = false;
+    rc = shape_state(ctx, {N}, {R}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+    pdit::CupimArgs c{};
+    c.N = N;
+    c.R = R;
+    c.D = D;
+    c.F = F;
+    c.perm = perm;
+    c.E = S.E;
+    c.E_best = S.E_best;
+    c.perm_best = S.perm_best;
+    c.counters = S.counters;
+    c.beta = beta;
+    c.T = n_sweeps;
+    c.seed = seed;
+    c.sweep_offset = ctx->sweep_offset;
+    c.inst_id = 0;
+    c.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
+    c.init_best = fresh ? 1 : 0;
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, pdit::launch_cupim(ctx->stream, cls, c));
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->timed = true;
+    ctx->sweep_offset += (uint64_t)n_sweeps;
+    ctx->last_updates = (int64_t)R * N * n_sweeps;
+    ctx->last_sweep = PDIT_SWEEP_FAST;
+    ctx->last_class = cls;
+    ctx->last_mode = 0;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
 int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                      const int32_t *perm, const float *grid, int32_t G, int64_t trial_sweeps,
                      uint64_t seed, int32_t L, int64_t *E_sum, float *ladder, int32_t *range) {

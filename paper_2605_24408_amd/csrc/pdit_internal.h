@@ -168,6 +168,50 @@ inline int default_seq_threshold(int nmax, int N) {
     return 3;
 }
 
+// GPU-CUPIM (concurrent updates): one replica per workgroup, N <= 128,
+// |D|, |F| <= 127; the kernel computes its own H and E.
+struct CupimArgs {
+    int N;
+    int R;
+    const int32_t *D;
+    const int32_t *F;
+    int32_t *perm;           // [R][N] in/out
+    int64_t *E;              // [R] out
+    int64_t *E_best;         // [R] in/out
+    int32_t *perm_best;      // [R][N] in/out
+    int64_t *counters;       // [R][3] out
+    const float *beta;       // [T]
+    int64_t T;
+    uint64_t seed;
+    uint64_t sweep_offset;
+    uint32_t inst_id;
+    bool zero_diag;
+    int init_best;           // start the best state from the initial one
+};
+struct CupimJob {
+    int N;
+    const int32_t *D;
+    const int32_t *F;
+    int32_t *perm;
+    int64_t *E;
+    int64_t *E_best;
+    int32_t *perm_best;
+    int64_t *counters;
+    const float *beta;
+    int64_t T;
+    uint64_t seed;
+    uint64_t sweep_offset;
+    uint32_t rep;
+    uint32_t inst;
+    int init_best;
+};
+// size class (16, 32, 64, 128) of the CUPIM kernel, 0 when it does not apply
+inline int cupim_class(int N, const InstanceStats &st) {
+    if (st.max_abs_d > 127 || st.max_abs_f > 127) return 0;
+    return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 0;
+}
+hipError_t launch_cupim(hipStream_t s, int nmax, const CupimArgs &c);
+
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
 // size class of the on-chip kernel that runs an instance (16, 32, 64, 128,
 // 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic

@@ -65,7 +65,7 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
            "pdit_last_timing", "pdit_autotune", "pdit_last_plan", "pdit_run_pt",
-           "pdit_beta_select"]
+           "pdit_beta_select", "pdit_run_cupim"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.pdit_run_sweeps.argtypes = [vp, i32, vp, vp, i32, vp, vp, i64, u64]
     L.pdit_run_sweeps_batch.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64]
     L.pdit_run_pt.argtypes = [vp, i32, vp, vp, i32, vp, C.POINTER(_PT), i64, u64]
+    L.pdit_run_cupim.argtypes = [vp, i32, vp, vp, i32, vp, vp, i64, u64]
     L.pdit_beta_select.argtypes = [vp, i32, vp, vp, i32, vp, vp, i32, i64, u64, i32, vp, vp, vp]
     L.pdit_energy.argtypes = [vp, vp]
     L.pdit_best.argtypes = [vp, vp, vp]
@@ -231,6 +232,21 @@ class Pdit:
                  int(timeout), PT_SCHEDULE[schedule])
         self._rc(self._L.pdit_run_pt(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), C.byref(pt),
                                      int(n_periods), int(seed)))
+        self._last = (R, R * N, N)
+
+    def run_cupim(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor,
+                  beta: torch.Tensor, seed: int) -> None:
+        """pdit_run_cupim: len(beta) concurrent-update iterations on every
+        row of perm (in/out)."""
+        N = int(D.shape[0])
+        for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"),
+                          (perm, torch.int32, "perm"), (beta, torch.float32, "beta")):
+            _check_dev(t, dt, nm, self.device)
+        if perm.dim() != 2 or perm.shape[1] != N:
+            raise ValueError("perm must be R x N")
+        R = int(perm.shape[0])
+        self._rc(self._L.pdit_run_cupim(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), _ptr(beta),
+                                        int(beta.numel()), int(seed)))
         self._last = (R, R * N, N)
 
     def beta_select(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor,
