@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-replicas", type=int, default=32)
-    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512", "pt"],
+    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512", "pt", "cupim"],
                     help="n64 is the benchmark configuration; the others report the same "
                          "fast-vs-plain comparison for the other workload shapes")
     ap.add_argument("--sweeps", type=int, default=0,
@@ -256,6 +256,89 @@ def pt_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def cupim_workload(args):
+    """GPU-CUPIM (concurrent updates) against the sequential p-dit sweep on
+    the N=64 instance, 1024 replicas, 10^4 iterations, on two schedules: the
+    benchmark's geometric 0.001 -> 1.0 and a geometric anneal across the
+    range the beta selection picks (hot: most draws move).  One JSON line
+    with update rates (N updates per iteration on both), kernel times, best
+    energies and the time each needs to reach the other's final best; not the
+    benchmark figure."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit
+    from paper_2605_24408_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    inst = W.config_n64()
+    N, R = inst.N, inst.R
+    T = args.sweeps or inst.T
+    D = torch.from_numpy(inst.D).to(dev)
+    F = torch.from_numpy(inst.F).to(dev)
+    perm0 = torch.from_numpy(inst.perms).to(dev)
+    perm = perm0.clone()
+    seed = W.PHILOX_SEED
+    ctx = pdit.Pdit(sweep="fast", recompute="i8")
+    s = W.energy_scale(inst.D, inst.F)
+    grid = torch.from_numpy(np.geomspace(0.01 / s, 100.0 / s, 32).astype(np.float32)).to(dev)
+    _, _, rng = ctx.beta_select(D, F, perm0[:64].contiguous(), grid, 400, seed, 10)
+    lo, hi = (int(x) for x in rng.cpu().numpy())
+    schedules = {"benchmark 0.001 -> 1.0": inst.beta[:T].copy(),
+                 "selected range": W.beta_geometric(float(grid[lo]), float(grid[hi]), T)}
+    chunks = 10
+
+    def run(method, beta, record):
+        perm.copy_(perm0)
+        ctx.set_sweep_offset(0)
+        ctx.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        curve, kms = [], 0.0
+        step = (T + chunks - 1) // chunks if record else T
+        done = 0
+        while done < T:
+            k = min(step, T - done)
+            b = beta[done:done + k].contiguous()
+            (ctx.run_cupim if method == "cupim" else ctx.run_sweeps)(D, F, perm, b, seed)
+            done += k
+            if record:
+                e, _ = ctx.best()
+                v = int(e.min())
+                curve.append((done, time.perf_counter() - t0, v))
+        e, _ = ctx.best()
+        torch.cuda.synchronize()
+        if not record:
+            kms = ctx.last_timing()[1]
+        cnt = ctx.counters()
+        return time.perf_counter() - t0, e.cpu().numpy(), curve, kms, cnt
+
+    def reach(curve, target):
+        hit = [c for c in curve if c[2] <= target]
+        return None if not hit else {"sweeps": hit[0][0], "seconds": hit[0][1]}
+
+    out = {"workload": "qap_n64_uniform99_cupim_vs_sequential", "N": N, "replicas": R,
+           "iterations": T, "beta_range": [float(grid[lo]), float(grid[hi])]}
+    for name, bnp in schedules.items():
+        beta = torch.from_numpy(bnp).to(dev)
+        res = {}
+        for method in ("cupim", "sequential"):
+            run(method, beta, False)
+            t, eb, _, kms, cnt = run(method, beta, False)
+            _, _, curve, _, _ = run(method, beta, True)
+            res[method] = (t, eb, curve, kms, cnt)
+        row = {}
+        for method, (t, eb, curve, kms, cnt) in res.items():
+            other = res["sequential" if method == "cupim" else "cupim"]
+            row[method] = {"updates_per_s": R * N * T / t, "seconds": t, "kernel_ms": kms,
+                           "best": int(eb.min()), "mean_best": float(eb.mean()),
+                           "accepted_per_iteration": cnt["accepted"] / (R * T),
+                           "curve": curve, "reaches_other_best": reach(curve, int(other[1].min()))}
+        out[name] = row
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -265,6 +348,9 @@ def main():
         sys.exit(2)
     if args.workload == "pt":
         pt_workload(args)
+        return
+    if args.workload == "cupim":
+        cupim_workload(args)
         return
     if args.workload != "n64":
         other_workload(args)

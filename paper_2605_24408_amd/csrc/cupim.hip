@@ -13,10 +13,10 @@
 // |D|, |F| <= 127.  LDS holds the snapshot table T[l][s] (int32; the stay's
 // slot on the diagonal holds a sentinel), int8 copies of D, F and F[p,p],
 // and p.  After an iteration with winners the table is rebuilt from
-// H = D F[p,p]: 16x16x64 int8 MFMAs write H into the table's storage, diag H
-// and E = trace H are read off, then every pair (l, s), l < s, turns its two
-// H entries into T[l][s] = T[s][l] in place (Eq. 3 with I = -2H).  An
-// iteration without winners leaves the snapshot valid and skips the refresh.
+// S = D F[p,p] + F[p,p] D on 16x16x64 int8 MFMAs, each lane turning its own
+// accumulator entries into table entries (Eq. 3 with I = -2H, H + H^T = S);
+// E = trace H.  An iteration without winners leaves the snapshot valid and
+// skips the refresh.
 // Draws use the same integer weights, CDF and Philox stream as the
 // sequential kernels: q = rint(expf(-fl32(beta fl32(d))) 2^25) of the
 // distance d to the row minimum, the first s with C_s 2^24 > u24 Z, u24 from
@@ -39,7 +39,7 @@ struct CupimSmem {
     static constexpr int PT = NMAX + 4;               // table row pitch (int32)
     static constexpr int KP = NMAX < 64 ? 64 : NMAX;  // K extent of the int8 rows (MFMA K = 64)
     static constexpr int P8 = KP + 16;                // int8 row pitch (bytes), 16-byte aligned
-    int32_t TH[NMAX * PT];                            // T; H during a refresh
+    int32_t TH[NMAX * PT];                            // T (pitch padding never read)
     int8_t D8[NMAX * P8];                             // D, zero outside N x N
     int8_t Fp8[NMAX * P8];                            // F[p,p], zero outside N x N
     int8_t F8[NMAX * NMAX];                           // F
@@ -50,70 +50,100 @@ struct CupimSmem {
     long long esum;                                   // trace of H
 };
 
-// Rebuilds the snapshot: H = D F[p,p] on MFMA into TH, diag H, E, then T in
-// place.  Returns E.  Every thread calls it.
+// Rebuilds the snapshot from S = D F[p,p] + F[p,p] D = H + H^T (both
+// operands symmetric): two 16x16x64 int8 MFMA products per output tile, so
+// each lane holds S[l][s] for its own (l, s) and turns it into
+// T[l][s] = 2 (S[l][s] - H[l][l] - H[s][s]) + correction (Eq. 3 with
+// I = -2H) in registers; H[x][x] = S[x][x] / 2 comes from the diagonal
+// tiles through LDS.  Returns E = trace H.  Every thread calls it; the table
+// must not be read concurrently.
 template <int NMAX, bool ZD>
 __device__ __forceinline__ int64_t cupim_refresh(CupimSmem<NMAX> &sm, int N) {
     constexpr int PT = CupimSmem<NMAX>::PT;
     constexpr int P8 = CupimSmem<NMAX>::P8;
     constexpr int KC = CupimSmem<NMAX>::KP / 64;  // K chunks
     constexpr int NJ = NMAX / 16;                 // column tiles
-    constexpr int NT = 4 * NMAX;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // ---- H: wave wv owns rows 16 wv .. 16 wv + 15, all NJ column tiles ----
-    {
-        v4i acc[NJ];
+    // wave wv owns rows 16 wv .. 16 wv + 15 and all NJ column tiles; element
+    // e of tile j is S[16 wv + 4 (lane / 16) + e][16 j + lane % 16]
+    v4i acc[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[j] = v4i{0, 0, 0, 0};
-        const int arow = 16 * wv + (lane & 15);
-        const int kb = (lane >> 4) * 16;
+    for (int j = 0; j < NJ; ++j) acc[j] = v4i{0, 0, 0, 0};
+    const int arow = 16 * wv + (lane & 15);
+    const int kb = (lane >> 4) * 16;
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const v4i a = *reinterpret_cast<const v4i *>(&sm.D8[arow * P8 + kc * 64 + kb]);
+    for (int kc = 0; kc < KC; ++kc) {
+        const v4i ad = *reinterpret_cast<const v4i *>(&sm.D8[arow * P8 + kc * 64 + kb]);
+        const v4i af = *reinterpret_cast<const v4i *>(&sm.Fp8[arow * P8 + kc * 64 + kb]);
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const v4i b = *reinterpret_cast<const v4i *>(&sm.Fp8[(16 * j + (lane & 15)) * P8 +
-                                                                     kc * 64 + kb]);
-                acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[j], 0, 0, 0);
-            }
+        for (int j = 0; j < NJ; ++j) {
+            const int brow = (16 * j + (lane & 15)) * P8 + kc * 64 + kb;
+            const v4i bf = *reinterpret_cast<const v4i *>(&sm.Fp8[brow]);
+            const v4i bd = *reinterpret_cast<const v4i *>(&sm.D8[brow]);
+            acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ad, bf, acc[j], 0, 0, 0);  // D Fp
+            acc[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bd, acc[j], 0, 0, 0);  // Fp D
         }
-        // element e of tile j: H[16 wv + 4 (lane / 16) + e][16 j + lane % 16]
+    }
+    const int r0 = 16 * wv + 4 * (lane >> 4);
+    const int c0 = lane & 15;
+    if (tid == 0) sm.esum = 0;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < NJ; ++j)
+        if (j == wv)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                sm.TH[(16 * wv + 4 * (lane >> 4) + e) * PT + 16 * j + (lane & 15)] = acc[j][e];
-    }
-    if (tid == 0) sm.esum = 0;
-    __syncthreads();
-    for (int x = tid; x < NMAX; x += NT) sm.hd[x] = x < N ? sm.TH[x * PT + x] : 0;
+                if (r0 + e == 16 * j + c0) sm.hd[r0 + e] = r0 + e < N ? acc[j][e] / 2 : 0;
     __syncthreads();
     if (tid < N) atomicAdd(reinterpret_cast<unsigned long long *>(&sm.esum),
                            (unsigned long long)(long long)sm.hd[tid]);
-    // ---- T from H, in place: the owner of (l, s), l < s, writes both entries ----
-    for (int e = tid; e < NMAX * NMAX; e += NT) {
-        const int l = e / NMAX, s = e % NMAX;
-        if (l < N && s < N && l < s) {
-            const uint32_t hls = (uint32_t)sm.TH[l * PT + s], hsl = (uint32_t)sm.TH[s * PT + l];
-            const uint32_t h = 2u * (hls + hsl - (uint32_t)sm.hd[l] - (uint32_t)sm.hd[s]);
-            const int32_t dls = sm.D8[l * P8 + s], fls = sm.Fp8[l * P8 + s];
-            uint32_t corr;
-            if (ZD) {
-                corr = 4u * (uint32_t)(dls * fls);
-            } else {
-                const int32_t dd = (int32_t)sm.D8[l * P8 + l] + (int32_t)sm.D8[s * P8 + s] - 2 * dls;
-                const int32_t ff = (int32_t)sm.Fp8[l * P8 + l] + (int32_t)sm.Fp8[s * P8 + s] - 2 * fls;
-                corr = (uint32_t)(dd * ff);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int l = r0 + e;
+        const int32_t hl = sm.hd[l];
+        int32_t dll = 0, fll = 0;
+        if (!ZD) {
+            dll = sm.D8[l * P8 + l];
+            fll = sm.Fp8[l * P8 + l];
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int c = 16 * j + c0;
+            int32_t v = kBig;
+            if (l < N && c < N && l != c) {
+                const uint32_t h = 2u * ((uint32_t)acc[j][e] - (uint32_t)hl - (uint32_t)sm.hd[c]);
+                const int32_t dls = sm.D8[l * P8 + c], fls = sm.Fp8[l * P8 + c];
+                uint32_t corr;
+                if (ZD) {
+                    corr = 4u * (uint32_t)(dls * fls);
+                } else {
+                    const int32_t dd = dll + (int32_t)sm.D8[c * P8 + c] - 2 * dls;
+                    const int32_t ff = fll + (int32_t)sm.Fp8[c * P8 + c] - 2 * fls;
+                    corr = (uint32_t)(dd * ff);
+                }
+                v = (int32_t)(h + corr);
             }
-            const int32_t v = (int32_t)(h + corr);
-            sm.TH[l * PT + s] = v;
-            sm.TH[s * PT + l] = v;
-        } else if (l == s || l >= N || s >= N) {
-            sm.TH[l * PT + s] = kBig;
+            sm.TH[l * PT + c] = v;
         }
     }
     __syncthreads();
     return (int64_t)sm.esum;
+}
+
+// F[p,p] from F and p, four bytes per store (zero beyond N).
+template <int NMAX>
+__device__ __forceinline__ void cupim_gather_fp(CupimSmem<NMAX> &sm, int N) {
+    constexpr int P8 = CupimSmem<NMAX>::P8;
+    constexpr int NT = 4 * NMAX;
+    const int n4 = (N + 3) / 4;
+    for (int e = threadIdx.x; e < N * n4; e += NT) {
+        const int i = e / n4, c = 4 * (e % n4);
+        const int8_t *frow = sm.F8 + sm.pv[i] * NMAX;
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (c + b < N) w |= (uint32_t)(uint8_t)frow[sm.pv[c + b]] << (8 * b);
+        *reinterpret_cast<uint32_t *>(&sm.Fp8[i * P8 + c]) = w;
+    }
 }
 
 // One replica's run: T iterations of the concurrent update.
@@ -138,13 +168,9 @@ __device__ __forceinline__ void cupim_replica(const CupimJob &a, CupimSmem<NMAX>
         const int i = e / NMAX, k = e % NMAX;
         sm.F8[e] = (int8_t)((i < N && k < N) ? a.F[i * N + k] : 0);
     }
-    for (int e = tid; e < NMAX * PT; e += NT)
-        if (e % PT >= NMAX) sm.TH[e] = kBig;  // pitch padding, never read
+    for (int e = tid; e < NMAX * P8; e += NT) sm.Fp8[e] = 0;
     __syncthreads();
-    for (int e = tid; e < NMAX * P8; e += NT) {
-        const int i = e / P8, k = e % P8;
-        sm.Fp8[e] = (i < N && k < N) ? sm.F8[sm.pv[i] * NMAX + sm.pv[k]] : (int8_t)0;
-    }
+    cupim_gather_fp<NMAX>(sm, N);
     __syncthreads();
     int64_t E = cupim_refresh<NMAX, ZD>(sm, N);
     int64_t E_best = a.init_best ? E : *a.E_best;
@@ -288,11 +314,8 @@ __device__ __forceinline__ void cupim_replica(const CupimJob &a, CupimSmem<NMAX>
         if (total == 0) continue;  // the snapshot stays valid
         n_acc += total;
 
-        // ---- 3. refresh: F[p,p], H, E, T ----
-        for (int e = tid; e < N * N; e += NT) {
-            const int i = e / N, k = e % N;
-            sm.Fp8[i * P8 + k] = sm.F8[sm.pv[i] * NMAX + sm.pv[k]];
-        }
+        // ---- 3. refresh: F[p,p], then S, E, T ----
+        cupim_gather_fp<NMAX>(sm, N);
         __syncthreads();
         E = cupim_refresh<NMAX, ZD>(sm, N);
         if (E < E_best) {
