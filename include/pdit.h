@@ -78,6 +78,17 @@ extern "C" {
                                |dE| < 2^30 - 1 and N <= 256.  N <= 128: the table of swap energy
                                changes in LDS, |D|, |F| <= 32767; N <= 160: 2H int32 in LDS;
                                N <= 256: 2H int16 in LDS, |2H| <= 32767 */
+#define PDIT_SWEEP_CLIQUE 3 /* clique flows (Methods, "CPU-PIM Algorithm", tai256c): F[a][b] =
+                               c(a) c(b) for a != b with c in {0, 1} (a clique on a facility
+                               subset, unit flows), F[a][a] = 0, D with a zero diagonal, N <= 512,
+                               (4N + 2) max|D| < 2^30.  The energy depends only on the set S of
+                               locations holding clique facilities; with g(x) = sum_{j in S}
+                               D[x][j] an exchange inside a class changes nothing and one across
+                               the classes changes E by 2 (g(s) - g(r) - D[r][s]) (r in S), so a
+                               candidate costs O(1) and an accepted move O(N).  Same dynamics and
+                               results as the other kernels.  AUTO and FAST pick it for N > 128
+                               when the data qualify; CLIQUE forces it (PDIT_EINVAL when they do
+                               not).  pdit_last_plan reports PDIT_SWEEP_CLIQUE. */
 
 typedef struct pdit_ctx pdit_t;
 

@@ -91,7 +91,8 @@ int shape_state(pdit_t *ctx, const std::vector<int32_t> &Ns, const std::vector<i
 // Reads the instance summary (one host synchronisation) and validates.
 int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
                   const int32_t *perm, const float *beta, int64_t T, InstanceStats *st,
-                  const pdit_pt *pt = nullptr, bool beta_is_grid = false) {
+                  const pdit_pt *pt = nullptr, bool beta_is_grid = false,
+                  int32_t *clique_member = nullptr) {
     int rc = ensure(ctx, ctx->scratch, sizeof(InstanceStats));
     if (rc) return rc;
     InstanceStats *dev = (InstanceStats *)ctx->scratch.ptr;
@@ -100,6 +101,8 @@ int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
         PDIT_HIP(ctx, pdit::launch_pt_check(ctx->stream, R / pt->L, pt->L, pt->slot,
                                             pt->since_top, dev));
     if (beta_is_grid) PDIT_HIP(ctx, pdit::launch_grid_check(ctx->stream, (int)T, beta, dev));
+    if (clique_member)
+        PDIT_HIP(ctx, pdit::launch_clique_check(ctx->stream, N, F, clique_member, dev));
     PDIT_HIP(ctx, hipMemcpyAsync(ctx->stats_host, dev, sizeof(InstanceStats),
                                  hipMemcpyDeviceToHost, ctx->stream));
     PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -229,6 +232,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->tstate.ptr);
     hipFree(ctx->pt_buf.ptr);
     hipFree(ctx->trial_buf.ptr);
+    hipFree(ctx->clique_buf.ptr);
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
@@ -242,6 +246,49 @@ int pdit_destroy(pdit_t *ctx) {
     return PDIT_OK;
 }
 
+// The clique-flow sweep (validated by the caller): no H; the kernel builds
+// its own state from D, the facility membership and p.
+int run_clique(pdit_t *ctx, int32_t N, const int32_t *D, int32_t R, int32_t *perm,
+               const float *beta, int64_t n_sweeps, uint64_t seed) {
+    bool fresh = false;
+    int rc = shape_state(ctx, {N}, {R}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+    pdit::CliqueArgs a{};
+    a.N = N;
+    a.R = R;
+    a.D = D;
+    a.member = (const int32_t *)ctx->clique_buf.ptr;
+    a.perm = perm;
+    a.E = S.E;
+    a.E_best = S.E_best;
+    a.perm_best = S.perm_best;
+    a.counters = S.counters;
+    a.beta = beta;
+    a.T = n_sweeps;
+    a.seed = seed;
+    a.sweep_offset = ctx->sweep_offset;
+    a.inst = 0;
+    a.init_best = fresh ? 1 : 0;
+    a.choices = ctx->rec_choices;
+    a.E_trace = ctx->rec_trace;
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, pdit::launch_sweep_clique(ctx->stream, a));
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->timed = true;
+    ctx->rec_choices = nullptr;
+    ctx->rec_trace = nullptr;
+    ctx->sweep_offset += (uint64_t)n_sweeps;
+    ctx->last_updates = (int64_t)R * N * n_sweeps;
+    ctx->last_sweep = PDIT_SWEEP_CLIQUE;
+    ctx->last_class = 0;
+    ctx->last_mode = 0;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
 int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                     int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed) {
     if (!ctx) return PDIT_EINVAL;
@@ -251,13 +298,28 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
     if (R < 1) return fail(ctx, PDIT_EINVAL, "R must be >= 1");
     if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
-    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
+    // clique flows are looked for where the table kernel does not apply
+    const bool try_clique = ctx->opts.sweep == PDIT_SWEEP_CLIQUE ||
+                            (ctx->opts.sweep != PDIT_SWEEP_PLAIN && N > 128);
+    int rc = PDIT_OK;
+    if (try_clique) {
+        rc = ensure(ctx, ctx->clique_buf, sizeof(int32_t) * (size_t)N);
+        if (rc) return rc;
+    }
     InstanceStats st;
-    int rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st);
+    rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st, nullptr, false,
+                       try_clique ? (int32_t *)ctx->clique_buf.ptr : nullptr);
     if (rc) return rc;
+    if (try_clique && pdit::clique_fits(N, st))
+        return run_clique(ctx, N, D, R, perm, beta, n_sweeps, seed);
+    if (ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
+        return fail(ctx, PDIT_EINVAL,
+                    "the clique kernel needs F = c c^T off the diagonal (0/1, a facility subset), "
+                    "zero diagonals, N <= 512 and (4N + 2) max|D| < 2^30");
     const int64_t bound = pdit::h_bound(st);
     const bool h64 = bound > INT32_MAX;
     // the on-chip kernel's size class, 0 if the data do not fit its exact arithmetic
@@ -351,7 +413,10 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for parallel tempering");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
-        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+        return fail(ctx, PDIT_EINVAL,
+                    ctx->opts.sweep == PDIT_SWEEP_CLIQUE
+                        ? "the clique kernel runs only in pdit_run_sweeps"
+                        : "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
     InstanceStats st;
@@ -553,7 +618,10 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for beta selection");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
-        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+        return fail(ctx, PDIT_EINVAL,
+                    ctx->opts.sweep == PDIT_SWEEP_CLIQUE
+                        ? "the clique kernel runs only in pdit_run_sweeps"
+                        : "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
     InstanceStats st;
@@ -645,7 +713,10 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for batched runs");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
-        return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+        return fail(ctx, PDIT_EINVAL,
+                    ctx->opts.sweep == PDIT_SWEEP_CLIQUE
+                        ? "the clique kernel runs only in pdit_run_sweeps"
+                        : "unknown sweep kernel");
     for (int k = 0; k < n_inst; ++k) {
         const pdit_instance &in = inst[k];
         if (in.N < 2 || in.N > PDIT_NMAX || in.R < 1)

@@ -28,6 +28,8 @@ struct InstanceStats {
     int32_t bad_slots;      // parallel tempering: sets whose slots are not a permutation of
                             // 0..L-1, or whose pass counter is negative
     int32_t bad_grid;       // beta selection: grid values <= 0 or not above the previous one
+    int32_t clique_bad;     // entries of F that break F[a][b] = c(a) c(b) (a != b), F[a][a] = 0
+    int32_t clique_size;    // facilities with c(a) = 1
 };
 
 // Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=
@@ -74,6 +76,7 @@ struct pdit_ctx {
     pdit::DeviceBuffer tstate;        // table-kernel states between parallel-tempering periods
     pdit::DeviceBuffer pt_buf;        // fused parallel tempering: published energy words
     pdit::DeviceBuffer trial_buf;     // beta selection: trial permutations and their slots
+    pdit::DeviceBuffer clique_buf;    // clique flows: membership of each facility
     int coop = 0;                     // the device supports cooperative launches
     int wall_clock_khz = 0;
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
@@ -104,6 +107,10 @@ hipError_t launch_pt_check(hipStream_t s, int n_sets, int L, const int32_t *slot
 hipError_t launch_pt_exchange(hipStream_t s, int n_sets, int L, const int64_t *E, int32_t *slot,
                               int32_t *since_top, int32_t timeout);
 hipError_t launch_grid_check(hipStream_t s, int G, const float *grid, InstanceStats *out);
+// clique flows: member[a] = c(a) (facility a has a nonzero flow), and the
+// count of entries of F that break F = c c^T off the diagonal, 0 on it
+hipError_t launch_clique_check(hipStream_t s, int N, const int32_t *F, int32_t *member,
+                               InstanceStats *out);
 // beta-range selection: trial replicas (perm rows repeated per grid value,
 // slot = grid index), summed ending energies per grid value, the range rule
 hipError_t launch_trial_setup(hipStream_t s, int N, int R, int G, const int32_t *perm,
@@ -211,6 +218,35 @@ inline int cupim_class(int N, const InstanceStats &st) {
     return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 0;
 }
 hipError_t launch_cupim(hipStream_t s, int nmax, const CupimArgs &c);
+
+// The sweep specialised to clique flows (one wave per replica, N <= 512).
+struct CliqueArgs {
+    int N;
+    int R;
+    const int32_t *D;
+    const int32_t *member;   // [N] c(a) of each facility
+    int32_t *perm;           // [R][N] in/out
+    int64_t *E;              // [R] out
+    int64_t *E_best;         // [R] in/out
+    int32_t *perm_best;      // [R][N] in/out
+    int64_t *counters;       // [R][3] out
+    const float *beta;       // [T]
+    int64_t T;
+    uint64_t seed;
+    uint64_t sweep_offset;
+    uint32_t inst;
+    int init_best;
+    int32_t *choices;        // optional [R][T][N]
+    int64_t *E_trace;        // optional [R][T]
+};
+constexpr int kCliqueNMax = 512;
+// the clique kernel applies: F is a 0/1 clique, D has a zero diagonal, and
+// every energy change 2 (g(s) - g(r) - D[r][s]) stays below 2^30 in magnitude
+inline bool clique_fits(int N, const InstanceStats &st) {
+    return N <= kCliqueNMax && st.clique_bad == 0 && st.diag_nz_d == 0 &&
+           (4 * (int64_t)N + 2) * st.max_abs_d < (int64_t)(1 << 30) - 1;
+}
+hipError_t launch_sweep_clique(hipStream_t s, const CliqueArgs &a);
 
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
 // size class of the on-chip kernel that runs an instance (16, 32, 64, 128,

@@ -21,6 +21,8 @@ __global__ void zero_stats_kernel(InstanceStats *s) {
         s->diag_nz_f = 0;
         s->bad_slots = 0;
         s->bad_grid = 0;
+        s->clique_bad = 0;
+        s->clique_size = 0;
     }
 }
 
@@ -98,6 +100,31 @@ __global__ void grid_check_kernel(int G, const float *__restrict__ grid, Instanc
     if (bad) atomicAdd(&s->bad_grid, bad);
 }
 
+// member[a] = 1 when facility a has a nonzero flow to another facility.
+__global__ void clique_member_kernel(int N, const int32_t *__restrict__ F,
+                                     int32_t *__restrict__ member) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    int32_t c = 0;
+    for (int b = 0; b < N; ++b)
+        if (b != a && F[(int64_t)a * N + b] != 0) c = 1;
+    member[a] = c;
+}
+
+// Entries that break F[a][b] = member[a] member[b] (a != b), F[a][a] = 0.
+__global__ void clique_check_kernel(int N, const int32_t *__restrict__ F,
+                                    const int32_t *__restrict__ member, InstanceStats *s) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= N) return;
+    int bad = 0;
+    for (int b = 0; b < N; ++b) {
+        const int32_t want = b == a ? 0 : member[a] * member[b];
+        bad += F[(int64_t)a * N + b] != want;
+    }
+    if (bad) atomicAdd(&s->clique_bad, bad);
+    if (member[a]) atomicAdd(&s->clique_size, 1);
+}
+
 // One thread per parallel-tempering set: its L slots are distinct values in
 // [0, L) and its pass counter is not negative.
 __global__ void pt_check_kernel(int n_sets, int L, const int32_t *__restrict__ slot,
@@ -127,6 +154,13 @@ hipError_t launch_pt_check(hipStream_t st, int n_sets, int L, const int32_t *slo
 
 hipError_t launch_grid_check(hipStream_t st, int G, const float *grid, InstanceStats *out) {
     grid_check_kernel<<<(G + 255) / 256 < 64 ? (G + 255) / 256 : 64, 256, 0, st>>>(G, grid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clique_check(hipStream_t st, int N, const int32_t *F, int32_t *member,
+                               InstanceStats *out) {
+    clique_member_kernel<<<(N + 255) / 256, 256, 0, st>>>(N, F, member);
+    clique_check_kernel<<<(N + 255) / 256, 256, 0, st>>>(N, F, member, out);
     return hipGetLastError();
 }
 

@@ -215,6 +215,28 @@ def config_n256(R: int = 512, T: int = 100_000) -> Instance:
                     {"beta_rule": "geometric 0.5/s->2000/s", "scale": s})
 
 
+def clique_flows(N: int, members) -> np.ndarray:
+    """F[a][b] = 1 for two distinct facilities of the clique, 0 otherwise."""
+    c = np.zeros(N, dtype=np.int32)
+    c[np.asarray(members)] = 1
+    F = np.outer(c, c).astype(np.int32)
+    np.fill_diagonal(F, 0)
+    return F
+
+
+def config_clique256(R: int = 512, T: int = 10_000) -> Instance:
+    """N=256 with clique flows, a synthetic stand-in for tai256c (Methods):
+    D = Manhattan distances on a 16 x 16 grid, F = 1 between any two of the
+    first 92 facilities and 0 otherwise; geometric beta 0.5/s -> 2000/s."""
+    N = 256
+    D = grid_manhattan(N, 16)
+    F = clique_flows(N, np.arange(92))
+    s = energy_scale(D, F)
+    perms = random_perms(np.random.default_rng(PERM_SEED), R, N)
+    return Instance("qap_n256_clique92_grid16", D, F, perms, beta_geometric(0.5 / s, 2000.0 / s, T),
+                    {"beta_rule": "geometric 0.5/s->2000/s", "scale": s, "clique": 92})
+
+
 def config_n512(R: int = 256, T: int = 20_000) -> Instance:
     """N=512: D and F symmetric uniform integers in [0, 10^4] with 20% of
     entries zeroed; geometric beta 0.5/s -> 2000/s."""
