@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-replicas", type=int, default=32)
-    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512", "pt", "cupim"],
+    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512", "pt", "cupim", "clique"],
                     help="n64 is the benchmark configuration; the others report the same "
                          "fast-vs-plain comparison for the other workload shapes")
     ap.add_argument("--sweeps", type=int, default=0,
@@ -339,6 +339,59 @@ def cupim_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def clique_workload(args):
+    """The clique-flow sweep against the general on-chip kernel and the plain
+    path on the N=256 tai256c stand-in (16 x 16 grid distances, a clique of
+    92 facilities), 512 replicas, the first 2000 sweeps of its schedule (the
+    plain path: the first 100).  All three give identical results on the
+    common prefix.  One JSON line; not the benchmark figure."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit
+    from paper_2605_24408_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    inst = W.config_clique256()
+    N, R = inst.N, inst.R
+    T = args.sweeps or 2000
+    D = torch.from_numpy(inst.D).to(dev)
+    F = torch.from_numpy(inst.F).to(dev)
+    perm0 = torch.from_numpy(inst.perms).to(dev)
+    perm = perm0.clone()
+    out = {"workload": inst.name, "N": N, "replicas": R, "clique": 92,
+           "beta": "geometric 0.5/s -> 2000/s over 10^4 sweeps, prefix"}
+    finals = {}
+    for path, sweep, steps in (("clique", "clique", T), ("general", "fast", T),
+                               ("plain", "plain", min(T, 100))):
+        ctx = pdit.Pdit(sweep=sweep, recompute="auto" if sweep != "plain" else "plain")
+        beta = torch.from_numpy(inst.beta[:steps].copy()).to(dev)
+        best = None
+        for _ in range(2 if path != "plain" else 1):
+            perm.copy_(perm0)
+            ctx.set_sweep_offset(0)
+            ctx.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.run_sweeps(D, F, perm, beta, W.PHILOX_SEED)
+            e, _ = ctx.best()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        cnt = ctx.counters()
+        plan = ctx.last_plan()
+        finals[path] = (steps, perm.cpu().numpy().copy(), e.cpu().numpy())
+        out[path] = {"sweeps": steps, "updates_per_s": R * N * steps / best, "seconds": best,
+                     "kernel_ms": ctx.last_timing()[1], "plan": plan,
+                     "acceptance": cnt["accepted"] / max(cnt["updates"], 1),
+                     "best": int(e.min().item())}
+        ctx.close()
+    out["clique_vs_general"] = out["clique"]["updates_per_s"] / out["general"]["updates_per_s"]
+    out["clique_vs_plain"] = out["clique"]["updates_per_s"] / out["plain"]["updates_per_s"]
+    out["identical_clique_general"] = bool(np.array_equal(finals["clique"][1], finals["general"][1]))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -351,6 +404,9 @@ def main():
         return
     if args.workload == "cupim":
         cupim_workload(args)
+        return
+    if args.workload == "clique":
+        clique_workload(args)
         return
     if args.workload != "n64":
         other_workload(args)

@@ -86,9 +86,10 @@ extern "C" {
                                D[x][j] an exchange inside a class changes nothing and one across
                                the classes changes E by 2 (g(s) - g(r) - D[r][s]) (r in S), so a
                                candidate costs O(1) and an accepted move O(N).  Same dynamics and
-                               results as the other kernels.  AUTO and FAST pick it for N > 128
-                               when the data qualify; CLIQUE forces it (PDIT_EINVAL when they do
-                               not).  pdit_last_plan reports PDIT_SWEEP_CLIQUE. */
+                               results as the other kernels.  AUTO picks it for N > 128 when the
+                               data qualify (FAST keeps the general on-chip kernels); CLIQUE
+                               forces it (PDIT_EINVAL when they do not).  pdit_last_plan reports
+                               PDIT_SWEEP_CLIQUE. */
 
 typedef struct pdit_ctx pdit_t;
 

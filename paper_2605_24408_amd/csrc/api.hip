@@ -304,7 +304,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
 
     // clique flows are looked for where the table kernel does not apply
     const bool try_clique = ctx->opts.sweep == PDIT_SWEEP_CLIQUE ||
-                            (ctx->opts.sweep != PDIT_SWEEP_PLAIN && N > 128);
+                            (ctx->opts.sweep == PDIT_SWEEP_AUTO && N > 128);
     int rc = PDIT_OK;
     if (try_clique) {
         rc = ensure(ctx, ctx->clique_buf, sizeof(int32_t) * (size_t)N);

@@ -16,8 +16,10 @@
 //
 // One wave per replica, every location's state in registers: lane l holds
 // locations l, l + 64, ... (p, class bit, g); D rows are read from device
-// memory (shared by all replicas, so L2-resident), the next row in flight
-// while the current update draws.
+// memory (shared by all replicas, so L2-resident).  An exchange inside a
+// class changes no energy change of any row, so rows are drawn a few at a
+// time from one state and committed in order up to the first exchange across
+// the classes.
 #include "device_common.h"
 #include "pdit_internal.h"
 
@@ -39,17 +41,20 @@ __device__ __forceinline__ T pick(const T (&v)[CPL], int c) {
     return out;
 }
 
-template <int CPL, bool REC>
-__global__ void __launch_bounds__(64) sweep_clique_kernel(CliqueArgs a) {
+template <int CPL, int RB, bool REC>
+__global__ void __launch_bounds__(64 * RB) sweep_clique_kernel(CliqueArgs a) {
     using CT = typename std::conditional<(CPL == 1), uint32_t, uint64_t>::type;
+    __shared__ int32_t sm_sel[2][RB], sm_v[2][RB], sm_tie[2][RB];
     const int N = a.N;
     const int64_t rep = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    int par = 0;
     const int32_t *D = a.D;
     int32_t *perm = a.perm + rep * N;
     int32_t *pbest = a.perm_best + rep * N;
 
-    int32_t pv[CPL], g[CPL], Dr[CPL], Dn[CPL];
+    int32_t pv[CPL], g[CPL];
     bool in[CPL], valid[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -72,7 +77,7 @@ __global__ void __launch_bounds__(64) sweep_clique_kernel(CliqueArgs a) {
     for (int c = 0; c < CPL; ++c) E += in[c] ? (int64_t)g[c] : 0;
     for (int off = 32; off > 0; off >>= 1) E += __shfl_xor(E, off);
     int64_t E_best = a.init_best ? E : a.E_best[rep];
-    if (a.init_best)
+    if (a.init_best && wv == 0)
 #pragma unroll
         for (int c = 0; c < CPL; ++c)
             if (valid[c]) pbest[lane + 64 * c] = pv[c];
@@ -95,95 +100,123 @@ __global__ void __launch_bounds__(64) sweep_clique_kernel(CliqueArgs a) {
         for (int c = 0; c < CPL; ++c)
             u24l[c] = uniform24(a.seed, (uint32_t)(lane + 64 * c), gs, (uint32_t)rep, a.inst);
         int32_t *ch = (REC && a.choices) ? a.choices + (rep * a.T + t) * N : nullptr;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) Dn[c] = valid[c] ? D[lane + 64 * c] : 0;  // row 0
-        for (int r = 0; r < N; ++r) {
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) Dr[c] = Dn[c];
-            if (r + 1 < N) {
+        // Rows are drawn RB at a time, one per wave, from the same state: a
+        // draw depends only on g and the class bits, which an exchange inside
+        // a class leaves unchanged, so the rows of a batch up to its first
+        // exchange across the classes are exactly what the one-at-a-time sweep
+        // draws.  Every wave commits them in order on its own copy of the
+        // state; the next batch starts after that exchange.  Results pass
+        // through LDS by batch parity (a wave is at most one batch ahead).
+        int r0 = 0;
+        while (r0 < N) {
+            const int r = r0 + wv;
+            if (r < N) {
+                const int cr = r >> 6, lr = r & 63;
+                int32_t Drow[CPL];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    Dn[c] = valid[c] ? D[(int64_t)(r + 1) * N + lane + 64 * c] : 0;
-            }
-            const int cr = r >> 6, lr = r & 63;
-            const int32_t gr = __builtin_amdgcn_readlane(pick<CPL>(g, cr), lr);
-            const bool inr = __builtin_amdgcn_readlane((int)pick<CPL>(in, cr), lr) != 0;
-            // energy change of every candidate (the stay's and same-class ones are 0)
-            int32_t v[CPL];
-            int32_t lmin = kExcluded;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                int32_t d = 0;
-                if (in[c] != inr)
-                    d = inr ? 2 * (g[c] - gr - Dr[c]) : 2 * (gr - g[c] - Dr[c]);
-                v[c] = valid[c] ? d : kExcluded;
-                lmin = min(lmin, v[c]);
-            }
-            const int32_t mn = wave_min_i32(lmin);
-            CT C[CPL];
-            uint32_t q[CPL];
-            CT base = 0;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int32_t d = valid[c] ? v[c] - mn : 0;
-                q[c] = d == 0 ? kOne : 0u;
-                if (d > 0 && d < dthr) q[c] = gibbs_weight(beta, (float)d);
-                if (!valid[c]) q[c] = 0;
-                // one chunk of 64 weights sums to at most 2^31
-                C[c] = base + (CT)wave_scan_u32(q[c]);
-                base = (CT)readlane_u64((uint64_t)C[c], 63);
-            }
-            const CT Z = base;
-            const uint32_t ur24 = (uint32_t)__builtin_amdgcn_readlane((int32_t)pick<CPL>(u24l, cr), lr);
-            const CT thr = (CT)(((uint64_t)ur24 * Z) >> 24);
-            int s = -1;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const uint64_t hit = __ballot(C[c] > thr);
-                if (s < 0 && hit) s = 64 * c + __ffsll((unsigned long long)hit) - 1;
-            }
-            if (s < 0 || s >= N) s = r;  // unreachable: location N-1 holds C = Z > thr
-            const int cs = s >> 6, ls = s & 63;
-            const CT csel = (CT)readlane_u64((uint64_t)pick<CPL>(C, cs), ls);
-            const uint32_t qsel = (uint32_t)__builtin_amdgcn_readlane((int32_t)pick<CPL>(q, cs), ls);
-            const int32_t vsel = __builtin_amdgcn_readlane(pick<CPL>(v, cs), ls);
-            n_tie += is_tie(csel - qsel, csel, Z, ur24) ? 1 : 0;
-            if (REC && ch && lane == 0) ch[r] = s;
-            if (s == r) continue;
-            // ---- accept: E, p, and for a move across the classes S and g ----
-            ++n_acc;
-            E += vsel;
-            const bool ins = __builtin_amdgcn_readlane((int)pick<CPL>(in, cs), ls) != 0;
-            const int32_t pr = __builtin_amdgcn_readlane(pick<CPL>(pv, cr), lr);
-            const int32_t ps = __builtin_amdgcn_readlane(pick<CPL>(pv, cs), ls);
-            if (ins != inr) {
-                // r in S: S loses r, gains s, g += D[.][s] - D[.][r]; else the reverse
+                    Drow[c] = valid[c] ? D[(int64_t)r * N + lane + 64 * c] : 0;
+                const int32_t gr = __builtin_amdgcn_readlane(pick<CPL>(g, cr), lr);
+                const bool inr = __builtin_amdgcn_readlane((int)pick<CPL>(in, cr), lr) != 0;
+                // energy change of every candidate (the stay's and same-class ones are 0)
+                int32_t v[CPL];
+                int32_t lmin = kExcluded;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
-                    const int32_t dsx = valid[c] ? D[(int64_t)s * N + lane + 64 * c] : 0;
-                    g[c] += inr ? dsx - Dr[c] : Dr[c] - dsx;
+                    int32_t d = 0;
+                    if (in[c] != inr)
+                        d = inr ? 2 * (g[c] - gr - Drow[c]) : 2 * (gr - g[c] - Drow[c]);
+                    v[c] = valid[c] ? d : kExcluded;
+                    lmin = min(lmin, v[c]);
+                }
+                const int32_t mn = wave_min_i32(lmin);
+                CT C[CPL];
+                uint32_t q[CPL];
+                CT base = 0;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int32_t d = valid[c] ? v[c] - mn : 0;
+                    q[c] = d == 0 ? kOne : 0u;
+                    if (d > 0 && d < dthr) q[c] = gibbs_weight(beta, (float)d);
+                    if (!valid[c]) q[c] = 0;
+                    // one chunk of 64 weights sums to at most 2^31
+                    C[c] = base + (CT)wave_scan_u32(q[c]);
+                    base = (CT)readlane_u64((uint64_t)C[c], 63);
+                }
+                const CT Z = base;
+                const uint32_t ur24 =
+                    (uint32_t)__builtin_amdgcn_readlane((int32_t)pick<CPL>(u24l, cr), lr);
+                const CT thr = (CT)(((uint64_t)ur24 * Z) >> 24);
+                int sb = -1;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const uint64_t hit = __ballot(C[c] > thr);
+                    if (sb < 0 && hit) sb = 64 * c + __ffsll((unsigned long long)hit) - 1;
+                }
+                if (sb < 0 || sb >= N) sb = r;  // unreachable: location N-1 holds C = Z > thr
+                const int cs = sb >> 6, ls = sb & 63;
+                const CT csel = (CT)readlane_u64((uint64_t)pick<CPL>(C, cs), ls);
+                const uint32_t qsel = (uint32_t)__builtin_amdgcn_readlane((int32_t)pick<CPL>(q, cs), ls);
+                const int32_t vs = __builtin_amdgcn_readlane(pick<CPL>(v, cs), ls);
+                const bool tie = is_tie(csel - qsel, csel, Z, ur24);
+                if (lane == 0) {
+                    sm_sel[par][wv] = sb;
+                    sm_v[par][wv] = vs;
+                    sm_tie[par][wv] = tie ? 1 : 0;
                 }
             }
+            __syncthreads();
+            // commit in order, up to and including the first exchange across the classes
+            int next = r0 + RB;
+            for (int b = 0; b < RB; ++b) {
+                const int rb = r0 + b;
+                if (rb >= N || rb >= next) break;
+                const int sb = __builtin_amdgcn_readfirstlane(sm_sel[par][b]);
+                n_tie += __builtin_amdgcn_readfirstlane(sm_tie[par][b]);
+                if (REC && ch && wv == 0 && lane == 0) ch[rb] = sb;
+                if (sb == rb) continue;
+                ++n_acc;
+                const int cr = rb >> 6, lr = rb & 63, cs = sb >> 6, ls = sb & 63;
+                const bool inr = __builtin_amdgcn_readlane((int)pick<CPL>(in, cr), lr) != 0;
+                const bool ins = __builtin_amdgcn_readlane((int)pick<CPL>(in, cs), ls) != 0;
+                const int32_t pr = __builtin_amdgcn_readlane(pick<CPL>(pv, cr), lr);
+                const int32_t ps = __builtin_amdgcn_readlane(pick<CPL>(pv, cs), ls);
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int x = lane + 64 * c;
-                if (x == r) {
-                    pv[c] = ps;
-                    in[c] = ins;
-                } else if (x == s) {
-                    pv[c] = pr;
-                    in[c] = inr;
+                for (int c = 0; c < CPL; ++c) {
+                    const int x = lane + 64 * c;
+                    if (x == rb) {
+                        pv[c] = ps;
+                        in[c] = ins;
+                    } else if (x == sb) {
+                        pv[c] = pr;
+                        in[c] = inr;
+                    }
                 }
-            }
-            if (E < E_best) {
-                E_best = E;
+                if (ins == inr) continue;  // inside a class: E, S and g unchanged
+                // across the classes: r in S: S loses r, gains s, g += D[.][s] - D[.][r];
+                // else the reverse
+                E += __builtin_amdgcn_readfirstlane(sm_v[par][b]);
 #pragma unroll
-                for (int c = 0; c < CPL; ++c)
-                    if (valid[c]) pbest[lane + 64 * c] = pv[c];
+                for (int c = 0; c < CPL; ++c) {
+                    const int32_t drx = valid[c] ? D[(int64_t)rb * N + lane + 64 * c] : 0;
+                    const int32_t dsx = valid[c] ? D[(int64_t)sb * N + lane + 64 * c] : 0;
+                    g[c] += inr ? dsx - drx : drx - dsx;
+                }
+                if (E < E_best) {
+                    E_best = E;
+                    if (wv == 0)
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            if (valid[c]) pbest[lane + 64 * c] = pv[c];
+                }
+                next = rb + 1;
             }
+            r0 = next;
+            par ^= 1;
         }
-        if (REC && a.E_trace && lane == 0) a.E_trace[rep * a.T + t] = E;
+        if (REC && a.E_trace && wv == 0 && lane == 0) a.E_trace[rep * a.T + t] = E;
     }
+    if (wv != 0) return;  // every wave holds the same state
 #pragma unroll
     for (int c = 0; c < CPL; ++c)
         if (valid[c]) perm[lane + 64 * c] = pv[c];
@@ -198,10 +231,11 @@ __global__ void __launch_bounds__(64) sweep_clique_kernel(CliqueArgs a) {
 
 template <int CPL>
 hipError_t launch_cpl(hipStream_t s, const CliqueArgs &a) {
+    constexpr int RB = 4;  // rows drawn together, one wave each
     if (a.choices || a.E_trace)
-        sweep_clique_kernel<CPL, true><<<a.R, 64, 0, s>>>(a);
+        sweep_clique_kernel<CPL, RB, true><<<a.R, 64 * RB, 0, s>>>(a);
     else
-        sweep_clique_kernel<CPL, false><<<a.R, 64, 0, s>>>(a);
+        sweep_clique_kernel<CPL, RB, false><<<a.R, 64 * RB, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ def clique_instance(rng, N, m, kind):
     (20, 7, 4, 30, "uniform", "clique"), (64, 30, 3, 20, "grid", "clique"),
     (100, 1, 2, 10, "uniform", "clique"), (130, 50, 2, 12, "uniform", "auto"),
     (200, 199, 2, 8, "uniform", "auto"), (256, 92, 2, 8, "grid", "auto"),
-    (300, 120, 2, 5, "uniform", "fast"), (512, 200, 1, 3, "uniform", "auto")])
+    (300, 120, 2, 5, "uniform", "auto"), (512, 200, 1, 3, "uniform", "auto")])
 def test_clique_matches_oracle(N, m, R, T, kind, sweep):
     from paper_2605_24408_amd import pdit as P
     say(f"clique N={N} m={m} R={R} T={T} kind={kind} sweep={sweep}")
@@ -81,7 +81,8 @@ def test_clique_matches_oracle(N, m, R, T, kind, sweep):
 
 
 def test_clique_resume_and_auto_plan():
-    """Two calls equal one; N <= 128 keeps the table kernel under AUTO."""
+    """Two calls equal one; N <= 128 keeps the table kernel under AUTO, and
+    FAST keeps the general kernel, with the same results."""
     from paper_2605_24408_amd import pdit as P
     rng = np.random.default_rng(5)
     N = 160
@@ -96,6 +97,11 @@ def test_clique_resume_and_auto_plan():
         b = run_gpu(ctx, D, F, a["perm"], beta[4:], 2)
     for f in ("perm", "E", "E_best", "perm_best"):
         assert np.array_equal(one[f], b[f]), f
+    with P.Pdit(sweep="fast") as ctx:
+        gen = run_gpu(ctx, D, F, perms, beta, 2)
+    assert gen["plan"]["sweep"] == "fast" and one["plan"]["sweep"] == "clique"
+    for f in ("perm", "E", "E_best", "perm_best", "counters"):
+        assert np.array_equal(one[f], gen[f]), f
     D2, F2 = clique_instance(rng, 100, 40, "uniform")
     with P.Pdit() as ctx:
         got = run_gpu(ctx, D2, F2, W.random_perms(rng, 2, 100), beta[:2], 2)
