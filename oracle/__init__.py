@@ -75,7 +75,7 @@ def lib():
         L.po_run_pt.restype = C.c_int
         L.po_run_pt.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_int, i32p, f32p, i32p, i32p,
                                 C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
-                                C.c_int32, i64p, i64p, i32p, C.c_int, i64p]
+                                C.c_int32, i64p, i64p, i32p, C.c_int, i64p, C.c_int]
         u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
         L.po_cupim_resolve.restype = C.c_int
         L.po_cupim_resolve.argtypes = [C.c_int, i32p, i64p, u8p]
@@ -232,9 +232,11 @@ class PTResult:
 
 
 def run_pt(D, F, perm, ladder, n_periods, period_sweeps, timeout, seed, sweep_offset=0,
-           slot=None, since_top=None, E_best=None, perm_best=None, inst_id=0) -> PTResult:
+           slot=None, since_top=None, E_best=None, perm_best=None, inst_id=0,
+           method="sequential") -> PTResult:
     """Parallel tempering: sets of L = len(ladder) replicas (rows of perm in
-    order), n_periods periods of period_sweeps sweeps at each replica's slot
+    order), n_periods periods of period_sweeps sweeps (method "sequential")
+    or GPU-CUPIM iterations (method "cupim") at each replica's slot
     temperature, each followed by an exchange pass."""
     D, F = _i32(D), _i32(F)
     N = D.shape[0]
@@ -253,7 +255,7 @@ def run_pt(D, F, perm, ladder, n_periods, period_sweeps, timeout, seed, sweep_of
     counters = np.zeros((R, 3), dtype=np.int64)
     rc = lib().po_run_pt(N, D, F, R, L, p, ladder, sl, st, int(n_periods), int(period_sweeps),
                          int(timeout), int(seed), int(sweep_offset), int(inst_id), E, Eb, pb,
-                         int(init_best), counters)
+                         int(init_best), counters, {"sequential": 0, "cupim": 1}[method])
     if rc != PO_OK:
         raise RuntimeError(f"oracle parallel tempering failed with status {rc}")
     return PTResult(p, E, Eb, pb, counters, sl, st)

@@ -392,10 +392,17 @@ int po_pt_exchange(int L, const int64_t *E, int32_t *slot_of, int32_t *since_top
     return top;
 }
 
+int po_run_cupim(int N, const int32_t *D, const int32_t *F, int R, const int32_t *rep_ids,
+                 int32_t inst_id, int32_t *perm, const float *beta, int64_t T, uint64_t seed,
+                 uint64_t sweep_off, int64_t *E, int64_t *E_best, int32_t *perm_best,
+                 int init_best, int64_t *counters, int32_t *choices, unsigned char *won);
+
 /*
  * n_periods periods of `period_sweeps` sweeps, each followed by an exchange
  * pass in every set; replica k (set k / L) runs its sweeps at
- * ladder[slot_of[k]].  The arguments are those of po_run, plus:
+ * ladder[slot_of[k]], with the sequential sweep (method 0) or the GPU-CUPIM
+ * iteration (method 1; Methods, "GPU-CUPIM Algorithm": the same exchange
+ * rules).  The arguments are those of po_run, plus:
  *   L          replicas per set (R a multiple of L)
  *   ladder     [L] inverse temperatures of the slots, lowest first
  *   slot_of    [R] in/out: slot of each replica within its set
@@ -407,9 +414,10 @@ int po_run_pt(int N, const int32_t *D, const int32_t *F, int R, int L, int32_t *
               const float *ladder, int32_t *slot_of, int32_t *since_top, int64_t n_periods,
               int64_t period_sweeps, int32_t timeout, uint64_t seed, uint64_t sweep_off,
               int32_t inst_id, int64_t *E, int64_t *E_best, int32_t *perm_best, int init_best,
-              int64_t *counters)
+              int64_t *counters, int method)
 {
     if (N < 2 || R < 1 || L < 1 || R % L || n_periods < 0 || period_sweeps < 0 || !ladder ||
+        (method != 0 && method != 1) ||
         !slot_of || !since_top || !E || !E_best || !perm_best || !counters)
         return PO_EINVAL;
     float *b = (float *)malloc(sizeof(float) * (size_t)(period_sweeps > 0 ? period_sweeps : 1));
@@ -426,10 +434,16 @@ int po_run_pt(int N, const int32_t *D, const int32_t *F, int R, int L, int32_t *
             for (int64_t t = 0; t < period_sweeps; ++t) b[t] = ladder[sl];
             int64_t cnt[3];
             const int32_t rep = k;
-            rc = po_run(N, D, F, 1, &rep, inst_id, perm + (int64_t)k * N, b, period_sweeps, seed,
-                        sweep_off + (uint64_t)(per * period_sweeps), E + k, E_best + k,
-                        perm_best + (int64_t)k * N, init_best && per == 0, cnt, NULL, 0, NULL,
-                        NULL, NULL, 0);
+            if (method == 0)
+                rc = po_run(N, D, F, 1, &rep, inst_id, perm + (int64_t)k * N, b, period_sweeps,
+                            seed, sweep_off + (uint64_t)(per * period_sweeps), E + k, E_best + k,
+                            perm_best + (int64_t)k * N, init_best && per == 0, cnt, NULL, 0, NULL,
+                            NULL, NULL, 0);
+            else
+                rc = po_run_cupim(N, D, F, 1, &rep, inst_id, perm + (int64_t)k * N, b,
+                                  period_sweeps, seed, sweep_off + (uint64_t)(per * period_sweeps),
+                                  E + k, E_best + k, perm_best + (int64_t)k * N,
+                                  init_best && per == 0, cnt, NULL, NULL);
             for (int c = 0; c < 3; ++c) counters[3 * k + c] += cnt[c];
         }
         for (int s = 0; s < R / L && rc == PO_OK; ++s) {

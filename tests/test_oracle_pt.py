@@ -114,3 +114,44 @@ def test_reaches_the_brute_force_minimum():
     pt = oracle.run_pt(D, F, W.random_perms(rng, 6, N), W.beta_geometric(0.5 / s, 40.0 / s, 6),
                        60, 4, 100, 1)
     assert pt.E_best.min() == best
+
+
+def test_cupim_dynamics_single_rung_is_a_cupim_run():
+    """Parallel tempering with the GPU-CUPIM iteration (Methods, "GPU-CUPIM
+    Algorithm"): with L = 1 the run equals run_cupim at the rung's beta over
+    n_periods * period_sweeps iterations."""
+    rng = np.random.default_rng(11)
+    D, F = W.random_instance(rng, 10, 0, 9)
+    perms = W.random_perms(rng, 3, 10)
+    s = W.energy_scale(D, F)
+    b = np.float32(1.5 / s)
+    pt = oracle.run_pt(D, F, perms, [b], 5, 4, 2, 7, method="cupim")
+    ref = oracle.run_cupim(D, F, perms, np.full(20, b, np.float32), 7)
+    assert np.array_equal(pt.perm, ref.perm) and np.array_equal(pt.E, ref.E)
+    assert np.array_equal(pt.E_best, ref.E_best) and np.array_equal(pt.counters, ref.counters)
+
+
+def test_cupim_dynamics_compose_with_exchanges():
+    """One period by hand with the CUPIM iteration: every replica runs
+    run_cupim at its rung's beta, then each set's exchange pass."""
+    rng = np.random.default_rng(12)
+    N, L, sets, per = 9, 3, 2, 4
+    D, F = W.random_instance(rng, N, 0, 9)
+    perms = W.random_perms(rng, L * sets, N)
+    s = W.energy_scale(D, F)
+    ladder = W.beta_geometric(0.2 / s, 20.0 / s, L)
+    slot = np.array([1, 2, 0, 0, 2, 1], np.int32)
+    since = np.array([0, 3], np.int32)
+    pt = oracle.run_pt(D, F, perms, ladder, 1, per, 4, 3, sweep_offset=9, slot=slot,
+                       since_top=since, method="cupim")
+    perm = perms.copy()
+    E = np.zeros(L * sets, np.int64)
+    for k in range(L * sets):
+        r = oracle.run_cupim(D, F, perm[k:k + 1], np.full(per, ladder[slot[k]], np.float32), 3,
+                             sweep_offset=9, rep_ids=[k])
+        perm[k] = r.perm[0]
+        E[k] = r.E[0]
+    assert np.array_equal(pt.perm, perm) and np.array_equal(pt.E, E)
+    for g in range(sets):
+        sl, st, _ = oracle.pt_exchange(E[g * L:(g + 1) * L], slot[g * L:(g + 1) * L], since[g], 4)
+        assert np.array_equal(pt.slot[g * L:(g + 1) * L], sl) and pt.since_top[g] == st
