@@ -189,7 +189,14 @@ typedef struct {
     int32_t timeout;        /* passes without the top rung changing hands after which it trades
                                with the bottom rung (100 in the paper); <= 0: never */
     int32_t schedule;       /* PDIT_PT_AUTO, PDIT_PT_PERIODIC or PDIT_PT_FUSED (below) */
+    int32_t dynamics;       /* PDIT_PT_SEQUENTIAL: sweeps as in pdit_run_sweeps;
+                               PDIT_PT_CUPIM: iterations as in pdit_run_cupim (Methods,
+                               "GPU-CUPIM Algorithm": the same exchange rules), with its data
+                               limits (PDIT_EOVERFLOW otherwise) and the periodic schedule */
 } pdit_pt;
+
+#define PDIT_PT_SEQUENTIAL 0
+#define PDIT_PT_CUPIM 1
 
 /* How pdit_run_pt launches its work; every schedule gives the same results.
  *   PERIODIC  one sweep launch per period (each replica's state saved and

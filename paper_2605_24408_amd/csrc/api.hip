@@ -396,6 +396,62 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     return PDIT_OK;
 }
 
+// Parallel tempering with concurrent updates: one CUPIM launch per period
+// (each replica at its rung's beta; the kernel rebuilds its snapshot from p,
+// so nothing is saved between periods), then the exchange pass.
+int run_pt_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                 int32_t *perm, const pdit_pt *pt, int64_t n_periods, uint64_t seed,
+                 const InstanceStats &st) {
+    const int cls = pdit::cupim_class(N, st);
+    if (!cls)
+        return fail(ctx, PDIT_EOVERFLOW,
+                    "concurrent updates need N <= 128 and |D|, |F| <= 127 (int8 MFMA refresh)");
+    bool fresh = false;
+    int rc = shape_state(ctx, {N}, {R}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &S = ctx->st;
+    pdit::CupimArgs c{};
+    c.N = N;
+    c.R = R;
+    c.D = D;
+    c.F = F;
+    c.perm = perm;
+    c.E = S.E;
+    c.E_best = S.E_best;
+    c.perm_best = S.perm_best;
+    c.counters = S.counters;
+    c.beta = pt->beta;
+    c.slot = pt->slot;
+    c.T = pt->period_sweeps;
+    c.seed = seed;
+    c.inst_id = 0;
+    c.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
+    ctx->timed = false;
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    // with no period, one launch of no iterations still yields E and zero counters
+    const int64_t launches = n_periods > 0 ? n_periods : 1;
+    for (int64_t per = 0; per < launches; ++per) {
+        c.T = n_periods > 0 ? pt->period_sweeps : 0;
+        c.sweep_offset = ctx->sweep_offset + (uint64_t)(per * pt->period_sweeps);
+        c.init_best = (fresh && per == 0) ? 1 : 0;
+        c.accumulate = per > 0 ? 1 : 0;
+        PDIT_HIP(ctx, pdit::launch_cupim(ctx->stream, cls, c));
+        if (n_periods > 0)
+            PDIT_HIP(ctx, pdit::launch_pt_exchange(ctx->stream, R / pt->L, pt->L, S.E, pt->slot,
+                                                   pt->since_top, pt->timeout));
+    }
+    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    ctx->timed = true;
+    ctx->sweep_offset += (uint64_t)(n_periods * pt->period_sweeps);
+    ctx->last_updates = (int64_t)R * N * n_periods * pt->period_sweeps;
+    ctx->last_sweep = PDIT_SWEEP_FAST;
+    ctx->last_class = cls;
+    ctx->last_mode = 0;
+    S.best_valid = true;
+    return PDIT_OK;
+}
+
 int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                 int32_t *perm, const pdit_pt *pt, int64_t n_periods, uint64_t seed) {
     if (!ctx) return PDIT_EINVAL;
@@ -410,6 +466,10 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
         return fail(ctx, PDIT_EINVAL, "n_periods and period_sweeps must be >= 0");
     if (pt->schedule < PDIT_PT_AUTO || pt->schedule > PDIT_PT_FUSED)
         return fail(ctx, PDIT_EINVAL, "unknown parallel-tempering schedule");
+    if (pt->dynamics != PDIT_PT_SEQUENTIAL && pt->dynamics != PDIT_PT_CUPIM)
+        return fail(ctx, PDIT_EINVAL, "unknown parallel-tempering dynamics");
+    if (pt->dynamics == PDIT_PT_CUPIM && pt->schedule == PDIT_PT_FUSED)
+        return fail(ctx, PDIT_EINVAL, "concurrent-update tempering runs on the periodic schedule");
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for parallel tempering");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
@@ -422,6 +482,7 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     InstanceStats st;
     int rc = instance_prep(ctx, N, D, F, R, perm, pt->beta, pt->L, &st, pt);
     if (rc) return rc;
+    if (pt->dynamics == PDIT_PT_CUPIM) return run_pt_cupim(ctx, N, D, F, R, perm, pt, n_periods, seed, st);
     const int64_t bound = pdit::h_bound(st);
     const bool h64 = bound > INT32_MAX;
     const int fclass = pdit::fast_class(N, st);

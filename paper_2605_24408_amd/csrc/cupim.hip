@@ -189,7 +189,7 @@ __device__ __forceinline__ void cupim_replica(const CupimJob &a, CupimSmem<NMAX>
         const int slot = (int)(t & 63);
         if (slot == 0) {
             const int64_t tt = t + lane < a.T ? t + lane : a.T - 1;
-            bcache = a.beta[tt];
+            bcache = a.beta[tt * a.beta_stride];
             dcache = zero_weight_distance(bcache);
         }
         const float beta = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bcache), slot));
@@ -337,9 +337,10 @@ __device__ __forceinline__ void cupim_replica(const CupimJob &a, CupimSmem<NMAX>
             for (int w = 0; w < WPR; ++w) ties += sm.nwin[w];
             *a.E = E;
             *a.E_best = E_best;
-            a.counters[0] = (int64_t)N * a.T;
-            a.counters[1] = n_acc;
-            a.counters[2] = ties;
+            const int64_t keep = a.accumulate ? 1 : 0;  // parallel-tempering periods add up
+            a.counters[0] = keep * a.counters[0] + (int64_t)N * a.T;
+            a.counters[1] = keep * a.counters[1] + n_acc;
+            a.counters[2] = keep * a.counters[2] + ties;
         }
     }
 }
@@ -358,7 +359,10 @@ cupim_kernel(CupimArgs c) {
     j.E_best = c.E_best + rep;
     j.perm_best = c.perm_best + rep * c.N;
     j.counters = c.counters + 3 * rep;
-    j.beta = c.beta;
+    // parallel tempering: every iteration at the rung's beta
+    j.beta = c.slot ? c.beta + c.slot[rep] : c.beta;
+    j.beta_stride = c.slot ? 0 : 1;
+    j.accumulate = c.accumulate;
     j.T = c.T;
     j.seed = c.seed;
     j.sweep_offset = c.sweep_offset;

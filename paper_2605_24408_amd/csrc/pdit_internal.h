@@ -194,6 +194,8 @@ struct CupimArgs {
     uint32_t inst_id;
     bool zero_diag;
     int init_best;           // start the best state from the initial one
+    const int32_t *slot;     // parallel tempering: replica k runs at beta[slot[k]] (else beta[t])
+    int accumulate;          // add to the counters instead of overwriting them
 };
 struct CupimJob {
     int N;
@@ -204,13 +206,15 @@ struct CupimJob {
     int64_t *E_best;
     int32_t *perm_best;
     int64_t *counters;
-    const float *beta;
+    const float *beta;       // beta of iteration t is beta[t * beta_stride]
+    int64_t beta_stride;
     int64_t T;
     uint64_t seed;
     uint64_t sweep_offset;
     uint32_t rep;
     uint32_t inst;
     int init_best;
+    int accumulate;
 };
 // size class (16, 32, 64, 128) of the CUPIM kernel, 0 when it does not apply
 inline int cupim_class(int N, const InstanceStats &st) {

@@ -24,6 +24,7 @@ NMAX = 512
 RECOMPUTE = {"auto": 0, "plain": 1, "i8": 2, "bf16": 3, "split": 4}
 SWEEP = {"auto": 0, "plain": 1, "fast": 2, "clique": 3}
 PT_SCHEDULE = {"auto": 0, "periodic": 1, "fused": 2}
+PT_DYNAMICS = {"sequential": 0, "cupim": 1}
 
 
 class PditError(RuntimeError):
@@ -54,7 +55,7 @@ class _Instance(C.Structure):
 class _PT(C.Structure):
     _fields_ = [("L", C.c_int32), ("beta", C.c_void_p), ("slot", C.c_void_p),
                 ("since_top", C.c_void_p), ("period_sweeps", C.c_int64), ("timeout", C.c_int32),
-                ("schedule", C.c_int32)]
+                ("schedule", C.c_int32), ("dynamics", C.c_int32)]
 
 
 _lib = None
@@ -218,10 +219,12 @@ class Pdit:
 
     def run_pt(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor, beta: torch.Tensor,
                slot: torch.Tensor, since_top: torch.Tensor, n_periods: int, period_sweeps: int,
-               timeout: int, seed: int, schedule: str = "auto") -> None:
+               timeout: int, seed: int, schedule: str = "auto",
+               dynamics: str = "sequential") -> None:
         """pdit_run_pt: parallel tempering over sets of L = len(beta) rows of
         perm (slot, since_top and perm in/out); schedule "auto", "periodic"
-        (a launch per period) or "fused" (every period in one launch)."""
+        (a launch per period) or "fused" (every period in one launch);
+        dynamics "sequential" (sweeps) or "cupim" (concurrent updates)."""
         N = int(D.shape[0])
         for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"), (perm, torch.int32, "perm"),
                           (beta, torch.float32, "beta"), (slot, torch.int32, "slot"),
@@ -229,7 +232,7 @@ class Pdit:
             _check_dev(t, dt, nm, self.device)
         R = int(perm.shape[0])
         pt = _PT(int(beta.shape[0]), _ptr(beta), _ptr(slot), _ptr(since_top), int(period_sweeps),
-                 int(timeout), PT_SCHEDULE[schedule])
+                 int(timeout), PT_SCHEDULE[schedule], PT_DYNAMICS[dynamics])
         self._rc(self._L.pdit_run_pt(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), C.byref(pt),
                                      int(n_periods), int(seed)))
         self._last = (R, R * N, N)

@@ -21,14 +21,14 @@ def dev(a, dtype):
 
 
 def gpu_pt(ctx, D, F, perms, ladder, periods, per_sweeps, timeout, seed, slot=None, since=None,
-           schedule="auto"):
+           schedule="auto", dynamics="sequential"):
     L = len(ladder)
     R = perms.shape[0]
     p = dev(perms, torch.int32)
     sl = dev(np.tile(np.arange(L), R // L) if slot is None else slot, torch.int32)
     st = dev(np.zeros(R // L) if since is None else since, torch.int32)
     ctx.run_pt(dev(D, torch.int32), dev(F, torch.int32), p, dev(ladder, torch.float32), sl, st,
-               periods, per_sweeps, timeout, seed, schedule)
+               periods, per_sweeps, timeout, seed, schedule, dynamics)
     E_best, perm_best = ctx.best()
     return {"perm": p.cpu().numpy(), "E": ctx.energy().cpu().numpy(),
             "E_best": E_best.cpu().numpy(), "perm_best": perm_best.cpu().numpy(),
@@ -181,3 +181,54 @@ def test_pt_error_paths():
         with pytest.raises(P.PditError) as e:
             gpu_pt(ctx, D2, F2, W.random_perms(rng, 4, 140), ladder, 1, 1, 5, 1, schedule="fused")
         assert e.value.status == "PDIT_EINVAL"
+
+
+@pytest.mark.parametrize("N,L,sets,kind", [(12, 4, 3, "grid"), (40, 5, 2, "uniform"),
+                                           (64, 10, 2, "uniform"), (100, 3, 2, "diag"),
+                                           (128, 4, 1, "uniform")])
+def test_pt_cupim_matches_oracle(N, L, sets, kind):
+    """Parallel tempering with concurrent updates (Methods, "GPU-CUPIM
+    Algorithm") against the oracle's run_pt(method="cupim")."""
+    from paper_2605_24408_amd import pdit as P
+    say(f"pt cupim N={N} L={L} sets={sets} kind={kind}")
+    rng = np.random.default_rng(N * 5 + L)
+    if kind == "grid":
+        inst = W.config_n12(R=L * sets, T=1)
+        D, F = inst.D, inst.F
+    else:
+        D, F = W.random_instance(rng, N, 0, 99, zero_diag=(kind != "diag"))
+    perms = W.random_perms(rng, L * sets, N)
+    s = W.energy_scale(D, F)
+    ladder = W.beta_geometric(0.5 / s, 60.0 / s, L)
+    ref = oracle.run_pt(D, F, perms, ladder, 10, 4, 3, 23, method="cupim")
+    with P.Pdit() as ctx:
+        got = gpu_pt(ctx, D, F, perms, ladder, 10, 4, 3, 23, dynamics="cupim")
+    differ = compare(got, ref, L)
+    assert sets == 1 or len(differ) < sets
+    assert ref.counters[:, 1].sum() > 0
+
+
+def test_pt_cupim_resume_and_errors():
+    from paper_2605_24408_amd import pdit as P
+    rng = np.random.default_rng(8)
+    N, L = 30, 5
+    D, F = W.random_instance(rng, N, 0, 50)
+    perms = W.random_perms(rng, 2 * L, N)
+    s = W.energy_scale(D, F)
+    ladder = W.beta_geometric(0.5 / s, 30.0 / s, L)
+    with P.Pdit() as ctx:
+        one = gpu_pt(ctx, D, F, perms, ladder, 8, 3, 2, 5, dynamics="cupim")
+    with P.Pdit() as ctx:
+        a = gpu_pt(ctx, D, F, perms, ladder, 5, 3, 2, 5, dynamics="cupim")
+        b = gpu_pt(ctx, D, F, a["perm"], ladder, 3, 3, 2, 5, slot=a["slot"], since=a["since_top"],
+                   dynamics="cupim")
+    for f in ("perm", "E", "E_best", "perm_best", "slot", "since_top"):
+        assert np.array_equal(one[f], b[f]), f
+    with P.Pdit() as ctx:
+        with pytest.raises(P.PditError) as e:
+            gpu_pt(ctx, D, F, perms, ladder, 1, 1, 2, 1, schedule="fused", dynamics="cupim")
+        assert e.value.status == "PDIT_EINVAL"
+        D2, F2 = W.random_instance(rng, N, 0, 300)
+        with pytest.raises(P.PditError) as e:
+            gpu_pt(ctx, D2, F2, perms, ladder, 1, 1, 2, 1, dynamics="cupim")
+        assert e.value.status == "PDIT_EOVERFLOW"
