@@ -171,7 +171,7 @@ def pt_workload(args):
            "mean_ending_energy": (E_sum.cpu().numpy() / trial_R).tolist(),
            "ladder": ladder.cpu().numpy().tolist()}
 
-    def run_pt(record, schedule="fused"):
+    def run_pt(record, schedule="fused", dynamics="sequential"):
         perm.copy_(perm0)
         slot.copy_(torch.arange(L, dtype=torch.int32, device=dev).repeat(sets))
         since.zero_()
@@ -184,7 +184,8 @@ def pt_workload(args):
         done = 0
         while done < n_periods:
             k = min(per_chunk, n_periods - done)
-            ctx.run_pt(D, F, perm, ladder, slot, since, k, period, timeout, seed, schedule)
+            ctx.run_pt(D, F, perm, ladder, slot, since, k, period, timeout, seed, schedule,
+                       dynamics)
             done += k
             if record:
                 e, _ = ctx.best()
@@ -221,6 +222,9 @@ def pt_workload(args):
     cnt = ctx.counters()
     run_pt(False, "periodic")
     t_per, eb_per, _ = run_pt(False, "periodic")
+    run_pt(False, "periodic", "cupim")
+    t_cu, eb_cu, _ = run_pt(False, "periodic", "cupim")
+    _, _, c_cu = run_pt(True, "periodic", "cupim")
     schedules = {"benchmark schedule 0.001 -> 1.0":
                  torch.from_numpy(inst.beta[:T].copy()).to(dev),
                  "selected range": torch.from_numpy(
@@ -248,8 +252,14 @@ def pt_workload(args):
                  "schedule": "fused (one cooperative launch, sets meet on the device)",
                  "periodic_schedule": {"updates_per_s": upd / t_per, "seconds": t_per,
                                        "identical_best": bool(np.array_equal(eb_per, eb_pt))}}
+    out["pt_cupim"] = {"updates_per_s": upd / t_cu, "seconds": t_cu, "best": int(eb_cu.min()),
+                       "mean_ladder_best": float(eb_cu.reshape(sets, L).min(axis=1).mean()),
+                       "curve": c_cu, "reaches_pt_best": reach(c_cu, int(eb_pt.min())),
+                       "schedule": "periodic, concurrent updates (GPU-CUPIM)"}
+    out["pt"]["reaches_pt_cupim_best"] = reach(c_pt, int(eb_cu.min()))
     for name, (t_an, eb_an, c_an) in anneal.items():
         out["pt"]["reaches_best_of_anneal_" + name] = reach(c_pt, int(eb_an.min()))
+        out["pt_cupim"]["reaches_best_of_anneal_" + name] = reach(c_cu, int(eb_an.min()))
         out["anneal " + name] = {"updates_per_s": R * N * T / t_an, "seconds": t_an,
                                  "best": int(eb_an.min()), "mean_best": float(eb_an.mean()),
                                  "curve": c_an, "reaches_pt_best": reach(c_an, int(eb_pt.min()))}
