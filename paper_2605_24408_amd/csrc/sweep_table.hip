@@ -331,13 +331,17 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
             T[r * PT + t] = -dE;
             T[t * PT + r] = -dE;
         }
-        // Fp' rows and columns r, t from the buffer; p(r) <-> p(t)
-        for (int x = tid; x < N; x += NT) {
-            const int16_t fr = (int16_t)sm.fnew[0][x], ft = (int16_t)sm.fnew[1][x];
-            Fp[r * PD + x] = fr;
-            Fp[x * PD + r] = fr;
-            Fp[t * PD + x] = ft;
-            Fp[x * PD + t] = ft;
+        // Fp' rows and columns r, t from the buffer, one store per thread
+        // across all waves (where a row and a column meet they carry the same
+        // value: Fp' is symmetric); p(r) <-> p(t)
+        for (int e = tid; e < 4 * N; e += NT) {
+            const int kind = e / N, x = e - kind * N;
+            const int16_t v = (int16_t)sm.fnew[kind >> 1][x];
+            const int w = kind < 2 ? r : t;
+            if (kind & 1)
+                Fp[x * PD + w] = v;
+            else
+                Fp[w * PD + x] = v;
         }
         if (tid == 0) {
             const int32_t fa = pv[r], fb = pv[t];
