@@ -1033,7 +1033,7 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
     if (rc == PDIT_OK) rc = pdit_create(&tmp, &o);
     // resident workgroups per CU to try: up to the most any kernel of the batch allows
     int max_bpc = pdit::plain_blocks_per_cu(false);
-    for (int nmax : {16, 32, 64, 128, 160, 256}) max_bpc = std::max(max_bpc, pdit::fast_blocks_per_cu(nmax));
+    for (int nmax : {16, 32, 64, 96, 128, 160, 256}) max_bpc = std::max(max_bpc, pdit::fast_blocks_per_cu(nmax));
     max_bpc = std::min(max_bpc, 4);
     pdit_tuning best{0, 0, 1e300};
     hipEvent_t e0 = nullptr, e1 = nullptr;

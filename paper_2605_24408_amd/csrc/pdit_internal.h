@@ -163,7 +163,13 @@ constexpr uint32_t kSaveState = 2;      // save the state at the end (table: tst
 constexpr uint32_t kAccumCounters = 4;  // add to the counters instead of overwriting them
 // int32 words of one replica's saved table state: the table (NMAX x (NMAX+4))
 // and diag H (NMAX) of its size class
-__host__ __device__ inline int64_t table_state_words(int nmax) { return (int64_t)nmax * (nmax + 4) + nmax; }
+// Row pitch (int32) of the table kernel's table: N + 4 keeps a row quarter
+// on distinct banks; at 96 the unpadded pitch already does (rows of 96 words
+// start 32 banks apart), and it keeps two replicas of that class per CU.
+__host__ __device__ constexpr int table_pitch(int nmax) { return nmax == 96 ? 96 : nmax + 4; }
+__host__ __device__ inline int64_t table_state_words(int nmax) {
+    return (int64_t)nmax * table_pitch(nmax) + nmax;
+}
 
 constexpr int kFastNMax = 256;            // largest N of the on-chip kernel
 // Accepted moves in a sweep above which the fast kernels run the next sweep
@@ -253,7 +259,7 @@ inline bool clique_fits(int N, const InstanceStats &st) {
 hipError_t launch_sweep_clique(hipStream_t s, const CliqueArgs &a);
 
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
-// size class of the on-chip kernel that runs an instance (16, 32, 64, 128,
+// size class of the on-chip kernel that runs an instance (16, 32, 64, 96, 128,
 // 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic
 int fast_class(int N, const InstanceStats &st);
 hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a);

@@ -7,10 +7,8 @@
 // NMAX/16 waves; wave w owns the 16 locations 16w..16w+15 and the lanes of a
 // quad split the candidates of one location four ways.
 //
-// Size classes:
-//   NMAX = 16, 32, 64, 128: 2H int32, D and the permuted flows Fp = F[p,p]
-//     (int16) in LDS too; four replicas of N = 64 share a CU with four waves
-//     per SIMD, one replica of N = 128 fills a CU's LDS;
+// Size classes (N <= 128 runs on the table kernel, sweep_table.hip; this
+// file also holds the class choice and the dispatch):
 //   NMAX = 160 (2H int32) and 256 (2H int16, for instances whose exact bound
 //     allows it): only H and per-location arrays in LDS, D and F read from
 //     device memory (shared by all replicas, so they stay in L2).
@@ -603,7 +601,7 @@ int fast_class(int N, const InstanceStats &st) {
     if (N <= 128) {
         // D and F[p,p] in int16
         if (st.max_abs_d > 32767 || st.max_abs_f > 32767) return 0;
-        return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : 128;
+        return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : N <= 96 ? 96 : 128;
     }
     if (N <= 160) return 160;
     // 2H in int16

@@ -67,7 +67,7 @@ __device__ __forceinline__ int32_t dot2(uint32_t x, uint32_t y, int32_t acc) {
 
 template <int NMAX>
 struct TableSmem {
-    static constexpr int PT = NMAX + 4;  // table row pitch (int32), rows 16-byte aligned
+    static constexpr int PT = table_pitch(NMAX);  // table row pitch (int32), rows 16-byte aligned
     static constexpr int PD = NMAX + 8;  // D and Fp row pitch (int16), rows 16-byte aligned
     int32_t T[NMAX * PT];                // T[l][s]; kBig on the diagonal and outside N x N
     int16_t Ds[NMAX * PD];               // D
@@ -218,9 +218,13 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
             const int frow = vec < 2 ? px : vec == 2 ? t : r;
             const int16_t *pu = Ds + urow * PD;
             const int16_t *pf = Fp + frow * PD;
-            uint4 xu[NMAX / 8], xf[NMAX / 8];
+            // the two rows in chunks of at most 8 x 16 bytes (up to 64 VGPRs
+            // in flight: all of a row at N <= 64)
+            constexpr int NK = NMAX / 8;
+            constexpr int CH = NK < 8 ? NK : 8;
+            uint4 xu[CH], xf[CH];
 #pragma unroll
-            for (int k = 0; k < NMAX / 8; ++k) {
+            for (int k = 0; k < CH; ++k) {
                 xu[k] = *reinterpret_cast<const uint4 *>(pu + 8 * k);
                 xf[k] = *reinterpret_cast<const uint4 *>(pf + 8 * k);
             }
@@ -233,11 +237,21 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
             const int32_t hdx = hd[x];
             int32_t acc = 0;
 #pragma unroll
-            for (int k = 0; k < NMAX / 8; ++k) {
-                acc = dot2(xu[k].x, xf[k].x, acc);
-                acc = dot2(xu[k].y, xf[k].y, acc);
-                acc = dot2(xu[k].z, xf[k].z, acc);
-                acc = dot2(xu[k].w, xf[k].w, acc);
+            for (int k0 = 0; k0 < NK; k0 += CH) {
+                if (k0 > 0) {
+#pragma unroll
+                    for (int k = 0; k < CH && k0 + k < NK; ++k) {
+                        xu[k] = *reinterpret_cast<const uint4 *>(pu + 8 * (k0 + k));
+                        xf[k] = *reinterpret_cast<const uint4 *>(pf + 8 * (k0 + k));
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < CH && k0 + k < NK; ++k) {
+                    acc = dot2(xu[k].x, xf[k].x, acc);
+                    acc = dot2(xu[k].y, xf[k].y, acc);
+                    acc = dot2(xu[k].z, xf[k].z, acc);
+                    acc = dot2(xu[k].w, xf[k].w, acc);
+                }
             }
             const int32_t h = (int32_t)((uint32_t)acc + (uint32_t)du * (uint32_t)df);
             if (x < N) {
@@ -751,10 +765,11 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
 }
 
 // Waves per SIMD: four replicas of N <= 64 share a CU (one wave per SIMD
-// each at N = 64), one replica of N = 128 fills a CU's LDS.
+// each at N = 64), two of N <= 96 (six waves each), one of N = 128 fills a
+// CU's LDS.
 template <int NMAX>
 constexpr int table_waves_per_eu() {
-    return NMAX <= 64 ? 4 : 2;
+    return NMAX <= 64 ? 4 : NMAX <= 96 ? 3 : 2;
 }
 
 // Replica rep's job in a single-instance launch.
@@ -909,6 +924,7 @@ hipError_t launch_sweep_table(hipStream_t s, int nmax, const SweepArgs &a) {
         case 16: return launch_nmax<16>(s, a);
         case 32: return launch_nmax<32>(s, a);
         case 64: return launch_nmax<64>(s, a);
+        case 96: return launch_nmax<96>(s, a);
         case 128: return launch_nmax<128>(s, a);
         default: return hipErrorInvalidValue;
     }
@@ -920,6 +936,7 @@ hipError_t launch_sweep_table_persistent(hipStream_t s, int nmax, bool zd, const
         case 16: return launch_persistent_nmax<16>(s, zd, b, grid);
         case 32: return launch_persistent_nmax<32>(s, zd, b, grid);
         case 64: return launch_persistent_nmax<64>(s, zd, b, grid);
+        case 96: return launch_persistent_nmax<96>(s, zd, b, grid);
         case 128: return launch_persistent_nmax<128>(s, zd, b, grid);
         default: return hipErrorInvalidValue;
     }
@@ -934,6 +951,7 @@ hipError_t launch_sweep_table_pt(hipStream_t s, int nmax, const SweepArgs &args,
         case 16: return launch_pt_nmax<16>(s, a, p, num_cus);
         case 32: return launch_pt_nmax<32>(s, a, p, num_cus);
         case 64: return launch_pt_nmax<64>(s, a, p, num_cus);
+        case 96: return launch_pt_nmax<96>(s, a, p, num_cus);
         case 128: return launch_pt_nmax<128>(s, a, p, num_cus);
         default: return hipErrorInvalidValue;
     }
@@ -944,6 +962,7 @@ int table_blocks_per_cu(int nmax) {
         case 16: return persistent_blocks_per_cu<16>();
         case 32: return persistent_blocks_per_cu<32>();
         case 64: return persistent_blocks_per_cu<64>();
+        case 96: return persistent_blocks_per_cu<96>();
         case 128: return persistent_blocks_per_cu<128>();
         default: return 1;
     }
