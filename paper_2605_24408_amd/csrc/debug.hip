@@ -45,13 +45,13 @@ __global__ void __launch_bounds__(64) choice_kernel(int N, const int64_t *__rest
     for (int off = 32; off > 0; off >>= 1) lmin = min(lmin, (int64_t)__shfl_xor(lmin, off));
     const int64_t m = lmin;
     const float b = beta[row];
-    const int32_t dthr = zero_weight_distance(b);
+    const int64_t dthr = zero_weight_distance64(b);
     uint64_t part = 0;
     for (int j = 0; j < J; ++j) {
         const int s = lane * J + j;
         if (s < N) {
             const int64_t d = dr[s] - m;
-            part += d < (int64_t)dthr ? gibbs_weight(b, (float)d) : 0u;
+            part += d < dthr ? gibbs_weight(b, (float)d) : 0u;
         }
     }
     const uint64_t incl = wave_scan_u64(part);
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(64) choice_kernel(int N, const int64_t *__rest
         const int s = lane * J + j;
         if (s < N) {
             const int64_t d = dr[s] - m;
-            const uint64_t q = d < (int64_t)dthr ? gibbs_weight(b, (float)d) : 0u;
+            const uint64_t q = d < dthr ? gibbs_weight(b, (float)d) : 0u;
             const uint64_t prev = C;
             C += q;
             if (prev <= thr && C > thr) {

@@ -62,12 +62,23 @@ __device__ __forceinline__ uint32_t gibbs_weight(float beta, float d) {
 // fl32(beta * fl32(d)) >= 19.5 for all d >= the returned value
 // (e^-19.5 * 2^25 < 0.12 rounds to 0).  The hardware reciprocal (error
 // within 1 ulp) and the rounding of beta * d are covered by the 1e-4 margin
-// and the +2.  Returns INT32_MAX when no such integer is in range.
+// and the +2.  Returns INT32_MAX when no such integer is in range: only for
+// kernels whose distances stay below 2^31 - 1.
 __device__ __forceinline__ int32_t zero_weight_distance(float beta) {
     if (!(beta > 0.0f)) return INT32_MAX;
     const float t = (19.5f * 1.0001f) * __builtin_amdgcn_rcpf(beta) + 2.0f;
     if (!(t < 2.0e9f)) return INT32_MAX;
     return (int32_t)t;
+}
+
+// The same bound for kernels whose distances are int64 (they may pass 2^31):
+// INT64_MAX when beta is 0 or so small that no int64 distance reaches it, so
+// that a distance is never cut that the weight formula does not round to 0.
+__device__ __forceinline__ int64_t zero_weight_distance64(float beta) {
+    if (!(beta > 0.0f)) return INT64_MAX;
+    const float t = (19.5f * 1.0001f) * __builtin_amdgcn_rcpf(beta) + 2.0f;
+    if (!(t < 9.0e18f)) return INT64_MAX;
+    return (int64_t)t;
 }
 
 // Tie test shared by the kernels: the threshold u24*Z lies within Z*2^4 of a

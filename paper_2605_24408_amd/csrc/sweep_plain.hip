@@ -63,7 +63,7 @@ __device__ void plain_replica(const ReplicaJob &a, PlainSmem &sm) {
     for (int64_t t = 0; t < a.T; ++t) {
         const float beta = a.beta[t * a.beta_stride];
         const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
-        const int32_t dthr = zero_weight_distance(beta);
+        const int64_t dthr = zero_weight_distance64(beta);
         for (int r = 0; r < N; ++r) {
             // ---- energy change of every candidate (Eq. 3) ----
             const int fa = p[r];
@@ -89,7 +89,7 @@ __device__ void plain_replica(const ReplicaJob &a, PlainSmem &sm) {
             // ---- Gibbs weights and their running sum (Eq. 5) ----
             for (int s = tid; s < N; s += nt) {
                 const int64_t d = dE[s] - m;
-                C[s] = d < (int64_t)dthr ? gibbs_weight(beta, (float)d) : 0u;
+                C[s] = d < dthr ? gibbs_weight(beta, (float)d) : 0u;
             }
             __syncthreads();
             for (int off = 1; off < N; off <<= 1) {
