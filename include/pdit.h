@@ -72,7 +72,8 @@ extern "C" {
 #define PDIT_RECOMPUTE_SPLIT 4  /* int8 MFMA on 7-bit byte planes, int64 combine: needs |D|,|F| < 2^14 */
 
 /* Which sweep kernel runs. */
-#define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else plain */
+#define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else large (pdit_run_sweeps,
+                               pdit_beta_select) or plain (the other entry points) */
 #define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
 #define PDIT_SWEEP_FAST 2   /* replica state on chip, speculative row evaluation; needs
                                |dE| < 2^30 - 1 and N <= 256.  N <= 128: the table of swap energy
@@ -90,6 +91,16 @@ extern "C" {
                                data qualify (FAST keeps the general on-chip kernels); CLIQUE
                                forces it (PDIT_EINVAL when they do not).  pdit_last_plan reports
                                PDIT_SWEEP_CLIQUE. */
+#define PDIT_SWEEP_LARGE 4  /* no stored H, any N <= PDIT_NMAX: for the update of location r
+                               (Eq. 3 with I = -2H, H = D F[p,p]) column r of H is recomputed as
+                               D f with f = F[p(r)][p(.)], row r as F^T applied to row r of D
+                               ordered by facility (2 N^2 multiply-adds on rows of D and F that
+                               all replicas share through the cache), diag H is kept on chip and
+                               moved in O(N) per accepted exchange.  512 threads per replica.
+                               Same dynamics and results as the other kernels.  AUTO picks it
+                               in pdit_run_sweeps and pdit_beta_select when the fast kernel
+                               does not fit; parallel tempering and batched runs reject it
+                               (PDIT_EINVAL). */
 
 typedef struct pdit_ctx pdit_t;
 
@@ -370,9 +381,10 @@ int pdit_debug_choice(pdit_t *ctx, int32_t N, int32_t M, const int64_t *delta, c
  * the H recompute, sweep_ms the sweep kernel.  Either pointer may be NULL. */
 int pdit_last_timing(pdit_t *ctx, double *recompute_ms, double *sweep_ms);
 
-/* What the last single-instance run used: *sweep is PDIT_SWEEP_PLAIN or
- * PDIT_SWEEP_FAST, *size_class the on-chip kernel's size class (16, 32, 64,
- * 128, 160 or 256; 0 for the plain kernel), *recompute the PDIT_RECOMPUTE_*
+/* What the last single-instance run used: *sweep is PDIT_SWEEP_PLAIN,
+ * PDIT_SWEEP_FAST, PDIT_SWEEP_CLIQUE or PDIT_SWEEP_LARGE, *size_class the
+ * on-chip kernel's size class (16, 32, 64, 96, 128, 160 or 256; 0 for the
+ * other kernels), *recompute the PDIT_RECOMPUTE_*
  * mode of the H recompute.  Any pointer may be NULL. */
 int pdit_last_plan(pdit_t *ctx, int *sweep, int *size_class, int *recompute);
 

@@ -233,6 +233,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->pt_buf.ptr);
     hipFree(ctx->trial_buf.ptr);
     hipFree(ctx->clique_buf.ptr);
+    hipFree(ctx->large_buf.ptr);
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
@@ -298,7 +299,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
     if (R < 1) return fail(ctx, PDIT_EINVAL, "R must be >= 1");
     if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
-    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_CLIQUE)
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_LARGE)
         return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
@@ -334,12 +335,20 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
         use_fast = fclass != 0;
     }
+    // without a fast class the kernel that stores no H replaces the plain one
+    const bool use_large = ctx->opts.sweep == PDIT_SWEEP_LARGE ||
+                           (ctx->opts.sweep == PDIT_SWEEP_AUTO && !use_fast);
     int mode = 0;
     rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
     if (rc) return rc;
 
     rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
     if (rc) return rc;
+    const pdit::LargePlan lplan = use_large ? pdit::large_plan(N, st) : pdit::LargePlan{};
+    if (use_large) {
+        rc = ensure(ctx, ctx->large_buf, lplan.bytes);
+        if (rc) return rc;
+    }
     bool fresh = false;
     rc = shape_state(ctx, {N}, {R}, &fresh);
     if (rc) return rc;
@@ -348,6 +357,10 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->timed = false;
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
+    pdit::LargeCopies lcopy;
+    if (use_large)
+        PDIT_HIP(ctx, pdit::launch_large_copy(ctx->stream, N, D, F, lplan, ctx->large_buf.ptr,
+                                              &lcopy));
     if (fresh) {
         PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * R, hipMemcpyDeviceToDevice,
                                      ctx->stream));
@@ -378,6 +391,8 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (n_sweeps > 0) {
         if (use_fast)
             PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
+        else if (use_large)
+            PDIT_HIP(ctx, pdit::launch_sweep_large(ctx->stream, a, h64, lplan, lcopy));
         else
             PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
     } else {
@@ -389,7 +404,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->rec_trace = nullptr;
     ctx->sweep_offset += (uint64_t)n_sweeps;
     ctx->last_updates = (int64_t)R * N * n_sweeps;
-    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
+    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : use_large ? PDIT_SWEEP_LARGE : PDIT_SWEEP_PLAIN;
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
@@ -476,7 +491,9 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
         return fail(ctx, PDIT_EINVAL,
                     ctx->opts.sweep == PDIT_SWEEP_CLIQUE
                         ? "the clique kernel runs only in pdit_run_sweeps"
-                        : "unknown sweep kernel");
+                        : ctx->opts.sweep == PDIT_SWEEP_LARGE
+                              ? "the large kernel runs only in pdit_run_sweeps and pdit_beta_select"
+                              : "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
     InstanceStats st;
@@ -678,7 +695,8 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     if (trial_sweeps < 0) return fail(ctx, PDIT_EINVAL, "trial_sweeps must be >= 0");
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for beta selection");
-    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_LARGE ||
+        ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL,
                     ctx->opts.sweep == PDIT_SWEEP_CLIQUE
                         ? "the clique kernel runs only in pdit_run_sweeps"
@@ -701,6 +719,9 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
         use_fast = fclass != 0;
     }
+    // without a fast class the kernel that stores no H replaces the plain one
+    const bool use_large = ctx->opts.sweep == PDIT_SWEEP_LARGE ||
+                           (ctx->opts.sweep == PDIT_SWEEP_AUTO && !use_fast);
     int mode = 0;
     rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
     if (rc) return rc;
@@ -709,6 +730,11 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     if (rc) return rc;
     rc = ensure(ctx, ctx->trial_buf, sizeof(int32_t) * (size_t)RT * (N + 1));
     if (rc) return rc;
+    const pdit::LargePlan lplan = use_large ? pdit::large_plan(N, st) : pdit::LargePlan{};
+    if (use_large) {
+        rc = ensure(ctx, ctx->large_buf, lplan.bytes);
+        if (rc) return rc;
+    }
     int32_t *tperm = (int32_t *)ctx->trial_buf.ptr;
     int32_t *tslot = tperm + (size_t)RT * N;
     ctx->st.best_valid = false;  // the trials start their own best states
@@ -721,6 +747,10 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     PDIT_HIP(ctx, pdit::launch_trial_setup(ctx->stream, N, R, G, perm, tperm, tslot));
     PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, RT, tperm, ctx->h_buf.ptr, h64, S.E));
+    pdit::LargeCopies lcopy;
+    if (use_large)
+        PDIT_HIP(ctx, pdit::launch_large_copy(ctx->stream, N, D, F, lplan, ctx->large_buf.ptr,
+                                              &lcopy));
     PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * RT, hipMemcpyDeviceToDevice,
                                  ctx->stream));
     PDIT_HIP(ctx, hipMemcpyAsync(S.perm_best, tperm, sizeof(int32_t) * (size_t)RT * N,
@@ -748,6 +778,8 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     if (trial_sweeps > 0) {
         if (use_fast)
             PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
+        else if (use_large)
+            PDIT_HIP(ctx, pdit::launch_sweep_large(ctx->stream, a, h64, lplan, lcopy));
         else
             PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
     } else {
@@ -758,7 +790,7 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     PDIT_HIP(ctx, pdit::launch_beta_rule(ctx->stream, G, E_sum, grid, L, ladder, range));
     ctx->timed = true;
     ctx->last_updates = (int64_t)RT * N * trial_sweeps;
-    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
+    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : use_large ? PDIT_SWEEP_LARGE : PDIT_SWEEP_PLAIN;
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
@@ -777,7 +809,9 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         return fail(ctx, PDIT_EINVAL,
                     ctx->opts.sweep == PDIT_SWEEP_CLIQUE
                         ? "the clique kernel runs only in pdit_run_sweeps"
-                        : "unknown sweep kernel");
+                        : ctx->opts.sweep == PDIT_SWEEP_LARGE
+                              ? "the large kernel runs only in pdit_run_sweeps and pdit_beta_select"
+                              : "unknown sweep kernel");
     for (int k = 0; k < n_inst; ++k) {
         const pdit_instance &in = inst[k];
         if (in.N < 2 || in.N > PDIT_NMAX || in.R < 1)

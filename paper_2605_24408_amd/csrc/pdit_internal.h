@@ -77,6 +77,7 @@ struct pdit_ctx {
     pdit::DeviceBuffer pt_buf;        // fused parallel tempering: published energy words
     pdit::DeviceBuffer trial_buf;     // beta selection: trial permutations and their slots
     pdit::DeviceBuffer clique_buf;    // clique flows: membership of each facility
+    pdit::DeviceBuffer large_buf;     // the large kernel's padded copies of D and F
     int coop = 0;                     // the device supports cooperative launches
     int wall_clock_khz = 0;
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
@@ -259,6 +260,25 @@ inline bool clique_fits(int N, const InstanceStats &st) {
 hipError_t launch_sweep_clique(hipStream_t s, const CliqueArgs &a);
 
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
+// The kernel that stores no H (any N <= kLargeNMax, 512 threads per replica):
+// reads diag H of the initial p from a.H (int64 when h64), never writes a.H.
+// Its products read padded copies of D and F made by launch_large_copy.
+constexpr int kLargeNMax = 512;
+struct LargePlan {
+    bool narrow = false;  // int32 partial sums of 24-bit products
+    int elem = 4;         // bytes per element of the copies (2: int16)
+    int rows = 0;         // rows of each copy (N rounded up to 16, plus 16 zero rows)
+    size_t bytes = 0;     // both copies
+};
+struct LargeCopies {
+    const void *D = nullptr;
+    const void *F = nullptr;
+};
+LargePlan large_plan(int N, const InstanceStats &st);
+hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32_t *F,
+                             const LargePlan &pl, void *buf, LargeCopies *out);
+hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const LargePlan &pl,
+                              const LargeCopies &c);
 // size class of the on-chip kernel that runs an instance (16, 32, 64, 96, 128,
 // 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic
 int fast_class(int N, const InstanceStats &st);

@@ -43,7 +43,8 @@ def tied_rows(D, F, perms, grid, trials, seed):
 
 @pytest.mark.parametrize("N,R,G,kind,sweep", [
     (12, 6, 10, "grid", "auto"), (40, 4, 12, "uniform", "auto"), (64, 4, 16, "uniform", "auto"),
-    (100, 3, 8, "diag", "auto"), (140, 3, 8, "uniform", "auto"), (33, 4, 10, "uniform", "plain")])
+    (100, 3, 8, "diag", "auto"), (140, 3, 8, "uniform", "auto"), (33, 4, 10, "uniform", "plain"),
+    (40, 4, 12, "uniform", "large")])
 def test_beta_select_matches_oracle(N, R, G, kind, sweep):
     from paper_2605_24408_amd import pdit as P
     say(f"beta_select N={N} R={R} G={G} kind={kind} sweep={sweep}")
@@ -61,7 +62,7 @@ def test_beta_select_matches_oracle(N, R, G, kind, sweep):
     with P.Pdit(sweep=sweep) as ctx:
         got = gpu_select(ctx, D, F, perms, grid, trials, seed, L)
         plan = ctx.last_plan()
-    assert plan["sweep"] == ("plain" if sweep == "plain" else "fast")
+    assert plan["sweep"] == (sweep if sweep in ("plain", "large") else "fast")
     assert np.array_equal(got["perm_after"], perms)  # the caller's permutations are untouched
     bad = np.nonzero(got["E"] != ref.E_trial.reshape(-1))[0]
     if bad.size:

@@ -1,0 +1,204 @@
+"""GPU parity of the sweep kernel that stores no H (pdit_run_sweeps with
+PDIT_SWEEP_LARGE, and AUTO where no on-chip class fits): every variant of its
+products (int16 or int32 copies of D and F, int32 partial sums of 24-bit
+products or int64 products), int32 and int64 initial H, ragged sizes from 2
+to 512, against the CPU oracle on the same seeded inputs.  Energies,
+permutations, best states, counters and every chosen candidate must match;
+a replica may leave the oracle's trajectory only after a draw the oracle
+counted as a tie."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_24408_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2605_24408_amd import pdit
+    return pdit
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def run_large(P, D, F, perms, beta, seed, sweep="large", record=True, offset=0, ctx=None):
+    own = ctx is None
+    if own:
+        ctx = P.Pdit(sweep=sweep)
+    Dd, Fd = dev(D, torch.int32), dev(F, torch.int32)
+    perm = dev(perms, torch.int32)
+    b = dev(np.asarray(beta, np.float32), torch.float32)
+    R, N = perm.shape
+    T = b.numel()
+    ch = tr = None
+    if record:
+        ch = torch.full((R, T, N), -1, dtype=torch.int32, device=DEV)
+        tr = torch.zeros((R, T), dtype=torch.int64, device=DEV)
+        ctx.set_recording(ch, tr)
+    ctx.set_sweep_offset(offset)
+    ctx.run_sweeps(Dd, Fd, perm, b, seed)
+    E = ctx.energy()
+    Eb, pb = ctx.best()
+    cnt = ctx.replica_counters()
+    torch.cuda.synchronize()
+    out = dict(perm=perm.cpu().numpy(), E=E.cpu().numpy(), E_best=Eb.cpu().numpy(),
+               perm_best=pb.cpu().numpy(), counters=cnt.cpu().numpy(),
+               choices=None if ch is None else ch.cpu().numpy(),
+               trace=None if tr is None else tr.cpu().numpy(), plan=ctx.last_plan())
+    if own:
+        ctx.close()
+    return out
+
+
+def check(got, ref, rows=None, max_bad=0):
+    R = ref.perm.shape[0]
+    rows = range(R) if rows is None else rows
+    bad = []
+    for i, k in enumerate(rows):
+        same = (np.array_equal(got["perm"][k], ref.perm[i]) and got["E"][k] == ref.E[i]
+                and got["E_best"][k] == ref.E_best[i]
+                and np.array_equal(got["perm_best"][k], ref.perm_best[i])
+                and np.array_equal(got["counters"][k][:2], ref.counters[i][:2]))
+        if same and got["choices"] is not None and ref.choices is not None:
+            same = (np.array_equal(got["choices"][k], ref.choices[i])
+                    and np.array_equal(got["trace"][k], ref.E_trace[i]))
+        if not same:
+            assert ref.counters[i][2] > 0, (
+                f"replica {k} differs from the oracle without a counted tie: gpu E={got['E'][k]} "
+                f"oracle E={ref.E[i]}, accepted {got['counters'][k][1]} vs {ref.counters[i][1]}")
+            bad.append(k)
+    assert len(bad) <= max_bad, f"replicas off the oracle's trajectory after ties: {bad}"
+    return bad
+
+
+def instance(rng, N, dmax, fmax, zero_diag=True):
+    D = W.sym_uniform(rng, N, 0, dmax).astype(np.int64)
+    F = W.sym_uniform(rng, N, 0, fmax).astype(np.int64)
+    if not zero_diag:
+        D[np.diag_indices(N)] = rng.integers(0, dmax + 1, size=N)
+        F[np.diag_indices(N)] = rng.integers(0, fmax + 1, size=N)
+    return D.astype(np.int32), F.astype(np.int32)
+
+
+# (N, R, T, max|D|, max|F|, zero diagonal, hot): the values pick the variant --
+# int16 copies when both maxima are <= 32767, int32 partial sums when
+# 16 max|D| max|F| < 2^31, int64 H when the bound on |H| exceeds 2^31 - 1
+CASES = [
+    (2, 6, 40, 9, 9, True, True),            # int16, narrow, H int32; the smallest instance
+    (7, 8, 30, 60, 60, False, True),         # nonzero diagonals
+    (33, 5, 12, 60, 60, True, False),        # one wave, cold
+    (64, 4, 8, 99, 99, True, True),          # exactly one wave
+    (65, 4, 8, 99, 99, False, True),         # two waves, one lane of the second
+    (130, 3, 4, 10_000, 10_000, True, True),   # int16, narrow, H int64
+    (150, 3, 4, 30_000, 30_000, True, True),   # int16, int64 products
+    (100, 3, 5, 200_000, 600, True, True),     # int32 copies, narrow
+    (90, 3, 5, 2_000_000, 5_000, False, True),  # int32 copies, int64 products, H int64
+    (257, 2, 2, 10_000, 10_000, True, True),   # ragged: 5 waves, one lane of the last
+    (300, 2, 2, 99, 99, True, True),
+    (512, 2, 2, 10_000, 10_000, True, True),   # the largest instance
+]
+
+
+@pytest.mark.parametrize("N,R,T,dmax,fmax,zd,hot", CASES)
+def test_large_trajectories(P, N, R, T, dmax, fmax, zd, hot):
+    rng = np.random.default_rng(7000 + N + dmax % 97)
+    D, F = instance(rng, N, dmax, fmax, zd)
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric((0.05 if hot else 2.0) / s, 50.0 / s, T)
+    say(f"large trajectory N={N} R={R} T={T} max|D|={dmax} max|F|={fmax}")
+    ref = oracle.run(D, F, perms, beta, 11, record_choices=True, record_trace=True)
+    got = run_large(P, D, F, perms, beta, 11)
+    assert got["plan"]["sweep"] == "large"
+    check(got, ref, max_bad=1)
+    assert got["counters"][:, 1].sum() > 0
+
+
+def test_auto_picks_large(P):
+    """AUTO runs the kernel without a stored H where no on-chip class fits
+    (N > 256, or values beyond the fast kernel's), with the same results."""
+    rng = np.random.default_rng(5)
+    for N, dmax in ((280, 50), (120, 100_000)):
+        D, F = instance(rng, N, dmax, 40)
+        perms = W.random_perms(rng, 2, N)
+        s = W.energy_scale(D, F)
+        beta = W.beta_geometric(0.2 / s, 20.0 / s, 2)
+        say(f"auto N={N} max|D|={dmax}")
+        ref = oracle.run(D, F, perms, beta, 3, record_choices=True, record_trace=True)
+        got = run_large(P, D, F, perms, beta, 3, sweep="auto")
+        assert got["plan"]["sweep"] == "large"
+        check(got, ref)
+
+
+def test_resume_matches_one_call(P):
+    """Two calls of T sweeps (the second from the first's state and sweep
+    offset) give what one call of 2T sweeps gives."""
+    rng = np.random.default_rng(21)
+    N, R, T = 260, 3, 2
+    D, F = instance(rng, N, 500, 500)
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric(0.1 / s, 10.0 / s, 2 * T)
+    say("large resume")
+    one = run_large(P, D, F, perms, beta, 9, record=False)
+    with P.Pdit(sweep="large") as ctx:
+        perm = dev(perms, torch.int32)
+        Dd, Fd = dev(D, torch.int32), dev(F, torch.int32)
+        ctx.run_sweeps(Dd, Fd, perm, dev(beta[:T], torch.float32), 9)
+        ctx.run_sweeps(Dd, Fd, perm, dev(beta[T:], torch.float32), 9)
+        E = ctx.energy().cpu().numpy()
+        Eb, pb = ctx.best()
+        torch.cuda.synchronize()
+        assert np.array_equal(perm.cpu().numpy(), one["perm"])
+        assert np.array_equal(E, one["E"])
+        assert np.array_equal(Eb.cpu().numpy(), one["E_best"])
+        assert np.array_equal(pb.cpu().numpy(), one["perm_best"])
+
+
+def test_n512_workload_sampled(P):
+    """The N=512 workload (D, F uniform in [0, 10^4] with 20% zeros) at its
+    full replica count, 256, in the launch the benchmark times, for the
+    first sweeps of its schedule: replicas 0, 97 and 255 match the oracle
+    run on those rows alone (same Philox replica indices), and every
+    replica's energy equals the energy of its final permutation."""
+    inst = W.config_n512()
+    T = 2
+    beta = inst.beta[:T]
+    say("n512 sampled")
+    got = run_large(P, inst.D, inst.F, inst.perms, beta, W.PHILOX_SEED, sweep="auto",
+                    record=False)
+    assert got["plan"]["sweep"] == "large"
+    rows = [0, 97, 255]
+    ref = oracle.run(inst.D, inst.F, inst.perms[rows], beta, W.PHILOX_SEED, rep_ids=rows)
+    check(got, ref, rows=rows)
+    for k in range(0, 256, 15):
+        assert got["E"][k] == oracle.energy(inst.D, inst.F, got["perm"][k])
+        assert got["E_best"][k] == oracle.energy(inst.D, inst.F, got["perm_best"][k])
+    assert (got["counters"][:, 0] == 512 * T).all()
+
+
+def test_large_rejected_elsewhere(P):
+    """Parallel tempering and batched runs do not take the large kernel."""
+    rng = np.random.default_rng(1)
+    N = 20
+    D, F = instance(rng, N, 9, 9)
+    with P.Pdit(sweep="large") as ctx:
+        insts = [(dev(D, torch.int32), dev(F, torch.int32),
+                  dev(W.random_perms(rng, 2, N), torch.int32),
+                  dev(np.ones(2, np.float32), torch.float32))]
+        with pytest.raises(Exception, match="large kernel runs only"):
+            ctx.run_sweeps_batch(insts, 1)

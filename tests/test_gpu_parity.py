@@ -461,3 +461,53 @@ def test_zero_sweeps_and_reset(P):
         ref = oracle.run(inst.D, inst.F, start, inst.beta[:5], 2, sweep_offset=50)
         assert np.array_equal(Eb.cpu().numpy(), ref.E_best)
         assert np.array_equal(pb.cpu().numpy(), ref.perm_best)
+
+
+@pytest.mark.parametrize("N", [7, 200, 512])
+def test_gibbs_choice_wide_distances(P, N):
+    """Energy changes far beyond 2^31 at temperatures where they still carry
+    weight (beta * d of order 1, and beta = 0): no candidate is cut by a
+    32-bit zero-weight bound.  Rows of the int64 kernels' range."""
+    rng = np.random.default_rng(90 + N)
+    M = 300
+    scale = rng.choice([3e9, 4e10, 7e12, 1e15], size=M)
+    delta = (rng.uniform(-1.0, 1.0, size=(M, N)) * scale[:, None]).astype(np.int64)
+    beta = (rng.uniform(0.1, 10.0, size=M) / scale).astype(np.float32)
+    beta[:4] = 0.0
+    u24 = rng.integers(0, 2**24, size=M).astype(np.int32)
+    with P.Pdit() as ctx:
+        ch, tie = ctx.debug_choice(dev(delta, torch.int64), dev(beta, torch.float32),
+                                   dev(u24, torch.int32))
+    ch = ch.cpu().numpy()
+    mism = 0
+    far = 0
+    for m in range(M):
+        k, t = oracle.gibbs_choice(delta[m], float(beta[m]), int(u24[m]))
+        far += int(delta[m][k] - delta[m].min() >= 2**31)
+        if ch[m] != k:
+            mism += 1
+            assert t, f"row {m}: gpu {ch[m]} oracle {k} without a tie"
+    assert mism <= 2
+    assert far > M // 4  # most draws land on candidates beyond 2^31 from the minimum
+
+
+@pytest.mark.parametrize("sweep", ["plain", "large"])
+def test_int64_distances_trajectory(P, sweep):
+    """An instance whose energy changes reach 10^10 (values to 30000), hot
+    schedule: the int64 kernels follow the oracle, including candidates more
+    than 2^31 above the row minimum."""
+    rng = np.random.default_rng(4242)
+    N, R, T = 150, 3, 3
+    D = W.sym_uniform(rng, N, 0, 30_000)
+    F = W.sym_uniform(rng, N, 0, 30_000)
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric(0.05 / s, 50.0 / s, T)
+    say(f"int64 distances sweep={sweep}")
+    ref = oracle.run(D, F, perms, beta, 5, record_choices=True)
+    got = run_gpu(P, D, F, perms, beta, 5, sweep=sweep, record=True)
+    bad = compare_runs(got, ref)
+    assert len(bad) <= 1
+    for k in range(R):
+        if k not in bad:
+            assert np.array_equal(got["choices"][k], ref.choices[k])
