@@ -487,13 +487,12 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
         return fail(ctx, PDIT_EINVAL, "concurrent-update tempering runs on the periodic schedule");
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for parallel tempering");
-    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_LARGE ||
+        ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL,
                     ctx->opts.sweep == PDIT_SWEEP_CLIQUE
                         ? "the clique kernel runs only in pdit_run_sweeps"
-                        : ctx->opts.sweep == PDIT_SWEEP_LARGE
-                              ? "the large kernel runs only in pdit_run_sweeps and pdit_beta_select"
-                              : "unknown sweep kernel");
+                        : "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
     InstanceStats st;
@@ -511,6 +510,9 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     } else if (ctx->opts.sweep == PDIT_SWEEP_AUTO) {
         use_fast = fclass != 0;
     }
+    // without a fast class the kernel that stores no H replaces the plain one
+    const bool use_large = ctx->opts.sweep == PDIT_SWEEP_LARGE ||
+                           (ctx->opts.sweep == PDIT_SWEEP_AUTO && !use_fast);
     const bool table = use_fast && fclass <= 128;
     // fused: the table kernel, cooperative launches, energies inside the
     // published word (|E| <= N max|H| < 2^35; the table classes imply it)
@@ -533,6 +535,11 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
         rc = ensure(ctx, ctx->tstate, sizeof(int32_t) * (size_t)R * pdit::table_state_words(fclass));
         if (rc) return rc;
     }
+    const pdit::LargePlan lplan = use_large ? pdit::large_plan(N, st) : pdit::LargePlan{};
+    if (use_large) {
+        rc = ensure(ctx, ctx->large_buf, lplan.bytes);
+        if (rc) return rc;
+    }
     bool fresh = false;
     rc = shape_state(ctx, {N}, {R}, &fresh);
     if (rc) return rc;
@@ -541,6 +548,10 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     ctx->timed = false;
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
+    pdit::LargeCopies lcopy;
+    if (use_large)
+        PDIT_HIP(ctx, pdit::launch_large_copy(ctx->stream, N, D, F, lplan, ctx->large_buf.ptr,
+                                              &lcopy));
     if (fresh) {
         PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * R, hipMemcpyDeviceToDevice,
                                      ctx->stream));
@@ -602,6 +613,8 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
             a.flags = pdit::kSaveState | (per > 0 ? pdit::kLoadState | pdit::kAccumCounters : 0u);
             if (use_fast)
                 PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
+            else if (use_large)
+                PDIT_HIP(ctx, pdit::launch_sweep_large(ctx->stream, a, h64, lplan, lcopy));
             else
                 PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
         }
@@ -619,7 +632,7 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     }
     ctx->sweep_offset += (uint64_t)(n_periods * pt->period_sweeps);
     ctx->last_updates = (int64_t)R * N * n_periods * pt->period_sweeps;
-    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : PDIT_SWEEP_PLAIN;
+    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : use_large ? PDIT_SWEEP_LARGE : PDIT_SWEEP_PLAIN;
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
@@ -810,7 +823,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                     ctx->opts.sweep == PDIT_SWEEP_CLIQUE
                         ? "the clique kernel runs only in pdit_run_sweeps"
                         : ctx->opts.sweep == PDIT_SWEEP_LARGE
-                              ? "the large kernel runs only in pdit_run_sweeps and pdit_beta_select"
+                              ? "batched runs do not take the large kernel"
                               : "unknown sweep kernel");
     for (int k = 0; k < n_inst; ++k) {
         const pdit_instance &in = inst[k];

@@ -160,7 +160,7 @@ struct SweepArgs {
 
 // Launch flags of the sweep kernels (parallel-tempering periods).
 constexpr uint32_t kLoadState = 1;      // resume from the saved state (table kernel: tstate)
-constexpr uint32_t kSaveState = 2;      // save the state at the end (table: tstate; H kernels: H)
+constexpr uint32_t kSaveState = 2;      // save the state at the end (table: tstate; H kernels: H; large: diag H)
 constexpr uint32_t kAccumCounters = 4;  // add to the counters instead of overwriting them
 // int32 words of one replica's saved table state: the table (NMAX x (NMAX+4))
 // and diag H (NMAX) of its size class
@@ -261,7 +261,9 @@ hipError_t launch_sweep_clique(hipStream_t s, const CliqueArgs &a);
 
 hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
 // The kernel that stores no H (any N <= kLargeNMax, 512 threads per replica):
-// reads diag H of the initial p from a.H (int64 when h64), never writes a.H.
+// reads diag H of the initial p from a.H (int64 when h64); with kSaveState it
+// writes the final diag H there (the state between tempering periods) and
+// leaves the rest of a.H stale.
 // Its products read padded copies of D and F made by launch_large_copy.
 constexpr int kLargeNMax = 512;
 struct LargePlan {

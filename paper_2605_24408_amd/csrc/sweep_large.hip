@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     for (int u = 0; u < W; ++u) voff[u] = col * 4 + u * pitch;
     int32_t *perm = a.perm + rep * N;
     int32_t *pbest = a.perm_best + rep * N;
-    const HT *H0 = (const HT *)a.H + rep * (int64_t)N * N;  // H of the initial p (diagonal read)
+    HT *H0 = (HT *)a.H + rep * (int64_t)N * N;  // diag H of the initial p; kSaveState writes it back
     const float *beta_p = a.slot ? a.beta + a.slot[rep] : a.beta;
     const int64_t beta_stride = a.slot ? 0 : 1;
 
@@ -350,7 +350,10 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
         }
         if (a.E_trace && k == 0) a.E_trace[rep * a.T + t] = E;
     }
-    if (own) perm[k] = sm.p[k];
+    if (own) {
+        perm[k] = sm.p[k];
+        if (a.flags & kSaveState) H0[(int64_t)k * N + k] = (HT)sm.hd[k];
+    }
     if (k == 0) {
         a.E[rep] = E;
         a.E_best[rep] = E_best;

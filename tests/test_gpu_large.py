@@ -191,8 +191,8 @@ def test_n512_workload_sampled(P):
     assert (got["counters"][:, 0] == 512 * T).all()
 
 
-def test_large_rejected_elsewhere(P):
-    """Parallel tempering and batched runs do not take the large kernel."""
+def test_large_rejected_in_batches(P):
+    """Batched runs do not take the large kernel."""
     rng = np.random.default_rng(1)
     N = 20
     D, F = instance(rng, N, 9, 9)
@@ -200,5 +200,5 @@ def test_large_rejected_elsewhere(P):
         insts = [(dev(D, torch.int32), dev(F, torch.int32),
                   dev(W.random_perms(rng, 2, N), torch.int32),
                   dev(np.ones(2, np.float32), torch.float32))]
-        with pytest.raises(Exception, match="large kernel runs only"):
+        with pytest.raises(Exception, match="do not take the large kernel"):
             ctx.run_sweeps_batch(insts, 1)

@@ -67,7 +67,9 @@ TABLE_CASES = [(12, 4, 3, "fast", "grid"), (16, 4, 2, "fast", "uniform"),
 @pytest.mark.parametrize("N,L,sets,sweep,kind,schedule",
                          [c + (s,) for c in TABLE_CASES for s in ("periodic", "fused")]
                          + [(140, 4, 2, "fast", "uniform", "auto"),
-                            (33, 5, 2, "plain", "uniform", "auto")])
+                            (33, 5, 2, "plain", "uniform", "auto"),
+                            (33, 5, 2, "large", "uniform", "auto"),
+                            (200, 3, 1, "large", "diag", "auto")])
 def test_pt_matches_oracle(N, L, sets, sweep, kind, schedule):
     from paper_2605_24408_amd import pdit as P
     say(f"pt N={N} L={L} sets={sets} sweep={sweep} kind={kind} schedule={schedule}")
