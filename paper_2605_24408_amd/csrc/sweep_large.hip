@@ -18,16 +18,23 @@
 // sweep kernel: locations 0..N-1 in order, Eq. 5 over the N candidates with
 // the same integer weights, CDF and Philox stream.
 //
-// One workgroup of 512 threads (8 waves) per replica: thread k owns location
-// k in the draw and column k of both products.  The products read padded
-// copies of D and F whose rows N..N32+15 (N32 = N rounded up to 32) are
-// zero, so blocks of 16 rows run in pairs without a tail and the next block
-// is always loadable.  When |D|, |F| <= 32767 the copies hold int16 values in row
-// pairs (one 32-bit word = rows 2i and 2i+1 of a column) and a block is 8
-// word loads and 8 `v_dot2_i32_i16` per matrix, each exact in int32; else
-// they are int32 rows with 24-bit (|D|, |F| < 2^23) or int64 products.
-// Narrow instances (16 max|D| max|F| < 2^31) sum a block in int32 before the
-// int64 total.
+// One workgroup of 512 threads (8 waves) per replica; thread k owns location
+// k in the draw.  The products read library copies of D and F:
+// * |D|, |F| <= 32767: int16 row pairs, one 32-bit word = rows 2i and 2i+1
+//   of a column, rows padded with zeros to N128 (N rounded up to 128) and
+//   columns to N4 (rounded up to 4), plus 4 zero word rows.  Each lane takes
+//   four adjacent columns with one 16-byte load per word row and matrix and
+//   `v_dot2_i32_i16` (exact in int32 per word); the two waves of pair q take
+//   word rows [q N128/8, (q+1) N128/8) for 256 columns each, and the four
+//   quarter sums meet in LDS.  Wide 16-byte loads matter: one-column 4-byte
+//   loads ran at half the per-CU rate from L2.
+// * otherwise: int32 rows (N32 = N rounded up to 32, plus 16 zero rows), one
+//   column per lane, 24-bit (|D|, |F| < 2^23) or int64 products.
+// Narrow instances (16 max|D| max|F| < 2^31) sum each block in int32 before
+// the int64 total.  A load's lane offsets live in registers for the whole
+// kernel and its row offset is wave-uniform; two blocks per iteration in
+// alternating registers keep the next block's loads in flight while one
+// block's products run.
 #include <algorithm>
 
 #include "device_common.h"
@@ -52,6 +59,7 @@ struct LargeSmem {
     int64_t G[kLargeNMax];                // H[r][.] by facility
     int64_t hd[kLargeNMax];               // H[x][x]
     int64_t hcol[kLargeNMax];             // H[.][r]
+    int64_t part1[4][kLargeNMax], part2[4][kLargeNMax];  // quarter sums (paired copies)
     int32_t u[kLargeNMax], v[kLargeNMax];
     int64_t wmin[kLargeWaves];
     uint64_t wsum[kLargeWaves];
@@ -74,15 +82,30 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t copy_rsrc(const void *p, uint3
                                              0x00020000);
 }
 
-// Words of one block per lane: 8 row pairs (int16 copies) or 16 rows (int32).
-template <bool PAIRS>
-struct Block {
-    static constexpr int W = PAIRS ? kRowBlock / 2 : kRowBlock;
-};
+// Minimum of a 64-bit value over the wave: DPP shifts within rows of 16
+// lanes (neutral INT64_MAX shifted in), then the four row results.
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+#define PDIT_MIN_STEP(K)                                                               \
+    {                                                                                  \
+        const uint32_t tl = (uint32_t)dpp_row_shr<K>(-1, (int32_t)(uint32_t)v);        \
+        const uint32_t th = (uint32_t)dpp_row_shr<K>(INT32_MAX, (int32_t)(v >> 32));   \
+        const int64_t t = (int64_t)((uint64_t)th << 32 | tl);                          \
+        v = t < v ? t : v;                                                             \
+    }
+    PDIT_MIN_STEP(1)
+    PDIT_MIN_STEP(2)
+    PDIT_MIN_STEP(4)
+    PDIT_MIN_STEP(8)
+#undef PDIT_MIN_STEP
+    const int64_t a = readlane_i64(v, 15), b = readlane_i64(v, 31);
+    const int64_t c = readlane_i64(v, 47), d = readlane_i64(v, 63);
+    const int64_t ab = a < b ? a : b, cd = c < d ? c : d;
+    return ab < cd ? ab : cd;
+}
 
-// The lane's words of a block: its offsets (column k of each word row of a
-// block) stay in vector registers for the whole kernel and the block's row
-// offset is wave-uniform, so a load is one instruction.
+// The lane's entries of a block of int32 rows: its offsets (column k of each
+// row of a block) stay in vector registers for the whole kernel and the
+// block's row offset is wave-uniform, so a load is one instruction.
 template <int W>
 __device__ __forceinline__ void load_block(__amdgpu_buffer_rsrc_t rs, const uint32_t (&voff)[W],
                                            uint32_t soff, uint32_t (&x)[W]) {
@@ -90,98 +113,150 @@ __device__ __forceinline__ void load_block(__amdgpu_buffer_rsrc_t rs, const uint
     for (int u = 0; u < W; ++u) x[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff[u], soff, 0);
 }
 
-// Adds the products of one block (the lane's words x1, x2 of rows j0..j0+15)
-// with entries j0..j0+15 of a and b to acc1, acc2.
-template <bool PAIRS, bool NARROW>
-__device__ __forceinline__ void block_products(const uint32_t (&x1)[Block<PAIRS>::W],
-                                               const uint32_t (&x2)[Block<PAIRS>::W],
-                                               const void *a, const void *b, int j0,
-                                               int64_t &acc1, int64_t &acc2) {
-    if constexpr (PAIRS) {
-        // 16 int16 entries of a and b = 8 packed words each
-        const uint4 *a4 = (const uint4 *)((const int16_t *)a + j0);
-        const uint4 *b4 = (const uint4 *)((const int16_t *)b + j0);
-        const uint4 aw0 = a4[0], aw1 = a4[1], bw0 = b4[0], bw1 = b4[1];
-        const uint32_t aw[8] = {aw0.x, aw0.y, aw0.z, aw0.w, aw1.x, aw1.y, aw1.z, aw1.w};
-        const uint32_t bw[8] = {bw0.x, bw0.y, bw0.z, bw0.w, bw1.x, bw1.y, bw1.z, bw1.w};
-        if (NARROW) {
-            int32_t s1 = 0, s2 = 0;
+// Adds the products of one block of int32 rows (the lane's entries x1, x2 of
+// rows j0..j0+15) with entries j0..j0+15 of a and b to acc1, acc2.
+template <bool NARROW>
+__device__ __forceinline__ void block_products(const uint32_t (&x1)[kRowBlock],
+                                               const uint32_t (&x2)[kRowBlock], const int32_t *a,
+                                               const int32_t *b, int j0, int64_t &acc1,
+                                               int64_t &acc2) {
+    const int4 *a4 = (const int4 *)(a + j0);
+    const int4 *b4 = (const int4 *)(b + j0);
+    if (NARROW) {
+        int32_t s1 = 0, s2 = 0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                s1 = dot2(x1[u], aw[u], s1);
-                s2 = dot2(x2[u], bw[u], s2);
-            }
-            acc1 += s1;
-            acc2 += s2;
-        } else {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                acc1 += dot2(x1[u], aw[u], 0);
-                acc2 += dot2(x2[u], bw[u], 0);
-            }
+        for (int q = 0; q < kRowBlock / 4; ++q) {
+            const int4 av = a4[q], bv = b4[q];
+            s1 = __mul24((int32_t)x1[4 * q + 0], av.x) + s1;
+            s1 = __mul24((int32_t)x1[4 * q + 1], av.y) + s1;
+            s1 = __mul24((int32_t)x1[4 * q + 2], av.z) + s1;
+            s1 = __mul24((int32_t)x1[4 * q + 3], av.w) + s1;
+            s2 = __mul24((int32_t)x2[4 * q + 0], bv.x) + s2;
+            s2 = __mul24((int32_t)x2[4 * q + 1], bv.y) + s2;
+            s2 = __mul24((int32_t)x2[4 * q + 2], bv.z) + s2;
+            s2 = __mul24((int32_t)x2[4 * q + 3], bv.w) + s2;
         }
+        acc1 += s1;
+        acc2 += s2;
     } else {
-        const int4 *a4 = (const int4 *)((const int32_t *)a + j0);
-        const int4 *b4 = (const int4 *)((const int32_t *)b + j0);
-        if (NARROW) {
-            int32_t s1 = 0, s2 = 0;
 #pragma unroll
-            for (int q = 0; q < kRowBlock / 4; ++q) {
-                const int4 av = a4[q], bv = b4[q];
-                s1 = __mul24((int32_t)x1[4 * q + 0], av.x) + s1;
-                s1 = __mul24((int32_t)x1[4 * q + 1], av.y) + s1;
-                s1 = __mul24((int32_t)x1[4 * q + 2], av.z) + s1;
-                s1 = __mul24((int32_t)x1[4 * q + 3], av.w) + s1;
-                s2 = __mul24((int32_t)x2[4 * q + 0], bv.x) + s2;
-                s2 = __mul24((int32_t)x2[4 * q + 1], bv.y) + s2;
-                s2 = __mul24((int32_t)x2[4 * q + 2], bv.z) + s2;
-                s2 = __mul24((int32_t)x2[4 * q + 3], bv.w) + s2;
-            }
-            acc1 += s1;
-            acc2 += s2;
-        } else {
-#pragma unroll
-            for (int q = 0; q < kRowBlock / 4; ++q) {
-                const int4 av = a4[q], bv = b4[q];
-                acc1 += (int64_t)(int32_t)x1[4 * q + 0] * av.x +
-                        (int64_t)(int32_t)x1[4 * q + 1] * av.y +
-                        (int64_t)(int32_t)x1[4 * q + 2] * av.z +
-                        (int64_t)(int32_t)x1[4 * q + 3] * av.w;
-                acc2 += (int64_t)(int32_t)x2[4 * q + 0] * bv.x +
-                        (int64_t)(int32_t)x2[4 * q + 1] * bv.y +
-                        (int64_t)(int32_t)x2[4 * q + 2] * bv.z +
-                        (int64_t)(int32_t)x2[4 * q + 3] * bv.w;
-            }
+        for (int q = 0; q < kRowBlock / 4; ++q) {
+            const int4 av = a4[q], bv = b4[q];
+            acc1 += (int64_t)(int32_t)x1[4 * q + 0] * av.x + (int64_t)(int32_t)x1[4 * q + 1] * av.y +
+                    (int64_t)(int32_t)x1[4 * q + 2] * av.z + (int64_t)(int32_t)x1[4 * q + 3] * av.w;
+            acc2 += (int64_t)(int32_t)x2[4 * q + 0] * bv.x + (int64_t)(int32_t)x2[4 * q + 1] * bv.y +
+                    (int64_t)(int32_t)x2[4 * q + 2] * bv.z + (int64_t)(int32_t)x2[4 * q + 3] * bv.w;
         }
     }
 }
 
-// hkr = sum_j M1[j][k] a[j], gk = sum_j M2[j][k] b[j] over rows 0..N32-1
-// (N32 = N rounded up to 32; a, b: int16 vectors for paired copies, int32
-// otherwise, zero beyond N).  Two blocks per iteration in alternating
-// registers: the loads of one block are in flight while the other's
-// products run, with no register copies that would wait for them.
-template <bool PAIRS, bool NARROW>
-__device__ __forceinline__ void two_products(__amdgpu_buffer_rsrc_t M1, __amdgpu_buffer_rsrc_t M2,
-                                             const uint32_t (&voff)[Block<PAIRS>::W],
-                                             uint32_t block_bytes, const void *a, const void *b,
-                                             int N32, int64_t &hkr, int64_t &gk) {
-    constexpr int W = Block<PAIRS>::W;
-    uint32_t xa1[W], xa2[W], xb1[W], xb2[W];
-    load_block<W>(M1, voff, 0, xa1);
-    load_block<W>(M2, voff, 0, xa2);
+// Paired copies, four adjacent columns per lane (one 16-byte load per word
+// row and matrix), one quarter of the word rows per wave pair: partial sums
+// of the quarter for columns c0..c0+3.  Word rows q0 .. q0+Q-1, blocks of 4.
+template <bool NARROW>
+__device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
+                                                 __amdgpu_buffer_rsrc_t M2, uint32_t pitchB,
+                                                 uint32_t voff0, int q0, int Q,
+                                                 const int16_t *a, const int16_t *b,
+                                                 int64_t (&acc1)[4], int64_t (&acc2)[4]) {
+    constexpr int B = 4;  // word rows per block
+    uint32_t voff[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) voff[u] = voff0 + u * pitchB;
+    uint4 xa1[B], xa2[B], xb1[B], xb2[B];
+    uint32_t soff = (uint32_t)q0 * pitchB;
+    const uint32_t block_bytes = B * pitchB;
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+        xa1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M1, voff[u], soff, 0));
+        xa2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc1[c] = acc2[c] = 0;
+    auto block = [&](const uint4 (&x1)[B], const uint4 (&x2)[B], int w0) {
+        // words w0..w0+3 of a and b (rows 2 w0 .. 2 w0 + 7)
+        const uint4 aw = *(const uint4 *)(a + 2 * w0);
+        const uint4 bw = *(const uint4 *)(b + 2 * w0);
+        const uint32_t av[4] = {aw.x, aw.y, aw.z, aw.w};
+        const uint32_t bv[4] = {bw.x, bw.y, bw.z, bw.w};
+        if (NARROW) {
+            int32_t s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                s1[0] = dot2(x1[u].x, av[u], s1[0]);
+                s1[1] = dot2(x1[u].y, av[u], s1[1]);
+                s1[2] = dot2(x1[u].z, av[u], s1[2]);
+                s1[3] = dot2(x1[u].w, av[u], s1[3]);
+                s2[0] = dot2(x2[u].x, bv[u], s2[0]);
+                s2[1] = dot2(x2[u].y, bv[u], s2[1]);
+                s2[2] = dot2(x2[u].z, bv[u], s2[2]);
+                s2[3] = dot2(x2[u].w, bv[u], s2[3]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                acc1[c] += s1[c];
+                acc2[c] += s2[c];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                acc1[0] += dot2(x1[u].x, av[u], 0);
+                acc1[1] += dot2(x1[u].y, av[u], 0);
+                acc1[2] += dot2(x1[u].z, av[u], 0);
+                acc1[3] += dot2(x1[u].w, av[u], 0);
+                acc2[0] += dot2(x2[u].x, bv[u], 0);
+                acc2[1] += dot2(x2[u].y, bv[u], 0);
+                acc2[2] += dot2(x2[u].z, bv[u], 0);
+                acc2[3] += dot2(x2[u].w, bv[u], 0);
+            }
+        }
+    };
+    for (int w = q0; w < q0 + Q; w += 2 * B) {
+        soff += block_bytes;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            xb1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M1, voff[u], soff, 0));
+            xb2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
+        }
+        block(xa1, xa2, w);
+        // the block after a quarter's last is the next quarter's first, or the pad block
+        soff += block_bytes;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            xa1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M1, voff[u], soff, 0));
+            xa2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
+        }
+        block(xb1, xb2, w + B);
+    }
+}
+
+// int32 copies, one column per lane: hkr = sum_j M1[j][k] a[j], gk =
+// sum_j M2[j][k] b[j] over rows 0..N32-1 (N32 = N rounded up to 32; a, b zero
+// beyond N).  Two blocks per iteration in alternating registers: the loads
+// of one block are in flight while the other's products run, with no
+// register copies that would wait for them.
+template <bool NARROW>
+__device__ __forceinline__ void column_products(__amdgpu_buffer_rsrc_t M1,
+                                                __amdgpu_buffer_rsrc_t M2,
+                                                const uint32_t (&voff)[kRowBlock],
+                                                uint32_t block_bytes, const int32_t *a,
+                                                const int32_t *b, int N32, int64_t &hkr,
+                                                int64_t &gk) {
+    uint32_t xa1[kRowBlock], xa2[kRowBlock], xb1[kRowBlock], xb2[kRowBlock];
+    load_block<kRowBlock>(M1, voff, 0, xa1);
+    load_block<kRowBlock>(M2, voff, 0, xa2);
     int64_t acc1 = 0, acc2 = 0;
     uint32_t soff = 0;
     for (int j0 = 0; j0 < N32; j0 += 2 * kRowBlock) {
         soff += block_bytes;
-        load_block<W>(M1, voff, soff, xb1);
-        load_block<W>(M2, voff, soff, xb2);
-        block_products<PAIRS, NARROW>(xa1, xa2, a, b, j0, acc1, acc2);
+        load_block<kRowBlock>(M1, voff, soff, xb1);
+        load_block<kRowBlock>(M2, voff, soff, xb2);
+        block_products<NARROW>(xa1, xa2, a, b, j0, acc1, acc2);
         // the block after the last one is the zero pad block: always in range
         soff += block_bytes;
-        load_block<W>(M1, voff, soff, xa1);
-        load_block<W>(M2, voff, soff, xa2);
-        block_products<PAIRS, NARROW>(xb1, xb2, a, b, j0 + kRowBlock, acc1, acc2);
+        load_block<kRowBlock>(M1, voff, soff, xa1);
+        load_block<kRowBlock>(M2, voff, soff, xa2);
+        block_products<NARROW>(xb1, xb2, a, b, j0 + kRowBlock, acc1, acc2);
     }
     hkr = acc1;
     gk = acc2;
@@ -197,18 +272,21 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     const bool own = k < N;
     const int32_t *__restrict__ D = a.D;
     const int32_t *__restrict__ F = a.F;
-    // word rows of a copy: row pairs (int16) or rows (int32), N words each
-    constexpr int W = Block<PAIRS>::W;
-    const uint32_t pitch = (uint32_t)N * 4;
-    const uint32_t copy_bytes = (uint32_t)(N32 + kRowBlock) * (PAIRS ? 2 : 4) * N;
+    // word rows of a copy: row pairs (int16, N4 = N rounded up to 4 words,
+    // N128 / 2 + 4 word rows) or rows (int32, N words, N32 + 16 rows)
+    const int N4 = (N + 3) & ~3;
+    const int N128 = (N + 127) & ~127;
+    const uint32_t pitch = (uint32_t)(PAIRS ? N4 : N) * 4;
+    const uint32_t copy_bytes = PAIRS ? (uint32_t)(N128 / 2 + 4) * pitch
+                                      : (uint32_t)(N32 + kRowBlock) * pitch;
     const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(c.D, copy_bytes);
     const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(c.F, copy_bytes);
     // lanes past N read column 0 (results unused): every offset stays inside
     // the copy even for the prefetch of the zero block
     const uint32_t col = own ? (uint32_t)k : 0u;
-    uint32_t voff[W];
+    uint32_t voff[kRowBlock];  // int32 copies: column k of the rows of a block
 #pragma unroll
-    for (int u = 0; u < W; ++u) voff[u] = col * 4 + u * pitch;
+    for (int u = 0; u < kRowBlock; ++u) voff[u] = col * 4 + u * pitch;
     int32_t *perm = a.perm + rep * N;
     int32_t *pbest = a.perm_best + rep * N;
     HT *H0 = (HT *)a.H + rep * (int64_t)N * N;  // diag H of the initial p; kSaveState writes it back
@@ -254,13 +332,35 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
             __syncthreads();
             // ---- column r of H (location k) and row r of H by facility (facility k) ----
             int64_t hkr = 0, gk = 0;
-            if (wv * 64 < N) {  // waves with no location skip the products
-                if constexpr (PAIRS)
-                    two_products<true, NARROW>(Dc, Fc, voff, W * pitch, sm.f16, sm.dq16, N32, hkr,
-                                               gk);
-                else
-                    two_products<false, NARROW>(Dc, Fc, voff, W * pitch, sm.f, sm.dq, N32, hkr,
-                                                gk);
+            if constexpr (PAIRS) {
+                // wave pair rq takes word rows [rq Q, (rq + 1) Q), wave ch of the
+                // pair columns 256 ch + 4 lane .. + 3
+                const int rq = wv >> 1, ch = wv & 1;
+                const int c0 = 256 * ch + 4 * lane;
+                const bool act = c0 < N4;
+                const int Q = N128 / 8;
+                if (256 * ch < N4) {
+                    int64_t p1[4], p2[4];
+                    quarter_products<NARROW>(Dc, Fc, pitch, act ? (uint32_t)c0 * 4 : 0u, rq * Q,
+                                             Q, sm.f16, sm.dq16, p1, p2);
+                    if (act) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            sm.part1[rq][c0 + c] = p1[c];
+                            sm.part2[rq][c0 + c] = p2[c];
+                        }
+                    }
+                }
+                __syncthreads();
+                if (own) {
+                    hkr = sm.part1[0][k] + sm.part1[1][k] + sm.part1[2][k] + sm.part1[3][k];
+                    gk = sm.part2[0][k] + sm.part2[1][k] + sm.part2[2][k] + sm.part2[3][k];
+                    sm.G[k] = gk;
+                    sm.hcol[k] = hkr;
+                }
+            } else if (wv * 64 < N) {  // waves with no location skip the products
+                column_products<NARROW>(Dc, Fc, voff, kRowBlock * pitch, sm.f, sm.dq, N32, hkr,
+                                        gk);
                 if (own) {
                     sm.G[k] = gk;
                     sm.hcol[k] = hkr;
@@ -277,11 +377,10 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
                 v = k == r ? 0 : 2 * h + dd * ff;
             }
             // ---- block minimum ----
-            int64_t m = v;
-            for (int off = 32; off > 0; off >>= 1) m = min(m, (int64_t)__shfl_xor(m, off));
-            if (lane == 0) sm.wmin[wv] = m;
+            const int64_t m0 = wave_min_i64(v);
+            if (lane == 0) sm.wmin[wv] = m0;
             __syncthreads();
-            m = sm.wmin[0];
+            int64_t m = sm.wmin[0];
 #pragma unroll
             for (int w = 1; w < kLargeWaves; ++w) m = min(m, sm.wmin[w]);
             // ---- integer weights, running sums, the draw (Eq. 5) ----
@@ -376,16 +475,19 @@ __global__ void large_copy32_kernel(int N, int rows, const int32_t *D, const int
     }
 }
 
-// Paired int16 copies: word (i, k) = M[2i][k] | M[2i+1][k] << 16 (rows beyond
-// N zero); the host checks |D|, |F| <= 32767.
-__global__ void large_copy16_kernel(int N, int rows, const int32_t *D, const int32_t *F,
+// Paired int16 copies: word (i, c) = M[2i][c] | M[2i+1][c] << 16 for
+// c < N4 (N rounded up to 4), entries outside N x N zero; the host checks
+// |D|, |F| <= 32767.
+__global__ void large_copy16_kernel(int N, int wrows, const int32_t *D, const int32_t *F,
                                     uint32_t *Dc, uint32_t *Fc) {
-    const int64_t total = (int64_t)(rows / 2) * N;
+    const int N4 = (N + 3) & ~3;
+    const int64_t total = (int64_t)wrows * N4;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / N, k = e - i * N;
-        const int64_t lo = 2 * i * N + k, hi = lo + N;
-        const bool in_lo = 2 * i < N, in_hi = 2 * i + 1 < N;
+        const int64_t i = e / N4, c = e - i * N4;
+        const int64_t lo = 2 * i * N + c, hi = lo + N;
+        const bool in_c = c < N;
+        const bool in_lo = in_c && 2 * i < N, in_hi = in_c && 2 * i + 1 < N;
         Dc[e] = (uint32_t)(uint16_t)(in_lo ? D[lo] : 0) | (uint32_t)(uint16_t)(in_hi ? D[hi] : 0) << 16;
         Fc[e] = (uint32_t)(uint16_t)(in_lo ? F[lo] : 0) | (uint32_t)(uint16_t)(in_hi ? F[hi] : 0) << 16;
     }
@@ -399,17 +501,22 @@ LargePlan large_plan(int N, const InstanceStats &st) {
     pl.narrow = mx < (1 << 23) &&
                 (int64_t)kRowBlock * st.max_abs_d * st.max_abs_f < ((int64_t)1 << 31);
     pl.elem = mx <= 32767 ? 2 : 4;
-    pl.rows = (N + 2 * kRowBlock - 1) / (2 * kRowBlock) * (2 * kRowBlock) + kRowBlock;
-    pl.bytes = 2 * (size_t)pl.rows * N * pl.elem;
+    if (pl.elem == 2) {
+        pl.rows = ((N + 127) & ~127) / 2 + 4;  // word rows
+        pl.bytes = 2 * (size_t)pl.rows * ((N + 3) & ~3) * 4;
+    } else {
+        pl.rows = (N + 2 * kRowBlock - 1) / (2 * kRowBlock) * (2 * kRowBlock) + kRowBlock;
+        pl.bytes = 2 * (size_t)pl.rows * N * 4;
+    }
     return pl;
 }
 
 hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                              const LargePlan &pl, void *buf, LargeCopies *out) {
-    const size_t one = (size_t)pl.rows * N * pl.elem;
+    const size_t one = pl.bytes / 2;
     out->D = buf;
     out->F = (char *)buf + one;
-    const int64_t total = (int64_t)pl.rows * N;
+    const int64_t total = (int64_t)pl.rows * ((N + 3) & ~3);
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 1024);
     if (pl.elem == 2)
         large_copy16_kernel<<<grid, 256, 0, s>>>(N, pl.rows, D, F, (uint32_t *)out->D,
