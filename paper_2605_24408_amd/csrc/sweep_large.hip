@@ -64,6 +64,7 @@ struct LargeSmem {
     int64_t wmin[kLargeWaves];
     uint64_t wsum[kLargeWaves];
     int32_t wsel[kLargeWaves];
+    int32_t xf[2];  // prefetched next-row flows of locations r and s (accepted exchange)
     int32_t tie;
 };
 
@@ -173,16 +174,18 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc1[c] = acc2[c] = 0;
-    auto block = [&](const uint4 (&x1)[B], const uint4 (&x2)[B], int w0) {
-        // words w0..w0+3 of a and b (rows 2 w0 .. 2 w0 + 7)
+    // products of one block (word rows w0..w0+3) added to s1, s2: int32 partial
+    // sums of at most 16 products (two blocks) when NARROW, else each word's
+    // pair of products (exact in int32) straight into the int64 totals
+    auto block = [&](const uint4 (&x1)[B], const uint4 (&x2)[B], int w0, int32_t (&s1)[4],
+                     int32_t (&s2)[4]) {
         const uint4 aw = *(const uint4 *)(a + 2 * w0);
         const uint4 bw = *(const uint4 *)(b + 2 * w0);
         const uint32_t av[4] = {aw.x, aw.y, aw.z, aw.w};
         const uint32_t bv[4] = {bw.x, bw.y, bw.z, bw.w};
-        if (NARROW) {
-            int32_t s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
+        for (int u = 0; u < B; ++u) {
+            if (NARROW) {
                 s1[0] = dot2(x1[u].x, av[u], s1[0]);
                 s1[1] = dot2(x1[u].y, av[u], s1[1]);
                 s1[2] = dot2(x1[u].z, av[u], s1[2]);
@@ -191,15 +194,7 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
                 s2[1] = dot2(x2[u].y, bv[u], s2[1]);
                 s2[2] = dot2(x2[u].z, bv[u], s2[2]);
                 s2[3] = dot2(x2[u].w, bv[u], s2[3]);
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                acc1[c] += s1[c];
-                acc2[c] += s2[c];
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
+            } else {
                 acc1[0] += dot2(x1[u].x, av[u], 0);
                 acc1[1] += dot2(x1[u].y, av[u], 0);
                 acc1[2] += dot2(x1[u].z, av[u], 0);
@@ -218,7 +213,8 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
             xb1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M1, voff[u], soff, 0));
             xb2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
         }
-        block(xa1, xa2, w);
+        int32_t s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
+        block(xa1, xa2, w, s1, s2);
         // the block after a quarter's last is the next quarter's first, or the pad block
         soff += block_bytes;
 #pragma unroll
@@ -226,7 +222,14 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
             xa1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M1, voff[u], soff, 0));
             xa2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
         }
-        block(xb1, xb2, w + B);
+        block(xb1, xb2, w + B, s1, s2);
+        if (NARROW) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                acc1[c] += s1[c];
+                acc2[c] += s2[c];
+            }
+        }
     }
 }
 
@@ -268,7 +271,8 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     const int N = a.N;
     const int N32 = (N + 2 * kRowBlock - 1) / (2 * kRowBlock) * (2 * kRowBlock);
     const int64_t rep = blockIdx.x;
-    const int k = threadIdx.x, lane = k & 63, wv = k >> 6;
+    const int k = threadIdx.x, lane = k & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(k >> 6);  // wave-uniform, as the compiler must see
     const bool own = k < N;
     const int32_t *__restrict__ D = a.D;
     const int32_t *__restrict__ F = a.F;
@@ -308,6 +312,13 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     int64_t E_best = a.E_best[rep];
     int64_t n_acc = 0, n_tie = 0;
     __syncthreads();
+    // location k's entries of the current row: D[r][k] and F[p(r)][p(k)],
+    // loaded for row 0, then prefetched during the previous update
+    int32_t drk = 0, fk = 0;
+    if (own) {
+        drk = D[k];
+        fk = F[(int64_t)sm.p[0] * N + sm.p[k]];
+    }
 
     for (int64_t t = 0; t < a.T; ++t) {
         const float beta = beta_p[t * beta_stride];
@@ -318,8 +329,6 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
             // ---- row r of D, by location and by facility, and of the permuted flows ----
             if (own) {
                 const int pk = sm.p[k];
-                const int32_t drk = D[(int64_t)r * N + k];
-                const int32_t fk = F[(int64_t)pr * N + pk];
                 sm.d[k] = drk;
                 sm.f[k] = fk;
                 if (PAIRS) {
@@ -330,6 +339,14 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
                 }
             }
             __syncthreads();
+            // prefetch of the next location's rows under the current p; an
+            // accepted exchange of r and s permutes the flows afterwards
+            const int rn = r + 1 < N ? r + 1 : 0;
+            int32_t dn = 0, fn = 0;
+            if (own) {
+                dn = D[(int64_t)rn * N + k];
+                fn = F[(int64_t)sm.p[rn] * N + sm.p[k]];
+            }
             // ---- column r of H (location k) and row r of H by facility (facility k) ----
             int64_t hkr = 0, gk = 0;
             if constexpr (PAIRS) {
@@ -414,13 +431,19 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
             __syncthreads();
             n_tie += sm.tie;
             if (a.choices && k == 0) a.choices[(rep * a.T + t) * N + r] = s;
-            if (s == r) continue;
+            if (s == r) {
+                drk = dn;
+                fk = fn;
+                continue;
+            }
             // ---- accepted exchange of r and s: E, diag H, p ----
             ++n_acc;
             const int ps = sm.p[s];
             if (own) {
-                sm.u[k] = D[(int64_t)s * N + k] - sm.d[k];          // D[k][s] - D[k][r]
-                sm.v[k] = sm.f[k] - F[(int64_t)ps * N + sm.p[k]];   // Fp[r][k] - Fp[s][k]
+                sm.u[k] = D[(int64_t)s * N + k] - drk;              // D[k][s] - D[k][r]
+                sm.v[k] = fk - F[(int64_t)ps * N + sm.p[k]];        // Fp[r][k] - Fp[s][k]
+                if (k == r) sm.xf[0] = fn;
+                if (k == s) sm.xf[1] = fn;
             }
             const int64_t h_rs = sm.G[ps], h_sr = sm.hcol[s];
             const int64_t dE = 2 * (h_rs + h_sr - sm.hd[r] - sm.hd[s]) +
@@ -440,6 +463,14 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
             if (k == 0) {
                 sm.p[r] = ps;
                 sm.p[s] = pr;
+            }
+            // the next row after the exchange (tau swaps r and s): D[rn][k] as
+            // prefetched; F[p'(rn)][p'(k)] = F[p(rn)][p(tau k)], the prefetched
+            // row at tau k, or, when rn = s (p'(s) = p(r)), the current row at tau k
+            drk = dn;
+            if (own) {
+                const int tk = k == r ? s : k == s ? r : k;
+                fk = rn == s ? sm.f[tk] : k == r ? sm.xf[1] : k == s ? sm.xf[0] : fn;
             }
             __syncthreads();
             if (E < E_best) {
