@@ -72,8 +72,7 @@ extern "C" {
 #define PDIT_RECOMPUTE_SPLIT 4  /* int8 MFMA on 7-bit byte planes, int64 combine: needs |D|,|F| < 2^14 */
 
 /* Which sweep kernel runs. */
-#define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else large (single
-                               instances) or plain (batched runs) */
+#define PDIT_SWEEP_AUTO 0   /* fast kernel when the instance fits it, else large */
 #define PDIT_SWEEP_PLAIN 1  /* one workgroup per replica, H in device memory */
 #define PDIT_SWEEP_FAST 2   /* replica state on chip, speculative row evaluation; needs
                                |dE| < 2^30 - 1 and N <= 256.  N <= 128: the table of swap energy
@@ -98,10 +97,10 @@ extern "C" {
                                all replicas share through the cache), diag H is kept on chip and
                                moved in O(N) per accepted exchange.  512 threads per replica.
                                Same dynamics and results as the other kernels.  AUTO picks it
-                               in pdit_run_sweeps, pdit_beta_select and pdit_run_pt (periodic
-                               schedule; diag H is the state saved between periods) when the
-                               fast kernel does not fit; batched runs reject it
-                               (PDIT_EINVAL). */
+                               wherever the fast kernel does not fit: single runs, beta-range
+                               selection, periodic tempering (diag H is the state saved
+                               between periods) and batched runs (a persistent group per copy
+                               layout, product width and H width). */
 
 typedef struct pdit_ctx pdit_t;
 

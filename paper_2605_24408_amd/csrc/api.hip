@@ -818,13 +818,12 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
     if (ctx->rec_choices || ctx->rec_trace)
         return fail(ctx, PDIT_EINVAL, "recording is not available for batched runs");
-    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_FAST)
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_LARGE ||
+        ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL,
                     ctx->opts.sweep == PDIT_SWEEP_CLIQUE
                         ? "the clique kernel runs only in pdit_run_sweeps"
-                        : ctx->opts.sweep == PDIT_SWEEP_LARGE
-                              ? "batched runs do not take the large kernel"
-                              : "unknown sweep kernel");
+                        : "unknown sweep kernel");
     for (int k = 0; k < n_inst; ++k) {
         const pdit_instance &in = inst[k];
         if (in.N < 2 || in.N > PDIT_NMAX || in.R < 1)
@@ -850,11 +849,13 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     struct Plan {
         int mode;
         int fclass;
-        bool h64, fast, zd;
+        bool h64, fast, large, zd;
         int64_t hoff;  // byte offset of replica 0's H
+        pdit::LargePlan lp;
+        size_t coff;   // large kernel: byte offset of the instance's copies
     };
     std::vector<Plan> plan(n_inst);
-    size_t hbytes = 0;
+    size_t hbytes = 0, cbytes = 0;
     for (int k = 0; k < n_inst; ++k) {
         const InstanceStats &q = st[k];
         if (q.asym_d || q.asym_f) return fail(ctx, PDIT_ENOTSYM, "D or F of an instance is not symmetric");
@@ -872,7 +873,10 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         pl.fclass = pdit::fast_class(inst[k].N, q);
         if (ctx->opts.sweep == PDIT_SWEEP_FAST && !pl.fclass)
             return fail(ctx, PDIT_EOVERFLOW, "an instance does not fit the fast sweep kernel");
-        pl.fast = ctx->opts.sweep != PDIT_SWEEP_PLAIN && pl.fclass != 0;
+        pl.fast = (ctx->opts.sweep == PDIT_SWEEP_AUTO || ctx->opts.sweep == PDIT_SWEEP_FAST) &&
+                  pl.fclass != 0;
+        // without a fast class the kernel that stores no H replaces the plain one
+        pl.large = !pl.fast && ctx->opts.sweep != PDIT_SWEEP_PLAIN;
         pl.zd = q.diag_nz_d == 0 && q.diag_nz_f == 0;
         rc = pick_recompute(ctx, q, bound, ctx->opts.recompute, &pl.mode);
         if (rc) return rc;
@@ -880,9 +884,19 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         hbytes = (hbytes + 7) & ~(size_t)7;
         pl.hoff = (int64_t)hbytes;
         hbytes += (size_t)inst[k].R * inst[k].N * inst[k].N * elem;
+        if (pl.large) {
+            pl.lp = pdit::large_plan(inst[k].N, q);
+            cbytes = (cbytes + 255) & ~(size_t)255;
+            pl.coff = cbytes;
+            cbytes += pl.lp.bytes;
+        }
     }
     rc = ensure(ctx, ctx->h_buf, hbytes);
     if (rc) return rc;
+    if (cbytes) {
+        rc = ensure(ctx, ctx->large_buf, cbytes);
+        if (rc) return rc;
+    }
     std::vector<int32_t> Ns(n_inst), Rs(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         Ns[k] = inst[k].N;
@@ -909,6 +923,10 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         d.perm_off = perm_off;
         d.zero_diag = plan[k].zd ? 1 : 0;
         d.inst_id = k;
+        if (plan[k].large) {
+            d.cD = (const char *)ctx->large_buf.ptr + plan[k].coff;
+            d.cF = (const char *)d.cD + plan[k].lp.bytes / 2;
+        }
         rep_base += inst[k].R;
         perm_off += (int64_t)inst[k].R * inst[k].N;
     }
@@ -920,6 +938,13 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         PDIT_HIP(ctx, run_recompute(ctx, plan[k].mode, inst[k].N, inst[k].D, inst[k].F, inst[k].R,
                                     inst[k].perm, (char *)ctx->h_buf.ptr + plan[k].hoff,
                                     plan[k].h64, S.E + desc[k].rep_base));
+    for (int k = 0; k < n_inst; ++k)
+        if (plan[k].large) {
+            pdit::LargeCopies lc;
+            PDIT_HIP(ctx, pdit::launch_large_copy(ctx->stream, inst[k].N, inst[k].D, inst[k].F,
+                                                  plan[k].lp, (char *)ctx->large_buf.ptr +
+                                                  plan[k].coff, &lc));
+        }
     if (fresh) {
         PDIT_HIP(ctx, hipMemcpyAsync(S.E_best, S.E, sizeof(int64_t) * S.R_total,
                                      hipMemcpyDeviceToDevice, ctx->stream));
@@ -937,6 +962,8 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
             int nmax;
             std::vector<int2> items;
             int grid;
+            bool large;
+            pdit::LargePlan lp;  // large kernel: copy layout and product width of the group
         };
         std::vector<Group> groups;
         std::vector<int> order(n_inst);
@@ -948,16 +975,21 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
             const int nmax = pl.fast ? pl.fclass : 0;
             Group *g = nullptr;
             for (auto &gg : groups)
-                if (gg.fast == pl.fast && gg.nmax == nmax && (pl.fast ? gg.zd == pl.zd : gg.h64 == pl.h64))
+                if (gg.fast == pl.fast && gg.large == pl.large && gg.nmax == nmax &&
+                    (pl.fast ? gg.zd == pl.zd : gg.h64 == pl.h64) &&
+                    (!pl.large || (gg.lp.elem == pl.lp.elem && gg.lp.narrow == pl.lp.narrow)))
                     g = &gg;
             if (!g) {
-                groups.push_back(Group{pl.fast, pl.fast && pl.zd, !pl.fast && pl.h64, nmax, {}, 0});
+                groups.push_back(Group{pl.fast, pl.fast && pl.zd, !pl.fast && pl.h64, nmax, {}, 0,
+                                       pl.large, pl.lp});
                 g = &groups.back();
             }
             for (int r = 0; r < inst[k].R; ++r) g->items.push_back(make_int2(k, r));
         }
         for (auto &g : groups) {
-            int bpc = g.fast ? pdit::fast_blocks_per_cu(g.nmax) : pdit::plain_blocks_per_cu(g.h64);
+            int bpc = g.fast    ? pdit::fast_blocks_per_cu(g.nmax)
+                      : g.large ? pdit::large_blocks_per_cu()
+                                : pdit::plain_blocks_per_cu(g.h64);
             if (ctx->opts.blocks_per_cu > 0 && ctx->opts.blocks_per_cu < bpc) bpc = ctx->opts.blocks_per_cu;
             const int64_t want = (int64_t)bpc * std::max(ctx->num_cus, 1);
             g.grid = (int)std::min<int64_t>(want, (int64_t)g.items.size());
@@ -1028,8 +1060,9 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                 b.counters = S.counters;
                 b.T = n_sweeps;
                 b.seq_threshold = seq_thr >= 0 ? seq_thr : pdit::default_seq_threshold(g.nmax, g.nmax);
-                cap = g.fast ? pdit::launch_sweep_fast_persistent(cs, g.nmax, g.zd, b, g.grid)
-                             : pdit::launch_sweep_plain_persistent(cs, g.h64, b, g.grid);
+                cap = g.fast    ? pdit::launch_sweep_fast_persistent(cs, g.nmax, g.zd, b, g.grid)
+                      : g.large ? pdit::launch_sweep_large_persistent(cs, g.lp, g.h64, b, g.grid)
+                                : pdit::launch_sweep_plain_persistent(cs, g.h64, b, g.grid);
             }
             hipGraph_t graph = nullptr;
             const hipError_t end = hipStreamEndCapture(cs, &graph);

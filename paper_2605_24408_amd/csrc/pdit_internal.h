@@ -281,6 +281,10 @@ hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32
                              const LargePlan &pl, void *buf, LargeCopies *out);
 hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const LargePlan &pl,
                               const LargeCopies &c);
+struct BatchArgs;
+hipError_t launch_sweep_large_persistent(hipStream_t s, const LargePlan &pl, bool h64,
+                                         const BatchArgs &b, int grid);
+int large_blocks_per_cu();
 // size class of the on-chip kernel that runs an instance (16, 32, 64, 96, 128,
 // 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic
 int fast_class(int N, const InstanceStats &st);

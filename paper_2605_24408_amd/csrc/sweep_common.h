@@ -14,6 +14,7 @@ struct ReplicaJob {
     int N;
     const int32_t *D;        // [N][N]
     const int32_t *F;        // [N][N]
+    const void *cD, *cF;     // large kernel: padded copies of D and F (else null)
     int32_t *perm;           // [N] in/out
     const void *H;           // [N][N] initial H (int32, or int64 on the plain kernel)
     int64_t *E;              // in: initial energy, out: final
@@ -50,6 +51,7 @@ struct BatchInstance {
     const int32_t *D;
     const int32_t *F;
     int32_t *perm;           // [R][N]
+    const void *cD, *cF;     // large kernel: the instance's padded copies of D and F (else null)
     const float *beta;       // [T]
     int64_t h_off;           // element offset of replica 0's H in the H buffer
     int64_t rep_base;        // index of replica 0 in the per-replica state arrays
@@ -88,6 +90,8 @@ __device__ __forceinline__ ReplicaJob batch_job(const BatchArgs &b, int item, si
     j.N = in.N;
     j.D = in.D;
     j.F = in.F;
+    j.cD = in.cD;
+    j.cF = in.cF;
     j.perm = in.perm + r * in.N;
     j.H = (const char *)b.H + (in.h_off + r * (int64_t)in.N * in.N) * hsize;
     j.E = b.E + in.rep_base + r;

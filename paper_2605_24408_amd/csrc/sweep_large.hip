@@ -39,6 +39,7 @@
 
 #include "device_common.h"
 #include "pdit_internal.h"
+#include "sweep_common.h"
 
 namespace pdit {
 namespace {
@@ -265,17 +266,16 @@ __device__ __forceinline__ void column_products(__amdgpu_buffer_rsrc_t M1,
     gk = acc2;
 }
 
+// One replica's sweeps with the whole workgroup (512 threads).
 template <bool PAIRS, bool NARROW, typename HT>
-__global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a, LargeCopies c) {
-    __shared__ LargeSmem sm;
-    const int N = a.N;
+__device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
+    const int N = j.N;
     const int N32 = (N + 2 * kRowBlock - 1) / (2 * kRowBlock) * (2 * kRowBlock);
-    const int64_t rep = blockIdx.x;
     const int k = threadIdx.x, lane = k & 63;
     const int wv = __builtin_amdgcn_readfirstlane(k >> 6);  // wave-uniform, as the compiler must see
     const bool own = k < N;
-    const int32_t *__restrict__ D = a.D;
-    const int32_t *__restrict__ F = a.F;
+    const int32_t *__restrict__ D = j.D;
+    const int32_t *__restrict__ F = j.F;
     // word rows of a copy: row pairs (int16, N4 = N rounded up to 4 words,
     // N128 / 2 + 4 word rows) or rows (int32, N words, N32 + 16 rows)
     const int N4 = (N + 3) & ~3;
@@ -283,19 +283,21 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     const uint32_t pitch = (uint32_t)(PAIRS ? N4 : N) * 4;
     const uint32_t copy_bytes = PAIRS ? (uint32_t)(N128 / 2 + 4) * pitch
                                       : (uint32_t)(N32 + kRowBlock) * pitch;
-    const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(c.D, copy_bytes);
-    const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(c.F, copy_bytes);
+    const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(j.cD, copy_bytes);
+    const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(j.cF, copy_bytes);
     // lanes past N read column 0 (results unused): every offset stays inside
     // the copy even for the prefetch of the zero block
     const uint32_t col = own ? (uint32_t)k : 0u;
     uint32_t voff[kRowBlock];  // int32 copies: column k of the rows of a block
 #pragma unroll
     for (int u = 0; u < kRowBlock; ++u) voff[u] = col * 4 + u * pitch;
-    int32_t *perm = a.perm + rep * N;
-    int32_t *pbest = a.perm_best + rep * N;
-    HT *H0 = (HT *)a.H + rep * (int64_t)N * N;  // diag H of the initial p; kSaveState writes it back
-    const float *beta_p = a.slot ? a.beta + a.slot[rep] : a.beta;
-    const int64_t beta_stride = a.slot ? 0 : 1;
+    int32_t *perm = j.perm;
+    int32_t *pbest = j.perm_best;
+    // diag H of the initial p; kSaveState writes the final one back (the
+    // library's H buffer, writable)
+    HT *H0 = (HT *)const_cast<void *>(j.H);
+    const float *beta_p = j.beta;
+    const int64_t beta_stride = j.beta_stride;
 
     if (own) {
         sm.p[k] = perm[k];
@@ -308,8 +310,8 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
         sm.f16[k] = 0;
         sm.dq16[k] = 0;
     }
-    int64_t E = a.E[rep];
-    int64_t E_best = a.E_best[rep];
+    int64_t E = *j.E;
+    int64_t E_best = *j.E_best;
     int64_t n_acc = 0, n_tie = 0;
     __syncthreads();
     // location k's entries of the current row: D[r][k] and F[p(r)][p(k)],
@@ -320,10 +322,10 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
         fk = F[(int64_t)sm.p[0] * N + sm.p[k]];
     }
 
-    for (int64_t t = 0; t < a.T; ++t) {
+    for (int64_t t = 0; t < j.T; ++t) {
         const float beta = beta_p[t * beta_stride];
         const int64_t dthr = zero_weight_distance64(beta);
-        const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
+        const uint32_t g = (uint32_t)(j.sweep_offset + (uint64_t)t);
         for (int r = 0; r < N; ++r) {
             const int pr = sm.p[r];
             // ---- row r of D, by location and by facility, and of the permuted flows ----
@@ -417,7 +419,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
                 Z += x;
             }
             const uint64_t C = off + cw;
-            const uint32_t u24 = uniform24(a.seed, (uint32_t)r, g, (uint32_t)rep, a.inst_id);
+            const uint32_t u24 = uniform24(j.seed, (uint32_t)r, g, j.rep, j.inst);
             const uint64_t thr = ((uint64_t)u24 * Z) >> 24;
             // the first candidate whose running sum exceeds the threshold
             const uint64_t hit = __ballot(own && C > thr);
@@ -430,7 +432,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
             if (k == s) sm.tie = is_tie(C - qk, C, Z, u24) ? 1 : 0;
             __syncthreads();
             n_tie += sm.tie;
-            if (a.choices && k == 0) a.choices[(rep * a.T + t) * N + r] = s;
+            if (j.choices && k == 0) j.choices[t * N + r] = s;
             if (s == r) {
                 drk = dn;
                 fk = fn;
@@ -478,21 +480,70 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
                 if (own) pbest[k] = sm.p[k];
             }
         }
-        if (a.E_trace && k == 0) a.E_trace[rep * a.T + t] = E;
+        if (j.E_trace && k == 0) j.E_trace[t] = E;
     }
     if (own) {
         perm[k] = sm.p[k];
-        if (a.flags & kSaveState) H0[(int64_t)k * N + k] = (HT)sm.hd[k];
+        if (j.flags & kSaveState) H0[(int64_t)k * N + k] = (HT)sm.hd[k];
     }
     if (k == 0) {
-        a.E[rep] = E;
-        a.E_best[rep] = E_best;
-        const bool acc = (a.flags & kAccumCounters) != 0;
-        a.counters[3 * rep + 0] = (acc ? a.counters[3 * rep + 0] : 0) + (int64_t)N * a.T;
-        a.counters[3 * rep + 1] = (acc ? a.counters[3 * rep + 1] : 0) + n_acc;
-        a.counters[3 * rep + 2] = (acc ? a.counters[3 * rep + 2] : 0) + n_tie;
+        *j.E = E;
+        *j.E_best = E_best;
+        const bool acc = (j.flags & kAccumCounters) != 0;
+        j.counters[0] = (acc ? j.counters[0] : 0) + (int64_t)N * j.T;
+        j.counters[1] = (acc ? j.counters[1] : 0) + n_acc;
+        j.counters[2] = (acc ? j.counters[2] : 0) + n_tie;
     }
 }
+
+template <bool PAIRS, bool NARROW, typename HT>
+__global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a, LargeCopies c) {
+    __shared__ LargeSmem sm;
+    const int64_t rep = blockIdx.x;
+    ReplicaJob j;
+    j.N = a.N;
+    j.D = a.D;
+    j.F = a.F;
+    j.cD = c.D;
+    j.cF = c.F;
+    j.perm = a.perm + rep * a.N;
+    j.H = (HT *)a.H + rep * (int64_t)a.N * a.N;
+    j.E = a.E + rep;
+    j.E_best = a.E_best + rep;
+    j.perm_best = a.perm_best + rep * a.N;
+    j.counters = a.counters + 3 * rep;
+    job_beta(j, a.beta, a.slot, rep);
+    j.T = a.T;
+    j.seed = a.seed;
+    j.sweep_offset = a.sweep_offset;
+    j.rep = (uint32_t)rep;
+    j.inst = a.inst_id;
+    j.choices = a.choices ? a.choices + rep * a.T * a.N : nullptr;
+    j.E_trace = a.E_trace ? a.E_trace + rep * a.T : nullptr;
+    j.seq_threshold = a.seq_threshold;
+    j.zero_diag = a.zero_diag;
+    j.tstate = nullptr;
+    j.flags = a.flags;
+    large_replica<PAIRS, NARROW, HT>(j, sm);
+}
+
+// Persistent: each workgroup takes (instance, replica) items of one group
+// (same copy layout and H width) from a queue until it is exhausted.
+template <bool PAIRS, bool NARROW, typename HT>
+__global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArgs b) {
+    __shared__ LargeSmem sm;
+    __shared__ int item_sh;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(item_sh);  // wave-uniform
+        __syncthreads();
+        if (item >= b.n_items) break;
+        large_replica<PAIRS, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
+        __syncthreads();
+    }
+}
+
 
 // Padded int32 copies: rows 0..N-1 of D (then F), the other rows zero.
 __global__ void large_copy32_kernel(int N, int rows, const int32_t *D, const int32_t *F,
@@ -556,6 +607,35 @@ hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32
         large_copy32_kernel<<<grid, 256, 0, s>>>(N, pl.rows, D, F, (int32_t *)out->D,
                                                  (int32_t *)out->F);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_large_persistent(hipStream_t s, const LargePlan &pl, bool h64,
+                                         const BatchArgs &b, int grid) {
+#define PDIT_LARGE_P(PAIRS, NARROW)                                                          \
+    do {                                                                                     \
+        if (h64)                                                                             \
+            sweep_large_persistent<PAIRS, NARROW, int64_t><<<grid, kLargeThreads, 0, s>>>(b); \
+        else                                                                                 \
+            sweep_large_persistent<PAIRS, NARROW, int32_t><<<grid, kLargeThreads, 0, s>>>(b); \
+    } while (0)
+    if (pl.elem == 2 && pl.narrow)
+        PDIT_LARGE_P(true, true);
+    else if (pl.elem == 2)
+        PDIT_LARGE_P(true, false);
+    else if (pl.narrow)
+        PDIT_LARGE_P(false, true);
+    else
+        PDIT_LARGE_P(false, false);
+#undef PDIT_LARGE_P
+    return hipGetLastError();
+}
+
+int large_blocks_per_cu() {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, sweep_large_persistent<true, true, int64_t>, kLargeThreads, 0);
+    (void)hipGetLastError();
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const LargePlan &pl,

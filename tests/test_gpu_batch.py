@@ -191,3 +191,40 @@ def test_uneven_workload_full_size_sampled():
             assert got[k]["E"][j] == oracle.energy(i.D, i.F, got[k]["perm"][j])
             assert got[k]["E_best"][j] == oracle.energy(i.D, i.F, got[k]["perm_best"][j])
             assert got[k]["counters"][j][0] == i.N * 2000
+
+
+def large_batch(T=3, R=2):
+    """Instances that no on-chip class takes (N > 256, or values beyond the
+    fast kernels' exact range) beside table-kernel ones: every copy layout
+    and product width of the kernel without a stored H, int32 and int64 H."""
+    rng = np.random.default_rng(91)
+    out = []
+    for N, hi in [(300, 40), (40, 40), (140, 100_000), (260, 10_000), (70, 30_000), (512, 99)]:
+        D = W.sym_uniform(rng, N, 0, hi)
+        F = W.sym_uniform(rng, N, 0, 40 if hi == 100_000 else hi)
+        perms = W.random_perms(rng, R, N)
+        s = W.energy_scale(D, F)
+        beta = W.beta_geometric(0.1 / s, 30.0 / s, T)
+        out.append((D, F, perms, beta))
+    return out
+
+
+@pytest.mark.parametrize("sweep", ["auto", "large"])
+def test_batch_large_groups(sweep):
+    """Batched runs put the instances without an on-chip class on the
+    persistent kernel without a stored H (grouped by copy layout, product
+    width and H width); every replica matches the oracle, and a second call
+    (the captured graph replayed) matches the resumed oracle."""
+    from paper_2605_24408_amd import pdit as P
+    batch = large_batch()
+    dbatch = to_dev(batch)
+    say(f"batch large groups sweep={sweep}")
+    refs = oracle_batch(batch, 21)
+    with P.Pdit(sweep=sweep) as ctx:
+        ctx.run_sweeps_batch(dbatch, 21)
+        got = gpu_state(ctx, dbatch)
+        assert check(got, refs) <= 1
+        ctx.run_sweeps_batch(dbatch, 21)
+        got2 = gpu_state(ctx, dbatch)
+    refs2 = oracle_batch(batch, 21, sweep_offset=3, prev=refs)
+    assert check(got2, refs2) <= 2

@@ -189,16 +189,3 @@ def test_n512_workload_sampled(P):
         assert got["E"][k] == oracle.energy(inst.D, inst.F, got["perm"][k])
         assert got["E_best"][k] == oracle.energy(inst.D, inst.F, got["perm_best"][k])
     assert (got["counters"][:, 0] == 512 * T).all()
-
-
-def test_large_rejected_in_batches(P):
-    """Batched runs do not take the large kernel."""
-    rng = np.random.default_rng(1)
-    N = 20
-    D, F = instance(rng, N, 9, 9)
-    with P.Pdit(sweep="large") as ctx:
-        insts = [(dev(D, torch.int32), dev(F, torch.int32),
-                  dev(W.random_perms(rng, 2, N), torch.int32),
-                  dev(np.ones(2, np.float32), torch.float32))]
-        with pytest.raises(Exception, match="do not take the large kernel"):
-            ctx.run_sweeps_batch(insts, 1)
