@@ -21,11 +21,11 @@
 // One workgroup of 512 threads (8 waves) per replica; thread k owns location
 // k in the draw.  The products read library copies of D and F:
 // * |D|, |F| <= 32767: int16 row pairs, one 32-bit word = rows 2i and 2i+1
-//   of a column, rows padded with zeros to N128 (N rounded up to 128) and
+//   of a column, rows padded with zeros to N64 (N rounded up to 64) and
 //   columns to N4 (rounded up to 4), plus 4 zero word rows.  Each lane takes
 //   four adjacent columns with one 16-byte load per word row and matrix and
 //   `v_dot2_i32_i16` (exact in int32 per word); the two waves of pair q take
-//   word rows [q N128/8, (q+1) N128/8) for 256 columns each, and the four
+//   word rows [q N64/8, (q+1) N64/8) for 256 columns each, and the four
 //   quarter sums meet in LDS.  Wide 16-byte loads matter: one-column 4-byte
 //   loads ran at half the per-CU rate from L2.
 // * otherwise: int32 rows (N32 = N rounded up to 32, plus 16 zero rows), one
@@ -65,8 +65,9 @@ struct LargeSmem {
     int64_t wmin[kLargeWaves];
     uint64_t wsum[kLargeWaves];
     int32_t wsel[kLargeWaves];
+    int32_t wtie[kLargeWaves];     // tie flag of each wave's first hit
+    uint32_t u24s[kLargeNMax];     // the sweep's uniforms, one per location
     int32_t xf[2];  // prefetched next-row flows of locations r and s (accepted exchange)
-    int32_t tie;
 };
 
 typedef short short2v __attribute__((ext_vector_type(2)));
@@ -277,11 +278,11 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
     const int32_t *__restrict__ D = j.D;
     const int32_t *__restrict__ F = j.F;
     // word rows of a copy: row pairs (int16, N4 = N rounded up to 4 words,
-    // N128 / 2 + 4 word rows) or rows (int32, N words, N32 + 16 rows)
+    // N64 / 2 + 4 word rows) or rows (int32, N words, N32 + 16 rows)
     const int N4 = (N + 3) & ~3;
-    const int N128 = (N + 127) & ~127;
+    const int N64 = (N + 63) & ~63;
     const uint32_t pitch = (uint32_t)(PAIRS ? N4 : N) * 4;
-    const uint32_t copy_bytes = PAIRS ? (uint32_t)(N128 / 2 + 4) * pitch
+    const uint32_t copy_bytes = PAIRS ? (uint32_t)(N64 / 2 + 4) * pitch
                                       : (uint32_t)(N32 + kRowBlock) * pitch;
     const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(j.cD, copy_bytes);
     const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(j.cF, copy_bytes);
@@ -326,6 +327,9 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
         const float beta = beta_p[t * beta_stride];
         const int64_t dthr = zero_weight_distance64(beta);
         const uint32_t g = (uint32_t)(j.sweep_offset + (uint64_t)t);
+        // the sweep's N uniforms at once, lane k for location k (ordered
+        // before their first use by the first barrier of update 0)
+        if (own) sm.u24s[k] = uniform24(j.seed, (uint32_t)k, g, j.rep, j.inst);
         for (int r = 0; r < N; ++r) {
             const int pr = sm.p[r];
             // ---- row r of D, by location and by facility, and of the permuted flows ----
@@ -357,7 +361,7 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                 const int rq = wv >> 1, ch = wv & 1;
                 const int c0 = 256 * ch + 4 * lane;
                 const bool act = c0 < N4;
-                const int Q = N128 / 8;
+                const int Q = N64 / 8;  // a multiple of 8 word rows: whole block pairs
                 if (256 * ch < N4) {
                     int64_t p1[4], p2[4];
                     quarter_products<NARROW>(Dc, Fc, pitch, act ? (uint32_t)c0 * 4 : 0u, rq * Q,
@@ -370,13 +374,6 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                         }
                     }
                 }
-                __syncthreads();
-                if (own) {
-                    hkr = sm.part1[0][k] + sm.part1[1][k] + sm.part1[2][k] + sm.part1[3][k];
-                    gk = sm.part2[0][k] + sm.part2[1][k] + sm.part2[2][k] + sm.part2[3][k];
-                    sm.G[k] = gk;
-                    sm.hcol[k] = hkr;
-                }
             } else if (wv * 64 < N) {  // waves with no location skip the products
                 column_products<NARROW>(Dc, Fc, voff, kRowBlock * pitch, sm.f, sm.dq, N32, hkr,
                                         gk);
@@ -386,10 +383,25 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                 }
             }
             __syncthreads();
+            // H[x][r] and H[r][x] (= G at facility p(x)): on the paired path the
+            // sums of the four quarters, read where they lie
+            auto hcol_at = [&](int x) -> int64_t {
+                if constexpr (PAIRS)
+                    return sm.part1[0][x] + sm.part1[1][x] + sm.part1[2][x] + sm.part1[3][x];
+                else
+                    return sm.hcol[x];
+            };
+            auto g_at = [&](int c) -> int64_t {
+                if constexpr (PAIRS)
+                    return sm.part2[0][c] + sm.part2[1][c] + sm.part2[2][c] + sm.part2[3][c];
+                else
+                    return sm.G[c];
+            };
             // ---- energy change of candidate k (Eq. 3) ----
             int64_t v = INT64_MAX;
             if (own) {
-                const int64_t hrk = sm.G[sm.p[k]];
+                if constexpr (PAIRS) hkr = hcol_at(k);
+                const int64_t hrk = g_at(sm.p[k]);
                 const int64_t h = hrk + hkr - sm.hd[r] - sm.hd[k];
                 const int64_t dd = (int64_t)sm.ddiag[r] + sm.ddiag[k] - 2 * (int64_t)sm.d[k];
                 const int64_t ff = (int64_t)sm.fdiag[pr] + sm.fdiag[sm.p[k]] - 2 * (int64_t)sm.f[k];
@@ -419,19 +431,28 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                 Z += x;
             }
             const uint64_t C = off + cw;
-            const uint32_t u24 = uniform24(j.seed, (uint32_t)r, g, j.rep, j.inst);
+            const uint32_t u24 = sm.u24s[r];
             const uint64_t thr = ((uint64_t)u24 * Z) >> 24;
-            // the first candidate whose running sum exceeds the threshold
+            // the first candidate whose running sum exceeds the threshold: each
+            // wave publishes its first hit and that candidate's tie flag
             const uint64_t hit = __ballot(own && C > thr);
-            if (lane == 0) sm.wsel[wv] = hit ? 64 * wv + __ffsll((unsigned long long)hit) - 1 : 0x7fffffff;
+            const int first = hit ? __ffsll((unsigned long long)hit) - 1 : -1;  // wave-uniform
+            if (first < 0) {
+                if (lane == 0) sm.wsel[wv] = 0x7fffffff;
+            } else if (lane == first) {
+                sm.wsel[wv] = 64 * wv + first;
+                sm.wtie[wv] = is_tie(C - qk, C, Z, u24) ? 1 : 0;
+            }
             __syncthreads();
             int s = 0x7fffffff;
 #pragma unroll
             for (int w = 0; w < kLargeWaves; ++w) s = min(s, sm.wsel[w]);
-            if (s >= N) s = r;  // unreachable: location N-1 holds C = Z > thr
-            if (k == s) sm.tie = is_tie(C - qk, C, Z, u24) ? 1 : 0;
-            __syncthreads();
-            n_tie += sm.tie;
+            int tie = 0;
+            if (s >= N)
+                s = r;  // unreachable: location N-1 holds C = Z > thr
+            else
+                tie = sm.wtie[s >> 6];
+            n_tie += tie;
             if (j.choices && k == 0) j.choices[t * N + r] = s;
             if (s == r) {
                 drk = dn;
@@ -447,7 +468,7 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                 if (k == r) sm.xf[0] = fn;
                 if (k == s) sm.xf[1] = fn;
             }
-            const int64_t h_rs = sm.G[ps], h_sr = sm.hcol[s];
+            const int64_t h_rs = g_at(ps), h_sr = hcol_at(s);
             const int64_t dE = 2 * (h_rs + h_sr - sm.hd[r] - sm.hd[s]) +
                                ((int64_t)sm.ddiag[r] + sm.ddiag[s] - 2 * (int64_t)sm.d[s]) *
                                    ((int64_t)sm.fdiag[pr] + sm.fdiag[ps] - 2 * (int64_t)sm.f[s]);
@@ -584,7 +605,7 @@ LargePlan large_plan(int N, const InstanceStats &st) {
                 (int64_t)kRowBlock * st.max_abs_d * st.max_abs_f < ((int64_t)1 << 31);
     pl.elem = mx <= 32767 ? 2 : 4;
     if (pl.elem == 2) {
-        pl.rows = ((N + 127) & ~127) / 2 + 4;  // word rows
+        pl.rows = ((N + 63) & ~63) / 2 + 4;  // word rows
         pl.bytes = 2 * (size_t)pl.rows * ((N + 3) & ~3) * 4;
     } else {
         pl.rows = (N + 2 * kRowBlock - 1) / (2 * kRowBlock) * (2 * kRowBlock) + kRowBlock;
