@@ -69,8 +69,9 @@ def src_hash(path: str) -> str:
 
 
 def other_workload(args):
-    """Fast (auto) vs plain path on one of the other workload shapes; one
-    JSON line, not the benchmark figure."""
+    """Automatic plan ("fast"), the kernel without a stored H ("large") and
+    the plain path on one of the other workload shapes; one JSON line, not
+    the benchmark figure."""
     import numpy as np
     import torch
 
@@ -92,11 +93,11 @@ def other_workload(args):
     out = {"workload": args.workload, "instances": len(insts),
            "replicas": sum(i.R for i in insts), "sweeps": insts[0].T, "updates": updates}
     results = {}
-    for path in ("fast", "plain"):
-        ctx = pdit.Pdit(sweep="auto" if path == "fast" else "plain",
-                        recompute="auto" if path == "fast" else "plain")
+    for path in ("fast", "large", "plain"):
+        ctx = pdit.Pdit(sweep={"fast": "auto"}.get(path, path),
+                        recompute="plain" if path == "plain" else "auto")
         times = []
-        for rep in range(2 if path == "fast" else 1):
+        for rep in range(1 if path == "plain" else 2):
             for (_, _, p, _), p0 in zip(dbatch, perms0):
                 p.copy_(p0)
             ctx.set_sweep_offset(0)
@@ -118,7 +119,8 @@ def other_workload(args):
                      "acceptance": cnt["accepted"] / max(cnt["updates"], 1), "ties": cnt["ties"]}
         ctx.close()
     out["speedup"] = results["plain"][0] / results["fast"][0]
-    out["identical_best"] = bool(np.array_equal(results["fast"][1], results["plain"][1]))
+    out["identical_best"] = bool(np.array_equal(results["fast"][1], results["plain"][1]) and
+                                 np.array_equal(results["large"][1], results["plain"][1]))
     print(json.dumps(out), flush=True)
 
 
