@@ -168,13 +168,20 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
             src[c] = k == r ? s : k == s ? r : k;
             v[c] = fp_at(r, src[c]) - fp_at(s, src[c]);
         }
+        // 2 u_i of the wave's 16 rows, lane l for row 16 wv + l: one round of
+        // loads beside the v gathers instead of one per row in the loop below
+        int32_t u2l = 0;
+        if (lane < 16) {
+            const int i = 16 * wv + lane;
+            const int32_t du = d_at(s, i) - d_at(r, i);
+            u2l = kDScale == 4 ? du / 2 : 2 * du;
+        }
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
 #pragma unroll 4
         for (int ii = 0; ii < 16; ++ii) {
             const int i = 16 * wv + ii;
             if (EXACT || i < N) {
-                const int32_t du = d_at(s, i) - d_at(r, i);
-                const int32_t u2 = kDScale == 4 ? du / 2 : 2 * du;  // 2 u_i
+                const int32_t u2 = __builtin_amdgcn_readlane(u2l, ii);  // 2 u_i
                 int32_t x[CPL];
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) x[c] = Hs[i * P + src[c]];
