@@ -160,34 +160,44 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         ++n_acc;
         // column k of the new H is column src(k) of H + u v^T, with
         // u_i = D[i][s] - D[i][r] and v_src = Fp[r][src] - Fp[s][src]
+        // padding rows (i >= N) get u = 0 and padding columns v = 0, so the
+        // update leaves them as they are and the loop below needs no bound
+        // test per row or column (such tests made it a chain of branches
+        // that waited for every row's LDS reads)
         int src[CPL];
         int32_t v[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int k = (lane + 64 * c) < NMAX ? lane + 64 * c : 0;
             src[c] = k == r ? s : k == s ? r : k;
-            v[c] = fp_at(r, src[c]) - fp_at(s, src[c]);
+            v[c] = (EXACT || k < N) ? fp_at(r, src[c]) - fp_at(s, src[c]) : 0;
         }
         // 2 u_i of the wave's 16 rows, lane l for row 16 wv + l: one round of
         // loads beside the v gathers instead of one per row in the loop below
         int32_t u2l = 0;
         if (lane < 16) {
             const int i = 16 * wv + lane;
-            const int32_t du = d_at(s, i) - d_at(r, i);
+            const int32_t du = (EXACT || i < N) ? d_at(s, i) - d_at(r, i) : 0;
             u2l = kDScale == 4 ? du / 2 : 2 * du;
         }
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
-#pragma unroll 4
-        for (int ii = 0; ii < 16; ++ii) {
-            const int i = 16 * wv + ii;
-            if (EXACT || i < N) {
-                const int32_t u2 = __builtin_amdgcn_readlane(u2l, ii);  // 2 u_i
-                int32_t x[CPL];
+        // four rows at a time: every read of the group before its writes, so
+        // one LDS round trip serves four rows
+        for (int i0 = 16 * wv; i0 < 16 * wv + 16; i0 += 4) {
+            int32_t x[4][CPL];
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) x[c] = Hs[i * P + src[c]];
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
-                    if (lane + 64 * c < N) Hs[i * P + lane + 64 * c] = (HT)(x[c] + u2 * v[c]);
+                    if (64 * c + 64 <= NMAX || lane + 64 * c < NMAX)
+                        x[q][c] = Hs[(i0 + q) * P + src[c]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t u2 = __builtin_amdgcn_readlane(u2l, i0 - 16 * wv + q);  // 2 u_i
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if (64 * c + 64 <= NMAX || lane + 64 * c < NMAX)
+                        Hs[(i0 + q) * P + lane + 64 * c] = (HT)(x[q][c] + u2 * v[c]);
             }
         }
         __builtin_amdgcn_wave_barrier();
