@@ -62,6 +62,7 @@ struct FastSmem {
     int32_t pv[NMAX];                    // p(l)
     int32_t sel_row[2][NMAX];
     int32_t flag_row[2][NMAX];           // bit 0: the row swaps, bit 1: tie
+    int32_t seq_msg[2][2];               // one update at a time: wave 0's choice, energy change
 };
 
 // Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).
@@ -140,6 +141,7 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
     int64_t E_best = *a.E_best;
     int64_t n_acc = 0, n_tie = 0;
     int parity = 0;
+    int seq_slot = 0;
     bool seq_mode = false;
 
     // speculative layout: this lane's location and candidate quarter
@@ -409,73 +411,85 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
             for (int c = 0; c < CPL; ++c)
                 u24l[c] = uniform24(a.seed, (uint32_t)(lane + 64 * c), g, a.rep, a.inst);
             for (int r = 0; r < N; ++r) {
-                int32_t v[CPL];
-                uint32_t q[CPL];
-                int32_t lmin = kBig;
-                const int32_t pr = pv[r];
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int ls = lane + 64 * c;
-                    v[c] = kBig;
-                    if (ls < N) {
-                        const int32_t x = (int32_t)Hs[r * P + ls] + (int32_t)Hs[ls * P + r] - hdv[r] - hdv[ls];
-                        int32_t dv, fv;
-                        if (LARGE) {
-                            dv = Dg[(int64_t)r * N + ls];
-                            fv = Fg[(int64_t)pr * N + pv[ls]];
-                        } else {
-                            dv = Ds[r * NMAX + ls];
-                            fv = Fp[r * PF + ls];
+                // wave 0 draws; the other waves take its choice at the barrier
+                // (slots alternate per update, so one barrier per update suffices)
+                if (wv == 0) {
+                    int32_t v[CPL];
+                    uint32_t q[CPL];
+                    int32_t lmin = kBig;
+                    const int32_t pr = pv[r];
+    #pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const int ls = lane + 64 * c;
+                        v[c] = kBig;
+                        if (ls < N) {
+                            const int32_t x = (int32_t)Hs[r * P + ls] + (int32_t)Hs[ls * P + r] - hdv[r] - hdv[ls];
+                            int32_t dv, fv;
+                            if (LARGE) {
+                                dv = Dg[(int64_t)r * N + ls];
+                                fv = Fg[(int64_t)pr * N + pv[ls]];
+                            } else {
+                                dv = Ds[r * NMAX + ls];
+                                fv = Fp[r * PF + ls];
+                            }
+                            if (ZD) {
+                                v[c] = kProdScale * __mul24(dv, fv) + x;
+                            } else {
+                                v[c] = x + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
+                            }
                         }
-                        if (ZD) {
-                            v[c] = kProdScale * __mul24(dv, fv) + x;
-                        } else {
-                            v[c] = x + __mul24(ddv[r] + ddv[ls] - 2 * dv, fdv[r] + fdv[ls] - 2 * fv);
+                        lmin = min(lmin, v[c]);
+                    }
+                    const int32_t mn = wave_min_i32(lmin);
+                    CT C[CPL];
+                    CT base = 0;
+    #pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const bool valid = lane + 64 * c < N;
+                        const int32_t d = valid ? v[c] - mn : 0;
+                        q[c] = d == 0 ? kOne : 0u;
+                        if (d > 0 && d < dthr) q[c] = gibbs_weight(beta, (float)d);
+                        if (!valid) q[c] = 0;
+                        // one chunk of 64 weights sums to at most 2^31
+                        C[c] = base + (CT)wave_scan_u32(q[c]);
+                        base = (CT)readlane_u64((uint64_t)C[c], 63);
+                    }
+                    const CT Z = base;
+                    uint32_t ur24 = 0;
+    #pragma unroll
+                    for (int c = 0; c < CPL; ++c)
+                        if ((r >> 6) == c) ur24 = (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l[c], r & 63);
+                    const CT thr = (CT)(((uint64_t)ur24 * Z) >> 24);
+                    int s = -1;
+    #pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const uint64_t hit = __ballot(C[c] > thr);
+                        if (s < 0 && hit) s = 64 * c + __ffsll((unsigned long long)hit) - 1;
+                    }
+                    if (s < 0 || s >= N) s = r;  // unreachable: location N-1 holds C = Z > thr
+                    const int sl = s & 63;
+                    CT csel = 0;
+                    uint32_t qsel = 0;
+                    int32_t vsel = 0;
+    #pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        if ((s >> 6) == c) {
+                            csel = (CT)readlane_u64((uint64_t)C[c], sl);
+                            qsel = (uint32_t)__builtin_amdgcn_readlane((int32_t)q[c], sl);
+                            vsel = __builtin_amdgcn_readlane(v[c], sl);
                         }
                     }
-                    lmin = min(lmin, v[c]);
-                }
-                const int32_t mn = wave_min_i32(lmin);
-                CT C[CPL];
-                CT base = 0;
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const bool valid = lane + 64 * c < N;
-                    const int32_t d = valid ? v[c] - mn : 0;
-                    q[c] = d == 0 ? kOne : 0u;
-                    if (d > 0 && d < dthr) q[c] = gibbs_weight(beta, (float)d);
-                    if (!valid) q[c] = 0;
-                    // one chunk of 64 weights sums to at most 2^31
-                    C[c] = base + (CT)wave_scan_u32(q[c]);
-                    base = (CT)readlane_u64((uint64_t)C[c], 63);
-                }
-                const CT Z = base;
-                uint32_t ur24 = 0;
-#pragma unroll
-                for (int c = 0; c < CPL; ++c)
-                    if ((r >> 6) == c) ur24 = (uint32_t)__builtin_amdgcn_readlane((int32_t)u24l[c], r & 63);
-                const CT thr = (CT)(((uint64_t)ur24 * Z) >> 24);
-                int s = -1;
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const uint64_t hit = __ballot(C[c] > thr);
-                    if (s < 0 && hit) s = 64 * c + __ffsll((unsigned long long)hit) - 1;
-                }
-                if (s < 0 || s >= N) s = r;  // unreachable: location N-1 holds C = Z > thr
-                const int sl = s & 63;
-                CT csel = 0;
-                uint32_t qsel = 0;
-                int32_t vsel = 0;
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    if ((s >> 6) == c) {
-                        csel = (CT)readlane_u64((uint64_t)C[c], sl);
-                        qsel = (uint32_t)__builtin_amdgcn_readlane((int32_t)q[c], sl);
-                        vsel = __builtin_amdgcn_readlane(v[c], sl);
+                    if (wv == 0) n_tie += is_tie(csel - qsel, csel, Z, ur24) ? 1 : 0;
+                    if (ch && lane == 0) ch[r] = s;
+                    if (lane == 0) {
+                        sm.seq_msg[seq_slot][0] = s;
+                        sm.seq_msg[seq_slot][1] = vsel;
                     }
                 }
-                if (wv == 0) n_tie += is_tie(csel - qsel, csel, Z, ur24) ? 1 : 0;
-                if (ch && lane == 0) ch[r] = s;
+                __syncthreads();
+                const int s = sm.seq_msg[seq_slot][0];
+                const int32_t vsel = sm.seq_msg[seq_slot][1];
+                seq_slot ^= 1;
                 if (s != r) apply_swap(r, s, (int64_t)vsel);
             }
         }
