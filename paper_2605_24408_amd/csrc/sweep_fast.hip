@@ -172,16 +172,18 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         for (int c = 0; c < CPL; ++c) {
             const int k = (lane + 64 * c) < NMAX ? lane + 64 * c : 0;
             src[c] = k == r ? s : k == s ? r : k;
-            v[c] = (EXACT || k < N) ? fp_at(r, src[c]) - fp_at(s, src[c]) : 0;
+            // gathered unconditionally (padding entries of pv are 0, so every
+            // address is valid), then zeroed: a conditional load becomes a
+            // branch that waits for its own result, one round trip per c
+            const int32_t dv = fp_at(r, src[c]) - fp_at(s, src[c]);
+            v[c] = (EXACT || k < N) ? dv : 0;
         }
         // 2 u_i of the wave's 16 rows, lane l for row 16 wv + l: one round of
         // loads beside the v gathers instead of one per row in the loop below
-        int32_t u2l = 0;
-        if (lane < 16) {
-            const int i = 16 * wv + lane;
-            const int32_t du = (EXACT || i < N) ? d_at(s, i) - d_at(r, i) : 0;
-            u2l = kDScale == 4 ? du / 2 : 2 * du;
-        }
+        // (d_at clamps its indices, so lanes 16..63 load valid entries too)
+        const int iu = 16 * wv + (lane & 15);
+        const int32_t du = d_at(s, iu) - d_at(r, iu);
+        const int32_t u2l = (lane < 16 && (EXACT || iu < N)) ? (kDScale == 4 ? du / 2 : 2 * du) : 0;
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
         // four rows at a time: every read of the group before its writes, so
         // one LDS round trip serves four rows
