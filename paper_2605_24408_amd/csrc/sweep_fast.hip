@@ -63,6 +63,7 @@ struct FastSmem {
     int32_t sel_row[2][NMAX];
     int32_t flag_row[2][NMAX];           // bit 0: the row swaps, bit 1: tie
     int32_t seq_msg[2][2];               // one update at a time: wave 0's choice, energy change
+    int32_t vswap[NMAX];                 // accepted swap: Fp[r][src] - Fp[s][src] by column
 };
 
 // Runs one replica's sweeps with the whole workgroup (NMAX/16 waves).
@@ -167,16 +168,23 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         // test per row or column (such tests made it a chain of branches
         // that waited for every row's LDS reads)
         int src[CPL];
-        int32_t v[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int k = (lane + 64 * c) < NMAX ? lane + 64 * c : 0;
             src[c] = k == r ? s : k == s ? r : k;
-            // gathered unconditionally (padding entries of pv are 0, so every
-            // address is valid), then zeroed: a conditional load becomes a
-            // branch that waits for its own result, one round trip per c
-            const int32_t dv = fp_at(r, src[c]) - fp_at(s, src[c]);
-            v[c] = (EXACT || k < N) ? dv : 0;
+        }
+        // v of every column, gathered once (waves 0..CPL-1, one column per
+        // lane) into LDS for all waves after the barrier below: every wave
+        // gathering all N columns itself had the scattered loads queue in the
+        // CU's load path.  Gathered unconditionally (padding entries of pv
+        // are 0, so every address is valid), then zeroed.
+        if (wv < CPL) {
+            const int k = 64 * wv + lane;
+            if (k < NMAX) {
+                const int sk = k == r ? s : k == s ? r : k;
+                const int32_t dv = fp_at(r, sk) - fp_at(s, sk);
+                sm.vswap[k] = (EXACT || k < N) ? dv : 0;
+            }
         }
         // 2 u_i of the wave's 16 rows, lane l for row 16 wv + l: one round of
         // loads beside the v gathers instead of one per row in the loop below
@@ -185,6 +193,9 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         const int32_t du = d_at(s, iu) - d_at(r, iu);
         const int32_t u2l = (lane < 16 && (EXACT || iu < N)) ? (kDScale == 4 ? du / 2 : 2 * du) : 0;
         __syncthreads();  // every read of H, Fp and the per-location arrays is done
+        int32_t v[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) v[c] = (lane + 64 * c) < NMAX ? sm.vswap[lane + 64 * c] : 0;
         // four rows at a time: every read of the group before its writes, so
         // one LDS round trip serves four rows
         for (int i0 = 16 * wv; i0 < 16 * wv + 16; i0 += 4) {
