@@ -279,153 +279,65 @@ __device__ __forceinline__ void table_replica(const ReplicaJob &a, TableSmem<NMA
         // Phase B.  Entries off rows/columns r, t: T += (a_s - a_l)(2c_l - 2c_s).
         // Columns r and t from Eq. 3, written with their transposes (rows r and
         // t) by the owner of row l; T[r][t] = T[t][r] = -dE (the way back).
-        if constexpr (NMAX < 96) {
-            if (rr < N && rr != r && rr != t) {
-                const int l = rr;
-                int32_t *row = T + l * PT + cq * K;
-                int4 xs[K / 4], as4[K / 4], cs4[K / 4];
+        if (rr < N && rr != r && rr != t) {
+            const int l = rr;
+            int32_t *row = T + l * PT + cq * K;
+            int4 xs[K / 4], as4[K / 4], cs4[K / 4];
 #pragma unroll
-                for (int j = 0; j < K / 4; ++j) {
-                    xs[j] = *reinterpret_cast<const int4 *>(row + 4 * j);
-                    as4[j] = *reinterpret_cast<const int4 *>(av + cq * K + 4 * j);
-                    cs4[j] = *reinterpret_cast<const int4 *>(cv2 + cq * K + 4 * j);
-                }
-                const int32_t al = av[l], cl2 = cv2[l];
-                // inputs of Eq. 3 for the entries (l, r) and (l, t)
-                const int32_t sr = (int32_t)((uint32_t)sm.hv[2][l] + (uint32_t)sm.hv[0][l]);
-                const int32_t st = (int32_t)((uint32_t)sm.hv[3][l] + (uint32_t)sm.hv[1][l]);
-                const int32_t hdl = hd[l], hdr = hd[r], hdt = hd[t];
-                const int32_t dlr = Ds[l * PD + r], dlt = Ds[l * PD + t];
-                const int32_t flr = sm.fnew[0][l], flt = sm.fnew[1][l];
-                int32_t dll = 0, drr = 0, dtt = 0, fll = 0, frr = 0, ftt = 0;
-                if (!ZD) {
-                    dll = Ds[l * PD + l];
-                    drr = Ds[r * PD + r];
-                    dtt = Ds[t * PD + t];
-                    fll = sm.fdn[l];
-                    frr = sm.fdn[r];
-                    ftt = sm.fdn[t];
-                }
-#pragma unroll
-                for (int j = 0; j < K / 4; ++j) {
-                    int4 x = xs[j];
-                    const int4 as = as4[j], cs = cs4[j];
-                    const int s0 = cq * K + 4 * j;
-                    const int32_t n0 = __mul24(as.x - al, cl2 - cs.x) + x.x;
-                    const int32_t n1 = __mul24(as.y - al, cl2 - cs.y) + x.y;
-                    const int32_t n2 = __mul24(as.z - al, cl2 - cs.z) + x.z;
-                    const int32_t n3 = __mul24(as.w - al, cl2 - cs.w) + x.w;
-                    x.x = (EXACT || s0 + 0 < N) ? n0 : x.x;
-                    x.y = (EXACT || s0 + 1 < N) ? n1 : x.y;
-                    x.z = (EXACT || s0 + 2 < N) ? n2 : x.z;
-                    x.w = (EXACT || s0 + 3 < N) ? n3 : x.w;
-                    *reinterpret_cast<int4 *>(row + 4 * j) = x;
-                }
-#pragma unroll
-                for (int wi = 0; wi < 2; ++wi) {
-                    const int w = wi == 0 ? r : t;
-                    if (w >= cq * K && w < cq * K + K) {
-                        const uint32_t h = 2u * ((uint32_t)(wi == 0 ? sr : st) - (uint32_t)hdl -
-                                                 (uint32_t)(wi == 0 ? hdr : hdt));
-                        const int32_t dlw = wi == 0 ? dlr : dlt, flw = wi == 0 ? flr : flt;
-                        uint32_t corr;
-                        if (ZD) {
-                            corr = 4u * (uint32_t)(dlw * flw);
-                        } else {
-                            const int32_t dd = dll + (wi == 0 ? drr : dtt) - 2 * dlw;
-                            const int32_t ff = fll + (wi == 0 ? frr : ftt) - 2 * flw;
-                            corr = (uint32_t)dd * (uint32_t)ff;
-                        }
-                        const int32_t v = (int32_t)(h + corr);
-                        T[l * PT + w] = v;
-                        T[w * PT + l] = v;
-                    }
-                }
+            for (int j = 0; j < K / 4; ++j) {
+                xs[j] = *reinterpret_cast<const int4 *>(row + 4 * j);
+                as4[j] = *reinterpret_cast<const int4 *>(av + cq * K + 4 * j);
+                cs4[j] = *reinterpret_cast<const int4 *>(cv2 + cq * K + 4 * j);
             }
-        } else {
-            if constexpr (NMAX >= 96) {
-                // Columns per lane: lane + 64 m, their a and 2c read once; the
-                // wave's 16 rows four at a time, every read of a group before its
-                // writes.  Rows r and t are left to the Eq. 3 step below.
-                int32_t acol[CPL], ccol[CPL];
-                bool live[CPL];
-#pragma unroll
-                for (int m = 0; m < CPL; ++m) {
-                    const int c = lane + 64 * m;
-                    live[m] = c < NMAX && (EXACT || c < N);
-                    acol[m] = c < NMAX ? av[c] : 0;
-                    ccol[m] = c < NMAX ? cv2[c] : 0;
-                }
-#pragma unroll
-                for (int i0 = 0; i0 < 16; i0 += 4) {
-                    int32_t xg[4][CPL], alg[4], clg[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int l = 16 * wv + i0 + q;
-                        alg[q] = av[l];
-                        clg[q] = cv2[l];
-#pragma unroll
-                        for (int m = 0; m < CPL; ++m)
-                            xg[q][m] = (lane + 64 * m) < NMAX ? T[l * PT + lane + 64 * m] : 0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int l = 16 * wv + i0 + q;
-                        if (l < N && l != r && l != t) {
-#pragma unroll
-                            for (int m = 0; m < CPL; ++m) {
-                                if ((lane + 64 * m) < NMAX) {
-                                    const int32_t n = __mul24(acol[m] - alg[q], clg[q] - ccol[m]) + xg[q][m];
-                                    T[l * PT + lane + 64 * m] = live[m] ? n : xg[q][m];
-                                }
-                            }
-                        }
-                    }
-                }
+            const int32_t al = av[l], cl2 = cv2[l];
+            // inputs of Eq. 3 for the entries (l, r) and (l, t)
+            const int32_t sr = (int32_t)((uint32_t)sm.hv[2][l] + (uint32_t)sm.hv[0][l]);
+            const int32_t st = (int32_t)((uint32_t)sm.hv[3][l] + (uint32_t)sm.hv[1][l]);
+            const int32_t hdl = hd[l], hdr = hd[r], hdt = hd[t];
+            const int32_t dlr = Ds[l * PD + r], dlt = Ds[l * PD + t];
+            const int32_t flr = sm.fnew[0][l], flt = sm.fnew[1][l];
+            int32_t dll = 0, drr = 0, dtt = 0, fll = 0, frr = 0, ftt = 0;
+            if (!ZD) {
+                dll = Ds[l * PD + l];
+                drr = Ds[r * PD + r];
+                dtt = Ds[t * PD + t];
+                fll = sm.fdn[l];
+                frr = sm.fdn[r];
+                ftt = sm.fdn[t];
             }
-            // Eq. 3 entries (l, r), (l, t) and their transposes: for N >= 96 by
-            // lanes 0..15 for the wave's rows, else by the lanes of each row's
-            // quarters that hold columns r and t, after the generic update of
-            // the row's own quarter
-            const int lrow = NMAX >= 96 ? 16 * wv + (lane & 15) : rr;
-            const bool eq_lane = NMAX >= 96 ? lane < 16 : true;
-            if (eq_lane && lrow < N && lrow != r && lrow != t) {
-                const int l = lrow;
-                const int32_t al = av[l], cl2 = cv2[l];
-                // inputs of Eq. 3 for the entries (l, r) and (l, t)
-                const int32_t sr = (int32_t)((uint32_t)sm.hv[2][l] + (uint32_t)sm.hv[0][l]);
-                const int32_t st = (int32_t)((uint32_t)sm.hv[3][l] + (uint32_t)sm.hv[1][l]);
-                const int32_t hdl = hd[l], hdr = hd[r], hdt = hd[t];
-                const int32_t dlr = Ds[l * PD + r], dlt = Ds[l * PD + t];
-                const int32_t flr = sm.fnew[0][l], flt = sm.fnew[1][l];
-                int32_t dll = 0, drr = 0, dtt = 0, fll = 0, frr = 0, ftt = 0;
-                if (!ZD) {
-                    dll = Ds[l * PD + l];
-                    drr = Ds[r * PD + r];
-                    dtt = Ds[t * PD + t];
-                    fll = sm.fdn[l];
-                    frr = sm.fdn[r];
-                    ftt = sm.fdn[t];
-                }
 #pragma unroll
-                for (int wi = 0; wi < 2; ++wi) {
-                    const int w = wi == 0 ? r : t;
-                    if (NMAX >= 96 || (w >= cq * K && w < cq * K + K)) {
-                        const uint32_t h = 2u * ((uint32_t)(wi == 0 ? sr : st) - (uint32_t)hdl -
-                                                 (uint32_t)(wi == 0 ? hdr : hdt));
-                        const int32_t dlw = wi == 0 ? dlr : dlt, flw = wi == 0 ? flr : flt;
-                        uint32_t corr;
-                        if (ZD) {
-                            corr = 4u * (uint32_t)(dlw * flw);
-                        } else {
-                            const int32_t dd = dll + (wi == 0 ? drr : dtt) - 2 * dlw;
-                            const int32_t ff = fll + (wi == 0 ? frr : ftt) - 2 * flw;
-                            corr = (uint32_t)dd * (uint32_t)ff;
-                        }
-                        const int32_t v = (int32_t)(h + corr);
-                        T[l * PT + w] = v;
-                        T[w * PT + l] = v;
+            for (int j = 0; j < K / 4; ++j) {
+                int4 x = xs[j];
+                const int4 as = as4[j], cs = cs4[j];
+                const int s0 = cq * K + 4 * j;
+                const int32_t n0 = __mul24(as.x - al, cl2 - cs.x) + x.x;
+                const int32_t n1 = __mul24(as.y - al, cl2 - cs.y) + x.y;
+                const int32_t n2 = __mul24(as.z - al, cl2 - cs.z) + x.z;
+                const int32_t n3 = __mul24(as.w - al, cl2 - cs.w) + x.w;
+                x.x = (EXACT || s0 + 0 < N) ? n0 : x.x;
+                x.y = (EXACT || s0 + 1 < N) ? n1 : x.y;
+                x.z = (EXACT || s0 + 2 < N) ? n2 : x.z;
+                x.w = (EXACT || s0 + 3 < N) ? n3 : x.w;
+                *reinterpret_cast<int4 *>(row + 4 * j) = x;
+            }
+#pragma unroll
+            for (int wi = 0; wi < 2; ++wi) {
+                const int w = wi == 0 ? r : t;
+                if (w >= cq * K && w < cq * K + K) {
+                    const uint32_t h = 2u * ((uint32_t)(wi == 0 ? sr : st) - (uint32_t)hdl -
+                                             (uint32_t)(wi == 0 ? hdr : hdt));
+                    const int32_t dlw = wi == 0 ? dlr : dlt, flw = wi == 0 ? flr : flt;
+                    uint32_t corr;
+                    if (ZD) {
+                        corr = 4u * (uint32_t)(dlw * flw);
+                    } else {
+                        const int32_t dd = dll + (wi == 0 ? drr : dtt) - 2 * dlw;
+                        const int32_t ff = fll + (wi == 0 ? frr : ftt) - 2 * flw;
+                        corr = (uint32_t)dd * (uint32_t)ff;
                     }
+                    const int32_t v = (int32_t)(h + corr);
+                    T[l * PT + w] = v;
+                    T[w * PT + l] = v;
                 }
             }
         }
