@@ -196,18 +196,20 @@ __device__ __forceinline__ void fast_replica(const ReplicaJob &a, FastSmem<NMAX,
         int32_t v[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) v[c] = (lane + 64 * c) < NMAX ? sm.vswap[lane + 64 * c] : 0;
-        // four rows at a time: every read of the group before its writes, so
-        // one LDS round trip serves four rows
-        for (int i0 = 16 * wv; i0 < 16 * wv + 16; i0 += 4) {
-            int32_t x[4][CPL];
+        // RG rows at a time: every read of the group before its writes, so
+        // one LDS round trip serves RG rows (two in the largest class, whose
+        // 128 registers per lane would otherwise spill)
+        constexpr int RG = CPL > 3 ? 2 : 4;
+        for (int i0 = 16 * wv; i0 < 16 * wv + 16; i0 += RG) {
+            int32_t x[RG][CPL];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < RG; ++q)
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
                     if (64 * c + 64 <= NMAX || lane + 64 * c < NMAX)
                         x[q][c] = Hs[(i0 + q) * P + src[c]];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < RG; ++q) {
                 const int32_t u2 = __builtin_amdgcn_readlane(u2l, i0 - 16 * wv + q);  // 2 u_i
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
