@@ -988,7 +988,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         }
         for (auto &g : groups) {
             int bpc = g.fast    ? pdit::fast_blocks_per_cu(g.nmax)
-                      : g.large ? pdit::large_blocks_per_cu()
+                      : g.large ? pdit::large_blocks_per_cu(g.lp)
                                 : pdit::plain_blocks_per_cu(g.h64);
             if (ctx->opts.blocks_per_cu > 0 && ctx->opts.blocks_per_cu < bpc) bpc = ctx->opts.blocks_per_cu;
             const int64_t want = (int64_t)bpc * std::max(ctx->num_cus, 1);

@@ -284,7 +284,7 @@ hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const
 struct BatchArgs;
 hipError_t launch_sweep_large_persistent(hipStream_t s, const LargePlan &pl, bool h64,
                                          const BatchArgs &b, int grid);
-int large_blocks_per_cu();
+int large_blocks_per_cu(const LargePlan &pl);
 // size class of the on-chip kernel that runs an instance (16, 32, 64, 96, 128,
 // 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic
 int fast_class(int N, const InstanceStats &st);

@@ -36,6 +36,7 @@
 // alternating registers keep the next block's loads in flight while one
 // block's products run.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "pdit_internal.h"
@@ -47,12 +48,11 @@ namespace {
 constexpr int kLargeThreads = 512;
 constexpr int kLargeWaves = kLargeThreads / 64;
 constexpr int kRowBlock = 16;  // rows per block of the two products
+constexpr int kLargeRows = 2;  // locations per pass over the paired copies
 
 struct LargeSmem {
     alignas(16) int32_t f[kLargeNMax];    // F[p(r)][p(.)], zero beyond N
     alignas(16) int32_t dq[kLargeNMax];   // D[r][q(.)] (row r of D by facility), zero beyond N
-    alignas(16) int16_t f16[kLargeNMax];  // the same as int16 (paired copies)
-    alignas(16) int16_t dq16[kLargeNMax];
     int32_t p[kLargeNMax];                // facility at each location
     int32_t d[kLargeNMax];                // D[r][.]
     int32_t ddiag[kLargeNMax];            // D[x][x]
@@ -60,7 +60,6 @@ struct LargeSmem {
     int64_t G[kLargeNMax];                // H[r][.] by facility
     int64_t hd[kLargeNMax];               // H[x][x]
     int64_t hcol[kLargeNMax];             // H[.][r]
-    int64_t part1[4][kLargeNMax], part2[4][kLargeNMax];  // quarter sums (paired copies)
     int32_t u[kLargeNMax], v[kLargeNMax];
     int64_t wmin[kLargeWaves];
     uint64_t wsum[kLargeWaves];
@@ -155,13 +154,17 @@ __device__ __forceinline__ void block_products(const uint32_t (&x1)[kRowBlock],
 
 // Paired copies, four adjacent columns per lane (one 16-byte load per word
 // row and matrix), one quarter of the word rows per wave pair: partial sums
-// of the quarter for columns c0..c0+3.  Word rows q0 .. q0+Q-1, blocks of 4.
-template <bool NARROW>
+// of the quarter for columns c0..c0+3 and each of the K rows of a pass
+// (a[i], b[i]: the int16 vectors of row i).  Every loaded word meets the K
+// rows' words, so one pass over the copies serves K rows.  Word rows
+// q0 .. q0+Q-1, blocks of 4.
+template <int K, bool NARROW>
 __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
                                                  __amdgpu_buffer_rsrc_t M2, uint32_t pitchB,
                                                  uint32_t voff0, int q0, int Q,
-                                                 const int16_t *a, const int16_t *b,
-                                                 int64_t (&acc1)[4], int64_t (&acc2)[4]) {
+                                                 const int16_t (*a)[kLargeNMax],
+                                                 const int16_t (*b)[kLargeNMax],
+                                                 int64_t (&acc1)[K][4], int64_t (&acc2)[K][4]) {
     constexpr int B = 4;  // word rows per block
     uint32_t voff[B];
 #pragma unroll
@@ -175,36 +178,41 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
         xa2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc1[c] = acc2[c] = 0;
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc1[i][c] = acc2[i][c] = 0;
     // products of one block (word rows w0..w0+3) added to s1, s2: int32 partial
     // sums of at most 16 products (two blocks) when NARROW, else each word's
     // pair of products (exact in int32) straight into the int64 totals
-    auto block = [&](const uint4 (&x1)[B], const uint4 (&x2)[B], int w0, int32_t (&s1)[4],
-                     int32_t (&s2)[4]) {
-        const uint4 aw = *(const uint4 *)(a + 2 * w0);
-        const uint4 bw = *(const uint4 *)(b + 2 * w0);
-        const uint32_t av[4] = {aw.x, aw.y, aw.z, aw.w};
-        const uint32_t bv[4] = {bw.x, bw.y, bw.z, bw.w};
+    auto block = [&](const uint4 (&x1)[B], const uint4 (&x2)[B], int w0, int32_t (&s1)[K][4],
+                     int32_t (&s2)[K][4]) {
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            if (NARROW) {
-                s1[0] = dot2(x1[u].x, av[u], s1[0]);
-                s1[1] = dot2(x1[u].y, av[u], s1[1]);
-                s1[2] = dot2(x1[u].z, av[u], s1[2]);
-                s1[3] = dot2(x1[u].w, av[u], s1[3]);
-                s2[0] = dot2(x2[u].x, bv[u], s2[0]);
-                s2[1] = dot2(x2[u].y, bv[u], s2[1]);
-                s2[2] = dot2(x2[u].z, bv[u], s2[2]);
-                s2[3] = dot2(x2[u].w, bv[u], s2[3]);
-            } else {
-                acc1[0] += dot2(x1[u].x, av[u], 0);
-                acc1[1] += dot2(x1[u].y, av[u], 0);
-                acc1[2] += dot2(x1[u].z, av[u], 0);
-                acc1[3] += dot2(x1[u].w, av[u], 0);
-                acc2[0] += dot2(x2[u].x, bv[u], 0);
-                acc2[1] += dot2(x2[u].y, bv[u], 0);
-                acc2[2] += dot2(x2[u].z, bv[u], 0);
-                acc2[3] += dot2(x2[u].w, bv[u], 0);
+        for (int i = 0; i < K; ++i) {
+            const uint4 aw = *(const uint4 *)(a[i] + 2 * w0);
+            const uint4 bw = *(const uint4 *)(b[i] + 2 * w0);
+            const uint32_t av[4] = {aw.x, aw.y, aw.z, aw.w};
+            const uint32_t bv[4] = {bw.x, bw.y, bw.z, bw.w};
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                if (NARROW) {
+                    s1[i][0] = dot2(x1[u].x, av[u], s1[i][0]);
+                    s1[i][1] = dot2(x1[u].y, av[u], s1[i][1]);
+                    s1[i][2] = dot2(x1[u].z, av[u], s1[i][2]);
+                    s1[i][3] = dot2(x1[u].w, av[u], s1[i][3]);
+                    s2[i][0] = dot2(x2[u].x, bv[u], s2[i][0]);
+                    s2[i][1] = dot2(x2[u].y, bv[u], s2[i][1]);
+                    s2[i][2] = dot2(x2[u].z, bv[u], s2[i][2]);
+                    s2[i][3] = dot2(x2[u].w, bv[u], s2[i][3]);
+                } else {
+                    acc1[i][0] += dot2(x1[u].x, av[u], 0);
+                    acc1[i][1] += dot2(x1[u].y, av[u], 0);
+                    acc1[i][2] += dot2(x1[u].z, av[u], 0);
+                    acc1[i][3] += dot2(x1[u].w, av[u], 0);
+                    acc2[i][0] += dot2(x2[u].x, bv[u], 0);
+                    acc2[i][1] += dot2(x2[u].y, bv[u], 0);
+                    acc2[i][2] += dot2(x2[u].z, bv[u], 0);
+                    acc2[i][3] += dot2(x2[u].w, bv[u], 0);
+                }
             }
         }
     };
@@ -215,7 +223,11 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
             xb1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M1, voff[u], soff, 0));
             xb2[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(M2, voff[u], soff, 0));
         }
-        int32_t s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
+        int32_t s1[K][4], s2[K][4];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s1[i][c] = s2[i][c] = 0;
         block(xa1, xa2, w, s1, s2);
         // the block after a quarter's last is the next quarter's first, or the pad block
         soff += block_bytes;
@@ -227,10 +239,12 @@ __device__ __forceinline__ void quarter_products(__amdgpu_buffer_rsrc_t M1,
         block(xb1, xb2, w + B, s1, s2);
         if (NARROW) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                acc1[c] += s1[c];
-                acc2[c] += s2[c];
-            }
+            for (int i = 0; i < K; ++i)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc1[i][c] += s1[i][c];
+                    acc2[i][c] += s2[i][c];
+                }
         }
     }
 }
@@ -267,8 +281,334 @@ __device__ __forceinline__ void column_products(__amdgpu_buffer_rsrc_t M1,
     gk = acc2;
 }
 
-// One replica's sweeps with the whole workgroup (512 threads).
-template <bool PAIRS, bool NARROW, typename HT>
+// LDS of the paired-copies path: the vectors and quarter sums of the
+// kLargeRows rows of a products pass, and the state shared by all rows.
+struct PairSmem {
+    alignas(16) int16_t f16[kLargeRows][kLargeNMax];   // F[p(x)][p(.)] (row x of the pass), zero beyond N
+    alignas(16) int16_t dq16[kLargeRows][kLargeNMax];  // D[x][q(.)] by facility, zero beyond N
+    int64_t part1[kLargeRows][4][kLargeNMax];  // quarter sums: H[.][x] by location
+    int64_t part2[kLargeRows][4][kLargeNMax];  // quarter sums: H[x][.] by facility
+    int32_t fr[kLargeRows][kLargeNMax];        // F[p(x)][p(k)] under the current p
+    int32_t dr[kLargeRows][kLargeNMax];        // D[x][k]
+    int32_t p[kLargeNMax];                     // facility at each location
+    int32_t ddiag[kLargeNMax];                 // D[x][x]
+    int32_t fdiag[kLargeNMax];                 // F[c][c]
+    int64_t hd[kLargeNMax];                    // H[x][x]
+    int32_t v[kLargeNMax];
+    int64_t wmin[kLargeWaves];
+    uint64_t wsum[kLargeWaves];
+    int32_t wsel[kLargeWaves];
+    int32_t wtie[kLargeWaves];     // tie flag of each wave's first hit
+    uint32_t u24s[kLargeNMax];     // the sweep's uniforms, one per location
+    int32_t xf[kLargeRows][2];     // prefetched next-pass flows of locations r and s (accepted exchange)
+};
+
+// One replica's sweeps on the paired copies, kLargeRows locations per pass
+// over the copies.  The pass takes the products of its rows under the p at
+// its start; an accepted exchange of r and s (p -> p tau, tau exchanging r
+// and s) moves the sums of a later row x of the pass by rank-1 terms:
+//   H'[k][x] = H[k][x] + (D[r][k] - D[s][k]) (F[p(x)][p(s)] - F[p(x)][p(r)])
+// for x != s, and for x = s (p'(s) = p(r)) the sums of row r itself:
+//   H'[k][s] = H[k][r] + (D[r][k] - D[s][k]) (F[p(r)][p(s)] - F[p(r)][p(r)]);
+// by facility, G'[c] = G[c] + (F[p(r)][c] - F[p(s)][c]) (D[x][s] - D[x][r])
+// in both cases.  A stay changes nothing.  So every row of a pass is drawn
+// exactly as if its products had been taken just before its update.
+template <bool NARROW, typename HT>
+__device__ void pair_replica(const ReplicaJob &j, PairSmem &sm) {
+    constexpr int K = kLargeRows;
+    const int N = j.N;
+    const int k = threadIdx.x, lane = k & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(k >> 6);  // wave-uniform, as the compiler must see
+    const bool own = k < N;
+    const int32_t *__restrict__ D = j.D;
+    const int32_t *__restrict__ F = j.F;
+    // word rows of a copy: row pairs, N4 = N rounded up to 4 words, N64 / 2 + 4 word rows
+    const int N4 = (N + 3) & ~3;
+    const int N64 = (N + 63) & ~63;
+    const uint32_t pitch = (uint32_t)N4 * 4;
+    const uint32_t copy_bytes = (uint32_t)(N64 / 2 + 4) * pitch;
+    const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(j.cD, copy_bytes);
+    const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(j.cF, copy_bytes);
+    int32_t *perm = j.perm;
+    int32_t *pbest = j.perm_best;
+    // diag H of the initial p; kSaveState writes the final one back (the
+    // library's H buffer, writable)
+    HT *H0 = (HT *)const_cast<void *>(j.H);
+    const float *beta_p = j.beta;
+    const int64_t beta_stride = j.beta_stride;
+    // the next pass's rows are loaded during the products, unless the pass
+    // wraps onto itself (N <= K)
+    const bool pre = N > K;
+
+    if (own) {
+        sm.p[k] = perm[k];
+        sm.ddiag[k] = D[(int64_t)k * N + k];
+        sm.fdiag[k] = F[(int64_t)k * N + k];
+        sm.hd[k] = (int64_t)H0[(int64_t)k * N + k];
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            sm.f16[i][k] = 0;  // the products' zero pad
+            sm.dq16[i][k] = 0;
+        }
+    }
+    int64_t E = *j.E;
+    int64_t E_best = *j.E_best;
+    int64_t n_acc = 0, n_tie = 0;
+    __syncthreads();
+    // location k's entries of the pass's rows: D[x][k] and F[p(x)][p(k)]
+    int32_t pd[K], pf[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        pd[i] = pf[i] = 0;
+        if (own && i < N) {
+            pd[i] = D[(int64_t)i * N + k];
+            pf[i] = F[(int64_t)sm.p[i] * N + sm.p[k]];
+        }
+    }
+
+    for (int64_t t = 0; t < j.T; ++t) {
+        const float beta = beta_p[t * beta_stride];
+        const int64_t dthr = zero_weight_distance64(beta);
+        const uint32_t g = (uint32_t)(j.sweep_offset + (uint64_t)t);
+        // the sweep's N uniforms at once, lane k for location k (ordered
+        // before their first use by the first barrier of the first pass)
+        if (own) sm.u24s[k] = uniform24(j.seed, (uint32_t)k, g, j.rep, j.inst);
+        for (int r0 = 0; r0 < N; r0 += K) {
+            const int kb = N - r0 < K ? N - r0 : K;  // rows of this pass
+            // ---- the pass's rows: by location, by facility, and as int16 ----
+            if (own) {
+                const int pk = sm.p[k];
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    int32_t dx = pd[i], fx = pf[i];
+                    if (!pre) {
+                        dx = fx = 0;
+                        if (i < kb) {
+                            dx = D[(int64_t)(r0 + i) * N + k];
+                            fx = F[(int64_t)sm.p[r0 + i] * N + pk];
+                        }
+                    }
+                    sm.dr[i][k] = dx;
+                    sm.fr[i][k] = fx;
+                    sm.f16[i][k] = (int16_t)fx;
+                    sm.dq16[i][pk] = (int16_t)dx;
+                }
+            }
+            __syncthreads();
+            // the next pass's rows under the current p; accepted exchanges of
+            // this pass permute them afterwards
+            const int nb = r0 + K < N ? r0 + K : 0;
+            if (pre) {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    pd[i] = pf[i] = 0;
+                    if (own && nb + i < N) {
+                        pd[i] = D[(int64_t)(nb + i) * N + k];
+                        pf[i] = F[(int64_t)sm.p[nb + i] * N + sm.p[k]];
+                    }
+                }
+            }
+            // ---- products: columns x of H and rows x of H by facility, x in the pass ----
+            {
+                // wave pair rq takes word rows [rq Q, (rq + 1) Q), wave ch of the
+                // pair columns 256 ch + 4 lane .. + 3
+                const int rq = wv >> 1, ch = wv & 1;
+                const int c0 = 256 * ch + 4 * lane;
+                const bool act = c0 < N4;
+                const int Q = N64 / 8;  // a multiple of 8 word rows: whole block pairs
+                if (256 * ch < N4) {
+                    int64_t p1[K][4], p2[K][4];
+                    quarter_products<K, NARROW>(Dc, Fc, pitch, act ? (uint32_t)c0 * 4 : 0u,
+                                                rq * Q, Q, sm.f16, sm.dq16, p1, p2);
+                    if (act) {
+#pragma unroll
+                        for (int i = 0; i < K; ++i)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                sm.part1[i][rq][c0 + c] = p1[i][c];
+                                sm.part2[i][rq][c0 + c] = p2[i][c];
+                            }
+                    }
+                }
+            }
+            __syncthreads();
+            // H[y][x] and H[x][y] (= G at facility p(y)) for row i of the pass:
+            // the sums of the four quarters, read where they lie
+            auto hcol_at = [&](int i, int y) -> int64_t {
+                return sm.part1[i][0][y] + sm.part1[i][1][y] + sm.part1[i][2][y] + sm.part1[i][3][y];
+            };
+            auto g_at = [&](int i, int c) -> int64_t {
+                return sm.part2[i][0][c] + sm.part2[i][1][c] + sm.part2[i][2][c] + sm.part2[i][3][c];
+            };
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                if (i >= kb) break;
+                const int r = r0 + i;
+                const int pr = sm.p[r];
+                // ---- energy change of candidate k (Eq. 3) ----
+                int64_t v = INT64_MAX;
+                if (own) {
+                    const int64_t hkr = hcol_at(i, k);
+                    const int64_t hrk = g_at(i, sm.p[k]);
+                    const int64_t h = hrk + hkr - sm.hd[r] - sm.hd[k];
+                    const int64_t dd = (int64_t)sm.ddiag[r] + sm.ddiag[k] - 2 * (int64_t)sm.dr[i][k];
+                    const int64_t ff =
+                        (int64_t)sm.fdiag[pr] + sm.fdiag[sm.p[k]] - 2 * (int64_t)sm.fr[i][k];
+                    v = k == r ? 0 : 2 * h + dd * ff;
+                }
+                // ---- block minimum ----
+                const int64_t m0 = wave_min_i64(v);
+                if (lane == 0) sm.wmin[wv] = m0;
+                __syncthreads();
+                int64_t m = sm.wmin[0];
+#pragma unroll
+                for (int w = 1; w < kLargeWaves; ++w) m = min(m, sm.wmin[w]);
+                // ---- integer weights, running sums, the draw (Eq. 5) ----
+                uint32_t qk = 0;
+                if (own) {
+                    const int64_t dk = v - m;
+                    qk = dk < dthr ? gibbs_weight(beta, (float)dk) : 0u;
+                }
+                const uint64_t cw = (uint64_t)wave_scan_u32(qk);  // at most 64 x 2^25 = 2^31
+                if (lane == 63) sm.wsum[wv] = cw;
+                __syncthreads();
+                uint64_t off = 0, Z = 0;
+#pragma unroll
+                for (int w = 0; w < kLargeWaves; ++w) {
+                    const uint64_t x = sm.wsum[w];
+                    off += w < wv ? x : 0;
+                    Z += x;
+                }
+                const uint64_t C = off + cw;
+                const uint32_t u24 = sm.u24s[r];
+                const uint64_t thr = ((uint64_t)u24 * Z) >> 24;
+                // the first candidate whose running sum exceeds the threshold: each
+                // wave publishes its first hit and that candidate's tie flag
+                const uint64_t hit = __ballot(own && C > thr);
+                const int first = hit ? __ffsll((unsigned long long)hit) - 1 : -1;  // wave-uniform
+                if (first < 0) {
+                    if (lane == 0) sm.wsel[wv] = 0x7fffffff;
+                } else if (lane == first) {
+                    sm.wsel[wv] = 64 * wv + first;
+                    sm.wtie[wv] = is_tie(C - qk, C, Z, u24) ? 1 : 0;
+                }
+                __syncthreads();
+                int s = 0x7fffffff;
+#pragma unroll
+                for (int w = 0; w < kLargeWaves; ++w) s = min(s, sm.wsel[w]);
+                int tie = 0;
+                if (s >= N)
+                    s = r;  // unreachable: location N-1 holds C = Z > thr
+                else
+                    tie = sm.wtie[s >> 6];
+                n_tie += tie;
+                if (j.choices && k == 0) j.choices[t * N + r] = s;
+                if (s == r) continue;
+                // ---- accepted exchange of r and s: E, diag H, p, the later rows ----
+                ++n_acc;
+                const int ps = sm.p[s];
+                int32_t uk = 0, wk = 0;
+                if (own) {
+                    uk = D[(int64_t)s * N + k] - sm.dr[i][k];             // D[k][s] - D[k][r]
+                    sm.v[k] = sm.fr[i][k] - F[(int64_t)ps * N + sm.p[k]];  // Fp[r][k] - Fp[s][k]
+                    wk = F[(int64_t)pr * N + k] - F[(int64_t)ps * N + k];  // F[p(r)][c] - F[p(s)][c], c = k
+                    if (pre) {
+#pragma unroll
+                        for (int i2 = 0; i2 < K; ++i2) {
+                            if (k == r) sm.xf[i2][0] = pf[i2];
+                            if (k == s) sm.xf[i2][1] = pf[i2];
+                        }
+                    }
+                }
+                // later rows' factors, read before anything moves
+                int32_t frr[K], frs[K], ddl[K];
+#pragma unroll
+                for (int i2 = 0; i2 < K; ++i2) {
+                    frr[i2] = frs[i2] = ddl[i2] = 0;
+                    if (i2 > i && i2 < kb) {
+                        frr[i2] = sm.fr[i2][r];
+                        frs[i2] = sm.fr[i2][s];
+                        ddl[i2] = sm.dr[i2][s] - sm.dr[i2][r];
+                    }
+                }
+                const int32_t dfr = sm.fr[i][s] - sm.fr[i][r];
+                const int64_t h_rs = g_at(i, ps), h_sr = hcol_at(i, s);
+                const int64_t dE = 2 * (h_rs + h_sr - sm.hd[r] - sm.hd[s]) +
+                                   ((int64_t)sm.ddiag[r] + sm.ddiag[s] - 2 * (int64_t)sm.dr[i][s]) *
+                                       ((int64_t)sm.fdiag[pr] + sm.fdiag[ps] - 2 * (int64_t)sm.fr[i][s]);
+                __syncthreads();
+                E += dE;
+                const int tk = k == r ? s : k == s ? r : k;
+                if (own) {
+                    if (k == r)
+                        sm.hd[k] = h_rs + (int64_t)uk * sm.v[s];
+                    else if (k == s)
+                        sm.hd[k] = h_sr + (int64_t)uk * sm.v[r];
+                    else
+                        sm.hd[k] += (int64_t)uk * sm.v[k];
+                    // the later rows of the pass
+#pragma unroll
+                    for (int i2 = 0; i2 < K; ++i2) {
+                        if (i2 <= i || i2 >= kb) continue;
+                        if (r0 + i2 == s) {
+                            sm.part1[i2][0][k] = hcol_at(i, k) - (int64_t)uk * dfr;
+                            sm.part1[i2][1][k] = 0;
+                            sm.part1[i2][2][k] = 0;
+                            sm.part1[i2][3][k] = 0;
+                            sm.fr[i2][k] = sm.fr[i][tk];
+                        } else {
+                            sm.part1[i2][0][k] -= (int64_t)uk * (frs[i2] - frr[i2]);
+                            if (k == r) sm.fr[i2][k] = frs[i2];
+                            if (k == s) sm.fr[i2][k] = frr[i2];
+                        }
+                        sm.part2[i2][0][k] += (int64_t)wk * ddl[i2];
+                    }
+                }
+                if (k == 0) {
+                    sm.p[r] = ps;
+                    sm.p[s] = pr;
+                }
+                // the next pass's rows after the exchange: D as prefetched;
+                // F[p'(y)][p'(k)] = F[p(y)][p(tau k)], the prefetched row at
+                // tau k, or, when y = s (p'(s) = p(r)), row r's at tau k
+                if (pre && own) {
+#pragma unroll
+                    for (int i2 = 0; i2 < K; ++i2) {
+                        if (nb + i2 >= N) continue;
+                        if (nb + i2 == s)
+                            pf[i2] = sm.fr[i][tk];
+                        else if (k == r)
+                            pf[i2] = sm.xf[i2][1];
+                        else if (k == s)
+                            pf[i2] = sm.xf[i2][0];
+                    }
+                }
+                __syncthreads();
+                if (E < E_best) {
+                    E_best = E;
+                    if (own) pbest[k] = sm.p[k];
+                }
+            }
+        }
+        if (j.E_trace && k == 0) j.E_trace[t] = E;
+    }
+    if (own) {
+        perm[k] = sm.p[k];
+        if (j.flags & kSaveState) H0[(int64_t)k * N + k] = (HT)sm.hd[k];
+    }
+    if (k == 0) {
+        *j.E = E;
+        *j.E_best = E_best;
+        const bool acc = (j.flags & kAccumCounters) != 0;
+        j.counters[0] = (acc ? j.counters[0] : 0) + (int64_t)N * j.T;
+        j.counters[1] = (acc ? j.counters[1] : 0) + n_acc;
+        j.counters[2] = (acc ? j.counters[2] : 0) + n_tie;
+    }
+}
+
+// One replica's sweeps on the int32 copies, one location at a time.
+template <bool NARROW, typename HT>
 __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
     const int N = j.N;
     const int N32 = (N + 2 * kRowBlock - 1) / (2 * kRowBlock) * (2 * kRowBlock);
@@ -277,13 +617,9 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
     const bool own = k < N;
     const int32_t *__restrict__ D = j.D;
     const int32_t *__restrict__ F = j.F;
-    // word rows of a copy: row pairs (int16, N4 = N rounded up to 4 words,
-    // N64 / 2 + 4 word rows) or rows (int32, N words, N32 + 16 rows)
-    const int N4 = (N + 3) & ~3;
-    const int N64 = (N + 63) & ~63;
-    const uint32_t pitch = (uint32_t)(PAIRS ? N4 : N) * 4;
-    const uint32_t copy_bytes = PAIRS ? (uint32_t)(N64 / 2 + 4) * pitch
-                                      : (uint32_t)(N32 + kRowBlock) * pitch;
+    // rows of a copy: N words, N32 + 16 rows
+    const uint32_t pitch = (uint32_t)N * 4;
+    const uint32_t copy_bytes = (uint32_t)(N32 + kRowBlock) * pitch;
     const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(j.cD, copy_bytes);
     const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(j.cF, copy_bytes);
     // lanes past N read column 0 (results unused): every offset stays inside
@@ -308,8 +644,6 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
     } else {
         sm.f[k] = 0;  // the products' zero pad
         sm.dq[k] = 0;
-        sm.f16[k] = 0;
-        sm.dq16[k] = 0;
     }
     int64_t E = *j.E;
     int64_t E_best = *j.E_best;
@@ -337,12 +671,7 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                 const int pk = sm.p[k];
                 sm.d[k] = drk;
                 sm.f[k] = fk;
-                if (PAIRS) {
-                    sm.dq16[pk] = (int16_t)drk;
-                    sm.f16[k] = (int16_t)fk;
-                } else {
-                    sm.dq[pk] = drk;
-                }
+                sm.dq[pk] = drk;
             }
             __syncthreads();
             // prefetch of the next location's rows under the current p; an
@@ -355,26 +684,7 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
             }
             // ---- column r of H (location k) and row r of H by facility (facility k) ----
             int64_t hkr = 0, gk = 0;
-            if constexpr (PAIRS) {
-                // wave pair rq takes word rows [rq Q, (rq + 1) Q), wave ch of the
-                // pair columns 256 ch + 4 lane .. + 3
-                const int rq = wv >> 1, ch = wv & 1;
-                const int c0 = 256 * ch + 4 * lane;
-                const bool act = c0 < N4;
-                const int Q = N64 / 8;  // a multiple of 8 word rows: whole block pairs
-                if (256 * ch < N4) {
-                    int64_t p1[4], p2[4];
-                    quarter_products<NARROW>(Dc, Fc, pitch, act ? (uint32_t)c0 * 4 : 0u, rq * Q,
-                                             Q, sm.f16, sm.dq16, p1, p2);
-                    if (act) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            sm.part1[rq][c0 + c] = p1[c];
-                            sm.part2[rq][c0 + c] = p2[c];
-                        }
-                    }
-                }
-            } else if (wv * 64 < N) {  // waves with no location skip the products
+            if (wv * 64 < N) {  // waves with no location skip the products
                 column_products<NARROW>(Dc, Fc, voff, kRowBlock * pitch, sm.f, sm.dq, N32, hkr,
                                         gk);
                 if (own) {
@@ -383,24 +693,12 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
                 }
             }
             __syncthreads();
-            // H[x][r] and H[r][x] (= G at facility p(x)): on the paired path the
-            // sums of the four quarters, read where they lie
-            auto hcol_at = [&](int x) -> int64_t {
-                if constexpr (PAIRS)
-                    return sm.part1[0][x] + sm.part1[1][x] + sm.part1[2][x] + sm.part1[3][x];
-                else
-                    return sm.hcol[x];
-            };
-            auto g_at = [&](int c) -> int64_t {
-                if constexpr (PAIRS)
-                    return sm.part2[0][c] + sm.part2[1][c] + sm.part2[2][c] + sm.part2[3][c];
-                else
-                    return sm.G[c];
-            };
+            // H[x][r] and H[r][x] (= G at facility p(x))
+            auto hcol_at = [&](int x) -> int64_t { return sm.hcol[x]; };
+            auto g_at = [&](int c) -> int64_t { return sm.G[c]; };
             // ---- energy change of candidate k (Eq. 3) ----
             int64_t v = INT64_MAX;
             if (own) {
-                if constexpr (PAIRS) hkr = hcol_at(k);
                 const int64_t hrk = g_at(sm.p[k]);
                 const int64_t h = hrk + hkr - sm.hd[r] - sm.hd[k];
                 const int64_t dd = (int64_t)sm.ddiag[r] + sm.ddiag[k] - 2 * (int64_t)sm.d[k];
@@ -519,7 +817,6 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
 
 template <bool PAIRS, bool NARROW, typename HT>
 __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a, LargeCopies c) {
-    __shared__ LargeSmem sm;
     const int64_t rep = blockIdx.x;
     ReplicaJob j;
     j.N = a.N;
@@ -545,14 +842,21 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     j.zero_diag = a.zero_diag;
     j.tstate = nullptr;
     j.flags = a.flags;
-    large_replica<PAIRS, NARROW, HT>(j, sm);
+    if constexpr (PAIRS) {
+        __shared__ PairSmem sp;
+        pair_replica<NARROW, HT>(j, sp);
+    } else {
+        __shared__ LargeSmem sm;
+        large_replica<NARROW, HT>(j, sm);
+    }
 }
 
 // Persistent: each workgroup takes (instance, replica) items of one group
 // (same copy layout and H width) from a queue until it is exhausted.
 template <bool PAIRS, bool NARROW, typename HT>
 __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArgs b) {
-    __shared__ LargeSmem sm;
+    using Smem = typename std::conditional<PAIRS, PairSmem, LargeSmem>::type;
+    __shared__ Smem sm;
     __shared__ int item_sh;
     for (;;) {
         if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1);
@@ -560,7 +864,10 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArg
         const int item = __builtin_amdgcn_readfirstlane(item_sh);  // wave-uniform
         __syncthreads();
         if (item >= b.n_items) break;
-        large_replica<PAIRS, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
+        if constexpr (PAIRS)
+            pair_replica<NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
+        else
+            large_replica<NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
         __syncthreads();
     }
 }
@@ -651,10 +958,13 @@ hipError_t launch_sweep_large_persistent(hipStream_t s, const LargePlan &pl, boo
     return hipGetLastError();
 }
 
-int large_blocks_per_cu() {
+int large_blocks_per_cu(const LargePlan &pl) {
     int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, sweep_large_persistent<true, true, int64_t>, kLargeThreads, 0);
+    const hipError_t e =
+        pl.elem == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &n, sweep_large_persistent<true, true, int64_t>, kLargeThreads, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &n, sweep_large_persistent<false, true, int64_t>, kLargeThreads, 0);
     (void)hipGetLastError();
     return (e == hipSuccess && n > 0) ? n : 1;
 }
