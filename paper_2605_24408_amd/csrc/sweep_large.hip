@@ -27,7 +27,11 @@
 //   `v_dot2_i32_i16` (exact in int32 per word); the two waves of pair q take
 //   word rows [q N64/8, (q+1) N64/8) for 256 columns each, and the four
 //   quarter sums meet in LDS.  Wide 16-byte loads matter: one-column 4-byte
-//   loads ran at half the per-CU rate from L2.
+//   loads ran at half the per-CU rate from L2.  One pass over the copies
+//   serves several consecutive locations (three, two in the persistent
+//   kernel): their products are taken under the p at the start of the pass
+//   and an accepted exchange corrects the later rows' sums by rank-1 terms
+//   (pair_replica), which costs O(N) where a new pass would cost 2 N^2.
 // * otherwise: int32 rows (N32 = N rounded up to 32, plus 16 zero rows), one
 //   column per lane, 24-bit (|D|, |F| < 2^23) or int64 products.
 // Narrow instances (16 max|D| max|F| < 2^31) sum each block in int32 before
@@ -48,7 +52,9 @@ namespace {
 constexpr int kLargeThreads = 512;
 constexpr int kLargeWaves = kLargeThreads / 64;
 constexpr int kRowBlock = 16;  // rows per block of the two products
-constexpr int kLargeRows = 2;  // locations per pass over the paired copies
+// locations per pass over the paired copies: three where one replica runs per
+// workgroup, two in the persistent kernel (three would spill registers there)
+constexpr int kRowsSingle = 3, kRowsBatch = 2;
 
 struct LargeSmem {
     alignas(16) int32_t f[kLargeNMax];    // F[p(r)][p(.)], zero beyond N
@@ -282,14 +288,15 @@ __device__ __forceinline__ void column_products(__amdgpu_buffer_rsrc_t M1,
 }
 
 // LDS of the paired-copies path: the vectors and quarter sums of the
-// kLargeRows rows of a products pass, and the state shared by all rows.
+// K rows of a products pass, and the state shared by all rows.
+template <int K>
 struct PairSmem {
-    alignas(16) int16_t f16[kLargeRows][kLargeNMax];   // F[p(x)][p(.)] (row x of the pass), zero beyond N
-    alignas(16) int16_t dq16[kLargeRows][kLargeNMax];  // D[x][q(.)] by facility, zero beyond N
-    int64_t part1[kLargeRows][4][kLargeNMax];  // quarter sums: H[.][x] by location
-    int64_t part2[kLargeRows][4][kLargeNMax];  // quarter sums: H[x][.] by facility
-    int32_t fr[kLargeRows][kLargeNMax];        // F[p(x)][p(k)] under the current p
-    int32_t dr[kLargeRows][kLargeNMax];        // D[x][k]
+    alignas(16) int16_t f16[K][kLargeNMax];   // F[p(x)][p(.)] (row x of the pass), zero beyond N
+    alignas(16) int16_t dq16[K][kLargeNMax];  // D[x][q(.)] by facility, zero beyond N
+    int64_t part1[K][4][kLargeNMax];  // quarter sums: H[.][x] by location
+    int64_t part2[K][4][kLargeNMax];  // quarter sums: H[x][.] by facility
+    int32_t fr[K][kLargeNMax];        // F[p(x)][p(k)] under the current p
+    int32_t dr[K][kLargeNMax];        // D[x][k]
     int32_t p[kLargeNMax];                     // facility at each location
     int32_t ddiag[kLargeNMax];                 // D[x][x]
     int32_t fdiag[kLargeNMax];                 // F[c][c]
@@ -300,10 +307,10 @@ struct PairSmem {
     int32_t wsel[kLargeWaves];
     int32_t wtie[kLargeWaves];     // tie flag of each wave's first hit
     uint32_t u24s[kLargeNMax];     // the sweep's uniforms, one per location
-    int32_t xf[kLargeRows][2];     // prefetched next-pass flows of locations r and s (accepted exchange)
+    int32_t xf[K][2];     // prefetched next-pass flows of locations r and s (accepted exchange)
 };
 
-// One replica's sweeps on the paired copies, kLargeRows locations per pass
+// One replica's sweeps on the paired copies, K locations per pass
 // over the copies.  The pass takes the products of its rows under the p at
 // its start; an accepted exchange of r and s (p -> p tau, tau exchanging r
 // and s) moves the sums of a later row x of the pass by rank-1 terms:
@@ -313,9 +320,8 @@ struct PairSmem {
 // by facility, G'[c] = G[c] + (F[p(r)][c] - F[p(s)][c]) (D[x][s] - D[x][r])
 // in both cases.  A stay changes nothing.  So every row of a pass is drawn
 // exactly as if its products had been taken just before its update.
-template <bool NARROW, typename HT>
-__device__ void pair_replica(const ReplicaJob &j, PairSmem &sm) {
-    constexpr int K = kLargeRows;
+template <int K, bool NARROW, typename HT>
+__device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
     const int N = j.N;
     const int k = threadIdx.x, lane = k & 63;
     const int wv = __builtin_amdgcn_readfirstlane(k >> 6);  // wave-uniform, as the compiler must see
@@ -843,8 +849,8 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     j.tstate = nullptr;
     j.flags = a.flags;
     if constexpr (PAIRS) {
-        __shared__ PairSmem sp;
-        pair_replica<NARROW, HT>(j, sp);
+        __shared__ PairSmem<kRowsSingle> sp;
+        pair_replica<kRowsSingle, NARROW, HT>(j, sp);
     } else {
         __shared__ LargeSmem sm;
         large_replica<NARROW, HT>(j, sm);
@@ -855,7 +861,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
 // (same copy layout and H width) from a queue until it is exhausted.
 template <bool PAIRS, bool NARROW, typename HT>
 __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArgs b) {
-    using Smem = typename std::conditional<PAIRS, PairSmem, LargeSmem>::type;
+    using Smem = typename std::conditional<PAIRS, PairSmem<kRowsBatch>, LargeSmem>::type;
     __shared__ Smem sm;
     __shared__ int item_sh;
     for (;;) {
@@ -865,7 +871,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArg
         __syncthreads();
         if (item >= b.n_items) break;
         if constexpr (PAIRS)
-            pair_replica<NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
+            pair_replica<kRowsBatch, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
         else
             large_replica<NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
         __syncthreads();
