@@ -126,6 +126,15 @@ def test_large_trajectories(P, N, R, T, dmax, fmax, zd, hot):
     assert got["plan"]["sweep"] == "large"
     check(got, ref, max_bad=1)
     assert got["counters"][:, 1].sum() > 0
+    if hot and N >= 7:
+        # a single launch serves three locations per pass over the copies: the
+        # corrections after an accepted exchange whose partner is a later
+        # location of the same pass, or one of the next pass, are exercised
+        r = np.arange(N)[None, None, :]
+        s = ref.choices
+        r0 = (r // 3) * 3
+        assert ((s > r) & (s < r0 + 3)).sum() > 0
+        assert ((s >= r0 + 3) & (s < r0 + 6)).sum() > 0
 
 
 def test_auto_picks_large(P):
