@@ -95,7 +95,10 @@ extern "C" {
                                D f with f = F[p(r)][p(.)], row r as F^T applied to row r of D
                                ordered by facility (2 N^2 multiply-adds on rows of D and F that
                                all replicas share through the cache), diag H is kept on chip and
-                               moved in O(N) per accepted exchange.  512 threads per replica.
+                               moved in O(N) per accepted exchange.  With values <= 32767 one
+                               pass over D and F serves three consecutive locations (two in
+                               batched runs); an accepted exchange corrects the later ones'
+                               sums in O(N).  512 threads per replica.
                                Same dynamics and results as the other kernels.  AUTO picks it
                                wherever the fast kernel does not fit: single runs, beta-range
                                selection, periodic tempering (diag H is the state saved
