@@ -268,7 +268,8 @@ hipError_t launch_sweep_plain(hipStream_t s, const SweepArgs &a, bool h64);
 constexpr int kLargeNMax = 512;
 struct LargePlan {
     bool narrow = false;  // int32 partial sums of 24-bit products
-    int elem = 4;         // bytes per element of the copies (2: int16)
+    int elem = 4;         // bytes per element of the copies (2: int16, 1: int8 planes)
+    bool planes = false;  // int8 hi/lo planes for the MFMA products (|D|, |F| <= 16383)
     int rows = 0;         // rows of each copy (N rounded up to 16, plus 16 zero rows)
     size_t bytes = 0;     // both copies
 };
@@ -276,7 +277,8 @@ struct LargeCopies {
     const void *D = nullptr;
     const void *F = nullptr;
 };
-LargePlan large_plan(int N, const InstanceStats &st);
+// allow_planes: single launches (the persistent batch kernel reads int16 or int32 copies)
+LargePlan large_plan(int N, const InstanceStats &st, bool allow_planes = true);
 hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                              const LargePlan &pl, void *buf, LargeCopies *out);
 hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const LargePlan &pl,

@@ -55,6 +55,7 @@ constexpr int kRowBlock = 16;  // rows per block of the two products
 // locations per pass over the paired copies: three where one replica runs per
 // workgroup, two in the persistent kernel (three would spill registers there)
 constexpr int kRowsSingle = 3, kRowsBatch = 2;
+constexpr int kRowsPlanes = 6;  // locations per pass on the int8 plane copies (MFMA products)
 
 struct LargeSmem {
     alignas(16) int32_t f[kLargeNMax];    // F[p(r)][p(.)], zero beyond N
@@ -287,14 +288,116 @@ __device__ __forceinline__ void column_products(__amdgpu_buffer_rsrc_t M1,
     gk = acc2;
 }
 
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+// row pitch of the int8 plane vectors in LDS: 16 bytes beyond a multiple of
+// 512, so the 16 rows one B operand reads start in different banks
+constexpr int kPlanePitch = kLargeNMax + 16;
+
+// MFMA products of one pass over the int8 plane copies: for the K rows of the
+// pass, S1[k][i] = sum_j D[k][j] f_i[j] and S2[c][i] = sum_b F[c][b] dq_i[b]
+// (D and F symmetric, so rows stand for columns).  Every operand is split as
+// x = 128 hi + lo with hi signed and lo in [0, 127] (|x| <= 16383), so a
+// product is four `v_mfma_i32_16x16x64_i8`: hi hi, the two cross terms in one
+// accumulator, lo lo, each exact in int32 for N <= 512 (at most 512 terms of
+// 2^14).  A operand: rows 16 t .. 16 t + 15 of a copy; B operand: the pass's
+// rows as columns, zero beyond K.  Wave w takes tiles w, w + 8, ...; the next
+// chunk's copy rows are loaded while the current chunk's products run.
+template <int K>
+__device__ __forceinline__ void plane_products(__amdgpu_buffer_rsrc_t Dp,
+                                               __amdgpu_buffer_rsrc_t Fp, uint32_t plane,
+                                               int N, int N16, int N64, int wv, int lane,
+                                               const int8_t (*fh)[kPlanePitch],
+                                               const int8_t (*fl)[kPlanePitch],
+                                               const int8_t (*dh)[kPlanePitch],
+                                               const int8_t (*dl)[kPlanePitch],
+                                               int64_t (*out1)[1][kLargeNMax],
+                                               int64_t (*out2)[1][kLargeNMax]) {
+    static_assert(K <= 16, "one 16-column B tile");
+    const int n = lane & 15;          // row of the A tile and column of B
+    const int kq = (lane >> 4) * 16;  // this lane's 16 bytes of the 64-wide chunk
+    const int NT = N16 / 16, NC = N64 / 64;
+    const int steps = ((NT - wv + kLargeWaves - 1) / kLargeWaves) * NC;  // (tile, chunk) pairs
+    if (wv >= NT) return;
+    auto load = [&](int q, mf_v4i (&a)[4]) {
+        // the copies hold each operand in lane order: 1 KB per tile and chunk
+        const int t = wv + kLargeWaves * (q / NC), c = q % NC;
+        const uint32_t off = (uint32_t)(((t * NC + c) * 64 + lane) * 16);
+        a[0] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Dp, off, 0, 0));
+        a[1] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Dp, off, plane, 0));
+        a[2] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Fp, off, 0, 0));
+        a[3] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Fp, off, plane, 0));
+    };
+    const mf_v4i z = {0, 0, 0, 0};
+    mf_v4i h1 = z, x1 = z, l1 = z, h2 = z, x2 = z, l2 = z;
+    // products of step q from the operands in a
+    auto step = [&](int q, const mf_v4i (&a)[4]) {
+        const int c = q % NC;
+        mf_v4i bfh = z, bfl = z, bdh = z, bdl = z;
+        if (n < K) {
+            bfh = *(const mf_v4i *)&fh[n][64 * c + kq];
+            bfl = *(const mf_v4i *)&fl[n][64 * c + kq];
+            bdh = *(const mf_v4i *)&dh[n][64 * c + kq];
+            bdl = *(const mf_v4i *)&dl[n][64 * c + kq];
+        }
+        h1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0], bfh, h1, 0, 0, 0);
+        h2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[2], bdh, h2, 0, 0, 0);
+        x1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0], bfl, x1, 0, 0, 0);
+        x2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[2], bdl, x2, 0, 0, 0);
+        l1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1], bfl, l1, 0, 0, 0);
+        l2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[3], bdl, l2, 0, 0, 0);
+        x1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[1], bfh, x1, 0, 0, 0);
+        x2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[3], bdh, x2, 0, 0, 0);
+        if (c == NC - 1) {
+            // element e: row 16 t + 4 (lane / 16) + e of the tile, column n
+            const int t = wv + kLargeWaves * (q / NC);
+            if (n < K) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * t + 4 * (lane >> 4) + e;
+                    if (k < N) {
+                        out1[n][0][k] = 16384 * (int64_t)h1[e] + 128 * (int64_t)x1[e] + l1[e];
+                        out2[n][0][k] = 16384 * (int64_t)h2[e] + 128 * (int64_t)x2[e] + l2[e];
+                    }
+                }
+            }
+            h1 = x1 = l1 = h2 = x2 = l2 = z;
+        }
+    };
+    // a ring of four operand sets, three steps in flight, no register copies
+    // (a copy would wait for its loads); a step past the wave's last reloads
+    // its first: always in range
+    auto wrap = [&](int q) { return q < steps ? q : 0; };
+    mf_v4i a0[4], a1[4], a2[4], a3[4];
+    load(0, a0);
+    load(wrap(1), a1);
+    load(wrap(2), a2);
+    for (int q = 0; q < steps; q += 4) {
+        load(wrap(q + 3), a3);
+        step(q, a0);
+        load(wrap(q + 4), a0);
+        if (q + 1 < steps) step(q + 1, a1);
+        load(wrap(q + 5), a1);
+        if (q + 2 < steps) step(q + 2, a2);
+        load(wrap(q + 6), a2);
+        if (q + 3 < steps) step(q + 3, a3);
+    }
+}
+
 // LDS of the paired-copies path: the vectors and quarter sums of the
 // K rows of a products pass, and the state shared by all rows.
-template <int K>
+template <int K, bool MF>
 struct PairSmem {
-    alignas(16) int16_t f16[K][kLargeNMax];   // F[p(x)][p(.)] (row x of the pass), zero beyond N
-    alignas(16) int16_t dq16[K][kLargeNMax];  // D[x][q(.)] by facility, zero beyond N
-    int64_t part1[K][4][kLargeNMax];  // quarter sums: H[.][x] by location
-    int64_t part2[K][4][kLargeNMax];  // quarter sums: H[x][.] by facility
+    static constexpr int K16 = MF ? 1 : K;  // rows of the int16 vectors (dot2 products)
+    static constexpr int K8 = MF ? K : 1;   // rows of the int8 planes (MFMA products)
+    static constexpr int QN = MF ? 1 : 4;   // partial sums per row and column
+    alignas(16) int16_t f16[K16][kLargeNMax];   // F[p(x)][p(.)] (row x of the pass), zero beyond N
+    alignas(16) int16_t dq16[K16][kLargeNMax];  // D[x][q(.)] by facility, zero beyond N
+    alignas(16) int8_t fh[K8][kPlanePitch];     // the same two as int8 planes, hi and lo
+    alignas(16) int8_t fl[K8][kPlanePitch];
+    alignas(16) int8_t dh[K8][kPlanePitch];
+    alignas(16) int8_t dl[K8][kPlanePitch];
+    int64_t part1[K][QN][kLargeNMax];  // partial sums: H[.][x] by location
+    int64_t part2[K][QN][kLargeNMax];  // partial sums: H[x][.] by facility
     int32_t fr[K][kLargeNMax];        // F[p(x)][p(k)] under the current p
     int32_t dr[K][kLargeNMax];        // D[x][k]
     int32_t p[kLargeNMax];                     // facility at each location
@@ -320,8 +423,9 @@ struct PairSmem {
 // by facility, G'[c] = G[c] + (F[p(r)][c] - F[p(s)][c]) (D[x][s] - D[x][r])
 // in both cases.  A stay changes nothing.  So every row of a pass is drawn
 // exactly as if its products had been taken just before its update.
-template <int K, bool NARROW, typename HT>
-__device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
+template <int K, bool MF, bool NARROW, typename HT>
+__device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
+    constexpr int QN = PairSmem<K, MF>::QN;
     const int N = j.N;
     const int k = threadIdx.x, lane = k & 63;
     const int wv = __builtin_amdgcn_readfirstlane(k >> 6);  // wave-uniform, as the compiler must see
@@ -332,7 +436,10 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
     const int N4 = (N + 3) & ~3;
     const int N64 = (N + 63) & ~63;
     const uint32_t pitch = (uint32_t)N4 * 4;
-    const uint32_t copy_bytes = (uint32_t)(N64 / 2 + 4) * pitch;
+    // plane copies: N16 x N64 bytes per plane, hi then lo
+    const int N16 = (N + 15) & ~15;
+    const uint32_t plane = (uint32_t)N16 * (uint32_t)N64;
+    const uint32_t copy_bytes = MF ? 2 * plane : (uint32_t)(N64 / 2 + 4) * pitch;
     const __amdgpu_buffer_rsrc_t Dc = copy_rsrc(j.cD, copy_bytes);
     const __amdgpu_buffer_rsrc_t Fc = copy_rsrc(j.cF, copy_bytes);
     int32_t *perm = j.perm;
@@ -352,10 +459,13 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
         sm.fdiag[k] = F[(int64_t)k * N + k];
         sm.hd[k] = (int64_t)H0[(int64_t)k * N + k];
     } else {
+        // the products' zero pad
+        if constexpr (MF) {
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            sm.f16[i][k] = 0;  // the products' zero pad
-            sm.dq16[i][k] = 0;
+            for (int i = 0; i < K; ++i) sm.fh[i][k] = sm.fl[i][k] = sm.dh[i][k] = sm.dl[i][k] = 0;
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i) sm.f16[i][k] = sm.dq16[i][k] = 0;
         }
     }
     int64_t E = *j.E;
@@ -397,8 +507,15 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
                     }
                     sm.dr[i][k] = dx;
                     sm.fr[i][k] = fx;
-                    sm.f16[i][k] = (int16_t)fx;
-                    sm.dq16[i][pk] = (int16_t)dx;
+                    if constexpr (MF) {
+                        sm.fh[i][k] = (int8_t)(fx >> 7);
+                        sm.fl[i][k] = (int8_t)(fx & 127);
+                        sm.dh[i][pk] = (int8_t)(dx >> 7);
+                        sm.dl[i][pk] = (int8_t)(dx & 127);
+                    } else {
+                        sm.f16[i][k] = (int16_t)fx;
+                        sm.dq16[i][pk] = (int16_t)dx;
+                    }
                 }
             }
             __syncthreads();
@@ -416,7 +533,10 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
                 }
             }
             // ---- products: columns x of H and rows x of H by facility, x in the pass ----
-            {
+            if constexpr (MF) {
+                plane_products<K>(Dc, Fc, plane, N, N16, N64, wv, lane, sm.fh, sm.fl, sm.dh, sm.dl,
+                                  sm.part1, sm.part2);
+            } else {
                 // wave pair rq takes word rows [rq Q, (rq + 1) Q), wave ch of the
                 // pair columns 256 ch + 4 lane .. + 3
                 const int rq = wv >> 1, ch = wv & 1;
@@ -440,12 +560,18 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
             }
             __syncthreads();
             // H[y][x] and H[x][y] (= G at facility p(y)) for row i of the pass:
-            // the sums of the four quarters, read where they lie
+            // the sums of the partial sums, read where they lie
             auto hcol_at = [&](int i, int y) -> int64_t {
-                return sm.part1[i][0][y] + sm.part1[i][1][y] + sm.part1[i][2][y] + sm.part1[i][3][y];
+                int64_t a = sm.part1[i][0][y];
+#pragma unroll
+                for (int q = 1; q < QN; ++q) a += sm.part1[i][q][y];
+                return a;
             };
             auto g_at = [&](int i, int c) -> int64_t {
-                return sm.part2[i][0][c] + sm.part2[i][1][c] + sm.part2[i][2][c] + sm.part2[i][3][c];
+                int64_t a = sm.part2[i][0][c];
+#pragma unroll
+                for (int q = 1; q < QN; ++q) a += sm.part2[i][q][c];
+                return a;
             };
 #pragma unroll
             for (int i = 0; i < K; ++i) {
@@ -559,9 +685,8 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K> &sm) {
                         if (i2 <= i || i2 >= kb) continue;
                         if (r0 + i2 == s) {
                             sm.part1[i2][0][k] = hcol_at(i, k) - (int64_t)uk * dfr;
-                            sm.part1[i2][1][k] = 0;
-                            sm.part1[i2][2][k] = 0;
-                            sm.part1[i2][3][k] = 0;
+#pragma unroll
+                            for (int q = 1; q < QN; ++q) sm.part1[i2][q][k] = 0;
                             sm.fr[i2][k] = sm.fr[i][tk];
                         } else {
                             sm.part1[i2][0][k] -= (int64_t)uk * (frs[i2] - frr[i2]);
@@ -821,7 +946,7 @@ __device__ void large_replica(const ReplicaJob &j, LargeSmem &sm) {
     }
 }
 
-template <bool PAIRS, bool NARROW, typename HT>
+template <bool PAIRS, bool NARROW, typename HT, bool MF>
 __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a, LargeCopies c) {
     const int64_t rep = blockIdx.x;
     ReplicaJob j;
@@ -848,9 +973,12 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
     j.zero_diag = a.zero_diag;
     j.tstate = nullptr;
     j.flags = a.flags;
-    if constexpr (PAIRS) {
-        __shared__ PairSmem<kRowsSingle> sp;
-        pair_replica<kRowsSingle, NARROW, HT>(j, sp);
+    if constexpr (MF) {
+        __shared__ PairSmem<kRowsPlanes, true> sp;
+        pair_replica<kRowsPlanes, true, NARROW, HT>(j, sp);
+    } else if constexpr (PAIRS) {
+        __shared__ PairSmem<kRowsSingle, false> sp;
+        pair_replica<kRowsSingle, false, NARROW, HT>(j, sp);
     } else {
         __shared__ LargeSmem sm;
         large_replica<NARROW, HT>(j, sm);
@@ -861,7 +989,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
 // (same copy layout and H width) from a queue until it is exhausted.
 template <bool PAIRS, bool NARROW, typename HT>
 __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArgs b) {
-    using Smem = typename std::conditional<PAIRS, PairSmem<kRowsBatch>, LargeSmem>::type;
+    using Smem = typename std::conditional<PAIRS, PairSmem<kRowsBatch, false>, LargeSmem>::type;
     __shared__ Smem sm;
     __shared__ int item_sh;
     for (;;) {
@@ -871,7 +999,7 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArg
         __syncthreads();
         if (item >= b.n_items) break;
         if constexpr (PAIRS)
-            pair_replica<kRowsBatch, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
+            pair_replica<kRowsBatch, false, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
         else
             large_replica<NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
         __syncthreads();
@@ -909,15 +1037,44 @@ __global__ void large_copy16_kernel(int N, int wrows, const int32_t *D, const in
     }
 }
 
+// int8 plane copies for the MFMA products: for M = D then F, plane hi then
+// plane lo of M[k][j] (x = 128 hi + lo, lo in [0, 127]) for k < N16 (N
+// rounded up to 16), j < N64 (rounded up to 64), zero outside N x N; the
+// host checks |D|, |F| <= 16383.  Stored in MFMA operand order: block
+// (t, c) of 1 KB holds rows 16 t .. 16 t + 15 and columns 64 c .. 64 c + 63,
+// lane l's 16 bytes (row 16 t + l % 16, columns 64 c + 16 (l / 16) ..) at
+// 16 l, so one operand load per wave is one contiguous 1 KB read.
+__global__ void large_copy8_kernel(int N, int N16, int N64, const int32_t *D, const int32_t *F,
+                                   int8_t *out) {
+    const int64_t plane = (int64_t)N16 * N64;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 2 * plane;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = e < plane ? e : e - plane;
+        const int64_t blk = w >> 10, l = (w >> 4) & 63, byte = w & 15;
+        const int64_t NC = N64 / 64, t = blk / NC, c = blk - t * NC;
+        const int64_t k = 16 * t + (l & 15), jj = 64 * c + 16 * (l >> 4) + byte;
+        const int32_t *M = e < plane ? D : F;
+        const int32_t x = (k < N && jj < N) ? M[k * N + jj] : 0;
+        int8_t *base = out + (e < plane ? 0 : 2 * plane);
+        base[w] = (int8_t)(x >> 7);
+        base[plane + w] = (int8_t)(x & 127);
+    }
+}
+
 }  // namespace
 
-LargePlan large_plan(int N, const InstanceStats &st) {
+LargePlan large_plan(int N, const InstanceStats &st, bool allow_planes) {
     LargePlan pl;
     const int32_t mx = st.max_abs_d > st.max_abs_f ? st.max_abs_d : st.max_abs_f;
     pl.narrow = mx < (1 << 23) &&
                 (int64_t)kRowBlock * st.max_abs_d * st.max_abs_f < ((int64_t)1 << 31);
     pl.elem = mx <= 32767 ? 2 : 4;
-    if (pl.elem == 2) {
+    pl.planes = allow_planes && mx <= 16383;
+    if (pl.planes) {
+        pl.elem = 1;
+        pl.rows = (N + 15) & ~15;  // rows of a plane, N64 bytes each
+        pl.bytes = 4 * (size_t)pl.rows * ((N + 63) & ~63);
+    } else if (pl.elem == 2) {
         pl.rows = ((N + 63) & ~63) / 2 + 4;  // word rows
         pl.bytes = 2 * (size_t)pl.rows * ((N + 3) & ~3) * 4;
     } else {
@@ -934,7 +1091,9 @@ hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32
     out->F = (char *)buf + one;
     const int64_t total = (int64_t)pl.rows * ((N + 3) & ~3);
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 1024);
-    if (pl.elem == 2)
+    if (pl.planes)
+        large_copy8_kernel<<<grid, 256, 0, s>>>(N, pl.rows, (N + 63) & ~63, D, F, (int8_t *)buf);
+    else if (pl.elem == 2)
         large_copy16_kernel<<<grid, 256, 0, s>>>(N, pl.rows, D, F, (uint32_t *)out->D,
                                                  (uint32_t *)out->F);
     else
@@ -981,11 +1140,16 @@ hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const
 #define PDIT_LARGE(PAIRS, NARROW)                                                               \
     do {                                                                                    \
         if (h64)                                                                            \
-            sweep_large_kernel<PAIRS, NARROW, int64_t><<<a.R, kLargeThreads, 0, s>>>(a, c);     \
+            sweep_large_kernel<PAIRS, NARROW, int64_t, false><<<a.R, kLargeThreads, 0, s>>>(a, c); \
         else                                                                                \
-            sweep_large_kernel<PAIRS, NARROW, int32_t><<<a.R, kLargeThreads, 0, s>>>(a, c);     \
+            sweep_large_kernel<PAIRS, NARROW, int32_t, false><<<a.R, kLargeThreads, 0, s>>>(a, c); \
     } while (0)
-    if (pl.elem == 2 && pl.narrow)
+    if (pl.planes) {
+        if (h64)
+            sweep_large_kernel<true, true, int64_t, true><<<a.R, kLargeThreads, 0, s>>>(a, c);
+        else
+            sweep_large_kernel<true, true, int32_t, true><<<a.R, kLargeThreads, 0, s>>>(a, c);
+    } else if (pl.elem == 2 && pl.narrow)
         PDIT_LARGE(true, true);
     else if (pl.elem == 2)
         PDIT_LARGE(true, false);

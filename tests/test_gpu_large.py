@@ -95,8 +95,10 @@ def instance(rng, N, dmax, fmax, zero_diag=True):
 
 
 # (N, R, T, max|D|, max|F|, zero diagonal, hot): the values pick the variant --
-# int16 copies when both maxima are <= 32767, int32 partial sums when
-# 16 max|D| max|F| < 2^31, int64 H when the bound on |H| exceeds 2^31 - 1
+# int8 plane copies and MFMA products (six locations per pass) when both
+# maxima are <= 16383, int16 copies (three per pass) up to 32767, int32
+# partial sums when 16 max|D| max|F| < 2^31, int64 H when the bound on |H|
+# exceeds 2^31 - 1
 CASES = [
     (2, 6, 40, 9, 9, True, True),            # int16, narrow, H int32; the smallest instance
     (7, 8, 30, 60, 60, False, True),         # nonzero diagonals
@@ -105,11 +107,14 @@ CASES = [
     (65, 4, 8, 99, 99, False, True),         # two waves, one lane of the second
     (130, 3, 4, 10_000, 10_000, True, True),   # int16, narrow, H int64
     (150, 3, 4, 30_000, 30_000, True, True),   # int16, int64 products
+    (40, 4, 10, 20_000, 20_000, True, True),   # int16 pairs, N = 1 mod 3
+    (259, 2, 2, 20_000, 20_000, False, True),  # int16 pairs, ragged, nonzero diagonals
     (100, 3, 5, 200_000, 600, True, True),     # int32 copies, narrow
     (90, 3, 5, 2_000_000, 5_000, False, True),  # int32 copies, int64 products, H int64
     (257, 2, 2, 10_000, 10_000, True, True),   # ragged: 5 waves, one lane of the last
     (300, 2, 2, 99, 99, True, True),
     (512, 2, 2, 10_000, 10_000, True, True),   # the largest instance
+    (97, 3, 6, 16_383, 16_383, True, True),    # planes at their largest values
 ]
 
 
@@ -126,15 +131,37 @@ def test_large_trajectories(P, N, R, T, dmax, fmax, zd, hot):
     assert got["plan"]["sweep"] == "large"
     check(got, ref, max_bad=1)
     assert got["counters"][:, 1].sum() > 0
-    if hot and N >= 7:
-        # a single launch serves three locations per pass over the copies: the
-        # corrections after an accepted exchange whose partner is a later
-        # location of the same pass, or one of the next pass, are exercised
+    # a single launch serves w locations per pass over the copies (6 on the
+    # int8 planes, 3 on the int16 pairs): the corrections after an accepted
+    # exchange whose partner is a later location of the same pass, or one of
+    # the next pass, are exercised
+    vmax = max(dmax, fmax)
+    w = 6 if vmax <= 16_383 else 3 if vmax <= 32_767 else 0
+    if hot and w and N >= 2 * w:
         r = np.arange(N)[None, None, :]
         s = ref.choices
-        r0 = (r // 3) * 3
-        assert ((s > r) & (s < r0 + 3)).sum() > 0
-        assert ((s >= r0 + 3) & (s < r0 + 6)).sum() > 0
+        r0 = (r // w) * w
+        assert ((s > r) & (s < r0 + w)).sum() > 0
+        assert ((s >= r0 + w) & (s < r0 + 2 * w)).sum() > 0
+
+
+@pytest.mark.parametrize("N,vmax", [(70, 5_000), (71, 16_383), (45, 30_000)])
+def test_large_signed_values(P, N, vmax):
+    """Negative entries (D and F symmetric, uniform in [-vmax, vmax]): the
+    int8 planes split x = 128 hi + lo with hi negative, the int16 pairs
+    carry the sign in each half."""
+    rng = np.random.default_rng(900 + N)
+    D = W.sym_uniform(rng, N, -vmax, vmax).astype(np.int32)
+    F = W.sym_uniform(rng, N, -vmax, vmax).astype(np.int32)
+    perms = W.random_perms(rng, 3, N)
+    s = W.energy_scale(D, F)
+    beta = W.beta_geometric(0.05 / s, 50.0 / s, 6)
+    say(f"large signed N={N} max={vmax}")
+    ref = oracle.run(D, F, perms, beta, 13, record_choices=True, record_trace=True)
+    got = run_large(P, D, F, perms, beta, 13)
+    assert got["plan"]["sweep"] == "large"
+    check(got, ref, max_bad=1)
+    assert got["counters"][:, 1].sum() > 0
 
 
 def test_auto_picks_large(P):
