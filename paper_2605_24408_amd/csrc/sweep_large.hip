@@ -20,6 +20,10 @@
 //
 // One workgroup of 512 threads (8 waves) per replica; thread k owns location
 // k in the draw.  The products read library copies of D and F:
+// * |D|, |F| <= 16383 (single launches): two int8 planes per matrix,
+//   x = 128 hi + lo, in MFMA operand order; a pass over six locations is
+//   the product of the copies with the locations' permuted rows, four
+//   `v_mfma_i32_16x16x64_i8` per tile and chunk (plane_products).
 // * |D|, |F| <= 32767: int16 row pairs, one 32-bit word = rows 2i and 2i+1
 //   of a column, rows padded with zeros to N64 (N rounded up to 64) and
 //   columns to N4 (rounded up to 4), plus 4 zero word rows.  Each lane takes
