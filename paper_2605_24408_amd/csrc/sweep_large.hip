@@ -322,10 +322,21 @@ __device__ __forceinline__ void plane_products(__amdgpu_buffer_rsrc_t Dp,
     const int NT = N16 / 16, NC = N64 / 64;
     const int steps = ((NT - wv + kLargeWaves - 1) / kLargeWaves) * NC;  // (tile, chunk) pairs
     if (wv >= NT) return;
-    auto load = [&](int q, mf_v4i (&a)[4]) {
+    // (tile, chunk) of the next load and of the next step, advanced by
+    // counting (a division by the runtime NC per step costs more than the step)
+    int lt = wv, lc = 0, st = wv, sc = 0;
+    auto load = [&](mf_v4i (&a)[4]) {
+        // past the wave's last step the ring reloads its first: always in range
+        if (lt >= NT) {
+            lt = wv;
+            lc = 0;
+        }
         // the copies hold each operand in lane order: 1 KB per tile and chunk
-        const int t = wv + kLargeWaves * (q / NC), c = q % NC;
-        const uint32_t off = (uint32_t)(((t * NC + c) * 64 + lane) * 16);
+        const uint32_t off = (uint32_t)(((lt * NC + lc) * 64 + lane) * 16);
+        if (++lc == NC) {
+            lc = 0;
+            lt += kLargeWaves;
+        }
         a[0] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Dp, off, 0, 0));
         a[1] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Dp, off, plane, 0));
         a[2] = __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(Fp, off, 0, 0));
@@ -333,9 +344,9 @@ __device__ __forceinline__ void plane_products(__amdgpu_buffer_rsrc_t Dp,
     };
     const mf_v4i z = {0, 0, 0, 0};
     mf_v4i h1 = z, x1 = z, l1 = z, h2 = z, x2 = z, l2 = z;
-    // products of step q from the operands in a
-    auto step = [&](int q, const mf_v4i (&a)[4]) {
-        const int c = q % NC;
+    // products of the next step from the operands in a
+    auto step = [&](const mf_v4i (&a)[4]) {
+        const int c = sc;
         mf_v4i bfh = z, bfl = z, bdh = z, bdl = z;
         if (n < K) {
             bfh = *(const mf_v4i *)&fh[n][64 * c + kq];
@@ -353,7 +364,7 @@ __device__ __forceinline__ void plane_products(__amdgpu_buffer_rsrc_t Dp,
         x2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[3], bdh, x2, 0, 0, 0);
         if (c == NC - 1) {
             // element e: row 16 t + 4 (lane / 16) + e of the tile, column n
-            const int t = wv + kLargeWaves * (q / NC);
+            const int t = st;
             if (n < K) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -366,24 +377,26 @@ __device__ __forceinline__ void plane_products(__amdgpu_buffer_rsrc_t Dp,
             }
             h1 = x1 = l1 = h2 = x2 = l2 = z;
         }
+        if (++sc == NC) {
+            sc = 0;
+            st += kLargeWaves;
+        }
     };
     // a ring of four operand sets, three steps in flight, no register copies
-    // (a copy would wait for its loads); a step past the wave's last reloads
-    // its first: always in range
-    auto wrap = [&](int q) { return q < steps ? q : 0; };
+    // (a copy would wait for its loads)
     mf_v4i a0[4], a1[4], a2[4], a3[4];
-    load(0, a0);
-    load(wrap(1), a1);
-    load(wrap(2), a2);
+    load(a0);
+    load(a1);
+    load(a2);
     for (int q = 0; q < steps; q += 4) {
-        load(wrap(q + 3), a3);
-        step(q, a0);
-        load(wrap(q + 4), a0);
-        if (q + 1 < steps) step(q + 1, a1);
-        load(wrap(q + 5), a1);
-        if (q + 2 < steps) step(q + 2, a2);
-        load(wrap(q + 6), a2);
-        if (q + 3 < steps) step(q + 3, a3);
+        load(a3);
+        step(a0);
+        load(a0);
+        if (q + 1 < steps) step(a1);
+        load(a1);
+        if (q + 2 < steps) step(a2);
+        load(a2);
+        if (q + 3 < steps) step(a3);
     }
 }
 
