@@ -885,7 +885,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         pl.hoff = (int64_t)hbytes;
         hbytes += (size_t)inst[k].R * inst[k].N * inst[k].N * elem;
         if (pl.large) {
-            pl.lp = pdit::large_plan(inst[k].N, q, false);
+            pl.lp = pdit::large_plan(inst[k].N, q);
             cbytes = (cbytes + 255) & ~(size_t)255;
             pl.coff = cbytes;
             cbytes += pl.lp.bytes;

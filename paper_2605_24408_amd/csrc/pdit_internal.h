@@ -277,8 +277,7 @@ struct LargeCopies {
     const void *D = nullptr;
     const void *F = nullptr;
 };
-// allow_planes: single launches (the persistent batch kernel reads int16 or int32 copies)
-LargePlan large_plan(int N, const InstanceStats &st, bool allow_planes = true);
+LargePlan large_plan(int N, const InstanceStats &st);
 hipError_t launch_large_copy(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                              const LargePlan &pl, void *buf, LargeCopies *out);
 hipError_t launch_sweep_large(hipStream_t s, const SweepArgs &a, bool h64, const LargePlan &pl,

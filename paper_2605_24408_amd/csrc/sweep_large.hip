@@ -20,10 +20,11 @@
 //
 // One workgroup of 512 threads (8 waves) per replica; thread k owns location
 // k in the draw.  The products read library copies of D and F:
-// * |D|, |F| <= 16383 (single launches): two int8 planes per matrix,
+// * |D|, |F| <= 16383: two int8 planes per matrix,
 //   x = 128 hi + lo, in MFMA operand order; a pass over six locations is
 //   the product of the copies with the locations' permuted rows, four
-//   `v_mfma_i32_16x16x64_i8` per tile and chunk (plane_products).
+//   `v_mfma_i32_16x16x64_i8` per tile and chunk (plane_products), in
+//   single launches and in the persistent batch kernel.
 // * |D|, |F| <= 32767: int16 row pairs, one 32-bit word = rows 2i and 2i+1
 //   of a column, rows padded with zeros to N64 (N rounded up to 64) and
 //   columns to N4 (rounded up to 4), plus 4 zero word rows.  Each lane takes
@@ -56,7 +57,7 @@ namespace {
 constexpr int kLargeThreads = 512;
 constexpr int kLargeWaves = kLargeThreads / 64;
 constexpr int kRowBlock = 16;  // rows per block of the two products
-// locations per pass over the paired copies: three where one replica runs per
+// locations per pass over the int16 pairs: three where one replica runs per
 // workgroup, two in the persistent kernel (three would spill registers there)
 constexpr int kRowsSingle = 3, kRowsBatch = 2;
 constexpr int kRowsPlanes = 6;  // locations per pass on the int8 plane copies (MFMA products)
@@ -1004,9 +1005,11 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_kernel(SweepArgs a,
 
 // Persistent: each workgroup takes (instance, replica) items of one group
 // (same copy layout and H width) from a queue until it is exhausted.
-template <bool PAIRS, bool NARROW, typename HT>
+template <bool PAIRS, bool NARROW, typename HT, bool MF>
 __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArgs b) {
-    using Smem = typename std::conditional<PAIRS, PairSmem<kRowsBatch, false>, LargeSmem>::type;
+    using Smem = typename std::conditional<
+        MF, PairSmem<kRowsPlanes, true>,
+        typename std::conditional<PAIRS, PairSmem<kRowsBatch, false>, LargeSmem>::type>::type;
     __shared__ Smem sm;
     __shared__ int item_sh;
     for (;;) {
@@ -1015,7 +1018,9 @@ __global__ void __launch_bounds__(kLargeThreads) sweep_large_persistent(BatchArg
         const int item = __builtin_amdgcn_readfirstlane(item_sh);  // wave-uniform
         __syncthreads();
         if (item >= b.n_items) break;
-        if constexpr (PAIRS)
+        if constexpr (MF)
+            pair_replica<kRowsPlanes, true, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
+        else if constexpr (PAIRS)
             pair_replica<kRowsBatch, false, NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
         else
             large_replica<NARROW, HT>(batch_job(b, item, sizeof(HT)), sm);
@@ -1080,13 +1085,13 @@ __global__ void large_copy8_kernel(int N, int N16, int N64, const int32_t *D, co
 
 }  // namespace
 
-LargePlan large_plan(int N, const InstanceStats &st, bool allow_planes) {
+LargePlan large_plan(int N, const InstanceStats &st) {
     LargePlan pl;
     const int32_t mx = st.max_abs_d > st.max_abs_f ? st.max_abs_d : st.max_abs_f;
     pl.narrow = mx < (1 << 23) &&
                 (int64_t)kRowBlock * st.max_abs_d * st.max_abs_f < ((int64_t)1 << 31);
     pl.elem = mx <= 32767 ? 2 : 4;
-    pl.planes = allow_planes && mx <= 16383;
+    pl.planes = mx <= 16383;
     if (pl.planes) {
         pl.elem = 1;
         pl.rows = (N + 15) & ~15;  // rows of a plane, N64 bytes each
@@ -1124,11 +1129,16 @@ hipError_t launch_sweep_large_persistent(hipStream_t s, const LargePlan &pl, boo
 #define PDIT_LARGE_P(PAIRS, NARROW)                                                          \
     do {                                                                                     \
         if (h64)                                                                             \
-            sweep_large_persistent<PAIRS, NARROW, int64_t><<<grid, kLargeThreads, 0, s>>>(b); \
+            sweep_large_persistent<PAIRS, NARROW, int64_t, false><<<grid, kLargeThreads, 0, s>>>(b); \
         else                                                                                 \
-            sweep_large_persistent<PAIRS, NARROW, int32_t><<<grid, kLargeThreads, 0, s>>>(b); \
+            sweep_large_persistent<PAIRS, NARROW, int32_t, false><<<grid, kLargeThreads, 0, s>>>(b); \
     } while (0)
-    if (pl.elem == 2 && pl.narrow)
+    if (pl.planes) {
+        if (h64)
+            sweep_large_persistent<true, true, int64_t, true><<<grid, kLargeThreads, 0, s>>>(b);
+        else
+            sweep_large_persistent<true, true, int32_t, true><<<grid, kLargeThreads, 0, s>>>(b);
+    } else if (pl.elem == 2 && pl.narrow)
         PDIT_LARGE_P(true, true);
     else if (pl.elem == 2)
         PDIT_LARGE_P(true, false);
@@ -1143,10 +1153,12 @@ hipError_t launch_sweep_large_persistent(hipStream_t s, const LargePlan &pl, boo
 int large_blocks_per_cu(const LargePlan &pl) {
     int n = 0;
     const hipError_t e =
-        pl.elem == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &n, sweep_large_persistent<true, true, int64_t>, kLargeThreads, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &n, sweep_large_persistent<false, true, int64_t>, kLargeThreads, 0);
+        pl.planes      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, sweep_large_persistent<true, true, int64_t, true>, kLargeThreads, 0)
+        : pl.elem == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, sweep_large_persistent<true, true, int64_t, false>, kLargeThreads, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, sweep_large_persistent<false, true, int64_t, false>, kLargeThreads, 0);
     (void)hipGetLastError();
     return (e == hipSuccess && n > 0) ? n : 1;
 }
