@@ -21,7 +21,7 @@
 // One workgroup of 512 threads (8 waves) per replica; thread k owns location
 // k in the draw.  The products read library copies of D and F:
 // * |D|, |F| <= 16383: two int8 planes per matrix,
-//   x = 128 hi + lo, in MFMA operand order; a pass over six locations is
+//   x = 128 hi + lo, in MFMA operand order; a pass over eight locations is
 //   the product of the copies with the locations' permuted rows, four
 //   `v_mfma_i32_16x16x64_i8` per tile and chunk (plane_products), in
 //   single launches and in the persistent batch kernel.
@@ -60,7 +60,7 @@ constexpr int kRowBlock = 16;  // rows per block of the two products
 // locations per pass over the int16 pairs: three where one replica runs per
 // workgroup, two in the persistent kernel (three would spill registers there)
 constexpr int kRowsSingle = 3, kRowsBatch = 2;
-constexpr int kRowsPlanes = 6;  // locations per pass on the int8 plane copies (MFMA products)
+constexpr int kRowsPlanes = 8;  // locations per pass on the int8 plane copies (MFMA products)
 
 struct LargeSmem {
     alignas(16) int32_t f[kLargeNMax];    // F[p(r)][p(.)], zero beyond N
@@ -467,9 +467,12 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
     HT *H0 = (HT *)const_cast<void *>(j.H);
     const float *beta_p = j.beta;
     const int64_t beta_stride = j.beta_stride;
-    // the next pass's rows are loaded during the products, unless the pass
-    // wraps onto itself (N <= K)
-    const bool pre = N > K;
+    // the next pass's rows are loaded during the products (int16 pairs),
+    // unless the pass wraps onto itself (N <= K); on the planes, with eight
+    // locations per pass, each pass loads its rows at its start: permuting
+    // eight prefetched rows after every accepted exchange cost more than
+    // that load
+    const bool pre = !MF && N > K;
 
     if (own) {
         sm.p[k] = perm[k];
@@ -495,7 +498,7 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         pd[i] = pf[i] = 0;
-        if (own && i < N) {
+        if (pre && own) {
             pd[i] = D[(int64_t)i * N + k];
             pf[i] = F[(int64_t)sm.p[i] * N + sm.p[k]];
         }

@@ -95,7 +95,7 @@ def instance(rng, N, dmax, fmax, zero_diag=True):
 
 
 # (N, R, T, max|D|, max|F|, zero diagonal, hot): the values pick the variant --
-# int8 plane copies and MFMA products (six locations per pass) when both
+# int8 plane copies and MFMA products (eight locations per pass) when both
 # maxima are <= 16383, int16 copies (three per pass) up to 32767, int32
 # partial sums when 16 max|D| max|F| < 2^31, int64 H when the bound on |H|
 # exceeds 2^31 - 1
@@ -131,12 +131,12 @@ def test_large_trajectories(P, N, R, T, dmax, fmax, zd, hot):
     assert got["plan"]["sweep"] == "large"
     check(got, ref, max_bad=1)
     assert got["counters"][:, 1].sum() > 0
-    # a single launch serves w locations per pass over the copies (6 on the
+    # a single launch serves w locations per pass over the copies (8 on the
     # int8 planes, 3 on the int16 pairs): the corrections after an accepted
     # exchange whose partner is a later location of the same pass, or one of
     # the next pass, are exercised
     vmax = max(dmax, fmax)
-    w = 6 if vmax <= 16_383 else 3 if vmax <= 32_767 else 0
+    w = 8 if vmax <= 16_383 else 3 if vmax <= 32_767 else 0
     if hot and w and N >= 2 * w:
         r = np.arange(N)[None, None, :]
         s = ref.choices
