@@ -96,7 +96,7 @@ extern "C" {
                                ordered by facility (2 N^2 multiply-adds on rows of D and F that
                                all replicas share through the cache), diag H is kept on chip and
                                moved in O(N) per accepted exchange.  One pass over D and F
-                               serves several consecutive locations: six with values <= 16383
+                               serves several consecutive locations: eight with values <= 16383
                                (int8 planes, MFMA products), three with values <= 32767 (two in
                                batched runs); an accepted exchange corrects the later ones'
                                sums in O(N).  512 threads per replica.
