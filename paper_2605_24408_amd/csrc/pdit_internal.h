@@ -270,7 +270,8 @@ struct LargePlan {
     bool narrow = false;  // int32 partial sums of 24-bit products
     int elem = 4;         // bytes per element of the copies (2: int16, 1: int8 planes)
     bool planes = false;  // int8 hi/lo planes for the MFMA products (|D|, |F| <= 16383)
-    int rows = 0;         // rows of each copy (N rounded up to 16, plus 16 zero rows)
+    int rows = 0;         // rows of each copy: int32, N rounded up to 32 plus 16 zero
+                          // rows; int16 pairs, word rows N64 / 2 + 4; planes, N16
     size_t bytes = 0;     // both copies
 };
 struct LargeCopies {
