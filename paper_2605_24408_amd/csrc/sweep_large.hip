@@ -401,8 +401,9 @@ __device__ __forceinline__ void plane_products(__amdgpu_buffer_rsrc_t Dp,
     }
 }
 
-// LDS of the paired-copies path: the vectors and quarter sums of the
-// K rows of a products pass, and the state shared by all rows.
+// LDS of the multi-location passes (int16 pairs or int8 planes): the
+// vectors and partial sums of the K rows of a products pass, and the state
+// shared by all rows.
 template <int K, bool MF>
 struct PairSmem {
     static constexpr int K16 = MF ? 1 : K;  // rows of the int16 vectors (dot2 products)
@@ -431,8 +432,8 @@ struct PairSmem {
     int32_t xf[K][2];     // prefetched next-pass flows of locations r and s (accepted exchange)
 };
 
-// One replica's sweeps on the paired copies, K locations per pass
-// over the copies.  The pass takes the products of its rows under the p at
+// One replica's sweeps on the int16 pairs (MF false) or the int8 planes (MF
+// true), K locations per pass over the copies.  The pass takes the products of its rows under the p at
 // its start; an accepted exchange of r and s (p -> p tau, tau exchanging r
 // and s) moves the sums of a later row x of the pass by rank-1 terms:
 //   H'[k][x] = H[k][x] + (D[r][k] - D[s][k]) (F[p(x)][p(s)] - F[p(x)][p(r)])
