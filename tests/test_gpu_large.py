@@ -91,6 +91,9 @@ def instance(rng, N, dmax, fmax, zero_diag=True):
     if not zero_diag:
         D[np.diag_indices(N)] = rng.integers(0, dmax + 1, size=N)
         F[np.diag_indices(N)] = rng.integers(0, fmax + 1, size=N)
+    # the maxima pick the copy layout: make sure they occur
+    D[0, 1] = D[1, 0] = max(D[0, 1], dmax * (D.max() < dmax))
+    F[0, 1] = F[1, 0] = max(F[0, 1], fmax * (F.max() < fmax))
     return D.astype(np.int32), F.astype(np.int32)
 
 
@@ -115,6 +118,7 @@ CASES = [
     (300, 2, 2, 99, 99, True, True),
     (512, 2, 2, 10_000, 10_000, True, True),   # the largest instance
     (97, 3, 6, 16_383, 16_383, True, True),    # planes at their largest values
+    (98, 3, 6, 16_384, 16_384, True, True),    # int16 pairs from here: a plane's hi byte would be 128
 ]
 
 
