@@ -494,6 +494,12 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
     int64_t E_best = *j.E_best;
     int64_t n_acc = 0, n_tie = 0;
     __syncthreads();
+    // this lane's own location: facility, D[k][k], F[p(k)][p(k)] and H[k][k]
+    // in registers (LDS keeps them for the other lanes)
+    int32_t myp = own ? sm.p[k] : 0;
+    const int32_t ddk = own ? sm.ddiag[k] : 0;
+    int32_t fdk = own ? sm.fdiag[myp] : 0;
+    int64_t hdk = own ? sm.hd[k] : 0;
     // location k's entries of the pass's rows: D[x][k] and F[p(x)][p(k)]
     int32_t pd[K], pf[K];
 #pragma unroll
@@ -501,7 +507,7 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
         pd[i] = pf[i] = 0;
         if (pre && own) {
             pd[i] = D[(int64_t)i * N + k];
-            pf[i] = F[(int64_t)sm.p[i] * N + sm.p[k]];
+            pf[i] = F[(int64_t)sm.p[i] * N + myp];
         }
     }
 
@@ -516,7 +522,7 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
             const int kb = N - r0 < K ? N - r0 : K;  // rows of this pass
             // ---- the pass's rows: by location, by facility, and as int16 ----
             if (own) {
-                const int pk = sm.p[k];
+                const int pk = myp;
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     int32_t dx = pd[i], fx = pf[i];
@@ -550,7 +556,7 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
                     pd[i] = pf[i] = 0;
                     if (own && nb + i < N) {
                         pd[i] = D[(int64_t)(nb + i) * N + k];
-                        pf[i] = F[(int64_t)sm.p[nb + i] * N + sm.p[k]];
+                        pf[i] = F[(int64_t)sm.p[nb + i] * N + myp];
                     }
                 }
             }
@@ -604,11 +610,10 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
                 int64_t v = INT64_MAX;
                 if (own) {
                     const int64_t hkr = hcol_at(i, k);
-                    const int64_t hrk = g_at(i, sm.p[k]);
-                    const int64_t h = hrk + hkr - sm.hd[r] - sm.hd[k];
-                    const int64_t dd = (int64_t)sm.ddiag[r] + sm.ddiag[k] - 2 * (int64_t)sm.dr[i][k];
-                    const int64_t ff =
-                        (int64_t)sm.fdiag[pr] + sm.fdiag[sm.p[k]] - 2 * (int64_t)sm.fr[i][k];
+                    const int64_t hrk = g_at(i, myp);
+                    const int64_t h = hrk + hkr - sm.hd[r] - hdk;
+                    const int64_t dd = (int64_t)sm.ddiag[r] + ddk - 2 * (int64_t)sm.dr[i][k];
+                    const int64_t ff = (int64_t)sm.fdiag[pr] + fdk - 2 * (int64_t)sm.fr[i][k];
                     v = k == r ? 0 : 2 * h + dd * ff;
                 }
                 // ---- block minimum ----
@@ -665,7 +670,7 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
                 int32_t uk = 0, wk = 0;
                 if (own) {
                     uk = D[(int64_t)s * N + k] - sm.dr[i][k];             // D[k][s] - D[k][r]
-                    sm.v[k] = sm.fr[i][k] - F[(int64_t)ps * N + sm.p[k]];  // Fp[r][k] - Fp[s][k]
+                    sm.v[k] = sm.fr[i][k] - F[(int64_t)ps * N + myp];  // Fp[r][k] - Fp[s][k]
                     wk = F[(int64_t)pr * N + k] - F[(int64_t)ps * N + k];  // F[p(r)][c] - F[p(s)][c], c = k
                     if (pre) {
 #pragma unroll
@@ -696,11 +701,16 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
                 const int tk = k == r ? s : k == s ? r : k;
                 if (own) {
                     if (k == r)
-                        sm.hd[k] = h_rs + (int64_t)uk * sm.v[s];
+                        hdk = h_rs + (int64_t)uk * sm.v[s];
                     else if (k == s)
-                        sm.hd[k] = h_sr + (int64_t)uk * sm.v[r];
+                        hdk = h_sr + (int64_t)uk * sm.v[r];
                     else
-                        sm.hd[k] += (int64_t)uk * sm.v[k];
+                        hdk += (int64_t)uk * sm.v[k];
+                    sm.hd[k] = hdk;
+                    if (k == r || k == s) {
+                        myp = k == r ? ps : pr;
+                        fdk = sm.fdiag[myp];
+                    }
                     // the later rows of the pass
 #pragma unroll
                     for (int i2 = 0; i2 < K; ++i2) {
@@ -740,15 +750,15 @@ __device__ void pair_replica(const ReplicaJob &j, PairSmem<K, MF> &sm) {
                 __syncthreads();
                 if (E < E_best) {
                     E_best = E;
-                    if (own) pbest[k] = sm.p[k];
+                    if (own) pbest[k] = myp;
                 }
             }
         }
         if (j.E_trace && k == 0) j.E_trace[t] = E;
     }
     if (own) {
-        perm[k] = sm.p[k];
-        if (j.flags & kSaveState) H0[(int64_t)k * N + k] = (HT)sm.hd[k];
+        perm[k] = myp;
+        if (j.flags & kSaveState) H0[(int64_t)k * N + k] = (HT)hdk;
     }
     if (k == 0) {
         *j.E = E;
