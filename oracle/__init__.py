@@ -5,8 +5,8 @@ benchmark's CPU-baseline leg may use this package; the GPU library never
 does.  The oracle shares no code with the GPU path.
 
 ``build()`` compiles the C file with gcc (plain -O2, no vector intrinsics,
-floating-point contraction off so float32 products round exactly as
-written).
+floating-point contraction off so the double-precision evaluation of Eq. 5
+rounds exactly as written).
 """
 from __future__ import annotations
 
@@ -60,14 +60,19 @@ def lib():
         L.po_uniform24.restype = C.c_uint32
         L.po_uniform24.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
         L.po_gibbs_choice.restype = C.c_int
-        L.po_gibbs_choice.argtypes = [C.c_int, i64p, C.c_float, C.c_uint32, C.POINTER(C.c_int)]
+        L.po_gibbs_choice.argtypes = [C.c_int, i64p, C.c_float, C.c_uint32, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_double)]
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.po_gibbs_rows.restype = C.c_int
+        L.po_gibbs_rows.argtypes = [C.c_int64, C.c_int, i64p, f32p, u32p, i32p, i32p, f64p]
         L.po_sample_choices.restype = C.c_int
         L.po_sample_choices.argtypes = [C.c_int, i64p, C.c_float, C.c_uint64, C.c_uint32,
                                         C.c_uint32, C.c_uint32, C.c_uint32, C.c_int64, i64p]
         L.po_run.restype = C.c_int
         L.po_run.argtypes = [C.c_int, i32p, i32p, C.c_int, C.c_void_p, C.c_int32, i32p, f32p,
                              C.c_int64, C.c_uint64, C.c_uint64, i64p, i64p, i32p, C.c_int, i64p,
-                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                             C.c_void_p, C.c_void_p, C.c_void_p]
         L.po_brute_min.restype = C.c_int64
         L.po_brute_min.argtypes = [C.c_int, i32p, i32p, C.c_int, i32p]
         L.po_pt_exchange.restype = C.c_int
@@ -145,12 +150,38 @@ def uniform24(seed, r, g, rep, inst) -> int:
 
 
 def gibbs_choice(dE, beta, u24) -> tuple[int, bool]:
+    """Eq. 5 in double precision: (chosen candidate, tie flag)."""
+    k, tie, _ = gibbs_choice_margin(dE, beta, u24)
+    return k, tie
+
+
+def gibbs_choice_margin(dE, beta, u24) -> tuple[int, bool, float]:
+    """(chosen candidate, tie flag, distance of tau to the nearest boundary
+    between candidates of nonzero weight over Z; inf when there is none)."""
     dE = np.ascontiguousarray(dE, dtype=np.int64)
     tie = C.c_int(0)
-    k = lib().po_gibbs_choice(dE.shape[0], dE, np.float32(beta), int(u24), C.byref(tie))
+    margin = C.c_double(0.0)
+    k = lib().po_gibbs_choice(dE.shape[0], dE, np.float32(beta), int(u24), C.byref(tie),
+                              C.byref(margin))
     if k < 0:
         raise MemoryError
-    return int(k), bool(tie.value)
+    return int(k), bool(tie.value), float(margin.value)
+
+
+def gibbs_rows(dE, beta, u24):
+    """Eq. 5 on every row of dE [M, N] with beta[M] and u24[M]: returns
+    (choices, tie flags, margins)."""
+    dE = np.ascontiguousarray(dE, dtype=np.int64)
+    M, N = dE.shape
+    beta = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float32), (M,)))
+    u24 = np.ascontiguousarray(np.broadcast_to(np.asarray(u24, np.uint32), (M,)))
+    sel = np.zeros(M, dtype=np.int32)
+    tie = np.zeros(M, dtype=np.int32)
+    margin = np.zeros(M, dtype=np.float64)
+    rc = lib().po_gibbs_rows(M, N, dE, beta, u24, sel, tie, margin)
+    if rc != PO_OK:
+        raise RuntimeError(f"po_gibbs_rows failed: {rc}")
+    return sel, tie.astype(bool), margin
 
 
 def sample_choices(dE, beta, seed, r, g0, rep, inst, M) -> np.ndarray:
@@ -173,14 +204,27 @@ class RunResult:
     ties: np.ndarray              # [n, 3]: (row, sweep, location)
     choices: np.ndarray | None    # [R, T, N]
     E_trace: np.ndarray | None    # [R, T]
+    excused: np.ndarray | None = None  # [R]: forced draws adopted at ties
+
+
+class OracleMismatch(AssertionError):
+    """A forced draw differed from the oracle's own choice off a tie."""
+
+    def __init__(self, row, t, r, own, forced):
+        super().__init__(f"draw (row {row}, sweep {t} of the call, location {r}): oracle "
+                         f"chose {own}, the other path {forced}, and the oracle saw no tie")
+        self.row, self.t, self.r, self.own, self.forced = row, t, r, own, forced
 
 
 def run(D, F, perm, beta, seed, sweep_offset=0, rep_ids=None, inst_id=0, E_best=None,
         perm_best=None, record_choices=False, record_trace=False, paranoid=False,
-        tie_cap=100_000) -> RunResult:
+        tie_cap=100_000, forced=None) -> RunResult:
     """Run len(beta) sweeps on every row of ``perm`` (a copy; the input is
     left untouched).  Without ``E_best`` the best state starts from the
-    initial one."""
+    initial one.  ``forced`` ([R, T, N], optional): draws of another
+    evaluation of the same dynamics; the oracle adopts a forced draw only
+    where its own draw is a tie and raises OracleMismatch at the first
+    disagreement off a tie."""
     D, F = _i32(D), _i32(F)
     N = D.shape[0]
     p = np.array(perm, dtype=np.int32, copy=True).reshape(-1, N)
@@ -198,14 +242,28 @@ def run(D, F, perm, beta, seed, sweep_offset=0, rep_ids=None, inst_id=0, E_best=
     choices = np.full((R, T, N), -1, dtype=np.int32) if record_choices else None
     trace = np.zeros((R, T), dtype=np.int64) if record_trace else None
     reps = None if rep_ids is None else np.ascontiguousarray(rep_ids, dtype=np.int32)
+    fc = None
+    excused = fail_at = None
+    if forced is not None:
+        fc = np.ascontiguousarray(forced, dtype=np.int32)
+        if fc.shape != (R, T, N):
+            raise ValueError(f"forced draws must have shape {(R, T, N)}, not {fc.shape}")
+        excused = np.zeros(R, dtype=np.int64)
+        fail_at = np.full(5, -1, dtype=np.int64)
     rc = lib().po_run(N, D, F, R, None if reps is None else reps.ctypes.data, int(inst_id), p,
                       beta, T, int(seed), int(sweep_offset), E, Eb, pb, int(init_best),
                       counters, tie_log.ctypes.data, tie_cap, tie_n.ctypes.data,
                       None if choices is None else choices.ctypes.data,
-                      None if trace is None else trace.ctypes.data, int(paranoid))
+                      None if trace is None else trace.ctypes.data, int(paranoid),
+                      None if fc is None else fc.ctypes.data,
+                      None if excused is None else excused.ctypes.data,
+                      None if fail_at is None else fail_at.ctypes.data)
+    if rc == PO_EMISMATCH and fc is not None and fail_at[0] >= 0:
+        raise OracleMismatch(*(int(v) for v in fail_at))
     if rc != PO_OK:
         raise RuntimeError(f"oracle run failed with status {rc}")
-    return RunResult(p, E, Eb, pb, counters, tie_log[: int(tie_n[0])].copy(), choices, trace)
+    return RunResult(p, E, Eb, pb, counters, tie_log[: int(tie_n[0])].copy(), choices, trace,
+                     excused)
 
 
 def pt_exchange(E, slot_of, since_top, timeout):

@@ -35,19 +35,20 @@
  *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
  *     key = (lo32(seed), hi32(seed)), counter = (r, g, replica, instance)
  *     for the update of location r in global sweep g; word 0 shifted right
- *     by 8 gives a 24-bit uniform u24 (u = u24 / 2^24);
- *   - sampling is taken in the GPU kernel's precision: with m = min_k dE_k,
- *     x_k = fl32(beta * fl32(dE_k - m)), w_k = expf(-x_k), and the weight is
- *     quantised to q_k = rint(w_k * 2^25) (an integer in [0, 2^25]); the CDF
- *     C_k = q_0 + ... + q_k is exact in 64-bit integers, Z = C_{N-1}, and the
- *     chosen candidate is the first k with C_k * 2^24 > u24 * Z;
- *   - a "tie" is a draw whose threshold u24 * Z lies within Z * 2^4 (a
- *     relative 2^-20, about 1e-6) of a CDF boundary that separates two
- *     candidates of nonzero weight: a last-ulp difference in expf could move
- *     such a draw to the neighbouring candidate, so ties are counted.
+ *     by 8 gives a 24-bit uniform u24, u = u24 * 2^-24 (exact in double);
+ *   - Eq. 5 is evaluated in double precision: with m = min_k dE_k (a no-op
+ *     for the probabilities that keeps exp from overflowing),
+ *     w_k = exp(-beta (dE_k - m)) with the C library's exp, the running sum
+ *     C_k = w_0 + ... + w_k taken in ascending k, Z = C_{N-1},
+ *     tau = u Z, and the chosen candidate is the first k with C_k > tau;
+ *   - a "tie" is a draw whose tau lies within 2^-20 Z (about 1e-6 of the
+ *     total) of a boundary C_k that separates two candidates of nonzero
+ *     weight (0 < C_k < Z): a different but equally valid evaluation of the
+ *     weights (single precision, another exp) may move such a draw to the
+ *     neighbouring candidate, so ties are counted and logged.
  *
  * Integer arithmetic is int64 throughout; the only floating point is the
- * float32 sampling above.
+ * double-precision evaluation of Eq. 5 above.
  */
 #include <math.h>
 #include <stdint.h>
@@ -155,43 +156,68 @@ uint32_t po_uniform24(uint64_t seed, uint32_t r, uint32_t g, uint32_t rep, uint3
 }
 
 /* ------------------------------------------------------------------ */
-/* Eq. 5: Gibbs choice among the N candidates                          */
+/* Eq. 5: Gibbs choice among the N candidates, in double precision      */
 /* ------------------------------------------------------------------ */
-int po_gibbs_choice(int N, const int64_t *dE, float beta, uint32_t u24, int *tie)
+#define PO_TIE_BAND 9.5367431640625e-07 /* 2^-20, relative to Z */
+
+/*
+ * Chosen candidate of one update with energy changes dE[0..N-1] at inverse
+ * temperature beta and uniform u24 (returns PO_ENOMEM on allocation
+ * failure).  *tie (optional) is set when tau = u Z lies within 2^-20 Z of a
+ * boundary between two candidates of nonzero weight; *margin (optional)
+ * receives the distance of tau to the nearest such boundary divided by Z
+ * (HUGE_VAL when there is none).
+ */
+int po_gibbs_choice(int N, const int64_t *dE, float beta, uint32_t u24, int *tie, double *margin)
 {
-    uint64_t *q = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
-    if (!q) return PO_ENOMEM;
+    if (N < 1 || !dE) return PO_EINVAL;
+    double *C = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!C) return PO_ENOMEM;
     int64_t m = dE[0];
     for (int s = 1; s < N; ++s)
         if (dE[s] < m) m = dE[s];
-    uint64_t Z = 0;
+    const double b = (double)beta;
+    double acc = 0.0;
     for (int s = 0; s < N; ++s) {
-        const float d = (float)(dE[s] - m);
-        const float x = beta * d;
-        const float w = expf(-x);
-        q[s] = (uint64_t)rintf(w * 33554432.0f); /* 2^25 */
-        Z += q[s];
+        const double x = b * (double)(dE[s] - m);
+        /* exp(-x) is exactly 0 in double beyond x = 745.2; skip the call */
+        acc += x > 746.0 ? 0.0 : exp(-x);
+        C[s] = acc;
     }
-    const uint64_t target = (uint64_t)u24 * Z; /* u24 * Z < 2^24 * 2^34 */
-    const uint64_t thr = target >> 24;         /* C*2^24 > target <=> C > thr */
-    uint64_t C = 0, Cprev = 0;
+    const double Z = acc;
+    const double tau = ((double)u24 / 16777216.0) * Z;
     int sel = N - 1;
-    for (int s = 0; s < N; ++s) {
-        Cprev = C;
-        C += q[s];
-        if (C > thr) {
+    for (int s = 0; s < N; ++s)
+        if (C[s] > tau) {
             sel = s;
             break;
         }
-    }
-    if (tie) {
-        const uint64_t band = Z << 4;
-        const uint64_t lo_margin = target - (Cprev << 24);
-        const uint64_t hi_margin = (C << 24) - target;
-        *tie = (Cprev > 0 && lo_margin < band) || (C < Z && hi_margin <= band);
-    }
-    free(q);
+    double near = HUGE_VAL;
+    if (sel > 0 && C[sel - 1] > 0.0) near = tau - C[sel - 1];
+    if (C[sel] < Z && C[sel] - tau < near) near = C[sel] - tau;
+    if (tie) *tie = near < PO_TIE_BAND * Z;
+    if (margin) *margin = near == HUGE_VAL ? HUGE_VAL : near / Z;
+    free(C);
     return sel;
+}
+
+/* po_gibbs_choice on M rows: row i has energy changes dE[i*N .. i*N+N-1],
+ * inverse temperature beta[i] and uniform u24[i]; sel, tie (optional) and
+ * margin (optional) receive one value per row. */
+int po_gibbs_rows(int64_t M, int N, const int64_t *dE, const float *beta, const uint32_t *u24,
+                  int32_t *sel, int32_t *tie, double *margin)
+{
+    if (M < 0 || N < 1 || !dE || !beta || !u24 || !sel) return PO_EINVAL;
+    for (int64_t i = 0; i < M; ++i) {
+        int t = 0;
+        double mg = 0.0;
+        const int k = po_gibbs_choice(N, dE + i * N, beta[i], u24[i], &t, &mg);
+        if (k < 0) return k;
+        sel[i] = k;
+        if (tie) tie[i] = t;
+        if (margin) margin[i] = mg;
+    }
+    return PO_OK;
 }
 
 /* Draw M updates of p-dit r from the fixed energy-change row dE, with the
@@ -202,7 +228,7 @@ int po_sample_choices(int N, const int64_t *dE, float beta, uint64_t seed, uint3
 {
     for (int64_t m = 0; m < M; ++m) {
         const uint32_t u24 = po_uniform24(seed, r, g0 + (uint32_t)m, rep, inst);
-        const int k = po_gibbs_choice(N, dE, beta, u24, NULL);
+        const int k = po_gibbs_choice(N, dE, beta, u24, NULL, NULL);
         if (k < 0) return k;
         counts[k] += 1;
     }
@@ -239,12 +265,22 @@ static int is_permutation(int N, const int32_t *p, unsigned char *seen)
  *   choices    optional [R*T*N]: the chosen candidate of every update
  *   E_trace    optional [R*T]: the energy after every sweep
  *   paranoid   after every sweep, check I against Eq. 2 and E against Eq. 1
+ *   forced     optional [R*T*N]: draws made by another evaluation of the
+ *              same dynamics (for parity checks).  Where forced differs from
+ *              this oracle's own choice, the draw must be a tie: the oracle
+ *              then takes the forced candidate (so it follows the other
+ *              trajectory from there on) and counts it in excused[row];
+ *              otherwise the run stops with PO_EMISMATCH and fail_at =
+ *              (row, t, r, own choice, forced choice).
+ *   excused    optional [R] out (with forced): adopted draws per row
+ *   fail_at    optional [5] out (with forced): first disagreement off a tie
  */
 int po_run(int N, const int32_t *D, const int32_t *F, int R, const int32_t *rep_ids,
            int32_t inst_id, int32_t *perm, const float *beta, int64_t T, uint64_t seed,
            uint64_t sweep_off, int64_t *E, int64_t *E_best, int32_t *perm_best, int init_best,
            int64_t *counters, int32_t *tie_log, int64_t tie_cap, int64_t *tie_n,
-           int32_t *choices, int64_t *E_trace, int paranoid)
+           int32_t *choices, int64_t *E_trace, int paranoid, const int32_t *forced,
+           int64_t *excused, int64_t *fail_at)
 {
     if (N < 2 || R < 1 || T < 0 || !D || !F || !perm || !beta || !E || !E_best || !perm_best ||
         !counters)
@@ -259,6 +295,7 @@ int po_run(int N, const int32_t *D, const int32_t *F, int R, const int32_t *rep_
         goto done;
     }
     if (tie_n) *tie_n = 0;
+    if (forced && excused) memset(excused, 0, sizeof(int64_t) * (size_t)R);
 
     for (int row = 0; row < R; ++row) {
         int32_t *p = perm + (int64_t)row * N;
@@ -282,10 +319,32 @@ int po_run(int N, const int32_t *D, const int32_t *F, int R, const int32_t *rep_
                 for (int s = 0; s < N; ++s) dE[s] = po_delta_eq3(N, D, F, p, I, r, s);
                 const uint32_t u24 = po_uniform24(seed, (uint32_t)r, g, rep, (uint32_t)inst_id);
                 int tie = 0;
-                const int k = po_gibbs_choice(N, dE, b, u24, &tie);
+                int k = po_gibbs_choice(N, dE, b, u24, &tie, NULL);
                 if (k < 0) {
                     rc = k;
                     goto done;
+                }
+                if (forced) {
+                    const int32_t kf = forced[((int64_t)row * T + t) * N + r];
+                    if (kf < 0 || kf >= N) {
+                        rc = PO_EINVAL;
+                        goto done;
+                    }
+                    if (kf != k) {
+                        if (!tie) {
+                            if (fail_at) {
+                                fail_at[0] = row;
+                                fail_at[1] = t;
+                                fail_at[2] = r;
+                                fail_at[3] = k;
+                                fail_at[4] = kf;
+                            }
+                            rc = PO_EMISMATCH;
+                            goto done;
+                        }
+                        k = kf;
+                        if (excused) ++excused[row];
+                    }
                 }
                 ++n_upd;
                 if (tie) {
@@ -438,7 +497,7 @@ int po_run_pt(int N, const int32_t *D, const int32_t *F, int R, int L, int32_t *
                 rc = po_run(N, D, F, 1, &rep, inst_id, perm + (int64_t)k * N, b, period_sweeps,
                             seed, sweep_off + (uint64_t)(per * period_sweeps), E + k, E_best + k,
                             perm_best + (int64_t)k * N, init_best && per == 0, cnt, NULL, 0, NULL,
-                            NULL, NULL, 0);
+                            NULL, NULL, 0, NULL, NULL, NULL);
             else
                 rc = po_run_cupim(N, D, F, 1, &rep, inst_id, perm + (int64_t)k * N, b,
                                   period_sweeps, seed, sweep_off + (uint64_t)(per * period_sweeps),
@@ -546,7 +605,7 @@ int po_run_cupim(int N, const int32_t *D, const int32_t *F, int R, const int32_t
                 for (int s = 0; s < N; ++s) row[s] = po_delta_eq3(N, D, F, p, I, r, s);
                 const uint32_t u24 = po_uniform24(seed, (uint32_t)r, g, rep, (uint32_t)inst_id);
                 int tie = 0;
-                const int c = po_gibbs_choice(N, row, beta[t], u24, &tie);
+                const int c = po_gibbs_choice(N, row, beta[t], u24, &tie, NULL);
                 if (c < 0) {
                     rc = c;
                     goto done;
@@ -663,7 +722,7 @@ int po_beta_select(int N, const int32_t *D, const int32_t *F, int R, const int32
         for (int k = 0; k < R; ++k) ids[k] = g * R + k;
         for (int64_t t = 0; t < trial_sweeps; ++t) b[t] = grid[g];
         rc = po_run(N, D, F, R, ids, inst_id, p, b, trial_sweeps, seed, 0, E, Eb, pb, 1, cnt, NULL,
-                    0, NULL, NULL, NULL, 0);
+                    0, NULL, NULL, NULL, 0, NULL, NULL, NULL);
         int64_t sum = 0;
         for (int k = 0; k < R; ++k) {
             sum += E[k];
