@@ -56,7 +56,8 @@ extern "C" {
 #define PDIT_EINVAL (-1)    /* null pointer, N < 2, N > PDIT_NMAX, R < 1, n_sweeps < 0, bad option */
 #define PDIT_ENOTSYM (-2)   /* D or F is not symmetric */
 #define PDIT_EBADPERM (-3)  /* a permutation row is not a permutation of 0..N-1 */
-#define PDIT_EOVERFLOW (-4) /* an exact integer bound does not fit the requested arithmetic */
+#define PDIT_EOVERFLOW (-4) /* an exact integer bound does not fit the requested arithmetic, or
+                               an entry of D or F equals INT32_MIN */
 #define PDIT_ENOMEM (-5)    /* device allocation failed */
 #define PDIT_EDEVICE (-6)   /* HIP runtime error (text in pdit_last_error) */
 #define PDIT_EBETA (-7)     /* an inverse temperature is NaN, infinite or negative */
@@ -134,6 +135,10 @@ typedef struct {
     const int32_t *F;     /* device, N x N, symmetric */
     int32_t *perm;        /* device, R x N, in/out */
     const float *beta;    /* device, n_sweeps values */
+    int32_t *choices;     /* optional (NULL: not recorded): device int32 R x n_sweeps x N, the
+                             drawn candidate of every update of this instance */
+    int64_t *E_trace;     /* optional (NULL: not recorded): device int64 R x n_sweeps, the
+                             energy after every sweep */
 } pdit_instance;
 
 /* Fills *opts with the defaults (device 0, null stream, AUTO modes). */
@@ -184,7 +189,9 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
  * energies, and permutation rows of each instance's own length N_n.
  *   inst   host array of n_inst descriptors (device pointers inside)
  * The sweep offset and best state behave as in pdit_run_sweeps.  Recording
- * (pdit_set_recording) is not available for batched runs.
+ * goes through each instance's choices and E_trace pointers (pdit_set_recording
+ * applies to single-instance runs only); the buffers are part of what the
+ * captured graph was built for, so changing them captures a new graph.
  */
 int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst,
                           int64_t n_sweeps, uint64_t seed);
@@ -267,8 +274,8 @@ int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, i
                    int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed);
 
 /*
- * Beta-range selection (Results, "Implementation"; Methods, "CPU-PIM
- * Algorithm"): short trials at fixed beta, without exchanges, on an
+ * Beta-range selection (Results, "Implementation", Figure 2b; Methods,
+ * "CPU-PIM Algorithm"): short trials at fixed beta, without exchanges, on an
  * ascending grid; the averaged ending energies fall with beta and turn up
  * again where the replicas freeze.  For every grid value g, R trial
  * replicas start from the rows of perm (unchanged by the call) and run
@@ -276,27 +283,35 @@ int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, i
  * grid value g draws as replica g R + k of a run from sweep 0 (the
  * context's sweep offset is neither used nor advanced).  Then, with Smax and
  * Smin the largest and smallest sums of ending energies:
- *   range[0] = lo, the first g whose sum has come down from Smax by at least
- *              40% of Smax - Smin (5 E_sum[g] <= 3 Smax + 2 Smin);
+ *   range[0] = lo, the first g whose sum is at most the level lying
+ *              level_pct percent of Smax - Smin above Smin
+ *              (100 E_sum[g] <= level_pct Smax + (100 - level_pct) Smin,
+ *              exact).  The paper takes the energy that has dropped to about
+ *              40% between the minimum and the maximum: level_pct = 40; 60
+ *              gives the other reading of its wording (a drop of 40% from
+ *              the maximum);
  *   range[1] = hi, two grid values past the first g holding Smin (at most
  *              G - 1);
  *   ladder[i] = grid[lo] (grid[hi] / grid[lo])^(i / (L - 1)), evaluated in
- *              double and rounded to float, ladder[0] = grid[lo] and
- *              ladder[L - 1] = grid[hi] exactly: a parallel-tempering ladder
- *              (pdit_pt.beta) of L rungs.
+ *              double on the host and rounded to float, ladder[0] = grid[lo]
+ *              and ladder[L - 1] = grid[hi] exactly: a parallel-tempering
+ *              ladder (pdit_pt.beta) of L rungs.
  *   perm     device int32 R x N, the trials' starting permutations
  *   grid     device float G, finite, > 0, strictly ascending (PDIT_EBETA)
+ *   level_pct  0..100 (PDIT_EINVAL otherwise)
  *   E_sum    device int64 G, out: summed ending energies (exact; the mean
  *            times R)
  *   ladder   device float L (L >= 2), out;   range: device int32 2, out
  * R * N * (bound on |H|) must stay below 2^59 (PDIT_EOVERFLOW).  The
  * context's replica state becomes that of the G * R trial replicas
- * (pdit_energy, pdit_best, pdit_replica_counters report them).  Recording is
- * not available.
+ * (pdit_energy, pdit_best, pdit_replica_counters report them).  The rule
+ * reads the sums back, so the call ends with a host synchronisation.
+ * Recording is not available.
  */
 int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                      const int32_t *perm, const float *grid, int32_t G, int64_t trial_sweeps,
-                     uint64_t seed, int32_t L, int64_t *E_sum, float *ladder, int32_t *range);
+                     uint64_t seed, int32_t L, int32_t level_pct, int64_t *E_sum, float *ladder,
+                     int32_t *range);
 
 /* Result of pdit_autotune. */
 typedef struct {

@@ -89,11 +89,11 @@ def lib():
                                    C.c_int64, C.c_uint64, C.c_uint64, i64p, i64p, i32p, C.c_int,
                                    i64p, C.c_void_p, C.c_void_p]
         L.po_beta_rule.restype = C.c_int
-        L.po_beta_rule.argtypes = [C.c_int, i64p, f32p, C.c_int, f32p, i32p]
+        L.po_beta_rule.argtypes = [C.c_int, i64p, f32p, C.c_int, C.c_int, f32p, i32p]
         L.po_beta_select.restype = C.c_int
         L.po_beta_select.argtypes = [C.c_int, i32p, i32p, C.c_int, i32p, f32p, C.c_int, C.c_int64,
-                                     C.c_uint64, C.c_int32, C.c_int, i64p, C.c_void_p, C.c_void_p,
-                                     C.c_void_p]
+                                     C.c_uint64, C.c_int32, C.c_int, C.c_int, i64p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -371,15 +371,16 @@ def run_cupim(D, F, perm, beta, seed, sweep_offset=0, rep_ids=None, inst_id=0, E
     return CupimResult(p, E, Eb, pb, counters, choices, None if won is None else won.astype(bool))
 
 
-def beta_rule(E_sum, grid, L):
+def beta_rule(E_sum, grid, L, level_pct=40):
     """The range rule of the beta selection (Results, "Implementation";
-    Methods, "CPU-PIM Algorithm") on summed trial energies: returns
+    Methods, "CPU-PIM Algorithm") on summed trial energies, with the low
+    end's level level_pct percent of the range above the minimum: returns
     (lo, hi, ladder)."""
     E_sum = np.ascontiguousarray(E_sum, dtype=np.int64)
     grid = np.ascontiguousarray(grid, dtype=np.float32)
     ladder = np.zeros(int(L), dtype=np.float32)
     lo_hi = np.zeros(2, dtype=np.int32)
-    rc = lib().po_beta_rule(E_sum.shape[0], E_sum, grid, int(L), ladder, lo_hi)
+    rc = lib().po_beta_rule(E_sum.shape[0], E_sum, grid, int(L), int(level_pct), ladder, lo_hi)
     if rc != PO_OK:
         raise RuntimeError(f"oracle beta rule failed with status {rc}")
     return int(lo_hi[0]), int(lo_hi[1]), ladder
@@ -394,10 +395,12 @@ class BetaSelection:
     ladder: np.ndarray     # [L]
 
 
-def beta_select(D, F, perm, grid, trial_sweeps, seed, L, inst_id=0) -> BetaSelection:
+def beta_select(D, F, perm, grid, trial_sweeps, seed, L, inst_id=0,
+                level_pct=40) -> BetaSelection:
     """Beta-range selection: fixed-beta trials of trial_sweeps sweeps from
-    the rows of perm at every grid value, then the range rule and a
-    geometric ladder of L rungs."""
+    the rows of perm at every grid value, then the range rule (low-end
+    level level_pct percent of the range above the minimum) and a geometric
+    ladder of L rungs."""
     D, F = _i32(D), _i32(F)
     N = D.shape[0]
     p = np.ascontiguousarray(perm, dtype=np.int32).reshape(-1, N)
@@ -409,8 +412,8 @@ def beta_select(D, F, perm, grid, trial_sweeps, seed, L, inst_id=0) -> BetaSelec
     ladder = np.zeros(int(L), dtype=np.float32)
     lo_hi = np.zeros(2, dtype=np.int32)
     rc = lib().po_beta_select(N, D, F, R, p, grid, G, int(trial_sweeps), int(seed), int(inst_id),
-                              int(L), E_sum, ladder.ctypes.data, lo_hi.ctypes.data,
-                              E_trial.ctypes.data)
+                              int(L), int(level_pct), E_sum, ladder.ctypes.data,
+                              lo_hi.ctypes.data, E_trial.ctypes.data)
     if rc != PO_OK:
         raise RuntimeError(f"oracle beta selection failed with status {rc}")
     return BetaSelection(E_sum, E_trial, int(lo_hi[0]), int(lo_hi[1]), ladder)

@@ -652,18 +652,25 @@ done:
  * The rule, on the summed ending energies of the trials (E_sum[g] = sum of
  * the R trial replicas' energies at grid[g], the mean times R, so exact):
  * with Smax and Smin the largest and smallest sums, the low end lo is the
- * first g (lowest beta first) whose sum has come down from Smax by at least
- * 40% of Smax - Smin, i.e. 5 E_sum[g] <= 3 Smax + 2 Smin; the high end is
- * two grid steps past the first g holding Smin, at most G - 1.  The ladder
- * of L >= 2 rungs is geometric between grid[lo] and grid[hi]:
- * ladder[i] = fl32(grid[lo] * exp(log(grid[hi] / grid[lo]) * i / (L - 1)))
- * in double, with both ends exactly the grid values.  lo_hi[0] = lo,
- * lo_hi[1] = hi.  Sums must stay below 2^59 in magnitude.
+ * first g (lowest beta first) whose sum is at most the level that lies
+ * level_pct percent of Smax - Smin above Smin,
+ *   100 E_sum[g] <= level_pct Smax + (100 - level_pct) Smin
+ * (exact in 128-bit integers).  The paper puts the level at about 40% of the
+ * range between the minimum and the maximum: level_pct = 40; the other
+ * reading of its wording, a drop of 40% from the maximum, is level_pct = 60.
+ * The high end is two grid steps past the first g holding Smin, at most
+ * G - 1.  The ladder of L >= 2 rungs is geometric between grid[lo] and
+ * grid[hi]: ladder[i] = fl32(grid[lo] * exp(log(grid[hi] / grid[lo]) * i /
+ * (L - 1))) in double, with both ends exactly the grid values.
+ * lo_hi[0] = lo, lo_hi[1] = hi.  Sums must stay below 2^59 in magnitude and
+ * level_pct lie in [0, 100].
  */
-int po_beta_rule(int G, const int64_t *E_sum, const float *grid, int L, float *ladder,
-                 int32_t *lo_hi)
+int po_beta_rule(int G, const int64_t *E_sum, const float *grid, int L, int level_pct,
+                 float *ladder, int32_t *lo_hi)
 {
-    if (G < 1 || L < 2 || !E_sum || !grid || !ladder || !lo_hi) return PO_EINVAL;
+    if (G < 1 || L < 2 || !E_sum || !grid || !ladder || !lo_hi || level_pct < 0 ||
+        level_pct > 100)
+        return PO_EINVAL;
     const int64_t lim = (int64_t)1 << 59;
     int64_t smax = E_sum[0], smin = E_sum[0];
     int gmin = 0;
@@ -675,9 +682,10 @@ int po_beta_rule(int G, const int64_t *E_sum, const float *grid, int L, float *l
             gmin = g;
         }
     }
+    const __int128 level = (__int128)level_pct * smax + (__int128)(100 - level_pct) * smin;
     int lo = -1;
     for (int g = 0; g < G && lo < 0; ++g)
-        if (5 * E_sum[g] <= 3 * smax + 2 * smin) lo = g;
+        if ((__int128)100 * E_sum[g] <= level) lo = g;
     int hi = gmin + 2 < G ? gmin + 2 : G - 1;
     lo_hi[0] = lo;
     lo_hi[1] = hi;
@@ -694,11 +702,13 @@ int po_beta_rule(int G, const int64_t *E_sum, const float *grid, int L, float *l
  * R replicas start from the given permutations and run trial_sweeps sweeps
  * at that fixed beta with no exchanges; trial replica k of grid point g
  * draws with Philox replica id g R + k, instance inst_id, from sweep 0.
- * E_trial (optional, [G*R]) receives every ending energy; then the rule.
+ * E_trial (optional, [G*R]) receives every ending energy; then the rule
+ * with the given level.
  */
 int po_beta_select(int N, const int32_t *D, const int32_t *F, int R, const int32_t *perm,
                    const float *grid, int G, int64_t trial_sweeps, uint64_t seed, int32_t inst_id,
-                   int L, int64_t *E_sum, float *ladder, int32_t *lo_hi, int64_t *E_trial)
+                   int L, int level_pct, int64_t *E_sum, float *ladder, int32_t *lo_hi,
+                   int64_t *E_trial)
 {
     if (N < 2 || R < 1 || G < 1 || trial_sweeps < 0 || !D || !F || !perm || !grid || !E_sum)
         return PO_EINVAL;
@@ -730,7 +740,8 @@ int po_beta_select(int N, const int32_t *D, const int32_t *F, int R, const int32
         }
         E_sum[g] = sum;
     }
-    if (rc == PO_OK && ladder && lo_hi) rc = po_beta_rule(G, E_sum, grid, L, ladder, lo_hi);
+    if (rc == PO_OK && ladder && lo_hi)
+        rc = po_beta_rule(G, E_sum, grid, L, level_pct, ladder, lo_hi);
 done:
     free(p);
     free(pb);

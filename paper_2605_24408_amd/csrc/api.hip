@@ -8,6 +8,8 @@
 
 #include "pdit_internal.h"
 
+#include <cmath>
+
 using pdit::InstanceStats;
 
 namespace {
@@ -108,6 +110,8 @@ int instance_prep(pdit_t *ctx, int N, const int32_t *D, const int32_t *F, int R,
     PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     *st = *ctx->stats_host;
     if (st->asym_d || st->asym_f) return fail(ctx, PDIT_ENOTSYM, "D or F is not symmetric");
+    if (st->int_min)
+        return fail(ctx, PDIT_EOVERFLOW, "D and F entries must be greater than INT32_MIN");
     if (st->bad_perm_rows)
         return fail(ctx, PDIT_EBADPERM, "a row of perm is not a permutation of 0..N-1");
     if (st->bad_beta) return fail(ctx, PDIT_EBETA, "an inverse temperature is NaN, infinite or negative");
@@ -696,11 +700,14 @@ int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, i
 
 int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                      const int32_t *perm, const float *grid, int32_t G, int64_t trial_sweeps,
-                     uint64_t seed, int32_t L, int64_t *E_sum, float *ladder, int32_t *range) {
+                     uint64_t seed, int32_t L, int32_t level_pct, int64_t *E_sum, float *ladder,
+                     int32_t *range) {
     if (!ctx) return PDIT_EINVAL;
     ctx->last_error.clear();
     if (!D || !F || !perm || !grid || !E_sum || !ladder || !range)
         return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    if (level_pct < 0 || level_pct > 100)
+        return fail(ctx, PDIT_EINVAL, "level_pct must be in [0, 100]");
     if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
     if (R < 1 || G < 1 || (int64_t)R * G > INT32_MAX)
         return fail(ctx, PDIT_EINVAL, "R and G must be >= 1 with R * G < 2^31");
@@ -800,8 +807,38 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     }
     PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
     PDIT_HIP(ctx, pdit::launch_group_sums(ctx->stream, R, G, S.E, E_sum));
-    PDIT_HIP(ctx, pdit::launch_beta_rule(ctx->stream, G, E_sum, grid, L, ladder, range));
     ctx->timed = true;
+    // the rule on the G sums, on the host: integers compared exactly in 128
+    // bits, the geometric ladder in double
+    std::vector<int64_t> sums(G);
+    std::vector<float> gv(G);
+    PDIT_HIP(ctx, hipMemcpyAsync(sums.data(), E_sum, sizeof(int64_t) * G, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    PDIT_HIP(ctx, hipMemcpyAsync(gv.data(), grid, sizeof(float) * G, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    int64_t smax = sums[0], smin = sums[0];
+    int gmin = 0;
+    for (int g = 1; g < G; ++g) {
+        if (sums[g] > smax) smax = sums[g];
+        if (sums[g] < smin) {
+            smin = sums[g];
+            gmin = g;
+        }
+    }
+    const __int128 level = (__int128)level_pct * smax + (__int128)(100 - level_pct) * smin;
+    int32_t rng[2] = {0, gmin + 2 < G ? gmin + 2 : G - 1};
+    while (rng[0] < G - 1 && (__int128)100 * sums[rng[0]] > level) ++rng[0];  // Smin meets it
+    std::vector<float> lad(L);
+    const double b0 = gv[rng[0]], b1 = gv[rng[1]];
+    const double lr = log(b1 / b0);
+    for (int i = 1; i + 1 < L; ++i) lad[i] = (float)(b0 * exp(lr * (double)i / (double)(L - 1)));
+    lad[0] = gv[rng[0]];
+    lad[L - 1] = gv[rng[1]];
+    PDIT_HIP(ctx, hipMemcpyAsync(range, rng, sizeof(rng), hipMemcpyHostToDevice, ctx->stream));
+    PDIT_HIP(ctx, hipMemcpyAsync(ladder, lad.data(), sizeof(float) * L, hipMemcpyHostToDevice,
+                                 ctx->stream));
+    PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->last_updates = (int64_t)RT * N * trial_sweeps;
     ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : use_large ? PDIT_SWEEP_LARGE : PDIT_SWEEP_PLAIN;
     ctx->last_class = use_fast ? fclass : 0;
@@ -817,7 +854,9 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     if (!inst || n_inst < 1) return fail(ctx, PDIT_EINVAL, "empty or null instance list");
     if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
     if (ctx->rec_choices || ctx->rec_trace)
-        return fail(ctx, PDIT_EINVAL, "recording is not available for batched runs");
+        return fail(ctx, PDIT_EINVAL,
+                    "pdit_set_recording applies to single-instance runs: batched runs record "
+                    "through the instances' choices and E_trace pointers");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_LARGE ||
         ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL,
@@ -859,6 +898,8 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     for (int k = 0; k < n_inst; ++k) {
         const InstanceStats &q = st[k];
         if (q.asym_d || q.asym_f) return fail(ctx, PDIT_ENOTSYM, "D or F of an instance is not symmetric");
+        if (q.int_min)
+            return fail(ctx, PDIT_EOVERFLOW, "an instance has an entry equal to INT32_MIN");
         if (q.bad_perm_rows)
             return fail(ctx, PDIT_EBADPERM, "a row of an instance's perm is not a permutation");
         if (q.bad_beta)
@@ -910,6 +951,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     // ---- descriptors ----
     std::vector<pdit::BatchInstance> desc(n_inst);
     int64_t rep_base = 0, perm_off = 0;
+    bool rec = false;
     for (int k = 0; k < n_inst; ++k) {
         pdit::BatchInstance &d = desc[k];
         d.N = inst[k].N;
@@ -923,6 +965,9 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         d.perm_off = perm_off;
         d.zero_diag = plan[k].zd ? 1 : 0;
         d.inst_id = k;
+        d.choices = inst[k].choices;
+        d.E_trace = inst[k].E_trace;
+        if (d.choices || d.E_trace) rec = true;
         if (plan[k].large) {
             d.cD = (const char *)ctx->large_buf.ptr + plan[k].coff;
             d.cF = (const char *)d.cD + plan[k].lp.bytes / 2;
@@ -1029,6 +1074,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
         push(ptrs, sizeof(ptrs));
         push(&n_sweeps, sizeof(n_sweeps));
         push(&seq_thr, sizeof(seq_thr));
+        push(&rec, sizeof(rec));
         for (auto &g : groups) push(&g.grid, sizeof(g.grid));
 
         char *dbuf = (char *)ctx->batch_buf.ptr;
@@ -1060,6 +1106,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                 b.counters = S.counters;
                 b.T = n_sweeps;
                 b.seq_threshold = seq_thr >= 0 ? seq_thr : pdit::default_seq_threshold(g.nmax, g.nmax);
+                b.rec = rec ? 1 : 0;
                 cap = g.fast    ? pdit::launch_sweep_fast_persistent(cs, g.nmax, g.zd, b, g.grid)
                       : g.large ? pdit::launch_sweep_large_persistent(cs, g.lp, g.h64, b, g.grid)
                                 : pdit::launch_sweep_plain_persistent(cs, g.h64, b, g.grid);
@@ -1108,6 +1155,8 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
         else if (hipMalloc(&copies[k], sizeof(int32_t) * (size_t)inst[k].R * inst[k].N) != hipSuccess)
             rc = PDIT_ENOMEM;
         trial[k].perm = copies[k];
+        trial[k].choices = nullptr;  // trials record nothing
+        trial[k].E_trace = nullptr;
     }
     pdit_opts o = ctx->opts;
     if (rc == PDIT_OK) rc = pdit_create(&tmp, &o);

@@ -30,6 +30,7 @@ struct InstanceStats {
     int32_t bad_grid;       // beta selection: grid values <= 0 or not above the previous one
     int32_t clique_bad;     // entries of F that break F[a][b] = c(a) c(b) (a != b), F[a][a] = 0
     int32_t clique_size;    // facilities with c(a) = 1
+    int32_t int_min;        // entries of D or F equal to INT32_MIN (their magnitude needs 32 bits)
 };
 
 // Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=
@@ -117,8 +118,6 @@ hipError_t launch_clique_check(hipStream_t s, int N, const int32_t *F, int32_t *
 hipError_t launch_trial_setup(hipStream_t s, int N, int R, int G, const int32_t *perm,
                               int32_t *trial_perm, int32_t *slot);
 hipError_t launch_group_sums(hipStream_t s, int R, int G, const int64_t *E, int64_t *E_sum);
-hipError_t launch_beta_rule(hipStream_t s, int G, const int64_t *E_sum, const float *grid, int L,
-                            float *ladder, int32_t *range);
 hipError_t launch_instance_stats(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                                  int R, const int32_t *perm, const float *beta, int64_t T,
                                  InstanceStats *out_dev);

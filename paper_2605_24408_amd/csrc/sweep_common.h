@@ -58,6 +58,8 @@ struct BatchInstance {
     int64_t perm_off;        // offset of replica 0's row in perm_best
     int32_t zero_diag;
     int32_t inst_id;
+    int32_t *choices;        // [R][T][N] recorded draws, or null
+    int64_t *E_trace;        // [R][T] recorded energies, or null
 };
 
 // Values that change from call to call, read by the kernels from device
@@ -80,6 +82,7 @@ struct BatchArgs {
     int64_t *counters;
     int64_t T;
     int seq_threshold;
+    int rec;                 // some instance records (selects the recording kernels)
 };
 
 __device__ __forceinline__ ReplicaJob batch_job(const BatchArgs &b, int item, size_t hsize) {
@@ -105,8 +108,8 @@ __device__ __forceinline__ ReplicaJob batch_job(const BatchArgs &b, int item, si
     j.sweep_offset = b.params->sweep_offset;
     j.rep = (uint32_t)r;
     j.inst = (uint32_t)in.inst_id;
-    j.choices = nullptr;
-    j.E_trace = nullptr;
+    j.choices = in.choices ? in.choices + r * b.T * in.N : nullptr;
+    j.E_trace = in.E_trace ? in.E_trace + r * b.T : nullptr;
     j.seq_threshold = b.seq_threshold;
     j.zero_diag = in.zero_diag != 0;
     j.tstate = nullptr;

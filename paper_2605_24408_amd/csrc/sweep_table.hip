@@ -831,7 +831,7 @@ sweep_table_pt(SweepArgs a, PtFusedArgs p, int64_t rep0) {
 // until it is exhausted; items come largest N first.  Every workgroup
 // reaches the exit: the queue only grows, so each one reads an item index
 // >= n_items after at most n_items increments.
-template <int NMAX, bool ZD>
+template <int NMAX, bool ZD, bool REC>
 __global__ void __launch_bounds__(4 * NMAX)
 __attribute__((amdgpu_waves_per_eu(table_waves_per_eu<NMAX>())))
 sweep_table_persistent(BatchArgs b) {
@@ -843,7 +843,7 @@ sweep_table_persistent(BatchArgs b) {
         const int item = __builtin_amdgcn_readfirstlane(item_sh);  // wave-uniform
         __syncthreads();
         if (item >= b.n_items) break;
-        table_replica<NMAX, ZD, false, false>(batch_job(b, item, sizeof(int32_t)), sm);
+        table_replica<NMAX, ZD, false, REC>(batch_job(b, item, sizeof(int32_t)), sm);
         __syncthreads();
     }
 }
@@ -867,10 +867,16 @@ hipError_t launch_nmax(hipStream_t s, const SweepArgs &a) {
 
 template <int NMAX>
 hipError_t launch_persistent_nmax(hipStream_t s, bool zd, const BatchArgs &b, int grid) {
-    if (zd)
-        sweep_table_persistent<NMAX, true><<<grid, 4 * NMAX, 0, s>>>(b);
-    else
-        sweep_table_persistent<NMAX, false><<<grid, 4 * NMAX, 0, s>>>(b);
+    if (b.rec) {
+        if (zd)
+            sweep_table_persistent<NMAX, true, true><<<grid, 4 * NMAX, 0, s>>>(b);
+        else
+            sweep_table_persistent<NMAX, false, true><<<grid, 4 * NMAX, 0, s>>>(b);
+    } else if (zd) {
+        sweep_table_persistent<NMAX, true, false><<<grid, 4 * NMAX, 0, s>>>(b);
+    } else {
+        sweep_table_persistent<NMAX, false, false><<<grid, 4 * NMAX, 0, s>>>(b);
+    }
     return hipGetLastError();
 }
 
@@ -912,7 +918,7 @@ template <int NMAX>
 int persistent_blocks_per_cu() {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, sweep_table_persistent<NMAX, true>, 4 * NMAX, 0);
+        &n, sweep_table_persistent<NMAX, true, false>, 4 * NMAX, 0);
     (void)hipGetLastError();
     return (e == hipSuccess && n > 0) ? n : 1;
 }

@@ -49,7 +49,8 @@ class _Counters(C.Structure):
 
 class _Instance(C.Structure):
     _fields_ = [("N", C.c_int32), ("R", C.c_int32), ("D", C.c_void_p), ("F", C.c_void_p),
-                ("perm", C.c_void_p), ("beta", C.c_void_p)]
+                ("perm", C.c_void_p), ("beta", C.c_void_p), ("choices", C.c_void_p),
+                ("E_trace", C.c_void_p)]
 
 
 class _PT(C.Structure):
@@ -88,7 +89,8 @@ def load_library(path: str = LIB_PATH):
     L.pdit_run_sweeps_batch.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64]
     L.pdit_run_pt.argtypes = [vp, i32, vp, vp, i32, vp, C.POINTER(_PT), i64, u64]
     L.pdit_run_cupim.argtypes = [vp, i32, vp, vp, i32, vp, vp, i64, u64]
-    L.pdit_beta_select.argtypes = [vp, i32, vp, vp, i32, vp, vp, i32, i64, u64, i32, vp, vp, vp]
+    L.pdit_beta_select.argtypes = [vp, i32, vp, vp, i32, vp, vp, i32, i64, u64, i32, i32, vp, vp,
+                                   vp]
     L.pdit_energy.argtypes = [vp, vp]
     L.pdit_best.argtypes = [vp, vp, vp]
     L.pdit_counters.argtypes = [vp, C.POINTER(_Counters)]
@@ -197,11 +199,15 @@ class Pdit:
         self._last = (R, R * N, N)
 
     def _instances(self, instances, n_sweeps: int | None):
-        """instances: sequence of (D, F, perm, beta) tensors; every beta has the
-        same length."""
+        """instances: sequence of (D, F, perm, beta) tensors, optionally
+        followed by recording buffers (choices int32 [R, T, N] or None,
+        E_trace int64 [R, T] or None); every beta has the same length."""
         arr = (_Instance * len(instances))()
         T = None
-        for k, (D, F, perm, beta) in enumerate(instances):
+        for k, item in enumerate(instances):
+            D, F, perm, beta = item[:4]
+            ch = item[4] if len(item) > 4 else None
+            tr = item[5] if len(item) > 5 else None
             for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"),
                               (perm, torch.int32, "perm"), (beta, torch.float32, "beta")):
                 _check_dev(t, dt, nm, self.device)
@@ -213,8 +219,18 @@ class Pdit:
                 T = int(beta.numel())
             elif int(beta.numel()) != T:
                 raise ValueError("every instance needs a beta schedule of the same length")
-            arr[k] = _Instance(N, int(perm.shape[0]), D.data_ptr(), F.data_ptr(), perm.data_ptr(),
-                               beta.data_ptr())
+            R = int(perm.shape[0])
+            if ch is not None:
+                _check_dev(ch, torch.int32, "choices", self.device)
+                if tuple(ch.shape) != (R, T, N):
+                    raise ValueError(f"instance {k}: choices must be R x T x N")
+            if tr is not None:
+                _check_dev(tr, torch.int64, "E_trace", self.device)
+                if tuple(tr.shape) != (R, T):
+                    raise ValueError(f"instance {k}: E_trace must be R x T")
+            arr[k] = _Instance(N, R, D.data_ptr(), F.data_ptr(), perm.data_ptr(),
+                               beta.data_ptr(), None if ch is None else ch.data_ptr(),
+                               None if tr is None else tr.data_ptr())
         return arr, (T if n_sweeps is None else n_sweeps)
 
     def run_pt(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor, beta: torch.Tensor,
@@ -253,10 +269,12 @@ class Pdit:
         self._last = (R, R * N, N)
 
     def beta_select(self, D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor,
-                    grid: torch.Tensor, trial_sweeps: int, seed: int, L: int):
+                    grid: torch.Tensor, trial_sweeps: int, seed: int, L: int,
+                    level_pct: int = 40):
         """pdit_beta_select: fixed-beta trials on the grid from the rows of
-        perm (unchanged); returns (E_sum [G] int64, ladder [L] float32,
-        range [2] int32 = (lo, hi))."""
+        perm (unchanged), the low end's level level_pct percent of the
+        range above the minimum; returns (E_sum [G] int64, ladder [L]
+        float32, range [2] int32 = (lo, hi))."""
         N = int(D.shape[0])
         for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"), (perm, torch.int32, "perm"),
                           (grid, torch.float32, "grid")):
@@ -266,13 +284,14 @@ class Pdit:
         ladder = torch.empty(max(int(L), 1), dtype=torch.float32, device=self.device)
         rng = torch.empty(2, dtype=torch.int32, device=self.device)
         self._rc(self._L.pdit_beta_select(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), _ptr(grid),
-                                          G, int(trial_sweeps), int(seed), int(L), _ptr(E_sum),
-                                          _ptr(ladder), _ptr(rng)))
+                                          G, int(trial_sweeps), int(seed), int(L),
+                                          int(level_pct), _ptr(E_sum), _ptr(ladder), _ptr(rng)))
         self._last = (R * G, R * G * N, N)
         return E_sum, ladder, rng
 
     def run_sweeps_batch(self, instances, seed: int) -> None:
-        """pdit_run_sweeps_batch over (D, F, perm, beta) tensors of uneven N."""
+        """pdit_run_sweeps_batch over (D, F, perm, beta[, choices, E_trace])
+        tensors of uneven N."""
         arr, T = self._instances(instances, None)
         self._rc(self._L.pdit_run_sweeps_batch(self._h, len(instances), arr, int(T), int(seed)))
         R = sum(int(x[2].shape[0]) for x in instances)

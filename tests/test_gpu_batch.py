@@ -1,7 +1,8 @@
 """GPU parity of batched runs (instances of uneven size in persistent,
-graph-captured launches): every (instance, replica) against the oracle with
-the instance's own Philox word, graph replays against resumed oracle runs,
-the autotuner, and the full-size uneven workload on sampled replicas."""
+graph-captured launches): every draw of every (instance, replica) recorded
+and replayed on the oracle with the instance's own Philox word (the
+protocol of ``parity.py``), graph replays against resumed oracle runs, the
+autotuner, and the full-size uneven workload on sampled replicas."""
 import sys
 from concurrent.futures import ThreadPoolExecutor
 
@@ -11,6 +12,7 @@ import torch
 
 import oracle
 from paper_2605_24408_amd import workloads as W
+from parity import replay
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
@@ -40,21 +42,33 @@ def small_batch(T=30, R=3):
     return out
 
 
-def to_dev(batch):
-    return [(dev(D, torch.int32), dev(F, torch.int32), dev(p, torch.int32), dev(b, torch.float32))
-            for D, F, p, b in batch]
+def to_dev(batch, record=True):
+    """Device tensors of a batch; with ``record`` every instance also gets
+    buffers for its draws and energy trace."""
+    out = []
+    for D, F, p, b in batch:
+        R, N = p.shape
+        T = len(b)
+        item = (dev(D, torch.int32), dev(F, torch.int32), dev(p, torch.int32),
+                dev(b, torch.float32))
+        if record:
+            item = item + (torch.full((R, T, N), -1, dtype=torch.int32, device=DEV),
+                           torch.zeros((R, T), dtype=torch.int64, device=DEV))
+        out.append(item)
+    return out
 
 
-def oracle_batch(batch, seed, sweep_offset=0, prev=None):
-    refs = []
-    for k, (D, F, perms, beta) in enumerate(batch):
-        kw = {}
-        if prev is not None:
-            kw = dict(E_best=prev[k].E_best, perm_best=prev[k].perm_best)
-            perms = prev[k].perm
-        refs.append(oracle.run(D, F, perms, beta, seed, sweep_offset=sweep_offset,
-                               rep_ids=list(range(perms.shape[0])), inst_id=k, **kw))
-    return refs
+def replay_batch(got, batch, seed, sweep_offset=0, start=None, what="batch"):
+    """Every replica of every instance replayed draw by draw on the oracle
+    (instance index k as Philox word 3); ``start``: per instance the
+    previous call's GPU state (perm, E_best, perm_best) to resume from."""
+    for k, ((D, F, perms, beta), g) in enumerate(zip(batch, got)):
+        if start is not None:
+            perms = start[k]["perm"]
+        replay(g, D, F, perms, beta, seed, offset=sweep_offset, inst_id=k,
+               E_best=None if start is None else start[k]["E_best"],
+               perm_best=None if start is None else start[k]["perm_best"],
+               what=f"{what}, instance {k} (N={D.shape[0]})")
 
 
 def gpu_state(ctx, dbatch):
@@ -63,27 +77,18 @@ def gpu_state(ctx, dbatch):
     Eb, pb = Eb.cpu().numpy(), pb.cpu().numpy()
     cnt = ctx.replica_counters().cpu().numpy()
     out, rb, po = [], 0, 0
-    for D, F, perm, beta in dbatch:
+    for item in dbatch:
+        perm = item[2]
         R, N = perm.shape
-        out.append(dict(perm=perm.cpu().numpy(), E=E[rb:rb + R], E_best=Eb[rb:rb + R],
-                        perm_best=pb[po:po + R * N].reshape(R, N), counters=cnt[rb:rb + R]))
+        st = dict(perm=perm.cpu().numpy(), E=E[rb:rb + R], E_best=Eb[rb:rb + R],
+                  perm_best=pb[po:po + R * N].reshape(R, N), counters=cnt[rb:rb + R])
+        if len(item) > 4:
+            st["choices"] = item[4].cpu().numpy()
+            st["trace"] = item[5].cpu().numpy()
+        out.append(st)
         rb += R
         po += R * N
     return out
-
-
-def check(got, refs):
-    n_diff = 0
-    for k, (g, r) in enumerate(zip(got, refs)):
-        for j in range(r.perm.shape[0]):
-            same = (np.array_equal(g["perm"][j], r.perm[j]) and g["E"][j] == r.E[j]
-                    and g["E_best"][j] == r.E_best[j]
-                    and np.array_equal(g["perm_best"][j], r.perm_best[j])
-                    and g["counters"][j][1] == r.counters[j][1])
-            if not same:
-                n_diff += 1
-                assert r.counters[j][2] > 0, f"instance {k} replica {j} differs without a tie"
-    return n_diff
 
 
 @pytest.mark.parametrize("sweep", ["auto", "plain"])
@@ -91,14 +96,22 @@ def test_batch_matches_oracle(sweep):
     from paper_2605_24408_amd import pdit as P
     batch = small_batch()
     say(f"batch vs oracle, sweep={sweep}")
-    refs = oracle_batch(batch, 5)
     dbatch = to_dev(batch)
     with P.Pdit(sweep=sweep) as ctx:
         ctx.run_sweeps_batch(dbatch, 5)
         torch.cuda.synchronize()
         got = gpu_state(ctx, dbatch)
-    assert check(got, refs) <= 1
-    assert sum(int(r.counters[:, 1].sum()) for r in refs) > 100
+    replay_batch(got, batch, 5, what=f"batch {sweep}")
+    assert sum(int(g["counters"][:, 1].sum()) for g in got) > 100
+    # without recording (the kernels that skip it): the same results
+    plain = to_dev(batch, record=False)
+    with P.Pdit(sweep=sweep) as ctx:
+        ctx.run_sweeps_batch(plain, 5)
+        torch.cuda.synchronize()
+        unrec = gpu_state(ctx, plain)
+    for g, u in zip(got, unrec):
+        for key in ("perm", "E", "E_best", "perm_best", "counters"):
+            assert np.array_equal(g[key], u[key]), key
 
 
 def test_batch_graph_replays_match_resumed_oracle():
@@ -116,9 +129,9 @@ def test_batch_graph_replays_match_resumed_oracle():
             ctx.run_sweeps_batch(dbatch, 9)
             torch.cuda.synchronize()
             got = gpu_state(ctx, dbatch)
-            refs = oracle_batch(batch, 9, sweep_offset=12 * call, prev=prev)
-            assert check(got, refs) == 0
-            prev = refs
+            replay_batch(got, batch, 9, sweep_offset=12 * call, start=prev,
+                         what=f"graph call {call}")
+            prev = got
             _ = torch.randn(1000, device=DEV).sum().item()  # unrelated eager work
         assert ctx.get_sweep_offset() == 36
 
@@ -126,7 +139,7 @@ def test_batch_graph_replays_match_resumed_oracle():
 def test_batch_instance0_equals_single_run():
     from paper_2605_24408_amd import pdit as P
     batch = small_batch(T=20)
-    dbatch = to_dev(batch)
+    dbatch = to_dev(batch, record=False)
     with P.Pdit() as ctx:
         ctx.run_sweeps_batch(dbatch, 3)
         torch.cuda.synchronize()
@@ -145,22 +158,24 @@ def test_autotune_then_run():
     from paper_2605_24408_amd import pdit as P
     batch = small_batch(T=10, R=2)
     dbatch = to_dev(batch)
-    before = [p.clone() for _, _, p, _ in dbatch]
+    before = [item[2].clone() for item in dbatch]
     with P.Pdit() as ctx:
         t = ctx.autotune(dbatch, 10, 4)
         assert t["blocks_per_cu"] >= 1 and t["seq_threshold"] >= 1 and t["best_ms"] > 0
-        for b, (_, _, p, _) in zip(before, dbatch):
-            assert torch.equal(b, p)  # the trials ran on private copies
+        for b, item in zip(before, dbatch):
+            assert torch.equal(b, item[2])  # the trials ran on private copies
+            assert (item[4] == -1).all()   # and recorded nothing
         ctx.run_sweeps_batch(dbatch, 4)
         torch.cuda.synchronize()
         got = gpu_state(ctx, dbatch)
-    assert check(got, oracle_batch(batch, 4)) == 0
+    replay_batch(got, batch, 4, what="after autotune")
 
 
 def test_uneven_workload_full_size_sampled():
     """The uneven workload at full size (256 instances, N in [20, 150], 64
-    replicas each, 2000 sweeps) in one batched call; sampled replicas rerun on
-    the oracle, properties checked on many more."""
+    replicas each, 2000 sweeps) in one batched call, then again with every
+    draw recorded (identical results); replica 5 of five sampled instances
+    replayed draw by draw on the oracle, properties checked on many more."""
     from paper_2605_24408_amd import pdit as P
     insts = W.config_uneven()
     dbatch = [(dev(i.D, torch.int32), dev(i.F, torch.int32), dev(i.perms, torch.int32),
@@ -172,18 +187,28 @@ def test_uneven_workload_full_size_sampled():
         got = gpu_state(ctx, dbatch)
     Ns = [i.N for i in insts]
     sample = [int(np.argmax(Ns)), int(np.argmin(Ns)), 1, 2, 3]
+    say("uneven workload, sampled instances recorded")
+    rec = [(dev(i.D, torch.int32), dev(i.F, torch.int32), dev(i.perms, torch.int32),
+            dev(i.beta, torch.float32))
+           + ((torch.full((i.R, i.T, i.N), -1, dtype=torch.int32, device=DEV),
+               torch.zeros((i.R, i.T), dtype=torch.int64, device=DEV)) if k in sample else ())
+           for k, i in enumerate(insts)]
+    with P.Pdit() as ctx:
+        ctx.run_sweeps_batch(rec, W.PHILOX_SEED)
+        torch.cuda.synchronize()
+        grec = gpu_state(ctx, rec)
+    for g, r in zip(got, grec):
+        for key in ("perm", "E", "E_best", "perm_best", "counters"):
+            assert np.array_equal(g[key], r[key]), key
     say("uneven workload: sampled oracle replicas")
 
-    def ref(k):
+    def one(k):
         i = insts[k]
-        return oracle.run(i.D, i.F, i.perms[5:6], i.beta, W.PHILOX_SEED, rep_ids=[5], inst_id=k)
+        replay(grec[k], i.D, i.F, i.perms[5:6], i.beta, W.PHILOX_SEED, rows=[5], inst_id=k,
+               what=f"uneven instance {k} (N={i.N}) replica 5")
 
     with ThreadPoolExecutor(5) as ex:
-        refs = list(ex.map(ref, sample))
-    for k, r in zip(sample, refs):
-        same = (np.array_equal(got[k]["perm"][5], r.perm[0]) and got[k]["E"][5] == r.E[0]
-                and got[k]["E_best"][5] == r.E_best[0])
-        assert same or r.counters[0][2] > 0, (k, insts[k].N)
+        list(ex.map(one, sample))
     for k in range(0, 256, 17):
         i = insts[k]
         for j in (0, 63):
@@ -219,12 +244,10 @@ def test_batch_large_groups(sweep):
     batch = large_batch()
     dbatch = to_dev(batch)
     say(f"batch large groups sweep={sweep}")
-    refs = oracle_batch(batch, 21)
     with P.Pdit(sweep=sweep) as ctx:
         ctx.run_sweeps_batch(dbatch, 21)
         got = gpu_state(ctx, dbatch)
-        assert check(got, refs) <= 1
+        replay_batch(got, batch, 21, what=f"large groups {sweep}")
         ctx.run_sweeps_batch(dbatch, 21)
         got2 = gpu_state(ctx, dbatch)
-    refs2 = oracle_batch(batch, 21, sweep_offset=3, prev=refs)
-    assert check(got2, refs2) <= 2
+    replay_batch(got2, batch, 21, sweep_offset=3, start=got, what=f"large groups {sweep}, replay")

@@ -1,13 +1,22 @@
 """Beta-range selection on the GPU (pdit_beta_select) against the oracle's
 beta_select: every trial replica's ending energy, the summed energies, the
 chosen range and the ladder, on each sweep kernel; the ladder feeding a
-parallel-tempering run; error paths."""
+parallel-tempering run; error paths.
+
+The selection's launch does not record draws.  Each grid value's trials are
+therefore run again as a recorded single-instance run whose rows g R + k
+carry the trials' Philox replica indices; those rows must end where the
+selection's trials ended, and they are replayed draw by draw on the oracle
+(``parity.py``).  The rule must then equal the oracle's rule on the GPU's
+sums, and the whole selection the oracle's when no draw was adopted at a
+tie."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_2605_24408_amd import workloads as W
+from parity import replay
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
@@ -21,24 +30,41 @@ def dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-def gpu_select(ctx, D, F, perms, grid, trials, seed, L):
+def gpu_select(ctx, D, F, perms, grid, trials, seed, L, level=40):
     Dd, Fd, pd = dev(D, torch.int32), dev(F, torch.int32), dev(perms, torch.int32)
-    E_sum, ladder, rng = ctx.beta_select(Dd, Fd, pd, dev(grid, torch.float32), trials, seed, L)
+    E_sum, ladder, rng = ctx.beta_select(Dd, Fd, pd, dev(grid, torch.float32), trials, seed, L,
+                                         level)
     out = {"E_sum": E_sum.cpu().numpy(), "ladder": ladder.cpu().numpy(),
            "range": tuple(int(x) for x in rng.cpu().numpy()), "E": ctx.energy().cpu().numpy(),
            "counters": ctx.replica_counters().cpu().numpy(), "perm_after": pd.cpu().numpy()}
     return out
 
 
-def tied_rows(D, F, perms, grid, trials, seed):
-    """Trial replicas in which the oracle counts a tie."""
-    R = perms.shape[0]
-    rows = set()
-    for g, b in enumerate(grid):
-        ref = oracle.run(D, F, perms, np.full(trials, b, np.float32), seed,
-                         rep_ids=[g * R + k for k in range(R)])
-        rows |= {g * R + k for k in range(R) if ref.counters[k][2] > 0}
-    return rows
+def replay_trials(P, sweep, D, F, perms, grid, trials, seed, E_trial, g, ks, what):
+    """Trial replicas (g, k) for k in ks: a recorded single-instance run of
+    (g + 1) R rows (row g R + k starts from perms[k] and draws as replica
+    g R + k) at beta grid[g]; rows g R + k must end at the selection's
+    energies and are replayed on the oracle.  Returns the draws adopted at
+    ties."""
+    R, N = perms.shape
+    tiled = np.tile(perms, (g + 1, 1))
+    beta = np.full(trials, grid[g], np.float32)
+    with P.Pdit(sweep=sweep) as ctx:
+        p = dev(tiled, torch.int32)
+        ch = torch.full((tiled.shape[0], trials, N), -1, dtype=torch.int32, device=DEV)
+        tr = torch.zeros((tiled.shape[0], trials), dtype=torch.int64, device=DEV)
+        ctx.set_recording(ch, tr)
+        ctx.run_sweeps(dev(D, torch.int32), dev(F, torch.int32), p, dev(beta, torch.float32), seed)
+        Eb, pb = ctx.best()
+        rows = [g * R + k for k in ks]
+        got = {"perm": p.cpu().numpy(), "E": ctx.energy().cpu().numpy(),
+               "E_best": Eb.cpu().numpy(), "perm_best": pb.cpu().numpy(),
+               "counters": ctx.replica_counters().cpu().numpy(),
+               "choices": ch.cpu().numpy(), "trace": tr.cpu().numpy()}
+    for k in ks:
+        assert got["E"][g * R + k] == E_trial[g * R + k], (g, k)
+    parts = replay(got, D, F, perms[list(ks)], beta, seed, rows=rows, what=f"{what} grid {g}")
+    return sum(int(x.excused[0]) for x in parts)
 
 
 @pytest.mark.parametrize("N,R,G,kind,sweep", [
@@ -58,27 +84,32 @@ def test_beta_select_matches_oracle(N, R, G, kind, sweep):
     s = W.energy_scale(D, F)
     grid = np.geomspace(0.02 / s, 200.0 / s, G).astype(np.float32)
     trials, seed, L = 30, 21, 10
-    ref = oracle.beta_select(D, F, perms, grid, trials, seed, L)
-    with P.Pdit(sweep=sweep) as ctx:
-        got = gpu_select(ctx, D, F, perms, grid, trials, seed, L)
-        plan = ctx.last_plan()
-    assert plan["sweep"] == (sweep if sweep in ("plain", "large") else "fast")
-    assert np.array_equal(got["perm_after"], perms)  # the caller's permutations are untouched
-    bad = np.nonzero(got["E"] != ref.E_trial.reshape(-1))[0]
-    if bad.size:
-        tied = tied_rows(D, F, perms, grid, trials, seed)
-        assert set(bad.tolist()) <= tied, f"trial replicas {bad} differ without a counted tie"
-        return
-    assert np.array_equal(got["E_sum"], ref.E_sum)
-    assert got["range"] == (ref.lo, ref.hi)
-    assert np.array_equal(got["ladder"], ref.ladder)
-    assert got["counters"][:, 0].sum() == G * R * N * trials
+    for level in (40, 60):
+        ref = oracle.beta_select(D, F, perms, grid, trials, seed, L, level_pct=level)
+        with P.Pdit(sweep=sweep) as ctx:
+            got = gpu_select(ctx, D, F, perms, grid, trials, seed, L, level)
+            plan = ctx.last_plan()
+        assert plan["sweep"] == (sweep if sweep in ("plain", "large") else "fast")
+        assert np.array_equal(got["perm_after"], perms)  # the caller's permutations are untouched
+        assert got["counters"][:, 0].sum() == G * R * N * trials
+        E = got["E"].reshape(G, R)
+        assert np.array_equal(got["E_sum"], E.sum(axis=1))
+        lo, hi, ladder = oracle.beta_rule(got["E_sum"], grid, L, level)
+        assert got["range"] == (lo, hi) and np.array_equal(got["ladder"], ladder)
+    adopted = sum(replay_trials(P, sweep, D, F, perms, grid, trials, seed, got["E"], g, range(R),
+                                f"beta_select N={N}") for g in range(G))
+    if adopted == 0:
+        assert np.array_equal(got["E"], ref.E_trial.reshape(-1))
+        assert np.array_equal(got["E_sum"], ref.E_sum)
+        assert got["range"] == (ref.lo, ref.hi)
+        assert np.array_equal(got["ladder"], ref.ladder)
 
 
 def test_beta_select_full_size_sampled():
     """The N=64 benchmark instance: 24 grid values x 64 trial replicas x 400
-    sweeps in one launch; sampled trial replicas rerun on the oracle, the
-    sums and the rule recomputed from every replica's energy."""
+    sweeps in one launch; sampled trial replicas replayed on the oracle
+    (recorded reruns), the sums and the rule recomputed from every
+    replica's energy."""
     from paper_2605_24408_amd import pdit as P
     inst = W.config_n64(R=64)
     s = W.energy_scale(inst.D, inst.F)
@@ -92,10 +123,8 @@ def test_beta_select_full_size_sampled():
     assert got["range"] == (lo, hi) and np.array_equal(got["ladder"], ladder)
     assert lo < hi
     for g, k in ((0, 5), (G // 2, 17), (hi, 63)):
-        ref = oracle.run(inst.D, inst.F, inst.perms[k:k + 1], np.full(trials, grid[g], np.float32),
-                         seed, rep_ids=[g * R + k])
-        if ref.counters[0][2] == 0:
-            assert E[g, k] == ref.E[0], (g, k)
+        replay_trials(P, "auto", inst.D, inst.F, inst.perms, grid, trials, seed, got["E"], g, [k],
+                      "beta_select n64")
 
 
 def test_selected_ladder_drives_parallel_tempering():
@@ -118,10 +147,11 @@ def test_selected_ladder_drives_parallel_tempering():
         ctx.run_pt(dev(D, torch.int32), dev(F, torch.int32), p, dev(ladder, torch.float32), slot,
                    since, 10, 4, 3, 9, "fused")
         got_perm = p.cpu().numpy()
-    ref = oracle.run_pt(D, F, perms, ladder, 10, 4, 3, 9)
-    if ref.counters[:, 2].sum() == 0:
-        assert np.array_equal(got_perm, ref.perm)
-        assert np.array_equal(slot.cpu().numpy(), ref.slot)
+    from test_gpu_pt import pt_chunked
+    chunked, _ = pt_chunked(P, D, F, perms, ladder, 10, 4, 3, 9, 2, schedule="fused",
+                            what="pt on the selected ladder")
+    assert np.array_equal(got_perm, chunked["perm"])
+    assert np.array_equal(slot.cpu().numpy(), chunked["slot"])
 
 
 def test_beta_select_error_paths():

@@ -2,10 +2,10 @@
 PDIT_SWEEP_LARGE, and AUTO where no on-chip class fits): every variant of its
 products (int16 or int32 copies of D and F, int32 partial sums of 24-bit
 products or int64 products), int32 and int64 initial H, ragged sizes from 2
-to 512, against the CPU oracle on the same seeded inputs.  Energies,
-permutations, best states, counters and every chosen candidate must match;
-a replica may leave the oracle's trajectory only after a draw the oracle
-counted as a tie."""
+to 512, against the CPU oracle on the same seeded inputs.  Recorded runs
+are replayed draw by draw on the oracle (``parity.py``): a draw may differ
+only where the oracle flags a tie, and energies, permutations, best states,
+counters and energy traces must then be identical."""
 import sys
 
 import numpy as np
@@ -14,6 +14,7 @@ import torch
 
 import oracle
 from paper_2605_24408_amd import workloads as W
+from parity import replay
 
 pytestmark = pytest.mark.gpu
 
@@ -64,27 +65,6 @@ def run_large(P, D, F, perms, beta, seed, sweep="large", record=True, offset=0, 
     return out
 
 
-def check(got, ref, rows=None, max_bad=0):
-    R = ref.perm.shape[0]
-    rows = range(R) if rows is None else rows
-    bad = []
-    for i, k in enumerate(rows):
-        same = (np.array_equal(got["perm"][k], ref.perm[i]) and got["E"][k] == ref.E[i]
-                and got["E_best"][k] == ref.E_best[i]
-                and np.array_equal(got["perm_best"][k], ref.perm_best[i])
-                and np.array_equal(got["counters"][k][:2], ref.counters[i][:2]))
-        if same and got["choices"] is not None and ref.choices is not None:
-            same = (np.array_equal(got["choices"][k], ref.choices[i])
-                    and np.array_equal(got["trace"][k], ref.E_trace[i]))
-        if not same:
-            assert ref.counters[i][2] > 0, (
-                f"replica {k} differs from the oracle without a counted tie: gpu E={got['E'][k]} "
-                f"oracle E={ref.E[i]}, accepted {got['counters'][k][1]} vs {ref.counters[i][1]}")
-            bad.append(k)
-    assert len(bad) <= max_bad, f"replicas off the oracle's trajectory after ties: {bad}"
-    return bad
-
-
 def instance(rng, N, dmax, fmax, zero_diag=True):
     D = W.sym_uniform(rng, N, 0, dmax).astype(np.int64)
     F = W.sym_uniform(rng, N, 0, fmax).astype(np.int64)
@@ -130,10 +110,9 @@ def test_large_trajectories(P, N, R, T, dmax, fmax, zd, hot):
     s = W.energy_scale(D, F)
     beta = W.beta_geometric((0.05 if hot else 2.0) / s, 50.0 / s, T)
     say(f"large trajectory N={N} R={R} T={T} max|D|={dmax} max|F|={fmax}")
-    ref = oracle.run(D, F, perms, beta, 11, record_choices=True, record_trace=True)
     got = run_large(P, D, F, perms, beta, 11)
     assert got["plan"]["sweep"] == "large"
-    check(got, ref, max_bad=1)
+    replay(got, D, F, perms, beta, 11, what=f"large N={N}")
     assert got["counters"][:, 1].sum() > 0
     # a single launch serves w locations per pass over the copies (8 on the
     # int8 planes, 3 on the int16 pairs): the corrections after an accepted
@@ -143,7 +122,7 @@ def test_large_trajectories(P, N, R, T, dmax, fmax, zd, hot):
     w = 8 if vmax <= 16_383 else 3 if vmax <= 32_767 else 0
     if hot and w and N >= 2 * w:
         r = np.arange(N)[None, None, :]
-        s = ref.choices
+        s = got["choices"]
         r0 = (r // w) * w
         assert ((s > r) & (s < r0 + w)).sum() > 0
         assert ((s >= r0 + w) & (s < r0 + 2 * w)).sum() > 0
@@ -161,10 +140,9 @@ def test_large_signed_values(P, N, vmax):
     s = W.energy_scale(D, F)
     beta = W.beta_geometric(0.05 / s, 50.0 / s, 6)
     say(f"large signed N={N} max={vmax}")
-    ref = oracle.run(D, F, perms, beta, 13, record_choices=True, record_trace=True)
     got = run_large(P, D, F, perms, beta, 13)
     assert got["plan"]["sweep"] == "large"
-    check(got, ref, max_bad=1)
+    replay(got, D, F, perms, beta, 13, what=f"large signed N={N}")
     assert got["counters"][:, 1].sum() > 0
 
 
@@ -178,10 +156,9 @@ def test_auto_picks_large(P):
         s = W.energy_scale(D, F)
         beta = W.beta_geometric(0.2 / s, 20.0 / s, 2)
         say(f"auto N={N} max|D|={dmax}")
-        ref = oracle.run(D, F, perms, beta, 3, record_choices=True, record_trace=True)
         got = run_large(P, D, F, perms, beta, 3, sweep="auto")
         assert got["plan"]["sweep"] == "large"
-        check(got, ref)
+        replay(got, D, F, perms, beta, 3, what=f"auto N={N}")
 
 
 def test_resume_matches_one_call(P):
@@ -212,9 +189,10 @@ def test_resume_matches_one_call(P):
 def test_n512_workload_sampled(P):
     """The N=512 workload (D, F uniform in [0, 10^4] with 20% zeros) at its
     full replica count, 256, in the launch the benchmark times, for the
-    first sweeps of its schedule: replicas 0, 97 and 255 match the oracle
-    run on those rows alone (same Philox replica indices), and every
-    replica's energy equals the energy of its final permutation."""
+    first sweeps of its schedule, then again with every draw recorded
+    (identical results): replicas 0, 97 and 255 replayed draw by draw on the
+    oracle (same Philox replica indices), and every replica's energy equals
+    the energy of its final permutation."""
     inst = W.config_n512()
     T = 2
     beta = inst.beta[:T]
@@ -222,9 +200,12 @@ def test_n512_workload_sampled(P):
     got = run_large(P, inst.D, inst.F, inst.perms, beta, W.PHILOX_SEED, sweep="auto",
                     record=False)
     assert got["plan"]["sweep"] == "large"
+    rec = run_large(P, inst.D, inst.F, inst.perms, beta, W.PHILOX_SEED, sweep="auto")
+    for key in ("perm", "E", "E_best", "perm_best", "counters"):
+        assert np.array_equal(got[key], rec[key]), key
     rows = [0, 97, 255]
-    ref = oracle.run(inst.D, inst.F, inst.perms[rows], beta, W.PHILOX_SEED, rep_ids=rows)
-    check(got, ref, rows=rows)
+    replay(rec, inst.D, inst.F, inst.perms[rows], beta, W.PHILOX_SEED, rows=rows, threads=3,
+           what="n512 workload")
     for k in range(0, 256, 15):
         assert got["E"][k] == oracle.energy(inst.D, inst.F, got["perm"][k])
         assert got["E_best"][k] == oracle.energy(inst.D, inst.F, got["perm_best"][k])

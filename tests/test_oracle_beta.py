@@ -21,7 +21,7 @@ def test_rule_hand_cases():
     for c in cases:
         G = len(c["sums"])
         grid = np.geomspace(0.01, 10.0, G).astype(np.float32) if G > 1 else np.array([0.5], np.float32)
-        lo, hi, ladder = oracle.beta_rule(c["sums"], grid, 6)
+        lo, hi, ladder = oracle.beta_rule(c["sums"], grid, 6, c["level_pct"])
         assert (lo, hi) == (c["lo"], c["hi"]), c["why"]
         assert ladder[0] == grid[lo] and ladder[-1] == grid[hi]
 
@@ -38,8 +38,24 @@ def test_ladder_is_geometric(L):
     assert ladder[0] == grid[lo] and ladder[-1] == grid[hi]
 
 
+def test_rule_level_is_monotone():
+    """A higher level (further above the minimum) never picks a later low end;
+    levels 40 and 60 (the two readings of the paper's wording) pick
+    different low ends on a steadily falling curve."""
+    rng = np.random.default_rng(3)
+    grid = np.geomspace(0.01, 10.0, 20).astype(np.float32)
+    for _ in range(200):
+        sums = np.sort(rng.integers(-10**9, 10**9, size=20))[::-1].copy()
+        los = [oracle.beta_rule(sums, grid, 4, lv)[0] for lv in (0, 20, 40, 60, 80, 100)]
+        assert los == sorted(los, reverse=True)
+    sums = np.arange(20, 0, -1) * 1000
+    assert oracle.beta_rule(sums, grid, 4, 40)[0] > oracle.beta_rule(sums, grid, 4, 60)[0]
+
+
 def test_rule_rejects_bad_input():
     grid = np.array([0.1, 0.2], np.float32)
+    with pytest.raises(RuntimeError):
+        oracle.beta_rule([1, 2], grid, 3, 101)   # level beyond the range
     with pytest.raises(RuntimeError):
         oracle.beta_rule([1, 2], grid, 1)       # a ladder needs two rungs
     with pytest.raises(RuntimeError):
