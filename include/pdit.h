@@ -412,6 +412,45 @@ int pdit_last_plan(pdit_t *ctx, int *sweep, int *size_class, int *recompute);
 int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t seed,
                          uint32_t *out);
 
+/* Size of the device work space of pdit_run_sweeps_noalloc, per GPU. */
+#define PDIT_NOALLOC_SCRATCH_BYTES (64 << 20)
+
+/*
+ * pdit_run_sweeps for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid hipMalloc, code that must not grow the
+ * device heap): no context, no hipMalloc, hipFree or allocating library
+ * call.  The same sweeps, kernels and results as pdit_run_sweeps with the
+ * given options (recording is not available).
+ *
+ * Work space: a device array of PDIT_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs this call on, until the process ends.  It
+ * holds the instance summary, the clique membership, the copies of D and F
+ * of the kernel without a stored H (up to 4 MiB) and the initial H of every
+ * replica (R N^2 int32, or int64 when the bound on |H| needs it); a run
+ * that needs more returns PDIT_ENOMEM with a message.  Every call on a GPU
+ * uses that GPU's one array (and one host copy of the instance summary), so
+ * calls that overlap on one GPU, from two host threads or on two streams,
+ * race: serialise them.  Nothing in the array needs clearing between calls.
+ *
+ *   opts       device, stream, sweep, recompute and seq_threshold as for
+ *              pdit_create (NULL: the defaults); blocks_per_cu is unused
+ *   N, D, F, R, perm, beta, n_sweeps, seed   as for pdit_run_sweeps
+ *   sweep_offset  global index of the first sweep (Philox counter word 1)
+ *   init_best  nonzero: E_best and perm_best start from the initial state;
+ *              zero: they hold a previous best state and are updated
+ *   E          device int64 R, out: energies of the final permutations
+ *   E_best     device int64 R, in/out;  perm_best: device int32 R x N, in/out
+ *   counters   device int64 R x 3, out: (updates, accepted, ties) per replica
+ *   err        optional host buffer of err_len bytes: the error message
+ * Validation synchronises the stream once, as in pdit_run_sweeps; the
+ * sweeps then run asynchronously on the stream.
+ */
+int pdit_run_sweeps_noalloc(const pdit_opts *opts, int32_t N, const int32_t *D, const int32_t *F,
+                            int32_t R, int32_t *perm, const float *beta, int64_t n_sweeps,
+                            uint64_t seed, uint64_t sweep_offset, int init_best, int64_t *E,
+                            int64_t *E_best, int32_t *perm_best, int64_t *counters, char *err,
+                            int32_t err_len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 
 #include "pdit_internal.h"
@@ -33,8 +34,17 @@ int fail_hip(pdit_t *ctx, hipError_t e, const char *where) {
         if (e_ != hipSuccess) return fail_hip(ctx, e_, #expr); \
     } while (0)
 
+// The step timers; a context made by the no-allocation entry point has none.
+hipError_t record_event(pdit_t *ctx, int i) {
+    return ctx->ev[i] ? hipEventRecord(ctx->ev[i], ctx->stream) : hipSuccess;
+}
+
 int ensure(pdit_t *ctx, pdit::DeviceBuffer &b, size_t bytes) {
     if (b.bytes >= bytes && b.ptr) return PDIT_OK;
+    if (ctx->noalloc)
+        return fail(ctx, PDIT_ENOMEM,
+                    "the run needs more device memory than the no-allocation scratch holds "
+                    "(PDIT_NOALLOC_SCRATCH_BYTES)");
     if (b.ptr) {
         PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
         PDIT_HIP(ctx, hipFree(b.ptr));
@@ -66,6 +76,10 @@ void free_state(pdit::ReplicaState &s) {
 int shape_state(pdit_t *ctx, const std::vector<int32_t> &Ns, const std::vector<int32_t> &Rs,
                 bool *fresh) {
     pdit::ReplicaState &s = ctx->st;
+    if (ctx->noalloc) {  // the caller's output buffers, set up for this one run
+        *fresh = !s.best_valid;
+        return PDIT_OK;
+    }
     const bool same = s.E && s.Ns == Ns && s.Rs == Rs;
     if (!same) {
         PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -278,10 +292,10 @@ int run_clique(pdit_t *ctx, int32_t N, const int32_t *D, int32_t R, int32_t *per
     a.choices = ctx->rec_choices;
     a.E_trace = ctx->rec_trace;
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     PDIT_HIP(ctx, pdit::launch_sweep_clique(ctx->stream, a));
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     ctx->timed = true;
     ctx->rec_choices = nullptr;
     ctx->rec_trace = nullptr;
@@ -359,7 +373,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     pdit::ReplicaState &S = ctx->st;
 
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
     PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
     pdit::LargeCopies lcopy;
     if (use_large)
@@ -391,7 +405,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     a.E_trace = ctx->rec_trace;
     a.seq_threshold = ctx->opts.seq_threshold;
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     if (n_sweeps > 0) {
         if (use_fast)
             PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
@@ -400,9 +414,9 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
         else
             PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
     } else {
-        PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * R, ctx->stream));
+        PDIT_HIP(ctx, pdit::launch_zero_i64(ctx->stream, S.counters, 3 * (int64_t)R));
     }
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     ctx->timed = true;
     ctx->rec_choices = nullptr;
     ctx->rec_trace = nullptr;
@@ -446,8 +460,8 @@ int run_pt_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int
     c.inst_id = 0;
     c.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     // with no period, one launch of no iterations still yields E and zero counters
     const int64_t launches = n_periods > 0 ? n_periods : 1;
     for (int64_t per = 0; per < launches; ++per) {
@@ -460,7 +474,7 @@ int run_pt_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int
             PDIT_HIP(ctx, pdit::launch_pt_exchange(ctx->stream, R / pt->L, pt->L, S.E, pt->slot,
                                                    pt->since_top, pt->timeout));
     }
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     ctx->timed = true;
     ctx->sweep_offset += (uint64_t)(n_periods * pt->period_sweeps);
     ctx->last_updates = (int64_t)R * N * n_periods * pt->period_sweeps;
@@ -550,7 +564,7 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     pdit::ReplicaState &S = ctx->st;
 
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
     PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
     pdit::LargeCopies lcopy;
     if (use_large)
@@ -581,7 +595,7 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     a.seq_threshold = ctx->opts.seq_threshold;
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     a.tstate = table ? (int32_t *)ctx->tstate.ptr : nullptr;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     if (!fused && (pt->period_sweeps == 0 || n_periods == 0))
         PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * R, ctx->stream));
     if (fused) {
@@ -625,7 +639,7 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
         PDIT_HIP(ctx, pdit::launch_pt_exchange(ctx->stream, R / pt->L, pt->L, S.E, pt->slot,
                                                pt->since_top, pt->timeout));
     }
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     ctx->timed = true;
     if (fused) {
         PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -684,10 +698,10 @@ int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, i
     c.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     c.init_best = fresh ? 1 : 0;
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     PDIT_HIP(ctx, pdit::launch_cupim(ctx->stream, cls, c));
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     ctx->timed = true;
     ctx->sweep_offset += (uint64_t)n_sweeps;
     ctx->last_updates = (int64_t)R * N * n_sweeps;
@@ -764,7 +778,7 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     pdit::ReplicaState &S = ctx->st;
 
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
     PDIT_HIP(ctx, pdit::launch_trial_setup(ctx->stream, N, R, G, perm, tperm, tslot));
     PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, RT, tperm, ctx->h_buf.ptr, h64, S.E));
     pdit::LargeCopies lcopy;
@@ -794,7 +808,7 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     a.inst_id = 0;
     a.seq_threshold = ctx->opts.seq_threshold;
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     if (trial_sweeps > 0) {
         if (use_fast)
             PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
@@ -805,7 +819,7 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     } else {
         PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * RT, ctx->stream));
     }
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     PDIT_HIP(ctx, pdit::launch_group_sums(ctx->stream, R, G, S.E, E_sum));
     ctx->timed = true;
     // the rule on the G sums, on the host: integers compared exactly in 128
@@ -978,7 +992,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
 
     // ---- H recompute and fresh best state ----
     ctx->timed = false;
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 0));
     for (int k = 0; k < n_inst; ++k)
         PDIT_HIP(ctx, run_recompute(ctx, plan[k].mode, inst[k].N, inst[k].D, inst[k].F, inst[k].R,
                                     inst[k].perm, (char *)ctx->h_buf.ptr + plan[k].hoff,
@@ -998,7 +1012,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                                          sizeof(int32_t) * (size_t)inst[k].R * inst[k].N,
                                          hipMemcpyDeviceToDevice, ctx->stream));
     }
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 1));
 
     if (n_sweeps > 0) {
         // ---- groups of work items: (kernel, size class, diagonal mode), largest N first ----
@@ -1129,7 +1143,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     } else {
         PDIT_HIP(ctx, hipMemsetAsync(S.counters, 0, sizeof(int64_t) * 3 * S.R_total, ctx->stream));
     }
-    PDIT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    PDIT_HIP(ctx, record_event(ctx, 2));
     ctx->timed = true;
     ctx->sweep_offset += (uint64_t)n_sweeps;
     ctx->last_updates = 0;
@@ -1384,6 +1398,111 @@ int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t s
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
     PDIT_HIP(ctx, pdit::launch_debug_uniform24(ctx->stream, M, ctr, seed, out));
     return PDIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The no-allocation variant of pdit_run_sweeps.  Its device work space (the
+// instance summary, the clique membership, the large kernel's copies and the
+// initial H) lives in `scratch`, a file-scope device array that each GPU the
+// library runs on holds until the process ends; host code reaches it only
+// through the per-device address hipGetSymbolAddress returns.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kNoAllocScratch = (size_t)PDIT_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kNoAllocStats = 4096;             // instance summary
+constexpr size_t kNoAllocClique = 4096;            // clique membership, N <= 512 words
+constexpr size_t kNoAllocCopies = (size_t)4 << 20;  // large kernel copies, any N <= 512
+constexpr int kNoAllocDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::atomic<void *> g_scratch_addr[kNoAllocDevices];
+InstanceStats g_noalloc_stats[kNoAllocDevices];  // host copies of the summary
+
+// Address of `scratch` on the current device (looked up once per device).
+hipError_t noalloc_scratch(int device, void **out) {
+    void *p = g_scratch_addr[device].load(std::memory_order_acquire);
+    if (!p) {
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return hipSuccess;
+}
+
+void copy_error(const char *msg, char *err, int32_t err_len) {
+    if (!err || err_len < 1) return;
+    snprintf(err, (size_t)err_len, "%s", msg);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdit_run_sweeps_noalloc(const pdit_opts *opts, int32_t N, const int32_t *D, const int32_t *F,
+                            int32_t R, int32_t *perm, const float *beta, int64_t n_sweeps,
+                            uint64_t seed, uint64_t sweep_offset, int init_best, int64_t *E,
+                            int64_t *E_best, int32_t *perm_best, int64_t *counters, char *err,
+                            int32_t err_len) {
+    copy_error("", err, err_len);
+    pdit_opts o;
+    if (opts)
+        o = *opts;
+    else
+        pdit_default_opts(&o);
+    if (!E || !E_best || !perm_best || !counters) {
+        copy_error("null output pointer", err, err_len);
+        return PDIT_EINVAL;
+    }
+    if (o.device < 0 || o.device >= kNoAllocDevices) {
+        copy_error("device ordinal outside the supported range", err, err_len);
+        return PDIT_EINVAL;
+    }
+    if (hipSetDevice(o.device) != hipSuccess) {
+        (void)hipGetLastError();
+        copy_error("hipSetDevice failed", err, err_len);
+        return PDIT_EDEVICE;
+    }
+    void *base = nullptr;
+    const hipError_t se = noalloc_scratch(o.device, &base);
+    if (se != hipSuccess) {
+        (void)hipGetLastError();
+        copy_error("hipGetSymbolAddress of the scratch array failed", err, err_len);
+        return PDIT_EDEVICE;
+    }
+    pdit_ctx c;
+    c.opts = o;
+    c.stream = (hipStream_t)o.stream;
+    c.noalloc = true;
+    c.sweep_offset = sweep_offset;
+    c.stats_host = &g_noalloc_stats[o.device];
+    char *b = (char *)base;
+    c.scratch = {b, kNoAllocStats};
+    c.clique_buf = {b + kNoAllocStats, kNoAllocClique};
+    c.large_buf = {b + kNoAllocStats + kNoAllocClique, kNoAllocCopies};
+    const size_t used = kNoAllocStats + kNoAllocClique + kNoAllocCopies;
+    c.h_buf = {b + used, kNoAllocScratch - used};
+    pdit::ReplicaState &S = c.st;
+    S.n_inst = 1;
+    S.Ns = {N};
+    S.Rs = {R};
+    S.R_total = R;
+    S.perm_total = (int64_t)R * N;
+    S.E = E;
+    S.E_best = E_best;
+    S.perm_best = perm_best;
+    S.counters = counters;
+    S.best_valid = init_best == 0;
+    const int rc = pdit_run_sweeps(&c, N, D, F, R, perm, beta, n_sweeps, seed);
+    copy_error(c.last_error.c_str(), err, err_len);
+    // the context borrowed every buffer: nothing to free
+    S.E = S.E_best = S.counters = nullptr;
+    S.perm_best = nullptr;
+    return rc;
 }
 
 }  // extern "C"

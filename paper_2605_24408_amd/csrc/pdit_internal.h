@@ -97,6 +97,7 @@ struct pdit_ctx {
     std::vector<char> graph_sig;                      // what the captured graph was built for
     int num_cus = 0;
     int last_sweep = 0, last_class = 0, last_mode = 0;  // plan of the last single-instance run
+    bool noalloc = false;  // borrowed buffers only (pdit_run_sweeps_noalloc): never allocate
 };
 
 namespace pdit {
@@ -109,6 +110,8 @@ hipError_t launch_pt_check(hipStream_t s, int n_sets, int L, const int32_t *slot
 hipError_t launch_pt_exchange(hipStream_t s, int n_sets, int L, const int64_t *E, int32_t *slot,
                               int32_t *since_top, int32_t timeout);
 hipError_t launch_grid_check(hipStream_t s, int G, const float *grid, InstanceStats *out);
+// out[0 .. n-1] = 0 by a kernel (no memset node in code a caller may capture)
+hipError_t launch_zero_i64(hipStream_t s, int64_t *out, int64_t n);
 // clique flows: member[a] = c(a) (facility a has a nonzero flow), and the
 // count of entries of F that break F = c c^T off the diagonal, 0 on it
 hipError_t launch_clique_check(hipStream_t s, int N, const int32_t *F, int32_t *member,

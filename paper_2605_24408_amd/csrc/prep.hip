@@ -169,6 +169,21 @@ hipError_t launch_clique_check(hipStream_t st, int N, const int32_t *F, int32_t 
     return hipGetLastError();
 }
 
+namespace {
+__global__ void zero_i64_kernel(int64_t *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = 0;
+}
+}  // namespace
+
+hipError_t launch_zero_i64(hipStream_t s, int64_t *out, int64_t n) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    zero_i64_kernel<<<(int)(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_instance_stats(hipStream_t st, int N, const int32_t *D, const int32_t *F,
                                  int R, const int32_t *perm, const float *beta, int64_t T,
                                  InstanceStats *out) {

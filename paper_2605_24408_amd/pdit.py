@@ -67,7 +67,7 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
            "pdit_last_timing", "pdit_autotune", "pdit_last_plan", "pdit_run_pt",
-           "pdit_beta_select", "pdit_run_cupim"]
+           "pdit_beta_select", "pdit_run_cupim", "pdit_run_sweeps_noalloc"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH):
     L.pdit_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.pdit_autotune.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64, C.POINTER(_Tuning)]
     L.pdit_last_plan.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.pdit_run_sweeps_noalloc.argtypes = [C.POINTER(_Opts), i32, vp, vp, i32, vp, vp, i64, u64,
+                                          u64, C.c_int, vp, vp, vp, vp, C.c_char_p, i32]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("pdit_default_opts", "pdit_last_error"):
@@ -130,6 +132,47 @@ def _check_dev(t: torch.Tensor, dtype, name: str, device: torch.device):
         raise ValueError(f"{name} must live on {device}, got {t.device}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def run_sweeps_noalloc(D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor, beta: torch.Tensor,
+                       seed: int, sweep_offset: int, E: torch.Tensor, E_best: torch.Tensor,
+                       perm_best: torch.Tensor, counters: torch.Tensor, init_best: bool = True,
+                       stream: torch.cuda.Stream | None = None, sweep: str = "auto",
+                       recompute: str = "auto", seq_threshold: int = -1) -> None:
+    """pdit_run_sweeps_noalloc: the sweeps of ``Pdit.run_sweeps`` with the
+    library's static device scratch instead of a context's buffers; the
+    caller's E [R], E_best [R], perm_best [R, N] and counters [R, 3]
+    receive the results (E_best and perm_best in/out unless init_best)."""
+    L = load_library()
+    device = perm.device
+    N = int(D.shape[0])
+    R = int(perm.shape[0])
+    for t, dt, nm in ((D, torch.int32, "D"), (F, torch.int32, "F"), (perm, torch.int32, "perm"),
+                      (beta, torch.float32, "beta"), (E, torch.int64, "E"),
+                      (E_best, torch.int64, "E_best"), (perm_best, torch.int32, "perm_best"),
+                      (counters, torch.int64, "counters")):
+        _check_dev(t, dt, nm, device)
+    if tuple(D.shape) != (N, N) or tuple(F.shape) != (N, N) or tuple(perm.shape) != (R, N):
+        raise ValueError("D and F must be N x N and perm R x N")
+    if (tuple(E.shape) != (R,) or tuple(E_best.shape) != (R,) or tuple(perm_best.shape) != (R, N)
+            or tuple(counters.shape) != (R, 3)):
+        raise ValueError("outputs must be E [R], E_best [R], perm_best [R, N], counters [R, 3]")
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    o = _Opts()
+    L.pdit_default_opts(C.byref(o))
+    o.device = device.index or 0
+    o.stream = stream.cuda_stream
+    o.recompute = RECOMPUTE[recompute]
+    o.sweep = SWEEP[sweep]
+    o.seq_threshold = seq_threshold
+    err = C.create_string_buffer(256)
+    rc = L.pdit_run_sweeps_noalloc(C.byref(o), N, _ptr(D), _ptr(F), R, _ptr(perm), _ptr(beta),
+                                   int(beta.numel()), int(seed), int(sweep_offset),
+                                   int(bool(init_best)), _ptr(E), _ptr(E_best), _ptr(perm_best),
+                                   _ptr(counters), err, 256)
+    if rc != PDIT_OK:
+        raise PditError(rc, err.value.decode())
 
 
 class Pdit:
