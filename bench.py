@@ -2,19 +2,26 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload: the N=64 QAP (D and F symmetric, zero diagonal, uniform integers in
-[0, 99]; 1024 replicas from random permutations; 10^4 sweeps with geometric
-beta 0.001 -> 1.0).  One step is the whole hot path on that batch: input
-validation and width selection, the H recompute (int8 MFMA), 10^4 sweeps of
-the fast kernel, and the read-out of energies and best states.  Every step
-restarts from the same initial permutations and sweep offset, so all steps
-do identical work.
+Workload: the N=256 QAP (D = rounded Euclidean distances of 256 uniform
+points in [0, 100]^2, F symmetric 0/1 at density 0.1, zero diagonals; 512
+replicas from random permutations; 10^5 sweeps of a geometric beta schedule
+from 0.5/s to 2000/s, s the instance's RMS swap change).  The schedule is cut
+into slices of --slice sweeps (default 5000, 20 slices); one step is one
+slice of the whole hot path on the 512 replicas: validation and width
+selection, the exact H recompute (bf16 MFMA), the slice's sweeps on the
+automatic kernel plan, and the read-out of energies, best states and the
+per-sweep energy trace.  The steps resume each other through the sweep
+offset and the carried best state, so warmup W plus K steps run the first
+(W + K) slices of the one schedule; the defaults (W = 1, K = 19) run all of
+it.
 
-Printed: one JSON line with p-dit updates/s of the fast path (the value),
-the plain path (int32 H in device memory, vector-ALU recompute) on the same
-batch, sweeps/time to the target energy (the plain path's best), the
-roofline of the dominant kernel (the fast sweep) and the CPU oracle's rate
-on a bounded sample of the same workload.
+Printed: one JSON line with p-dit updates/s of the timed slices (the value);
+the plain path (int32 H in device memory) timed on the first 100 sweeps of
+every other slice, from the fast path's own state at that slice's start, and
+its estimated full-schedule time; sweeps and seconds to the target energy
+(the final best: the plain path follows the same trajectory); the roofline
+of the sweep kernels; and the CPU oracle on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -29,6 +36,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "p-dit updates/s + time-to-target gap; batched+int8 MFMA vs plain, 1 GPU"
+# 32-bit integer lane operations per second of one MI355X (the non-packed
+# VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz)
+VALU_PEAK = 256 * 64 * 2.4e9
+
+
+def method_ops_per_update(N: int, alpha: float) -> float:
+    """Algorithmic integer work of one p-dit update of the method: the energy
+    change of all N candidates (about 13 operations each: the H row, column
+    and diagonal terms of Eq. 3 and the D/F correction), the row minimum and
+    the CDF scan (2 log2 N), and with probability alpha the O(N^2) rank-1
+    update of H after an accepted exchange."""
+    import math
+    return 13 * N + 2 * math.log2(N) + alpha * N * N
 # int32 vector lane-ops per second of one MI355X: 256 CUs x 4 SIMD x 16 lanes
 # x 2.4 GHz (non-packed 32-bit integer VALU rate)
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
@@ -53,9 +73,18 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-replicas", type=int, default=32)
-    ap.add_argument("--workload", default="n64", choices=["n64", "n12", "uneven", "n256", "n512", "pt", "cupim", "clique"],
-                    help="n64 is the benchmark configuration; the others report the same "
-                         "fast-vs-plain comparison for the other workload shapes")
+    ap.add_argument("--cpu-sweeps", type=int, default=30,
+                    help="n256: oracle sweeps per sampled state (CPU baseline)")
+    ap.add_argument("--slice", type=int, default=5000,
+                    help="n256: sweeps per step (a slice of the 10^5-sweep schedule)")
+    ap.add_argument("--sweep", default="auto", choices=["auto", "fast", "large"],
+                    help="n256: sweep kernel of the timed path")
+    ap.add_argument("--workload", default="n256",
+                    choices=["n256", "n64", "n12", "uneven", "n256p", "n512", "pt", "cupim",
+                             "clique"],
+                    help="n256 is the benchmark configuration; n64 times the N=64 workload's "
+                         "full schedule; the others report the fast-vs-plain comparison for "
+                         "the other workload shapes (n256p: a prefix of the N=256 schedule)")
     ap.add_argument("--sweeps", type=int, default=0,
                     help="run only the first SWEEPS sweeps of the schedule (0 = all)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -82,7 +111,7 @@ def other_workload(args):
     if args.workload == "uneven":
         insts = W.config_uneven()
     else:
-        insts = [{"n12": W.config_n12, "n256": W.config_n256, "n512": W.config_n512}[args.workload]()]
+        insts = [{"n12": W.config_n12, "n256p": W.config_n256, "n512": W.config_n512}[args.workload]()]
     if args.sweeps:
         for i in insts:
             i.beta = i.beta[: args.sweeps]
@@ -406,6 +435,209 @@ def clique_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_info() -> dict:
+    """Host cores and CPU model (for the CPU baseline)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def n256_workload(args):
+    """The benchmark: the N=256 workload's schedule in slices (see the module
+    docstring)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit
+    from paper_2605_24408_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    inst = W.config_n256()
+    N, R, T = inst.N, inst.R, inst.T
+    S = args.slice
+    n_slices = (T + S - 1) // S
+    if args.warmup + args.steps > n_slices:
+        print(f"warmup + steps must be at most {n_slices} slices of {S} sweeps", file=sys.stderr)
+        sys.exit(2)
+    D = torch.from_numpy(inst.D).to(dev)
+    F = torch.from_numpy(inst.F).to(dev)
+    beta = torch.from_numpy(inst.beta).to(dev)
+    perm = torch.from_numpy(inst.perms).to(dev)
+    seed = W.PHILOX_SEED
+    trace = torch.zeros((R, S), dtype=torch.int64, device=dev)
+    ctx = pdit.Pdit(sweep=args.sweep)
+    ctx.set_sweep_offset(0)
+    ctx.reset()
+
+    # the plain path is sampled at the start of every other slice, from the
+    # fast path's own state there (the two follow the same trajectory)
+    sample_at = set(range(0, n_slices, 2))
+    saved = {}
+    per_slice = []
+    best_trace = np.full(T, np.iinfo(np.int64).max, dtype=np.int64)
+    last_trace = [trace]
+
+    def one_slice(i, timed):
+        t0, t1 = i * S, min(T, (i + 1) * S)
+        if i in sample_at:
+            Eb, pb = ctx.best() if i > 0 else (None, None)
+            saved[i] = (perm.clone(), None if Eb is None else Eb.clone(),
+                        None if pb is None else pb.clone())
+        tr = trace if t1 - t0 == S else torch.zeros((R, t1 - t0), dtype=torch.int64, device=dev)
+        ctx.set_recording(None, tr)
+        ctx.run_sweeps(D, F, perm, beta[t0:t1], seed)
+        last_trace[0] = tr
+        return t0, t1
+
+    # ---------------- warmup slices (untimed) ----------------
+    for i in range(args.warmup):
+        t0, t1 = one_slice(i, False)
+        torch.cuda.synchronize()
+        best_trace[t0:t1] = last_trace[0].min(dim=0).values.cpu().numpy()
+        cnt = ctx.counters()
+        per_slice.append({"slice": i, "timed": False, "kernel_ms": ctx.last_timing()[1],
+                          "alpha": cnt["accepted"] / cnt["updates"], "plan": ctx.last_plan()})
+    # ---------------- timed slices ----------------
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        t0, t1 = one_slice(i, True)
+        cnt = ctx.counters()   # waits for the slice: per-slice acceptance and timing
+        best_trace[t0:t1] = last_trace[0].min(dim=0).values.cpu().numpy()
+        per_slice.append({"slice": i, "timed": True, "kernel_ms": ctx.last_timing()[1],
+                          "alpha": cnt["accepted"] / cnt["updates"], "plan": ctx.last_plan(),
+                          "end_s": time.perf_counter() - start, "ties": cnt["ties"]})
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - start
+    run_sweeps = (args.warmup + args.steps) * S
+    timed_updates = R * N * sum(min(T, (i + 1) * S) - i * S
+                                for i in range(args.warmup, args.warmup + args.steps))
+    value = timed_updates / elapsed
+    Eb, pb = ctx.best()
+    Eb_fast = Eb.cpu().numpy()
+    timed = [p for p in per_slice if p["timed"]]
+    kernel_s = sum(p["kernel_ms"] for p in timed) / 1e3
+    alpha_timed = float(np.mean([p["alpha"] for p in timed]))
+
+    # ---------------- roofline of the sweep kernels (timed slices) ----------------
+    ops = sum(method_ops_per_update(N, p["alpha"]) * R * N * S for p in timed)
+    achieved = ops / kernel_s
+    plans = sorted({(p["plan"]["sweep"], p["plan"]["size_class"]) for p in timed})
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "T int32 lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "kernels": [f"{k} (class {c})" if c else k for k, c in plans],
+                "kernel_s": kernel_s,
+                "ops_per_update": "13 N + 2 log2 N + alpha N^2 per slice (alpha measured)",
+                "mean_alpha": alpha_timed}
+
+    # ---------------- time to target ----------------
+    target = int(Eb_fast.min())
+    ttt = {"target_energy": target,
+           "target": "final best over all replicas of the schedule run (the plain path "
+                     "follows the same trajectory and ends at the same best)"}
+    ends = {p["slice"]: p.get("end_s") for p in per_slice}
+    for gap in (0.01, 0.001, 0.0):
+        lim = target + abs(target) * gap
+        hit = np.nonzero(best_trace[:run_sweeps] <= lim)[0]
+        if hit.size:
+            k = int(hit[0])
+            sl = k // S
+            prev_end = ends.get(sl - 1) if sl > args.warmup else 0.0
+            end = ends.get(sl)
+            ttt[f"gap_{gap:g}"] = {"sweep": k + 1, "timed": end is not None,
+                                   "seconds_at_slice_end": end,
+                                   "seconds_interpolated": None if end is None else
+                                   prev_end + (end - prev_end) * ((k % S) + 1) / S}
+
+    # ---------------- plain path on the sampled slices ----------------
+    plain_rec = None
+    if not args.no_plain:
+        plain = pdit.Pdit(sweep="plain", recompute="plain")
+        fastc = pdit.Pdit(sweep=args.sweep)
+        PS = min(100, S)
+        samples, same = [], True
+        for i in sorted(saved):
+            p0, eb0, pb0 = saved[i]
+            res = {}
+            for name, c in (("plain", plain), ("fast", fastc)):
+                p = p0.clone()
+                c.set_sweep_offset(i * S)
+                c.reset()
+                torch.cuda.synchronize()
+                t_ = time.perf_counter()
+                c.run_sweeps(D, F, p, beta[i * S:i * S + PS].contiguous(), seed)
+                e = c.energy()
+                torch.cuda.synchronize()
+                res[name] = (time.perf_counter() - t_, p.cpu().numpy(), e.cpu().numpy())
+            same = same and np.array_equal(res["plain"][1], res["fast"][1]) and \
+                np.array_equal(res["plain"][2], res["fast"][2])
+            samples.append({"slice": i, "plain_s": res["plain"][0], "fast_s": res["fast"][0]})
+        plain.close()
+        fastc.close()
+        # each sample stands for the two slices it starts (every other slice)
+        est = sum(x["plain_s"] / PS * S * 2 for x in samples)
+        fast_total = sum(p["kernel_ms"] for p in per_slice) / 1e3
+        plain_rec = {"sweeps_per_sample": PS, "samples": samples,
+                     "estimated_full_schedule_s": est,
+                     "fast_full_schedule_kernel_s": fast_total,
+                     "value": R * N * T / est,
+                     "speedup": est / fast_total, "identical_results_on_samples": bool(same)}
+
+    # ---------------- CPU oracle on a bounded sample ----------------
+    cpu = None
+    if not args.no_cpu and saved:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        info = cpu_info()
+        threads = max(1, min(16, info["nproc"] or 1))
+        oracle.lib()
+        starts = sorted(saved)[::2]                 # every fourth slice
+        tasks = [(i, k) for i in starts for k in range(threads)]
+        host = {i: saved[i][0].cpu().numpy() for i in starts}
+        CS = args.cpu_sweeps
+
+        def run_task(ik):
+            i, k = ik
+            return oracle.run(inst.D, inst.F, host[i][k:k + 1], inst.beta[i * S:i * S + CS], seed,
+                              sweep_offset=i * S, rep_ids=[k]).counters[0, 1]
+
+        t2 = time.perf_counter()
+        run_task(tasks[0])
+        one_s = time.perf_counter() - t2
+        t2 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(run_task, tasks))
+        all_s = time.perf_counter() - t2
+        upd = len(tasks) * N * CS
+        cpu = {"value": upd / all_s, "unit": "p-dit updates/s", "cores": threads,
+               "kind": "oracle", "single_core": N * CS / one_s, "nproc": info["nproc"],
+               "cpu_model": info["cpu_model"],
+               "sample": f"{threads} replicas x {CS} sweeps from the fast path's states at the "
+                         f"starts of slices {starts} ({len(tasks)} tasks, one replica per "
+                         f"thread), the schedule's beta and sweep offsets there"}
+    ctx.close()
+
+    out = {"metric": METRIC, "value": value, "unit": "p-dit updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": "qap_n256_euclid", "N": N, "replicas": R, "sweeps": T,
+                      "slice_sweeps": S, "timed_sweeps": f"{args.warmup * S}..{run_sweeps}",
+                      "beta": f"geometric 0.5/s -> 2000/s, s = {inst.meta['scale']:.1f}",
+                      "sweep_plan": args.sweep, "parallelism": "replicas"},
+           "acceptance": alpha_timed, "roofline": roofline, "plain": plain_rec,
+           "time_to_target": ttt, "cpu_baseline": cpu,
+           "slices": [{k: v for k, v in p.items() if k != "plan"} | {"kernel": p["plan"]["sweep"]}
+                      for p in per_slice]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -422,10 +654,18 @@ def main():
     if args.workload == "clique":
         clique_workload(args)
         return
+    if args.workload == "n256":
+        n256_workload(args)
+        return
     if args.workload != "n64":
         other_workload(args)
         return
+    n64_workload(args)
 
+
+def n64_workload(args):
+    """The N=64 workload's full schedule as the step (the previous headline
+    configuration, kept for comparison); same JSON fields."""
     import numpy as np
     import torch
 
