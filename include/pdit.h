@@ -106,6 +106,16 @@ extern "C" {
                                selection, periodic tempering (diag H is the state saved
                                between periods) and batched runs (a persistent group per copy
                                layout, product width and H width). */
+#define PDIT_SWEEP_REG 5    /* G = D F[p,:] in registers, 128 < N <= 256: each of the replica's
+                               256 lanes keeps its location's row of G (H[i][k] = G[i][p(k)])
+                               as packed int16 pairs, exact while |H| <= 32767; an accepted
+                               exchange of the facilities a = p(r), b = p(s) adds the rank-1
+                               term (D[i][r] - D[i][s]) (F[b][c] - F[a][c]) and moves no
+                               column; D and F are 8-bit copies in LDS ([0, 255] or
+                               [-128, 127]) shared by the two replicas of a workgroup.  Same
+                               dynamics and results as the other kernels.  AUTO picks it for
+                               single-instance runs wherever the data fit; REG forces it
+                               (PDIT_EOVERFLOW when they do not). */
 
 typedef struct pdit_ctx pdit_t;
 
@@ -401,9 +411,10 @@ int pdit_debug_choice(pdit_t *ctx, int32_t N, int32_t M, const int64_t *delta, c
 int pdit_last_timing(pdit_t *ctx, double *recompute_ms, double *sweep_ms);
 
 /* What the last single-instance run used: *sweep is PDIT_SWEEP_PLAIN,
- * PDIT_SWEEP_FAST, PDIT_SWEEP_CLIQUE or PDIT_SWEEP_LARGE, *size_class the
- * on-chip kernel's size class (16, 32, 64, 96, 128, 160 or 256; 0 for the
- * other kernels), *recompute the PDIT_RECOMPUTE_*
+ * PDIT_SWEEP_FAST, PDIT_SWEEP_CLIQUE, PDIT_SWEEP_LARGE or PDIT_SWEEP_REG,
+ * *size_class the on-chip kernel's size class (16, 32, 64, 96, 128, 160 or
+ * 256; 256 for the register kernel; 0 for the other kernels), *recompute
+ * the PDIT_RECOMPUTE_*
  * mode of the H recompute.  Any pointer may be NULL. */
 int pdit_last_plan(pdit_t *ctx, int *sweep, int *size_class, int *recompute);
 

@@ -237,6 +237,10 @@ int pdit_create(pdit_t **out, const pdit_opts *opts) {
         pdit_destroy(ctx);
         return PDIT_ENOMEM;
     }
+    if (hipMemset(ctx->err_dev, 0, sizeof(int32_t)) != hipSuccess) {
+        pdit_destroy(ctx);
+        return PDIT_EDEVICE;
+    }
     *out = ctx;
     return PDIT_OK;
 }
@@ -317,7 +321,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (N < 2 || N > PDIT_NMAX) return fail(ctx, PDIT_EINVAL, "N must be in [2, PDIT_NMAX]");
     if (R < 1) return fail(ctx, PDIT_EINVAL, "R must be >= 1");
     if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
-    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_LARGE)
+    if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_REG)
         return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
@@ -341,8 +345,16 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
                     "zero diagonals, N <= 512 and (4N + 2) max|D| < 2^30");
     const int64_t bound = pdit::h_bound(st);
     const bool h64 = bound > INT32_MAX;
+    // the register kernel (G in registers, 8-bit D and F in LDS) where it fits
+    const int rclass = pdit::reg_class(N, st);
+    if (ctx->opts.sweep == PDIT_SWEEP_REG && !rclass)
+        return fail(ctx, PDIT_EOVERFLOW,
+                    "the register sweep kernel needs 128 < N <= 256, |H| <= 32767 and D, F in "
+                    "[0, 255] or in [-128, 127]");
+    const bool use_reg = rclass != 0 && (ctx->opts.sweep == PDIT_SWEEP_REG ||
+                                         ctx->opts.sweep == PDIT_SWEEP_AUTO);
     // the on-chip kernel's size class, 0 if the data do not fit its exact arithmetic
-    const int fclass = pdit::fast_class(N, st);
+    const int fclass = use_reg ? 0 : pdit::fast_class(N, st);
     bool use_fast = false;
     if (ctx->opts.sweep == PDIT_SWEEP_FAST) {
         if (!fclass)
@@ -354,8 +366,8 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
         use_fast = fclass != 0;
     }
     // without a fast class the kernel that stores no H replaces the plain one
-    const bool use_large = ctx->opts.sweep == PDIT_SWEEP_LARGE ||
-                           (ctx->opts.sweep == PDIT_SWEEP_AUTO && !use_fast);
+    const bool use_large = !use_reg && (ctx->opts.sweep == PDIT_SWEEP_LARGE ||
+                                        (ctx->opts.sweep == PDIT_SWEEP_AUTO && !use_fast));
     int mode = 0;
     rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
     if (rc) return rc;
@@ -405,9 +417,12 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     a.E_trace = ctx->rec_trace;
     a.seq_threshold = ctx->opts.seq_threshold;
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
+    a.err = ctx->err_dev;
     PDIT_HIP(ctx, record_event(ctx, 1));
     if (n_sweeps > 0) {
-        if (use_fast)
+        if (use_reg)
+            PDIT_HIP(ctx, pdit::launch_sweep_reg(ctx->stream, rclass, a));
+        else if (use_fast)
             PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
         else if (use_large)
             PDIT_HIP(ctx, pdit::launch_sweep_large(ctx->stream, a, h64, lplan, lcopy));
@@ -422,8 +437,11 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->rec_trace = nullptr;
     ctx->sweep_offset += (uint64_t)n_sweeps;
     ctx->last_updates = (int64_t)R * N * n_sweeps;
-    ctx->last_sweep = use_fast ? PDIT_SWEEP_FAST : use_large ? PDIT_SWEEP_LARGE : PDIT_SWEEP_PLAIN;
-    ctx->last_class = use_fast ? fclass : 0;
+    ctx->last_sweep = use_reg    ? PDIT_SWEEP_REG
+                      : use_fast ? PDIT_SWEEP_FAST
+                      : use_large ? PDIT_SWEEP_LARGE
+                                  : PDIT_SWEEP_PLAIN;
+    ctx->last_class = use_fast ? fclass : use_reg ? 256 : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
     return PDIT_OK;
@@ -1292,6 +1310,14 @@ int pdit_sync(pdit_t *ctx) {
     if (!ctx) return PDIT_EINVAL;
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
     PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->err_dev) {
+        int32_t e = 0;
+        PDIT_HIP(ctx, hipMemcpy(&e, ctx->err_dev, sizeof(e), hipMemcpyDeviceToHost));
+        if (e) {
+            PDIT_HIP(ctx, hipMemset(ctx->err_dev, 0, sizeof(int32_t)));
+            return fail(ctx, PDIT_EDEVICE, "a sweep kernel's internal wait gave up (its results are undefined)");
+        }
+    }
     return PDIT_OK;
 }
 

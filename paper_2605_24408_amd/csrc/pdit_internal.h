@@ -31,6 +31,8 @@ struct InstanceStats {
     int32_t clique_bad;     // entries of F that break F[a][b] = c(a) c(b) (a != b), F[a][a] = 0
     int32_t clique_size;    // facilities with c(a) = 1
     int32_t int_min;        // entries of D or F equal to INT32_MIN (their magnitude needs 32 bits)
+    int32_t neg_d;          // negative entries of D
+    int32_t neg_f;          // negative entries of F
 };
 
 // Exact bound on |H_ik| for any permutation: |sum_j D_ij F_{p(j)p(k)}| <=
@@ -158,6 +160,7 @@ struct SweepArgs {
     const int32_t *slot;
     int32_t *tstate;         // table kernel: [R][table_state_words(N)] replica state between launches
     uint32_t flags;          // kLoadState | kSaveState | kAccumCounters
+    int32_t *err;            // deferred device error word (set to 1 on an internal wait's timeout), or null
 };
 
 // Launch flags of the sweep kernels (parallel-tempering periods).
@@ -293,6 +296,10 @@ int large_blocks_per_cu(const LargePlan &pl);
 // 160 or 256), or 0 when its data do not fit that kernel's exact arithmetic
 int fast_class(int N, const InstanceStats &st);
 hipError_t launch_sweep_fast(hipStream_t s, int nmax, const SweepArgs &a);
+// the kernel with G = D F[p,:] in registers (128 < N <= 256, 8-bit D and F,
+// |H| <= 32767): 1 for unsigned copies, 2 for signed, 0 when it does not fit
+int reg_class(int N, const InstanceStats &st);
+hipError_t launch_sweep_reg(hipStream_t s, int cls, const SweepArgs &a);
 hipError_t launch_sweep_fast_persistent(hipStream_t s, int nmax, bool zero_diag, const BatchArgs &b,
                                         int grid);
 int fast_blocks_per_cu(int nmax);

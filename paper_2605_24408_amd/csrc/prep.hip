@@ -24,6 +24,8 @@ __global__ void zero_stats_kernel(InstanceStats *s) {
         s->clique_bad = 0;
         s->clique_size = 0;
         s->int_min = 0;
+        s->neg_d = 0;
+        s->neg_f = 0;
     }
 }
 
@@ -36,7 +38,7 @@ __global__ void matrix_stats_kernel(int N, const int32_t *__restrict__ D,
     const int i = isD ? t : t - N;
     const int32_t *M = isD ? D : F;
     int64_t sum = 0;
-    int32_t mx = 0, asym = 0, int_min = 0;
+    int32_t mx = 0, asym = 0, int_min = 0, neg = 0;
     for (int j = 0; j < N; ++j) {
         // row i of D; column i of F (sum over the row index j)
         const int32_t v = isD ? M[(int64_t)i * N + j] : M[(int64_t)j * N + i];
@@ -44,11 +46,13 @@ __global__ void matrix_stats_kernel(int N, const int32_t *__restrict__ D,
         // instead of folded into the maximum
         const int64_t a = v < 0 ? -(int64_t)v : (int64_t)v;
         int_min += v == INT32_MIN;
+        neg += v < 0;
         sum += a;
         mx = max(mx, (int32_t)min(a, (int64_t)INT32_MAX));
         if (j > i && M[(int64_t)i * N + j] != M[(int64_t)j * N + i]) ++asym;
     }
     if (int_min) atomicAdd(&s->int_min, int_min);
+    if (neg) atomicAdd(isD ? &s->neg_d : &s->neg_f, neg);
     const bool diag_nz = M[(int64_t)i * N + i] != 0;
     if (isD) {
         if (diag_nz) atomicAdd(&s->diag_nz_d, 1);

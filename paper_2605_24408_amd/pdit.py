@@ -22,7 +22,7 @@ STATUS = {0: "PDIT_OK", -1: "PDIT_EINVAL", -2: "PDIT_ENOTSYM", -3: "PDIT_EBADPER
 NMAX = 512
 
 RECOMPUTE = {"auto": 0, "plain": 1, "i8": 2, "bf16": 3, "split": 4}
-SWEEP = {"auto": 0, "plain": 1, "fast": 2, "clique": 3, "large": 4}
+SWEEP = {"auto": 0, "plain": 1, "fast": 2, "clique": 3, "large": 4, "reg": 5}
 PT_SCHEDULE = {"auto": 0, "periodic": 1, "fused": 2}
 PT_DYNAMICS = {"sequential": 0, "cupim": 1}
 
@@ -384,7 +384,8 @@ class Pdit:
         a, b, c = C.c_int(), C.c_int(), C.c_int()
         self._rc(self._L.pdit_last_plan(self._h, C.byref(a), C.byref(b), C.byref(c)))
         inv = {v: k for k, v in RECOMPUTE.items()}
-        return {"sweep": {1: "plain", 2: "fast", 3: "clique", 4: "large"}[a.value], "size_class": b.value,
+        return {"sweep": {1: "plain", 2: "fast", 3: "clique", 4: "large", 5: "reg"}[a.value],
+                "size_class": b.value,
                 "recompute": inv[c.value]}
 
     def set_sweep_offset(self, offset: int):
