@@ -2,33 +2,41 @@
 // registers, for 128 < N <= 256 with D and F held as 8-bit copies.
 //
 // The state is G = D F[p,:] (location x facility): G[i][c] = sum_j D[i][j]
-// F[p(j)][c], so H = D F[p,p] is H[i][k] = G[i][p(k)].  Lane l of a
-// replica's 256 lanes (four waves) owns location l and keeps row l of G in
-// 128 registers as packed int16 pairs (exact while |H| <= 32767), and diag
-// H[l][l].  An accepted exchange of the facilities a = p(r) and b = p(s)
-// changes G by one rank-1 term and moves no column (Methods, "CPU-PIM
-// Algorithm": the influence is kept incrementally; with symmetric data
-// I = -2H, Eq. 2):
-//   G'[i][c] = G[i][c] + (D[i][r] - D[i][s]) (F[b][c] - F[a][c]),
-// 128 packed multiply-adds per lane.
+// F[p(j)][c], so H = D F[p,p] is H[i][k] = G[i][p(k)].  An accepted exchange
+// of the facilities a = p(r) and b = p(s) changes G by one rank-1 term and
+// moves no column (Methods, "CPU-PIM Algorithm": the influence is kept
+// incrementally; with symmetric data I = -2H, Eq. 2):
+//   G'[i][c] = G[i][c] + u_i w_c,  u_i = D[i][r] - D[i][s],
+//                                   w_c = F[b][c] - F[a][c].
+//
+// A replica has four waves.  Lane j of wave w holds the 4 x 64 tile of G at
+// rows 4j .. 4j + 3 and facilities 64w .. 64w + 63, as packed int16 pairs
+// (exact while |H| <= 32767): 128 registers, and an accepted exchange costs
+// 128 packed multiply-adds per lane, with w read for the wave's 64
+// facilities only.
 //
 // The update of location r (Results, "Implementation": locations 0..N-1 in
-// order; Eq. 3 and Eq. 5) needs row r of H, H[r][k] = G[r][p(k)] (lane r
-// writes its row to LDS, lane k reads entry p(k)), column r, H[k][r] =
-// G[k][p(r)] (each lane reads its own register at the uniform index p(r)),
-// and the diagonal.  Then
+// order; Eq. 3 and Eq. 5) needs row r of G (H[r][k] = G[r][p(k)]) and the
+// column of G at a = p(r) (H[k][r] = G[k][a]).  Before each update the waves
+// publish exactly these two vectors to LDS (the lane holding row r writes
+// its 64 entries in every wave; the wave holding facility a writes the
+// column) and wait for each other: that is the only exchange between waves.
+// Then every wave evaluates all N candidates itself, four consecutive
+// locations per lane,
 //   dE_k = 2 (H[r][k] - H[r][r] + H[k][r] - H[k][k])
 //          + (D_rr + D_kk - 2 D_rk)(F_aa + F_cc - 2 F_ac),  c = p(k),
-// the row minimum, the integer Gibbs weights q = rint(expf(-beta d) 2^25)
-// and their exact 64-bit CDF, as in the other sweep kernels, so every kernel
-// draws the same candidate.  A row whose only nonzero weight is its own
-// stay (the minimum is 0 and every other candidate lies beyond the
-// zero-weight distance) keeps its facility without weights or scan.
+// with H[k][k], p and the diagonals of D and F kept per candidate in its
+// registers, takes the row minimum, the integer Gibbs weights
+// q = rint(expf(-beta d) 2^25) and their exact 64-bit CDF in location
+// order, as the other sweep kernels do, and draws the same candidate: the
+// four waves reach the same decision with no message.  A row whose only
+// nonzero weight is its own stay (every other candidate lies at or beyond the
+// zero-weight distance above 0) keeps its facility without weights or scan.
 //
-// Two replicas share a workgroup (eight waves) and its LDS: D and F as 8-bit
-// copies (64 KB each, unsigned in [0, 255] or signed in [-128, 127]), so
-// every read of D and F on the path is an LDS read.  The two replicas move
-// in step: an update takes four workgroup barriers whatever happens in it.
+// Two replicas share a workgroup (eight waves, each SIMD holding one wave of
+// each) and its LDS: D and F as 8-bit copies (64 KB each, unsigned in
+// [0, 255] or signed in [-128, 127]), so every read of D and F on the path
+// is an LDS read.  The replicas wait only for their own waves.
 #include "device_common.h"
 #include "pdit_internal.h"
 #include "sweep_common.h"
@@ -38,11 +46,10 @@
 namespace pdit {
 namespace {
 
-constexpr int kRN = 256;          // locations (lanes) per replica
+constexpr int kRN = 256;          // locations (and facilities) per replica
 constexpr int kRWaves = 4;        // waves per replica
 constexpr int kRReps = 2;         // replicas per workgroup
 constexpr int kRThreads = 64 * kRWaves * kRReps;
-constexpr int kRBlock = 16;       // rows of G copied to LDS together
 constexpr int32_t kRBig = (1 << 30) - 1;  // padding candidates (|dE| < 2^30 - 1)
 // spins of a replica's wait before it gives up (about 0.1 s): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
@@ -52,20 +59,14 @@ constexpr uint32_t kRSpinLimit = 1u << 22;
 typedef int v32i __attribute__((ext_vector_type(32)));
 typedef short v64s __attribute__((ext_vector_type(64)));
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef short v8s __attribute__((ext_vector_type(8)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 struct alignas(16) RegRep {
-    alignas(16) int16_t blk[kRBlock][kRN];  // rows 16 b .. 16 b + 15 of G, by facility
-    alignas(16) uint32_t w[kRN / 2];        // accepted exchange: F[b][c] - F[a][c], int16 pairs
-    alignas(16) uint32_t sync[kRWaves];     // per wave: the last step it finished
-    int32_t pv[kRN];                        // p(l)
-    uint32_t u24[2][kRN];                   // the sweep's uniforms by location, by sweep parity
-    int32_t xmin[2][kRWaves][2];            // per wave: minimum, minimum over l != r (update parity)
-    uint64_t xz[kRWaves];                   // per wave: sum of the weights
-    uint64_t xr[2];                         // the wave of r: exclusive sum at r, weight of r
-    int32_t msg[3];                         // accepted: s, dE, p(s)
-    int16_t ublk[kRBlock];                  // accepted: u of the block's rows
-    int32_t ties[kRWaves];
+    alignas(16) int16_t prow[2][kRN];     // row r of G by facility (by update parity)
+    alignas(16) int16_t pcol[2][kRN];     // column p(r) of G by location (by update parity)
+    alignas(16) int16_t w[kRWaves][kRN];  // per wave: the accepted exchange's w, by facility
+    alignas(16) uint32_t sync[kRWaves];   // per wave: the last step it finished
+    int32_t pinv[kRN];                    // set-up: p^-1
 };
 
 template <bool SGN>
@@ -76,21 +77,14 @@ struct RegSmem {
     RegRep rep[kRReps];
 };
 
-// Entry c of a row of 256 int16 values packed in four 32-register vectors;
-// c is wave-uniform, so each read is a relative register move.
-__device__ __forceinline__ int32_t row_entry(const v32i &g0, const v32i &g1, const v32i &g2,
-                                             const v32i &g3, int c) {
-    const int cu = __builtin_amdgcn_readfirstlane(c);
-    const int k = cu >> 1;
-    const int lo = k & 31;
-    const int v0 = g0[lo], v1 = g1[lo], v2 = g2[lo], v3 = g3[lo];
-    const int hi = k >> 5;
-    const int word = hi == 0 ? v0 : hi == 1 ? v1 : hi == 2 ? v2 : v3;
-    return (cu & 1) ? (word >> 16) : (int32_t)(int16_t)(word & 0xFFFF);
-}
-
 __device__ __forceinline__ uint32_t pack16(int32_t lo, int32_t hi) {
     return ((uint32_t)lo & 0xFFFFu) | ((uint32_t)hi << 16);
+}
+
+// byte t of a packed word of four 8-bit entries, widened
+template <bool SGN>
+__device__ __forceinline__ int32_t byte_at(uint32_t x, int t) {
+    return SGN ? (int32_t)(int8_t)(x >> (8 * t)) : (int32_t)((x >> (8 * t)) & 0xFFu);
 }
 
 // g += u w elementwise on int16 lanes (modulo 2^16; the true values fit)
@@ -100,22 +94,90 @@ __device__ __forceinline__ v32i rank1(v32i g, short u, v32i w) {
     return __builtin_bit_cast(v32i, gs + (v64s)u * ws);
 }
 
-// Wait of the kRWaves waves of one replica (the other replica of the
-// workgroup goes on): wave w records that it finished step `seq`, after its
-// LDS writes have completed, and waits until every wave of the replica has.
-// Returns false when the wait gave up (kRSpinLimit).
-__device__ __forceinline__ bool rep_wait(uint32_t *slots, int w, uint32_t seq) {
-    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+// entry (uniform) facility c of a tile row: register c / 2, half c % 2
+__device__ __forceinline__ int32_t tile_entry(const v32i &g, int m, int half) {
+    const int word = g[__builtin_amdgcn_readfirstlane(m)];
+    return half ? (word >> 16) : (int32_t)(int16_t)(word & 0xFFFF);
+}
+
+// value of the candidate slot of location k (uniform): lane k / 4, slot k % 4
+__device__ __forceinline__ int32_t pick(const int32_t (&v)[4], int k) {
+    const int t = k & 3;
+    const int32_t x = t == 0 ? v[0] : t == 1 ? v[1] : t == 2 ? v[2] : v[3];
+    return __builtin_amdgcn_readlane(x, k >> 2);
+}
+
+typedef __attribute__((address_space(3))) volatile v4i lds_v4i;
+typedef __attribute__((address_space(3))) char lds_char;
+
+// LDS byte address of a pointer into the kernel's shared memory
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const lds_char *)p;
+}
+
+// 128-byte store of a tile row to LDS (eight 16-byte writes).  Each call site
+// passes its own tag, so that the stores of different rows stay separate
+// instructions and no copy of a row is formed to merge them.
+#define PDIT_REG_STORE_ROW(addr, g, tag)                                                   \
+    __asm__ volatile("; tile row " tag "\n\t"                                              \
+                     "ds_write_b128 %0, %1\n\t"                                            \
+                     "ds_write_b128 %0, %2 offset:16\n\t"                                  \
+                     "ds_write_b128 %0, %3 offset:32\n\t"                                  \
+                     "ds_write_b128 %0, %4 offset:48\n\t"                                  \
+                     "ds_write_b128 %0, %5 offset:64\n\t"                                  \
+                     "ds_write_b128 %0, %6 offset:80\n\t"                                  \
+                     "ds_write_b128 %0, %7 offset:96\n\t"                                  \
+                     "ds_write_b128 %0, %8 offset:112"                                     \
+                     :                                                                     \
+                     : "v"(addr), "v"((g).s0123), "v"((g).s4567), "v"((g).s89ab),          \
+                       "v"((g).scdef), "v"((g).hi.s0123), "v"((g).hi.s4567),               \
+                       "v"((g).hi.s89ab), "v"((g).hi.scdef)                                \
+                     : "memory")
+
+// Inclusive prefix sum of a 32-bit value across the wave (lane order):
+// shifts within rows of 16, then the row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ uint32_t scan_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
+// The waves of a replica meet through one LDS word per wave, not workgroup
+// barriers, so the two replicas of a workgroup run independently.  The LDS
+// operations of one wave are carried out in the order it issues them, so
+// (1) a wave's flag store lands after its publication stores, and (2) a
+// read issued after a poll that found every flag set returns the published
+// data: a wave issues its poll and the publication's reads back to back and
+// pays one LDS round trip for both.
+__device__ __forceinline__ void rep_signal(uint32_t *slots, int w, uint32_t seq) {
+    __asm__ volatile("" ::: "memory");
     __hip_atomic_store(&slots[w], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ const lds_v4i *rep_flags(uint32_t *slots) {
+    return (const lds_v4i *)(__attribute__((address_space(3))) uint32_t *)slots;
+}
+
+// every wave of the replica has finished step seq (uniform)
+__device__ __forceinline__ bool rep_done(v4i v, uint32_t seq) {
+    const bool done = (int32_t)(v.x - seq) >= 0 && (int32_t)(v.y - seq) >= 0 &&
+                      (int32_t)(v.z - seq) >= 0 && (int32_t)(v.w - seq) >= 0;
+    return __builtin_amdgcn_readfirstlane((int)done) != 0;
+}
+
+// Polls until every wave has finished step seq; false when the wait gave up
+// (kRSpinLimit).
+__device__ __forceinline__ bool rep_spin(const lds_v4i *ps, uint32_t seq) {
     for (uint32_t it = 0; it < kRSpinLimit; ++it) {
-        const v4i v = *(volatile const v4i *)slots;
-        const bool done = (int32_t)(v.x - seq) >= 0 && (int32_t)(v.y - seq) >= 0 &&
-                          (int32_t)(v.z - seq) >= 0 && (int32_t)(v.w - seq) >= 0;
-        if (__builtin_amdgcn_readfirstlane((int)done)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (rep_done(*ps, seq)) {
             __asm__ volatile("" ::: "memory");
             return true;
         }
-        __builtin_amdgcn_s_sleep(1);
     }
     return false;
 }
@@ -123,261 +185,298 @@ __device__ __forceinline__ bool rep_wait(uint32_t *slots, int w, uint32_t seq) {
 template <bool SGN, bool ZD>
 __global__ void __launch_bounds__(kRThreads)
 sweep_reg_kernel(SweepArgs a) {
+    using E8 = typename RegSmem<SGN>::E8;
     __shared__ __align__(16) RegSmem<SGN> sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wv = tid >> 6;
-    const int qr = wv / kRWaves;       // replica slot of this wave in the workgroup
-    const int w = wv % kRWaves;        // wave within the replica
-    const int l = 64 * w + lane;       // this lane's location
+    const int wv = __builtin_amdgcn_readfirstlane((tid >> 6) % kRWaves);  // wave in the replica
+    const int qr = __builtin_amdgcn_readfirstlane((tid >> 6) / kRWaves);  // replica slot
     const int N = a.N;
     int64_t rep = (int64_t)kRReps * blockIdx.x + qr;
     // an odd last replica: the second slot repeats the first and writes nothing
     const bool live = rep < a.R;
     if (!live) rep = (int64_t)kRReps * blockIdx.x;
     RegRep &rs = sm.rep[qr];
-    const bool valid = l < N;
+    const uint32_t *D32 = (const uint32_t *)sm.D;
+    const uint32_t *F32 = (const uint32_t *)sm.F;
 
     // ---- D and F copies (both replicas) ----
     for (int e = tid; e < kRN * kRN; e += kRThreads) {
         const int i = e >> 8, j = e & 255;
         const bool in = i < N && j < N;
-        sm.D[e] = (typename RegSmem<SGN>::E8)(in ? a.D[(int64_t)i * N + j] : 0);
-        sm.F[e] = (typename RegSmem<SGN>::E8)(in ? a.F[(int64_t)i * N + j] : 0);
+        sm.D[e] = (E8)(in ? a.D[(int64_t)i * N + j] : 0);
+        sm.F[e] = (E8)(in ? a.F[(int64_t)i * N + j] : 0);
     }
-    // ---- p, p^-1 (padding locations hold the padding facilities) ----
-    int p_l = valid ? a.perm[rep * N + l] : l;
-    rs.pv[l] = p_l;
-    rs.u24[0][p_l] = (uint32_t)l;
-    if (lane < kRWaves && w == 0) rs.sync[lane] = 0;
+    // ---- candidates 4 lane + t: p (padding locations hold the padding facilities) ----
+    int32_t pk[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = 4 * lane + t;
+        pk[t] = k < N ? a.perm[rep * N + k] : k;
+        if (wv == 0) rs.pinv[pk[t]] = k;
+    }
+    if (lane < kRWaves && wv == 0) rs.sync[lane] = 0;
     __syncthreads();
 
-    // ---- row l of G = row l of H reordered by facility: G[l][c] = H[l][p^-1(c)] ----
-    const int32_t *Hl = (const int32_t *)a.H + (rep * N + (valid ? l : 0)) * (int64_t)N;
+    // ---- the tile: G[4 lane + t][64 wv + c] = H[4 lane + t][p^-1(64 wv + c)] ----
     v32i g0, g1, g2, g3;
+    {
+        const int32_t *Hb = (const int32_t *)a.H + rep * N * (int64_t)N;
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-#define PDIT_G_AT(c) ((valid && (c) < N) ? Hl[rs.u24[0][(c)]] : 0)
-        g0[k] = (int)pack16(PDIT_G_AT(2 * k), PDIT_G_AT(2 * k + 1));
-        g1[k] = (int)pack16(PDIT_G_AT(64 + 2 * k), PDIT_G_AT(64 + 2 * k + 1));
-        g2[k] = (int)pack16(PDIT_G_AT(128 + 2 * k), PDIT_G_AT(128 + 2 * k + 1));
-        g3[k] = (int)pack16(PDIT_G_AT(192 + 2 * k), PDIT_G_AT(192 + 2 * k + 1));
+        for (int m = 0; m < 32; ++m) {
+            const int c0 = 64 * wv + 2 * m, c1 = c0 + 1;
+            const int j0 = c0 < N ? rs.pinv[c0] : -1, j1 = c1 < N ? rs.pinv[c1] : -1;
+#define PDIT_G_AT(t, j) ((4 * lane + (t) < N && (j) >= 0) ? Hb[(4 * lane + (t)) * (int64_t)N + (j)] : 0)
+            g0[m] = (int)pack16(PDIT_G_AT(0, j0), PDIT_G_AT(0, j1));
+            g1[m] = (int)pack16(PDIT_G_AT(1, j0), PDIT_G_AT(1, j1));
+            g2[m] = (int)pack16(PDIT_G_AT(2, j0), PDIT_G_AT(2, j1));
+            g3[m] = (int)pack16(PDIT_G_AT(3, j0), PDIT_G_AT(3, j1));
 #undef PDIT_G_AT
+        }
     }
-    int32_t diag = valid ? Hl[l] : 0;                    // H[l][l]
-    const int32_t dd_l = ZD ? 0 : (int32_t)sm.D[l * kRN + l];
-    int32_t fd_l = ZD ? 0 : (int32_t)sm.F[p_l * kRN + p_l];
+    // per candidate: H[k][k], D[k][k], F[p(k)][p(k)]
+    int32_t dg[4], ddk[4], fdk[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int k = 4 * lane + t;
+        dg[t] = k < N ? ((const int32_t *)a.H)[(rep * N + k) * (int64_t)N + k] : 0;
+        ddk[t] = ZD ? 0 : (int32_t)sm.D[k * kRN + k];
+        fdk[t] = ZD ? 0 : (int32_t)sm.F[pk[t] * kRN + pk[t]];
+    }
     int64_t E = a.E[rep];
     int64_t E_best = a.E_best[rep];
     int64_t n_acc = 0;
     int32_t n_tie = 0;
-    int32_t *ch_base = (a.choices && live) ? a.choices + rep * a.T * N : nullptr;
+    int32_t *ch_base = (a.choices && live && wv == 0) ? a.choices + rep * a.T * N : nullptr;
     const float *bp = a.slot ? a.beta + a.slot[rep] : a.beta;
     const int64_t bstride = a.slot ? 0 : 1;
-    uint32_t seq = 0;      // steps of this replica's waits
+    const bool writer = live && wv == 0;   // wave 0 writes the replica's outputs
+
+    // publication of row nr and of the column at facility an, into buffer par
+#define PDIT_REG_PUBLISH(nr, an, par)                                                      \
+    {                                                                                      \
+        const int nr_ = __builtin_amdgcn_readfirstlane(nr);                                \
+        const int an_ = __builtin_amdgcn_readfirstlane(an);                                \
+        if (lane == (nr_ >> 2)) {                                                          \
+            const uint32_t dst_ = lds_addr(&rs.prow[(par)][64 * wv]);                      \
+            const int t_ = nr_ & 3;                                                        \
+            if (t_ == 0) PDIT_REG_STORE_ROW(dst_, g0, "0");                                \
+            else if (t_ == 1) PDIT_REG_STORE_ROW(dst_, g1, "1");                           \
+            else if (t_ == 2) PDIT_REG_STORE_ROW(dst_, g2, "2");                           \
+            else PDIT_REG_STORE_ROW(dst_, g3, "3");                                        \
+        }                                                                                  \
+        if (wv == (an_ >> 6)) {                                                            \
+            const int m_ = (an_ & 63) >> 1, h_ = an_ & 1;                                  \
+            v2i x_;                                                                        \
+            x_.x = (int)pack16(tile_entry(g0, m_, h_), tile_entry(g1, m_, h_));            \
+            x_.y = (int)pack16(tile_entry(g2, m_, h_), tile_entry(g3, m_, h_));            \
+            *(v2i *)&rs.pcol[(par)][4 * lane] = x_;                                        \
+        }                                                                                  \
+    }
+
+    const lds_v4i *flags = rep_flags(rs.sync);
+    uint32_t seq = 0;      // steps of this replica's waits (also the update parity)
+    PDIT_REG_PUBLISH(0, pick(pk, 0), 0)
+    rep_signal(rs.sync, wv, ++seq);
     bool ok = true;        // every wait completed
-    __syncthreads();       // every read of p^-1 is done before the uniforms reuse the buffer
 
     for (int64_t t = 0; t < a.T && ok; ++t) {
         const float beta = bp[t * bstride];
-        const uint32_t g = (uint32_t)(a.sweep_offset + (uint64_t)t);
+        const uint32_t gsw = (uint32_t)(a.sweep_offset + (uint64_t)t);
         const int32_t dthr = zero_weight_distance(beta);
         int32_t *ch = ch_base ? ch_base + t * N : nullptr;
-        uint32_t *u24 = rs.u24[t & 1];
-        u24[l] = uniform24(a.seed, (uint32_t)l, g, (uint32_t)rep, a.inst_id);
+        int32_t uu[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            uu[i] = (int32_t)uniform24(a.seed, (uint32_t)(4 * lane + i), gsw, (uint32_t)rep,
+                                       a.inst_id);
 
         for (int r = 0; r < N && ok; ++r) {
-            const int rb = r & (kRBlock - 1);
-            if (rb == 0) {
-                // rows r .. r + 15 of G to LDS (their lanes are in one wave)
-                if ((l & ~(kRBlock - 1)) == r) {
-                    v32i *dst = (v32i *)rs.blk[l - r];
-                    dst[0] = g0;
-                    dst[1] = g1;
-                    dst[2] = g2;
-                    dst[3] = g3;
-                }
-                ok = rep_wait(rs.sync, w, ++seq);
-            }
+            const int par = (seq - 1) & 1;      // the buffer that holds row r, column p(r)
+            const int af = pick(pk, r);         // a = p(r)
+            const int16_t *prow = rs.prow[par];
             // ================= energy changes of the N candidates =================
-            const int af = rs.pv[r];
-            const int16_t *hrow = rs.blk[rb];      // H[r][k] = G[r][p(k)]
-            int32_t dv = kRBig;
-            if (valid) {
-                const int32_t hrs = hrow[p_l];
-                const int32_t hrr = hrow[af];
-                const int32_t hsr = row_entry(g0, g1, g2, g3, af);
-                const int32_t x = 2 * (hrs - hrr + hsr - diag);
-                const int32_t d_rl = sm.D[r * kRN + l];
-                const int32_t f_al = sm.F[af * kRN + p_l];
-                if (ZD) {
-                    dv = x + 4 * d_rl * f_al;
-                } else {
-                    const int32_t d_rr = sm.D[r * kRN + r];
-                    const int32_t f_aa = sm.F[af * kRN + af];
-                    dv = x + (d_rr + dd_l - 2 * d_rl) * (f_aa + fd_l - 2 * f_al);
-                }
-            }
+            // the flags and the publication (row r, column p(r)) in one LDS round
+            // trip; every read is issued before the first use
+            int32_t hrr_v, d_rr_v, f_aa_v, hr[4], fak[4];
+            v2i hc2;
+            uint32_t drw;
+#define PDIT_REG_READ_P                                                                    \
+    {                                                                                      \
+        hrr_v = prow[af];                                                                  \
+        hc2 = *(const v2i *)&rs.pcol[par][4 * lane];                                       \
+        drw = D32[r * (kRN / 4) + lane]; /* D[r][4 lane + t] */                            \
+        d_rr_v = ZD ? 0 : (int32_t)sm.D[r * kRN + r];                                      \
+        f_aa_v = ZD ? 0 : (int32_t)sm.F[af * kRN + af];                                    \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
+            hr[i] = prow[pk[i]];                                                           \
+            fak[i] = (int32_t)sm.F[af * kRN + pk[i]];                                      \
+        }                                                                                  \
+    }
             {
-                const int32_t m1 = wave_min_i32(dv);
-                const int32_t m2 = wave_min_i32(l == r ? kRBig : dv);
-                if (lane == 0) {
-                    rs.xmin[r & 1][w][0] = m1;
-                    rs.xmin[r & 1][w][1] = m2;
+                const v4i fl = *flags;
+                __asm__ volatile("" ::: "memory");
+                PDIT_REG_READ_P
+                if (!rep_done(fl, seq)) {
+                    ok = rep_spin(flags, seq);
+                    if (!ok) break;
+                    PDIT_REG_READ_P
                 }
             }
-            ok = ok && rep_wait(rs.sync, w, ++seq);
-
-            // ================= weights and their CDF =================
-            int32_t mn = rs.xmin[r & 1][0][0], mn2 = rs.xmin[r & 1][0][1];
+#undef PDIT_REG_READ_P
+            const int32_t hrr = __builtin_amdgcn_readfirstlane(hrr_v);
+            const int32_t d_rr = __builtin_amdgcn_readfirstlane(d_rr_v);
+            const int32_t f_aa = __builtin_amdgcn_readfirstlane(f_aa_v);
+            const int32_t hc[4] = {(int32_t)(int16_t)(hc2.x & 0xFFFF), hc2.x >> 16,
+                                   (int32_t)(int16_t)(hc2.y & 0xFFFF), hc2.y >> 16};
+            int32_t drk[4], dv[4];
+            int32_t m2 = kRBig;
 #pragma unroll
-            for (int k = 1; k < kRWaves; ++k) {
-                mn = min(mn, rs.xmin[r & 1][k][0]);
-                mn2 = min(mn2, rs.xmin[r & 1][k][1]);
+            for (int i = 0; i < 4; ++i) {
+                const int k = 4 * lane + i;
+                drk[i] = byte_at<SGN>(drw, i);
+                const int32_t x = 2 * (hr[i] - hrr + hc[i] - dg[i]);
+                const int32_t y = ZD ? 4 * __mul24(drk[i], fak[i])
+                                     : __mul24(d_rr + ddk[i] - 2 * drk[i], f_aa + fdk[i] - 2 * fak[i]);
+                dv[i] = k >= N ? kRBig : k == r ? 0 : x + y;
+                m2 = min(m2, k == r ? kRBig : dv[i]);
             }
-            // only the stay (dE = 0) carries weight: the draw keeps r
-            if (mn == 0 && mn2 >= dthr) {
-                if (ch && w == 0 && lane == 0) ch[r] = r;
-                continue;
-            }
-            uint32_t qw = 0;
-            {
-                const int32_t d = dv - mn;
-                const bool need = valid && d > 0 && d < dthr;
-                if (valid && d == 0) qw = kWeightOne;
-                if (__ballot(need)) {
-                    if (need) qw = gibbs_weight(beta, (float)d);
+            m2 = wave_min_i32(m2);                        // minimum over k != r
+            int s = r;
+            if (m2 < dthr) {
+                // ================= weights, CDF and the draw =================
+                const int32_t mn = min(m2, 0);
+                uint32_t q[4];
+                int32_t dd[4];
+                bool any = false;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    dd[i] = dv[i] - mn;                   // >= 0
+                    const bool valid = 4 * lane + i < N;
+                    q[i] = (valid && dd[i] == 0) ? kWeightOne : 0u;
+                    any = any || (valid && dd[i] > 0 && dd[i] < dthr);
                 }
-            }
-            const uint64_t C = wave_scan_u64((uint64_t)qw);
-            if (lane == 63) rs.xz[w] = C;
-            if (l == r) {
-                rs.xr[0] = C - qw;
-                rs.xr[1] = qw;
-            }
-            ok = ok && rep_wait(rs.sync, w, ++seq);
-
-            // ================= the draw =================
-            uint64_t off = 0, Z = 0, off_r = 0;
+                if (__ballot(any)) {
 #pragma unroll
-            for (int k = 0; k < kRWaves; ++k) {
-                const uint64_t zk = rs.xz[k];
-                if (k < w) off += zk;
-                if (k < (r >> 6)) off_r += zk;
-                Z += zk;
-            }
-            const uint32_t ur = u24[r];
-            const uint64_t thr = ((uint64_t)ur * Z) >> 24;  // first C > thr
-            const uint64_t c_prev = off_r + rs.xr[0];
-            const bool stay = c_prev <= thr && thr < c_prev + rs.xr[1];
-            const uint64_t zw = rs.xz[w];
-            if (off <= thr && thr < off + zw) {  // the wave holding the threshold
-                const uint64_t cg = off + C;
-                const uint64_t hit = __ballot(valid && cg > thr);
+                    for (int i = 0; i < 4; ++i) {
+                        const bool need = 4 * lane + i < N && dd[i] > 0 && dd[i] < dthr;
+                        const uint32_t wq = gibbs_weight(beta, (float)dd[i]);
+                        q[i] = need ? wq : q[i];
+                    }
+                }
+                // exact running sums: the lane's four weights (< 2^27) scanned as
+                // 16-bit halves, each half's wave sum within 32 bits
+                const uint32_t qs = q[0] + q[1] + q[2] + q[3];
+                const uint32_t slo = scan_u32(qs & 0xFFFFu);
+                const uint32_t shi = scan_u32(qs >> 16);
+                const uint64_t C = ((uint64_t)shi << 16) + slo;      // inclusive, by lane
+                const uint64_t Z = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)shi, 63) << 16) +
+                                   (uint32_t)__builtin_amdgcn_readlane((int)slo, 63);
+                const uint32_t ur = (uint32_t)pick(uu, r);
+                const uint64_t thr = ((uint64_t)ur * Z) >> 24;   // first C > thr
+                const uint64_t hit = __ballot(C > thr);
                 const int sl = __ffsll((unsigned long long)hit) - 1;
-                const int s = 64 * w + sl;
-                const uint64_t csel = readlane_u64(cg, sl);
-                const uint32_t qsel = (uint32_t)__builtin_amdgcn_readlane((int32_t)qw, sl);
-                n_tie += is_tie(csel - qsel, csel, Z, ur) ? 1 : 0;
-                if (ch && lane == 0) ch[r] = s;
-                if (s != r) {
-                    const int32_t dsel = __builtin_amdgcn_readlane(dv, sl);
-                    const int bf = rs.pv[s];
-                    // F[b][c] - F[a][c] for c = 4 lane .. 4 lane + 3, as two int16 pairs
-                    const uint32_t fa4 = ((const uint32_t *)sm.F)[af * (kRN / 4) + lane];
-                    const uint32_t fb4 = ((const uint32_t *)sm.F)[bf * (kRN / 4) + lane];
-                    int32_t dw[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int32_t xa = SGN ? (int32_t)(int8_t)(fa4 >> (8 * k))
-                                               : (int32_t)((fa4 >> (8 * k)) & 0xFF);
-                        const int32_t xb = SGN ? (int32_t)(int8_t)(fb4 >> (8 * k))
-                                               : (int32_t)((fb4 >> (8 * k)) & 0xFF);
-                        dw[k] = xb - xa;
-                    }
-                    rs.w[2 * lane] = pack16(dw[0], dw[1]);
-                    rs.w[2 * lane + 1] = pack16(dw[2], dw[3]);
-                    if (lane < kRBlock) {
-                        // u of the block's rows: D[i][r] - D[i][s], i = 16 (r / 16) + lane
-                        const int i = (r & ~(kRBlock - 1)) + lane;
-                        rs.ublk[lane] = (int16_t)((int32_t)sm.D[r * kRN + i] -
-                                                  (int32_t)sm.D[s * kRN + i]);
-                    }
-                    if (lane == 0) {
-                        rs.msg[0] = s;
-                        rs.msg[1] = dsel;
-                        rs.msg[2] = bf;
-                    }
-                }
+                // the first of the lane's four running sums above thr
+                const uint64_t c0 = C - qs + q[0], c1 = c0 + q[1], c2 = c1 + q[2];
+                const bool b0 = c0 > thr, b1 = c1 > thr, b2 = c2 > thr;
+                const int sel = b0 ? 0 : b1 ? 1 : b2 ? 2 : 3;
+                const uint64_t csel = b0 ? c0 : b1 ? c1 : b2 ? c2 : C;
+                const uint32_t qsel = b0 ? q[0] : b1 ? q[1] : b2 ? q[2] : q[3];
+                const int ssel = __builtin_amdgcn_readlane(sel, sl);
+                const uint64_t cs = readlane_u64(csel, sl);
+                const uint32_t qq = (uint32_t)__builtin_amdgcn_readlane((int32_t)qsel, sl);
+                n_tie += is_tie(cs - qq, cs, Z, ur) ? 1 : 0;
+                s = 4 * sl + ssel;
             }
-            if (stay) continue;
-            ok = ok && rep_wait(rs.sync, w, ++seq);
+            if (ch && lane == 0) ch[r] = s;
 
-            // ================= accepted exchange of r and s =================
-            {
-                const int s = rs.msg[0];
-                const int bf = rs.msg[2];
-                E += rs.msg[1];
+            if (s != r) {
+                // ================= accepted exchange of r and s =================
+                const int bf = pick(pk, s);           // b = p(s)
+                E += pick(dv, s);
                 ++n_acc;
-                // u_l = D[l][r] - D[l][s] (rows r and s of the symmetric D)
-                const int32_t u = valid ? (int32_t)sm.D[r * kRN + l] - (int32_t)sm.D[s * kRN + l] : 0;
-                const v32i *wv32 = (const v32i *)rs.w;
-                g0 = rank1(g0, (short)u, wv32[0]);
-                g1 = rank1(g1, (short)u, wv32[1]);
-                g2 = rank1(g2, (short)u, wv32[2]);
-                g3 = rank1(g3, (short)u, wv32[3]);
-                // the block's copy of rows 16 (r / 16) + i: lane (i, j) moves
-                // columns 16 j .. 16 j + 15 of row i
+                const uint32_t dsw = D32[s * (kRN / 4) + lane];   // D[s][4 lane + t]
+                const uint32_t fb4 = F32[bf * (kRN / 4) + lane];  // F[b][4 lane + t]
+                const uint32_t fa4 = F32[af * (kRN / 4) + lane];
+                const int32_t h_rb_v = prow[bf];                  // G[r][b]
+                const int32_t f_ba_v = (int32_t)sm.F[bf * kRN + af];
+                const int32_t f_bb_v = (int32_t)sm.F[bf * kRN + bf];
+                const int32_t f_ab_v = (int32_t)sm.F[af * kRN + bf];
+                int32_t fbk[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) fbk[i] = (int32_t)sm.F[bf * kRN + pk[i]];
+                // w of facilities 4 lane .. 4 lane + 3, to this wave's copy
+                int16_t *wl = rs.w[wv];
                 {
-                    const int i = l >> 4, j = l & 15;
-                    const short ui = rs.ublk[i];
-                    v8s *bp8 = (v8s *)&rs.blk[i][16 * j];
-                    const v8s *wp8 = (const v8s *)&rs.w[8 * j];
-                    const v8s b0 = bp8[0], b1 = bp8[1];
-                    bp8[0] = b0 + (v8s)ui * wp8[0];
-                    bp8[1] = b1 + (v8s)ui * wp8[1];
+                    v2i x;
+                    x.x = (int)pack16(byte_at<SGN>(fb4, 0) - byte_at<SGN>(fa4, 0),
+                                      byte_at<SGN>(fb4, 1) - byte_at<SGN>(fa4, 1));
+                    x.y = (int)pack16(byte_at<SGN>(fb4, 2) - byte_at<SGN>(fa4, 2),
+                                      byte_at<SGN>(fb4, 3) - byte_at<SGN>(fa4, 3));
+                    *(v2i *)&wl[4 * lane] = x;
                 }
-                // diag H: H'[l][l] = G'[l][p'(l)]; off {r, s} p(l) stays and
-                // the change is u_l (F[b][p(l)] - F[a][p(l)])
-                const int32_t at_b = row_entry(g0, g1, g2, g3, bf);
-                const int32_t at_a = row_entry(g0, g1, g2, g3, af);
-                if (l == r) {
-                    p_l = bf;
-                    diag = at_b;
-                } else if (l == s) {
-                    p_l = af;
-                    diag = at_a;
-                } else {
-                    diag += u * (int32_t)((const int16_t *)rs.w)[p_l];
+                // LDS accesses of one wave complete in order: this read sees the
+                // whole wave's writes
+                __asm__ volatile("" ::: "memory");
+                const v32i wt = *(const v32i *)&wl[64 * wv];     // w of the wave's facilities
+                int32_t u[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) u[i] = drk[i] - byte_at<SGN>(dsw, i);
+                const int32_t h_rb = __builtin_amdgcn_readfirstlane(h_rb_v);
+                const int32_t f_bb = __builtin_amdgcn_readfirstlane(f_bb_v);
+                const int32_t w_a = __builtin_amdgcn_readfirstlane(f_ba_v) - f_aa;  // F[b][a] - F[a][a]
+                const int32_t w_b = f_bb - __builtin_amdgcn_readfirstlane(f_ab_v);  // F[b][b] - F[a][b]
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 4 * lane + i;
+                    const int32_t wp = fbk[i] - fak[i];           // w at p(k)
+                    const bool is_r = k == r, is_s = k == s;
+                    dg[i] = is_r ? h_rb + __mul24(u[i], w_b)       // G'[r][b]
+                          : is_s ? hc[i] + __mul24(u[i], w_a)      // G'[s][a]
+                                 : dg[i] + __mul24(u[i], wp);
+                    if (!ZD) fdk[i] = is_r ? f_bb : is_s ? f_aa : fdk[i];
+                    pk[i] = is_r ? bf : is_s ? af : pk[i];
                 }
-                if (!ZD && (l == r || l == s)) fd_l = (int32_t)sm.F[p_l * kRN + p_l];
-                if (l == r || l == s) rs.pv[l] = p_l;
+                // the tile: G += u w over the wave's 64 facilities
+                g0 = rank1(g0, (short)u[0], wt);
+                g1 = rank1(g1, (short)u[1], wt);
+                g2 = rank1(g2, (short)u[2], wt);
+                g3 = rank1(g3, (short)u[3], wt);
                 if (E < E_best) {
                     E_best = E;
-                    if (live && valid) a.perm_best[rep * N + l] = p_l;
+                    if (writer) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int k = 4 * lane + i;
+                            if (k < N) a.perm_best[rep * N + k] = pk[i];
+                        }
+                    }
                 }
             }
-            ok = ok && rep_wait(rs.sync, w, ++seq);
+            // ================= publish row r + 1 and its column =================
+            const int nr = r + 1 < N ? r + 1 : 0;
+            PDIT_REG_PUBLISH(nr, pick(pk, nr), seq & 1)
+            rep_signal(rs.sync, wv, ++seq);
         }
-        if (a.E_trace && live && l == 0) a.E_trace[rep * a.T + t] = E;
+        if (a.E_trace && writer && lane == 0) a.E_trace[rep * a.T + t] = E;
     }
 
+#undef PDIT_REG_PUBLISH
     // ---- outputs ----
     if (!ok && a.err) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (lane == 0) rs.ties[w] = n_tie;
-    __syncthreads();
-    if (live) {
-        if (valid) a.perm[rep * N + l] = p_l;
-        if (l == 0) {
-            int64_t ties = 0;
+    if (writer) {
 #pragma unroll
-            for (int k = 0; k < kRWaves; ++k) ties += rs.ties[k];
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * lane + i;
+            if (k < N) a.perm[rep * N + k] = pk[i];
+        }
+        if (lane == 0) {
             a.E[rep] = E;
             a.E_best[rep] = E_best;
             const bool accum = (a.flags & kAccumCounters) != 0;
             a.counters[3 * rep + 0] = (accum ? a.counters[3 * rep + 0] : 0) + (int64_t)N * a.T;
             a.counters[3 * rep + 1] = (accum ? a.counters[3 * rep + 1] : 0) + n_acc;
-            a.counters[3 * rep + 2] = (accum ? a.counters[3 * rep + 2] : 0) + ties;
+            a.counters[3 * rep + 2] = (accum ? a.counters[3 * rep + 2] : 0) + n_tie;
         }
     }
 }
