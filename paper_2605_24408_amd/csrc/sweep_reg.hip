@@ -33,6 +33,16 @@
 // nonzero weight is its own stay (every other candidate lies at or beyond the
 // zero-weight distance above 0) keeps its facility without weights or scan.
 //
+// Batches.  An update that keeps its facility changes nothing, so when few
+// exchanges are accepted the updates of locations r0 .. r0 + 11 can all be
+// evaluated on the same state: the waves publish the 12 rows and columns
+// together, each wave evaluates three of the updates, and the stays up to
+// the first exchange are committed.  The update with that exchange then runs
+// as a single update on the batch's row and column (it draws the same
+// candidate, the state being the one it was evaluated on) and the next batch
+// starts after it.  Every draw is the sequential one; a sweep runs in
+// batches when the sweep before it accepted at most kRSpecAcc exchanges.
+//
 // Two replicas share a workgroup (eight waves, each SIMD holding one wave of
 // each) and its LDS: D and F as 8-bit copies (64 KB each, unsigned in
 // [0, 255] or signed in [-128, 127]), so every read of D and F on the path
@@ -51,6 +61,10 @@ constexpr int kRWaves = 4;        // waves per replica
 constexpr int kRReps = 2;         // replicas per workgroup
 constexpr int kRThreads = 64 * kRWaves * kRReps;
 constexpr int32_t kRBig = (1 << 30) - 1;  // padding candidates (|dE| < 2^30 - 1)
+// Batches: kRSpec consecutive updates evaluated on one state (kRSpec / kRWaves
+// per wave) when the previous sweep accepted at most kRSpecAcc exchanges
+constexpr int kRSpec = 12;
+constexpr int kRSpecAcc = 48;
 // spins of a replica's wait before it gives up (about 0.1 s): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
 // control flow excludes; the call then reports PDIT_EDEVICE at pdit_sync
@@ -62,11 +76,20 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
 struct alignas(16) RegRep {
-    alignas(16) int16_t prow[2][kRN];     // row r of G by facility (by update parity)
-    alignas(16) int16_t pcol[2][kRN];     // column p(r) of G by location (by update parity)
-    alignas(16) int16_t w[kRWaves][kRN];  // per wave: the accepted exchange's w, by facility
-    alignas(16) uint32_t sync[kRWaves];   // per wave: the last step it finished
-    int32_t pinv[kRN];                    // set-up: p^-1
+    union {
+        struct {                               // one update at a time
+            alignas(16) int16_t prow[2][kRN];  // row r of G by facility (by update parity)
+            alignas(16) int16_t pcol[2][kRN];  // column p(r) of G by location
+        } sq;
+        struct {                               // a batch of kRSpec updates
+            alignas(16) int16_t brow[kRSpec][kRN];
+            alignas(16) int16_t bcol[kRSpec][kRN];
+        } sp;
+        int32_t pinv[kRN];                     // set-up: p^-1
+    } u;
+    alignas(16) int16_t w[kRWaves][kRN];       // per wave: the accepted exchange's w, by facility
+    alignas(16) v4i outc[kRSpec];              // batch: per update its draw s and tie flag
+    alignas(16) uint32_t sync[kRWaves];        // per wave: the last step it finished
 };
 
 template <bool SGN>
@@ -213,7 +236,7 @@ sweep_reg_kernel(SweepArgs a) {
     for (int t = 0; t < 4; ++t) {
         const int k = 4 * lane + t;
         pk[t] = k < N ? a.perm[rep * N + k] : k;
-        if (wv == 0) rs.pinv[pk[t]] = k;
+        if (wv == 0) rs.u.pinv[pk[t]] = k;
     }
     if (lane < kRWaves && wv == 0) rs.sync[lane] = 0;
     __syncthreads();
@@ -225,7 +248,7 @@ sweep_reg_kernel(SweepArgs a) {
 #pragma unroll
         for (int m = 0; m < 32; ++m) {
             const int c0 = 64 * wv + 2 * m, c1 = c0 + 1;
-            const int j0 = c0 < N ? rs.pinv[c0] : -1, j1 = c1 < N ? rs.pinv[c1] : -1;
+            const int j0 = c0 < N ? rs.u.pinv[c0] : -1, j1 = c1 < N ? rs.u.pinv[c1] : -1;
 #define PDIT_G_AT(t, j) ((4 * lane + (t) < N && (j) >= 0) ? Hb[(4 * lane + (t)) * (int64_t)N + (j)] : 0)
             g0[m] = (int)pack16(PDIT_G_AT(0, j0), PDIT_G_AT(0, j1));
             g1[m] = (int)pack16(PDIT_G_AT(1, j0), PDIT_G_AT(1, j1));
@@ -252,33 +275,205 @@ sweep_reg_kernel(SweepArgs a) {
     const int64_t bstride = a.slot ? 0 : 1;
     const bool writer = live && wv == 0;   // wave 0 writes the replica's outputs
 
-    // publication of row nr and of the column at facility an, into buffer par
+    // every wave has read p^-1 before the publications (which share its LDS) begin
+    __syncthreads();
+
+    // ---------------- publication ----------------
+    // the column of G at facility an, for this lane's four locations, to dst
+#define PDIT_REG_STORE_COL(an, dst)                                                        \
+    {                                                                                      \
+        const int an_ = __builtin_amdgcn_readfirstlane(an);                                \
+        if (wv == (an_ >> 6)) {                                                            \
+            const int m_ = (an_ & 63) >> 1, h_ = an_ & 1;                                  \
+            v2i x_;                                                                        \
+            x_.x = (int)pack16(tile_entry(g0, m_, h_), tile_entry(g1, m_, h_));            \
+            x_.y = (int)pack16(tile_entry(g2, m_, h_), tile_entry(g3, m_, h_));            \
+            *(v2i *)&(dst)[4 * lane] = x_;                                                 \
+        }                                                                                  \
+    }
+    // row nr (the wave's 64 facilities) and the column at facility an, into buffer par
 #define PDIT_REG_PUBLISH(nr, an, par)                                                      \
     {                                                                                      \
         const int nr_ = __builtin_amdgcn_readfirstlane(nr);                                \
-        const int an_ = __builtin_amdgcn_readfirstlane(an);                                \
         if (lane == (nr_ >> 2)) {                                                          \
-            const uint32_t dst_ = lds_addr(&rs.prow[(par)][64 * wv]);                      \
+            const uint32_t dst_ = lds_addr(&rs.u.sq.prow[(par)][64 * wv]);                 \
             const int t_ = nr_ & 3;                                                        \
             if (t_ == 0) PDIT_REG_STORE_ROW(dst_, g0, "0");                                \
             else if (t_ == 1) PDIT_REG_STORE_ROW(dst_, g1, "1");                           \
             else if (t_ == 2) PDIT_REG_STORE_ROW(dst_, g2, "2");                           \
             else PDIT_REG_STORE_ROW(dst_, g3, "3");                                        \
         }                                                                                  \
-        if (wv == (an_ >> 6)) {                                                            \
-            const int m_ = (an_ & 63) >> 1, h_ = an_ & 1;                                  \
-            v2i x_;                                                                        \
-            x_.x = (int)pack16(tile_entry(g0, m_, h_), tile_entry(g1, m_, h_));            \
-            x_.y = (int)pack16(tile_entry(g2, m_, h_), tile_entry(g3, m_, h_));            \
-            *(v2i *)&rs.pcol[(par)][4 * lane] = x_;                                        \
+        PDIT_REG_STORE_COL(an, rs.u.sq.pcol[(par)])                                        \
+    }
+    // rows r0 .. r0 + nb - 1 and their columns, into the batch buffers
+#define PDIT_REG_PUBLISH_BATCH(r0, nb)                                                     \
+    {                                                                                      \
+        const int row_ = 4 * lane - (r0);                                                  \
+        const uint32_t dst_ = lds_addr(&rs.u.sp.brow[0][64 * wv]) + 2 * kRN * row_;        \
+        if (row_ >= 0 && row_ < (nb)) PDIT_REG_STORE_ROW(dst_, g0, "b0");                  \
+        if (row_ + 1 >= 0 && row_ + 1 < (nb)) PDIT_REG_STORE_ROW(dst_ + 2 * kRN, g1, "b1");\
+        if (row_ + 2 >= 0 && row_ + 2 < (nb)) PDIT_REG_STORE_ROW(dst_ + 4 * kRN, g2, "b2");\
+        if (row_ + 3 >= 0 && row_ + 3 < (nb)) PDIT_REG_STORE_ROW(dst_ + 6 * kRN, g3, "b3");\
+        for (int j_ = 0; j_ < (nb); ++j_) PDIT_REG_STORE_COL(pick(pk, (r0) + j_), rs.u.sp.bcol[j_]) \
+    }
+
+    // ---------------- one update's candidates ----------------
+    // LDS reads for the update of location R (a = AF) from row PROW and column PCOL
+    int32_t hrr_v, d_rr_v, f_aa_v, hr[4], fak[4];
+    v2i hc2;
+    uint32_t drw;
+#define PDIT_REG_READS(PROW, PCOL, R, AF)                                                  \
+    {                                                                                      \
+        hrr_v = (PROW)[AF];                                                                \
+        hc2 = *(const v2i *)&(PCOL)[4 * lane];                                             \
+        drw = D32[(R) * (kRN / 4) + lane]; /* D[r][4 lane + t] */                          \
+        d_rr_v = ZD ? 0 : (int32_t)sm.D[(R) * kRN + (R)];                                  \
+        f_aa_v = ZD ? 0 : (int32_t)sm.F[(AF) * kRN + (AF)];                                \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
+            hr[i] = (PROW)[pk[i]];                                                         \
+            fak[i] = (int32_t)sm.F[(AF) * kRN + pk[i]];                                    \
+        }                                                                                  \
+    }
+    int32_t hrr, d_rr, f_aa, hc[4], drk[4], dv[4], m2;
+    // dE of the N candidates (four per lane) and the minimum over k != R
+#define PDIT_REG_DELTA(R)                                                                  \
+    {                                                                                      \
+        hrr = __builtin_amdgcn_readfirstlane(hrr_v);                                       \
+        d_rr = __builtin_amdgcn_readfirstlane(d_rr_v);                                     \
+        f_aa = __builtin_amdgcn_readfirstlane(f_aa_v);                                     \
+        hc[0] = (int32_t)(int16_t)(hc2.x & 0xFFFF);                                        \
+        hc[1] = hc2.x >> 16;                                                               \
+        hc[2] = (int32_t)(int16_t)(hc2.y & 0xFFFF);                                        \
+        hc[3] = hc2.y >> 16;                                                               \
+        m2 = kRBig;                                                                        \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
+            const int k = 4 * lane + i;                                                    \
+            drk[i] = byte_at<SGN>(drw, i);                                                 \
+            const int32_t x = 2 * (hr[i] - hrr + hc[i] - dg[i]);                           \
+            const int32_t y = ZD ? 4 * __mul24(drk[i], fak[i])                             \
+                                 : __mul24(d_rr + ddk[i] - 2 * drk[i], f_aa + fdk[i] - 2 * fak[i]); \
+            dv[i] = k >= N ? kRBig : k == (R) ? 0 : x + y;                                 \
+            m2 = min(m2, k == (R) ? kRBig : dv[i]);                                        \
+        }                                                                                  \
+        m2 = wave_min_i32(m2);                                                             \
+    }
+    // the draw of the update of location R: S (R for a stay) and whether its
+    // threshold fell within the tie band (TIE)
+#define PDIT_REG_DRAW(R, S, TIE)                                                           \
+    {                                                                                      \
+        S = (R);                                                                           \
+        TIE = 0;                                                                           \
+        if (m2 < dthr) {                                                                   \
+            const int32_t mn = min(m2, 0);                                                 \
+            uint32_t q[4];                                                                 \
+            int32_t dd[4];                                                                 \
+            bool any = false;                                                              \
+            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                \
+                dd[i] = dv[i] - mn; /* >= 0 */                                             \
+                const bool valid = 4 * lane + i < N;                                       \
+                q[i] = (valid && dd[i] == 0) ? kWeightOne : 0u;                            \
+                any = any || (valid && dd[i] > 0 && dd[i] < dthr);                         \
+            }                                                                              \
+            if (__ballot(any)) {                                                           \
+                _Pragma("unroll") for (int i = 0; i < 4; ++i) {                            \
+                    const bool need = 4 * lane + i < N && dd[i] > 0 && dd[i] < dthr;       \
+                    const uint32_t wq = gibbs_weight(beta, (float)dd[i]);                  \
+                    q[i] = need ? wq : q[i];                                               \
+                }                                                                          \
+            }                                                                              \
+            /* exact running sums: the lane's four weights (< 2^27) scanned as */          \
+            /* 16-bit halves, each half's wave sum within 32 bits */                       \
+            const uint32_t qs = q[0] + q[1] + q[2] + q[3];                                 \
+            const uint32_t slo = scan_u32(qs & 0xFFFFu);                                   \
+            const uint32_t shi = scan_u32(qs >> 16);                                       \
+            const uint64_t C = ((uint64_t)shi << 16) + slo;                                \
+            const uint64_t Z =                                                             \
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)shi, 63) << 16) +      \
+                (uint32_t)__builtin_amdgcn_readlane((int)slo, 63);                         \
+            const uint32_t ur = (uint32_t)pick(uu, (R));                                   \
+            const uint64_t thr = ((uint64_t)ur * Z) >> 24; /* first C > thr */             \
+            const uint64_t hit = __ballot(C > thr);                                        \
+            const int sl = __ffsll((unsigned long long)hit) - 1;                           \
+            const uint64_t c0 = C - qs + q[0], c1 = c0 + q[1], c2 = c1 + q[2];             \
+            const bool b0 = c0 > thr, b1 = c1 > thr, b2 = c2 > thr;                        \
+            const int sel = b0 ? 0 : b1 ? 1 : b2 ? 2 : 3;                                  \
+            const uint64_t csel = b0 ? c0 : b1 ? c1 : b2 ? c2 : C;                         \
+            const uint32_t qsel = b0 ? q[0] : b1 ? q[1] : b2 ? q[2] : q[3];                \
+            const int ssel = __builtin_amdgcn_readlane(sel, sl);                           \
+            const uint64_t cs = readlane_u64(csel, sl);                                    \
+            const uint32_t qq = (uint32_t)__builtin_amdgcn_readlane((int32_t)qsel, sl);    \
+            TIE = is_tie(cs - qq, cs, Z, ur) ? 1 : 0;                                      \
+            S = 4 * sl + ssel;                                                             \
+        }                                                                                  \
+    }
+    // the accepted exchange of R and S (a = AF): dE DES; G[R][b] from row PROW,
+    // hc_s = G[S][a]; drk, fak and f_aa hold the update's D and F reads
+#define PDIT_REG_ACCEPT(R, S, AF, DES, PROW, HC_S)                                         \
+    {                                                                                      \
+        const int bf = pick(pk, (S)); /* b = p(s) */                                       \
+        const int32_t h_rb_v = (int32_t)(PROW)[bf];                                        \
+        E += (DES);                                                                        \
+        ++n_acc;                                                                           \
+        const uint32_t dsw = D32[(S) * (kRN / 4) + lane]; /* D[s][4 lane + t] */           \
+        const uint32_t fb4 = F32[bf * (kRN / 4) + lane];  /* F[b][4 lane + t] */           \
+        const uint32_t fa4 = F32[(AF) * (kRN / 4) + lane];                                 \
+        const int32_t f_ba_v = (int32_t)sm.F[bf * kRN + (AF)];                             \
+        const int32_t f_bb_v = (int32_t)sm.F[bf * kRN + bf];                               \
+        const int32_t f_ab_v = (int32_t)sm.F[(AF) * kRN + bf];                             \
+        int32_t fbk[4];                                                                    \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) fbk[i] = (int32_t)sm.F[bf * kRN + pk[i]]; \
+        /* w of facilities 4 lane .. 4 lane + 3, to this wave's copy */                    \
+        int16_t *wl = rs.w[wv];                                                            \
+        {                                                                                  \
+            v2i x;                                                                         \
+            x.x = (int)pack16(byte_at<SGN>(fb4, 0) - byte_at<SGN>(fa4, 0),                 \
+                              byte_at<SGN>(fb4, 1) - byte_at<SGN>(fa4, 1));                \
+            x.y = (int)pack16(byte_at<SGN>(fb4, 2) - byte_at<SGN>(fa4, 2),                 \
+                              byte_at<SGN>(fb4, 3) - byte_at<SGN>(fa4, 3));                \
+            *(v2i *)&wl[4 * lane] = x;                                                     \
+        }                                                                                  \
+        /* LDS accesses of one wave complete in order: this read sees the */               \
+        /* whole wave's writes */                                                          \
+        __asm__ volatile("" ::: "memory");                                                 \
+        const v32i wt = *(const v32i *)&wl[64 * wv]; /* w of the wave's facilities */      \
+        int32_t u[4];                                                                      \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) u[i] = drk[i] - byte_at<SGN>(dsw, i); \
+        const int32_t f_bb = __builtin_amdgcn_readfirstlane(f_bb_v);                       \
+        const int32_t h_rb = __builtin_amdgcn_readfirstlane(h_rb_v);                       \
+        const int32_t w_a = __builtin_amdgcn_readfirstlane(f_ba_v) - f_aa; /* F[b][a] - F[a][a] */ \
+        const int32_t w_b = f_bb - __builtin_amdgcn_readfirstlane(f_ab_v); /* F[b][b] - F[a][b] */ \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
+            const int k = 4 * lane + i;                                                    \
+            const int32_t wp = fbk[i] - fak[i]; /* w at p(k) */                            \
+            const bool is_r = k == (R), is_s = k == (S);                                   \
+            dg[i] = is_r ? h_rb + __mul24(u[i], w_b)        /* G'[r][b] */                 \
+                  : is_s ? (HC_S) + __mul24(u[i], w_a)      /* G'[s][a] */                 \
+                         : dg[i] + __mul24(u[i], wp);                                      \
+            if (!ZD) fdk[i] = is_r ? f_bb : is_s ? f_aa : fdk[i];                          \
+            pk[i] = is_r ? bf : is_s ? (AF) : pk[i];                                       \
+        }                                                                                  \
+        /* the tile: G += u w over the wave's 64 facilities */                             \
+        g0 = rank1(g0, (short)u[0], wt);                                                   \
+        g1 = rank1(g1, (short)u[1], wt);                                                   \
+        g2 = rank1(g2, (short)u[2], wt);                                                   \
+        g3 = rank1(g3, (short)u[3], wt);                                                   \
+        if (E < E_best) {                                                                  \
+            E_best = E;                                                                    \
+            if (writer) {                                                                  \
+                _Pragma("unroll") for (int i = 0; i < 4; ++i) {                            \
+                    const int k = 4 * lane + i;                                            \
+                    if (k < N) a.perm_best[rep * N + k] = pk[i];                           \
+                }                                                                          \
+            }                                                                              \
         }                                                                                  \
     }
 
     const lds_v4i *flags = rep_flags(rs.sync);
-    uint32_t seq = 0;      // steps of this replica's waits (also the update parity)
+    uint32_t seq = 0;      // steps of this replica's waits
     PDIT_REG_PUBLISH(0, pick(pk, 0), 0)
     rep_signal(rs.sync, wv, ++seq);
     bool ok = true;        // every wait completed
+    bool batch = false;    // this sweep runs in batches
 
     for (int64_t t = 0; t < a.T && ok; ++t) {
         const float beta = bp[t * bstride];
@@ -290,178 +485,135 @@ sweep_reg_kernel(SweepArgs a) {
         for (int i = 0; i < 4; ++i)
             uu[i] = (int32_t)uniform24(a.seed, (uint32_t)(4 * lane + i), gsw, (uint32_t)rep,
                                        a.inst_id);
+        const int64_t acc0 = n_acc;
+        // the next sweep runs in batches when this one accepts few exchanges
+#define PDIT_REG_NEXT_BATCH() (t + 1 < a.T && n_acc - acc0 <= kRSpecAcc)
 
-        for (int r = 0; r < N && ok; ++r) {
-            const int par = (seq - 1) & 1;      // the buffer that holds row r, column p(r)
+        // Steps: one update, which every wave evaluates, or in a batch sweep a
+        // batch of kRSpec updates evaluated on one state, kRSpec / kRWaves per
+        // wave.  A batch commits its stays up to the first exchange; the update
+        // with the exchange then runs as a single update on the batch's row and
+        // column, which draws the same candidate.
+        if (batch && !rep_done(*flags, seq)) ok = rep_spin(flags, seq);  // buffers free
+        bool replayed = false;                  // batch: the last step was a single update
+        int r0 = 0;
+        while (r0 < N && ok) {
+            const int16_t *prow, *pcol;
+            bool fresh = true;                  // the row and column were just published
+            if (batch) {
+                // ============ a batch: rows r0 .. r0 + nb - 1 ============
+                if (replayed && !rep_done(*flags, seq)) {  // every wave left that update
+                    ok = rep_spin(flags, seq);
+                    if (!ok) break;
+                }
+                const int nb = min(kRSpec, N - r0);
+                PDIT_REG_PUBLISH_BATCH(r0, nb)
+                rep_signal(rs.sync, wv, ++seq);
+                // this wave's updates j = wv, wv + kRWaves, ...: the draw and its tie
+                // flag to the outcome slots
+                for (int j = wv; j < nb; j += kRWaves) {
+                    const int rj = r0 + j;
+                    const int af = pick(pk, rj);
+                    const int16_t *brow = rs.u.sp.brow[j];
+                    {
+                        const v4i fl = *flags;
+                        __asm__ volatile("" ::: "memory");
+                        PDIT_REG_READS(brow, rs.u.sp.bcol[j], rj, af)
+                        if (j == wv && !rep_done(fl, seq)) {
+                            ok = rep_spin(flags, seq);
+                            if (!ok) break;
+                            PDIT_REG_READS(brow, rs.u.sp.bcol[j], rj, af)
+                        }
+                    }
+                    PDIT_REG_DELTA(rj)
+                    int sj, tie;
+                    PDIT_REG_DRAW(rj, sj, tie)
+                    if (lane == 0) rs.outc[j] = v4i{sj, tie, 0, 0};
+                }
+                if (!ok) break;
+                rep_signal(rs.sync, wv, ++seq);
+                // the outcomes: the first exchange ends the batch
+                v4i o;
+                {
+                    const v4i fl = *flags;
+                    __asm__ volatile("" ::: "memory");
+                    o = rs.outc[lane < nb ? lane : 0];
+                    if (!rep_done(fl, seq)) {
+                        ok = rep_spin(flags, seq);
+                        if (!ok) break;
+                        o = rs.outc[lane < nb ? lane : 0];
+                    }
+                }
+                const uint64_t moves = __ballot(lane < nb && o.x != r0 + lane);
+                const int jm = moves ? __ffsll((unsigned long long)moves) - 1 : nb;
+                n_tie += __popcll(__ballot(lane < jm && o.y != 0));
+                if (ch && lane < jm) ch[r0 + lane] = o.x;
+                replayed = false;
+                if (jm == nb) {
+                    r0 += nb;
+                    continue;
+                }
+                r0 += jm;
+                prow = rs.u.sp.brow[jm];
+                pcol = rs.u.sp.bcol[jm];
+                fresh = false;
+            } else {
+                const int par = (seq - 1) & 1;  // the buffer that holds row r0, column p(r0)
+                prow = rs.u.sq.prow[par];
+                pcol = rs.u.sq.pcol[par];
+            }
+            // ============ one update: location r0 ============
+            const int r = r0;
             const int af = pick(pk, r);         // a = p(r)
-            const int16_t *prow = rs.prow[par];
-            // ================= energy changes of the N candidates =================
-            // the flags and the publication (row r, column p(r)) in one LDS round
-            // trip; every read is issued before the first use
-            int32_t hrr_v, d_rr_v, f_aa_v, hr[4], fak[4];
-            v2i hc2;
-            uint32_t drw;
-#define PDIT_REG_READ_P                                                                    \
-    {                                                                                      \
-        hrr_v = prow[af];                                                                  \
-        hc2 = *(const v2i *)&rs.pcol[par][4 * lane];                                       \
-        drw = D32[r * (kRN / 4) + lane]; /* D[r][4 lane + t] */                            \
-        d_rr_v = ZD ? 0 : (int32_t)sm.D[r * kRN + r];                                      \
-        f_aa_v = ZD ? 0 : (int32_t)sm.F[af * kRN + af];                                    \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
-            hr[i] = prow[pk[i]];                                                           \
-            fak[i] = (int32_t)sm.F[af * kRN + pk[i]];                                      \
-        }                                                                                  \
-    }
+            // the flags and the publication in one LDS round trip
             {
                 const v4i fl = *flags;
                 __asm__ volatile("" ::: "memory");
-                PDIT_REG_READ_P
-                if (!rep_done(fl, seq)) {
+                PDIT_REG_READS(prow, pcol, r, af)
+                if (fresh && !rep_done(fl, seq)) {
                     ok = rep_spin(flags, seq);
                     if (!ok) break;
-                    PDIT_REG_READ_P
+                    PDIT_REG_READS(prow, pcol, r, af)
                 }
             }
-#undef PDIT_REG_READ_P
-            const int32_t hrr = __builtin_amdgcn_readfirstlane(hrr_v);
-            const int32_t d_rr = __builtin_amdgcn_readfirstlane(d_rr_v);
-            const int32_t f_aa = __builtin_amdgcn_readfirstlane(f_aa_v);
-            const int32_t hc[4] = {(int32_t)(int16_t)(hc2.x & 0xFFFF), hc2.x >> 16,
-                                   (int32_t)(int16_t)(hc2.y & 0xFFFF), hc2.y >> 16};
-            int32_t drk[4], dv[4];
-            int32_t m2 = kRBig;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = 4 * lane + i;
-                drk[i] = byte_at<SGN>(drw, i);
-                const int32_t x = 2 * (hr[i] - hrr + hc[i] - dg[i]);
-                const int32_t y = ZD ? 4 * __mul24(drk[i], fak[i])
-                                     : __mul24(d_rr + ddk[i] - 2 * drk[i], f_aa + fdk[i] - 2 * fak[i]);
-                dv[i] = k >= N ? kRBig : k == r ? 0 : x + y;
-                m2 = min(m2, k == r ? kRBig : dv[i]);
-            }
-            m2 = wave_min_i32(m2);                        // minimum over k != r
-            int s = r;
-            if (m2 < dthr) {
-                // ================= weights, CDF and the draw =================
-                const int32_t mn = min(m2, 0);
-                uint32_t q[4];
-                int32_t dd[4];
-                bool any = false;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    dd[i] = dv[i] - mn;                   // >= 0
-                    const bool valid = 4 * lane + i < N;
-                    q[i] = (valid && dd[i] == 0) ? kWeightOne : 0u;
-                    any = any || (valid && dd[i] > 0 && dd[i] < dthr);
-                }
-                if (__ballot(any)) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const bool need = 4 * lane + i < N && dd[i] > 0 && dd[i] < dthr;
-                        const uint32_t wq = gibbs_weight(beta, (float)dd[i]);
-                        q[i] = need ? wq : q[i];
-                    }
-                }
-                // exact running sums: the lane's four weights (< 2^27) scanned as
-                // 16-bit halves, each half's wave sum within 32 bits
-                const uint32_t qs = q[0] + q[1] + q[2] + q[3];
-                const uint32_t slo = scan_u32(qs & 0xFFFFu);
-                const uint32_t shi = scan_u32(qs >> 16);
-                const uint64_t C = ((uint64_t)shi << 16) + slo;      // inclusive, by lane
-                const uint64_t Z = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)shi, 63) << 16) +
-                                   (uint32_t)__builtin_amdgcn_readlane((int)slo, 63);
-                const uint32_t ur = (uint32_t)pick(uu, r);
-                const uint64_t thr = ((uint64_t)ur * Z) >> 24;   // first C > thr
-                const uint64_t hit = __ballot(C > thr);
-                const int sl = __ffsll((unsigned long long)hit) - 1;
-                // the first of the lane's four running sums above thr
-                const uint64_t c0 = C - qs + q[0], c1 = c0 + q[1], c2 = c1 + q[2];
-                const bool b0 = c0 > thr, b1 = c1 > thr, b2 = c2 > thr;
-                const int sel = b0 ? 0 : b1 ? 1 : b2 ? 2 : 3;
-                const uint64_t csel = b0 ? c0 : b1 ? c1 : b2 ? c2 : C;
-                const uint32_t qsel = b0 ? q[0] : b1 ? q[1] : b2 ? q[2] : q[3];
-                const int ssel = __builtin_amdgcn_readlane(sel, sl);
-                const uint64_t cs = readlane_u64(csel, sl);
-                const uint32_t qq = (uint32_t)__builtin_amdgcn_readlane((int32_t)qsel, sl);
-                n_tie += is_tie(cs - qq, cs, Z, ur) ? 1 : 0;
-                s = 4 * sl + ssel;
-            }
+            PDIT_REG_DELTA(r)
+            int s, tie;
+            PDIT_REG_DRAW(r, s, tie)
+            n_tie += tie;
             if (ch && lane == 0) ch[r] = s;
-
-            if (s != r) {
-                // ================= accepted exchange of r and s =================
-                const int bf = pick(pk, s);           // b = p(s)
-                E += pick(dv, s);
-                ++n_acc;
-                const uint32_t dsw = D32[s * (kRN / 4) + lane];   // D[s][4 lane + t]
-                const uint32_t fb4 = F32[bf * (kRN / 4) + lane];  // F[b][4 lane + t]
-                const uint32_t fa4 = F32[af * (kRN / 4) + lane];
-                const int32_t h_rb_v = prow[bf];                  // G[r][b]
-                const int32_t f_ba_v = (int32_t)sm.F[bf * kRN + af];
-                const int32_t f_bb_v = (int32_t)sm.F[bf * kRN + bf];
-                const int32_t f_ab_v = (int32_t)sm.F[af * kRN + bf];
-                int32_t fbk[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) fbk[i] = (int32_t)sm.F[bf * kRN + pk[i]];
-                // w of facilities 4 lane .. 4 lane + 3, to this wave's copy
-                int16_t *wl = rs.w[wv];
-                {
-                    v2i x;
-                    x.x = (int)pack16(byte_at<SGN>(fb4, 0) - byte_at<SGN>(fa4, 0),
-                                      byte_at<SGN>(fb4, 1) - byte_at<SGN>(fa4, 1));
-                    x.y = (int)pack16(byte_at<SGN>(fb4, 2) - byte_at<SGN>(fa4, 2),
-                                      byte_at<SGN>(fb4, 3) - byte_at<SGN>(fa4, 3));
-                    *(v2i *)&wl[4 * lane] = x;
+            if (s != r) PDIT_REG_ACCEPT(r, s, af, pick(dv, s), prow, pick(hc, s))
+            ++r0;
+            if (!batch) {
+                // the next update's row and column (the next sweep's first, unless
+                // it runs in batches)
+                if (r0 < N || !PDIT_REG_NEXT_BATCH()) {
+                    const int nr = r0 < N ? r0 : 0;
+                    PDIT_REG_PUBLISH(nr, pick(pk, nr), seq & 1)
                 }
-                // LDS accesses of one wave complete in order: this read sees the
-                // whole wave's writes
-                __asm__ volatile("" ::: "memory");
-                const v32i wt = *(const v32i *)&wl[64 * wv];     // w of the wave's facilities
-                int32_t u[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) u[i] = drk[i] - byte_at<SGN>(dsw, i);
-                const int32_t h_rb = __builtin_amdgcn_readfirstlane(h_rb_v);
-                const int32_t f_bb = __builtin_amdgcn_readfirstlane(f_bb_v);
-                const int32_t w_a = __builtin_amdgcn_readfirstlane(f_ba_v) - f_aa;  // F[b][a] - F[a][a]
-                const int32_t w_b = f_bb - __builtin_amdgcn_readfirstlane(f_ab_v);  // F[b][b] - F[a][b]
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = 4 * lane + i;
-                    const int32_t wp = fbk[i] - fak[i];           // w at p(k)
-                    const bool is_r = k == r, is_s = k == s;
-                    dg[i] = is_r ? h_rb + __mul24(u[i], w_b)       // G'[r][b]
-                          : is_s ? hc[i] + __mul24(u[i], w_a)      // G'[s][a]
-                                 : dg[i] + __mul24(u[i], wp);
-                    if (!ZD) fdk[i] = is_r ? f_bb : is_s ? f_aa : fdk[i];
-                    pk[i] = is_r ? bf : is_s ? af : pk[i];
-                }
-                // the tile: G += u w over the wave's 64 facilities
-                g0 = rank1(g0, (short)u[0], wt);
-                g1 = rank1(g1, (short)u[1], wt);
-                g2 = rank1(g2, (short)u[2], wt);
-                g3 = rank1(g3, (short)u[3], wt);
-                if (E < E_best) {
-                    E_best = E;
-                    if (writer) {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int k = 4 * lane + i;
-                            if (k < N) a.perm_best[rep * N + k] = pk[i];
-                        }
-                    }
-                }
+            } else {
+                replayed = true;
             }
-            // ================= publish row r + 1 and its column =================
-            const int nr = r + 1 < N ? r + 1 : 0;
-            PDIT_REG_PUBLISH(nr, pick(pk, nr), seq & 1)
             rep_signal(rs.sync, wv, ++seq);
         }
+        if (ok && batch && !PDIT_REG_NEXT_BATCH()) {
+            // the next sweep goes one update at a time: its first row and column,
+            // once every wave has left the batch buffers they share
+            if (replayed && !rep_done(*flags, seq)) ok = rep_spin(flags, seq);
+            PDIT_REG_PUBLISH(0, pick(pk, 0), seq & 1)
+            rep_signal(rs.sync, wv, ++seq);
+        }
+        batch = PDIT_REG_NEXT_BATCH();
+#undef PDIT_REG_NEXT_BATCH
         if (a.E_trace && writer && lane == 0) a.E_trace[rep * a.T + t] = E;
     }
-
+#undef PDIT_REG_STORE_COL
 #undef PDIT_REG_PUBLISH
+#undef PDIT_REG_PUBLISH_BATCH
+#undef PDIT_REG_READS
+#undef PDIT_REG_DELTA
+#undef PDIT_REG_DRAW
+#undef PDIT_REG_ACCEPT
+
     // ---- outputs ----
     if (!ok && a.err) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (writer) {

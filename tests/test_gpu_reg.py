@@ -3,8 +3,9 @@
 draw by draw (``parity.py``) at ragged and full sizes, zero and nonzero
 diagonals, unsigned and signed 8-bit data, hot, cold, constant and zero
 beta, an odd replica count (the second slot of the last workgroup idle),
-plateau moves, resume across calls, AUTO choosing it, and windows of the
-N=256 workload's schedule."""
+plateau moves, resume across calls, AUTO choosing it, sweeps switching
+between single updates and batches, and windows of the N=256 workload's
+schedule."""
 import numpy as np
 import pytest
 import torch
@@ -113,6 +114,34 @@ def test_reg_plateau_and_resume():
         b = run(ctx, D, F, a["perm"], beta[15:], 21, offset=15, record=False)
     for key in ("perm", "E", "E_best", "perm_best"):
         assert np.array_equal(got[key], b[key]), key
+
+
+@pytest.mark.parametrize("N,R", [(203, 3), (256, 2)])
+def test_reg_batches_and_switches(N, R):
+    """Sweeps that accept few exchanges are followed by sweeps evaluated in
+    batches of updates on one state (the prefix up to the first exchange
+    committed); a schedule alternating cold and hot stretches, from an
+    annealed state, switches between the two ways several times.  N = 203
+    leaves a ragged last batch in every sweep."""
+    from paper_2605_24408_amd import pdit as P
+    rng = np.random.default_rng(N + 5)
+    D, F = instance(rng, N, "euclid")
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    cold, hot = 2000.0 / s, 2.0 / s
+    pre = W.beta_geometric(5.0 / s, cold, 60)
+    blocks = [(cold, 4), (hot, 2), (cold, 5), (hot, 1), (cold, 3)]
+    beta = np.concatenate([np.full(n, b, np.float32) for b, n in blocks])
+    with P.Pdit(sweep="reg") as ctx:
+        a = run(ctx, D, F, perms, pre, 5, offset=500, record=False)
+        start = a["perm"]
+        ctx.reset()
+        got = run(ctx, D, F, start, beta, 5)
+    replay(got, D, F, start, beta, 5, what=f"reg switches N={N}")
+    # exchanges per sweep: both kinds of sweep follow each other
+    moved = (got["choices"] != np.arange(N)[None, None, :]).sum(axis=2)
+    few = moved <= 48
+    assert few[:, :-1].any() and (~few[:, :-1]).any(), moved
 
 
 def test_reg_auto_and_refusals():
