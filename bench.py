@@ -63,20 +63,24 @@ def ops_per_update(N: int, alpha: float) -> float:
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_table_n64_counters.json")
 FAST_SRC = os.path.join(ROOT, "paper_2605_24408_amd", "csrc", "sweep_table.hip")
+TRAFFIC_N256 = os.path.join(ROOT, "profiles", "sweep_reg_n256_counters.json")
+REG_SRC = os.path.join(ROOT, "paper_2605_24408_amd", "csrc", "sweep_reg.hip")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (n256: schedule slices, default 19; n64: full runs, default 5)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before them (default 1)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-replicas", type=int, default=32)
     ap.add_argument("--cpu-sweeps", type=int, default=30,
                     help="n256: oracle sweeps per sampled state (CPU baseline)")
-    ap.add_argument("--slice", type=int, default=5000,
-                    help="n256: sweeps per step (a slice of the 10^5-sweep schedule)")
+    ap.add_argument("--slice", type=int, default=0,
+                    help="n256: sweeps per step (default: the schedule cut into warmup + steps "
+                         "slices, so that the run covers all of it)")
     ap.add_argument("--sweep", default="auto", choices=["auto", "fast", "large"],
                     help="n256: sweep kernel of the timed path")
     ap.add_argument("--workload", default="n256",
@@ -460,11 +464,26 @@ def n256_workload(args):
     dev = torch.device("cuda", 0)
     inst = W.config_n256()
     N, R, T = inst.N, inst.R, inst.T
-    S = args.slice
+    if args.steps is None:
+        args.steps = 19
+    if args.warmup is None:
+        args.warmup = 1
+    if args.steps < 1 or args.warmup < 0:
+        print("steps must be at least 1 and warmup at least 0", file=sys.stderr)
+        sys.exit(2)
+    S = args.slice or -(-T // (args.warmup + args.steps))
     n_slices = (T + S - 1) // S
     if args.warmup + args.steps > n_slices:
         print(f"warmup + steps must be at most {n_slices} slices of {S} sweeps", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        # a plain device-to-device copy of 256 MiB: the profiler's byte counters
+        # for it calibrate those of the sweep kernel
+        src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     D = torch.from_numpy(inst.D).to(dev)
     F = torch.from_numpy(inst.F).to(dev)
     beta = torch.from_numpy(inst.beta).to(dev)
@@ -515,7 +534,7 @@ def n256_workload(args):
                           "end_s": time.perf_counter() - start, "ties": cnt["ties"]})
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - start
-    run_sweeps = (args.warmup + args.steps) * S
+    run_sweeps = min(T, (args.warmup + args.steps) * S)
     timed_updates = R * N * sum(min(T, (i + 1) * S) - i * S
                                 for i in range(args.warmup, args.warmup + args.steps))
     value = timed_updates / elapsed
@@ -529,8 +548,18 @@ def n256_workload(args):
     ops = sum(method_ops_per_update(N, p["alpha"]) * R * N * S for p in timed)
     achieved = ops / kernel_s
     plans = sorted({(p["plan"]["sweep"], p["plan"]["size_class"]) for p in timed})
+    # HBM bytes per launch of the sweep kernel from the profiler's counters
+    # (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), stored with
+    # the hash of the kernel source they were taken on; null once it changed
+    traffic, traffic_src = None, None
+    if os.path.exists(TRAFFIC_N256):
+        rec = json.load(open(TRAFFIC_N256))
+        if rec.get("kernel_source_sha") == src_hash(REG_SRC) and rec.get("slice_sweeps") == S:
+            traffic = rec.get("bytes_per_launch")
+            traffic_src = "stored: " + os.path.relpath(TRAFFIC_N256, ROOT)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "T int32 lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                "unit": "T int32 lane-op/s", "frac": achieved / VALU_PEAK, "traffic": traffic,
+                "traffic_source": traffic_src,
                 "kernels": [f"{k} (class {c})" if c else k for k, c in plans],
                 "kernel_s": kernel_s,
                 "ops_per_update": "13 N + 2 log2 N + alpha N^2 per slice (alpha measured)",
@@ -666,6 +695,10 @@ def main():
 def n64_workload(args):
     """The N=64 workload's full schedule as the step (the previous headline
     configuration, kept for comparison); same JSON fields."""
+    if args.steps is None:
+        args.steps = 5
+    if args.warmup is None:
+        args.warmup = 1
     import numpy as np
     import torch
 

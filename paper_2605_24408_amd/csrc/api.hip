@@ -172,10 +172,11 @@ int pick_recompute(pdit_t *ctx, const InstanceStats &st, int64_t bound, int requ
 }
 
 hipError_t run_recompute(pdit_t *ctx, int mode, int N, const int32_t *D, const int32_t *F, int R,
-                         const int32_t *perm, void *H, bool h64, int64_t *E) {
+                         const int32_t *perm, void *H, bool h64, int64_t *E,
+                         bool g_layout = false) {
     if (mode == PDIT_RECOMPUTE_PLAIN)
-        return pdit::launch_h_recompute_plain(ctx->stream, N, D, F, R, perm, H, h64, E);
-    return pdit::launch_h_recompute_mfma(ctx->stream, mode, N, D, F, R, perm, H, h64, E);
+        return pdit::launch_h_recompute_plain(ctx->stream, N, D, F, R, perm, H, h64, E, g_layout);
+    return pdit::launch_h_recompute_mfma(ctx->stream, mode, N, D, F, R, perm, H, h64, E, g_layout);
 }
 
 }  // namespace
@@ -386,7 +387,8 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
 
     ctx->timed = false;
     PDIT_HIP(ctx, record_event(ctx, 0));
-    PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E));
+    // the register kernel takes G = D F[p,:] (its tile rows read contiguously)
+    PDIT_HIP(ctx, run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, S.E, use_reg));
     pdit::LargeCopies lcopy;
     if (use_large)
         PDIT_HIP(ctx, pdit::launch_large_copy(ctx->stream, N, D, F, lplan, ctx->large_buf.ptr,

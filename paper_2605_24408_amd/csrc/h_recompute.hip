@@ -1,7 +1,9 @@
 // h_recompute.hip -- step "H recompute": for every replica, the influence
 // matrix H = D F[p,p] (H_ik = sum_j D_ij F_{p(j) p(k)}; for symmetric data
 // the influence of Eq. 2 is I_i^{p(k)} = -2 H_ik) and the energy
-// E = trace(H) = Eq. 1.
+// E = trace(H) = Eq. 1.  The G layout (for the register sweep kernel) keeps
+// the columns by facility instead: G = D F[p,:], G_ic = sum_j D_ij
+// F_{p(j) c}, so H_ik = G_{i p(k)} and E = sum_i G_{i p(i)}.
 //
 // Variants (all exact for the data they accept):
 //   plain  vector ALU, int64 accumulation;
@@ -23,7 +25,7 @@ namespace {
 // ---------------------------------------------------------------------------
 // plain: one block per (row i, replica); threads over columns k.
 // ---------------------------------------------------------------------------
-template <typename HT>
+template <typename HT, bool GL>
 __global__ void __launch_bounds__(256) h_plain_kernel(int N, const int32_t *__restrict__ D,
                                                       const int32_t *__restrict__ F,
                                                       const int32_t *__restrict__ perm,
@@ -40,21 +42,24 @@ __global__ void __launch_bounds__(256) h_plain_kernel(int N, const int32_t *__re
     __syncthreads();
     HT *out = H + (rep * N + i) * (int64_t)N;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        const int pk = p[k];
+        const int pk = GL ? k : p[k];
         int64_t acc = 0;
         for (int j = 0; j < N; ++j) acc += (int64_t)drow[j] * F[(int64_t)p[j] * N + pk];
         out[k] = (HT)acc;
     }
 }
 
-// E[rep] = sum_i H[rep][i][i]; one block per replica.
-template <typename HT>
+// E[rep] = sum_i H[rep][i][i] (G layout: sum_i G[rep][i][p(i)]); one block
+// per replica.
+template <typename HT, bool GL>
 __global__ void __launch_bounds__(256) trace_kernel(int N, const HT *__restrict__ H,
+                                                    const int32_t *__restrict__ perm,
                                                     int64_t *__restrict__ E) {
     __shared__ int64_t part[256];
     const int64_t rep = blockIdx.x;
     int64_t s = 0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) s += (int64_t)H[(rep * N + i) * N + i];
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        s += (int64_t)H[(rep * N + i) * N + (GL ? perm[rep * N + i] : i)];
     part[threadIdx.x] = s;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -95,7 +100,7 @@ enum { kModeI8 = 0, kModeBF16 = 1, kModeSplit = 2 };
 __device__ __forceinline__ int8_t lo7(int32_t x) { return (int8_t)(x & 127); }
 __device__ __forceinline__ int8_t hi7(int32_t x) { return (int8_t)(x >> 7); }  // floor(x / 128)
 
-template <int MODE, typename HT>
+template <int MODE, typename HT, bool GL>
 __global__ void __launch_bounds__(256) h_mfma_kernel(int N, int tiles, const int32_t *__restrict__ D,
                                                      const int32_t *__restrict__ F,
                                                      const int32_t *__restrict__ perm,
@@ -136,7 +141,7 @@ __global__ void __launch_bounds__(256) h_mfma_kernel(int N, int tiles, const int
             const int gi = tm * kTile + r, gn = tn * kTile + r, gk = kc * kTile + c;
             const bool kin = gk < N;
             const int32_t a = (gi < N && kin) ? D[(int64_t)gi * N + gk] : 0;
-            const int32_t b = (gn < N && kin) ? F[(int64_t)p[gn] * N + p[gk]] : 0;
+            const int32_t b = (gn < N && kin) ? F[(int64_t)(GL ? gn : p[gn]) * N + p[gk]] : 0;
             if constexpr (MODE == kModeI8) {
                 As[0][r * kRow + c] = (unsigned char)(int8_t)a;
                 Bs[0][r * kRow + c] = (unsigned char)(int8_t)b;
@@ -218,40 +223,50 @@ __global__ void __launch_bounds__(256) h_mfma_kernel(int N, int tiles, const int
 }  // namespace
 
 hipError_t launch_h_recompute_plain(hipStream_t s, int N, const int32_t *D, const int32_t *F,
-                                    int R, const int32_t *perm, void *H, bool h64, int64_t *E) {
+                                    int R, const int32_t *perm, void *H, bool h64, int64_t *E,
+                                    bool g_layout) {
     dim3 grid(N, R);
-    if (h64) {
-        h_plain_kernel<int64_t><<<grid, 256, 0, s>>>(N, D, F, perm, (int64_t *)H);
-        trace_kernel<int64_t><<<R, 256, 0, s>>>(N, (const int64_t *)H, E);
-    } else {
-        h_plain_kernel<int32_t><<<grid, 256, 0, s>>>(N, D, F, perm, (int32_t *)H);
-        trace_kernel<int32_t><<<R, 256, 0, s>>>(N, (const int32_t *)H, E);
+#define PDIT_LAUNCH(HT, GL)                                                            \
+    {                                                                                  \
+        h_plain_kernel<HT, GL><<<grid, 256, 0, s>>>(N, D, F, perm, (HT *)H);           \
+        trace_kernel<HT, GL><<<R, 256, 0, s>>>(N, (const HT *)H, perm, E);             \
     }
+    if (h64) {
+        if (g_layout) PDIT_LAUNCH(int64_t, true) else PDIT_LAUNCH(int64_t, false)
+    } else {
+        if (g_layout) PDIT_LAUNCH(int32_t, true) else PDIT_LAUNCH(int32_t, false)
+    }
+#undef PDIT_LAUNCH
     return hipGetLastError();
 }
 
 hipError_t launch_h_recompute_mfma(hipStream_t s, int mode, int N, const int32_t *D,
                                    const int32_t *F, int R, const int32_t *perm, void *H,
-                                   bool h64, int64_t *E) {
+                                   bool h64, int64_t *E, bool g_layout) {
     const int tiles = (N + kTile - 1) / kTile;
     const int64_t blocks = (int64_t)R * tiles * tiles;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-#define PDIT_LAUNCH(MODE, HT) \
-    h_mfma_kernel<MODE, HT><<<(unsigned)blocks, 256, 0, s>>>(N, tiles, D, F, perm, (HT *)H)
-    if (mode == PDIT_RECOMPUTE_I8) {
-        if (h64) PDIT_LAUNCH(kModeI8, int64_t); else PDIT_LAUNCH(kModeI8, int32_t);
-    } else if (mode == PDIT_RECOMPUTE_BF16) {
-        if (h64) PDIT_LAUNCH(kModeBF16, int64_t); else PDIT_LAUNCH(kModeBF16, int32_t);
-    } else if (mode == PDIT_RECOMPUTE_SPLIT) {
-        if (h64) PDIT_LAUNCH(kModeSplit, int64_t); else PDIT_LAUNCH(kModeSplit, int32_t);
-    } else {
-        return hipErrorInvalidValue;
+    int kmode;
+    if (mode == PDIT_RECOMPUTE_I8) kmode = kModeI8;
+    else if (mode == PDIT_RECOMPUTE_BF16) kmode = kModeBF16;
+    else if (mode == PDIT_RECOMPUTE_SPLIT) kmode = kModeSplit;
+    else return hipErrorInvalidValue;
+#define PDIT_LAUNCH(MODE, HT, GL) \
+    h_mfma_kernel<MODE, HT, GL><<<(unsigned)blocks, 256, 0, s>>>(N, tiles, D, F, perm, (HT *)H)
+#define PDIT_LAUNCH_MODES(HT, GL)                                                      \
+    {                                                                                  \
+        if (kmode == kModeI8) PDIT_LAUNCH(kModeI8, HT, GL);                            \
+        else if (kmode == kModeBF16) PDIT_LAUNCH(kModeBF16, HT, GL);                   \
+        else PDIT_LAUNCH(kModeSplit, HT, GL);                                          \
+        trace_kernel<HT, GL><<<R, 256, 0, s>>>(N, (const HT *)H, perm, E);             \
     }
+    if (h64) {
+        if (g_layout) PDIT_LAUNCH_MODES(int64_t, true) else PDIT_LAUNCH_MODES(int64_t, false)
+    } else {
+        if (g_layout) PDIT_LAUNCH_MODES(int32_t, true) else PDIT_LAUNCH_MODES(int32_t, false)
+    }
+#undef PDIT_LAUNCH_MODES
 #undef PDIT_LAUNCH
-    if (h64)
-        trace_kernel<int64_t><<<R, 256, 0, s>>>(N, (const int64_t *)H, E);
-    else
-        trace_kernel<int32_t><<<R, 256, 0, s>>>(N, (const int32_t *)H, E);
     return hipGetLastError();
 }
 

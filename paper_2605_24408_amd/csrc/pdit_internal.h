@@ -127,12 +127,14 @@ hipError_t launch_instance_stats(hipStream_t s, int N, const int32_t *D, const i
                                  int R, const int32_t *perm, const float *beta, int64_t T,
                                  InstanceStats *out_dev);
 
+// g_layout: G = D F[p,:] (columns by facility, for the register sweep kernel)
+// instead of H = D F[p,p]
 hipError_t launch_h_recompute_plain(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                                     int R, const int32_t *perm, void *H, bool h64,
-                                    int64_t *E);
+                                    int64_t *E, bool g_layout = false);
 hipError_t launch_h_recompute_mfma(hipStream_t s, int mode, int N, const int32_t *D,
                                    const int32_t *F, int R, const int32_t *perm, void *H,
-                                   bool h64, int64_t *E);
+                                   bool h64, int64_t *E, bool g_layout = false);
 hipError_t launch_widen_h(hipStream_t s, int64_t count, const int32_t *src, int64_t *dst);
 
 struct SweepArgs {

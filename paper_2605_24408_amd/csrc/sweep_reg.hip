@@ -85,7 +85,7 @@ struct alignas(16) RegRep {
             alignas(16) int16_t brow[kRSpec][kRN];
             alignas(16) int16_t bcol[kRSpec][kRN];
         } sp;
-        int32_t pinv[kRN];                     // set-up: p^-1
+        alignas(16) int16_t stage[kRWaves][16][64];  // set-up: rows of G on their way to the tiles
     } u;
     alignas(16) int16_t w[kRWaves][kRN];       // per wave: the accepted exchange's w, by facility
     alignas(16) v4i outc[kRSpec];              // batch: per update its draw s and tie flag
@@ -236,33 +236,45 @@ sweep_reg_kernel(SweepArgs a) {
     for (int t = 0; t < 4; ++t) {
         const int k = 4 * lane + t;
         pk[t] = k < N ? a.perm[rep * N + k] : k;
-        if (wv == 0) rs.u.pinv[pk[t]] = k;
     }
     if (lane < kRWaves && wv == 0) rs.sync[lane] = 0;
-    __syncthreads();
 
-    // ---- the tile: G[4 lane + t][64 wv + c] = H[4 lane + t][p^-1(64 wv + c)] ----
+    // ---- the tile: G[4 lane + t][64 wv + c], from G = D F[p,:] (row k of a
+    // replica's N x N block, columns by facility).  Rows 16 q .. 16 q + 15 of
+    // the wave's 64 facilities are read along the rows (lane c takes column
+    // 64 wv + c), staged in the wave's part of LDS as int16, and
+    // read back by the four lanes that hold them; LDS accesses of one wave
+    // complete in order, so the wave needs no barrier. ----
     v32i g0, g1, g2, g3;
     {
-        const int32_t *Hb = (const int32_t *)a.H + rep * N * (int64_t)N;
+        const int32_t *Gb = (const int32_t *)a.H + rep * N * (int64_t)N;
+        int16_t *stage = rs.u.stage[wv][0];     // 16 rows x 64 facilities
+        const int c = 64 * wv + lane;
+        for (int q = 0; q < kRN / 16; ++q) {
 #pragma unroll
-        for (int m = 0; m < 32; ++m) {
-            const int c0 = 64 * wv + 2 * m, c1 = c0 + 1;
-            const int j0 = c0 < N ? rs.u.pinv[c0] : -1, j1 = c1 < N ? rs.u.pinv[c1] : -1;
-#define PDIT_G_AT(t, j) ((4 * lane + (t) < N && (j) >= 0) ? Hb[(4 * lane + (t)) * (int64_t)N + (j)] : 0)
-            g0[m] = (int)pack16(PDIT_G_AT(0, j0), PDIT_G_AT(0, j1));
-            g1[m] = (int)pack16(PDIT_G_AT(1, j0), PDIT_G_AT(1, j1));
-            g2[m] = (int)pack16(PDIT_G_AT(2, j0), PDIT_G_AT(2, j1));
-            g3[m] = (int)pack16(PDIT_G_AT(3, j0), PDIT_G_AT(3, j1));
-#undef PDIT_G_AT
+            for (int i = 0; i < 16; ++i) {
+                const int k = 16 * q + i;
+                stage[i * 64 + lane] = (int16_t)((k < N && c < N) ? Gb[k * (int64_t)N + c] : 0);
+            }
+            __asm__ volatile("" ::: "memory");
+            if ((lane >> 2) == q) {
+                const v32i *src = (const v32i *)&stage[(4 * (lane & 3)) * 64];
+                g0 = src[0];
+                g1 = src[1];
+                g2 = src[2];
+                g3 = src[3];
+            }
+            __asm__ volatile("" ::: "memory");
         }
     }
-    // per candidate: H[k][k], D[k][k], F[p(k)][p(k)]
+    // the D and F copies and the flags are complete before the first reads
+    __syncthreads();
+    // per candidate: H[k][k] = G[k][p(k)], D[k][k], F[p(k)][p(k)]
     int32_t dg[4], ddk[4], fdk[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int k = 4 * lane + t;
-        dg[t] = k < N ? ((const int32_t *)a.H)[(rep * N + k) * (int64_t)N + k] : 0;
+        dg[t] = k < N ? ((const int32_t *)a.H)[(rep * N + k) * (int64_t)N + pk[t]] : 0;
         ddk[t] = ZD ? 0 : (int32_t)sm.D[k * kRN + k];
         fdk[t] = ZD ? 0 : (int32_t)sm.F[pk[t] * kRN + pk[t]];
     }
@@ -275,8 +287,6 @@ sweep_reg_kernel(SweepArgs a) {
     const int64_t bstride = a.slot ? 0 : 1;
     const bool writer = live && wv == 0;   // wave 0 writes the replica's outputs
 
-    // every wave has read p^-1 before the publications (which share its LDS) begin
-    __syncthreads();
 
     // ---------------- publication ----------------
     // the column of G at facility an, for this lane's four locations, to dst
