@@ -7,8 +7,10 @@ library is missing, loading fails loudly; there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import torch
 
@@ -175,6 +177,23 @@ def run_sweeps_noalloc(D: torch.Tensor, F: torch.Tensor, perm: torch.Tensor, bet
         raise PditError(rc, err.value.decode())
 
 
+# Contexts still open at interpreter exit are closed by an exit hook, while
+# the HIP runtime and torch are intact: a context left to garbage collection
+# during interpreter finalization would call pdit_destroy (hipSetDevice,
+# hipStreamSynchronize, hipFree, ...) in whatever order the runtime's own
+# teardown has reached by then.
+_open_contexts: "weakref.WeakSet[Pdit]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_contexts():
+    for ctx in list(_open_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+
+
 class Pdit:
     """A library context (``pdit_create``) bound to one device and stream."""
 
@@ -200,12 +219,14 @@ class Pdit:
             raise PditError(rc, "pdit_create failed")
         self._h = h
         self._last = None   # (R_total, perm_total, N) of the last run
+        _open_contexts.add(self)
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None):
             self._L.pdit_destroy(self._h)
             self._h = None
+        _open_contexts.discard(self)
 
     def __del__(self):
         try:

@@ -14,6 +14,8 @@ test checks, on rows drawn from the five benchmark workloads at hot and
 cold temperatures, that the integer rule never leaves Eq. 5 except at a
 draw the oracle flags as a tie.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -183,7 +185,8 @@ def test_integer_rule_leaves_eq5_only_at_ties(orc, name):
     kernels' integer-weight rule and Eq. 5 in double precision disagree is a
     tie of the oracle; the two tie flags agree except where tau sits at the
     band's edge."""
-    rng = np.random.default_rng(hash(name) % 2**32)
+    # a fixed seed per workload (str hashes are salted per process)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
     if name == "uneven":
         insts = W.config_uneven()
         picks = [insts[k] for k in (0, 1, 40, 77, 130, 201)]
