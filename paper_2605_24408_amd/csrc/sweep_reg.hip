@@ -61,9 +61,9 @@ constexpr int kRWaves = 4;        // waves per replica
 constexpr int kRReps = 2;         // replicas per workgroup
 constexpr int kRThreads = 64 * kRWaves * kRReps;
 constexpr int32_t kRBig = (1 << 30) - 1;  // padding candidates (|dE| < 2^30 - 1)
-// Batches: kRSpec consecutive updates evaluated on one state (kRSpec / kRWaves
-// per wave) when the previous sweep accepted at most kRSpecAcc exchanges
-constexpr int kRSpec = 12;
+// Batches: kRSpec consecutive updates evaluated on one state when the
+// previous sweep accepted at most kRSpecAcc exchanges
+constexpr int kRSpec = 10;
 constexpr int kRSpecAcc = 48;
 // spins of a replica's wait before it gives up (about 0.1 s): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
@@ -87,9 +87,14 @@ struct alignas(16) RegRep {
         } sp;
         alignas(16) int16_t stage[kRWaves][16][64];  // set-up: rows of G on their way to the tiles
     } u;
-    alignas(16) int16_t w[kRWaves][kRN];       // per wave: the accepted exchange's w, by facility
-    alignas(16) v4i outc[kRSpec];              // batch: per update its draw s and tie flag
-    alignas(16) uint32_t sync[kRWaves];        // per wave: the last step it finished
+    alignas(16) int16_t w[kRN];              // accepted exchange: F[b][c] - F[a][c] (wave w: c in its 64)
+    alignas(16) int32_t pv[kRN];             // p by location
+    alignas(16) int32_t dga[kRN];            // batch: H[k][k] by location
+    alignas(16) uint32_t u24[kRN];           // the sweep's uniforms by location
+    alignas(16) v2i cd[kRWaves][64];         // per candidate: its wave's running weight sum, dE
+    alignas(16) int32_t bmin[kRSpec][kRWaves];  // batch: per update and wave, min dE over k != r
+    alignas(16) int32_t smin[kRWaves];       // one update: per wave, min dE over k != r
+    alignas(16) uint32_t sync[kRWaves];      // per wave: the last step it finished
 };
 
 template <bool SGN>
@@ -121,13 +126,6 @@ __device__ __forceinline__ v32i rank1(v32i g, short u, v32i w) {
 __device__ __forceinline__ int32_t tile_entry(const v32i &g, int m, int half) {
     const int word = g[__builtin_amdgcn_readfirstlane(m)];
     return half ? (word >> 16) : (int32_t)(int16_t)(word & 0xFFFF);
-}
-
-// value of the candidate slot of location k (uniform): lane k / 4, slot k % 4
-__device__ __forceinline__ int32_t pick(const int32_t (&v)[4], int k) {
-    const int t = k & 3;
-    const int32_t x = t == 0 ? v[0] : t == 1 ? v[1] : t == 2 ? v[2] : v[3];
-    return __builtin_amdgcn_readlane(x, k >> 2);
 }
 
 typedef __attribute__((address_space(3))) volatile v4i lds_v4i;
@@ -222,6 +220,8 @@ sweep_reg_kernel(SweepArgs a) {
     RegRep &rs = sm.rep[qr];
     const uint32_t *D32 = (const uint32_t *)sm.D;
     const uint32_t *F32 = (const uint32_t *)sm.F;
+    const int k = 64 * wv + lane;     // this lane's candidate location
+    const bool kval = k < N;
 
     // ---- D and F copies (both replicas) ----
     for (int e = tid; e < kRN * kRN; e += kRThreads) {
@@ -230,21 +230,17 @@ sweep_reg_kernel(SweepArgs a) {
         sm.D[e] = (E8)(in ? a.D[(int64_t)i * N + j] : 0);
         sm.F[e] = (E8)(in ? a.F[(int64_t)i * N + j] : 0);
     }
-    // ---- candidates 4 lane + t: p (padding locations hold the padding facilities) ----
-    int32_t pk[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int k = 4 * lane + t;
-        pk[t] = k < N ? a.perm[rep * N + k] : k;
-    }
+    // ---- p (padding locations hold the padding facilities) ----
+    int32_t pk = kval ? a.perm[rep * N + k] : k;
+    rs.pv[k] = pk;
     if (lane < kRWaves && wv == 0) rs.sync[lane] = 0;
 
     // ---- the tile: G[4 lane + t][64 wv + c], from G = D F[p,:] (row k of a
     // replica's N x N block, columns by facility).  Rows 16 q .. 16 q + 15 of
     // the wave's 64 facilities are read along the rows (lane c takes column
-    // 64 wv + c), staged in the wave's part of LDS as int16, and
-    // read back by the four lanes that hold them; LDS accesses of one wave
-    // complete in order, so the wave needs no barrier. ----
+    // 64 wv + c), staged in the wave's part of LDS as int16, and read back by
+    // the four lanes that hold them; LDS accesses of one wave complete in
+    // order, so the wave needs no barrier. ----
     v32i g0, g1, g2, g3;
     {
         const int32_t *Gb = (const int32_t *)a.H + rep * N * (int64_t)N;
@@ -253,8 +249,8 @@ sweep_reg_kernel(SweepArgs a) {
         for (int q = 0; q < kRN / 16; ++q) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int k = 16 * q + i;
-                stage[i * 64 + lane] = (int16_t)((k < N && c < N) ? Gb[k * (int64_t)N + c] : 0);
+                const int kr = 16 * q + i;
+                stage[i * 64 + lane] = (int16_t)((kr < N && c < N) ? Gb[kr * (int64_t)N + c] : 0);
             }
             __asm__ volatile("" ::: "memory");
             if ((lane >> 2) == q) {
@@ -267,17 +263,12 @@ sweep_reg_kernel(SweepArgs a) {
             __asm__ volatile("" ::: "memory");
         }
     }
-    // the D and F copies and the flags are complete before the first reads
+    // the D and F copies, p and the flags are complete before the first reads
     __syncthreads();
-    // per candidate: H[k][k] = G[k][p(k)], D[k][k], F[p(k)][p(k)]
-    int32_t dg[4], ddk[4], fdk[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int k = 4 * lane + t;
-        dg[t] = k < N ? ((const int32_t *)a.H)[(rep * N + k) * (int64_t)N + pk[t]] : 0;
-        ddk[t] = ZD ? 0 : (int32_t)sm.D[k * kRN + k];
-        fdk[t] = ZD ? 0 : (int32_t)sm.F[pk[t] * kRN + pk[t]];
-    }
+    // the candidate's H[k][k] = G[k][p(k)], D[k][k], F[p(k)][p(k)]
+    int32_t dg = kval ? ((const int32_t *)a.H)[(rep * N + k) * (int64_t)N + pk] : 0;
+    const int32_t ddk = ZD ? 0 : (int32_t)sm.D[k * kRN + k];
+    int32_t fdk = ZD ? 0 : (int32_t)sm.F[pk * kRN + pk];
     int64_t E = a.E[rep];
     int64_t E_best = a.E_best[rep];
     int64_t n_acc = 0;
@@ -285,11 +276,10 @@ sweep_reg_kernel(SweepArgs a) {
     int32_t *ch_base = (a.choices && live && wv == 0) ? a.choices + rep * a.T * N : nullptr;
     const float *bp = a.slot ? a.beta + a.slot[rep] : a.beta;
     const int64_t bstride = a.slot ? 0 : 1;
-    const bool writer = live && wv == 0;   // wave 0 writes the replica's outputs
-
+    const bool writer = live && wv == 0;   // wave 0 writes the replica's scalar outputs
 
     // ---------------- publication ----------------
-    // the column of G at facility an, for this lane's four locations, to dst
+    // the column of G at facility an, for this lane's four tile rows, to dst
 #define PDIT_REG_STORE_COL(an, dst)                                                        \
     {                                                                                      \
         const int an_ = __builtin_amdgcn_readfirstlane(an);                                \
@@ -315,172 +305,152 @@ sweep_reg_kernel(SweepArgs a) {
         }                                                                                  \
         PDIT_REG_STORE_COL(an, rs.u.sq.pcol[(par)])                                        \
     }
-    // rows r0 .. r0 + nb - 1 and their columns, into the batch buffers
-#define PDIT_REG_PUBLISH_BATCH(r0, nb)                                                     \
-    {                                                                                      \
-        const int row_ = 4 * lane - (r0);                                                  \
-        const uint32_t dst_ = lds_addr(&rs.u.sp.brow[0][64 * wv]) + 2 * kRN * row_;        \
-        if (row_ >= 0 && row_ < (nb)) PDIT_REG_STORE_ROW(dst_, g0, "b0");                  \
-        if (row_ + 1 >= 0 && row_ + 1 < (nb)) PDIT_REG_STORE_ROW(dst_ + 2 * kRN, g1, "b1");\
-        if (row_ + 2 >= 0 && row_ + 2 < (nb)) PDIT_REG_STORE_ROW(dst_ + 4 * kRN, g2, "b2");\
-        if (row_ + 3 >= 0 && row_ + 3 < (nb)) PDIT_REG_STORE_ROW(dst_ + 6 * kRN, g3, "b3");\
-        for (int j_ = 0; j_ < (nb); ++j_) PDIT_REG_STORE_COL(pick(pk, (r0) + j_), rs.u.sp.bcol[j_]) \
-    }
 
-    // ---------------- one update's candidates ----------------
+    // ---------------- one update's candidates (this wave's 64) ----------------
+    int32_t hrr_v, d_rr_v, f_aa_v, hr_v, hc_v, drk_v, fak_v;
     // LDS reads for the update of location R (a = AF) from row PROW and column PCOL
-    int32_t hrr_v, d_rr_v, f_aa_v, hr[4], fak[4];
-    v2i hc2;
-    uint32_t drw;
 #define PDIT_REG_READS(PROW, PCOL, R, AF)                                                  \
     {                                                                                      \
         hrr_v = (PROW)[AF];                                                                \
-        hc2 = *(const v2i *)&(PCOL)[4 * lane];                                             \
-        drw = D32[(R) * (kRN / 4) + lane]; /* D[r][4 lane + t] */                          \
-        d_rr_v = ZD ? 0 : (int32_t)sm.D[(R) * kRN + (R)];                                  \
-        f_aa_v = ZD ? 0 : (int32_t)sm.F[(AF) * kRN + (AF)];                                \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
-            hr[i] = (PROW)[pk[i]];                                                         \
-            fak[i] = (int32_t)sm.F[(AF) * kRN + pk[i]];                                    \
-        }                                                                                  \
+        hr_v = (PROW)[pk];                                                                 \
+        hc_v = (PCOL)[k];                                                                  \
+        drk_v = (int32_t)sm.D[(R) * kRN + k];                                              \
+        fak_v = (int32_t)sm.F[(AF) * kRN + pk];                                            \
+        d_rr_v = ZD ? 0 : (int32_t)sm.D[(R) * (kRN + 1)];                                  \
+        f_aa_v = ZD ? 0 : (int32_t)sm.F[(AF) * (kRN + 1)];                                 \
     }
-    int32_t hrr, d_rr, f_aa, hc[4], drk[4], dv[4], m2;
-    // dE of the N candidates (four per lane) and the minimum over k != R
+    int32_t f_aa, dv, mw;
+    // dE of this lane's candidate and the wave's minimum over k != R
 #define PDIT_REG_DELTA(R)                                                                  \
     {                                                                                      \
-        hrr = __builtin_amdgcn_readfirstlane(hrr_v);                                       \
-        d_rr = __builtin_amdgcn_readfirstlane(d_rr_v);                                     \
+        const int32_t hrr = __builtin_amdgcn_readfirstlane(hrr_v);                         \
+        const int32_t d_rr = __builtin_amdgcn_readfirstlane(d_rr_v);                       \
         f_aa = __builtin_amdgcn_readfirstlane(f_aa_v);                                     \
-        hc[0] = (int32_t)(int16_t)(hc2.x & 0xFFFF);                                        \
-        hc[1] = hc2.x >> 16;                                                               \
-        hc[2] = (int32_t)(int16_t)(hc2.y & 0xFFFF);                                        \
-        hc[3] = hc2.y >> 16;                                                               \
-        m2 = kRBig;                                                                        \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
-            const int k = 4 * lane + i;                                                    \
-            drk[i] = byte_at<SGN>(drw, i);                                                 \
-            const int32_t x = 2 * (hr[i] - hrr + hc[i] - dg[i]);                           \
-            const int32_t y = ZD ? 4 * __mul24(drk[i], fak[i])                             \
-                                 : __mul24(d_rr + ddk[i] - 2 * drk[i], f_aa + fdk[i] - 2 * fak[i]); \
-            dv[i] = k >= N ? kRBig : k == (R) ? 0 : x + y;                                 \
-            m2 = min(m2, k == (R) ? kRBig : dv[i]);                                        \
-        }                                                                                  \
-        m2 = wave_min_i32(m2);                                                             \
+        const int32_t x = 2 * (hr_v - hrr + hc_v - dg);                                    \
+        const int32_t y = ZD ? 4 * __mul24(drk_v, fak_v)                                   \
+                             : __mul24(d_rr + ddk - 2 * drk_v, f_aa + fdk - 2 * fak_v);    \
+        dv = !kval ? kRBig : k == (R) ? 0 : x + y;                                         \
+        mw = wave_min_i32(k == (R) ? kRBig : dv);                                          \
     }
-    // the draw of the update of location R: S (R for a stay) and whether its
-    // threshold fell within the tie band (TIE)
-#define PDIT_REG_DRAW(R, S, TIE)                                                           \
+    // the accepted exchange of R and S (a = AF, b = BF): dE DES; G[R][b] from
+    // row PROW; hc_v, drk_v, fak_v and f_aa hold the update's reads
+#define PDIT_REG_ACCEPT(R, S, AF, BF, DES, PROW)                                           \
     {                                                                                      \
-        S = (R);                                                                           \
-        TIE = 0;                                                                           \
-        if (m2 < dthr) {                                                                   \
-            const int32_t mn = min(m2, 0);                                                 \
-            uint32_t q[4];                                                                 \
-            int32_t dd[4];                                                                 \
-            bool any = false;                                                              \
-            _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                \
-                dd[i] = dv[i] - mn; /* >= 0 */                                             \
-                const bool valid = 4 * lane + i < N;                                       \
-                q[i] = (valid && dd[i] == 0) ? kWeightOne : 0u;                            \
-                any = any || (valid && dd[i] > 0 && dd[i] < dthr);                         \
-            }                                                                              \
-            if (__ballot(any)) {                                                           \
-                _Pragma("unroll") for (int i = 0; i < 4; ++i) {                            \
-                    const bool need = 4 * lane + i < N && dd[i] > 0 && dd[i] < dthr;       \
-                    const uint32_t wq = gibbs_weight(beta, (float)dd[i]);                  \
-                    q[i] = need ? wq : q[i];                                               \
-                }                                                                          \
-            }                                                                              \
-            /* exact running sums: the lane's four weights (< 2^27) scanned as */          \
-            /* 16-bit halves, each half's wave sum within 32 bits */                       \
-            const uint32_t qs = q[0] + q[1] + q[2] + q[3];                                 \
-            const uint32_t slo = scan_u32(qs & 0xFFFFu);                                   \
-            const uint32_t shi = scan_u32(qs >> 16);                                       \
-            const uint64_t C = ((uint64_t)shi << 16) + slo;                                \
-            const uint64_t Z =                                                             \
-                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)shi, 63) << 16) +      \
-                (uint32_t)__builtin_amdgcn_readlane((int)slo, 63);                         \
-            const uint32_t ur = (uint32_t)pick(uu, (R));                                   \
-            const uint64_t thr = ((uint64_t)ur * Z) >> 24; /* first C > thr */             \
-            const uint64_t hit = __ballot(C > thr);                                        \
-            const int sl = __ffsll((unsigned long long)hit) - 1;                           \
-            const uint64_t c0 = C - qs + q[0], c1 = c0 + q[1], c2 = c1 + q[2];             \
-            const bool b0 = c0 > thr, b1 = c1 > thr, b2 = c2 > thr;                        \
-            const int sel = b0 ? 0 : b1 ? 1 : b2 ? 2 : 3;                                  \
-            const uint64_t csel = b0 ? c0 : b1 ? c1 : b2 ? c2 : C;                         \
-            const uint32_t qsel = b0 ? q[0] : b1 ? q[1] : b2 ? q[2] : q[3];                \
-            const int ssel = __builtin_amdgcn_readlane(sel, sl);                           \
-            const uint64_t cs = readlane_u64(csel, sl);                                    \
-            const uint32_t qq = (uint32_t)__builtin_amdgcn_readlane((int32_t)qsel, sl);    \
-            TIE = is_tie(cs - qq, cs, Z, ur) ? 1 : 0;                                      \
-            S = 4 * sl + ssel;                                                             \
-        }                                                                                  \
-    }
-    // the accepted exchange of R and S (a = AF): dE DES; G[R][b] from row PROW,
-    // hc_s = G[S][a]; drk, fak and f_aa hold the update's D and F reads
-#define PDIT_REG_ACCEPT(R, S, AF, DES, PROW, HC_S)                                         \
-    {                                                                                      \
-        const int bf = pick(pk, (S)); /* b = p(s) */                                       \
-        const int32_t h_rb_v = (int32_t)(PROW)[bf];                                        \
         E += (DES);                                                                        \
         ++n_acc;                                                                           \
+        const int32_t h_rb_v = (int32_t)(PROW)[BF];                                        \
+        const uint32_t drw = D32[(R) * (kRN / 4) + lane]; /* D[r][4 lane + t] */           \
         const uint32_t dsw = D32[(S) * (kRN / 4) + lane]; /* D[s][4 lane + t] */           \
-        const uint32_t fb4 = F32[bf * (kRN / 4) + lane];  /* F[b][4 lane + t] */           \
-        const uint32_t fa4 = F32[(AF) * (kRN / 4) + lane];                                 \
-        const int32_t f_ba_v = (int32_t)sm.F[bf * kRN + (AF)];                             \
-        const int32_t f_bb_v = (int32_t)sm.F[bf * kRN + bf];                               \
-        const int32_t f_ab_v = (int32_t)sm.F[(AF) * kRN + bf];                             \
-        int32_t fbk[4];                                                                    \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) fbk[i] = (int32_t)sm.F[bf * kRN + pk[i]]; \
-        /* w of facilities 4 lane .. 4 lane + 3, to this wave's copy */                    \
-        int16_t *wl = rs.w[wv];                                                            \
-        {                                                                                  \
-            v2i x;                                                                         \
-            x.x = (int)pack16(byte_at<SGN>(fb4, 0) - byte_at<SGN>(fa4, 0),                 \
-                              byte_at<SGN>(fb4, 1) - byte_at<SGN>(fa4, 1));                \
-            x.y = (int)pack16(byte_at<SGN>(fb4, 2) - byte_at<SGN>(fa4, 2),                 \
-                              byte_at<SGN>(fb4, 3) - byte_at<SGN>(fa4, 3));                \
-            *(v2i *)&wl[4 * lane] = x;                                                     \
-        }                                                                                  \
+        const int32_t dsk = (int32_t)sm.D[(S) * kRN + k];                                  \
+        const int32_t fbk = (int32_t)sm.F[(BF) * kRN + pk];                                \
+        const int32_t fbc = (int32_t)sm.F[(BF) * kRN + 64 * wv + lane];                    \
+        const int32_t fac = (int32_t)sm.F[(AF) * kRN + 64 * wv + lane];                    \
+        const int32_t f_ba_v = (int32_t)sm.F[(BF) * kRN + (AF)];                           \
+        const int32_t f_bb_v = (int32_t)sm.F[(BF) * (kRN + 1)];                            \
+        const int32_t f_ab_v = (int32_t)sm.F[(AF) * kRN + (BF)];                           \
+        /* w of this wave's facilities 64 wv + lane */                                     \
+        rs.w[64 * wv + lane] = (int16_t)(fbc - fac);                                       \
         /* LDS accesses of one wave complete in order: this read sees the */               \
         /* whole wave's writes */                                                          \
         __asm__ volatile("" ::: "memory");                                                 \
-        const v32i wt = *(const v32i *)&wl[64 * wv]; /* w of the wave's facilities */      \
-        int32_t u[4];                                                                      \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) u[i] = drk[i] - byte_at<SGN>(dsw, i); \
-        const int32_t f_bb = __builtin_amdgcn_readfirstlane(f_bb_v);                       \
+        const v32i wt = *(const v32i *)&rs.w[64 * wv];                                     \
         const int32_t h_rb = __builtin_amdgcn_readfirstlane(h_rb_v);                       \
+        const int32_t f_bb = __builtin_amdgcn_readfirstlane(f_bb_v);                       \
         const int32_t w_a = __builtin_amdgcn_readfirstlane(f_ba_v) - f_aa; /* F[b][a] - F[a][a] */ \
         const int32_t w_b = f_bb - __builtin_amdgcn_readfirstlane(f_ab_v); /* F[b][b] - F[a][b] */ \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                    \
-            const int k = 4 * lane + i;                                                    \
-            const int32_t wp = fbk[i] - fak[i]; /* w at p(k) */                            \
-            const bool is_r = k == (R), is_s = k == (S);                                   \
-            dg[i] = is_r ? h_rb + __mul24(u[i], w_b)        /* G'[r][b] */                 \
-                  : is_s ? (HC_S) + __mul24(u[i], w_a)      /* G'[s][a] */                 \
-                         : dg[i] + __mul24(u[i], wp);                                      \
-            if (!ZD) fdk[i] = is_r ? f_bb : is_s ? f_aa : fdk[i];                          \
-            pk[i] = is_r ? bf : is_s ? (AF) : pk[i];                                       \
+        const int32_t uk = drk_v - dsk;                 /* D[k][r] - D[k][s] */             \
+        const bool is_r = k == (R), is_s = k == (S);                                       \
+        dg = is_r ? h_rb + __mul24(uk, w_b)            /* G'[r][b] */                      \
+           : is_s ? hc_v + __mul24(uk, w_a)            /* G'[s][a] */                      \
+                  : dg + __mul24(uk, fbk - fak_v);     /* + u_k (F[b][p(k)] - F[a][p(k)]) */ \
+        if (!ZD) fdk = is_r ? f_bb : is_s ? f_aa : fdk;                                    \
+        if (is_r || is_s) {                                                                \
+            pk = is_r ? (BF) : (AF);                                                       \
+            rs.pv[k] = pk;                                                                 \
         }                                                                                  \
         /* the tile: G += u w over the wave's 64 facilities */                             \
-        g0 = rank1(g0, (short)u[0], wt);                                                   \
-        g1 = rank1(g1, (short)u[1], wt);                                                   \
-        g2 = rank1(g2, (short)u[2], wt);                                                   \
-        g3 = rank1(g3, (short)u[3], wt);                                                   \
+        g0 = rank1(g0, (short)(byte_at<SGN>(drw, 0) - byte_at<SGN>(dsw, 0)), wt);          \
+        g1 = rank1(g1, (short)(byte_at<SGN>(drw, 1) - byte_at<SGN>(dsw, 1)), wt);          \
+        g2 = rank1(g2, (short)(byte_at<SGN>(drw, 2) - byte_at<SGN>(dsw, 2)), wt);          \
+        g3 = rank1(g3, (short)(byte_at<SGN>(drw, 3) - byte_at<SGN>(dsw, 3)), wt);          \
         if (E < E_best) {                                                                  \
             E_best = E;                                                                    \
-            if (writer) {                                                                  \
-                _Pragma("unroll") for (int i = 0; i < 4; ++i) {                            \
-                    const int k = 4 * lane + i;                                            \
-                    if (k < N) a.perm_best[rep * N + k] = pk[i];                           \
-                }                                                                          \
-            }                                                                              \
+            if (live && kval) a.perm_best[rep * N + k] = pk;                               \
         }                                                                                  \
+    }
+
+#define PDIT_REG_POLL(READS)                                                               \
+    {                                                                                      \
+        const v4i fl_ = *flags;                                                            \
+        __asm__ volatile("" ::: "memory");                                                 \
+        READS                                                                              \
+        if (!rep_done(fl_, seq)) {                                                         \
+            ok = rep_spin(flags, seq);                                                     \
+            if (!ok) break;                                                                \
+            READS                                                                          \
+        }                                                                                  \
+    }
+
+    // p of candidates lane, 64 + lane, 128 + lane, 192 + lane (read in a meeting
+    // before any exchange can change them)
+    int32_t pw0 = 0, pw1 = 0, pw2 = 0, pw3 = 0;
+    // The draw of the update of location R whose minimum over k != R is M2
+    // (< dthr) and whose dE on this lane's candidate is DVJ, uniform UR:
+    // weights, this wave's running sums (64 weights of at most 2^25: 32
+    // bits), a meeting, and the first candidate whose running sum over all N
+    // exceeds the threshold.  Sets S, TIE, DES (dE_S) and BF (p(S)).
+#define PDIT_REG_DRAW(R, DVJ, M2, UR, S, TIE, DES, BF)                                     \
+    {                                                                                      \
+        const int32_t mn_ = min((M2), 0);                                                  \
+        const int32_t d_ = (DVJ) - mn_; /* >= 0 */                                         \
+        uint32_t q_ = (kval && d_ == 0) ? kWeightOne : 0u;                                 \
+        const bool need_ = kval && d_ > 0 && d_ < dthr;                                    \
+        if (__ballot(need_)) {                                                             \
+            const uint32_t wq_ = gibbs_weight(beta, (float)d_);                            \
+            q_ = need_ ? wq_ : q_;                                                         \
+        }                                                                                  \
+        const uint32_t C_ = scan_u32(q_);                                                  \
+        rs.cd[wv][lane] = v2i{(int)C_, (DVJ)};                                             \
+        rep_signal(rs.sync, wv, ++seq);                                                    \
+        v2i c0_, c1_, c2_, c3_;                                                            \
+        PDIT_REG_POLL({                                                                    \
+            c0_ = rs.cd[0][lane];                                                          \
+            c1_ = rs.cd[1][lane];                                                          \
+            c2_ = rs.cd[2][lane];                                                          \
+            c3_ = rs.cd[3][lane];                                                          \
+        })                                                                                 \
+        const uint64_t T0_ = (uint32_t)__builtin_amdgcn_readlane(c0_.x, 63);               \
+        const uint64_t T1_ = (uint32_t)__builtin_amdgcn_readlane(c1_.x, 63);               \
+        const uint64_t T2_ = (uint32_t)__builtin_amdgcn_readlane(c2_.x, 63);               \
+        const uint64_t T3_ = (uint32_t)__builtin_amdgcn_readlane(c3_.x, 63);               \
+        const uint64_t o1_ = T0_, o2_ = T0_ + T1_, o3_ = T0_ + T1_ + T2_;                  \
+        const uint64_t Z_ = o3_ + T3_;                                                     \
+        const uint32_t ur_ = (uint32_t)__builtin_amdgcn_readfirstlane((int)(UR));          \
+        const uint64_t thr_ = ((uint64_t)ur_ * Z_) >> 24; /* first C > thr */              \
+        const int ws_ = thr_ < o1_ ? 0 : thr_ < o2_ ? 1 : thr_ < o3_ ? 2 : 3;              \
+        const uint64_t off_ = ws_ == 0 ? 0 : ws_ == 1 ? o1_ : ws_ == 2 ? o2_ : o3_;        \
+        const v2i cw_ = ws_ == 0 ? c0_ : ws_ == 1 ? c1_ : ws_ == 2 ? c2_ : c3_;            \
+        const int32_t pwv_ = ws_ == 0 ? pw0 : ws_ == 1 ? pw1 : ws_ == 2 ? pw2 : pw3;       \
+        const uint64_t cg_ = off_ + (uint32_t)cw_.x;                                       \
+        const uint64_t hit_ = __ballot(cg_ > thr_);                                        \
+        const int sl_ = __ffsll((unsigned long long)hit_) - 1;                             \
+        const uint64_t csel_ = readlane_u64(cg_, sl_);                                     \
+        const uint64_t cprev_ = sl_ > 0 ? readlane_u64(cg_, sl_ > 0 ? sl_ - 1 : 0) : off_; \
+        TIE = is_tie(cprev_, csel_, Z_, ur_) ? 1 : 0;                                      \
+        S = 64 * ws_ + sl_;                                                                \
+        DES = __builtin_amdgcn_readlane(cw_.y, sl_);                                       \
+        BF = __builtin_amdgcn_readlane(pwv_, sl_);                                         \
     }
 
     const lds_v4i *flags = rep_flags(rs.sync);
     uint32_t seq = 0;      // steps of this replica's waits
-    PDIT_REG_PUBLISH(0, pick(pk, 0), 0)
+    int a_next = __builtin_amdgcn_readfirstlane(rs.pv[0]);  // p of the next single update's row
+    // the buffer (of two) that holds the next single update's row and column;
+    // it alternates per update, whatever the number of meetings in between, so
+    // that the next publication never overwrites the row a slower wave may
+    // still read in its accept
+    int pbuf = 0;
+    PDIT_REG_PUBLISH(0, a_next, 0)
     rep_signal(rs.sync, wv, ++seq);
     bool ok = true;        // every wait completed
     bool batch = false;    // this sweep runs in batches
@@ -490,156 +460,315 @@ sweep_reg_kernel(SweepArgs a) {
         const uint32_t gsw = (uint32_t)(a.sweep_offset + (uint64_t)t);
         const int32_t dthr = zero_weight_distance(beta);
         int32_t *ch = ch_base ? ch_base + t * N : nullptr;
-        int32_t uu[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            uu[i] = (int32_t)uniform24(a.seed, (uint32_t)(4 * lane + i), gsw, (uint32_t)rep,
-                                       a.inst_id);
+        // the sweep's uniforms by location; every read of them follows the
+        // first minimum meeting of the sweep, which follows this store
+        rs.u24[k] = uniform24(a.seed, (uint32_t)k, gsw, (uint32_t)rep, a.inst_id);
         const int64_t acc0 = n_acc;
         // the next sweep runs in batches when this one accepts few exchanges
 #define PDIT_REG_NEXT_BATCH() (t + 1 < a.T && n_acc - acc0 <= kRSpecAcc)
 
-        // Steps: one update, which every wave evaluates, or in a batch sweep a
-        // batch of kRSpec updates evaluated on one state, kRSpec / kRWaves per
-        // wave.  A batch commits its stays up to the first exchange; the update
-        // with the exchange then runs as a single update on the batch's row and
-        // column, which draws the same candidate.
+        // Steps: one update, evaluated by the four waves on 64 candidates each
+        // (meetings: the row and column, the minimum, the running sums), or in
+        // a batch sweep a batch of kRSpec updates evaluated on one state: their
+        // energy changes and minima, then the draws of the updates that can
+        // move, in order, until one exchanges; the stays before it are
+        // committed and the exchange is applied.
         if (batch && !rep_done(*flags, seq)) ok = rep_spin(flags, seq);  // buffers free
-        bool replayed = false;                  // batch: the last step was a single update
+        bool replayed = false;                  // batch: the last step ended in an exchange
         int r0 = 0;
         while (r0 < N && ok) {
-            const int16_t *prow, *pcol;
-            bool fresh = true;                  // the row and column were just published
+            // the step's exchange, if any: r, s, a, b, dE and the row of G[r][b]
+            int r = r0, s = r0, af = 0, bf = 0, nxt = 0;
+            int32_t des = 0;
+            const int16_t *prow = rs.u.sq.prow[0];
             if (batch) {
                 // ============ a batch: rows r0 .. r0 + nb - 1 ============
-                if (replayed && !rep_done(*flags, seq)) {  // every wave left that update
+                if (replayed && !rep_done(*flags, seq)) {  // every wave left the exchange
                     ok = rep_spin(flags, seq);
                     if (!ok) break;
                 }
                 const int nb = min(kRSpec, N - r0);
-                PDIT_REG_PUBLISH_BATCH(r0, nb)
+                const int ab = rs.pv[r0 + (lane < nb ? lane : 0)];  // p of the batch's rows
+                rs.dga[k] = dg;     // for the draws that every wave takes over all N
+                {
+                    const int row_ = 4 * lane - r0;
+                    const uint32_t dst_ = lds_addr(&rs.u.sp.brow[0][64 * wv]) + 2 * kRN * row_;
+                    if (row_ >= 0 && row_ < nb) PDIT_REG_STORE_ROW(dst_, g0, "b0");
+                    if (row_ + 1 >= 0 && row_ + 1 < nb) PDIT_REG_STORE_ROW(dst_ + 2 * kRN, g1, "b1");
+                    if (row_ + 2 >= 0 && row_ + 2 < nb) PDIT_REG_STORE_ROW(dst_ + 4 * kRN, g2, "b2");
+                    if (row_ + 3 >= 0 && row_ + 3 < nb) PDIT_REG_STORE_ROW(dst_ + 6 * kRN, g3, "b3");
+                    for (int j = 0; j < nb; ++j)
+                        PDIT_REG_STORE_COL(__builtin_amdgcn_readlane(ab, j), rs.u.sp.bcol[j])
+                }
                 rep_signal(rs.sync, wv, ++seq);
-                // this wave's updates j = wv, wv + kRWaves, ...: the draw and its tie
-                // flag to the outcome slots
-                for (int j = wv; j < nb; j += kRWaves) {
-                    const int rj = r0 + j;
-                    const int af = pick(pk, rj);
-                    const int16_t *brow = rs.u.sp.brow[j];
-                    {
-                        const v4i fl = *flags;
-                        __asm__ volatile("" ::: "memory");
-                        PDIT_REG_READS(brow, rs.u.sp.bcol[j], rj, af)
-                        if (j == wv && !rep_done(fl, seq)) {
-                            ok = rep_spin(flags, seq);
-                            if (!ok) break;
-                            PDIT_REG_READS(brow, rs.u.sp.bcol[j], rj, af)
+                // every update of the batch on this wave's 64 candidates: dE and
+                // minima.  After the meeting, lane j reads update j's uniform
+                // values (G[r][a], D[r][r], F[a][a], the uniform of r) and every
+                // lane p of every candidate (both fixed until the batch's
+                // exchange); then the candidates' reads of five updates at a time
+                // are issued before any of their arithmetic.
+                int32_t dvb[kRSpec];
+                uint32_t ub_v;
+                int32_t hb_v, db_v, fb_v;
+                v4i pk4v, dg4v;     // p and H[k][k] of candidates 4 lane .. 4 lane + 3
+                // (read before the minima's meeting: once a wave has passed it,
+                // it may reach the batch's exchange and change p)
+                PDIT_REG_POLL({
+                    const int jl = lane < nb ? lane : 0;
+                    hb_v = rs.u.sp.brow[jl][ab];
+                    db_v = ZD ? 0 : (int32_t)sm.D[(r0 + jl) * (kRN + 1)];
+                    fb_v = ZD ? 0 : (int32_t)sm.F[ab * (kRN + 1)];
+                    ub_v = rs.u24[r0 + jl];
+                    pk4v = *(const v4i *)&rs.pv[4 * lane];
+                    dg4v = *(const v4i *)&rs.dga[4 * lane];
+                })
+#pragma unroll
+                for (int h = 0; h < kRSpec; h += 5) {
+                    int32_t hr5[5], hc5[5], dr5[5], fa5[5];
+#pragma unroll
+                    for (int jj = 0; jj < 5; ++jj) {
+                        const int j = h + jj;
+                        if (j < kRSpec && j < nb) {
+                            const int aj = __builtin_amdgcn_readlane(ab, j);
+                            hr5[jj] = rs.u.sp.brow[j][pk];
+                            hc5[jj] = rs.u.sp.bcol[j][k];
+                            dr5[jj] = (int32_t)sm.D[(r0 + j) * kRN + k];
+                            fa5[jj] = (int32_t)sm.F[aj * kRN + pk];
                         }
                     }
-                    PDIT_REG_DELTA(rj)
-                    int sj, tie;
-                    PDIT_REG_DRAW(rj, sj, tie)
-                    if (lane == 0) rs.outc[j] = v4i{sj, tie, 0, 0};
+#pragma unroll
+                    for (int jj = 0; jj < 5; ++jj) {
+                        const int j = h + jj;
+                        if (j >= kRSpec) break;
+                        dvb[j] = kRBig;
+                        if (j < nb) {
+                            const int rj = r0 + j;
+                            const int32_t hrr = __builtin_amdgcn_readlane(hb_v, j);
+                            const int32_t d_rr = __builtin_amdgcn_readlane(db_v, j);
+                            const int32_t f_a = __builtin_amdgcn_readlane(fb_v, j);
+                            const int32_t x = 2 * (hr5[jj] - hrr + hc5[jj] - dg);
+                            const int32_t y = ZD ? 4 * __mul24(dr5[jj], fa5[jj])
+                                                 : __mul24(d_rr + ddk - 2 * dr5[jj],
+                                                           f_a + fdk - 2 * fa5[jj]);
+                            const int32_t dvj = !kval ? kRBig : k == rj ? 0 : x + y;
+                            dvb[j] = dvj;
+                            const int32_t mwj = wave_min_i32(k == rj ? kRBig : dvj);
+                            if (lane == 0) rs.bmin[j][wv] = mwj;
+                        }
+                    }
                 }
                 if (!ok) break;
                 rep_signal(rs.sync, wv, ++seq);
-                // the outcomes: the first exchange ends the batch
-                v4i o;
-                {
-                    const v4i fl = *flags;
-                    __asm__ volatile("" ::: "memory");
-                    o = rs.outc[lane < nb ? lane : 0];
-                    if (!rep_done(fl, seq)) {
-                        ok = rep_spin(flags, seq);
-                        if (!ok) break;
-                        o = rs.outc[lane < nb ? lane : 0];
+                // the minima: updates whose other candidates all lie beyond the
+                // zero-weight distance keep their facility; the others draw in
+                // order, on the batch's state, until one draws an exchange
+                int32_t m4;
+                PDIT_REG_POLL(m4 = (&rs.bmin[0][0])[lane < 4 * nb ? lane : 0];)
+                m4 = min(m4, quad<kQuadXor1>(m4));
+                m4 = min(m4, quad<kQuadXor2>(m4));
+                uint64_t open = __ballot(lane < 4 * nb && (lane & 3) == 0 && m4 < dthr);
+                int jm = nb, sm_ = 0, bm_ = 0;
+                int32_t dm_ = 0;
+                const bool drew = open != 0;
+                if (open) {
+                    // the draws of the open updates, each taken by every wave on
+                    // all N candidates, four consecutive locations per lane (no
+                    // meeting): their p, H[k][k], D[k][k] and F[p(k)][p(k)]
+                    const int32_t pk4[4] = {pk4v.x, pk4v.y, pk4v.z, pk4v.w};
+                    const int32_t dg4[4] = {dg4v.x, dg4v.y, dg4v.z, dg4v.w};
+                    int32_t dd4[4], fd4[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        dd4[i] = ZD ? 0 : (int32_t)sm.D[(4 * lane + i) * (kRN + 1)];
+                        fd4[i] = ZD ? 0 : (int32_t)sm.F[pk4[i] * (kRN + 1)];
+                    }
+                    while (open) {
+                        const int j = (__ffsll((unsigned long long)open) - 1) >> 2;
+                        open &= open - 1;
+                        const int rj = r0 + j;
+                        const int aj = __builtin_amdgcn_readlane(ab, j);
+                        const int16_t *brow = rs.u.sp.brow[j];
+                        const v2i hc2 = *(const v2i *)&rs.u.sp.bcol[j][4 * lane];
+                        const uint32_t drw = D32[rj * (kRN / 4) + lane];
+                        int32_t hr4[4], fa4[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            hr4[i] = brow[pk4[i]];
+                            fa4[i] = (int32_t)sm.F[aj * kRN + pk4[i]];
+                        }
+                        const int32_t hrr = __builtin_amdgcn_readlane(hb_v, j);
+                        const int32_t d_rr = __builtin_amdgcn_readlane(db_v, j);
+                        const int32_t f_a = __builtin_amdgcn_readlane(fb_v, j);
+                        const int32_t m2 = __builtin_amdgcn_readlane(m4, 4 * j);
+                        const int32_t hc4[4] = {(int32_t)(int16_t)(hc2.x & 0xFFFF), hc2.x >> 16,
+                                                (int32_t)(int16_t)(hc2.y & 0xFFFF), hc2.y >> 16};
+                        int32_t dv4[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int kk = 4 * lane + i;
+                            const int32_t dr = byte_at<SGN>(drw, i);
+                            const int32_t x = 2 * (hr4[i] - hrr + hc4[i] - dg4[i]);
+                            const int32_t y = ZD ? 4 * __mul24(dr, fa4[i])
+                                                 : __mul24(d_rr + dd4[i] - 2 * dr, f_a + fd4[i] - 2 * fa4[i]);
+                            dv4[i] = kk >= N ? kRBig : kk == rj ? 0 : x + y;
+                        }
+                        // weights, the exact 64-bit running sums (the lane's four
+                        // weights, < 2^27, scanned as 16-bit halves) and the draw
+                        const int32_t mn = min(m2, 0);
+                        uint32_t q[4];
+                        int32_t dd[4];
+                        bool any = false;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            dd[i] = dv4[i] - mn;
+                            const bool valid = 4 * lane + i < N;
+                            q[i] = (valid && dd[i] == 0) ? kWeightOne : 0u;
+                            any = any || (valid && dd[i] > 0 && dd[i] < dthr);
+                        }
+                        if (__ballot(any)) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const bool need = 4 * lane + i < N && dd[i] > 0 && dd[i] < dthr;
+                                const uint32_t wq = gibbs_weight(beta, (float)dd[i]);
+                                q[i] = need ? wq : q[i];
+                            }
+                        }
+                        const uint32_t qs = q[0] + q[1] + q[2] + q[3];
+                        const uint32_t slo = scan_u32(qs & 0xFFFFu);
+                        const uint32_t shi = scan_u32(qs >> 16);
+                        const uint64_t C = ((uint64_t)shi << 16) + slo;
+                        const uint64_t Z =
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)shi, 63) << 16) +
+                            (uint32_t)__builtin_amdgcn_readlane((int)slo, 63);
+                        const uint32_t ur = (uint32_t)__builtin_amdgcn_readlane((int)ub_v, j);
+                        const uint64_t thr = ((uint64_t)ur * Z) >> 24;   // first C > thr
+                        const uint64_t hit = __ballot(C > thr);
+                        const int sl = __ffsll((unsigned long long)hit) - 1;
+                        const uint64_t cc0 = C - qs + q[0], cc1 = cc0 + q[1], cc2 = cc1 + q[2];
+                        const bool b0 = cc0 > thr, b1 = cc1 > thr, b2 = cc2 > thr;
+                        const int sel = b0 ? 0 : b1 ? 1 : b2 ? 2 : 3;
+                        const uint64_t csel = b0 ? cc0 : b1 ? cc1 : b2 ? cc2 : C;
+                        const uint32_t qsel = b0 ? q[0] : b1 ? q[1] : b2 ? q[2] : q[3];
+                        const int32_t dsel = b0 ? dv4[0] : b1 ? dv4[1] : b2 ? dv4[2] : dv4[3];
+                        const int32_t psel = b0 ? pk4[0] : b1 ? pk4[1] : b2 ? pk4[2] : pk4[3];
+                        const int ssel = __builtin_amdgcn_readlane(sel, sl);
+                        const uint64_t cs = readlane_u64(csel, sl);
+                        const uint32_t qq = (uint32_t)__builtin_amdgcn_readlane((int32_t)qsel, sl);
+                        n_tie += is_tie(cs - qq, cs, Z, ur) ? 1 : 0;
+                        const int sj = 4 * sl + ssel;
+                        if (sj != rj) {
+                            jm = j;
+                            sm_ = sj;
+                            dm_ = __builtin_amdgcn_readlane(dsel, sl);
+                            bm_ = __builtin_amdgcn_readlane(psel, sl);
+                            break;
+                        }
                     }
                 }
-                const uint64_t moves = __ballot(lane < nb && o.x != r0 + lane);
-                const int jm = moves ? __ffsll((unsigned long long)moves) - 1 : nb;
-                n_tie += __popcll(__ballot(lane < jm && o.y != 0));
-                if (ch && lane < jm) ch[r0 + lane] = o.x;
+                if (!ok) break;
+                if (ch && lane < jm) ch[r0 + lane] = r0 + lane;
                 replayed = false;
                 if (jm == nb) {
                     r0 += nb;
+                    if (drew) {
+                        // the draws read the batch's rows and columns without a
+                        // meeting: the next publication waits for every wave
+                        rep_signal(rs.sync, wv, ++seq);
+                        replayed = true;
+                    }
                     continue;
                 }
-                r0 += jm;
+                // the exchange: the update's reads again (another wave may have
+                // evaluated it last)
+                r = r0 + jm;
+                s = sm_;
+                af = __builtin_amdgcn_readlane(ab, jm);
+                bf = bm_;
+                des = dm_;
                 prow = rs.u.sp.brow[jm];
-                pcol = rs.u.sp.bcol[jm];
-                fresh = false;
+                PDIT_REG_READS(prow, rs.u.sp.bcol[jm], r, af)
+                f_aa = ZD ? 0 : __builtin_amdgcn_readfirstlane(f_aa_v);
+                if (ch && lane == 0) ch[r] = s;
             } else {
-                const int par = (seq - 1) & 1;  // the buffer that holds row r0, column p(r0)
-                prow = rs.u.sq.prow[par];
-                pcol = rs.u.sq.pcol[par];
-            }
-            // ============ one update: location r0 ============
-            const int r = r0;
-            const int af = pick(pk, r);         // a = p(r)
-            // the flags and the publication in one LDS round trip
-            {
-                const v4i fl = *flags;
-                __asm__ volatile("" ::: "memory");
-                PDIT_REG_READS(prow, pcol, r, af)
-                if (fresh && !rep_done(fl, seq)) {
-                    ok = rep_spin(flags, seq);
-                    if (!ok) break;
-                    PDIT_REG_READS(prow, pcol, r, af)
-                }
-            }
+            // ============ one update: location r = r0 ============
+            prow = rs.u.sq.prow[pbuf];           // row r, column p(r)
+            const int16_t *pcol = rs.u.sq.pcol[pbuf];
+            af = a_next;                        // a = p(r)
+            const int nr = r + 1 < N ? r + 1 : 0;
+            int nxt_v;                          // p(nr) before this update
+            PDIT_REG_POLL({ PDIT_REG_READS(prow, pcol, r, af) nxt_v = rs.pv[nr]; })
             PDIT_REG_DELTA(r)
-            int s, tie;
-            PDIT_REG_DRAW(r, s, tie)
+            if (lane == 0) rs.smin[wv] = mw;
+            rep_signal(rs.sync, wv, ++seq);
+            // the minimum over k != r; with it the uniform of r and p of every
+            // candidate (nothing writes them before the next meeting)
+            v4i mv;
+            uint32_t ur_v;
+            PDIT_REG_POLL({
+                mv = *(const v4i *)rs.smin;
+                ur_v = rs.u24[r];
+                pw0 = rs.pv[lane];
+                pw1 = rs.pv[64 + lane];
+                pw2 = rs.pv[128 + lane];
+                pw3 = rs.pv[192 + lane];
+            })
+            const int32_t m2 = __builtin_amdgcn_readfirstlane(min(min(mv.x, mv.y), min(mv.z, mv.w)));
+            int tie = 0;
+            bf = af;
+            if (m2 < dthr) PDIT_REG_DRAW(r, dv, m2, ur_v, s, tie, des, bf)
+            if (!ok) break;
             n_tie += tie;
             if (ch && lane == 0) ch[r] = s;
-            if (s != r) PDIT_REG_ACCEPT(r, s, af, pick(dv, s), prow, pick(hc, s))
-            ++r0;
-            if (!batch) {
-                // the next update's row and column (the next sweep's first, unless
-                // it runs in batches)
-                if (r0 < N || !PDIT_REG_NEXT_BATCH()) {
-                    const int nr = r0 < N ? r0 : 0;
-                    PDIT_REG_PUBLISH(nr, pick(pk, nr), seq & 1)
-                }
-            } else {
+            nxt = __builtin_amdgcn_readfirstlane(nxt_v);
+            }
+            // ============ the accepted exchange (the step's only one) ============
+            if (s != r) PDIT_REG_ACCEPT(r, s, af, bf, des, prow)
+            r0 = r + 1;
+            if (batch) {
                 replayed = true;
+            } else {
+                // p(r + 1) after this update, and the next update's row and column
+                // (the next sweep's first, unless it runs in batches)
+                const int nr = r + 1 < N ? r + 1 : 0;
+                a_next = (s != r && s == nr) ? af : nxt;
+                if (r0 < N || !PDIT_REG_NEXT_BATCH()) {
+                    pbuf ^= 1;
+                    PDIT_REG_PUBLISH(nr, a_next, pbuf)
+                }
             }
             rep_signal(rs.sync, wv, ++seq);
         }
         if (ok && batch && !PDIT_REG_NEXT_BATCH()) {
             // the next sweep goes one update at a time: its first row and column,
             // once every wave has left the batch buffers they share
-            if (replayed && !rep_done(*flags, seq)) ok = rep_spin(flags, seq);
-            PDIT_REG_PUBLISH(0, pick(pk, 0), seq & 1)
+            if (!rep_done(*flags, seq)) ok = rep_spin(flags, seq);
+            a_next = __builtin_amdgcn_readfirstlane(rs.pv[0]);
+            pbuf ^= 1;
+            PDIT_REG_PUBLISH(0, a_next, pbuf)
             rep_signal(rs.sync, wv, ++seq);
         }
         batch = PDIT_REG_NEXT_BATCH();
 #undef PDIT_REG_NEXT_BATCH
         if (a.E_trace && writer && lane == 0) a.E_trace[rep * a.T + t] = E;
     }
+#undef PDIT_REG_POLL
+#undef PDIT_REG_DRAW
 #undef PDIT_REG_STORE_COL
 #undef PDIT_REG_PUBLISH
-#undef PDIT_REG_PUBLISH_BATCH
 #undef PDIT_REG_READS
 #undef PDIT_REG_DELTA
-#undef PDIT_REG_DRAW
 #undef PDIT_REG_ACCEPT
 
     // ---- outputs ----
     if (!ok && a.err) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (writer) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = 4 * lane + i;
-            if (k < N) a.perm[rep * N + k] = pk[i];
-        }
-        if (lane == 0) {
-            a.E[rep] = E;
-            a.E_best[rep] = E_best;
-            const bool accum = (a.flags & kAccumCounters) != 0;
-            a.counters[3 * rep + 0] = (accum ? a.counters[3 * rep + 0] : 0) + (int64_t)N * a.T;
-            a.counters[3 * rep + 1] = (accum ? a.counters[3 * rep + 1] : 0) + n_acc;
-            a.counters[3 * rep + 2] = (accum ? a.counters[3 * rep + 2] : 0) + n_tie;
-        }
+    if (live && kval) a.perm[rep * N + k] = pk;
+    if (writer && lane == 0) {
+        a.E[rep] = E;
+        a.E_best[rep] = E_best;
+        const bool accum = (a.flags & kAccumCounters) != 0;
+        a.counters[3 * rep + 0] = (accum ? a.counters[3 * rep + 0] : 0) + (int64_t)N * a.T;
+        a.counters[3 * rep + 1] = (accum ? a.counters[3 * rep + 1] : 0) + n_acc;
+        a.counters[3 * rep + 2] = (accum ? a.counters[3 * rep + 2] : 0) + n_tie;
     }
 }
 

@@ -4,8 +4,8 @@ draw by draw (``parity.py``) at ragged and full sizes, zero and nonzero
 diagonals, unsigned and signed 8-bit data, hot, cold, constant and zero
 beta, an odd replica count (the second slot of the last workgroup idle),
 plateau moves, resume across calls, AUTO choosing it, sweeps switching
-between single updates and batches, and windows of the N=256 workload's
-schedule."""
+between single updates and batches, windows of the N=256 workload's
+schedule, and that workload's 512 replicas against the on-chip H kernel."""
 import numpy as np
 import pytest
 import torch
@@ -196,3 +196,28 @@ def test_reg_n256_workload_windows(where):
                    what=f"n256 window at {start}")
     acc = sum(int(p.counters[0][1]) for p in parts)
     say(f"window at {start}: acceptance {acc / (len(rows) * 256 * win):.4f}")
+
+
+def test_reg_equals_h_kernel_on_all_replicas():
+    """Every exact kernel takes the same integer draws, so the register kernel
+    and the class-256 on-chip H kernel must end in identical states on all
+    512 replicas of the N=256 workload over a strided pass of its schedule
+    (every 50th beta up to sweep 75 000: hot sweeps one update at a time,
+    then batches).  Unlike the sampled oracle replays this covers every
+    replica and both replica slots of every workgroup, so a race between the
+    waves of one replica shows up as a difference."""
+    from paper_2605_24408_amd import pdit as P
+    inst = W.config_n256()
+    beta = inst.beta[:75_000:50].copy()
+    outs = {}
+    for sweep in ("reg", "fast"):
+        with P.Pdit(sweep=sweep) as ctx:
+            outs[sweep] = run(ctx, inst.D, inst.F, inst.perms, beta, W.PHILOX_SEED, record=False)
+            assert outs[sweep]["plan"]["sweep"] == sweep
+    a, b = outs["reg"], outs["fast"]
+    for key in ("perm", "E", "E_best", "perm_best"):
+        bad = np.nonzero((a[key] != b[key]).reshape(len(a[key]), -1).any(axis=1))[0]
+        assert bad.size == 0, f"{key} differs in replicas {bad[:16]} ({bad.size} of 512)"
+    assert np.array_equal(a["counters"][:, :2], b["counters"][:, :2])
+    say(f"reg = fast on 512 replicas x {len(beta)} sweeps; accepted "
+        f"{int(a['counters'][:, 1].sum())}")
