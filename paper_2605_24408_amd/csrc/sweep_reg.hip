@@ -20,27 +20,28 @@
 // column of G at a = p(r) (H[k][r] = G[k][a]).  Before each update the waves
 // publish exactly these two vectors to LDS (the lane holding row r writes
 // its 64 entries in every wave; the wave holding facility a writes the
-// column) and wait for each other: that is the only exchange between waves.
-// Then every wave evaluates all N candidates itself, four consecutive
-// locations per lane,
+// column) and wait for each other.  Lane j of wave w then evaluates the one
+// candidate k = 64w + j,
 //   dE_k = 2 (H[r][k] - H[r][r] + H[k][r] - H[k][k])
 //          + (D_rr + D_kk - 2 D_rk)(F_aa + F_cc - 2 F_ac),  c = p(k),
-// with H[k][k], p and the diagonals of D and F kept per candidate in its
-// registers, takes the row minimum, the integer Gibbs weights
-// q = rint(expf(-beta d) 2^25) and their exact 64-bit CDF in location
-// order, as the other sweep kernels do, and draws the same candidate: the
-// four waves reach the same decision with no message.  A row whose only
-// nonzero weight is its own stay (every other candidate lies at or beyond the
-// zero-weight distance above 0) keeps its facility without weights or scan.
+// with H[k][k], p(k) and the diagonals of D and F kept in its registers.
+// The waves meet twice more: for the row minimum over k != r (a row whose
+// only nonzero weight is its own stay, every other candidate lying at or
+// beyond the zero-weight distance above 0, keeps its facility without
+// weights or scan), and for the running sums of the integer Gibbs weights
+// q = rint(expf(-beta d) 2^25), each wave's exact within 32 bits, from which
+// every wave reads the same 64-bit CDF in location order and draws the same
+// candidate, as the other sweep kernels do.
 //
 // Batches.  An update that keeps its facility changes nothing, so when few
 // exchanges are accepted the updates of locations r0 .. r0 + 11 can all be
 // evaluated on the same state: the waves publish the 12 rows and columns
-// together, each wave evaluates three of the updates, and the stays up to
-// the first exchange are committed.  The update with that exchange then runs
-// as a single update on the batch's row and column (it draws the same
-// candidate, the state being the one it was evaluated on) and the next batch
-// starts after it.  Every draw is the sequential one; a sweep runs in
+// together, and each wave takes three of the updates whole, on all N
+// candidates at four consecutive locations per lane (their p and H[k][k]
+// read from LDS), with its own minimum and draw; the draws (candidate, dE,
+// its facility) meet in LDS and the stays up to the first exchange are
+// committed.  That exchange is applied as in a single update, and the next
+// batch starts after it.  Every draw is the sequential one; a sweep runs in
 // batches when the sweep before it accepted at most kRSpecAcc exchanges.
 //
 // Two replicas share a workgroup (eight waves, each SIMD holding one wave of
@@ -63,7 +64,7 @@ constexpr int kRThreads = 64 * kRWaves * kRReps;
 constexpr int32_t kRBig = (1 << 30) - 1;  // padding candidates (|dE| < 2^30 - 1)
 // Batches: kRSpec consecutive updates evaluated on one state when the
 // previous sweep accepted at most kRSpecAcc exchanges
-constexpr int kRSpec = 10;
+constexpr int kRSpec = 12;
 constexpr int kRSpecAcc = 48;
 // spins of a replica's wait before it gives up (about 0.1 s): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
@@ -80,6 +81,7 @@ struct alignas(16) RegRep {
         struct {                               // one update at a time
             alignas(16) int16_t prow[2][kRN];  // row r of G by facility (by update parity)
             alignas(16) int16_t pcol[2][kRN];  // column p(r) of G by location
+            alignas(16) v2i cd[kRWaves][64];   // per candidate: its wave's running weight sum, dE
         } sq;
         struct {                               // a batch of kRSpec updates
             alignas(16) int16_t brow[kRSpec][kRN];
@@ -91,8 +93,7 @@ struct alignas(16) RegRep {
     alignas(16) int32_t pv[kRN];             // p by location
     alignas(16) int32_t dga[kRN];            // batch: H[k][k] by location
     alignas(16) uint32_t u24[kRN];           // the sweep's uniforms by location
-    alignas(16) v2i cd[kRWaves][64];         // per candidate: its wave's running weight sum, dE
-    alignas(16) int32_t bmin[kRSpec][kRWaves];  // batch: per update and wave, min dE over k != r
+    alignas(16) v4i outc[kRSpec];              // batch: per update its draw s, tie flag, dE_s, p(s)
     alignas(16) int32_t smin[kRWaves];       // one update: per wave, min dE over k != r
     alignas(16) uint32_t sync[kRWaves];      // per wave: the last step it finished
 };
@@ -410,14 +411,14 @@ sweep_reg_kernel(SweepArgs a) {
             q_ = need_ ? wq_ : q_;                                                         \
         }                                                                                  \
         const uint32_t C_ = scan_u32(q_);                                                  \
-        rs.cd[wv][lane] = v2i{(int)C_, (DVJ)};                                             \
+        rs.u.sq.cd[wv][lane] = v2i{(int)C_, (DVJ)};                                        \
         rep_signal(rs.sync, wv, ++seq);                                                    \
         v2i c0_, c1_, c2_, c3_;                                                            \
         PDIT_REG_POLL({                                                                    \
-            c0_ = rs.cd[0][lane];                                                          \
-            c1_ = rs.cd[1][lane];                                                          \
-            c2_ = rs.cd[2][lane];                                                          \
-            c3_ = rs.cd[3][lane];                                                          \
+            c0_ = rs.u.sq.cd[0][lane];                                                     \
+            c1_ = rs.u.sq.cd[1][lane];                                                     \
+            c2_ = rs.u.sq.cd[2][lane];                                                     \
+            c3_ = rs.u.sq.cd[3][lane];                                                     \
         })                                                                                 \
         const uint64_t T0_ = (uint32_t)__builtin_amdgcn_readlane(c0_.x, 63);               \
         const uint64_t T1_ = (uint32_t)__builtin_amdgcn_readlane(c1_.x, 63);               \
@@ -489,7 +490,7 @@ sweep_reg_kernel(SweepArgs a) {
                 }
                 const int nb = min(kRSpec, N - r0);
                 const int ab = rs.pv[r0 + (lane < nb ? lane : 0)];  // p of the batch's rows
-                rs.dga[k] = dg;     // for the draws that every wave takes over all N
+                rs.dga[k] = dg;
                 {
                     const int row_ = 4 * lane - r0;
                     const uint32_t dst_ = lds_addr(&rs.u.sp.brow[0][64 * wv]) + 2 * kRN * row_;
@@ -501,120 +502,64 @@ sweep_reg_kernel(SweepArgs a) {
                         PDIT_REG_STORE_COL(__builtin_amdgcn_readlane(ab, j), rs.u.sp.bcol[j])
                 }
                 rep_signal(rs.sync, wv, ++seq);
-                // every update of the batch on this wave's 64 candidates: dE and
-                // minima.  After the meeting, lane j reads update j's uniform
-                // values (G[r][a], D[r][r], F[a][a], the uniform of r) and every
-                // lane p of every candidate (both fixed until the batch's
-                // exchange); then the candidates' reads of five updates at a time
-                // are issued before any of their arithmetic.
-                int32_t dvb[kRSpec];
-                uint32_t ub_v;
-                int32_t hb_v, db_v, fb_v;
-                v4i pk4v, dg4v;     // p and H[k][k] of candidates 4 lane .. 4 lane + 3
-                // (read before the minima's meeting: once a wave has passed it,
-                // it may reach the batch's exchange and change p)
+                // this wave's updates j = wv, wv + 4, wv + 8, each on all N
+                // candidates, four consecutive locations per lane: their p and
+                // H[k][k] from LDS (fixed until the batch's exchange)
+                v4i pk4v, dg4v;
                 PDIT_REG_POLL({
-                    const int jl = lane < nb ? lane : 0;
-                    hb_v = rs.u.sp.brow[jl][ab];
-                    db_v = ZD ? 0 : (int32_t)sm.D[(r0 + jl) * (kRN + 1)];
-                    fb_v = ZD ? 0 : (int32_t)sm.F[ab * (kRN + 1)];
-                    ub_v = rs.u24[r0 + jl];
                     pk4v = *(const v4i *)&rs.pv[4 * lane];
                     dg4v = *(const v4i *)&rs.dga[4 * lane];
                 })
+                const int32_t pk4[4] = {pk4v.x, pk4v.y, pk4v.z, pk4v.w};
+                const int32_t dg4[4] = {dg4v.x, dg4v.y, dg4v.z, dg4v.w};
+                int32_t dd4[4], fd4[4];
 #pragma unroll
-                for (int h = 0; h < kRSpec; h += 5) {
-                    int32_t hr5[5], hc5[5], dr5[5], fa5[5];
-#pragma unroll
-                    for (int jj = 0; jj < 5; ++jj) {
-                        const int j = h + jj;
-                        if (j < kRSpec && j < nb) {
-                            const int aj = __builtin_amdgcn_readlane(ab, j);
-                            hr5[jj] = rs.u.sp.brow[j][pk];
-                            hc5[jj] = rs.u.sp.bcol[j][k];
-                            dr5[jj] = (int32_t)sm.D[(r0 + j) * kRN + k];
-                            fa5[jj] = (int32_t)sm.F[aj * kRN + pk];
-                        }
-                    }
-#pragma unroll
-                    for (int jj = 0; jj < 5; ++jj) {
-                        const int j = h + jj;
-                        if (j >= kRSpec) break;
-                        dvb[j] = kRBig;
-                        if (j < nb) {
-                            const int rj = r0 + j;
-                            const int32_t hrr = __builtin_amdgcn_readlane(hb_v, j);
-                            const int32_t d_rr = __builtin_amdgcn_readlane(db_v, j);
-                            const int32_t f_a = __builtin_amdgcn_readlane(fb_v, j);
-                            const int32_t x = 2 * (hr5[jj] - hrr + hc5[jj] - dg);
-                            const int32_t y = ZD ? 4 * __mul24(dr5[jj], fa5[jj])
-                                                 : __mul24(d_rr + ddk - 2 * dr5[jj],
-                                                           f_a + fdk - 2 * fa5[jj]);
-                            const int32_t dvj = !kval ? kRBig : k == rj ? 0 : x + y;
-                            dvb[j] = dvj;
-                            const int32_t mwj = wave_min_i32(k == rj ? kRBig : dvj);
-                            if (lane == 0) rs.bmin[j][wv] = mwj;
-                        }
-                    }
+                for (int i = 0; i < 4; ++i) {
+                    dd4[i] = ZD ? 0 : (int32_t)sm.D[(4 * lane + i) * (kRN + 1)];
+                    fd4[i] = ZD ? 0 : (int32_t)sm.F[pk4[i] * (kRN + 1)];
                 }
-                if (!ok) break;
-                rep_signal(rs.sync, wv, ++seq);
-                // the minima: updates whose other candidates all lie beyond the
-                // zero-weight distance keep their facility; the others draw in
-                // order, on the batch's state, until one draws an exchange
-                int32_t m4;
-                PDIT_REG_POLL(m4 = (&rs.bmin[0][0])[lane < 4 * nb ? lane : 0];)
-                m4 = min(m4, quad<kQuadXor1>(m4));
-                m4 = min(m4, quad<kQuadXor2>(m4));
-                uint64_t open = __ballot(lane < 4 * nb && (lane & 3) == 0 && m4 < dthr);
-                int jm = nb, sm_ = 0, bm_ = 0;
-                int32_t dm_ = 0;
-                const bool drew = open != 0;
-                if (open) {
-                    // the draws of the open updates, each taken by every wave on
-                    // all N candidates, four consecutive locations per lane (no
-                    // meeting): their p, H[k][k], D[k][k] and F[p(k)][p(k)]
-                    const int32_t pk4[4] = {pk4v.x, pk4v.y, pk4v.z, pk4v.w};
-                    const int32_t dg4[4] = {dg4v.x, dg4v.y, dg4v.z, dg4v.w};
-                    int32_t dd4[4], fd4[4];
+#pragma unroll
+                for (int jj = 0; jj < kRSpec / kRWaves; ++jj) {
+                    const int j = wv + kRWaves * jj;
+                    if (j >= nb) break;
+                    const int rj = r0 + j;
+                    const int aj = __builtin_amdgcn_readlane(ab, j);
+                    const int16_t *brow = rs.u.sp.brow[j];
+                    const v2i hc2 = *(const v2i *)&rs.u.sp.bcol[j][4 * lane];
+                    const uint32_t drw = D32[rj * (kRN / 4) + lane];
+                    const int32_t hrr_j = brow[aj];
+                    const int32_t drr_j = ZD ? 0 : (int32_t)sm.D[rj * (kRN + 1)];
+                    const int32_t faa_j = ZD ? 0 : (int32_t)sm.F[aj * (kRN + 1)];
+                    const uint32_t ur_j = rs.u24[rj];
+                    int32_t hr4[4], fa4[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        dd4[i] = ZD ? 0 : (int32_t)sm.D[(4 * lane + i) * (kRN + 1)];
-                        fd4[i] = ZD ? 0 : (int32_t)sm.F[pk4[i] * (kRN + 1)];
+                        hr4[i] = brow[pk4[i]];
+                        fa4[i] = (int32_t)sm.F[aj * kRN + pk4[i]];
                     }
-                    while (open) {
-                        const int j = (__ffsll((unsigned long long)open) - 1) >> 2;
-                        open &= open - 1;
-                        const int rj = r0 + j;
-                        const int aj = __builtin_amdgcn_readlane(ab, j);
-                        const int16_t *brow = rs.u.sp.brow[j];
-                        const v2i hc2 = *(const v2i *)&rs.u.sp.bcol[j][4 * lane];
-                        const uint32_t drw = D32[rj * (kRN / 4) + lane];
-                        int32_t hr4[4], fa4[4];
+                    const int32_t hrr = __builtin_amdgcn_readfirstlane(hrr_j);
+                    const int32_t d_rr = __builtin_amdgcn_readfirstlane(drr_j);
+                    const int32_t f_a = __builtin_amdgcn_readfirstlane(faa_j);
+                    const int32_t hc4[4] = {(int32_t)(int16_t)(hc2.x & 0xFFFF), hc2.x >> 16,
+                                            (int32_t)(int16_t)(hc2.y & 0xFFFF), hc2.y >> 16};
+                    int32_t dv4[4], mj = kRBig;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            hr4[i] = brow[pk4[i]];
-                            fa4[i] = (int32_t)sm.F[aj * kRN + pk4[i]];
-                        }
-                        const int32_t hrr = __builtin_amdgcn_readlane(hb_v, j);
-                        const int32_t d_rr = __builtin_amdgcn_readlane(db_v, j);
-                        const int32_t f_a = __builtin_amdgcn_readlane(fb_v, j);
-                        const int32_t m2 = __builtin_amdgcn_readlane(m4, 4 * j);
-                        const int32_t hc4[4] = {(int32_t)(int16_t)(hc2.x & 0xFFFF), hc2.x >> 16,
-                                                (int32_t)(int16_t)(hc2.y & 0xFFFF), hc2.y >> 16};
-                        int32_t dv4[4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int kk = 4 * lane + i;
-                            const int32_t dr = byte_at<SGN>(drw, i);
-                            const int32_t x = 2 * (hr4[i] - hrr + hc4[i] - dg4[i]);
-                            const int32_t y = ZD ? 4 * __mul24(dr, fa4[i])
-                                                 : __mul24(d_rr + dd4[i] - 2 * dr, f_a + fd4[i] - 2 * fa4[i]);
-                            dv4[i] = kk >= N ? kRBig : kk == rj ? 0 : x + y;
-                        }
-                        // weights, the exact 64-bit running sums (the lane's four
-                        // weights, < 2^27, scanned as 16-bit halves) and the draw
-                        const int32_t mn = min(m2, 0);
+                    for (int i = 0; i < 4; ++i) {
+                        const int kk = 4 * lane + i;
+                        const int32_t dr = byte_at<SGN>(drw, i);
+                        const int32_t x = 2 * (hr4[i] - hrr + hc4[i] - dg4[i]);
+                        const int32_t y = ZD ? 4 * __mul24(dr, fa4[i])
+                                             : __mul24(d_rr + dd4[i] - 2 * dr, f_a + fd4[i] - 2 * fa4[i]);
+                        dv4[i] = kk >= N ? kRBig : kk == rj ? 0 : x + y;
+                        mj = min(mj, kk == rj ? kRBig : dv4[i]);
+                    }
+                    mj = wave_min_i32(mj);
+                    // the draw, when a candidate lies within the zero-weight
+                    // distance: weights, the exact 64-bit running sums (the
+                    // lane's four weights, < 2^27, scanned as 16-bit halves)
+                    int sj = rj, tj = 0, dj = 0, bj = aj;
+                    if (mj < dthr) {
+                        const int32_t mn = min(mj, 0);
                         uint32_t q[4];
                         int32_t dd[4];
                         bool any = false;
@@ -640,7 +585,7 @@ sweep_reg_kernel(SweepArgs a) {
                         const uint64_t Z =
                             ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)shi, 63) << 16) +
                             (uint32_t)__builtin_amdgcn_readlane((int)slo, 63);
-                        const uint32_t ur = (uint32_t)__builtin_amdgcn_readlane((int)ub_v, j);
+                        const uint32_t ur = (uint32_t)__builtin_amdgcn_readfirstlane((int)ur_j);
                         const uint64_t thr = ((uint64_t)ur * Z) >> 24;   // first C > thr
                         const uint64_t hit = __ballot(C > thr);
                         const int sl = __ffsll((unsigned long long)hit) - 1;
@@ -654,37 +599,33 @@ sweep_reg_kernel(SweepArgs a) {
                         const int ssel = __builtin_amdgcn_readlane(sel, sl);
                         const uint64_t cs = readlane_u64(csel, sl);
                         const uint32_t qq = (uint32_t)__builtin_amdgcn_readlane((int32_t)qsel, sl);
-                        n_tie += is_tie(cs - qq, cs, Z, ur) ? 1 : 0;
-                        const int sj = 4 * sl + ssel;
-                        if (sj != rj) {
-                            jm = j;
-                            sm_ = sj;
-                            dm_ = __builtin_amdgcn_readlane(dsel, sl);
-                            bm_ = __builtin_amdgcn_readlane(psel, sl);
-                            break;
-                        }
+                        tj = is_tie(cs - qq, cs, Z, ur) ? 1 : 0;
+                        sj = 4 * sl + ssel;
+                        dj = __builtin_amdgcn_readlane(dsel, sl);
+                        bj = __builtin_amdgcn_readlane(psel, sl);
                     }
+                    if (lane == 0) rs.outc[j] = v4i{sj, tj, dj, bj};
                 }
                 if (!ok) break;
+                rep_signal(rs.sync, wv, ++seq);
+                // the outcomes: the stays up to the first exchange are committed
+                v4i o;
+                PDIT_REG_POLL(o = rs.outc[lane < nb ? lane : 0];)
+                const uint64_t moves = __ballot(lane < nb && o.x != r0 + lane);
+                const int jm = moves ? __ffsll((unsigned long long)moves) - 1 : nb;
+                n_tie += __popcll(__ballot(lane < nb && lane <= jm && o.y != 0));
                 if (ch && lane < jm) ch[r0 + lane] = r0 + lane;
                 replayed = false;
                 if (jm == nb) {
                     r0 += nb;
-                    if (drew) {
-                        // the draws read the batch's rows and columns without a
-                        // meeting: the next publication waits for every wave
-                        rep_signal(rs.sync, wv, ++seq);
-                        replayed = true;
-                    }
                     continue;
                 }
-                // the exchange: the update's reads again (another wave may have
-                // evaluated it last)
+                // the exchange: this wave's reads of its row and column
                 r = r0 + jm;
-                s = sm_;
+                s = __builtin_amdgcn_readlane(o.x, jm);
+                des = __builtin_amdgcn_readlane(o.z, jm);
+                bf = __builtin_amdgcn_readlane(o.w, jm);
                 af = __builtin_amdgcn_readlane(ab, jm);
-                bf = bm_;
-                des = dm_;
                 prow = rs.u.sp.brow[jm];
                 PDIT_REG_READS(prow, rs.u.sp.bcol[jm], r, af)
                 f_aa = ZD ? 0 : __builtin_amdgcn_readfirstlane(f_aa_v);
