@@ -210,3 +210,33 @@ def test_n512_workload_sampled(P):
         assert got["E"][k] == oracle.energy(inst.D, inst.F, got["perm"][k])
         assert got["E_best"][k] == oracle.energy(inst.D, inst.F, got["perm_best"][k])
     assert (got["counters"][:, 0] == 512 * T).all()
+
+
+@pytest.mark.parametrize("where", ["start", "warm", "middle", "end"])
+def test_n512_workload_windows(P, where):
+    """The N=512 workload at its full replica count (256, so the sampled rows
+    keep their Philox replica indices) over windows of its 2x10^4-sweep
+    schedule: the first 100 sweeps, and 200 sweeps at sweep 6000 (where the
+    acceptance falls, about 0.27), at the middle and at the cold end, each started from the GPU's own state after a strided pass
+    over the schedule before it (every 100th beta) and at the window's own
+    sweep offset; 8 replicas replayed draw by draw on the oracle from the
+    same state."""
+    inst = W.config_n512()
+    rows = [0, 37, 73, 110, 146, 183, 219, 255]
+    start, win = {"start": (0, 100), "warm": (6_000, 200), "middle": (10_000, 200),
+                  "end": (19_800, 200)}[where]
+    perms = inst.perms.copy()
+    if start:
+        pre = inst.beta[:start:100].copy()
+        perms = run_large(P, inst.D, inst.F, perms, pre, W.PHILOX_SEED, sweep="auto",
+                          record=False, offset=10**6)["perm"]
+    say(f"n512 window at {start}")
+    beta = inst.beta[start:start + win]
+    got = run_large(P, inst.D, inst.F, perms, beta, W.PHILOX_SEED, sweep="auto", offset=start)
+    assert got["plan"]["sweep"] == "large"
+    parts = replay(got, inst.D, inst.F, perms[rows], beta, W.PHILOX_SEED, offset=start,
+                   rows=rows, threads=8, what=f"n512 window at {start}")
+    acc = sum(int(p.counters[0][1]) for p in parts)
+    say(f"n512 window at {start}: acceptance {acc / (len(rows) * 512 * win):.4f}")
+    for k in range(0, 256, 51):
+        assert got["E"][k] == oracle.energy(inst.D, inst.F, got["perm"][k])
