@@ -62,6 +62,8 @@ extern "C" {
 #define PDIT_EDEVICE (-6)   /* HIP runtime error (text in pdit_last_error) */
 #define PDIT_EBETA (-7)     /* an inverse temperature is NaN, infinite or negative */
 #define PDIT_ESTATE (-8)    /* query before any run, or buffers of the wrong run */
+#define PDIT_ECHECK (-9)    /* a paranoid recheck (pdit_opts.paranoid) found a replica whose state
+                               differs from its recomputation from p (Eq. 1) */
 
 #define PDIT_NMAX 512       /* largest supported instance size */
 
@@ -129,6 +131,9 @@ typedef struct {
     int seq_threshold;    /* fast kernel: accepted moves in a sweep above which the next sweep
                              runs one update at a time; < 0 = default: max(4, N/4) for
                              N <= 128, 3 above */
+    int paranoid;         /* nonzero: pdit_run_sweeps runs one sweep per launch and after each
+                             one recomputes every replica from its permutation and checks it
+                             (see pdit_run_sweeps); 0 = off (the default) */
 } pdit_opts;
 
 typedef struct {
@@ -181,6 +186,17 @@ int pdit_destroy(pdit_t *ctx);
  * otherwise.  Validation reads small summaries back to the host, so the call
  * synchronises once before the sweeps are queued; the sweeps themselves run
  * asynchronously.
+ *
+ * With opts.paranoid set, each sweep is its own launch (same draws and
+ * results), and after each one the call synchronises and checks every
+ * replica: its permutation and best permutation are permutations of 0..N-1;
+ * its energy and best energy equal Eq. 1 recomputed exactly from them
+ * (H = D F[p,p], E = tr H, the run's own recompute mode); and where H is
+ * kept in device memory between updates (the plain kernel) every entry of H
+ * equals the recomputation.  The first failing sweep returns PDIT_ECHECK,
+ * with the sweep index and the counts in pdit_last_error, and leaves the
+ * state of that sweep in place.  Recording (pdit_set_recording) is not
+ * available in this mode (PDIT_EINVAL).
  */
 int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                     int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed);
@@ -444,7 +460,8 @@ int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t s
  * race: serialise them.  Nothing in the array needs clearing between calls.
  *
  *   opts       device, stream, sweep, recompute and seq_threshold as for
- *              pdit_create (NULL: the defaults); blocks_per_cu is unused
+ *              pdit_create (NULL: the defaults); blocks_per_cu is unused;
+ *              paranoid must be 0 (its rechecks need buffers: PDIT_EINVAL)
  *   N, D, F, R, perm, beta, n_sweeps, seed   as for pdit_run_sweeps
  *   sweep_offset  global index of the first sweep (Philox counter word 1)
  *   init_best  nonzero: E_best and perm_best start from the initial state;

@@ -192,6 +192,7 @@ void pdit_default_opts(pdit_opts *o) {
     o->sweep = PDIT_SWEEP_AUTO;
     o->blocks_per_cu = 0;
     o->seq_threshold = -1;
+    o->paranoid = 0;
 }
 
 int pdit_create(pdit_t **out, const pdit_opts *opts) {
@@ -258,6 +259,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->clique_buf.ptr);
     hipFree(ctx->large_buf.ptr);
     hipFree(ctx->scratch.ptr);
+    hipFree(ctx->check_buf.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
         if (e) hipEventDestroy(e);
@@ -313,6 +315,76 @@ int run_clique(pdit_t *ctx, int32_t N, const int32_t *D, int32_t R, int32_t *per
     return PDIT_OK;
 }
 
+}  // extern "C"
+
+// Paranoid mode of pdit_run_sweeps: one launch per sweep (the later ones
+// adding to the counters), then every replica checked against its exact
+// recomputation from p (Eq. 1): both permutations, E and E_best, and H
+// itself where the kernel keeps it in device memory (plain).  For the other
+// kernels the recompute of p is written to the H buffer, which is what the
+// next launch starts from.
+template <typename Launch>
+int paranoid_sweeps(pdit_t *ctx, const pdit::SweepArgs &a, Launch &&launch, int mode, bool h64,
+                    bool g_layout, bool h_resident) {
+    const int N = a.N, R = a.R;
+    const size_t hbytes = (size_t)R * N * N * (h64 ? 8 : 4);
+    const size_t head = 256 + 2 * sizeof(int64_t) * (size_t)R;
+    int rc = ensure(ctx, ctx->check_buf, head + (h_resident ? hbytes : 0));
+    if (rc) return rc;
+    char *base = (char *)ctx->check_buf.ptr;
+    int32_t *counts = (int32_t *)base;   // bad perm rows, bad best rows, E, E_best, H
+    int64_t *E_chk = (int64_t *)(base + 256);
+    int64_t *Eb_chk = E_chk + R;
+    void *Hc = h_resident ? (void *)(base + head) : ctx->h_buf.ptr;
+    pdit::ReplicaState &S = ctx->st;
+    for (int64_t t = 0; t < a.T; ++t) {
+        pdit::SweepArgs x = a;
+        x.beta = a.beta + t;
+        x.T = 1;
+        x.sweep_offset = a.sweep_offset + (uint64_t)t;
+        x.flags = t ? pdit::kAccumCounters : 0u;
+        PDIT_HIP(ctx, launch(x));
+        PDIT_HIP(ctx, pdit::launch_zero_i64(ctx->stream, (int64_t *)counts, 4));
+        PDIT_HIP(ctx, pdit::launch_perm_rows_check(ctx->stream, N, R, a.perm, &counts[0]));
+        PDIT_HIP(ctx, pdit::launch_perm_rows_check(ctx->stream, N, R, S.perm_best, &counts[1]));
+        int32_t host[5] = {0, 0, 0, 0, 0};
+        PDIT_HIP(ctx, hipMemcpyAsync(host, counts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     ctx->stream));
+        PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        const uint64_t g = x.sweep_offset;
+        if (host[0] || host[1]) {
+            char msg[160];
+            snprintf(msg, sizeof msg,
+                     "paranoid recheck after sweep %llu: %d rows of perm and %d of perm_best are "
+                     "not permutations", (unsigned long long)g, host[0], host[1]);
+            return fail(ctx, PDIT_ECHECK, msg);
+        }
+        // the best states first, so that the H buffer ends with H of p
+        PDIT_HIP(ctx, run_recompute(ctx, mode, N, a.D, a.F, R, S.perm_best, Hc, h64, Eb_chk,
+                                    g_layout));
+        PDIT_HIP(ctx, pdit::launch_count_diff(ctx->stream, R, 8, Eb_chk, S.E_best, &counts[3]));
+        PDIT_HIP(ctx, run_recompute(ctx, mode, N, a.D, a.F, R, a.perm, Hc, h64, E_chk, g_layout));
+        PDIT_HIP(ctx, pdit::launch_count_diff(ctx->stream, R, 8, E_chk, S.E, &counts[2]));
+        if (h_resident)
+            PDIT_HIP(ctx, pdit::launch_count_diff(ctx->stream, (int64_t)R * N * N, h64 ? 8 : 4, Hc,
+                                                  ctx->h_buf.ptr, &counts[4]));
+        PDIT_HIP(ctx, hipMemcpyAsync(host, counts, sizeof host, hipMemcpyDeviceToHost,
+                                     ctx->stream));
+        PDIT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (host[2] || host[3] || host[4]) {
+            char msg[200];
+            snprintf(msg, sizeof msg,
+                     "paranoid recheck after sweep %llu: %d replicas' energies and %d best "
+                     "energies differ from Eq. 1, %d entries of H from D F[p,p]",
+                     (unsigned long long)g, host[2], host[3], host[4]);
+            return fail(ctx, PDIT_ECHECK, msg);
+        }
+    }
+    return PDIT_OK;
+}
+
+extern "C" {
+
 int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                     int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed) {
     if (!ctx) return PDIT_EINVAL;
@@ -324,6 +396,11 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     if (n_sweeps < 0) return fail(ctx, PDIT_EINVAL, "n_sweeps must be >= 0");
     if (ctx->opts.sweep < PDIT_SWEEP_AUTO || ctx->opts.sweep > PDIT_SWEEP_REG)
         return fail(ctx, PDIT_EINVAL, "unknown sweep kernel");
+    const bool paranoid = ctx->opts.paranoid != 0;
+    if (paranoid && (ctx->rec_choices || ctx->rec_trace))
+        return fail(ctx, PDIT_EINVAL, "recording is not available with paranoid rechecks");
+    if (paranoid && ctx->noalloc)
+        return fail(ctx, PDIT_EINVAL, "paranoid rechecks need buffers: not without allocation");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
 
     // clique flows are looked for where the table kernel does not apply
@@ -338,8 +415,10 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st, nullptr, false,
                        try_clique ? (int32_t *)ctx->clique_buf.ptr : nullptr);
     if (rc) return rc;
-    if (try_clique && pdit::clique_fits(N, st))
+    if (try_clique && pdit::clique_fits(N, st) && !paranoid)
         return run_clique(ctx, N, D, R, perm, beta, n_sweeps, seed);
+    if (paranoid && ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
+        return fail(ctx, PDIT_EINVAL, "the clique kernel has no paranoid rechecks");
     if (ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL,
                     "the clique kernel needs F = c c^T off the diagonal (0/1, a facility subset), "
@@ -421,15 +500,18 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     a.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
     a.err = ctx->err_dev;
     PDIT_HIP(ctx, record_event(ctx, 1));
-    if (n_sweeps > 0) {
-        if (use_reg)
-            PDIT_HIP(ctx, pdit::launch_sweep_reg(ctx->stream, rclass, a));
-        else if (use_fast)
-            PDIT_HIP(ctx, pdit::launch_sweep_fast(ctx->stream, fclass, a));
-        else if (use_large)
-            PDIT_HIP(ctx, pdit::launch_sweep_large(ctx->stream, a, h64, lplan, lcopy));
-        else
-            PDIT_HIP(ctx, pdit::launch_sweep_plain(ctx->stream, a, h64));
+    auto launch = [&](const pdit::SweepArgs &x) -> hipError_t {
+        if (use_reg) return pdit::launch_sweep_reg(ctx->stream, rclass, x);
+        if (use_fast) return pdit::launch_sweep_fast(ctx->stream, fclass, x);
+        if (use_large) return pdit::launch_sweep_large(ctx->stream, x, h64, lplan, lcopy);
+        return pdit::launch_sweep_plain(ctx->stream, x, h64);
+    };
+    if (n_sweeps > 0 && paranoid) {
+        rc = paranoid_sweeps(ctx, a, launch, mode, h64, use_reg,
+                             !use_reg && !use_fast && !use_large);
+        if (rc) return rc;
+    } else if (n_sweeps > 0) {
+        PDIT_HIP(ctx, launch(a));
     } else {
         PDIT_HIP(ctx, pdit::launch_zero_i64(ctx->stream, S.counters, 3 * (int64_t)R));
     }

@@ -84,6 +84,7 @@ struct pdit_ctx {
     int coop = 0;                     // the device supports cooperative launches
     int wall_clock_khz = 0;
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
+    pdit::DeviceBuffer check_buf;     // paranoid rechecks: recomputed energies, H and counts
     pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
     int32_t *err_dev = nullptr;       // deferred device error word
     int32_t *flag_host = nullptr;     // pinned: fused parallel tempering's wait flag
@@ -126,6 +127,12 @@ hipError_t launch_group_sums(hipStream_t s, int R, int G, const int64_t *E, int6
 hipError_t launch_instance_stats(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                                  int R, const int32_t *perm, const float *beta, int64_t T,
                                  InstanceStats *out_dev);
+// paranoid rechecks: rows of perm (R x N) that are not permutations of
+// 0..N-1, added to *bad; entries where two arrays of n elements of
+// elem_bytes (4 or 8) bytes differ, added to *count
+hipError_t launch_perm_rows_check(hipStream_t s, int N, int R, const int32_t *perm, int32_t *bad);
+hipError_t launch_count_diff(hipStream_t s, int64_t n, int elem_bytes, const void *a,
+                             const void *b, int32_t *count);
 
 // g_layout: G = D F[p,:] (columns by facility, for the register sweep kernel)
 // instead of H = D F[p,p]

@@ -69,7 +69,7 @@ __global__ void matrix_stats_kernel(int N, const int32_t *__restrict__ D,
 
 // One block per permutation row (grid-stride): every value in [0, N) seen once.
 __global__ void perm_check_kernel(int N, int R, const int32_t *__restrict__ perm,
-                                  InstanceStats *s) {
+                                  int32_t *bad_rows) {
     __shared__ int32_t seen[PDIT_NMAX];
     for (int row = blockIdx.x; row < R; row += gridDim.x) {
         for (int i = threadIdx.x; i < N; i += blockDim.x) seen[i] = 0;
@@ -86,7 +86,7 @@ __global__ void perm_check_kernel(int N, int R, const int32_t *__restrict__ perm
         for (int i = threadIdx.x; i < N; i += blockDim.x)
             if (seen[i] != 1) bad = 1;
         bad = __syncthreads_or(bad);
-        if (bad && threadIdx.x == 0) atomicAdd(&s->bad_perm_rows, 1);
+        if (bad && threadIdx.x == 0) atomicAdd(bad_rows, 1);
         __syncthreads();
     }
 }
@@ -179,12 +179,45 @@ __global__ void zero_i64_kernel(int64_t *out, int64_t n) {
          i += (int64_t)gridDim.x * blockDim.x)
         out[i] = 0;
 }
+
+// entries where a and b (n elements of T) differ, added to *count
+template <typename T>
+__global__ void count_diff_kernel(int64_t n, const T *__restrict__ a, const T *__restrict__ b,
+                                  int32_t *count) {
+    int diff = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        diff += a[i] != b[i];
+    // one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) diff += __shfl_xor(diff, o);
+    if ((threadIdx.x & 63) == 0 && diff) atomicAdd(count, diff);
+}
 }  // namespace
 
 hipError_t launch_zero_i64(hipStream_t s, int64_t *out, int64_t n) {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     zero_i64_kernel<<<(int)(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_perm_rows_check(hipStream_t s, int N, int R, const int32_t *perm, int32_t *bad) {
+    if (R <= 0) return hipSuccess;
+    perm_check_kernel<<<R < 2048 ? R : 2048, 256, 0, s>>>(N, R, perm, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_diff(hipStream_t s, int64_t n, int elem_bytes, const void *a,
+                             const void *b, int32_t *count) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    const int grid = (int)(blocks < 2048 ? blocks : 2048);
+    if (elem_bytes == 8)
+        count_diff_kernel<int64_t><<<grid, 256, 0, s>>>(n, (const int64_t *)a, (const int64_t *)b,
+                                                        count);
+    else
+        count_diff_kernel<int32_t><<<grid, 256, 0, s>>>(n, (const int32_t *)a, (const int32_t *)b,
+                                                        count);
     return hipGetLastError();
 }
 
@@ -195,7 +228,7 @@ hipError_t launch_instance_stats(hipStream_t st, int N, const int32_t *D, const 
     matrix_stats_kernel<<<(2 * N + 255) / 256, 256, 0, st>>>(N, D, F, out);
     if (perm && R > 0) {
         const int grid = R < 2048 ? R : 2048;
-        perm_check_kernel<<<grid, 256, 0, st>>>(N, R, perm, out);
+        perm_check_kernel<<<grid, 256, 0, st>>>(N, R, perm, &out->bad_perm_rows);
     }
     if (beta && T > 0) {
         const int64_t blocks = (T + 255) / 256;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpdit.so")
 PDIT_OK = 0
 STATUS = {0: "PDIT_OK", -1: "PDIT_EINVAL", -2: "PDIT_ENOTSYM", -3: "PDIT_EBADPERM",
           -4: "PDIT_EOVERFLOW", -5: "PDIT_ENOMEM", -6: "PDIT_EDEVICE", -7: "PDIT_EBETA",
-          -8: "PDIT_ESTATE"}
+          -8: "PDIT_ESTATE", -9: "PDIT_ECHECK"}
 NMAX = 512
 
 RECOMPUTE = {"auto": 0, "plain": 1, "i8": 2, "bf16": 3, "split": 4}
@@ -38,7 +38,8 @@ class PditError(RuntimeError):
 
 class _Opts(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("recompute", C.c_int),
-                ("sweep", C.c_int), ("blocks_per_cu", C.c_int), ("seq_threshold", C.c_int)]
+                ("sweep", C.c_int), ("blocks_per_cu", C.c_int), ("seq_threshold", C.c_int),
+                ("paranoid", C.c_int)]
 
 
 class _Tuning(C.Structure):
@@ -195,11 +196,14 @@ def _close_open_contexts():
 
 
 class Pdit:
-    """A library context (``pdit_create``) bound to one device and stream."""
+    """A library context (``pdit_create``) bound to one device and stream.
+    ``paranoid``: every sweep of ``run_sweeps`` is its own launch and is
+    rechecked against Eq. 1 recomputed from the permutations (PditError
+    PDIT_ECHECK on a mismatch; no recording in this mode)."""
 
     def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None,
                  recompute: str = "auto", sweep: str = "auto", blocks_per_cu: int = 0,
-                 seq_threshold: int = -1):
+                 seq_threshold: int = -1, paranoid: bool = False):
         self._L = load_library()
         self.device = torch.device("cuda", device)
         if stream is None:
@@ -213,6 +217,7 @@ class Pdit:
         o.sweep = SWEEP[sweep]
         o.blocks_per_cu = blocks_per_cu
         o.seq_threshold = seq_threshold
+        o.paranoid = int(bool(paranoid))
         h = C.c_void_p()
         rc = self._L.pdit_create(C.byref(h), C.byref(o))
         if rc != PDIT_OK:
