@@ -85,10 +85,12 @@ def parse():
                     help="n256: sweep kernel of the timed path")
     ap.add_argument("--workload", default="n256",
                     choices=["n256", "n64", "n12", "uneven", "n256p", "n512", "pt", "cupim",
-                             "clique"],
+                             "clique", "hrec"],
                     help="n256 is the benchmark configuration; n64 times the N=64 workload's "
-                         "full schedule; the others report the fast-vs-plain comparison for "
-                         "the other workload shapes (n256p: a prefix of the N=256 schedule)")
+                         "full schedule; hrec times the H recompute step on its own at the "
+                         "N=256 and N=512 workloads' shapes; the others report the "
+                         "fast-vs-plain comparison for the other workload shapes (n256p: a "
+                         "prefix of the N=256 schedule)")
     ap.add_argument("--sweeps", type=int, default=0,
                     help="run only the first SWEEPS sweeps of the schedule (0 = all)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -686,10 +688,71 @@ def main():
     if args.workload == "n256":
         n256_workload(args)
         return
+    if args.workload == "hrec":
+        hrec_workload(args)
+        return
     if args.workload != "n64":
         other_workload(args)
         return
     n64_workload(args)
+
+
+# peaks of MI355X: dense MFMA (bf16 2.5 PFLOP/s, int8 5.0 POP/s), HBM 8 TB/s
+PEAK_BF16 = 2.5e15
+PEAK_I8 = 5.0e15
+PEAK_HBM = 8.0e12
+
+
+def hrec_workload(args):
+    """Step "H recompute" (pdit_h_recompute) on its own, over all replicas of
+    the N=256 workload (bf16 MFMA; u8 distances above 127 rule out int8) and
+    the N=512 workload (byte-plane split MFMA, int64 H), plus the N=256 shape
+    with 7-bit data for the int8 mode.  Per call: the time of the recompute
+    (H in the library's buffer and its trace) from HIP events, the MFMA
+    operations it issues (2 R N^3 per product; four products in split mode)
+    against the dense peak of their type, and the HBM bytes of the H it
+    writes against 8 TB/s."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit as P
+    from paper_2605_24408_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    reps = args.steps or 20
+    warm = args.warmup if args.warmup is not None else 2
+    c4, c5 = W.config_n256(), W.config_n512()
+    small = np.minimum(c4.D, 127).astype(np.int32)   # the int8 mode's data at the same shape
+    cases = [("qap_n256_euclid", c4.D, c4.F, c4.perms, "bf16", 1),
+             ("qap_n256_euclid (D clipped to 127)", small, c4.F, c4.perms, "i8", 1),
+             ("qap_n512_uniform1e4", c5.D, c5.F, c5.perms, "split", 4)]
+    results = []
+    with P.Pdit() as ctx:
+        for name, D, F, perms, mode, products in cases:
+            Dd = torch.from_numpy(np.ascontiguousarray(D, dtype=np.int32)).to(dev)
+            Fd = torch.from_numpy(np.ascontiguousarray(F, dtype=np.int32)).to(dev)
+            pd = torch.from_numpy(np.ascontiguousarray(perms, dtype=np.int32)).to(dev)
+            R, N = pd.shape
+            times = []
+            for k in range(warm + reps):
+                ctx.h_recompute(Dd, Fd, pd, mode=mode, with_H=False)
+                if k >= warm:
+                    times.append(ctx.last_timing()[0])
+            ms = float(np.median(times))
+            h64 = mode == "split"            # the N=512 data need int64 H
+            hbytes = R * N * N * (8 if h64 else 4)
+            ops = products * 2.0 * R * N ** 3
+            peak = PEAK_BF16 if mode == "bf16" else PEAK_I8
+            achieved = ops / (ms * 1e-3)
+            results.append({"config": name, "N": N, "R": R, "mode": mode, "ms": ms,
+                            "mfma_ops": ops, "achieved_ops_per_s": achieved, "peak": peak,
+                            "frac_mfma": achieved / peak, "h_bytes": hbytes,
+                            "hbm_gbs": hbytes / (ms * 1e-3) / 1e9,
+                            "frac_hbm": hbytes / (ms * 1e-3) / PEAK_HBM})
+            print(f"{name} {mode}: {ms:.3f} ms, {achieved / 1e12:.1f} T ops/s "
+                  f"({100 * achieved / peak:.1f}% of peak), H {hbytes / 1e6:.0f} MB at "
+                  f"{hbytes / (ms * 1e-3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "h_recompute", "steps": reps, "warmup": warm,
+                      "unit": "ms per call", "results": results}), flush=True)
 
 
 def n64_workload(args):

@@ -399,6 +399,9 @@ int pdit_set_recording(pdit_t *ctx, int32_t *choices, int64_t *E_trace);
  * for R permutations, in the given PDIT_RECOMPUTE_* mode (PDIT_EOVERFLOW if
  * that mode is not exact for the data).
  *   H_out  device int64 R x N x N (may be NULL), E_out device int64 R.
+ * Afterwards pdit_last_timing reports the recompute (H in the library's own
+ * buffer and its trace) as recompute_ms and the copy to H_out as sweep_ms,
+ * and pdit_last_plan the mode that ran.
  */
 int pdit_h_recompute(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                      const int32_t *perm, int mode, int64_t *H_out, int64_t *E_out);
@@ -452,7 +455,8 @@ int pdit_debug_uniform24(pdit_t *ctx, int32_t M, const uint32_t *ctr, uint64_t s
  * Work space: a device array of PDIT_NOALLOC_SCRATCH_BYTES that the library
  * holds on every GPU it runs this call on, until the process ends.  It
  * holds the instance summary, the clique membership, the copies of D and F
- * of the kernel without a stored H (up to 4 MiB) and the initial H of every
+ * of the kernel without a stored H (up to 4 MiB), D and F in the MFMA
+ * operand format of the H recompute (up to 1 MiB) and the initial H of every
  * replica (R N^2 int32, or int64 when the bound on |H| needs it); a run
  * that needs more returns PDIT_ENOMEM with a message.  Every call on a GPU
  * uses that GPU's one array (and one host copy of the instance summary), so

@@ -176,7 +176,11 @@ hipError_t run_recompute(pdit_t *ctx, int mode, int N, const int32_t *D, const i
                          bool g_layout = false) {
     if (mode == PDIT_RECOMPUTE_PLAIN)
         return pdit::launch_h_recompute_plain(ctx->stream, N, D, F, R, perm, H, h64, E, g_layout);
-    return pdit::launch_h_recompute_mfma(ctx->stream, mode, N, D, F, R, perm, H, h64, E, g_layout);
+    // (a failure here leaves its message and reads as out of memory)
+    if (ensure(ctx, ctx->conv_buf, pdit::mfma_operand_bytes(mode, N)) != PDIT_OK)
+        return hipErrorOutOfMemory;
+    return pdit::launch_h_recompute_mfma(ctx->stream, mode, N, D, F, R, perm, H, h64, E, g_layout,
+                                         ctx->conv_buf.ptr);
 }
 
 }  // namespace
@@ -260,6 +264,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->large_buf.ptr);
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->check_buf.ptr);
+    hipFree(ctx->conv_buf.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
         if (e) hipEventDestroy(e);
@@ -1434,7 +1439,11 @@ int pdit_h_recompute(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     if (rc) return rc;
     rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
     if (rc) return rc;
+    // pdit_last_timing: the recompute (H and its trace), then the copy to H_out
+    ctx->timed = false;
+    PDIT_HIP(ctx, record_event(ctx, 0));
     PDIT_HIP(ctx, run_recompute(ctx, m, N, D, F, R, perm, ctx->h_buf.ptr, h64, E_out));
+    PDIT_HIP(ctx, record_event(ctx, 1));
     if (H_out) {
         const int64_t count = (int64_t)R * N * N;
         if (h64)
@@ -1444,6 +1453,9 @@ int pdit_h_recompute(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
             PDIT_HIP(ctx, pdit::launch_widen_h(ctx->stream, count, (const int32_t *)ctx->h_buf.ptr,
                                                H_out));
     }
+    PDIT_HIP(ctx, record_event(ctx, 2));
+    ctx->timed = true;
+    ctx->last_mode = m;
     return PDIT_OK;
 }
 
@@ -1525,6 +1537,7 @@ constexpr size_t kNoAllocScratch = (size_t)PDIT_NOALLOC_SCRATCH_BYTES;
 constexpr size_t kNoAllocStats = 4096;             // instance summary
 constexpr size_t kNoAllocClique = 4096;            // clique membership, N <= 512 words
 constexpr size_t kNoAllocCopies = (size_t)4 << 20;  // large kernel copies, any N <= 512
+constexpr size_t kNoAllocConv = (size_t)1 << 20;    // MFMA operand copies of D and F, N <= 512
 constexpr int kNoAllocDevices = 64;
 
 __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
@@ -1594,7 +1607,8 @@ int pdit_run_sweeps_noalloc(const pdit_opts *opts, int32_t N, const int32_t *D, 
     c.scratch = {b, kNoAllocStats};
     c.clique_buf = {b + kNoAllocStats, kNoAllocClique};
     c.large_buf = {b + kNoAllocStats + kNoAllocClique, kNoAllocCopies};
-    const size_t used = kNoAllocStats + kNoAllocClique + kNoAllocCopies;
+    c.conv_buf = {b + kNoAllocStats + kNoAllocClique + kNoAllocCopies, kNoAllocConv};
+    const size_t used = kNoAllocStats + kNoAllocClique + kNoAllocCopies + kNoAllocConv;
     c.h_buf = {b + used, kNoAllocScratch - used};
     pdit::ReplicaState &S = c.st;
     S.n_inst = 1;

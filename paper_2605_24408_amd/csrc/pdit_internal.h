@@ -85,6 +85,7 @@ struct pdit_ctx {
     int wall_clock_khz = 0;
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
     pdit::DeviceBuffer check_buf;     // paranoid rechecks: recomputed energies, H and counts
+    pdit::DeviceBuffer conv_buf;      // H recompute on MFMA: D and F in operand format
     pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
     int32_t *err_dev = nullptr;       // deferred device error word
     int32_t *flag_host = nullptr;     // pinned: fused parallel tempering's wait flag
@@ -139,9 +140,12 @@ hipError_t launch_count_diff(hipStream_t s, int64_t n, int elem_bytes, const voi
 hipError_t launch_h_recompute_plain(hipStream_t s, int N, const int32_t *D, const int32_t *F,
                                     int R, const int32_t *perm, void *H, bool h64,
                                     int64_t *E, bool g_layout = false);
+// operands: device work space of mfma_operand_bytes(mode, N) bytes for D and
+// F in the MFMA operand format (rewritten by every call)
+size_t mfma_operand_bytes(int mode, int N);
 hipError_t launch_h_recompute_mfma(hipStream_t s, int mode, int N, const int32_t *D,
                                    const int32_t *F, int R, const int32_t *perm, void *H,
-                                   bool h64, int64_t *E, bool g_layout = false);
+                                   bool h64, int64_t *E, bool g_layout, void *operands);
 hipError_t launch_widen_h(hipStream_t s, int64_t count, const int32_t *src, int64_t *dst);
 
 struct SweepArgs {

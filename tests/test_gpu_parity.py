@@ -104,6 +104,31 @@ def test_h_recompute_all_modes(P, N, R, lo, hi):
             assert np.array_equal(E.cpu().numpy(), want_E), mode
 
 
+@pytest.mark.parametrize("N,R,lo,hi", [(192, 2, -120, 120), (300, 2, -127, 127),
+                                       (512, 1, -256, 256), (449, 1, -10_000, 10_000)])
+def test_h_recompute_signed_and_wide(P, N, R, lo, hi):
+    """Negative entries (the split planes' floor division) and sizes that
+    leave ragged row and column tiles up to N = 512, in every exact mode."""
+    rng = np.random.default_rng(N + 1)
+    D = W.sym_uniform(rng, N, lo, hi).astype(np.int64)
+    F = W.sym_uniform(rng, N, lo, hi).astype(np.int64)
+    perms = W.random_perms(rng, R, N)
+    want_H = np.stack([D @ F[np.ix_(p, p)] for p in perms])
+    m = max(-lo, hi)
+    bound = m * int(np.abs(F).sum(0).max())
+    with P.Pdit() as ctx:
+        for mode in ("i8", "bf16", "split"):
+            if not {"i8": m <= 127 and bound <= 2**31 - 1, "bf16": m <= 256 and bound < 2**24,
+                    "split": m < 2**14}[mode]:
+                continue
+            say(f"h_recompute signed N={N} mode={mode}")
+            H, E = ctx.h_recompute(dev(D, torch.int32), dev(F, torch.int32),
+                                   dev(perms, torch.int32), mode)
+            torch.cuda.synchronize()
+            assert np.array_equal(H.cpu().numpy(), want_H), mode
+            assert np.array_equal(E.cpu().numpy(), np.trace(want_H, axis1=1, axis2=2)), mode
+
+
 def test_h_recompute_split_int64():
     """Byte-plane split products for values up to 10^4 (H needs int64)."""
     from paper_2605_24408_amd import pdit as P
