@@ -344,6 +344,7 @@ typedef struct {
     int blocks_per_cu;    /* chosen resident workgroups per CU */
     int seq_threshold;    /* chosen sequential-sweep threshold */
     double best_ms;       /* trial time of the chosen setting */
+    int cached;           /* 1: taken from the autotune cache file, no trials run */
 } pdit_tuning;
 
 /*
@@ -352,6 +353,15 @@ typedef struct {
  * changes) for every resident-workgroups-per-CU count and a few sequential
  * thresholds, and stores the fastest setting in the context's options for
  * later runs.  *out may be NULL.
+ *
+ * Cache: if the environment variable PDIT_AUTOTUNE_CACHE names a file, the
+ * setting is looked up there first, keyed by the device architecture, its
+ * compute-unit count and the batch's shape (every instance's N, R and data
+ * width: max(|D|, |F|) within 8, 16 or 32 bits, from the same validation as
+ * a run); a hit applies the stored setting without trials (out->cached = 1),
+ * a miss runs the trials and appends one line "key blocks_per_cu
+ * seq_threshold best_ms" (the last line of a key wins).  The file is plain
+ * text; concurrent writers are not coordinated.
  */
 int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_t n_trial_sweeps,
                   uint64_t seed, pdit_tuning *out);

@@ -1,11 +1,13 @@
 // api.hip -- the C ABI (include/pdit.h): validation, exact-width and mode
 // selection, buffer management and kernel sequencing on the caller's stream.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
 #include <new>
+#include <string>
 
 #include "pdit_internal.h"
 
@@ -271,6 +273,8 @@ int pdit_destroy(pdit_t *ctx) {
     if (ctx->graph_exec) hipGraphExecDestroy(ctx->graph_exec);
     hipFree(ctx->batch_buf.ptr);
     if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+    for (auto st : ctx->group_streams) hipStreamDestroy(st);
+    for (auto ev : ctx->group_events) hipEventDestroy(ev);
     if (ctx->stats_host) hipHostFree(ctx->stats_host);
     if (ctx->flag_host) hipHostFree(ctx->flag_host);
     delete ctx;
@@ -1209,11 +1213,31 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                 ctx->graph_exec = nullptr;
             }
             ctx->graph_sig.clear();
+            // the groups run as independent nodes of the graph: each on a
+            // stream of its own, forked from the capture stream after the
+            // queue reset and joined back to it (their persistent kernels
+            // share no queue and never wait for each other)
+            const size_t ng = groups.size();
+            const bool fork = ng > 1;
+            while (fork && ctx->group_streams.size() < ng) {
+                hipStream_t st = nullptr;
+                PDIT_HIP(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+                ctx->group_streams.push_back(st);
+            }
+            while (fork && ctx->group_events.size() < ng + 1) {
+                hipEvent_t ev = nullptr;
+                PDIT_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                ctx->group_events.push_back(ev);
+            }
             hipStream_t cs = ctx->capture_stream;
             PDIT_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            hipError_t cap = pdit::launch_queue_reset(cs, (int *)(dbuf + off_queue), (int)groups.size());
-            for (size_t gi = 0; gi < groups.size() && cap == hipSuccess; ++gi) {
+            hipError_t cap = pdit::launch_queue_reset(cs, (int *)(dbuf + off_queue), (int)ng);
+            if (fork && cap == hipSuccess) cap = hipEventRecord(ctx->group_events[ng], cs);
+            for (size_t gi = 0; gi < ng && cap == hipSuccess; ++gi) {
                 const auto &g = groups[gi];
+                hipStream_t gs = fork ? ctx->group_streams[gi] : cs;
+                if (fork) cap = hipStreamWaitEvent(gs, ctx->group_events[ng], 0);
+                if (cap != hipSuccess) break;
                 pdit::BatchArgs b{};
                 b.inst = (const pdit::BatchInstance *)(dbuf + off_desc);
                 b.items = (const int2 *)(dbuf + off_items[gi]);
@@ -1228,10 +1252,13 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
                 b.T = n_sweeps;
                 b.seq_threshold = seq_thr >= 0 ? seq_thr : pdit::default_seq_threshold(g.nmax, g.nmax);
                 b.rec = rec ? 1 : 0;
-                cap = g.fast    ? pdit::launch_sweep_fast_persistent(cs, g.nmax, g.zd, b, g.grid)
-                      : g.large ? pdit::launch_sweep_large_persistent(cs, g.lp, g.h64, b, g.grid)
-                                : pdit::launch_sweep_plain_persistent(cs, g.h64, b, g.grid);
+                cap = g.fast    ? pdit::launch_sweep_fast_persistent(gs, g.nmax, g.zd, b, g.grid)
+                      : g.large ? pdit::launch_sweep_large_persistent(gs, g.lp, g.h64, b, g.grid)
+                                : pdit::launch_sweep_plain_persistent(gs, g.h64, b, g.grid);
+                if (fork && cap == hipSuccess) cap = hipEventRecord(ctx->group_events[gi], gs);
             }
+            for (size_t gi = 0; fork && gi < ng && cap == hipSuccess; ++gi)
+                cap = hipStreamWaitEvent(cs, ctx->group_events[gi], 0);
             hipGraph_t graph = nullptr;
             const hipError_t end = hipStreamEndCapture(cs, &graph);
             if (cap != hipSuccess) {
@@ -1266,6 +1293,46 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
     if (!inst || n_inst < 1 || n_trial_sweeps < 1)
         return fail(ctx, PDIT_EINVAL, "bad instance list or trial length");
     PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    // the cache file, keyed by architecture, CU count and the batch's shape
+    const char *cache = getenv("PDIT_AUTOTUNE_CACHE");
+    std::string key;
+    if (cache && *cache) {
+        hipDeviceProp_t prop;
+        PDIT_HIP(ctx, hipGetDeviceProperties(&prop, ctx->opts.device));
+        key = std::string(prop.gcnArchName) + "/cu" + std::to_string(ctx->num_cus);
+        for (int k = 0; k < n_inst; ++k) {
+            if (!inst[k].perm || inst[k].N < 2 || inst[k].N > PDIT_NMAX || inst[k].R < 1)
+                return fail(ctx, PDIT_EINVAL, "bad instance descriptor");
+            InstanceStats st;
+            const int prc = instance_prep(ctx, inst[k].N, inst[k].D, inst[k].F, inst[k].R,
+                                          inst[k].perm, nullptr, 0, &st);
+            if (prc) return prc;
+            const int32_t mx = std::max(st.max_abs_d, st.max_abs_f);
+            key += "/" + std::to_string(inst[k].N) + "x" + std::to_string(inst[k].R) + "w" +
+                   (mx <= 127 ? "8" : mx <= 32767 ? "16" : "32");
+        }
+        for (char &c : key)
+            if (c == ' ' || c == '\t' || c == '\n') c = '_';
+        if (FILE *f = fopen(cache, "r")) {
+            char line[8192];
+            pdit_tuning hit{0, 0, 0.0, 0};
+            while (fgets(line, sizeof line, f)) {
+                char k2[4096];
+                int bpc = 0, thr = 0;
+                double ms = 0.0;
+                if (sscanf(line, "%4095s %d %d %lf", k2, &bpc, &thr, &ms) == 4 && key == k2 &&
+                    bpc > 0)
+                    hit = pdit_tuning{bpc, thr, ms, 1};
+            }
+            fclose(f);
+            if (hit.cached) {
+                ctx->opts.blocks_per_cu = hit.blocks_per_cu;
+                ctx->opts.seq_threshold = hit.seq_threshold;
+                if (out) *out = hit;
+                return PDIT_OK;
+            }
+        }
+    }
     // private copies of the permutations: trials must not touch the caller's state
     std::vector<pdit_instance> trial(inst, inst + n_inst);
     std::vector<int32_t *> copies(n_inst, nullptr);
@@ -1285,7 +1352,7 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
     int max_bpc = pdit::plain_blocks_per_cu(false);
     for (int nmax : {16, 32, 64, 96, 128, 160, 256}) max_bpc = std::max(max_bpc, pdit::fast_blocks_per_cu(nmax));
     max_bpc = std::min(max_bpc, 4);
-    pdit_tuning best{0, 0, 1e300};
+    pdit_tuning best{0, 0, 1e300, 0};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == PDIT_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = PDIT_EDEVICE;
@@ -1328,6 +1395,14 @@ int pdit_autotune(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst, int64_
     }
     ctx->opts.blocks_per_cu = best.blocks_per_cu;
     ctx->opts.seq_threshold = best.seq_threshold;
+    if (cache && *cache && key.size() < 4096) {
+        if (FILE *f = fopen(cache, "a")) {
+            fprintf(f, "%s %d %d %.6f\n", key.c_str(), best.blocks_per_cu, best.seq_threshold,
+                    best.best_ms);
+            fclose(f);
+        }
+    }
+    best.cached = 0;
     if (out) *out = best;
     return PDIT_OK;
 }

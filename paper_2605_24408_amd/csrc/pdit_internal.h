@@ -97,6 +97,11 @@ struct pdit_ctx {
     // batched runs: descriptors, work items, queues and per-call parameters
     pdit::DeviceBuffer batch_buf;
     hipStream_t capture_stream = nullptr;             // graphs are captured here, launched on `stream`
+    // batched runs: one stream per group of the captured graph (forked from
+    // and joined back to the capture stream, default priority) and the fork
+    // and join events
+    std::vector<hipStream_t> group_streams;
+    std::vector<hipEvent_t> group_events;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<char> graph_sig;                      // what the captured graph was built for
     int num_cus = 0;

@@ -43,7 +43,8 @@ class _Opts(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("blocks_per_cu", C.c_int), ("seq_threshold", C.c_int), ("best_ms", C.c_double)]
+    _fields_ = [("blocks_per_cu", C.c_int), ("seq_threshold", C.c_int), ("best_ms", C.c_double),
+                ("cached", C.c_int)]
 
 
 class _Counters(C.Structure):
@@ -368,13 +369,14 @@ class Pdit:
         self._last = (R, PT, 0)
 
     def autotune(self, instances, n_trial_sweeps: int, seed: int) -> dict:
-        """pdit_autotune: picks blocks per CU and the sequential threshold."""
+        """pdit_autotune: picks blocks per CU and the sequential threshold
+        (looked up in, or appended to, the file PDIT_AUTOTUNE_CACHE names)."""
         arr, _ = self._instances(instances, None)
         t = _Tuning()
         self._rc(self._L.pdit_autotune(self._h, len(instances), arr, int(n_trial_sweeps),
                                        int(seed), C.byref(t)))
         return {"blocks_per_cu": t.blocks_per_cu, "seq_threshold": t.seq_threshold,
-                "best_ms": t.best_ms}
+                "best_ms": t.best_ms, "cached": bool(t.cached)}
 
     def energy(self) -> torch.Tensor:
         out = torch.empty(self._last[0], dtype=torch.int64, device=self.device)

@@ -171,6 +171,35 @@ def test_autotune_then_run():
     replay_batch(got, batch, 4, what="after autotune")
 
 
+def test_autotune_cache(tmp_path, monkeypatch):
+    """PDIT_AUTOTUNE_CACHE: the first call runs the trials and appends its
+    setting under the batch's key; a second context takes it from the file
+    without trials; a batch of another shape misses and adds a line."""
+    from paper_2605_24408_amd import pdit as P
+    cache = tmp_path / "autotune.txt"
+    monkeypatch.setenv("PDIT_AUTOTUNE_CACHE", str(cache))
+    dbatch = to_dev(small_batch(T=6, R=2), record=False)
+    with P.Pdit() as ctx:
+        first = ctx.autotune(dbatch, 6, 4)
+    assert not first["cached"]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:3] == [str(first["blocks_per_cu"]),
+                                                       str(first["seq_threshold"])]
+    assert lines[0].split()[0].count("/") == 1 + len(dbatch)   # arch/CUs, then one part per instance
+    with P.Pdit() as ctx:
+        second = ctx.autotune(dbatch, 6, 4)
+        ctx.run_sweeps_batch(dbatch, 4)
+        torch.cuda.synchronize()
+    assert second["cached"]
+    assert (second["blocks_per_cu"], second["seq_threshold"]) == (first["blocks_per_cu"],
+                                                                  first["seq_threshold"])
+    other = to_dev(small_batch(T=6, R=3), record=False)
+    with P.Pdit() as ctx:
+        third = ctx.autotune(other, 6, 4)
+    assert not third["cached"]
+    assert len(cache.read_text().splitlines()) == 2
+
+
 def test_uneven_workload_full_size_sampled():
     """The uneven workload at full size (256 instances, N in [20, 150], 64
     replicas each, 2000 sweeps) in one batched call, then again with every
