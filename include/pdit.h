@@ -239,8 +239,9 @@ typedef struct {
     int32_t schedule;       /* PDIT_PT_AUTO, PDIT_PT_PERIODIC or PDIT_PT_FUSED (below) */
     int32_t dynamics;       /* PDIT_PT_SEQUENTIAL: sweeps as in pdit_run_sweeps;
                                PDIT_PT_CUPIM: iterations as in pdit_run_cupim (Methods,
-                               "GPU-CUPIM Algorithm": the same exchange rules), with its data
-                               limits (PDIT_EOVERFLOW otherwise) and the periodic schedule */
+                               "GPU-CUPIM Algorithm": the same exchange rules) on its on-chip
+                               kernel, N <= 128 and |D|, |F| <= 127 (PDIT_EOVERFLOW
+                               otherwise), and the periodic schedule */
 } pdit_pt;
 
 #define PDIT_PT_SEQUENTIAL 0
@@ -293,8 +294,13 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
  * refreshed.  Arguments, sweep offset, best state (checked once per
  * iteration) and outputs as in pdit_run_sweeps; counters: updates = N per
  * iteration, accepted = applied exchanges, ties = draws within the tie
- * band.  Needs N <= 128 and |D|, |F| <= 127 (PDIT_EOVERFLOW otherwise: the
- * refresh runs on int8 MFMA).  Recording is not available.
+ * band.  Any N <= PDIT_NMAX: with N <= 128 and |D|, |F| <= 127 the
+ * replica's snapshot stays on chip (one launch; the refresh on int8 MFMA);
+ * otherwise the snapshot H + H^T lives in device memory and each iteration
+ * is a draw, a resolve and an exact H recompute in the cheapest mode the
+ * data allow (pdit_last_plan: PDIT_SWEEP_LARGE), which needs
+ * 8 |H| + 16 max|D| max|F| < 2^53 (PDIT_EOVERFLOW otherwise).  Recording is
+ * not available.  (pdit_run_pt with PDIT_PT_CUPIM keeps the on-chip limits.)
  */
 int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                    int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed);

@@ -22,7 +22,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "prep.hip", "h_recompute.hip", "sweep_plain.hip", "sweep_fast.hip",
            "sweep_table.hip", "pt.hip", "beta_select.hip", "cupim.hip", "sweep_clique.hip",
-           "sweep_large.hip", "sweep_reg.hip", "debug.hip"]
+           "sweep_large.hip", "sweep_reg.hip", "debug.hip", "cupim_large.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

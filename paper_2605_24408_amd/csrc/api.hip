@@ -267,6 +267,7 @@ int pdit_destroy(pdit_t *ctx) {
     hipFree(ctx->scratch.ptr);
     hipFree(ctx->check_buf.ptr);
     hipFree(ctx->conv_buf.ptr);
+    hipFree(ctx->cupim_buf.ptr);
     hipFree(ctx->err_dev);
     for (auto &e : ctx->ev)
         if (e) hipEventDestroy(e);
@@ -549,7 +550,8 @@ int run_pt_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int
     const int cls = pdit::cupim_class(N, st);
     if (!cls)
         return fail(ctx, PDIT_EOVERFLOW,
-                    "concurrent updates need N <= 128 and |D|, |F| <= 127 (int8 MFMA refresh)");
+                    "parallel tempering with concurrent updates needs N <= 128 and |D|, |F| <= "
+                    "127 (the on-chip kernel)");
     bool fresh = false;
     int rc = shape_state(ctx, {N}, {R}, &fresh);
     if (rc) return rc;
@@ -768,6 +770,90 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     return PDIT_OK;
 }
 
+}  // extern "C"
+
+// GPU-CUPIM where the on-chip kernel does not fit (N > 128 or entries beyond
+// 8 bits): the snapshot S = H + H^T in device memory, one kernel per step of
+// an iteration (validated by the caller).
+int run_cupim_large(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
+                    int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed,
+                    const InstanceStats &st) {
+    const int64_t bound = pdit::h_bound(st);
+    // snapshot energy changes |dE| <= 8 bound + 16 max|D| max|F| must pack
+    // with the location index into the 64-bit proposal key
+    const __int128 dmax = (__int128)8 * bound + (__int128)16 * st.max_abs_d * st.max_abs_f;
+    if (dmax >= ((__int128)1 << 53))
+        return fail(ctx, PDIT_EOVERFLOW,
+                    "concurrent updates need 8 |H| + 16 max|D| max|F| < 2^53");
+    const bool h64 = bound > INT32_MAX;
+    int mode = 0;
+    int rc = pick_recompute(ctx, st, bound, ctx->opts.recompute, &mode);
+    if (rc) return rc;
+    rc = ensure(ctx, ctx->h_buf, (size_t)R * N * N * (h64 ? 8 : 4));
+    if (rc) return rc;
+    const size_t n1 = (size_t)R * N, n2 = n1 * N;
+    rc = ensure(ctx, ctx->cupim_buf, 8 * n2 + 16 * n1 + 8 * n1);
+    if (rc) return rc;
+    bool fresh = false;
+    rc = shape_state(ctx, {N}, {R}, &fresh);
+    if (rc) return rc;
+    pdit::ReplicaState &St = ctx->st;
+    char *b = (char *)ctx->cupim_buf.ptr;
+    pdit::CupimLargeArgs c{};
+    c.N = N;
+    c.R = R;
+    c.D = D;
+    c.F = F;
+    c.perm = perm;
+    int64_t *Sbuf = (int64_t *)b;
+    int64_t *hd = Sbuf + n2;
+    c.S = Sbuf;
+    c.hd = hd;
+    c.dsel = hd + n1;
+    c.sel = (int32_t *)(c.dsel + n1);
+    c.tie = c.sel + n1;
+    c.counters = St.counters;
+    c.beta = beta;
+    c.seed = seed;
+    c.inst_id = 0;
+    c.zero_diag = st.diag_nz_d == 0 && st.diag_nz_f == 0;
+    auto refresh = [&]() -> hipError_t {
+        hipError_t e = run_recompute(ctx, mode, N, D, F, R, perm, ctx->h_buf.ptr, h64, St.E);
+        if (e == hipSuccess) e = pdit::launch_cupim_large_sym(ctx->stream, N, R, ctx->h_buf.ptr, h64, Sbuf, hd);
+        return e;
+    };
+    ctx->timed = false;
+    PDIT_HIP(ctx, record_event(ctx, 0));
+    PDIT_HIP(ctx, refresh());
+    if (fresh) {
+        PDIT_HIP(ctx, hipMemcpyAsync(St.E_best, St.E, sizeof(int64_t) * R, hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+        PDIT_HIP(ctx, hipMemcpyAsync(St.perm_best, perm, sizeof(int32_t) * (size_t)R * N,
+                                     hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    PDIT_HIP(ctx, pdit::launch_zero_i64(ctx->stream, St.counters, 3 * (int64_t)R));
+    PDIT_HIP(ctx, record_event(ctx, 1));
+    for (int64_t t = 0; t < n_sweeps; ++t) {
+        const uint32_t g = (uint32_t)(ctx->sweep_offset + (uint64_t)t);
+        PDIT_HIP(ctx, pdit::launch_cupim_large_draw(ctx->stream, c, t, g));
+        PDIT_HIP(ctx, pdit::launch_cupim_large_resolve(ctx->stream, c));
+        PDIT_HIP(ctx, refresh());
+        PDIT_HIP(ctx, pdit::launch_cupim_large_best(ctx->stream, N, R, perm, St.E, St.E_best,
+                                                    St.perm_best));
+    }
+    PDIT_HIP(ctx, record_event(ctx, 2));
+    ctx->timed = true;
+    ctx->sweep_offset += (uint64_t)n_sweeps;
+    ctx->last_updates = (int64_t)R * N * n_sweeps;
+    ctx->last_sweep = PDIT_SWEEP_LARGE;
+    ctx->last_class = 0;
+    ctx->last_mode = mode;
+    St.best_valid = true;
+    return PDIT_OK;
+}
+
+extern "C" {
+
 int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                    int32_t *perm, const float *beta, int64_t n_sweeps, uint64_t seed) {
     if (!ctx) return PDIT_EINVAL;
@@ -784,9 +870,7 @@ int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, i
     int rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st);
     if (rc) return rc;
     const int cls = pdit::cupim_class(N, st);
-    if (!cls)
-        return fail(ctx, PDIT_EOVERFLOW,
-                    "concurrent updates need N <= 128 and |D|, |F| <= 127 (int8 MFMA refresh)");
+    if (!cls) return run_cupim_large(ctx, N, D, F, R, perm, beta, n_sweeps, seed, st);
     bool fresh = false;
     rc = shape_state(ctx, {N}, {R}, &fresh);
     if (rc) return rc;

@@ -86,6 +86,7 @@ struct pdit_ctx {
     pdit::DeviceBuffer scratch;       // small per-call scratch (stats, flags)
     pdit::DeviceBuffer check_buf;     // paranoid rechecks: recomputed energies, H and counts
     pdit::DeviceBuffer conv_buf;      // H recompute on MFMA: D and F in operand format
+    pdit::DeviceBuffer cupim_buf;     // GPU-CUPIM beyond the on-chip kernel: S, diag H, draws
     pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
     int32_t *err_dev = nullptr;       // deferred device error word
     int32_t *flag_host = nullptr;     // pinned: fused parallel tempering's wait flag
@@ -252,6 +253,33 @@ inline int cupim_class(int N, const InstanceStats &st) {
     return N <= 16 ? 16 : N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 0;
 }
 hipError_t launch_cupim(hipStream_t s, int nmax, const CupimArgs &c);
+
+// GPU-CUPIM with the snapshot in device memory (any N <= PDIT_NMAX, entries
+// beyond 8 bits): one iteration is draw, resolve, the H recompute into H,
+// S = H + H^T with diag H, and the best state.
+struct CupimLargeArgs {
+    int N;
+    int R;
+    const int32_t *D;
+    const int32_t *F;
+    int32_t *perm;           // [R][N] in/out
+    const int64_t *S;        // [R][N][N] H + H^T of the snapshot
+    const int64_t *hd;       // [R][N] diag H
+    int32_t *sel;            // [R][N] each location's draw
+    int64_t *dsel;           // [R][N] its snapshot dE
+    int32_t *tie;            // [R][N] the draw's threshold fell in the tie band
+    int64_t *counters;       // [R][3] (updates, accepted, ties), added to
+    const float *beta;       // [T] one value per iteration
+    uint64_t seed;
+    uint32_t inst_id;
+    bool zero_diag;
+};
+hipError_t launch_cupim_large_draw(hipStream_t s, const CupimLargeArgs &c, int64_t t, uint32_t g);
+hipError_t launch_cupim_large_resolve(hipStream_t s, const CupimLargeArgs &c);
+hipError_t launch_cupim_large_sym(hipStream_t s, int N, int R, const void *H, bool h64,
+                                  int64_t *S, int64_t *hd);
+hipError_t launch_cupim_large_best(hipStream_t s, int N, int R, const int32_t *perm,
+                                   const int64_t *E, int64_t *E_best, int32_t *perm_best);
 
 // The sweep specialised to clique flows (one wave per replica, N <= 512).
 struct CliqueArgs {

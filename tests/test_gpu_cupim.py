@@ -100,6 +100,30 @@ def test_cupim_matches_oracle(N, R, kind, sched):
     assert got["counters"][:, 1].sum() > 0
 
 
+@pytest.mark.parametrize("N,R,hi,zero_diag,sched", [
+    (150, 2, 99, True, "anneal"), (200, 2, 60, False, "hot"), (256, 2, 1000, True, "anneal"),
+    (64, 3, 5000, True, "anneal"), (300, 1, 300, False, "anneal")])
+def test_cupim_large_matches_oracle(N, R, hi, zero_diag, sched):
+    """Beyond the on-chip kernel (N > 128 or entries beyond 8 bits): the
+    snapshot in device memory, refreshed by the H recompute, iteration by
+    iteration against the oracle."""
+    from paper_2605_24408_amd import pdit as P
+    say(f"cupim large N={N} R={R} hi={hi} zero_diag={zero_diag} {sched}")
+    rng = np.random.default_rng(N * 3 + hi)
+    D, F = W.random_instance(rng, N, 0, hi, zero_diag=zero_diag)
+    perms = W.random_perms(rng, R, N)
+    s = W.energy_scale(D, F)
+    T = 30
+    beta = (np.full(T, 0.3 / s, np.float32) if sched == "hot"
+            else W.beta_geometric(0.2 / s, 50.0 / s, T))
+    got, plan = cupim_chunked(P, D, F, perms, beta, 13, what=f"cupim large N={N}")
+    assert plan["sweep"] == "large"
+    assert got["counters"][:, 1].sum() > 0
+    Di, Fi = D.astype(np.int64), F.astype(np.int64)
+    for k in range(R):
+        assert got["E"][k] == int((Di * Fi[np.ix_(got["perm"][k], got["perm"][k])]).sum())
+
+
 def test_cupim_resume_equals_single_call():
     from paper_2605_24408_amd import pdit as P
     rng = np.random.default_rng(2)
@@ -142,15 +166,29 @@ def test_cupim_full_size_sampled():
         assert np.array_equal(part[key], got[key]), key
 
 
+def test_cupim_n256_workload_sampled():
+    """The N=256 workload (distances to 141: beyond the on-chip kernel) at its
+    512 replicas for the first 20 iterations of its schedule: every sampled
+    replica's E equals Eq. 1, and replicas 0, 255 and 511 equal the oracle
+    after every iteration."""
+    from paper_2605_24408_amd import pdit as P
+    inst = W.config_n256()
+    beta = inst.beta[:20]
+    got, plan = cupim_chunked(P, inst.D, inst.F, inst.perms, beta, W.PHILOX_SEED,
+                              rows=[0, 255, 511], what="cupim n256 full size")
+    assert plan["sweep"] == "large"
+    Di, Fi = inst.D.astype(np.int64), inst.F.astype(np.int64)
+    for k in range(0, inst.R, 73):
+        assert got["E"][k] == int((Di * Fi[np.ix_(got["perm"][k], got["perm"][k])]).sum())
+    assert np.all(got["counters"][:, 0] == 256)   # the last call's one iteration
+
+
 def test_cupim_error_paths():
     from paper_2605_24408_amd import pdit as P
     rng = np.random.default_rng(1)
     with P.Pdit() as ctx:
-        D, F = W.random_instance(rng, 130, 0, 9)
-        with pytest.raises(P.PditError) as e:
-            gpu_cupim(ctx, D, F, W.random_perms(rng, 2, 130), np.ones(2, np.float32), 1)
-        assert e.value.status == "PDIT_EOVERFLOW"
-        D, F = W.random_instance(rng, 20, 0, 200)
+        # snapshot energy changes that do not pack into the 64-bit proposal key
+        D, F = W.random_instance(rng, 20, 0, 10**8)
         with pytest.raises(P.PditError) as e:
             gpu_cupim(ctx, D, F, W.random_perms(rng, 2, 20), np.ones(2, np.float32), 1)
         assert e.value.status == "PDIT_EOVERFLOW"
