@@ -184,11 +184,12 @@ __device__ __forceinline__ const lds_v4i *rep_flags(uint32_t *slots) {
     return (const lds_v4i *)(__attribute__((address_space(3))) uint32_t *)slots;
 }
 
-// every wave of the replica has finished step seq (uniform)
+// every wave of the replica has finished step seq (uniform: every lane reads
+// the same four flags, so the ballot is all lanes or none)
 __device__ __forceinline__ bool rep_done(v4i v, uint32_t seq) {
-    const bool done = (int32_t)(v.x - seq) >= 0 && (int32_t)(v.y - seq) >= 0 &&
-                      (int32_t)(v.z - seq) >= 0 && (int32_t)(v.w - seq) >= 0;
-    return __builtin_amdgcn_readfirstlane((int)done) != 0;
+    const int32_t d = min(min((int32_t)(v.x - seq), (int32_t)(v.y - seq)),
+                          min((int32_t)(v.z - seq), (int32_t)(v.w - seq)));
+    return __builtin_amdgcn_ballot_w64(d >= 0) != 0;
 }
 
 // Polls until every wave has finished step seq; false when the wait gave up
