@@ -85,7 +85,7 @@ def parse():
                     help="n256: sweep kernel of the timed path")
     ap.add_argument("--workload", default="n256",
                     choices=["n256", "n64", "n12", "uneven", "n256p", "n512", "pt", "cupim",
-                             "clique", "hrec"],
+                             "clique", "hrec", "cupim256"],
                     help="n256 is the benchmark configuration; n64 times the N=64 workload's "
                          "full schedule; hrec times the H recompute step on its own at the "
                          "N=256 and N=512 workloads' shapes; the others report the "
@@ -691,10 +691,52 @@ def main():
     if args.workload == "hrec":
         hrec_workload(args)
         return
+    if args.workload == "cupim256":
+        cupim256_workload(args)
+        return
     if args.workload != "n64":
         other_workload(args)
         return
     n64_workload(args)
+
+
+def cupim256_workload(args):
+    """GPU-CUPIM beyond the on-chip kernel: the N=256 workload (distances to
+    141) at its 512 replicas, the first --sweeps (default 200) iterations of
+    its schedule, against the sequential sweeps (the register kernel) on the
+    same schedule slice from the same start.  Per method the kernel time of
+    the run (HIP events), updates/s (N updates per iteration or sweep) and
+    the best energy reached; not the benchmark figure."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit as P
+    from paper_2605_24408_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    inst = W.config_n256()
+    T = args.sweeps or 200
+    D = torch.from_numpy(inst.D).to(dev)
+    F = torch.from_numpy(inst.F).to(dev)
+    beta = torch.from_numpy(inst.beta[:T].copy()).to(dev)
+    out = {"workload": "cupim256", "N": inst.N, "replicas": inst.R, "iterations": T}
+    for method in ("cupim", "sweeps"):
+        with P.Pdit() as ctx:
+            for rep in range(2):   # the first run allocates and builds
+                p = torch.from_numpy(inst.perms).to(dev)
+                ctx.set_sweep_offset(0)
+                ctx.reset()
+                (ctx.run_cupim if method == "cupim" else ctx.run_sweeps)(D, F, p, beta,
+                                                                      W.PHILOX_SEED)
+                torch.cuda.synchronize()
+            ms = ctx.last_timing()[1]
+            e, _ = ctx.best()
+            cnt = ctx.counters()
+            out[method] = {"kernel_ms": ms, "updates_per_s": inst.R * inst.N * T / (ms * 1e-3),
+                           "best_energy": int(e.min()), "accepted": cnt["accepted"],
+                           "plan": ctx.last_plan()}
+        print(f"{method}: {ms:.1f} ms, best {out[method]['best_energy']}", file=sys.stderr,
+              flush=True)
+    print(json.dumps(out), flush=True)
 
 
 # peaks of MI355X: dense MFMA (bf16 2.5 PFLOP/s, int8 5.0 POP/s), HBM 8 TB/s
