@@ -379,10 +379,13 @@ int pdit_energy(pdit_t *ctx, int64_t *E_out);
 /* E_best: device int64 R_total; perm_best: device int32, R_total rows of the
  * instance's N (packed instance after instance).  The lowest energy seen
  * since the best state was last reset, and the first permutation that
- * reached it. */
+ * reached it (the best result an algorithm logs: Methods, "Hardware and Data
+ * Reporting Details"). */
 int pdit_best(pdit_t *ctx, int64_t *E_best, int32_t *perm_best);
 
-/* Host struct: totals over all replicas of the last run. */
+/* Host struct: totals over all replicas of the last run (updates: one per
+ * p-dit per sweep or iteration, Results "Implementation"; accepted moves;
+ * draws in the tie band). */
 int pdit_counters(pdit_t *ctx, pdit_counters_t *out);
 
 /* Device int64 R_total x 3: per-replica (updates, accepted, ties) of the last run. */
@@ -430,6 +433,24 @@ int pdit_h_recompute(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
  */
 int pdit_debug_delta(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int32_t R,
                      const int32_t *perm, int32_t r, int64_t *delta_out);
+
+/*
+ * The same steps on the context's own replica state: replica `replica` of
+ * instance `inst` of the last pdit_run_sweeps, pdit_run_sweeps_batch,
+ * pdit_run_cupim or pdit_run_pt (inst 0 for single-instance runs), read
+ * through the D, F and perm pointers that run was given (the caller keeps
+ * them alive; the replica's permutation as the stream reaches this call).
+ *   pdit_debug_H      H = D F[p,p] of that replica (Eq. 2 with I = -2H for
+ *                     symmetric data), location-indexed, as int64 whatever the
+ *                     run stored: H_out device int64 N x N.
+ *   pdit_debug_delta_replica  Eq. 3 for the update of location r of that
+ *                     replica: delta_out device int64 N (0 at s = r).
+ * PDIT_ESTATE before any such run; PDIT_EINVAL for an inst, replica or r out
+ * of range.
+ */
+int pdit_debug_H(pdit_t *ctx, int32_t inst, int32_t replica, int64_t *H_out);
+int pdit_debug_delta_replica(pdit_t *ctx, int32_t inst, int32_t replica, int32_t r,
+                             int64_t *delta_out);
 
 /*
  * The sweep kernels' Gibbs choice on its own: for each of M rows of N energy

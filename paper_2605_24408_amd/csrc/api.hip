@@ -22,6 +22,18 @@ int fail(pdit_t *ctx, int code, const char *msg) {
     return code;
 }
 
+// The last run's instances, for the debug exports.
+void remember(pdit_t *ctx, int32_t N, int32_t R, const int32_t *D, const int32_t *F,
+              int32_t *perm) {
+    pdit_instance x{};
+    x.N = N;
+    x.R = R;
+    x.D = D;
+    x.F = F;
+    x.perm = perm;
+    ctx->last_insts.assign(1, x);
+}
+
 int fail_hip(pdit_t *ctx, hipError_t e, const char *where) {
     if (ctx) {
         ctx->last_error = std::string(where) + ": " + hipGetErrorString(e);
@@ -425,8 +437,11 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     rc = instance_prep(ctx, N, D, F, R, perm, beta, n_sweeps, &st, nullptr, false,
                        try_clique ? (int32_t *)ctx->clique_buf.ptr : nullptr);
     if (rc) return rc;
-    if (try_clique && pdit::clique_fits(N, st) && !paranoid)
-        return run_clique(ctx, N, D, R, perm, beta, n_sweeps, seed);
+    if (try_clique && pdit::clique_fits(N, st) && !paranoid) {
+        rc = run_clique(ctx, N, D, R, perm, beta, n_sweeps, seed);
+        if (rc == PDIT_OK) remember(ctx, N, R, D, F, perm);
+        return rc;
+    }
     if (paranoid && ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
         return fail(ctx, PDIT_EINVAL, "the clique kernel has no paranoid rechecks");
     if (ctx->opts.sweep == PDIT_SWEEP_CLIQUE)
@@ -538,6 +553,7 @@ int pdit_run_sweeps(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->last_class = use_fast ? fclass : use_reg ? 256 : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
+    remember(ctx, N, R, D, F, perm);
     return PDIT_OK;
 }
 
@@ -595,6 +611,7 @@ int run_pt_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int
     ctx->last_class = cls;
     ctx->last_mode = 0;
     S.best_valid = true;
+    remember(ctx, N, R, D, F, perm);
     return PDIT_OK;
 }
 
@@ -767,6 +784,7 @@ int pdit_run_pt(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, int3
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
+    remember(ctx, N, R, D, F, perm);
     return PDIT_OK;
 }
 
@@ -849,6 +867,7 @@ int run_cupim_large(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, 
     ctx->last_class = 0;
     ctx->last_mode = mode;
     St.best_valid = true;
+    remember(ctx, N, R, D, F, perm);
     return PDIT_OK;
 }
 
@@ -904,6 +923,7 @@ int pdit_run_cupim(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F, i
     ctx->last_class = cls;
     ctx->last_mode = 0;
     S.best_valid = true;
+    remember(ctx, N, R, D, F, perm);
     return PDIT_OK;
 }
 
@@ -1053,6 +1073,7 @@ int pdit_beta_select(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     ctx->last_class = use_fast ? fclass : 0;
     ctx->last_mode = mode;
     S.best_valid = true;
+    ctx->last_insts.clear();   // the trial replicas are the library's own
     return PDIT_OK;
 }
 
@@ -1367,6 +1388,7 @@ int pdit_run_sweeps_batch(pdit_t *ctx, int32_t n_inst, const pdit_instance *inst
     ctx->last_updates = 0;
     for (int k = 0; k < n_inst; ++k) ctx->last_updates += (int64_t)inst[k].R * inst[k].N * n_sweeps;
     S.best_valid = true;
+    ctx->last_insts.assign(inst, inst + n_inst);
     return PDIT_OK;
 }
 
@@ -1635,6 +1657,56 @@ int pdit_debug_delta(pdit_t *ctx, int32_t N, const int32_t *D, const int32_t *F,
     int64_t *E = H + (size_t)R * N * N;
     PDIT_HIP(ctx, pdit::launch_h_recompute_plain(ctx->stream, N, D, F, R, perm, H, true, E));
     PDIT_HIP(ctx, pdit::launch_debug_delta(ctx->stream, N, D, F, R, perm, H, r, delta_out));
+    return PDIT_OK;
+}
+
+// replica `replica` of instance `inst` of the last run: its N, D, F and row
+// of perm, validated
+static int last_replica(pdit_t *ctx, int32_t inst, int32_t replica, pdit_instance *x,
+                        const int32_t **prow) {
+    if (ctx->last_insts.empty()) return fail(ctx, PDIT_ESTATE, "no run yet");
+    if (inst < 0 || inst >= (int32_t)ctx->last_insts.size())
+        return fail(ctx, PDIT_EINVAL, "inst out of range");
+    *x = ctx->last_insts[inst];
+    if (replica < 0 || replica >= x->R) return fail(ctx, PDIT_EINVAL, "replica out of range");
+    if (!x->D || !x->F || !x->perm) return fail(ctx, PDIT_ESTATE, "the last run kept no data");
+    *prow = x->perm + (int64_t)replica * x->N;
+    return PDIT_OK;
+}
+
+int pdit_debug_H(pdit_t *ctx, int32_t inst, int32_t replica, int64_t *H_out) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!H_out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    pdit_instance x;
+    const int32_t *prow = nullptr;
+    int rc = last_replica(ctx, inst, replica, &x, &prow);
+    if (rc) return rc;
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    rc = ensure(ctx, ctx->check_buf, 256);
+    if (rc) return rc;
+    PDIT_HIP(ctx, pdit::launch_h_recompute_plain(ctx->stream, x.N, x.D, x.F, 1, prow, H_out, true,
+                                                 (int64_t *)ctx->check_buf.ptr));
+    return PDIT_OK;
+}
+
+int pdit_debug_delta_replica(pdit_t *ctx, int32_t inst, int32_t replica, int32_t r,
+                             int64_t *delta_out) {
+    if (!ctx) return PDIT_EINVAL;
+    ctx->last_error.clear();
+    if (!delta_out) return fail(ctx, PDIT_EINVAL, "null pointer argument");
+    pdit_instance x;
+    const int32_t *prow = nullptr;
+    int rc = last_replica(ctx, inst, replica, &x, &prow);
+    if (rc) return rc;
+    if (r < 0 || r >= x.N) return fail(ctx, PDIT_EINVAL, "r out of range");
+    PDIT_HIP(ctx, hipSetDevice(ctx->opts.device));
+    rc = ensure(ctx, ctx->check_buf, 256 + sizeof(int64_t) * (size_t)x.N * x.N);
+    if (rc) return rc;
+    int64_t *H = (int64_t *)((char *)ctx->check_buf.ptr + 256);
+    PDIT_HIP(ctx, pdit::launch_h_recompute_plain(ctx->stream, x.N, x.D, x.F, 1, prow, H, true,
+                                                 (int64_t *)ctx->check_buf.ptr));
+    PDIT_HIP(ctx, pdit::launch_debug_delta(ctx->stream, x.N, x.D, x.F, 1, prow, H, r, delta_out));
     return PDIT_OK;
 }
 

@@ -87,6 +87,9 @@ struct pdit_ctx {
     pdit::DeviceBuffer check_buf;     // paranoid rechecks: recomputed energies, H and counts
     pdit::DeviceBuffer conv_buf;      // H recompute on MFMA: D and F in operand format
     pdit::DeviceBuffer cupim_buf;     // GPU-CUPIM beyond the on-chip kernel: S, diag H, draws
+    // the instances of the last run (N, R, D, F, perm as given), for the
+    // debug exports on the context's replica state
+    std::vector<pdit_instance> last_insts;
     pdit::InstanceStats *stats_host = nullptr;  // pinned host mirror
     int32_t *err_dev = nullptr;       // deferred device error word
     int32_t *flag_host = nullptr;     // pinned: fused parallel tempering's wait flag

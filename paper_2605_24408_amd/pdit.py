@@ -71,7 +71,8 @@ EXPORTS = ["pdit_default_opts", "pdit_create", "pdit_destroy", "pdit_run_sweeps"
            "pdit_reset", "pdit_sync", "pdit_last_error", "pdit_set_recording",
            "pdit_h_recompute", "pdit_debug_delta", "pdit_debug_choice", "pdit_debug_uniform24",
            "pdit_last_timing", "pdit_autotune", "pdit_last_plan", "pdit_run_pt",
-           "pdit_beta_select", "pdit_run_cupim", "pdit_run_sweeps_noalloc"]
+           "pdit_beta_select", "pdit_run_cupim", "pdit_run_sweeps_noalloc", "pdit_debug_H",
+           "pdit_debug_delta_replica"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     L.pdit_last_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.pdit_autotune.argtypes = [vp, i32, C.POINTER(_Instance), i64, u64, C.POINTER(_Tuning)]
     L.pdit_last_plan.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.pdit_debug_H.argtypes = [vp, i32, i32, vp]
+    L.pdit_debug_delta_replica.argtypes = [vp, i32, i32, i32, vp]
     L.pdit_run_sweeps_noalloc.argtypes = [C.POINTER(_Opts), i32, vp, vp, i32, vp, vp, i64, u64,
                                           u64, C.c_int, vp, vp, vp, vp, C.c_char_p, i32]
     for name in EXPORTS:
@@ -452,6 +455,19 @@ class Pdit:
         out = torch.empty((R, N), dtype=torch.int64, device=self.device)
         self._rc(self._L.pdit_debug_delta(self._h, N, _ptr(D), _ptr(F), R, _ptr(perm), int(r),
                                           _ptr(out)))
+        return out
+
+    def debug_H(self, inst: int, replica: int, N: int) -> torch.Tensor:
+        """pdit_debug_H: H = D F[p,p] (int64 N x N) of a replica of the last run."""
+        H = torch.empty((N, N), dtype=torch.int64, device=self.device)
+        self._rc(self._L.pdit_debug_H(self._h, int(inst), int(replica), _ptr(H)))
+        return H
+
+    def debug_delta_replica(self, inst: int, replica: int, r: int, N: int) -> torch.Tensor:
+        """pdit_debug_delta_replica: Eq. 3 for location r of a replica of the last run."""
+        out = torch.empty(N, dtype=torch.int64, device=self.device)
+        self._rc(self._L.pdit_debug_delta_replica(self._h, int(inst), int(replica), int(r),
+                                                  _ptr(out)))
         return out
 
     def debug_choice(self, delta: torch.Tensor, beta: torch.Tensor, u24: torch.Tensor):

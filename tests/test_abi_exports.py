@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2605_24408_amd", "libpdit.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pdit_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(pdit_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():

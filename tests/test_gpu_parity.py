@@ -522,3 +522,52 @@ def test_int64_distances_trajectory(P, sweep):
     say(f"int64 distances sweep={sweep}")
     got = run_gpu(P, D, F, perms, beta, 5, sweep=sweep, record=True)
     replay(got, D, F, perms, beta, 5, what=f"int64 distances {sweep}")
+
+
+def test_debug_exports_on_replica_state(P):
+    """pdit_debug_H and pdit_debug_delta_replica read a replica of the last
+    run (single, batched and concurrent): H = D F[p,p] of its current
+    permutation, and the Eq. 3 row equal to pdit_debug_delta on that row;
+    PDIT_ESTATE before any run, PDIT_EINVAL out of range."""
+    rng = np.random.default_rng(21)
+    N, R = 40, 3
+    D, F = W.random_instance(rng, N, 0, 50, zero_diag=False)
+    perms = W.random_perms(rng, R, N)
+    Dd, Fd = dev(D, torch.int32), dev(F, torch.int32)
+    Di, Fi = D.astype(np.int64), F.astype(np.int64)
+    with P.Pdit() as ctx:
+        with pytest.raises(P.PditError) as e:
+            ctx.debug_H(0, 0, N)
+        assert e.value.status == "PDIT_ESTATE"
+        p = dev(perms, torch.int32)
+        ctx.run_sweeps(Dd, Fd, p, dev(np.full(5, 0.02, np.float32), torch.float32), 3)
+        pr = p.cpu().numpy()
+        for k in range(R):
+            H = ctx.debug_H(0, k, N).cpu().numpy()
+            assert np.array_equal(H, Di @ Fi[np.ix_(pr[k], pr[k])])
+        for r in (0, 17, N - 1):
+            got = ctx.debug_delta_replica(0, 2, r, N).cpu().numpy()
+            want = ctx.debug_delta(Dd, Fd, p[2:3].contiguous(), r).cpu().numpy()[0]
+            assert np.array_equal(got, want)
+        for args in ((1, 0), (0, R), (0, -1)):
+            with pytest.raises(P.PditError) as e:
+                ctx.debug_H(args[0], args[1], N)
+            assert e.value.status == "PDIT_EINVAL"
+        with pytest.raises(P.PditError) as e:
+            ctx.debug_delta_replica(0, 0, N, N)
+        assert e.value.status == "PDIT_EINVAL"
+        # a batch: instance 1's replica 1
+        # (the caller keeps D, F and perm alive for the debug exports)
+        D2, F2 = W.random_instance(rng, 23, 0, 30)
+        D2d, F2d = dev(D2, torch.int32), dev(F2, torch.int32)
+        p1 = dev(W.random_perms(rng, 2, 23), torch.int32)
+        p0 = dev(perms, torch.int32)
+        b4 = dev(np.full(4, 0.05, np.float32), torch.float32)
+        ctx.run_sweeps_batch([(Dd, Fd, p0, b4), (D2d, F2d, p1, b4)], 5)
+        q = p1.cpu().numpy()[1]
+        H = ctx.debug_H(1, 1, 23).cpu().numpy()
+        assert np.array_equal(H, D2.astype(np.int64) @ F2.astype(np.int64)[np.ix_(q, q)])
+        # concurrent updates
+        ctx.run_cupim(Dd, Fd, p0, dev(np.full(3, 0.05, np.float32), torch.float32), 6)
+        q = p0.cpu().numpy()[0]
+        assert np.array_equal(ctx.debug_H(0, 0, N).cpu().numpy(), Di @ Fi[np.ix_(q, q)])
