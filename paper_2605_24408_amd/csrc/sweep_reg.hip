@@ -65,7 +65,7 @@ constexpr int32_t kRBig = (1 << 30) - 1;  // padding candidates (|dE| < 2^30 - 1
 // Batches: kRSpec consecutive updates evaluated on one state when the
 // previous sweep accepted at most kRSpecAcc exchanges
 constexpr int kRSpec = 12;
-constexpr int kRSpecAcc = 48;
+constexpr int kRSpecAcc = 72;
 // spins of a replica's wait before it gives up (about 0.1 s): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
 // control flow excludes; the call then reports PDIT_EDEVICE at pdit_sync
