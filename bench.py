@@ -39,6 +39,8 @@ METRIC = "p-dit updates/s + time-to-target gap; batched+int8 MFMA vs plain, 1 GP
 # 32-bit integer lane operations per second of one MI355X (the non-packed
 # VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz)
 VALU_PEAK = 256 * 64 * 2.4e9
+# HBM3E bandwidth of one MI355X, bytes per second
+HBM_PEAK = 8.0e12
 
 
 def method_ops_per_update(N: int, alpha: float) -> float:
@@ -605,16 +607,30 @@ def n256_workload(args):
                 c.run_sweeps(D, F, p, beta[i * S:i * S + PS].contiguous(), seed)
                 e = c.energy()
                 torch.cuda.synchronize()
-                res[name] = (time.perf_counter() - t_, p.cpu().numpy(), e.cpu().numpy())
+                res[name] = (time.perf_counter() - t_, p.cpu().numpy(), e.cpu().numpy(),
+                             c.counters(), c.last_timing()[1] / 1e3)
             same = same and np.array_equal(res["plain"][1], res["fast"][1]) and \
                 np.array_equal(res["plain"][2], res["fast"][2])
-            samples.append({"slice": i, "plain_s": res["plain"][0], "fast_s": res["fast"][0]})
+            cnt, ks = res["plain"][3], res["plain"][4]
+            a_ = cnt["accepted"] / cnt["updates"]
+            # the plain kernel's algorithmic HBM bytes: per update the row, column
+            # and diagonal of H (3N elements), and per accepted exchange the
+            # read and write of the whole N x N H (4-byte elements)
+            hbm = cnt["updates"] * (3 * N + a_ * 2 * N * N) * 4
+            samples.append({"slice": i, "plain_s": res["plain"][0], "fast_s": res["fast"][0],
+                            "alpha": a_, "plain_kernel_s": ks, "plain_hbm_GBps": hbm / ks / 1e9,
+                            "plain_hbm_frac": hbm / ks / HBM_PEAK})
         plain.close()
         fastc.close()
         # each sample stands for the two slices it starts (every other slice)
         est = sum(x["plain_s"] / PS * S * 2 for x in samples)
         fast_total = sum(p["kernel_ms"] for p in per_slice) / 1e3
+        hot = samples[0]
         plain_rec = {"sweeps_per_sample": PS, "samples": samples,
+                     "hbm_roofline_first_sample": {
+                         "bound": "hbm", "achieved": hot["plain_hbm_GBps"],
+                         "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": hot["plain_hbm_frac"],
+                         "bytes_per_update": "(3 N + alpha 2 N^2) x 4 B"},
                      "estimated_full_schedule_s": est,
                      "fast_full_schedule_kernel_s": fast_total,
                      "value": R * N * T / est,

@@ -123,9 +123,23 @@ __device__ void plain_replica(const ReplicaJob &a, PlainSmem &sm) {
                     sm.vvec[i] = F[(int64_t)fa * N + c] - F[(int64_t)fb * N + c];
                 }
                 __syncthreads();
-                for (int64_t e = tid; e < (int64_t)N * N; e += nt) {
-                    const int i = (int)(e / N), k = (int)(e % N);
-                    H[e] += (HT)((int64_t)sm.uvec[i] * sm.vvec[k]);
+                // rows by wave, columns by lane (coalesced); four rows are
+                // read before any is written back, so that their loads are in
+                // flight together
+                const int nw = nt >> 6, wv = tid >> 6, ln = tid & 63;
+                for (int i0 = 4 * wv; i0 < N; i0 += 4 * nw) {
+                    const int nr = min(4, N - i0);
+                    HT *row = H + (int64_t)i0 * N;
+                    for (int k = ln; k < N; k += 64) {
+                        HT x[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (j < nr) x[j] = row[(int64_t)j * N + k];
+                        const int64_t vk = sm.vvec[k];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (j < nr) row[(int64_t)j * N + k] = x[j] + (HT)(sm.uvec[i0 + j] * vk);
+                    }
                 }
                 __syncthreads();
                 for (int i = tid; i < N; i += nt) {
