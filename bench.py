@@ -526,6 +526,8 @@ def n256_workload(args):
         cnt = ctx.counters()
         per_slice.append({"slice": i, "timed": False, "kernel_ms": ctx.last_timing()[1],
                           "alpha": cnt["accepted"] / cnt["updates"], "plan": ctx.last_plan()})
+        print(f"warmup slice {i}: {per_slice[-1]['kernel_ms']:.0f} ms of sweep kernel",
+              file=sys.stderr, flush=True)
     # ---------------- timed slices ----------------
     torch.cuda.synchronize()
     start = time.perf_counter()
@@ -536,6 +538,8 @@ def n256_workload(args):
         per_slice.append({"slice": i, "timed": True, "kernel_ms": ctx.last_timing()[1],
                           "alpha": cnt["accepted"] / cnt["updates"], "plan": ctx.last_plan(),
                           "end_s": time.perf_counter() - start, "ties": cnt["ties"]})
+        print(f"slice {i}: {per_slice[-1]['kernel_ms']:.0f} ms of sweep kernel", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - start
     run_sweeps = min(T, (args.warmup + args.steps) * S)

@@ -34,15 +34,18 @@
 // candidate, as the other sweep kernels do.
 //
 // Batches.  An update that keeps its facility changes nothing, so when few
-// exchanges are accepted the updates of locations r0 .. r0 + 11 can all be
-// evaluated on the same state: the waves publish the 12 rows and columns
-// together, and each wave takes three of the updates whole, on all N
+// exchanges are accepted the updates of locations r0 .. r0 + nb - 1 can all
+// be evaluated on the same state: the waves publish the nb rows and columns
+// together, and each wave takes up to three of the updates whole, on all N
 // candidates at four consecutive locations per lane (their p and H[k][k]
 // read from LDS), with its own minimum and draw; the draws (candidate, dE,
 // its facility) meet in LDS and the stays up to the first exchange are
 // committed.  That exchange is applied as in a single update, and the next
-// batch starts after it.  Every draw is the sequential one; a sweep runs in
-// batches when the sweep before it accepted at most kRSpecAcc exchanges.
+// batch starts after it.  Every draw is the sequential one.  A sweep runs in
+// batches when the sweep before it accepted at most kRAcc4 exchanges, with
+// nb = 12, 8 or 4 as that count falls below kRAcc12, kRAcc8 or kRAcc4: a
+// batch is cut at its first exchange, so the more exchanges, the shorter
+// the batch that pays.
 //
 // Two replicas share a workgroup (eight waves, each SIMD holding one wave of
 // each) and its LDS: D and F as 8-bit copies (64 KB each, unsigned in
@@ -62,10 +65,13 @@ constexpr int kRWaves = 4;        // waves per replica
 constexpr int kRReps = 2;         // replicas per workgroup
 constexpr int kRThreads = 64 * kRWaves * kRReps;
 constexpr int32_t kRBig = (1 << 30) - 1;  // padding candidates (|dE| < 2^30 - 1)
-// Batches: kRSpec consecutive updates evaluated on one state when the
-// previous sweep accepted at most kRSpecAcc exchanges
+// Batches: after a sweep that accepted at most kRAcc4 exchanges the next
+// sweep evaluates consecutive updates on one state, kRSpec of them when it
+// accepted at most kRAcc12, 8 up to kRAcc8, else 4
 constexpr int kRSpec = 12;
-constexpr int kRSpecAcc = 72;
+constexpr int kRAcc12 = 24;
+constexpr int kRAcc8 = 48;
+constexpr int kRAcc4 = 112;
 // spins of a replica's wait before it gives up (about 0.1 s): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
 // control flow excludes; the call then reports PDIT_EDEVICE at pdit_sync
@@ -456,6 +462,7 @@ sweep_reg_kernel(SweepArgs a) {
     rep_signal(rs.sync, wv, ++seq);
     bool ok = true;        // every wait completed
     bool batch = false;    // this sweep runs in batches
+    int nbs = kRSpec;      // updates per batch in this sweep
 
     for (int64_t t = 0; t < a.T && ok; ++t) {
         const float beta = bp[t * bstride];
@@ -467,7 +474,7 @@ sweep_reg_kernel(SweepArgs a) {
         rs.u24[k] = uniform24(a.seed, (uint32_t)k, gsw, (uint32_t)rep, a.inst_id);
         const int64_t acc0 = n_acc;
         // the next sweep runs in batches when this one accepts few exchanges
-#define PDIT_REG_NEXT_BATCH() (t + 1 < a.T && n_acc - acc0 <= kRSpecAcc)
+#define PDIT_REG_NEXT_BATCH() (t + 1 < a.T && n_acc - acc0 <= kRAcc4)
 
         // Steps: one update, evaluated by the four waves on 64 candidates each
         // (meetings: the row and column, the minimum, the running sums), or in
@@ -489,7 +496,7 @@ sweep_reg_kernel(SweepArgs a) {
                     ok = rep_spin(flags, seq);
                     if (!ok) break;
                 }
-                const int nb = min(kRSpec, N - r0);
+                const int nb = min(nbs, N - r0);
                 const int ab = rs.pv[r0 + (lane < nb ? lane : 0)];  // p of the batch's rows
                 rs.dga[k] = dg;
                 {
@@ -690,6 +697,7 @@ sweep_reg_kernel(SweepArgs a) {
             rep_signal(rs.sync, wv, ++seq);
         }
         batch = PDIT_REG_NEXT_BATCH();
+        nbs = n_acc - acc0 <= kRAcc12 ? kRSpec : n_acc - acc0 <= kRAcc8 ? 8 : 4;
 #undef PDIT_REG_NEXT_BATCH
         if (a.E_trace && writer && lane == 0) a.E_trace[rep * a.T + t] = E;
     }

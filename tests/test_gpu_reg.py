@@ -120,9 +120,11 @@ def test_reg_plateau_and_resume():
 def test_reg_batches_and_switches(N, R):
     """Sweeps that accept few exchanges are followed by sweeps evaluated in
     batches of updates on one state (the prefix up to the first exchange
-    committed); a schedule alternating cold and hot stretches, from an
-    annealed state, switches between the two ways several times.  N = 203
-    leaves a ragged last batch in every sweep."""
+    committed), of 12, 8 or 4 updates as the exchanges fall below 25, 49 and
+    113; a schedule alternating cold and hot stretches, from an annealed
+    state, then cooling from a warm one, switches between the ways several
+    times and takes every batch size.  N = 203 leaves a ragged last batch in
+    every sweep."""
     from paper_2605_24408_amd import pdit as P
     rng = np.random.default_rng(N + 5)
     D, F = instance(rng, N, "euclid")
@@ -130,7 +132,8 @@ def test_reg_batches_and_switches(N, R):
     s = W.energy_scale(D, F)
     cold, hot = 2000.0 / s, 2.0 / s
     pre = W.beta_geometric(5.0 / s, cold, 60)
-    blocks = [(cold, 4), (hot, 2), (cold, 5), (hot, 1), (cold, 3)]
+    blocks = [(cold, 4), (hot, 2), (cold, 5), (hot, 1), (cold, 3), (150.0 / s, 4),
+              (300.0 / s, 4), (600.0 / s, 3)]
     beta = np.concatenate([np.full(n, b, np.float32) for b, n in blocks])
     with P.Pdit(sweep="reg") as ctx:
         a = run(ctx, D, F, perms, pre, 5, offset=500, record=False)
@@ -138,10 +141,10 @@ def test_reg_batches_and_switches(N, R):
         ctx.reset()
         got = run(ctx, D, F, start, beta, 5)
     replay(got, D, F, start, beta, 5, what=f"reg switches N={N}")
-    # exchanges per sweep: both kinds of sweep follow each other
-    moved = (got["choices"] != np.arange(N)[None, None, :]).sum(axis=2)
-    few = moved <= 72
-    assert few[:, :-1].any() and (~few[:, :-1]).any(), moved
+    # exchanges per sweep: single updates and each batch size follow each other
+    moved = (got["choices"] != np.arange(N)[None, None, :]).sum(axis=2)[:, :-1]
+    for lo, hi in ((0, 24), (25, 48), (49, 112), (113, N)):
+        assert ((moved >= lo) & (moved <= hi)).any(), (lo, hi, moved)
 
 
 def test_reg_auto_and_refusals():
@@ -165,17 +168,19 @@ def test_reg_auto_and_refusals():
             assert e.value.status == "PDIT_EOVERFLOW"
 
 
-@pytest.mark.parametrize("where", ["start", "middle", "end"])
+@pytest.mark.parametrize("where", ["start", "middle", "cooling", "cool", "end"])
 def test_reg_n256_workload_windows(where):
     """The N=256 workload: 8 of its 512 replicas (rows 0, 73, ..., 511 of the
     full batch, with their own Philox replica indices) over a window of 200
-    sweeps at the start, the middle and the cold end of its 10^5-sweep
-    schedule, each window started from the GPU's own state after a strided
-    pass over the schedule before it; the window replayed draw by draw."""
+    sweeps at the start, the middle, two cooling points (batches of 4 and 8
+    updates) and the cold end (batches of 12) of its 10^5-sweep schedule,
+    each window started from the GPU's own state after a strided pass over
+    the schedule before it; the window replayed draw by draw."""
     from paper_2605_24408_amd import pdit as P
     inst = W.config_n256()
     rows = [0, 73, 146, 219, 292, 365, 438, 511]
-    start = {"start": 0, "middle": 50_000, "end": 99_800}[where]
+    start = {"start": 0, "middle": 50_000, "cooling": 65_000, "cool": 72_500,
+             "end": 99_800}[where]
     win = 200
     # the full batch, so the sampled rows keep their replica indices
     perms = inst.perms.copy()
