@@ -36,9 +36,17 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the gfx950 library cannot be built")
 
 
+# Per-source device flags.  The register sweep kernel is a long loop body
+# with many taken branches per update; aligning every jump target that has no
+# fall-through predecessor to 64 bytes (no executed padding) made its hot
+# sweeps about 1% faster on the N=256 workload, measured against the same
+# source without it on one box.
+EXTRA = {"sweep_reg.hip": ["-Xarch_device", "-mllvm=--align-all-nofallthru-blocks=6"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

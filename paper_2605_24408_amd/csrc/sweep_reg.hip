@@ -461,8 +461,7 @@ sweep_reg_kernel(SweepArgs a) {
     PDIT_REG_PUBLISH(0, a_next, 0)
     rep_signal(rs.sync, wv, ++seq);
     bool ok = true;        // every wait completed
-    bool batch = false;    // this sweep runs in batches
-    int nbs = kRSpec;      // updates per batch in this sweep
+    int nbat = 0;          // updates per batch in this sweep (0: one update at a time)
 
     for (int64_t t = 0; t < a.T && ok; ++t) {
         const float beta = bp[t * bstride];
@@ -478,11 +477,11 @@ sweep_reg_kernel(SweepArgs a) {
 
         // Steps: one update, evaluated by the four waves on 64 candidates each
         // (meetings: the row and column, the minimum, the running sums), or in
-        // a batch sweep a batch of kRSpec updates evaluated on one state: their
+        // a batch sweep a batch of nbat updates evaluated on one state: their
         // energy changes and minima, then the draws of the updates that can
         // move, in order, until one exchanges; the stays before it are
         // committed and the exchange is applied.
-        if (batch && !rep_done(*flags, seq)) ok = rep_spin(flags, seq);  // buffers free
+        if (nbat && !rep_done(*flags, seq)) ok = rep_spin(flags, seq);  // buffers free
         bool replayed = false;                  // batch: the last step ended in an exchange
         int r0 = 0;
         while (r0 < N && ok) {
@@ -490,13 +489,13 @@ sweep_reg_kernel(SweepArgs a) {
             int r = r0, s = r0, af = 0, bf = 0, nxt = 0;
             int32_t des = 0;
             const int16_t *prow = rs.u.sq.prow[0];
-            if (batch) {
+            if (nbat) {
                 // ============ a batch: rows r0 .. r0 + nb - 1 ============
                 if (replayed && !rep_done(*flags, seq)) {  // every wave left the exchange
                     ok = rep_spin(flags, seq);
                     if (!ok) break;
                 }
-                const int nb = min(nbs, N - r0);
+                const int nb = min(nbat, N - r0);
                 const int ab = rs.pv[r0 + (lane < nb ? lane : 0)];  // p of the batch's rows
                 rs.dga[k] = dg;
                 {
@@ -673,7 +672,7 @@ sweep_reg_kernel(SweepArgs a) {
             // ============ the accepted exchange (the step's only one) ============
             if (s != r) PDIT_REG_ACCEPT(r, s, af, bf, des, prow)
             r0 = r + 1;
-            if (batch) {
+            if (nbat) {
                 replayed = true;
             } else {
                 // p(r + 1) after this update, and the next update's row and column
@@ -687,7 +686,7 @@ sweep_reg_kernel(SweepArgs a) {
             }
             rep_signal(rs.sync, wv, ++seq);
         }
-        if (ok && batch && !PDIT_REG_NEXT_BATCH()) {
+        if (ok && nbat && !PDIT_REG_NEXT_BATCH()) {
             // the next sweep goes one update at a time: its first row and column,
             // once every wave has left the batch buffers they share
             if (!rep_done(*flags, seq)) ok = rep_spin(flags, seq);
@@ -696,8 +695,10 @@ sweep_reg_kernel(SweepArgs a) {
             PDIT_REG_PUBLISH(0, a_next, pbuf)
             rep_signal(rs.sync, wv, ++seq);
         }
-        batch = PDIT_REG_NEXT_BATCH();
-        nbs = n_acc - acc0 <= kRAcc12 ? kRSpec : n_acc - acc0 <= kRAcc8 ? 8 : 4;
+        nbat = !PDIT_REG_NEXT_BATCH()      ? 0
+             : n_acc - acc0 <= kRAcc12 ? kRSpec
+             : n_acc - acc0 <= kRAcc8  ? 8
+                                       : 4;
 #undef PDIT_REG_NEXT_BATCH
         if (a.E_trace && writer && lane == 0) a.E_trace[rep * a.T + t] = E;
     }
