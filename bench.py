@@ -95,6 +95,9 @@ def parse():
                          "prefix of the N=256 schedule)")
     ap.add_argument("--sweeps", type=int, default=0,
                     help="run only the first SWEEPS sweeps of the schedule (0 = all)")
+    ap.add_argument("--ttt-slices", type=int, default=0,
+                    help="n12, n256p, n512, uneven: time to target of the automatic plan over "
+                         "the whole schedule, run in this many slices")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates the "
                          "profiler's byte counters against a kernel of known traffic)")
@@ -160,6 +163,106 @@ def other_workload(args):
     out["speedup"] = results["plain"][0] / results["fast"][0]
     out["identical_best"] = bool(all(np.array_equal(results[p][1], results["plain"][1])
                                      for p in results))
+    print(json.dumps(out), flush=True)
+
+
+def ttt_workload(args):
+    """Time to target on one of the other workloads (automatic plan only):
+    the whole schedule in --ttt-slices slices resumed through the sweep
+    offset, each slice recording every replica's energy after every sweep.
+    An instance's target is the best energy over its replicas at the end of
+    the schedule; the batch reaches a gap when every instance has.  A first
+    hit is taken at the end of a sweep (a best state found inside a sweep
+    and left again by its end is seen at the next sweep end below the same
+    energy, or not at all).  A one-call run of the same schedule must end in
+    the same best states (the slices resume exactly)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_24408_amd import pdit
+    from paper_2605_24408_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    insts = W.config_uneven() if args.workload == "uneven" else \
+        [{"n12": W.config_n12, "n256p": W.config_n256, "n512": W.config_n512}[args.workload]()]
+    T = insts[0].T
+    K = args.ttt_slices
+    S = -(-T // K)
+    dbatch = [(torch.from_numpy(i.D).to(dev), torch.from_numpy(i.F).to(dev),
+               torch.from_numpy(i.perms).to(dev), torch.from_numpy(i.beta).to(dev)) for i in insts]
+    perms0 = [p.clone() for _, _, p, _ in dbatch]
+    best = [np.full(T, np.iinfo(np.int64).max, dtype=np.int64) for _ in insts]
+    ctx = pdit.Pdit()
+    ctx.reset()
+    ends = []
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    for j in range(K):
+        t0, t1 = j * S, min(T, (j + 1) * S)
+        if t0 >= t1:
+            break
+        traces = [torch.zeros((i.R, t1 - t0), dtype=torch.int64, device=dev) for i in insts]
+        ctx.set_sweep_offset(t0)
+        if len(insts) > 1:
+            ctx.run_sweeps_batch([(D, F, p, b[t0:t1].contiguous(), None, tr)
+                                  for (D, F, p, b), tr in zip(dbatch, traces)], W.PHILOX_SEED)
+        else:
+            D, F, p, b = dbatch[0]
+            ctx.set_recording(None, traces[0])
+            ctx.run_sweeps(D, F, p, b[t0:t1].contiguous(), W.PHILOX_SEED)
+        torch.cuda.synchronize()
+        ends.append((t1, time.perf_counter() - start))
+        for k, tr in enumerate(traces):
+            best[k][t0:t1] = tr.min(dim=0).values.cpu().numpy()
+        print(f"slice {j}: sweeps {t0}..{t1}, {ends[-1][1]:.2f} s", file=sys.stderr, flush=True)
+    Eb_s, _ = ctx.best()
+    Eb_s = Eb_s.cpu().numpy()
+    ctx.close()
+    # the same schedule in one call
+    one = pdit.Pdit()
+    for (_, _, p, _), p0 in zip(dbatch, perms0):
+        p.copy_(p0)
+    one.reset()
+    one.set_sweep_offset(0)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter()
+    if len(insts) > 1:
+        one.run_sweeps_batch(dbatch, W.PHILOX_SEED)
+    else:
+        D, F, p, b = dbatch[0]
+        one.run_sweeps(D, F, p, b, W.PHILOX_SEED)
+    Eb_1, _ = one.best()
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t_one
+    Eb_1 = Eb_1.cpu().numpy()
+    one.close()
+
+    def seconds_at(sweep):   # sweep index (0-based) -> seconds, within its slice
+        prev_t, prev_s = 0, 0.0
+        for t1, sec in ends:
+            if sweep < t1:
+                return prev_s + (sec - prev_s) * (sweep + 1 - prev_t) / (t1 - prev_t)
+            prev_t, prev_s = t1, sec
+        return None
+
+    offs = np.cumsum([0] + [i.R for i in insts])
+    targets = [int(Eb_s[offs[k]:offs[k + 1]].min()) for k in range(len(insts))]
+    out = {"workload": args.workload, "instances": len(insts), "replicas": int(offs[-1]),
+           "sweeps": T, "slices": len(ends), "seconds_sliced": ends[-1][1],
+           "seconds_one_call": t_one, "same_best_as_one_call": bool(np.array_equal(Eb_s, Eb_1)),
+           "target": "per instance, the best energy over its replicas at the end"}
+    for gap in (0.01, 0.001, 0.0):
+        hits = []
+        for k in range(len(insts)):
+            h = np.nonzero(best[k] <= targets[k] + abs(targets[k]) * gap)[0]
+            hits.append(int(h[0]) if h.size else None)
+        reached = [h for h in hits if h is not None]
+        last = max(reached) if len(reached) == len(hits) else None
+        out[f"gap_{gap:g}"] = {"instances_reached_at_a_sweep_end": len(reached),
+                               "sweep_all_reached": None if last is None else last + 1,
+                               "seconds": None if last is None else seconds_at(last),
+                               "median_instance_sweep": float(np.median(reached)) + 1
+                               if reached else None}
     print(json.dumps(out), flush=True)
 
 
@@ -715,7 +818,10 @@ def main():
         cupim256_workload(args)
         return
     if args.workload != "n64":
-        other_workload(args)
+        if args.ttt_slices:
+            ttt_workload(args)
+        else:
+            other_workload(args)
         return
     n64_workload(args)
 
