@@ -108,8 +108,9 @@ extern "C" {
                                selection, periodic tempering (diag H is the state saved
                                between periods) and batched runs (a persistent group per copy
                                layout, product width and H width). */
-#define PDIT_SWEEP_REG 5    /* G = D F[p,:] in registers, 128 < N <= 256: each of the replica's
-                               256 lanes keeps its location's row of G (H[i][k] = G[i][p(k)])
+#define PDIT_SWEEP_REG 5    /* G = D F[p,:] in registers, 128 < N <= 256: lane j of wave w
+                               of the replica's four keeps the 4 x 64 tile of G at rows
+                               4j .. 4j+3 and facilities 64w .. 64w+63 (H[i][k] = G[i][p(k)])
                                as packed int16 pairs, exact while |H| <= 32767; an accepted
                                exchange of the facilities a = p(r), b = p(s) adds the rank-1
                                term (D[i][r] - D[i][s]) (F[b][c] - F[a][c]) and moves no
