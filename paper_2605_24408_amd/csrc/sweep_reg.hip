@@ -72,7 +72,7 @@ constexpr int kRSpec = 12;
 constexpr int kRAcc12 = 24;
 constexpr int kRAcc8 = 48;
 constexpr int kRAcc4 = 112;
-// spins of a replica's wait before it gives up (about 0.1 s): reached only
+// polls of a replica's wait before it gives up (a fraction of a second): reached only
 // if a wave of the replica stopped taking part, which the kernel's uniform
 // control flow excludes; the call then reports PDIT_EDEVICE at pdit_sync
 constexpr uint32_t kRSpinLimit = 1u << 22;
@@ -199,10 +199,10 @@ __device__ __forceinline__ bool rep_done(v4i v, uint32_t seq) {
 }
 
 // Polls until every wave has finished step seq; false when the wait gave up
-// (kRSpinLimit).
+// (kRSpinLimit).  Each poll is one LDS round trip; a sleep between polls
+// (s_sleep 1) made the hot sweeps of the N=256 workload 1.3% slower.
 __device__ __forceinline__ bool rep_spin(const lds_v4i *ps, uint32_t seq) {
     for (uint32_t it = 0; it < kRSpinLimit; ++it) {
-        __builtin_amdgcn_s_sleep(1);
         if (rep_done(*ps, seq)) {
             __asm__ volatile("" ::: "memory");
             return true;
