@@ -39,8 +39,6 @@ METRIC = "p-dit updates/s + time-to-target gap; batched+int8 MFMA vs plain, 1 GP
 # 32-bit integer lane operations per second of one MI355X (the non-packed
 # VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz)
 VALU_PEAK = 256 * 64 * 2.4e9
-# HBM3E bandwidth of one MI355X, bytes per second
-HBM_PEAK = 8.0e12
 
 
 def method_ops_per_update(N: int, alpha: float) -> float:
@@ -726,7 +724,7 @@ def n256_workload(args):
             hbm = cnt["updates"] * (3 * N + a_ * 2 * N * N) * 4
             samples.append({"slice": i, "plain_s": res["plain"][0], "fast_s": res["fast"][0],
                             "alpha": a_, "plain_kernel_s": ks, "plain_hbm_GBps": hbm / ks / 1e9,
-                            "plain_hbm_frac": hbm / ks / HBM_PEAK})
+                            "plain_hbm_frac": hbm / ks / PEAK_HBM})
         plain.close()
         fastc.close()
         # each sample stands for the two slices it starts (every other slice)
@@ -736,7 +734,7 @@ def n256_workload(args):
         plain_rec = {"sweeps_per_sample": PS, "samples": samples,
                      "hbm_roofline_first_sample": {
                          "bound": "hbm", "achieved": hot["plain_hbm_GBps"],
-                         "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": hot["plain_hbm_frac"],
+                         "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": hot["plain_hbm_frac"],
                          "bytes_per_update": "(3 N + alpha 2 N^2) x 4 B"},
                      "estimated_full_schedule_s": est,
                      "fast_full_schedule_kernel_s": fast_total,
