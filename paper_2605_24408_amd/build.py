@@ -40,7 +40,7 @@ def hipcc() -> str:
 # with many taken branches per update; aligning every jump target that has no
 # fall-through predecessor to 64 bytes (no executed padding) made its hot
 # sweeps about 1% faster on the N=256 workload, measured against the same
-# source without it on one box.
+# source without it in back-to-back runs on one MI355X.
 EXTRA = {"sweep_reg.hip": ["-Xarch_device", "-mllvm=--align-all-nofallthru-blocks=6"]}
 
 
